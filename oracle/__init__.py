@@ -1,0 +1,227 @@
+"""CPU reference renderer for the hybrid 2D/3D rasterizer: TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``liboracle.so``, built from
+``hgs_oracle.cpp`` by :func:`build`.  It shares no code with the GPU library.
+
+Functions
+---------
+structural(scene, cams, dilation)      binary32 culls, rects, tiles, keys, signs
+sorted_pairs(st, cams)                 (key, value) list, stably sorted, + ranges
+forward(scene, cams, pix, ...)         binary64 per-pixel composite (Eq. 1-2)
+backward(scene, cams, pix, G, ...)     binary64 gradients (dual numbers)
+sh_basis(degree, dirs)                 real SH basis used for colour
+surfel_uv(params, cam, pxy)            ray-plane (u, v, depth) of one surfel
+full_pixels(cams) / all outputs reshaped to images: render_images(...)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hgs_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+DEFAULT_OPTS = dict(bg=(0.0, 0.0, 0.0), dilation=0.3, lambda_z=1.0, theta_z=1.05,
+                    temp_z=0.001)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (g++, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC",
+                               "-shared", "-pthread", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        _lib.oracle_structural.argtypes = [P] * 5 + [C.c_int64, P, C.c_int, C.c_float] + [P] * 5
+        _lib.oracle_sorted_pairs.argtypes = [P, P, P, C.c_int64, P, C.c_int, P, P, C.c_int64, P,
+                                             C.c_int64]
+        _lib.oracle_sorted_pairs.restype = C.c_int64
+        _lib.oracle_forward.argtypes = ([P] * 6 + [C.c_int64, C.c_int] + [P] * 5 +
+                                        [P, C.c_int, P, P, P, C.c_int64, C.c_int, C.c_int] +
+                                        [P] * 5)
+        _lib.oracle_backward.argtypes = ([P] * 6 + [C.c_int64, C.c_int] + [P] * 5 +
+                                         [P, C.c_int, P, P, C.c_int64, P, C.c_int] + [P] * 4)
+        _lib.oracle_sh_basis.argtypes = [C.c_int, P, C.c_int64, P]
+        _lib.oracle_surfel_uv.argtypes = [P, P, P, C.c_int64, P]
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def pack_cams(cams) -> np.ndarray:
+    if isinstance(cams, dict):
+        cams = [cams]
+    out = np.zeros((len(cams), 23), np.float32)
+    for i, c in enumerate(cams):
+        out[i, :16] = np.asarray(c["viewmat"], np.float32).reshape(16)
+        out[i, 16:20] = [c["fx"], c["fy"], c["cx"], c["cy"]]
+        out[i, 20] = c["width"]
+        out[i, 21] = c["height"]
+        out[i, 22] = c["znear"]
+    return out
+
+
+def _opts_vec(opts):
+    o = dict(DEFAULT_OPTS)
+    o.update(opts or {})
+    return np.array(list(o["bg"]) + [o["dilation"], o["lambda_z"], o["theta_z"], o["temp_z"]],
+                    np.float64)
+
+
+def _f32(scene):
+    return [np.ascontiguousarray(scene[k], np.float32) for k in
+            ("means", "scales", "rotations", "opacities", "sh")] + \
+        [np.ascontiguousarray(scene["types"], np.uint8)]
+
+
+def _f64(scene, params64=None):
+    src = params64 if params64 is not None else scene
+    return [np.ascontiguousarray(src[k], np.float64) for k in
+            ("means", "scales", "rotations", "opacities", "sh")]
+
+
+def structural(scene, cams, dilation=0.3):
+    lib = _load()
+    m, s, r, o, _, t = _f32(scene)
+    n = m.shape[0]
+    cp = pack_cams(cams)
+    V = cp.shape[0]
+    valid = np.zeros(V * n, np.uint8)
+    rect = np.zeros((V * n, 4), np.int32)
+    tiles = np.zeros(V * n, np.uint32)
+    zb = np.zeros(V * n, np.uint32)
+    flip = np.zeros(V * n, np.uint8)
+    lib.oracle_structural(_p(m), _p(s), _p(r), _p(o), _p(t), n, _p(cp), V, float(dilation),
+                          _p(valid), _p(rect), _p(tiles), _p(zb), _p(flip))
+    return dict(valid=valid, rect=rect, tiles=tiles, zbits=zb, flip=flip, n=n)
+
+
+def tile_counts(cams):
+    cp = pack_cams(cams)
+    return [((int(c[20]) + 15) // 16) * ((int(c[21]) + 15) // 16) for c in cp]
+
+
+def sorted_pairs(st, cams):
+    lib = _load()
+    cp = pack_cams(cams)
+    V = cp.shape[0]
+    wh = np.ascontiguousarray(cp[:, 20:22].astype(np.int32))
+    n_tiles = int(sum(tile_counts(cams)))
+    D = int(st["tiles"].astype(np.int64).sum())
+    keys = np.zeros(max(D, 1), np.uint64)
+    vals = np.zeros(max(D, 1), np.uint32)
+    ranges = np.zeros((n_tiles, 2), np.uint32)
+    got = lib.oracle_sorted_pairs(_p(st["valid"]), _p(st["rect"]), _p(st["zbits"]), st["n"],
+                                  _p(wh), V, _p(keys), _p(vals), D, _p(ranges), n_tiles)
+    assert got == D, (got, D)
+    return keys[:D], vals[:D], ranges
+
+
+def full_pixels(cam, view=0):
+    H, W = cam["height"], cam["width"]
+    yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    return np.ascontiguousarray(np.stack([np.full(H * W, view), yy.ravel(), xx.ravel()], 1),
+                                np.int32)
+
+
+def forward(scene, cams, pix, opts=None, *, params64=None, brute=False, threads=None,
+            margins=(1e-4, 1e-3, 1e-3)):
+    """Binary64 forward at pixels ``pix`` ([P,3] = view, y, x).
+
+    Returns dict(out=[P,8] (r,g,b,alpha,depth,nx,ny,nz), T=[P], n_contrib=[P],
+    last=[P], tie=[P] bit flags (1 alpha threshold, 2 stop, 4 clamp),
+    wcount=[2] (active pairs up to and including the stop, per type 2D/3D)).
+    """
+    lib = _load()
+    m, s, r, o, sh, t = _f32(scene)
+    m6, s6, r6, o6, sh6 = _f64(scene, params64)
+    cp = pack_cams(cams)
+    pix = np.ascontiguousarray(pix, np.int32)
+    P = pix.shape[0]
+    out = np.zeros((P, 8), np.float64)
+    T = np.zeros(P, np.float64)
+    cnt = np.zeros((P, 2), np.int32)
+    tie = np.zeros(P, np.uint8)
+    wc = np.zeros(2, np.int64)
+    ov = _opts_vec(opts)
+    mg = np.asarray(margins, np.float64)
+    lib.oracle_forward(_p(m), _p(s), _p(r), _p(o), _p(sh), _p(t), m.shape[0],
+                       int(scene["sh_degree"]), _p(m6), _p(s6), _p(r6), _p(o6), _p(sh6), _p(cp),
+                       cp.shape[0], _p(ov), _p(mg), _p(pix), P, int(brute),
+                       int(threads or os.cpu_count() or 1), _p(out), _p(T), _p(cnt), _p(tie),
+                       _p(wc))
+    return dict(out=out, T=T, n_contrib=cnt[:, 0], last=cnt[:, 1], tie=tie, wcount=wc)
+
+
+def backward(scene, cams, pix, G, opts=None, *, params64=None, threads=None):
+    """Binary64 gradients of L = sum_p <G_p, out_p> over pixels ``pix``.
+
+    Returns dict of gradients (means [N,3], scales [N,3], rotations [N,4],
+    opacities [N], sh [N,K,3]) and the same keys with suffix ``_abs``: sums
+    of the absolute per-pixel terms, a scale for tolerances.
+    """
+    lib = _load()
+    m, s, r, o, sh, t = _f32(scene)
+    m6, s6, r6, o6, sh6 = _f64(scene, params64)
+    cp = pack_cams(cams)
+    pix = np.ascontiguousarray(pix, np.int32)
+    G = np.ascontiguousarray(G, np.float64)
+    n = m.shape[0]
+    K = sh.shape[1]
+    gp = np.zeros((n, 11), np.float64)
+    ap = np.zeros((n, 11), np.float64)
+    gs = np.zeros((n, K, 3), np.float64)
+    as_ = np.zeros((n, K, 3), np.float64)
+    lib.oracle_backward(_p(m), _p(s), _p(r), _p(o), _p(sh), _p(t), n, int(scene["sh_degree"]),
+                        _p(m6), _p(s6), _p(r6), _p(o6), _p(sh6), _p(cp), cp.shape[0],
+                        _p(_opts_vec(opts)), _p(pix), pix.shape[0], _p(G),
+                        int(threads or os.cpu_count() or 1), _p(gp), _p(gs), _p(ap), _p(as_))
+    return dict(means=gp[:, 0:3], scales=gp[:, 3:6], rotations=gp[:, 6:10], opacities=gp[:, 10],
+                sh=gs, means_abs=ap[:, 0:3], scales_abs=ap[:, 3:6], rotations_abs=ap[:, 6:10],
+                opacities_abs=ap[:, 10], sh_abs=as_)
+
+
+def sh_basis(degree, dirs):
+    lib = _load()
+    d = np.ascontiguousarray(dirs, np.float64)
+    K = (degree + 1) ** 2
+    Y = np.zeros((d.shape[0], K), np.float64)
+    lib.oracle_sh_basis(int(degree), _p(d), d.shape[0], _p(Y))
+    return Y
+
+
+def surfel_uv(params10, cam, pxy):
+    lib = _load()
+    prm = np.ascontiguousarray(params10, np.float64)
+    pxy = np.ascontiguousarray(pxy, np.float64)
+    out = np.zeros((pxy.shape[0], 3), np.float64)
+    lib.oracle_surfel_uv(_p(prm), _p(pack_cams(cam)), _p(pxy), pxy.shape[0], _p(out))
+    return out
+
+
+def images(res, cam, n_views=1):
+    """Reshape a full-image ``forward`` result into [V,C,H,W] arrays."""
+    H, W = cam["height"], cam["width"]
+    o = res["out"].reshape(n_views, H, W, 8)
+    return dict(rgb=o[..., 0:3].transpose(0, 3, 1, 2), alpha=o[..., 3:4].transpose(0, 3, 1, 2),
+                depth=o[..., 4:5].transpose(0, 3, 1, 2), normal=o[..., 5:8].transpose(0, 3, 1, 2),
+                T=res["T"].reshape(n_views, H, W), n_contrib=res["n_contrib"].reshape(n_views, H, W),
+                last=res["last"].reshape(n_views, H, W), tie=res["tie"].reshape(n_views, H, W))

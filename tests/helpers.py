@@ -1,0 +1,44 @@
+"""Small builders shared by the tests (scene assembly and packing only)."""
+import numpy as np
+
+
+def make_scene(means, scales, quats, opac, sh, types):
+    means = np.asarray(means, np.float32).reshape(-1, 3)
+    n = means.shape[0]
+    sh = np.asarray(sh, np.float32).reshape(n, -1, 3)
+    return dict(means=means, scales=np.asarray(scales, np.float32).reshape(n, 3),
+                rotations=np.asarray(quats, np.float32).reshape(n, 4),
+                opacities=np.asarray(opac, np.float32).reshape(n),
+                sh=sh, types=np.asarray(types, np.uint8).reshape(n),
+                sh_degree=int(round(np.sqrt(sh.shape[1]))) - 1)
+
+
+def axis_camera(z=4.0, W=64, H=64, f=64.0, cx=None, cy=None):
+    V = np.eye(4, dtype=np.float32)
+    V[2, 3] = z
+    return dict(viewmat=V, fx=float(f), fy=float(f), cx=float(W / 2 if cx is None else cx),
+                cy=float(H / 2 if cy is None else cy), width=W, height=H, znear=0.2)
+
+
+def pack_G(G, v=0):
+    """[V,C,H,W] upstream gradient dict -> [P,8] in oracle pixel order."""
+    rgb = G["rgb"][v].reshape(3, -1).T
+    a = G["alpha"][v].reshape(1, -1).T
+    d = G["depth"][v].reshape(1, -1).T
+    n = G["normal"][v].reshape(3, -1).T
+    return np.ascontiguousarray(np.concatenate([rgb, a, d, n], 1), np.float64)
+
+
+def grad_close(g, ref, ref_abs, rtol=1e-3):
+    """Per-element |g - ref| <= rtol (|ref| + sum|terms|)."""
+    g = np.asarray(g, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = np.abs(ref) + np.asarray(ref_abs, np.float64)
+    bad = np.abs(g - ref) > rtol * scale + 1e-12
+    return bad
+
+
+def rel_l2(g, ref):
+    ref = np.asarray(ref, np.float64)
+    den = np.linalg.norm(ref)
+    return float(np.linalg.norm(np.asarray(g, np.float64) - ref) / (den if den > 0 else 1.0))
