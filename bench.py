@@ -1,0 +1,189 @@
+#!/usr/bin/env python
+"""Benchmark of the hybrid 2D/3D rasterizer on one MI355X.
+
+Headline metric: training-step throughput, forward + backward, in
+Mpixels/s, on 1M hybrid Gaussians (50/50 surfels / 3D Gaussians on a noisy
+(2,3) torus knot, SH degree 3) rendered at 1920x1080, with N(0,1)
+cotangents on every output channel.  A step is one pass of the whole
+rendering hot path:
+  preprocess, scan, duplicate, radix sort, ranges, raster forward,
+  raster backward, preprocess backward.
+Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line (rank 0).  It carries a `roofline` object for the
+dominant kernel and a `cpu_baseline` object for the CPU oracle, timed on a
+bounded band of image rows.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Per-pair VALU lane-operations of the minimal formulas (a transcendental
+# counts as 4 issue slots), used for the raster kernels' ALU roofline.
+OPS_FWD = {"3d": 27, "2d": 34}
+OPS_BWD = {"3d": 71, "2d": 82}
+# VALU issue peak with packed FP32 disabled: 256 CU x 64 lanes x 2.4 GHz.
+VALU_PEAK = 256 * 64 * 2.4e9
+HBM_PEAK = 8.0e12
+
+WORKLOADS = {
+    # name: (scene builder, camera builder, description)
+    "knot1m_1080p": ("scene_torus_knot", "camera_torus_knot_1080p",
+                     "torus-knot 1M hybrid Gaussians (50% surfels), SH3, 1920x1080, fwd+bwd"),
+    "knot1m_1600x1064": ("scene_torus_knot", "camera_torus_knot",
+                         "torus-knot 1M hybrid Gaussians (50% surfels), SH3, 1600x1064, fwd+bwd"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(scene_np, cam, G_np, rows: int):
+    """The CPU oracle (binary64, as it stands) on a band of `rows` image rows
+    through the centre of the image: forward + backward."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    H, W = cam["height"], cam["width"]
+    y0 = H // 2 - rows // 2
+    ys = np.arange(y0, y0 + rows)
+    pix = np.stack(np.meshgrid([0], ys, np.arange(W), indexing="ij"), -1).reshape(-1, 3)
+    pix = np.ascontiguousarray(pix, np.int32)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    v, y, x = pix[:, 0], pix[:, 1], pix[:, 2]
+    Gp = np.stack([G_np["rgb"][v, 0, y, x], G_np["rgb"][v, 1, y, x], G_np["rgb"][v, 2, y, x],
+                   G_np["alpha"][v, 0, y, x], G_np["depth"][v, 0, y, x],
+                   G_np["normal"][v, 0, y, x], G_np["normal"][v, 1, y, x],
+                   G_np["normal"][v, 2, y, x]], 1).astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.forward(scene_np, cam, pix, threads=cores)
+    oracle.backward(scene_np, cam, pix, Gp, threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(pix) / dt / 1e6, 6), "unit": "Mpixels/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"rows {y0}..{y0 + rows - 1} of {W}x{H} ({len(pix)} px), forward+backward, "
+                      f"binary64, {cores} threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="knot1m_1080p", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-rows", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import scenegen as sg
+    from paper_2512_02932_amd import _hgs
+    from paper_2512_02932_amd.rasterizer import get_rasterizer, pair_counts, to_device
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(3)
+    scene_fn, cam_fn, desc = WORKLOADS[args.workload]
+    log(f"[bench] generating {args.workload}")
+    scene_np = getattr(sg, scene_fn)()
+    cam = getattr(sg, cam_fn)()
+    H, W = cam["height"], cam["width"]
+    G_np = sg.upstream_grads(1, H, W, seed=3)
+
+    rast = get_rasterizer(0)
+    sc = to_device(scene_np, "cuda")
+    G = {k: torch.from_numpy(v).cuda() for k, v in G_np.items()}
+    grads = {k: torch.empty_like(sc[k]) for k in ("means", "scales", "rotations", "opacities", "sh")}
+    images = rast.alloc_images(1, H, W)
+    torch.cuda.synchronize()
+
+    def step():
+        _, state = rast.render(sc, cam, images=images, want_state=True)
+        rast.backward(state, G, grads)
+        state.free()
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # work accounting of this workload (identical every step)
+    _, st = rast.render(sc, cam, images=images, want_state=True)
+    counts = pair_counts(st)
+    sizes = st.sizes()
+    st.free()
+    torch.cuda.synchronize()
+
+    _hgs.hgs_profile_enable(rast.ctx, True)
+    _hgs.hgs_profile_read(rast.ctx, reset=True)
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = _hgs.hgs_profile_read(rast.ctx, reset=True)
+    _hgs.hgs_profile_enable(rast.ctx, False)
+
+    ms = (t1 - t0) * 1e3 / args.steps
+    P = H * W
+    value = P / (ms * 1e-3) / 1e6
+    stage_ms = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+    log("[bench] per-launch ms: " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
+    log(f"[bench] counts {counts} D={sizes['D']}")
+
+    # dominant kernel (the stages are single kernels except scan/sort/ranges)
+    dom = max(("raster_fwd", "raster_bwd", "preprocess", "preprocess_bwd"), key=lambda k: stage_ms[k])
+    if dom in ("raster_fwd", "raster_bwd"):
+        ops = OPS_FWD if dom == "raster_fwd" else OPS_BWD
+        key = "fwd" if dom == "raster_fwd" else "blend"
+        work = counts[f"{key}_3d"] * ops["3d"] + counts[f"{key}_2d"] * ops["2d"]
+        achieved = work / (stage_ms[dom] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK / 1e12, 4),
+                "unit": "Tops/s", "frac": round(achieved / (VALU_PEAK / 1e12), 4), "traffic": None,
+                "kernel": f"{dom}_kernel"}
+    else:
+        N = scene_np["means"].shape[0]
+        K = scene_np["sh"].shape[1]
+        byt = (N * (45 + 12 * K) + N * 88) if dom == "preprocess" else (N * 136 + 2 * N * (45 + 12 * K))
+        achieved = byt / (stage_ms[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": round(achieved / (HBM_PEAK / 1e9), 4), "traffic": None,
+                "kernel": f"{dom}_kernel"}
+
+    out = {
+        "metric": "fwd+bwd Mpixels/s @1M hybrid Gaussians 1080p; served-view p50/p99 ms",
+        "value": round(value, 3), "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": desc, "gaussians": int(scene_np["means"].shape[0]),
+                   "width": W, "height": H, "sh_degree": 3, "pairs_D": int(sizes["D"]),
+                   "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline on {args.cpu_rows} rows")
+        out["cpu_baseline"] = cpu_baseline(scene_np, cam, G_np, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * hgs.h - C ABI of the MI355X (gfx950) hybrid 2D/3D Gaussian rasterizer.
+ *
+ * What it renders (EGGS, "Exchangeable 2D/3D Gaussian Splatting"):
+ *   Sec. 3.1 "Hybrid Gaussian Rasterization".  A primitive has a centre mu,
+ *   scales s, a quaternion r, an opacity alpha, SH colour coefficients f and a
+ *   type flag t (0 = 2D surfel, 1 = 3D Gaussian).  Eq. 1 gives the distance
+ *   d_i: for t = 0, u^2 + v^2 at the ray-splat intersection (appendix on
+ *   rasterization, Eq. uv); for t = 1, the Mahalanobis distance under the
+ *   affine projection Sigma' = J W Sigma W^T J^T.  Each pair contributes
+ *   alpha_i exp(-d_i/2), and all pairs are composited front to back in one
+ *   pass (Eq. 2).  2D opacities are modulated by
+ *   alpha* = alpha exp(-lambda_z s_z*), s_z* = sigmoid((s_z - theta_z)/T_z) s_z
+ *   (Sec. 3.2, Eq. 6-7).
+ *
+ * Readings the paper leaves open, fixed here:
+ *   - pixel (x, y) is sampled at (x + 1/2, y + 1/2);
+ *   - cameras use OpenCV axes (x right, y down, z forward);
+ *   - a pair with alpha_i exp(-d_i/2) < 1/255 is skipped;
+ *   - a contribution is clamped at 0.99;
+ *   - a pixel stops before the pair that would take its transmittance
+ *     below 1e-4;
+ *   - 3D splats add delta (opts.dilation) to the diagonal of Sigma';
+ *   - depth and normal outputs are accumulated with the blend weights and
+ *     are not divided by alpha.
+ *
+ * Conventions
+ *   - Every pointer is a device pointer unless marked [host].
+ *   - Arrays are C-contiguous float32.  N = number of primitives,
+ *     K = (sh_degree+1)^2, V = number of views, H x W = image size.
+ *   - Every call validates its arguments on the host, enqueues work on
+ *     `stream` (a hipStream_t; NULL = the null stream) and returns a status.
+ *     Calls on one context must be serialised by the caller (one host thread,
+ *     one stream at a time).
+ *   - Asynchronous device errors show up in hgs_state_check or in the next
+ *     call that synchronises.
+ *   - No exception crosses this boundary.  On error, hgs_last_error() returns
+ *     a message.
+ *   - NaN/Inf parameters are not errors.  Every comparison that decides
+ *     culling or activity is false for NaN, so such a primitive or pair is
+ *     dropped.
+ */
+#ifndef HGS_H
+#define HGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hgs_ctx hgs_ctx;
+typedef struct hgs_state hgs_state;
+typedef int32_t hgs_status;
+
+enum {
+  HGS_OK = 0,
+  HGS_EINVAL = -1,    /* bad argument (null pointer, size out of range, ...) */
+  HGS_ENOMEM = -2,    /* device or host allocation failed */
+  HGS_EHIP = -3,      /* a HIP runtime call failed */
+  HGS_ECAPACITY = -4, /* more (tile, splat) pairs than 2^32 - 1 */
+  HGS_ESTATE = -5     /* state used in the wrong way (e.g. backward twice) */
+};
+
+/* Scene parameters, Sec. 3.1.  Activated values: scales >= 0 (a 2D surfel
+ * has s_z = 0 at initialisation and ignores it except through Eq. 6-7),
+ * opacity in (0, 1).  Layouts: means [N,3], scales [N,3], rotations [N,4]
+ * as (w, x, y, z), not necessarily unit length (normalised inside),
+ * opacities [N], sh [N,K,3] (coefficient-major, channel-last), types [N]
+ * uint8 (0 = 2D surfel, anything else = 3D Gaussian).  The caller owns
+ * every array. */
+typedef struct {
+  int64_t n;
+  int32_t sh_degree; /* 0..3 */
+  const float *means, *scales, *rotations, *opacities, *sh;
+  const uint8_t *types;
+} hgs_scene_desc;
+
+/* [host] A pinhole camera.  viewmat: row-major 4x4 world->camera, last row
+ * (0,0,0,1).  fx, fy, cx, cy in pixels.  width, height in [1, 16384].
+ * znear > 0: a 3D centre, or any point of a 2D surfel's support disc, at
+ * z <= znear culls the primitive. */
+typedef struct {
+  float viewmat[16];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float znear;
+} hgs_camera;
+
+/* [host] Render options.  Defaults: bg = 0, dilation = 0.3 px^2,
+ * lambda_z = 1, theta_z = 1.05, temp_z = 0.001 (Eq. 7's constants are the
+ * paper's, appendix "Implementation Details"). */
+typedef struct {
+  float bg[3];
+  float dilation;
+  float lambda_z, theta_z, temp_z;
+} hgs_opts;
+
+/* Output images, each [V,C,H,W]: rgb C=3, alpha C=1 (= 1 - T_final),
+ * depth C=1 (sum of weight x camera z), normal C=3 (sum of weight x
+ * camera-space unit normal facing the camera).  Any pointer may be NULL,
+ * and that channel is then not written. */
+typedef struct {
+  float *rgb, *alpha, *depth, *normal;
+} hgs_images;
+
+/* Upstream gradients dL/d(image), same shapes as hgs_images.  A NULL
+ * pointer means zero. */
+typedef struct {
+  const float *rgb, *alpha, *depth, *normal;
+} hgs_grad_images;
+
+/* Parameter gradients, same shapes as hgs_scene_desc (opacities and scales
+ * are gradients with respect to the activated values).  accumulate != 0
+ * adds into the arrays; 0 overwrites them.  Any pointer may be NULL. */
+typedef struct {
+  float *means, *scales, *rotations, *opacities, *sh;
+  int32_t accumulate;
+} hgs_grads;
+
+/* Create a context on HIP device `device`.  The context owns the device
+ * workspaces and the resident scenes. */
+hgs_status hgs_create(int32_t device, hgs_ctx **out);
+void hgs_destroy(hgs_ctx *ctx);
+
+/* Register a scene.  copy_resident = 1 copies the arrays into
+ * library-owned device memory (serving); 0 borrows the caller's pointers,
+ * which must stay valid (and may be updated in place between calls) until
+ * hgs_scene_release (training).  Returns an id >= 0 through scene_id. */
+hgs_status hgs_scene_init(hgs_ctx *ctx, const hgs_scene_desc *desc, int32_t copy_resident,
+                          int32_t *scene_id);
+hgs_status hgs_scene_release(hgs_ctx *ctx, int32_t scene_id);
+
+/* Forward render of scene `scene_id` into V = n_views views that share one
+ * image size (Sec. 3.1, Eq. 1-2).  The pipeline is: preprocess (cull,
+ * project, SH -> RGB, screen rectangle), exclusive scan, duplicate with
+ * (tile, depth) keys, LSD radix sort, tile ranges, per-16x16-tile
+ * compositing.
+ *
+ * `cams` [host] has n_views entries.  If `state` is not NULL, the call
+ * returns in *state a library-owned handle.  The handle keeps what the
+ * backward needs: per-splat records, the sorted list, tile ranges, final
+ * transmittance and the last contributor per pixel.  Free it with
+ * hgs_state_free.  Opts may be NULL (defaults).
+ *
+ * The call synchronises `stream` once, to read the number of (tile, splat)
+ * pairs and size the sort buffers. */
+hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, int32_t n_views,
+                      const hgs_opts *opts, const hgs_images *out, hgs_state **state,
+                      void *stream);
+
+/* Backward of the render that produced `state`: gradients of
+ * L = sum <grad_out, images> with respect to means, scales (including s_z of
+ * 2D surfels through Eq. 6-7), rotations, opacities and SH coefficients,
+ * summed over the views.  Transmittance is recovered in reverse order; no
+ * per-pixel list is stored.  The scene's parameters must be unchanged since
+ * the forward.  May be called more than once on a state. */
+hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *state, const hgs_grad_images *grad_out,
+                               const hgs_grads *grads, void *stream);
+
+void hgs_state_free(hgs_ctx *ctx, hgs_state *state);
+
+/* Sizes kept in a state: [0] V*N, [1] number of (tile, splat) pairs D,
+ * [2] total tiles, [3] pixels per view (H*W), [4] V. */
+hgs_status hgs_state_sizes(hgs_ctx *ctx, hgs_state *state, int64_t *sizes5 /* [host] */);
+
+/* Copy one internal array of a state to host memory, for parity tests.
+ * `what`:
+ *   0 sorted keys   u64[D]
+ *   1 sorted values u32[D]  (value = view * N + splat)
+ *   2 tile ranges   u32[T,2]
+ *   3 pixel rectangles of every (view, splat), i32[V*N,4]
+ *     (x0, y0, x1, y1 inclusive; garbage where tiles == 0)
+ *   4 tiles touched u32[V*N]  (0 = culled)
+ *   5 depth keys    u32[V*N]
+ *   6 T_final       f32[V,H,W]
+ *   7 last          u32[V,H,W]  (1 + list position of the last blended
+ *                               pair within its tile, 0 if none)
+ *   8 n_contrib     u32[V,H,W]
+ *   9 pair counts   u32[V,H,W]  (bits 0-14 blended 3D pairs, 15-29 blended
+ *                               2D pairs, bit 30 the pair that stopped the
+ *                               pixel was 2D, bit 31 the pixel stopped)
+ * `capacity` is the size of dst in bytes.  The call synchronises. */
+hgs_status hgs_state_debug(hgs_ctx *ctx, hgs_state *state, int32_t what, void *dst_host,
+                           int64_t capacity);
+
+/* Synchronise the state's stream and report any asynchronous error. */
+hgs_status hgs_state_check(hgs_ctx *ctx, hgs_state *state);
+
+/* Per-stage timing.  While enabled, every render/backward call records a
+ * HIP event pair around each stage on the stream it enqueues on.
+ * hgs_profile_read synchronises those events and returns the accumulated
+ * milliseconds per stage in ms[HGS_N_STAGES] and the number of launches in
+ * calls[HGS_N_STAGES] (either may be NULL); reset != 0 clears the totals. */
+enum {
+  HGS_STAGE_PREPROCESS = 0,
+  HGS_STAGE_SCAN = 1,
+  HGS_STAGE_DUPLICATE = 2,
+  HGS_STAGE_SORT = 3,
+  HGS_STAGE_RANGES = 4,
+  HGS_STAGE_RASTER_FWD = 5,
+  HGS_STAGE_RASTER_BWD = 6,
+  HGS_STAGE_PREPROCESS_BWD = 7,
+  HGS_STAGE_FILL = 8,
+  HGS_N_STAGES = 9
+};
+hgs_status hgs_profile_enable(hgs_ctx *ctx, int32_t on);
+hgs_status hgs_profile_read(hgs_ctx *ctx, double *ms, int64_t *calls, int32_t reset);
+
+/* Message of the last error on this host thread ("" if none). */
+const char *hgs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGS_H */

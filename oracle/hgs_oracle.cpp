@@ -50,6 +50,7 @@
 #include <cstdint>
 #include <cstring>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 namespace {
@@ -722,7 +723,7 @@ void render_pixel(const Work &w, const SplatCache &cache, int v, int x, int y,
   seq.clear();
   for (const PairRec &pr : cand) {
     if (std::fabs(pr.raw - kAlphaMin) <= mg.alpha_rel * kAlphaMin) po.tie |= 1;
-    if (!(pr.alpha >= kAlphaMin)) continue;
+    if (!(pr.raw >= kAlphaMin)) continue;  // false for NaN (std::min would hide it)
     po.wcount[w.s32->types[pr.g] == 0 ? 0 : 1] += 1;
     const double Tn = T * (1.0 - pr.alpha);
     if (std::fabs(Tn - kTMin) <= mg.t_rel * kTMin) po.tie |= 2;
@@ -836,7 +837,7 @@ int oracle_forward(const float *m32, const float *s32, const float *r32, const f
   build(w, cams, V, brute != 0);
   const Margins mg{margins[0], margins[1], margins[2]};
   SplatCache cache;
-  if (P > 4096) build_cache(w, cache, threads);
+  if (4 * P >= n) build_cache(w, cache, threads);
   std::vector<int64_t> wc(2 * std::max(1, threads), 0);
   parallel_for(P, threads, [&](int t, int64_t a, int64_t b) {
     std::vector<PairRec> seq;
@@ -880,16 +881,24 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
   build(w, cams, V, false);
   const Margins mg{0, 0, 0};
   SplatCache cache;
-  if (P > 4096) build_cache(w, cache, threads);
+  if (4 * P >= n) build_cache(w, cache, threads);
   const int K = (sh_degree + 1) * (sh_degree + 1);
   const int nt = std::max(1, threads);
-  std::vector<std::vector<double>> gp(nt), ap(nt), gs(nt), as(nt);
+  // Per-thread sparse accumulators: splat -> slot of [NP params | NP abs |
+  // 3K sh | 3K sh abs].  Merged in thread order (deterministic).
+  const size_t slot = (size_t)2 * NP + (size_t)6 * K;
+  std::vector<std::unordered_map<int64_t, size_t>> where(nt);
+  std::vector<std::vector<double>> acc(nt);
   parallel_for(P, threads, [&](int t, int64_t a, int64_t b) {
-    gp[t].assign((size_t)n * NP, 0.0);
-    ap[t].assign((size_t)n * NP, 0.0);
-    gs[t].assign((size_t)n * K * 3, 0.0);
-    as[t].assign((size_t)n * K * 3, 0.0);
     std::vector<PairRec> seq;
+    auto cell = [&](int64_t g) -> double * {
+      auto it = where[t].find(g);
+      if (it == where[t].end()) {
+        it = where[t].emplace(g, acc[t].size()).first;
+        acc[t].resize(acc[t].size() + slot, 0.0);
+      }
+      return acc[t].data() + it->second;
+    };
     for (int64_t i = a; i < b; ++i) {
       const int v = pix[3 * i], y = pix[3 * i + 1], x = pix[3 * i + 2];
       PixelOut po;
@@ -923,23 +932,22 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
         Ssuf = f[j] * al + (1.0 - al) * Ssuf;
         const double wgt = al * T[j];
         const Splat<Dual> &sp = sps[j];
-        double *gg = &gp[t][(size_t)g * NP];
-        double *ga = &ap[t][(size_t)g * NP];
+        double *c = cell(g);
+        double *gg = c, *ga = c + NP, *gs = c + 2 * NP, *as = c + 2 * NP + 3 * K;
         for (int q = 0; q < NP; ++q) {
-          double terms[9];
+          double terms[8];
           terms[0] = dLda * aa[j].d[q];
           terms[1] = wgt * Gp[4] * dep[j].d[q];
           for (int k = 0; k < 3; ++k) terms[2 + k] = wgt * Gp[5 + k] * sp.nrm[k].d[q];
           for (int k = 0; k < 3; ++k) terms[5 + k] = wgt * Gp[k] * sp.color[k].d[q];
-          terms[8] = 0.0;
           for (int k = 0; k < 8; ++k) { gg[q] += terms[k]; ga[q] += std::fabs(terms[k]); }
         }
         for (int ch = 0; ch < 3; ++ch) {
           if (sp.clamped[ch]) continue;
           const double dc = wgt * Gp[ch];
           for (int jj = 0; jj < K; ++jj) {
-            gs[t][((size_t)g * K + jj) * 3 + ch] += dc * sp.Y[jj];
-            as[t][((size_t)g * K + jj) * 3 + ch] += std::fabs(dc * sp.Y[jj]);
+            gs[jj * 3 + ch] += dc * sp.Y[jj];
+            as[jj * 3 + ch] += std::fabs(dc * sp.Y[jj]);
           }
         }
       }
@@ -950,9 +958,20 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
   std::memset(g_sh, 0, sizeof(double) * n * K * 3);
   std::memset(a_sh, 0, sizeof(double) * n * K * 3);
   for (int t = 0; t < nt; ++t) {
-    if (gp[t].empty()) continue;
-    for (size_t i = 0; i < (size_t)n * NP; ++i) { g_params[i] += gp[t][i]; a_params[i] += ap[t][i]; }
-    for (size_t i = 0; i < (size_t)n * K * 3; ++i) { g_sh[i] += gs[t][i]; a_sh[i] += as[t][i]; }
+    std::vector<std::pair<int64_t, size_t>> order(where[t].begin(), where[t].end());
+    std::sort(order.begin(), order.end());
+    for (const auto &e : order) {
+      const double *c = acc[t].data() + e.second;
+      const int64_t g = e.first;
+      for (int q = 0; q < NP; ++q) {
+        g_params[g * NP + q] += c[q];
+        a_params[g * NP + q] += c[NP + q];
+      }
+      for (int j = 0; j < 3 * K; ++j) {
+        g_sh[g * 3 * K + j] += c[2 * NP + j];
+        a_sh[g * 3 * K + j] += c[2 * NP + 3 * K + j];
+      }
+    }
   }
   return 0;
 }

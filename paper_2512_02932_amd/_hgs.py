@@ -1,0 +1,171 @@
+"""ctypes binding of ``libhgs.so`` (include/hgs.h).  Argument marshalling only.
+
+The functions carry the C names (``hgs_create``, ``hgs_render`` ...).  Every
+step of the render runs in the HIP library.  If the library is missing, the
+load raises immediately; nothing falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgs.so")
+
+HGS_OK, HGS_EINVAL, HGS_ENOMEM, HGS_EHIP, HGS_ECAPACITY, HGS_ESTATE = 0, -1, -2, -3, -4, -5
+
+EXPORTS = ("hgs_create", "hgs_destroy", "hgs_scene_init", "hgs_scene_release", "hgs_render",
+           "hgs_render_backward", "hgs_state_free", "hgs_state_sizes", "hgs_state_debug",
+           "hgs_state_check", "hgs_last_error", "hgs_profile_enable", "hgs_profile_read")
+
+STAGES = ("preprocess", "scan", "duplicate", "sort", "ranges", "raster_fwd", "raster_bwd",
+          "preprocess_bwd", "fill")
+
+
+class hgs_scene_desc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32),
+                ("means", C.c_void_p), ("scales", C.c_void_p), ("rotations", C.c_void_p),
+                ("opacities", C.c_void_p), ("sh", C.c_void_p), ("types", C.c_void_p)]
+
+
+class hgs_camera(C.Structure):
+    _fields_ = [("viewmat", C.c_float * 16), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int32),
+                ("height", C.c_int32), ("znear", C.c_float)]
+
+
+class hgs_opts(C.Structure):
+    _fields_ = [("bg", C.c_float * 3), ("dilation", C.c_float), ("lambda_z", C.c_float),
+                ("theta_z", C.c_float), ("temp_z", C.c_float)]
+
+
+class hgs_images(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("alpha", C.c_void_p), ("depth", C.c_void_p),
+                ("normal", C.c_void_p)]
+
+
+class hgs_grad_images(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("alpha", C.c_void_p), ("depth", C.c_void_p),
+                ("normal", C.c_void_p)]
+
+
+class hgs_grads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("rotations", C.c_void_p),
+                ("opacities", C.c_void_p), ("sh", C.c_void_p), ("accumulate", C.c_int32)]
+
+
+class HGSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hgs status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load the HIP library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built; run paper_2512_02932_amd.build.build() "
+                           "(or __graft_entry__.build()) first")
+    lib = C.CDLL(p)
+    P = C.c_void_p
+    lib.hgs_create.argtypes = [C.c_int32, C.POINTER(P)]
+    lib.hgs_destroy.argtypes = [P]
+    lib.hgs_destroy.restype = None
+    lib.hgs_scene_init.argtypes = [P, C.POINTER(hgs_scene_desc), C.c_int32, C.POINTER(C.c_int32)]
+    lib.hgs_scene_release.argtypes = [P, C.c_int32]
+    lib.hgs_render.argtypes = [P, C.c_int32, C.POINTER(hgs_camera), C.c_int32,
+                               C.POINTER(hgs_opts), C.POINTER(hgs_images), C.POINTER(P), P]
+    lib.hgs_render_backward.argtypes = [P, P, C.POINTER(hgs_grad_images), C.POINTER(hgs_grads), P]
+    lib.hgs_state_free.argtypes = [P, P]
+    lib.hgs_state_free.restype = None
+    lib.hgs_state_sizes.argtypes = [P, P, C.POINTER(C.c_int64)]
+    lib.hgs_state_debug.argtypes = [P, P, C.c_int32, P, C.c_int64]
+    lib.hgs_state_check.argtypes = [P, P]
+    lib.hgs_profile_enable.argtypes = [P, C.c_int32]
+    lib.hgs_profile_read.argtypes = [P, P, P, C.c_int32]
+    lib.hgs_last_error.argtypes = []
+    lib.hgs_last_error.restype = C.c_char_p
+    for name in ("hgs_create", "hgs_scene_init", "hgs_scene_release", "hgs_render",
+                 "hgs_render_backward", "hgs_state_sizes", "hgs_state_debug", "hgs_state_check",
+                 "hgs_profile_enable", "hgs_profile_read"):
+        getattr(lib, name).restype = C.c_int32
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != HGS_OK:
+        msg = _lib.hgs_last_error().decode() if _lib is not None else ""
+        raise HGSError(status, msg)
+
+
+# --- thin wrappers with the C names -----------------------------------------
+def hgs_create(device: int = 0):
+    lib = load()
+    h = C.c_void_p()
+    check(lib.hgs_create(int(device), C.byref(h)))
+    return h
+
+
+def hgs_destroy(ctx):
+    load().hgs_destroy(ctx)
+
+
+def hgs_scene_init(ctx, desc: hgs_scene_desc, copy_resident: int) -> int:
+    sid = C.c_int32()
+    check(load().hgs_scene_init(ctx, C.byref(desc), int(copy_resident), C.byref(sid)))
+    return sid.value
+
+
+def hgs_scene_release(ctx, scene_id: int):
+    check(load().hgs_scene_release(ctx, int(scene_id)))
+
+
+def hgs_render(ctx, scene_id, cams, opts, images, want_state: bool, stream: int):
+    """cams: ctypes array of hgs_camera; returns a state handle or None."""
+    st = C.c_void_p()
+    check(load().hgs_render(ctx, int(scene_id), cams, len(cams),
+                            C.byref(opts) if opts is not None else None, C.byref(images),
+                            C.byref(st) if want_state else None, C.c_void_p(stream)))
+    return st if want_state else None
+
+
+def hgs_render_backward(ctx, state, grad_images, grads, stream: int):
+    check(load().hgs_render_backward(ctx, state, C.byref(grad_images), C.byref(grads),
+                                     C.c_void_p(stream)))
+
+
+def hgs_state_free(ctx, state):
+    load().hgs_state_free(ctx, state)
+
+
+def hgs_state_sizes(ctx, state):
+    arr = (C.c_int64 * 5)()
+    check(load().hgs_state_sizes(ctx, state, arr))
+    return list(arr)
+
+
+def hgs_state_debug(ctx, state, what: int, dst_ptr: int, capacity: int):
+    check(load().hgs_state_debug(ctx, state, int(what), C.c_void_p(dst_ptr), int(capacity)))
+
+
+def hgs_state_check(ctx, state):
+    check(load().hgs_state_check(ctx, state))
+
+
+def hgs_profile_enable(ctx, on: bool):
+    check(load().hgs_profile_enable(ctx, 1 if on else 0))
+
+
+def hgs_profile_read(ctx, reset: bool = False):
+    """Returns {stage: (total_ms, launches)}."""
+    ms = (C.c_double * len(STAGES))()
+    calls = (C.c_int64 * len(STAGES))()
+    check(load().hgs_profile_read(ctx, ms, calls, 1 if reset else 0))
+    return {name: (ms[i], calls[i]) for i, name in enumerate(STAGES)}

@@ -1,0 +1,626 @@
+// C ABI of the hybrid rasterizer: argument validation, workspace management
+// and the launch sequence.  Declarations and contracts are in include/hgs.h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hgs.h"
+#include "hgs_internal.h"
+
+using namespace hgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+hgs_status fail(hgs_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HGS_HIP(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? HGS_ENOMEM : HGS_EHIP,                    \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+  } while (0)
+
+struct Scene {
+  bool used = false;
+  bool resident = false;
+  SceneDev dev{};
+  void *buf = nullptr;
+};
+
+}  // namespace
+
+struct StageEvent {
+  int stage;
+  hipEvent_t a, b;
+};
+
+struct hgs_ctx {
+  int device = 0;
+  std::vector<Scene> scenes;
+  bool profile = false;
+  std::vector<StageEvent> pending;
+  std::vector<hipEvent_t> event_pool;
+  double stage_ms[HGS_N_STAGES] = {0};
+  int64_t stage_calls[HGS_N_STAGES] = {0};
+};
+
+struct hgs_state {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  SceneDev scene{};
+  int V = 0;
+  int64_t N = 0;
+  int W = 0, H = 0, tiles_x = 0, tiles_y = 0, tiles_per_view = 0, n_tiles = 0;
+  DevOpts opt{};
+  std::vector<DevCam> cams_host;
+  DevCam *cams = nullptr;
+  Record *rec = nullptr;
+  uint32_t *tiles = nullptr, *zbits = nullptr, *offsets = nullptr;
+  int4 *rect = nullptr;
+  uint64_t *total = nullptr;
+  uint64_t *keys = nullptr;
+  uint32_t *vals = nullptr;
+  uint2 *ranges = nullptr;
+  float *T_final = nullptr;
+  uint32_t *last = nullptr, *n_contrib = nullptr, *wcount = nullptr;
+  int64_t D = 0;
+  std::vector<void *> allocs;
+};
+
+namespace {
+
+hipEvent_t pool_event(hgs_ctx *c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets the launches of one stage with events when profiling is on.
+struct StageTimer {
+  hgs_ctx *c;
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  StageTimer(hgs_ctx *ctx, int st, hipStream_t stream) : c(ctx), stage(st), s(stream) {
+    if (!c->profile) return;
+    a = pool_event(c);
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~StageTimer() {
+    if (!c->profile || !a) return;
+    hipEvent_t b = pool_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->pending.push_back(StageEvent{stage, a, b});
+  }
+};
+
+hipError_t dalloc(hgs_state *st, void **p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMallocAsync(p, bytes, st->stream);
+  if (e == hipSuccess) st->allocs.push_back(*p);
+  return e;
+}
+
+template <typename T>
+hipError_t dalloc_t(hgs_state *st, T **p, size_t count) {
+  return dalloc(st, reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+void release(hgs_state *st) {
+  if (!st) return;
+  for (void *p : st->allocs) (void)hipFreeAsync(p, st->stream);
+  st->allocs.clear();
+}
+
+DevOpts to_dev_opts(const hgs_opts *o) {
+  DevOpts d{};
+  if (o) {
+    for (int i = 0; i < 3; ++i) d.bg[i] = o->bg[i];
+    d.dilation = o->dilation;
+    d.lambda_z = o->lambda_z;
+    d.theta_z = o->theta_z;
+    d.temp_z = o->temp_z;
+  } else {
+    d.dilation = 0.3f;
+    d.lambda_z = 1.0f;
+    d.theta_z = 1.05f;
+    d.temp_z = 0.001f;
+  }
+  return d;
+}
+
+bool make_dev_cam(const hgs_camera &c, DevCam &d, int view, std::string &why) {
+  std::memset(&d, 0, sizeof(d));
+  for (int i = 0; i < 12; ++i) {
+    d.V[i] = c.viewmat[i];
+    d.Vd[i] = c.viewmat[i];
+  }
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(c.viewmat[i])) {
+      why = "camera " + std::to_string(view) + ": non-finite viewmat";
+      return false;
+    }
+  d.fx = c.fx;
+  d.fy = c.fy;
+  d.cx = c.cx;
+  d.cy = c.cy;
+  d.znear = c.znear;
+  d.W = c.width;
+  d.H = c.height;
+  if (!(std::isfinite(c.fx) && std::isfinite(c.fy) && c.fx != 0.0f && c.fy != 0.0f &&
+        std::isfinite(c.cx) && std::isfinite(c.cy))) {
+    why = "camera " + std::to_string(view) + ": bad intrinsics";
+    return false;
+  }
+  if (!(c.znear > 0.0f) || !std::isfinite(c.znear)) {
+    why = "camera " + std::to_string(view) + ": znear must be > 0";
+    return false;
+  }
+  if (c.width < 1 || c.width > 16384 || c.height < 1 || c.height > 16384) {
+    why = "camera " + std::to_string(view) + ": width/height must be in [1, 16384]";
+    return false;
+  }
+  d.tiles_x = (c.width + kTile - 1) / kTile;
+  d.tiles_y = (c.height + kTile - 1) / kTile;
+  const double *R = d.Vd;  // rows 0..2, stride 4
+  auto r = [&](int i, int j) { return R[4 * i + j]; };
+  const double det = r(0, 0) * (r(1, 1) * r(2, 2) - r(1, 2) * r(2, 1)) -
+                     r(0, 1) * (r(1, 0) * r(2, 2) - r(1, 2) * r(2, 0)) +
+                     r(0, 2) * (r(1, 0) * r(2, 1) - r(1, 1) * r(2, 0));
+  if (!(std::fabs(det) > 1e-12)) {
+    why = "camera " + std::to_string(view) + ": singular rotation";
+    return false;
+  }
+  double *Ri = d.Vinv;
+  Ri[0] = (r(1, 1) * r(2, 2) - r(1, 2) * r(2, 1)) / det;
+  Ri[1] = (r(0, 2) * r(2, 1) - r(0, 1) * r(2, 2)) / det;
+  Ri[2] = (r(0, 1) * r(1, 2) - r(0, 2) * r(1, 1)) / det;
+  Ri[3] = (r(1, 2) * r(2, 0) - r(1, 0) * r(2, 2)) / det;
+  Ri[4] = (r(0, 0) * r(2, 2) - r(0, 2) * r(2, 0)) / det;
+  Ri[5] = (r(0, 2) * r(1, 0) - r(0, 0) * r(1, 2)) / det;
+  Ri[6] = (r(1, 0) * r(2, 1) - r(1, 1) * r(2, 0)) / det;
+  Ri[7] = (r(0, 1) * r(2, 0) - r(0, 0) * r(2, 1)) / det;
+  Ri[8] = (r(0, 0) * r(1, 1) - r(0, 1) * r(1, 0)) / det;
+  const double t[3] = {R[3], R[7], R[11]};
+  for (int i = 0; i < 3; ++i) d.o[i] = -(Ri[3 * i] * t[0] + Ri[3 * i + 1] * t[1] + Ri[3 * i + 2] * t[2]);
+  return true;
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+hgs_status check_desc(const hgs_scene_desc *d) {
+  if (!d) return fail(HGS_EINVAL, "scene desc is NULL");
+  if (d->n < 0) return fail(HGS_EINVAL, "scene n < 0");
+  if (d->n > (int64_t)0x7fffffff) return fail(HGS_EINVAL, "scene n too large");
+  if (d->sh_degree < 0 || d->sh_degree > 3) return fail(HGS_EINVAL, "sh_degree must be 0..3");
+  if (d->n > 0 && (!d->means || !d->scales || !d->rotations || !d->opacities || !d->sh || !d->types))
+    return fail(HGS_EINVAL, "scene array pointer is NULL");
+  if (!aligned(d->means, 4) || !aligned(d->scales, 4) || !aligned(d->rotations, 4) ||
+      !aligned(d->opacities, 4) || !aligned(d->sh, 4))
+    return fail(HGS_EINVAL, "scene float arrays must be 4-byte aligned");
+  return HGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hgs_last_error(void) { return g_err.c_str(); }
+
+hgs_status hgs_create(int32_t device, hgs_ctx **out) {
+  if (!out) return fail(HGS_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HGS_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(HGS_EINVAL, "no such device");
+  HGS_HIP(hipSetDevice(device));
+  hipMemPool_t pool;
+  HGS_HIP(hipDeviceGetDefaultMemPool(&pool, device));
+  uint64_t thr = UINT64_MAX;
+  HGS_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+  hgs_ctx *c = new (std::nothrow) hgs_ctx();
+  if (!c) return fail(HGS_ENOMEM, "host allocation failed");
+  c->device = device;
+  *out = c;
+  return HGS_OK;
+}
+
+void hgs_destroy(hgs_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto &s : ctx->scenes)
+    if (s.used && s.buf) (void)hipFree(s.buf);
+  for (auto &p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+hgs_status hgs_scene_init(hgs_ctx *ctx, const hgs_scene_desc *desc, int32_t copy_resident,
+                          int32_t *scene_id) {
+  if (!ctx || !scene_id) return fail(HGS_EINVAL, "ctx or scene_id is NULL");
+  hgs_status st = check_desc(desc);
+  if (st != HGS_OK) return st;
+  HGS_HIP(hipSetDevice(ctx->device));
+  Scene s;
+  s.used = true;
+  s.resident = copy_resident != 0;
+  s.dev.n = desc->n;
+  s.dev.sh_degree = desc->sh_degree;
+  const int K = (desc->sh_degree + 1) * (desc->sh_degree + 1);
+  if (!s.resident) {
+    s.dev.means = desc->means;
+    s.dev.scales = desc->scales;
+    s.dev.rots = desc->rotations;
+    s.dev.opac = desc->opacities;
+    s.dev.sh = desc->sh;
+    s.dev.types = desc->types;
+  } else {
+    const size_t n = (size_t)desc->n;
+    const size_t fl = n * (3 + 3 + 4 + 1 + 3 * (size_t)K);
+    const size_t bytes = fl * sizeof(float) + n + 256;
+    void *buf = nullptr;
+    HGS_HIP(hipMalloc(&buf, bytes));
+    float *f = (float *)buf;
+    auto cp = [&](const float *src, size_t cnt) -> float * {
+      float *dst = f;
+      if (cnt) (void)hipMemcpy(dst, src, cnt * sizeof(float), hipMemcpyDeviceToDevice);
+      f += cnt;
+      return dst;
+    };
+    s.dev.means = cp(desc->means, 3 * n);
+    s.dev.scales = cp(desc->scales, 3 * n);
+    s.dev.rots = cp(desc->rotations, 4 * n);
+    s.dev.opac = cp(desc->opacities, n);
+    s.dev.sh = cp(desc->sh, 3 * K * n);
+    uint8_t *t = (uint8_t *)f;
+    if (n) {
+      hipError_t e = hipMemcpy(t, desc->types, n, hipMemcpyDeviceToDevice);
+      if (e != hipSuccess) {
+        (void)hipFree(buf);
+        return fail(HGS_EHIP, std::string("copying scene: ") + hipGetErrorString(e));
+      }
+    }
+    s.dev.types = t;
+    s.buf = buf;
+  }
+  for (size_t i = 0; i < ctx->scenes.size(); ++i)
+    if (!ctx->scenes[i].used) {
+      ctx->scenes[i] = s;
+      *scene_id = (int32_t)i;
+      return HGS_OK;
+    }
+  ctx->scenes.push_back(s);
+  *scene_id = (int32_t)(ctx->scenes.size() - 1);
+  return HGS_OK;
+}
+
+hgs_status hgs_scene_release(hgs_ctx *ctx, int32_t scene_id) {
+  if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
+  if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].used)
+    return fail(HGS_EINVAL, "bad scene id");
+  Scene &s = ctx->scenes[scene_id];
+  if (s.buf) {
+    HGS_HIP(hipSetDevice(ctx->device));
+    HGS_HIP(hipDeviceSynchronize());
+    HGS_HIP(hipFree(s.buf));
+  }
+  s = Scene();
+  return HGS_OK;
+}
+
+hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, int32_t n_views,
+                      const hgs_opts *opts, const hgs_images *out, hgs_state **state_out,
+                      void *stream) {
+  if (state_out) *state_out = nullptr;
+  if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
+  if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].used)
+    return fail(HGS_EINVAL, "bad scene id");
+  if (!cams || n_views < 1) return fail(HGS_EINVAL, "need at least one camera");
+  if (n_views > 4096) return fail(HGS_EINVAL, "too many views");
+  const Scene &sc = ctx->scenes[scene_id];
+  if (opts && !(opts->dilation >= 0.0f && std::isfinite(opts->dilation) &&
+                opts->temp_z > 0.0f && std::isfinite(opts->lambda_z) &&
+                std::isfinite(opts->theta_z) && std::isfinite(opts->temp_z)))
+    return fail(HGS_EINVAL, "bad opts (dilation >= 0, temp_z > 0, finite)");
+  const int W = cams[0].width, H = cams[0].height;
+  hgs_state *st = new (std::nothrow) hgs_state();
+  if (!st) return fail(HGS_ENOMEM, "host allocation failed");
+  st->stream = (hipStream_t)stream;
+  st->device = ctx->device;
+  st->scene = sc.dev;
+  st->V = n_views;
+  st->N = sc.dev.n;
+  st->W = W;
+  st->H = H;
+  st->opt = to_dev_opts(opts);
+  st->cams_host.resize(n_views);
+  std::string why;
+  for (int v = 0; v < n_views; ++v) {
+    if (!make_dev_cam(cams[v], st->cams_host[v], v, why)) {
+      delete st;
+      return fail(HGS_EINVAL, why);
+    }
+    if (cams[v].width != W || cams[v].height != H) {
+      delete st;
+      return fail(HGS_EINVAL, "all views of one call must share the image size");
+    }
+  }
+  st->tiles_x = st->cams_host[0].tiles_x;
+  st->tiles_y = st->cams_host[0].tiles_y;
+  st->tiles_per_view = st->tiles_x * st->tiles_y;
+  const int64_t n_tiles = (int64_t)st->tiles_per_view * n_views;
+  if (n_tiles > (int64_t)0x7fffffff) {
+    delete st;
+    return fail(HGS_EINVAL, "too many tiles");
+  }
+  st->n_tiles = (int)n_tiles;
+  for (int v = 0; v < n_views; ++v) st->cams_host[v].tile_base = v * st->tiles_per_view;
+  const int64_t VN = (int64_t)n_views * st->N;
+  if (VN > (int64_t)0xffffffffLL) {
+    delete st;
+    return fail(HGS_EINVAL, "views x primitives exceeds 2^32");
+  }
+  const int64_t P = (int64_t)n_views * W * H;
+
+  auto bail = [&](hgs_status s) {
+    release(st);
+    (void)hipStreamSynchronize(st->stream);
+    delete st;
+    return s;
+  };
+#define ST_HIP(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return bail(fail(e_ == hipErrorOutOfMemory ? HGS_ENOMEM : HGS_EHIP,               \
+                       std::string(#expr) + ": " + hipGetErrorString(e_)));             \
+  } while (0)
+
+  ST_HIP(hipSetDevice(ctx->device));
+  ST_HIP(dalloc_t(st, &st->cams, (size_t)n_views));
+  ST_HIP(hipMemcpyAsync(st->cams, st->cams_host.data(), sizeof(DevCam) * n_views,
+                        hipMemcpyHostToDevice, st->stream));
+  ST_HIP(dalloc_t(st, &st->rec, (size_t)VN));
+  ST_HIP(dalloc_t(st, &st->tiles, (size_t)VN));
+  ST_HIP(dalloc_t(st, &st->zbits, (size_t)VN));
+  ST_HIP(dalloc_t(st, &st->rect, (size_t)VN));
+  ST_HIP(dalloc_t(st, &st->offsets, (size_t)VN));
+  ST_HIP(dalloc_t(st, &st->total, (size_t)1));
+  void *scan_tmp = nullptr;
+  ST_HIP(dalloc(st, &scan_tmp, scan_tmp_bytes(VN)));
+  ST_HIP(dalloc_t(st, &st->ranges, (size_t)n_tiles));
+  ST_HIP(dalloc_t(st, &st->T_final, (size_t)P));
+  ST_HIP(dalloc_t(st, &st->last, (size_t)P));
+  ST_HIP(dalloc_t(st, &st->n_contrib, (size_t)P));
+  ST_HIP(dalloc_t(st, &st->wcount, (size_t)P));
+
+  {
+    StageTimer t(ctx, HGS_STAGE_PREPROCESS, st->stream);
+    launch_preprocess(st->scene, st->cams, n_views, st->opt, st->rec, st->tiles, st->zbits,
+                      st->rect, st->stream);
+  }
+  {
+    StageTimer t(ctx, HGS_STAGE_SCAN, st->stream);
+    launch_scan(st->tiles, st->offsets, VN, st->total, scan_tmp, st->stream);
+  }
+  uint64_t Dh = 0;
+  ST_HIP(hipMemcpyAsync(&Dh, st->total, sizeof(uint64_t), hipMemcpyDeviceToHost, st->stream));
+  ST_HIP(hipStreamSynchronize(st->stream));
+  ST_HIP(hipGetLastError());
+  if (Dh > 0xffffffffull) return bail(fail(HGS_ECAPACITY, "more than 2^32-1 (tile, splat) pairs"));
+  st->D = (int64_t)Dh;
+
+  uint64_t *kb = nullptr;
+  uint32_t *vb = nullptr;
+  void *sort_tmp = nullptr;
+  ST_HIP(dalloc_t(st, &st->keys, (size_t)st->D));
+  ST_HIP(dalloc_t(st, &st->vals, (size_t)st->D));
+  ST_HIP(dalloc_t(st, &kb, (size_t)st->D));
+  ST_HIP(dalloc_t(st, &vb, (size_t)st->D));
+  ST_HIP(dalloc(st, &sort_tmp, sort_tmp_bytes(st->D)));
+  {
+    StageTimer t(ctx, HGS_STAGE_DUPLICATE, st->stream);
+    launch_duplicate(st->offsets, st->tiles, st->rect, st->zbits, st->cams, n_views, st->N,
+                     st->keys, st->vals, st->stream);
+  }
+  int tile_bits = 0;
+  while ((int64_t(1) << tile_bits) < n_tiles) ++tile_bits;
+  int which = 0;
+  {
+    StageTimer t(ctx, HGS_STAGE_SORT, st->stream);
+    which = launch_radix_sort(st->keys, st->vals, kb, vb, st->D, 32 + tile_bits, sort_tmp,
+                              st->stream);
+  }
+  if (which) {
+    std::swap(st->keys, kb);
+    std::swap(st->vals, vb);
+  }
+  {
+    StageTimer t(ctx, HGS_STAGE_RANGES, st->stream);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(st->ranges), 0u, 2 * n_tiles, st->stream);
+    launch_ranges(st->keys, st->D, st->ranges, st->stream);
+  }
+
+  RasterOut ro{};
+  if (out) {
+    ro.rgb = out->rgb;
+    ro.alpha = out->alpha;
+    ro.depth = out->depth;
+    ro.normal = out->normal;
+  }
+  ro.T_final = st->T_final;
+  ro.last = st->last;
+  ro.n_contrib = st->n_contrib;
+  ro.wcount = st->wcount;
+  {
+    StageTimer t(ctx, HGS_STAGE_RASTER_FWD, st->stream);
+    launch_raster_fwd(st->ranges, st->vals, st->rec, st->cams, n_views, st->n_tiles, W, H,
+                      st->tiles_x, st->tiles_per_view, st->opt, ro, st->stream);
+  }
+  ST_HIP(hipGetLastError());
+#undef ST_HIP
+  if (state_out) {
+    *state_out = st;
+  } else {
+    release(st);
+    delete st;
+  }
+  return HGS_OK;
+}
+
+hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_images *gout,
+                               const hgs_grads *grads, void *stream) {
+  if (!ctx || !st) return fail(HGS_EINVAL, "ctx or state is NULL");
+  if (!grads) return fail(HGS_EINVAL, "grads is NULL");
+  if (st->device != ctx->device) return fail(HGS_ESTATE, "state belongs to another context");
+  HGS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (s != st->stream) {
+    // order this stream after the forward's work
+    hipEvent_t ev;
+    HGS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HGS_HIP(hipEventRecord(ev, st->stream));
+    HGS_HIP(hipStreamWaitEvent(s, ev, 0));
+    HGS_HIP(hipEventDestroy(ev));
+  }
+  const int64_t VN = (int64_t)st->V * st->N;
+  float *accum = nullptr;
+  HGS_HIP(hipMallocAsync((void **)&accum, (size_t)std::max<int64_t>(VN, 1) * kGradSlots * 4, s));
+  {
+    StageTimer t(ctx, HGS_STAGE_FILL, s);
+    launch_fill_f32(accum, 0.0f, VN * kGradSlots, s);
+  }
+  RasterGradIn gi{};
+  if (gout) {
+    gi.rgb = gout->rgb;
+    gi.alpha = gout->alpha;
+    gi.depth = gout->depth;
+    gi.normal = gout->normal;
+  }
+  {
+    StageTimer t(ctx, HGS_STAGE_RASTER_BWD, s);
+    launch_raster_bwd(st->ranges, st->vals, st->rec, st->n_tiles, st->W, st->H, st->tiles_x,
+                      st->tiles_per_view, st->opt, st->T_final, st->last, gi, accum, s);
+  }
+  {
+    StageTimer t(ctx, HGS_STAGE_PREPROCESS_BWD, s);
+    launch_preprocess_bwd(st->scene, st->cams, st->V, st->opt, st->tiles, accum, grads->means,
+                          grads->scales, grads->rotations, grads->opacities, grads->sh,
+                          grads->accumulate, s);
+  }
+  HGS_HIP(hipGetLastError());
+  HGS_HIP(hipFreeAsync(accum, s));
+  if (s != st->stream) {
+    hipEvent_t ev;
+    HGS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HGS_HIP(hipEventRecord(ev, s));
+    HGS_HIP(hipStreamWaitEvent(st->stream, ev, 0));
+    HGS_HIP(hipEventDestroy(ev));
+  }
+  return HGS_OK;
+}
+
+hgs_status hgs_profile_enable(hgs_ctx *ctx, int32_t on) {
+  if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
+  ctx->profile = on != 0;
+  return HGS_OK;
+}
+
+hgs_status hgs_profile_read(hgs_ctx *ctx, double *ms, int64_t *calls, int32_t reset) {
+  if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
+  HGS_HIP(hipSetDevice(ctx->device));
+  for (auto &p : ctx->pending) {
+    HGS_HIP(hipEventSynchronize(p.b));
+    float e = 0.0f;
+    HGS_HIP(hipEventElapsedTime(&e, p.a, p.b));
+    ctx->stage_ms[p.stage] += e;
+    ctx->stage_calls[p.stage] += 1;
+    ctx->event_pool.push_back(p.a);
+    ctx->event_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+  for (int i = 0; i < HGS_N_STAGES; ++i) {
+    if (ms) ms[i] = ctx->stage_ms[i];
+    if (calls) calls[i] = ctx->stage_calls[i];
+    if (reset) {
+      ctx->stage_ms[i] = 0.0;
+      ctx->stage_calls[i] = 0;
+    }
+  }
+  return HGS_OK;
+}
+
+void hgs_state_free(hgs_ctx *ctx, hgs_state *st) {
+  if (!st) return;
+  if (ctx) (void)hipSetDevice(ctx->device);
+  release(st);
+  delete st;
+}
+
+hgs_status hgs_state_sizes(hgs_ctx *ctx, hgs_state *st, int64_t *sizes5) {
+  if (!ctx || !st || !sizes5) return fail(HGS_EINVAL, "NULL argument");
+  sizes5[0] = (int64_t)st->V * st->N;
+  sizes5[1] = st->D;
+  sizes5[2] = st->n_tiles;
+  sizes5[3] = (int64_t)st->W * st->H;
+  sizes5[4] = st->V;
+  return HGS_OK;
+}
+
+hgs_status hgs_state_debug(hgs_ctx *ctx, hgs_state *st, int32_t what, void *dst, int64_t cap) {
+  if (!ctx || !st || !dst) return fail(HGS_EINVAL, "NULL argument");
+  HGS_HIP(hipSetDevice(ctx->device));
+  const int64_t VN = (int64_t)st->V * st->N;
+  const int64_t P = (int64_t)st->V * st->W * st->H;
+  const void *src = nullptr;
+  int64_t bytes = 0;
+  switch (what) {
+    case 0: src = st->keys; bytes = st->D * 8; break;
+    case 1: src = st->vals; bytes = st->D * 4; break;
+    case 2: src = st->ranges; bytes = (int64_t)st->n_tiles * 8; break;
+    case 3: src = st->rect; bytes = VN * 16; break;
+    case 4: src = st->tiles; bytes = VN * 4; break;
+    case 5: src = st->zbits; bytes = VN * 4; break;
+    case 6: src = st->T_final; bytes = P * 4; break;
+    case 7: src = st->last; bytes = P * 4; break;
+    case 8: src = st->n_contrib; bytes = P * 4; break;
+    case 9: src = st->wcount; bytes = P * 4; break;
+    default: return fail(HGS_EINVAL, "unknown debug array");
+  }
+  if (bytes > cap) return fail(HGS_EINVAL, "destination too small");
+  HGS_HIP(hipStreamSynchronize(st->stream));
+  if (bytes > 0) HGS_HIP(hipMemcpy(dst, src, (size_t)bytes, hipMemcpyDeviceToHost));
+  return HGS_OK;
+}
+
+hgs_status hgs_state_check(hgs_ctx *ctx, hgs_state *st) {
+  if (!ctx || !st) return fail(HGS_EINVAL, "NULL argument");
+  HGS_HIP(hipSetDevice(ctx->device));
+  HGS_HIP(hipStreamSynchronize(st->stream));
+  HGS_HIP(hipGetLastError());
+  return HGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,358 @@
+// Integer stages of the tile pipeline, gfx950: exclusive scan,
+// duplicate-with-keys, stable LSD radix sort of (u64 key, u32 value) pairs,
+// tile-range identification and fills.
+//
+// The radix sort uses 8-bit digits.  A pass is three launches over
+// fixed-size chunks of 4096 pairs:
+//   * a per-chunk digit histogram (LDS atomics);
+//   * an exclusive scan of the histogram table in digit-major order;
+//   * a stable scatter.
+// Within a chunk, elements are ranked in input order 256 at a time.  Each
+// wave64 matches equal digits with 8 ballots, the four waves are combined in
+// LDS, and a running per-digit base carries the count across rounds.
+// Stability across chunks follows from the digit-major scan.
+
+#include "hgs_internal.h"
+
+namespace hgs {
+
+namespace {
+
+constexpr int kScanItems = 16;                       // elements per thread
+constexpr int kScanChunk = kBlock * kScanItems;      // 4096 per block
+
+// ----- block-wide exclusive scan of one value per thread (256 threads) -----
+template <typename T>
+__device__ inline T block_exclusive_scan(T v, T *lds, T &total) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // inclusive scan within the wave
+  T x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  T off = 0;
+  T tot = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const T t = lds[k];
+    if (k < w) off += t;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return off + x - v;
+}
+
+// Level 0: per-chunk sums (u64) of u32 input.
+__global__ void __launch_bounds__(256) scan_reduce_u32(const uint32_t *__restrict__ in, int64_t n,
+                                                       uint64_t *__restrict__ sums) {
+  __shared__ uint64_t lds[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+    if (i < n) acc += in[i];
+  }
+  uint64_t tot;
+  block_exclusive_scan<uint64_t>(acc, lds, tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(256) scan_reduce_u64(const uint64_t *__restrict__ in, int64_t n,
+                                                       uint64_t *__restrict__ sums) {
+  __shared__ uint64_t lds[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+    if (i < n) acc += in[i];
+  }
+  uint64_t tot;
+  block_exclusive_scan<uint64_t>(acc, lds, tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Exclusive scan of one chunk in place given the chunk's offset.  Each
+// thread owns kScanItems consecutive elements.
+template <typename TI, typename TO>
+__device__ inline void scan_chunk(const TI *in, TO *out, int64_t n, uint64_t offset,
+                                  uint64_t *lds) {
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  uint64_t vals[kScanItems];
+  uint64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    vals[k] = i < n ? (uint64_t)in[i] : 0;
+    acc += vals[k];
+  }
+  uint64_t tot;
+  uint64_t run = block_exclusive_scan<uint64_t>(acc, lds, tot) + offset;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    if (i < n) out[i] = (TO)run;
+    run += vals[k];
+  }
+}
+
+__global__ void __launch_bounds__(256) scan_down_u32(const uint32_t *__restrict__ in,
+                                                     uint32_t *__restrict__ out, int64_t n,
+                                                     const uint64_t *__restrict__ offs) {
+  __shared__ uint64_t lds[4];
+  scan_chunk<uint32_t, uint32_t>(in, out, n, offs ? offs[blockIdx.x] : 0, lds);
+}
+
+__global__ void __launch_bounds__(256) scan_down_u64(const uint64_t *__restrict__ in,
+                                                     uint64_t *__restrict__ out, int64_t n,
+                                                     const uint64_t *__restrict__ offs) {
+  __shared__ uint64_t lds[4];
+  scan_chunk<uint64_t, uint64_t>(in, out, n, offs ? offs[blockIdx.x] : 0, lds);
+}
+
+__global__ void scan_total(const uint64_t *__restrict__ excl, const uint64_t *__restrict__ sums,
+                           int64_t nb, uint64_t *__restrict__ total) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *total = nb > 0 ? excl[nb - 1] + sums[nb - 1] : 0;
+}
+
+__global__ void single_total_u32(const uint32_t *__restrict__ in, int64_t n, uint64_t *total) {
+  // only used for n <= one chunk
+  __shared__ uint64_t lds[4];
+  uint64_t acc = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) acc += in[i];
+  uint64_t tot;
+  block_exclusive_scan<uint64_t>(acc, lds, tot);
+  if (threadIdx.x == 0) *total = tot;
+}
+
+int64_t nchunks(int64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
+
+// Exclusive scan of u64 values (recursive on chunk sums).
+void scan_u64(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *tmp, hipStream_t s) {
+  const int64_t nb = nchunks(n);
+  if (nb <= 1) {
+    hipLaunchKernelGGL(scan_down_u64, dim3(1), dim3(kBlock), 0, s, in, out, n,
+                       (const uint64_t *)nullptr);
+    return;
+  }
+  uint64_t *sums = tmp, *offs = tmp + nb, *rest = tmp + 2 * nb;
+  hipLaunchKernelGGL(scan_reduce_u64, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, sums);
+  scan_u64(sums, offs, nb, rest, s);
+  hipLaunchKernelGGL(scan_down_u64, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n,
+                     (const uint64_t *)offs);
+}
+
+size_t scan_u64_tmp(int64_t n) {
+  const int64_t nb = nchunks(n);
+  if (nb <= 1) return 0;
+  return (size_t)(2 * nb) * sizeof(uint64_t) + scan_u64_tmp(nb);
+}
+
+// ----- duplicate with keys -----
+// One thread per (view, splat); pairs are written at offsets[i] in tile
+// row-major order of the splat's rectangle.  key = (global tile << 32) | depth
+// bits, value = view * N + splat.
+__global__ void __launch_bounds__(256)
+duplicate_kernel(const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ tiles,
+                 const int4 *__restrict__ rect, const uint32_t *__restrict__ zbits,
+                 const DevCam *__restrict__ cams, int64_t N, int64_t total,
+                 uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  if (tiles[i] == 0) return;
+  const int v = (int)(i / N);
+  const DevCam &c = cams[v];
+  const int4 r = rect[i];
+  uint32_t o = offsets[i];
+  const uint64_t z = zbits[i];
+  const int tx0 = r.x >> 4, tx1 = r.z >> 4, ty0 = r.y >> 4, ty1 = r.w >> 4;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      const uint64_t tile = (uint64_t)(c.tile_base + ty * c.tiles_x + tx);
+      keys[o] = (tile << 32) | z;
+      vals[o] = (uint32_t)i;
+      ++o;
+    }
+}
+
+// ----- radix sort -----
+constexpr int kSortItems = 16;
+constexpr int kSortChunk = kBlock * kSortItems;  // 4096
+
+__global__ void __launch_bounds__(256) radix_hist(const uint64_t *__restrict__ keys, int64_t n,
+                                                  int shift, int64_t nb,
+                                                  uint32_t *__restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256)
+radix_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
+              int shift, int64_t nb, const uint32_t *__restrict__ offs,
+              uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+  __shared__ uint32_t base[256];        // running count of each digit in this chunk
+  __shared__ uint32_t wcnt[4][256];     // per-wave counts of the current round
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  base[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+  const int64_t chunk = (int64_t)blockIdx.x * kSortChunk;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t i = chunk + (int64_t)k * kBlock + tid;
+    const bool ok = i < n;
+    uint64_t key = 0;
+    uint32_t val = 0;
+    if (ok) {
+      key = kin[i];
+      val = vin[i];
+    }
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wcnt[j][tid] = 0;
+    __syncthreads();
+    // lanes of this wave with the same digit
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t m = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    const bool leader = ok && (peers >> lane) == 1ull;  // highest lane of its group
+    if (leader) wcnt[w][d] = cnt;
+    __syncthreads();
+    // per digit: prefix over the waves in order
+    {
+      const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
+      const uint32_t b0 = base[tid];
+      wcnt[0][tid] = b0;
+      wcnt[1][tid] = b0 + c0;
+      wcnt[2][tid] = b0 + c0 + c1;
+      wcnt[3][tid] = b0 + c0 + c1 + c2;
+      base[tid] = b0 + c0 + c1 + c2 + c3;
+    }
+    __syncthreads();
+    if (ok) {
+      const uint32_t pos = wcnt[w][d] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void fill_f32_kernel(float *p, float v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void ranges_kernel(const uint64_t *__restrict__ keys, int64_t D,
+                              uint2 *__restrict__ ranges) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D) return;
+  const uint32_t t = (uint32_t)(keys[i] >> 32);
+  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[t].x = (uint32_t)i;
+  if (i == D - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = (uint32_t)(i + 1);
+}
+
+}  // namespace
+
+size_t scan_tmp_bytes(int64_t n) {
+  const int64_t nb = nchunks(n);
+  return (size_t)(2 * nb + 2) * sizeof(uint64_t) + scan_u64_tmp(nb);
+}
+
+void launch_scan(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *total, void *tmp,
+                 hipStream_t s) {
+  if (n == 0) {
+    hipLaunchKernelGGL(single_total_u32, dim3(1), dim3(kBlock), 0, s, in, (int64_t)0, total);
+    return;
+  }
+  const int64_t nb = nchunks(n);
+  uint64_t *sums = (uint64_t *)tmp, *offs = sums + nb, *rest = sums + 2 * nb + 2;
+  hipLaunchKernelGGL(scan_reduce_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, sums);
+  scan_u64(sums, offs, nb, rest, s);
+  hipLaunchKernelGGL(scan_down_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n,
+                     (const uint64_t *)offs);
+  hipLaunchKernelGGL(scan_total, dim3(1), dim3(1), 0, s, (const uint64_t *)offs,
+                     (const uint64_t *)sums, nb, total);
+}
+
+void launch_duplicate(const uint32_t *offsets, const uint32_t *tiles, const int4 *rect,
+                      const uint32_t *zbits, const DevCam *cams, int V, int64_t N,
+                      uint64_t *keys, uint32_t *vals, hipStream_t s) {
+  const int64_t total = (int64_t)V * N;
+  if (total == 0) return;
+  const int64_t nb = (total + 255) / 256;
+  hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)nb), dim3(256), 0, s, offsets, tiles, rect,
+                     zbits, cams, N, total, keys, vals);
+}
+
+size_t sort_tmp_bytes(int64_t n) {
+  const int64_t nb = (n + kSortChunk - 1) / kSortChunk;
+  const int64_t h = 256 * std::max<int64_t>(nb, 1);
+  return (size_t)(2 * h) * sizeof(uint32_t) + scan_tmp_bytes(h) + 64;
+}
+
+int launch_radix_sort(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n, int bits,
+                      void *tmp, hipStream_t s) {
+  if (n <= 1) return 0;
+  const int64_t nb = (n + kSortChunk - 1) / kSortChunk;
+  const int64_t h = 256 * nb;
+  uint32_t *hist = (uint32_t *)tmp;
+  uint32_t *offs = hist + h;
+  uint64_t *total = (uint64_t *)(offs + h);
+  void *stmp = (void *)(total + 1);
+  uint64_t *kin = ka, *kout = kb;
+  uint32_t *vin = va, *vout = vb;
+  int which = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, (const uint64_t *)kin, n,
+                       shift, nb, hist);
+    launch_scan(hist, offs, h, total, stmp, s);
+    hipLaunchKernelGGL(radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, (const uint64_t *)kin,
+                       (const uint32_t *)vin, n, shift, nb, (const uint32_t *)offs, kout, vout);
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+    which ^= 1;
+  }
+  return which;
+}
+
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_ranges(const uint64_t *keys, int64_t D, uint2 *ranges, hipStream_t s) {
+  if (D <= 0) return;
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, keys, D,
+                     ranges);
+}
+
+}  // namespace hgs

@@ -1,0 +1,269 @@
+"""PyTorch-facing API of the gfx950 hybrid rasterizer.
+
+PyTorch supplies device memory and the current stream; every computation runs
+in ``libhgs.so`` through the C ABI (include/hgs.h).
+
+* ``Rasterizer``: one context per device; resident or borrowed scenes.
+* ``render(...)``: forward only (serving / evaluation).
+* ``HybridRasterize``: a ``torch.autograd.Function``.  Its forward keeps an
+  opaque library state, and its backward calls ``hgs_render_backward``, which
+  recomputes transmittance in reverse.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _hgs as H
+
+SCENE_KEYS = ("means", "scales", "rotations", "opacities", "sh", "types")
+DEFAULT_OPTS = dict(bg=(0.0, 0.0, 0.0), dilation=0.3, lambda_z=1.0, theta_z=1.05, temp_z=0.001)
+
+DEBUG = dict(keys=(0, np.uint64, 1), vals=(1, np.uint32, 1), ranges=(2, np.uint32, 2),
+             rect=(3, np.int32, 4), tiles=(4, np.uint32, 1), zbits=(5, np.uint32, 1),
+             T_final=(6, np.float32, 1), last=(7, np.uint32, 1), n_contrib=(8, np.uint32, 1),
+             wcount=(9, np.uint32, 1))
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def make_camera(cam: dict) -> H.hgs_camera:
+    c = H.hgs_camera()
+    vm = np.asarray(cam["viewmat"], np.float32).reshape(16)
+    for i in range(16):
+        c.viewmat[i] = float(vm[i])
+    c.fx, c.fy, c.cx, c.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    c.znear = float(cam.get("znear", 0.2))
+    return c
+
+
+def make_cameras(cams) -> C.Array:
+    if isinstance(cams, dict):
+        cams = [cams]
+    arr = (H.hgs_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = make_camera(c)
+    return arr
+
+
+def make_opts(opts: dict | None) -> H.hgs_opts:
+    o = dict(DEFAULT_OPTS)
+    o.update(opts or {})
+    r = H.hgs_opts()
+    for i in range(3):
+        r.bg[i] = float(o["bg"][i])
+    r.dilation, r.lambda_z, r.theta_z, r.temp_z = (float(o[k]) for k in
+                                                   ("dilation", "lambda_z", "theta_z", "temp_z"))
+    return r
+
+
+def _check_scene(t: dict):
+    for k in SCENE_KEYS:
+        x = t[k]
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.is_contiguous()):
+            raise ValueError(f"scene[{k!r}] must be a contiguous CUDA tensor")
+    for k in SCENE_KEYS[:-1]:
+        if t[k].dtype != torch.float32:
+            raise ValueError(f"scene[{k!r}] must be float32")
+    if t["types"].dtype != torch.uint8:
+        raise ValueError("scene['types'] must be uint8")
+
+
+def scene_desc(t: dict) -> H.hgs_scene_desc:
+    _check_scene(t)
+    n = t["means"].shape[0]
+    K = t["sh"].shape[1]
+    deg = int(round(K ** 0.5)) - 1
+    d = H.hgs_scene_desc()
+    d.n = n
+    d.sh_degree = deg
+    d.means, d.scales, d.rotations, d.opacities, d.sh, d.types = (
+        t[k].data_ptr() for k in SCENE_KEYS)
+    return d
+
+
+class State:
+    """Owns one ``hgs_state``; freed on ``free()`` or garbage collection."""
+
+    def __init__(self, rast: "Rasterizer", handle, keep=()):
+        self.rast = rast
+        self.handle = handle
+        self.keep = keep  # tensors the state borrows
+
+    def sizes(self):
+        VN, D, T, HW, V = H.hgs_state_sizes(self.rast.ctx, self.handle)
+        return dict(VN=VN, D=D, n_tiles=T, HW=HW, V=V)
+
+    def debug(self, name: str) -> np.ndarray:
+        what, dt, width = DEBUG[name]
+        sz = self.sizes()
+        count = {"keys": sz["D"], "vals": sz["D"], "ranges": sz["n_tiles"], "rect": sz["VN"],
+                 "tiles": sz["VN"], "zbits": sz["VN"], "T_final": sz["V"] * sz["HW"],
+                 "last": sz["V"] * sz["HW"], "n_contrib": sz["V"] * sz["HW"],
+                 "wcount": sz["V"] * sz["HW"]}[name]
+        out = np.zeros((max(count, 1), width), dt)
+        H.hgs_state_debug(self.rast.ctx, self.handle, what, out.ctypes.data, out.nbytes)
+        out = out[:count]
+        return out[:, 0] if width == 1 else out
+
+    def free(self):
+        if self.handle is not None:
+            H.hgs_state_free(self.rast.ctx, self.handle)
+            self.handle = None
+            self.keep = ()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Rasterizer:
+    """A library context bound to one CUDA (HIP) device."""
+
+    def __init__(self, device: int | torch.device = 0):
+        if isinstance(device, torch.device):
+            device = device.index or 0
+        self.device = int(device)
+        self.ctx = H.hgs_create(self.device)
+
+    def close(self):
+        if self.ctx is not None:
+            H.hgs_destroy(self.ctx)
+            self.ctx = None
+
+    # ----- scenes -----
+    def scene_init(self, scene: dict, copy_resident: bool) -> int:
+        return H.hgs_scene_init(self.ctx, scene_desc(scene), 1 if copy_resident else 0)
+
+    def scene_release(self, sid: int):
+        H.hgs_scene_release(self.ctx, sid)
+
+    # ----- forward -----
+    def alloc_images(self, n_views, height, width, channels=("rgb", "alpha", "depth", "normal")):
+        dev = torch.device("cuda", self.device)
+        nc = dict(rgb=3, alpha=1, depth=1, normal=3)
+        return {k: torch.empty((n_views, nc[k], height, width), device=dev, dtype=torch.float32)
+                for k in channels}
+
+    def render_scene(self, sid: int, cams, opts=None, images=None, want_state=False, stream=None):
+        cam_arr = make_cameras(cams)
+        V = len(cam_arr)
+        Hh, Ww = cam_arr[0].height, cam_arr[0].width
+        if images is None:
+            images = self.alloc_images(V, Hh, Ww)
+        im = H.hgs_images()
+        for k in ("rgb", "alpha", "depth", "normal"):
+            t = images.get(k)
+            if t is not None:
+                nc = dict(rgb=3, alpha=1, depth=1, normal=3)[k]
+                if tuple(t.shape) != (V, nc, Hh, Ww) or t.dtype != torch.float32 or not t.is_contiguous():
+                    raise ValueError(f"image {k!r} must be float32 [{V},{nc},{Hh},{Ww}] contiguous")
+            setattr(im, k, _ptr(t))
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        st = H.hgs_render(self.ctx, sid, cam_arr, make_opts(opts), im, want_state, s)
+        return images, (State(self, st) if want_state else None)
+
+    def render(self, scene: dict, cams, opts=None, images=None, want_state=False):
+        """Forward render of a borrowed scene (tensors on this device)."""
+        sid = self.scene_init(scene, copy_resident=False)
+        try:
+            images, state = self.render_scene(sid, cams, opts, images, want_state)
+        finally:
+            self.scene_release(sid)
+        if state is not None:
+            state.keep = tuple(scene[k] for k in SCENE_KEYS)
+        return images, state
+
+    # ----- backward -----
+    def backward(self, state: State, grad_images: dict, grads: dict, accumulate=False, stream=None):
+        gi = H.hgs_grad_images()
+        for k in ("rgb", "alpha", "depth", "normal"):
+            t = grad_images.get(k)
+            if t is not None and not t.is_contiguous():
+                raise ValueError(f"grad image {k!r} must be contiguous")
+            setattr(gi, k, _ptr(t))
+        g = H.hgs_grads()
+        for k in ("means", "scales", "rotations", "opacities", "sh"):
+            setattr(g, k, _ptr(grads.get(k)))
+        g.accumulate = 1 if accumulate else 0
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        H.hgs_render_backward(self.ctx, state.handle, gi, g, s)
+
+
+_RASTERIZERS: dict[int, Rasterizer] = {}
+
+
+def get_rasterizer(device=0) -> Rasterizer:
+    if isinstance(device, torch.device):
+        device = device.index or 0
+    r = _RASTERIZERS.get(int(device))
+    if r is None:
+        r = Rasterizer(int(device))
+        _RASTERIZERS[int(device)] = r
+    return r
+
+
+class HybridRasterize(torch.autograd.Function):
+    """Differentiable hybrid rendering: (means, scales, rotations, opacities,
+    sh) -> (rgb, alpha, depth, normal), each [V,C,H,W].  ``types`` (uint8)
+    and the cameras are not differentiated."""
+
+    @staticmethod
+    def forward(ctx, means, scales, rotations, opacities, sh, types, cams, opts):
+        rast = get_rasterizer(means.device)
+        scene = dict(means=means.contiguous(), scales=scales.contiguous(),
+                     rotations=rotations.contiguous(), opacities=opacities.contiguous(),
+                     sh=sh.contiguous(), types=types.contiguous())
+        images, state = rast.render(scene, cams, opts, want_state=True)
+        ctx.state = state
+        ctx.shapes = [(t.shape, t.device) for t in (means, scales, rotations, opacities, sh)]
+        return images["rgb"], images["alpha"], images["depth"], images["normal"]
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_alpha, g_depth, g_normal):
+        state = ctx.state
+        rast = state.rast
+        grads = {k: torch.empty(shp, device=dev, dtype=torch.float32)
+                 for k, (shp, dev) in zip(("means", "scales", "rotations", "opacities", "sh"),
+                                          ctx.shapes)}
+        gi = {k: (None if t is None else t.contiguous())
+              for k, t in (("rgb", g_rgb), ("alpha", g_alpha), ("depth", g_depth),
+                           ("normal", g_normal))}
+        rast.backward(state, gi, grads)
+        state.free()
+        return (grads["means"], grads["scales"], grads["rotations"], grads["opacities"],
+                grads["sh"], None, None, None)
+
+
+def rasterize(scene: dict, cams, opts=None):
+    """Differentiable render; returns (rgb, alpha, depth, normal)."""
+    return HybridRasterize.apply(scene["means"], scene["scales"], scene["rotations"],
+                                 scene["opacities"], scene["sh"], scene["types"], cams, opts)
+
+
+def to_device(scene_np: dict, device="cuda") -> dict:
+    """numpy scene (scenegen layout) -> torch tensors on ``device``."""
+    out = {}
+    for k in SCENE_KEYS:
+        out[k] = torch.from_numpy(np.ascontiguousarray(scene_np[k])).to(device)
+    return out
+
+
+def pair_counts(state: State) -> dict:
+    """Algorithmic pair counts of a forward render, by type: blended pairs
+    (backward work) and active pairs up to and including each pixel's stop
+    (forward work)."""
+    w = state.debug("wcount").astype(np.int64)
+    b3 = int((w & 0x7FFF).sum())
+    b2 = int(((w >> 15) & 0x7FFF).sum())
+    stopped = (w >> 31) & 1
+    s2 = int((stopped & ((w >> 30) & 1)).sum())
+    s3 = int(stopped.sum()) - s2
+    return dict(blend_3d=b3, blend_2d=b2, fwd_3d=b3 + s3, fwd_2d=b2 + s2)
