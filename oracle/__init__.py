@@ -56,7 +56,7 @@ def _load():
                                         [P, C.c_int, P, P, P, C.c_int64, C.c_int, C.c_int] +
                                         [P] * 5)
         _lib.oracle_backward.argtypes = ([P] * 6 + [C.c_int64, C.c_int] + [P] * 5 +
-                                         [P, C.c_int, P, P, C.c_int64, P, C.c_int] + [P] * 4)
+                                         [P, C.c_int, P, P, C.c_int64, P, C.c_int] + [P] * 5)
         _lib.oracle_sh_basis.argtypes = [C.c_int, P, C.c_int64, P]
         _lib.oracle_surfel_uv.argtypes = [P, P, P, C.c_int64, P]
     return _lib
@@ -175,8 +175,10 @@ def backward(scene, cams, pix, G, opts=None, *, params64=None, threads=None):
     """Binary64 gradients of L = sum_p <G_p, out_p> over pixels ``pix``.
 
     Returns dict of gradients (means [N,3], scales [N,3], rotations [N,4],
-    opacities [N], sh [N,K,3]) and the same keys with suffix ``_abs``: sums
-    of the absolute per-pixel terms, a scale for tolerances.
+    opacities [N], sh [N,K,3]) and, as tolerance scales, the same keys with
+    suffix ``_abs`` (sums of the absolute per-pair terms) and ``_cond`` (the
+    condition scale of a binary32 evaluation; SH terms are products, so
+    ``sh_cond`` equals ``sh_abs``).
     """
     lib = _load()
     m, s, r, o, sh, t = _f32(scene)
@@ -190,13 +192,17 @@ def backward(scene, cams, pix, G, opts=None, *, params64=None, threads=None):
     ap = np.zeros((n, 11), np.float64)
     gs = np.zeros((n, K, 3), np.float64)
     as_ = np.zeros((n, K, 3), np.float64)
+    cp_ = np.zeros((n, 11), np.float64)
     lib.oracle_backward(_p(m), _p(s), _p(r), _p(o), _p(sh), _p(t), n, int(scene["sh_degree"]),
                         _p(m6), _p(s6), _p(r6), _p(o6), _p(sh6), _p(cp), cp.shape[0],
                         _p(_opts_vec(opts)), _p(pix), pix.shape[0], _p(G),
-                        int(threads or os.cpu_count() or 1), _p(gp), _p(gs), _p(ap), _p(as_))
+                        int(threads or os.cpu_count() or 1), _p(gp), _p(gs), _p(ap), _p(as_),
+                        _p(cp_))
     return dict(means=gp[:, 0:3], scales=gp[:, 3:6], rotations=gp[:, 6:10], opacities=gp[:, 10],
                 sh=gs, means_abs=ap[:, 0:3], scales_abs=ap[:, 3:6], rotations_abs=ap[:, 6:10],
-                opacities_abs=ap[:, 10], sh_abs=as_)
+                opacities_abs=ap[:, 10], sh_abs=as_, means_cond=cp_[:, 0:3],
+                scales_cond=cp_[:, 3:6], rotations_cond=cp_[:, 6:10], opacities_cond=cp_[:, 10],
+                sh_cond=as_)
 
 
 def sh_basis(degree, dirs):

@@ -863,15 +863,18 @@ int oracle_forward(const float *m32, const float *s32, const float *r32, const f
 }
 
 // Backward of L = sum over listed pixels of <G, out> (G = [P,8] in the
-// order of out8).  Outputs dL/d(params) in binary64, plus the sums of the
-// absolute per-pixel terms (same shapes) used to scale tolerances.
+// order of out8).  Outputs dL/d(params) in binary64, plus two tolerance
+// scales of the same shapes: the sums of the absolute per-pair terms
+// (a_params, a_sh), and a condition scale of a binary32 evaluation
+// (c_params) in which the dL/dalpha~ = T (f - S) factor is counted as
+// T (|f| + |S|).
 int oracle_backward(const float *m32, const float *s32, const float *r32, const float *o32,
                     const float *sh32, const uint8_t *types, int64_t n, int sh_degree,
                     const double *m64, const double *s64, const double *r64, const double *o64,
                     const double *sh64, const float *cams, int V, const double *opts,
                     const int32_t *pix, int64_t P, const double *G, int threads,
                     double *g_params /* [n,11] */, double *g_sh /* [n,K,3] */,
-                    double *a_params, double *a_sh) {
+                    double *a_params, double *a_sh, double *c_params) {
   Scene32 sc32{m32, s32, r32, o32, sh32, types, n, sh_degree};
   Scene64 sc64{m64, s64, r64, o64, sh64};
   Work w;
@@ -886,7 +889,7 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
   const int nt = std::max(1, threads);
   // Per-thread sparse accumulators: splat -> slot of [NP params | NP abs |
   // 3K sh | 3K sh abs].  Merged in thread order (deterministic).
-  const size_t slot = (size_t)2 * NP + (size_t)6 * K;
+  const size_t slot = (size_t)3 * NP + (size_t)6 * K;
   std::vector<std::unordered_map<int64_t, size_t>> where(nt);
   std::vector<std::vector<double>> acc(nt);
   parallel_for(P, threads, [&](int t, int64_t a, int64_t b) {
@@ -929,11 +932,17 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
         const int64_t g = seq[j].g;
         const double al = seq[j].alpha;
         const double dLda = T[j] * (f[j] - Ssuf);
+        const double Sprev = Ssuf;
         Ssuf = f[j] * al + (1.0 - al) * Ssuf;
         const double wgt = al * T[j];
         const Splat<Dual> &sp = sps[j];
         double *c = cell(g);
-        double *gg = c, *ga = c + NP, *gs = c + 2 * NP, *as = c + 2 * NP + 3 * K;
+        double *gg = c, *ga = c + NP, *gcnd = c + 2 * NP, *gs = c + 3 * NP,
+               *as = c + 3 * NP + 3 * K;
+        // Tolerance scale: dL/dalpha~ = T (f - S) is a difference, so the
+        // error of evaluating it in binary32 scales with T (|f| + |S|), not
+        // with |T (f - S)|.  The other terms are products.
+        const double cond_a = T[j] * (std::fabs(f[j]) + std::fabs(Sprev));
         for (int q = 0; q < NP; ++q) {
           double terms[8];
           terms[0] = dLda * aa[j].d[q];
@@ -941,6 +950,8 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
           for (int k = 0; k < 3; ++k) terms[2 + k] = wgt * Gp[5 + k] * sp.nrm[k].d[q];
           for (int k = 0; k < 3; ++k) terms[5 + k] = wgt * Gp[k] * sp.color[k].d[q];
           for (int k = 0; k < 8; ++k) { gg[q] += terms[k]; ga[q] += std::fabs(terms[k]); }
+          gcnd[q] += cond_a * std::fabs(aa[j].d[q]);
+          for (int k = 1; k < 8; ++k) gcnd[q] += std::fabs(terms[k]);
         }
         for (int ch = 0; ch < 3; ++ch) {
           if (sp.clamped[ch]) continue;
@@ -955,6 +966,7 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
   });
   std::memset(g_params, 0, sizeof(double) * n * NP);
   std::memset(a_params, 0, sizeof(double) * n * NP);
+  std::memset(c_params, 0, sizeof(double) * n * NP);
   std::memset(g_sh, 0, sizeof(double) * n * K * 3);
   std::memset(a_sh, 0, sizeof(double) * n * K * 3);
   for (int t = 0; t < nt; ++t) {
@@ -966,10 +978,11 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
       for (int q = 0; q < NP; ++q) {
         g_params[g * NP + q] += c[q];
         a_params[g * NP + q] += c[NP + q];
+        c_params[g * NP + q] += c[2 * NP + q];
       }
       for (int j = 0; j < 3 * K; ++j) {
-        g_sh[g * 3 * K + j] += c[2 * NP + j];
-        a_sh[g * 3 * K + j] += c[2 * NP + 3 * K + j];
+        g_sh[g * 3 * K + j] += c[3 * NP + j];
+        a_sh[g * 3 * K + j] += c[3 * NP + 3 * K + j];
       }
     }
   }
