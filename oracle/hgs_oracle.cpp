@@ -943,6 +943,19 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
         // error of evaluating it in binary32 scales with T (|f| + |S|), not
         // with |T (f - S)|.  The other terms are products.
         const double cond_a = T[j] * (std::fabs(f[j]) + std::fabs(Sprev));
+        // For 3D pairs, d(alpha~)/d(theta) goes through the screen-space
+        // quantities of Eq. 1 (offset D = p - mu', conic Q).  Evaluated in
+        // binary32, its error scales with the entrywise magnitudes
+        // sum_ab |D_a D_b| |dQ_ab| + 2 sum_a |(Q D)_a| |dmu'_a|, not with
+        // the magnitude of their (possibly cancelling) sum.
+        double D0 = 0, D1 = 0, QD0 = 0, QD1 = 0, gexp = 0;
+        if (!sp.is2d) {
+          D0 = px - sp.mu2[0].v;
+          D1 = py - sp.mu2[1].v;
+          QD0 = sp.conic[0].v * D0 + sp.conic[1].v * D1;
+          QD1 = sp.conic[1].v * D0 + sp.conic[2].v * D1;
+          gexp = std::exp(-0.5 * dd[j].v);
+        }
         for (int q = 0; q < NP; ++q) {
           double terms[8];
           terms[0] = dLda * aa[j].d[q];
@@ -950,7 +963,16 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
           for (int k = 0; k < 3; ++k) terms[2 + k] = wgt * Gp[5 + k] * sp.nrm[k].d[q];
           for (int k = 0; k < 3; ++k) terms[5 + k] = wgt * Gp[k] * sp.color[k].d[q];
           for (int k = 0; k < 8; ++k) { gg[q] += terms[k]; ga[q] += std::fabs(terms[k]); }
-          gcnd[q] += cond_a * std::fabs(aa[j].d[q]);
+          double da = std::fabs(aa[j].d[q]);
+          if (!sp.is2d && !seq[j].clamped) {
+            const double cd = D0 * D0 * std::fabs(sp.conic[0].d[q]) +
+                              2.0 * std::fabs(D0 * D1) * std::fabs(sp.conic[1].d[q]) +
+                              D1 * D1 * std::fabs(sp.conic[2].d[q]) +
+                              2.0 * (std::fabs(QD0) * std::fabs(sp.mu2[0].d[q]) +
+                                     std::fabs(QD1) * std::fabs(sp.mu2[1].d[q]));
+            da = std::fabs(sp.alpha_eff.d[q]) * gexp + al * 0.5 * cd;
+          }
+          gcnd[q] += cond_a * da;
           for (int k = 1; k < 8; ++k) gcnd[q] += std::fabs(terms[k]);
         }
         for (int ch = 0; ch < 3; ++ch) {
