@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--workload", default="knot1m_1080p", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after timing, run one device-to-device copy of this many MiB "
+                         "(reference dispatch for scaling HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -142,6 +145,15 @@ def main():
     t1 = time.perf_counter()
     prof = _hgs.hgs_profile_read(rast.ctx, reset=True)
     _hgs.hgs_profile_enable(rast.ctx, False)
+
+    if args.calib_copy_mb > 0:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy_mb} MiB done")
 
     ms = (t1 - t0) * 1e3 / args.steps
     P = H * W

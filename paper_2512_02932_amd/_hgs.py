@@ -68,6 +68,10 @@ def load(path: str | None = None):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime.  Load it first so that libhgs.so binds
+    # to the runtime already in the process instead of bringing up a second
+    # one (two HSA runtimes in one process cannot share the device).
+    import torch  # noqa: F401
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is not built; run paper_2512_02932_amd.build.build() "

@@ -69,6 +69,7 @@ struct hgs_state {
   Record *rec = nullptr;
   uint32_t *tiles = nullptr, *zbits = nullptr, *offsets = nullptr;
   int4 *rect = nullptr;
+  uint8_t *flags = nullptr;
   uint64_t *total = nullptr;
   uint64_t *keys = nullptr;
   uint32_t *vals = nullptr;
@@ -406,6 +407,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc_t(st, &st->tiles, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->zbits, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->rect, (size_t)VN));
+  ST_HIP(dalloc_t(st, &st->flags, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->offsets, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->total, (size_t)1));
   void *scan_tmp = nullptr;
@@ -419,7 +421,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   {
     StageTimer t(ctx, HGS_STAGE_PREPROCESS, st->stream);
     launch_preprocess(st->scene, st->cams, n_views, st->opt, st->rec, st->tiles, st->zbits,
-                      st->rect, st->stream);
+                      st->rect, st->flags, st->stream);
   }
   {
     StageTimer t(ctx, HGS_STAGE_SCAN, st->stream);
@@ -526,9 +528,9 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_image
   }
   {
     StageTimer t(ctx, HGS_STAGE_PREPROCESS_BWD, s);
-    launch_preprocess_bwd(st->scene, st->cams, st->V, st->opt, st->tiles, accum, grads->means,
-                          grads->scales, grads->rotations, grads->opacities, grads->sh,
-                          grads->accumulate, s);
+    launch_preprocess_bwd(st->scene, st->cams, st->V, st->opt, st->flags, st->rect, accum,
+                          grads->means, grads->scales, grads->rotations, grads->opacities,
+                          grads->sh, grads->accumulate, s);
   }
   HGS_HIP(hipGetLastError());
   HGS_HIP(hipFreeAsync(accum, s));

@@ -37,16 +37,16 @@ struct DevOpts {
 
 // Per-(view, splat) record read by the raster kernels: five float4, the
 // same size for both types so a batch loads uniformly.
-//   r0 = (tag, ox, oy, alpha_eff)           tag 1 = 3D, 0 = 2D; (ox, oy) =
-//                                          integer pixel origin of the
-//                                          splat's local frame
-//   3D: r1 = (mx, my, A, B), r2 = (C, 0, 0, 0), r3 = (0, r, g, b),
-//       r4 = (nx, ny, nz, z)
-//       exponent = A dx^2 + B dx dy + C dy^2, dx = x+1/2-ox-mx,
+//   r0 = (x0, y0, x1, y1)  the splat's inclusive pixel rectangle; (x0, y0) is
+//                          also the origin of the splat's local pixel frame
+//   r4 = (nx, ny, nz, a)   camera-space normal; |a| = alpha_eff, and the sign
+//                          bit of a marks a 2D surfel
+//   3D: r1 = (mx, my, A, B), r2 = (C, z, 0, 0), r3 = (0, r, g, b)
+//       exponent = A dx^2 + B dx dy + C dy^2, dx = x+1/2-x0-mx,
 //       alpha~ = alpha_eff 2^-exponent  (A, B, C = log2(e)/2 * conic, B x2)
 //   2D: r1 = (H00, H01, H02, H10), r2 = (H11, H12, H20, H21),
-//       r3 = (H22, r, g, b), r4 = (nx, ny, nz, 0)
-//       (U, V, W) = H (x', y', 1), x' = x+1/2-ox; exponent = (U^2+V^2)/W^2,
+//       r3 = (H22, r, g, b)
+//       (U, V, W) = H (x', y', 1), x' = x+1/2-x0; exponent = (U^2+V^2)/W^2,
 //       depth = 1/W.  H is the inverse of the surfel's plane-to-pixel map,
 //       rows 0 and 1 scaled by sqrt(log2(e)/2).
 struct Record {
@@ -61,13 +61,14 @@ struct SceneDev {
 };
 
 // ----- launchers (all enqueue on `s`) -----
+// flags per (view, splat): bit 0 valid, bit 1 normal negated, bits 2-3 normal axis
 void launch_preprocess(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt,
                        Record *rec, uint32_t *tiles, uint32_t *zbits, int4 *rect,
-                       hipStream_t s);
+                       uint8_t *flags, hipStream_t s);
 void launch_preprocess_bwd(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt,
-                           const uint32_t *tiles, const float *accum, float *g_means,
-                           float *g_scales, float *g_rots, float *g_opac, float *g_sh,
-                           int accumulate, hipStream_t s);
+                           const uint8_t *flags, const int4 *rect, const float *accum,
+                           float *g_means, float *g_scales, float *g_rots, float *g_opac,
+                           float *g_sh, int accumulate, hipStream_t s);
 
 // Exclusive scan of n uint32 values; writes the 64-bit total to *total
 // (device).  `tmp` must hold scan_tmp_bytes(n) bytes.

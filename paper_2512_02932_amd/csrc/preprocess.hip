@@ -149,9 +149,13 @@ __host__ __device__ Structural structural_f32(const float *m, const float *sc, c
   const int py1 = (yhi >= Hm1) ? c.H - 1 : (int)floorf(yhi);
   if (px0 > px1 || py0 > py1) return o;
 
-  const float nc0 = (V[0] * R[k] + V[1] * R[3 + k]) + V[2] * R[6 + k];
-  const float nc1 = (V[4] * R[k] + V[5] * R[3 + k]) + V[6] * R[6 + k];
-  const float nc2 = (V[8] * R[k] + V[9] * R[3 + k]) + V[10] * R[6 + k];
+  // column k of R, selected without dynamic register indexing
+  const float rk0 = k == 0 ? R[0] : (k == 1 ? R[1] : R[2]);
+  const float rk1 = k == 0 ? R[3] : (k == 1 ? R[4] : R[5]);
+  const float rk2 = k == 0 ? R[6] : (k == 1 ? R[7] : R[8]);
+  const float nc0 = (V[0] * rk0 + V[1] * rk1) + V[2] * rk2;
+  const float nc1 = (V[4] * rk0 + V[5] * rk1) + V[6] * rk2;
+  const float nc2 = (V[8] * rk0 + V[9] * rk1) + V[10] * rk2;
   const float dot = (nc0 * xc + nc1 * yc) + nc2 * zc;
 
   o.valid = 1;
@@ -170,7 +174,7 @@ __host__ __device__ Structural structural_f32(const float *m, const float *sc, c
 
 // ---------------------------------------------------------------------------
 // Real spherical harmonics up to degree 3 (Condon-Shortley phase), as
-// polynomials of the unit direction, and their gradient.
+// polynomials of the unit direction, and (backward only) their gradient.
 // Coefficient j = l^2 + l + m.
 // ---------------------------------------------------------------------------
 constexpr double kY0 = 0.28209479177387814;   // 1 / (2 sqrt(pi))
@@ -184,40 +188,90 @@ constexpr double kY3c = 0.45704579946446572;  // sqrt(21 / (32 pi))
 constexpr double kY3d = 0.37317633259011546;  // sqrt(7 / (16 pi))
 constexpr double kY3e = 1.4453057213202769;   // sqrt(105 / (16 pi))
 
-__device__ inline void sh_basis(int deg, double x, double y, double z, double *Y,
-                                double (*dY)[3]) {
+template <int D>
+__device__ __forceinline__ void sh_basis(double x, double y, double z, double *Y) {
   Y[0] = kY0;
-  dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
-  if (deg < 1) return;
-  Y[1] = -kY1 * y;  dY[1][0] = 0;        dY[1][1] = -kY1;     dY[1][2] = 0;
-  Y[2] = kY1 * z;   dY[2][0] = 0;        dY[2][1] = 0;        dY[2][2] = kY1;
-  Y[3] = -kY1 * x;  dY[3][0] = -kY1;     dY[3][1] = 0;        dY[3][2] = 0;
-  if (deg < 2) return;
-  Y[4] = kY2a * x * y;
-  dY[4][0] = kY2a * y; dY[4][1] = kY2a * x; dY[4][2] = 0;
-  Y[5] = -kY2a * y * z;
-  dY[5][0] = 0; dY[5][1] = -kY2a * z; dY[5][2] = -kY2a * y;
-  Y[6] = kY2b * (3.0 * z * z - 1.0);
-  dY[6][0] = 0; dY[6][1] = 0; dY[6][2] = 6.0 * kY2b * z;
-  Y[7] = -kY2a * x * z;
-  dY[7][0] = -kY2a * z; dY[7][1] = 0; dY[7][2] = -kY2a * x;
-  Y[8] = kY2c * (x * x - y * y);
-  dY[8][0] = 2.0 * kY2c * x; dY[8][1] = -2.0 * kY2c * y; dY[8][2] = 0;
-  if (deg < 3) return;
-  Y[9] = -kY3a * y * (3.0 * x * x - y * y);
-  dY[9][0] = -kY3a * 6.0 * x * y; dY[9][1] = -kY3a * (3.0 * x * x - 3.0 * y * y); dY[9][2] = 0;
-  Y[10] = kY3b * x * y * z;
-  dY[10][0] = kY3b * y * z; dY[10][1] = kY3b * x * z; dY[10][2] = kY3b * x * y;
-  Y[11] = -kY3c * y * (5.0 * z * z - 1.0);
-  dY[11][0] = 0; dY[11][1] = -kY3c * (5.0 * z * z - 1.0); dY[11][2] = -kY3c * 10.0 * y * z;
-  Y[12] = kY3d * z * (5.0 * z * z - 3.0);
-  dY[12][0] = 0; dY[12][1] = 0; dY[12][2] = kY3d * (15.0 * z * z - 3.0);
-  Y[13] = -kY3c * x * (5.0 * z * z - 1.0);
-  dY[13][0] = -kY3c * (5.0 * z * z - 1.0); dY[13][1] = 0; dY[13][2] = -kY3c * 10.0 * x * z;
-  Y[14] = kY3e * z * (x * x - y * y);
-  dY[14][0] = kY3e * 2.0 * x * z; dY[14][1] = -kY3e * 2.0 * y * z; dY[14][2] = kY3e * (x * x - y * y);
-  Y[15] = -kY3a * x * (x * x - 3.0 * y * y);
-  dY[15][0] = -kY3a * (3.0 * x * x - 3.0 * y * y); dY[15][1] = kY3a * 6.0 * x * y; dY[15][2] = 0;
+  if constexpr (D >= 1) {
+    Y[1] = -kY1 * y;
+    Y[2] = kY1 * z;
+    Y[3] = -kY1 * x;
+  }
+  if constexpr (D >= 2) {
+    Y[4] = kY2a * x * y;
+    Y[5] = -kY2a * y * z;
+    Y[6] = kY2b * (3.0 * z * z - 1.0);
+    Y[7] = -kY2a * x * z;
+    Y[8] = kY2c * (x * x - y * y);
+  }
+  if constexpr (D >= 3) {
+    Y[9] = -kY3a * y * (3.0 * x * x - y * y);
+    Y[10] = kY3b * x * y * z;
+    Y[11] = -kY3c * y * (5.0 * z * z - 1.0);
+    Y[12] = kY3d * z * (5.0 * z * z - 3.0);
+    Y[13] = -kY3c * x * (5.0 * z * z - 1.0);
+    Y[14] = kY3e * z * (x * x - y * y);
+    Y[15] = -kY3a * x * (x * x - 3.0 * y * y);
+  }
+}
+
+// sum_j w_j dY_j/d(x, y, z) for weights w (one per coefficient)
+template <int D>
+__device__ __forceinline__ void sh_grad_dot(double x, double y, double z, const double *w,
+                                            double *g) {
+  g[0] = g[1] = g[2] = 0.0;
+  if constexpr (D >= 1) {
+    g[1] += -kY1 * w[1];
+    g[2] += kY1 * w[2];
+    g[0] += -kY1 * w[3];
+  }
+  if constexpr (D >= 2) {
+    g[0] += kY2a * y * w[4];
+    g[1] += kY2a * x * w[4];
+    g[1] += -kY2a * z * w[5];
+    g[2] += -kY2a * y * w[5];
+    g[2] += 6.0 * kY2b * z * w[6];
+    g[0] += -kY2a * z * w[7];
+    g[2] += -kY2a * x * w[7];
+    g[0] += 2.0 * kY2c * x * w[8];
+    g[1] += -2.0 * kY2c * y * w[8];
+  }
+  if constexpr (D >= 3) {
+    g[0] += -kY3a * 6.0 * x * y * w[9];
+    g[1] += -kY3a * (3.0 * x * x - 3.0 * y * y) * w[9];
+    g[0] += kY3b * y * z * w[10];
+    g[1] += kY3b * x * z * w[10];
+    g[2] += kY3b * x * y * w[10];
+    g[1] += -kY3c * (5.0 * z * z - 1.0) * w[11];
+    g[2] += -kY3c * 10.0 * y * z * w[11];
+    g[2] += kY3d * (15.0 * z * z - 3.0) * w[12];
+    g[0] += -kY3c * (5.0 * z * z - 1.0) * w[13];
+    g[2] += -kY3c * 10.0 * x * z * w[13];
+    g[0] += kY3e * 2.0 * x * z * w[14];
+    g[1] += -kY3e * 2.0 * y * z * w[14];
+    g[2] += kY3e * (x * x - y * y) * w[14];
+    g[0] += -kY3a * (3.0 * x * x - 3.0 * y * y) * w[15];
+    g[1] += kY3a * 6.0 * x * y * w[15];
+  }
+}
+
+// SH coefficients of one splat, [K][3] floats.
+template <int K>
+__device__ __forceinline__ void load_sh(const float *__restrict__ sh, int64_t g, float *f) {
+  const float *p = sh + (size_t)g * (3 * K);
+  if constexpr ((3 * K) % 4 == 0) {
+    const float4 *p4 = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int i = 0; i < (3 * K) / 4; ++i) {
+      const float4 t = p4[i];
+      f[4 * i] = t.x;
+      f[4 * i + 1] = t.y;
+      f[4 * i + 2] = t.z;
+      f[4 * i + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) f[i] = p[i];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -225,95 +279,58 @@ __device__ inline void sh_basis(int deg, double x, double y, double z, double *Y
 // ---------------------------------------------------------------------------
 struct Geo {
   double q[4], qn;      // normalised quaternion and |r|
-  double R[9];          // rotation (row-major)
   double s[3];
   double pc[3];         // camera-space centre
-  double RvR[9];        // R_v R
-  double dir[3], dist;  // unit direction camera centre -> mean, distance
-  double alpha_eff, gate_sig, gate_arg;
-  double color[3];
-  int clamped[3];
-  double Y[16];
-  double dY[16][3];
-  double nrm[3];        // oriented camera-space normal
-  double ox, oy;        // local pixel frame origin (integers)
+  double RvR[9];        // R_v R (row-major)
+  double alpha_eff, gate_sig;
+  double ox, oy;        // local pixel frame origin: the rectangle's corner
   // 3D
   double A[6];          // 2x3, Sigma' = A A^T + delta I
-  double Sp[3];         // Sigma' (00, 01, 11)
   double conic[3];
   double mu2[2];
   // 2D
-  double M[9];          // plane -> pixel map in the local frame
-  double Hi[9];         // M^{-1}
+  double Hi[9];         // inverse of the plane -> pixel map in the local frame
 };
 
-__device__ inline double frame_origin(double v) {
-  double f = floor(v);
-  if (!(f > -1.0e6)) f = -1.0e6;  // also catches NaN
-  if (f > 1.0e6) f = 1.0e6;
-  return f;
-}
-
-__device__ void geo_setup(const SceneDev &sc, int64_t g, const DevCam &c, const DevOpts &opt,
-                          const Structural &st, bool is2d, Geo &o) {
-  const float *mf = sc.means + 3 * g;
-  const float *sf = sc.scales + 3 * g;
-  const float *qf = sc.rots + 4 * g;
+__device__ __forceinline__ void geo_setup(const float *mf, const float *sf, const float *qf,
+                                          float opac, bool is2d, const DevCam &c,
+                                          const DevOpts &opt, double ox, double oy, Geo &o) {
   const double mu[3] = {mf[0], mf[1], mf[2]};
   for (int i = 0; i < 3; ++i) o.s[i] = sf[i];
   const double r[4] = {qf[0], qf[1], qf[2], qf[3]};
   o.qn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
   for (int i = 0; i < 4; ++i) o.q[i] = r[i] / o.qn;
   const double w = o.q[0], x = o.q[1], y = o.q[2], z = o.q[3];
-  o.R[0] = 1.0 - 2.0 * (y * y + z * z);
-  o.R[1] = 2.0 * (x * y - w * z);
-  o.R[2] = 2.0 * (x * z + w * y);
-  o.R[3] = 2.0 * (x * y + w * z);
-  o.R[4] = 1.0 - 2.0 * (x * x + z * z);
-  o.R[5] = 2.0 * (y * z - w * x);
-  o.R[6] = 2.0 * (x * z - w * y);
-  o.R[7] = 2.0 * (y * z + w * x);
-  o.R[8] = 1.0 - 2.0 * (x * x + y * y);
+  double R[9];
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
   const double *Vd = c.Vd;
   for (int i = 0; i < 3; ++i)
     o.pc[i] = Vd[4 * i] * mu[0] + Vd[4 * i + 1] * mu[1] + Vd[4 * i + 2] * mu[2] + Vd[4 * i + 3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
-      o.RvR[3 * i + j] = Vd[4 * i] * o.R[j] + Vd[4 * i + 1] * o.R[3 + j] + Vd[4 * i + 2] * o.R[6 + j];
+      o.RvR[3 * i + j] = Vd[4 * i] * R[j] + Vd[4 * i + 1] * R[3 + j] + Vd[4 * i + 2] * R[6 + j];
 
   // opacity; 2D: alpha* = alpha exp(-lambda_z sigmoid((s_z - theta_z)/T_z) s_z)
-  const double al = sc.opac[g];
+  const double al = opac;
   if (is2d) {
-    o.gate_arg = (o.s[2] - (double)opt.theta_z) / (double)opt.temp_z;
-    const double za = o.gate_arg;
+    const double za = (o.s[2] - (double)opt.theta_z) / (double)opt.temp_z;
     o.gate_sig = za >= 0 ? 1.0 / (1.0 + exp(-za)) : exp(za) / (1.0 + exp(za));
     o.alpha_eff = al * exp(-(double)opt.lambda_z * o.gate_sig * o.s[2]);
   } else {
-    o.gate_arg = 0.0;
     o.gate_sig = 0.0;
     o.alpha_eff = al;
   }
 
-  // colour
-  double dv[3];
-  for (int i = 0; i < 3; ++i) dv[i] = mu[i] - c.o[i];
-  o.dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-  for (int i = 0; i < 3; ++i) o.dir[i] = dv[i] / o.dist;
-  const int deg = sc.sh_degree;
-  const int K = (deg + 1) * (deg + 1);
-  sh_basis(deg, o.dir[0], o.dir[1], o.dir[2], o.Y, o.dY);
-  const float *shp = sc.sh + (size_t)g * K * 3;
-  for (int ch = 0; ch < 3; ++ch) {
-    double acc = 0.5;
-    for (int j = 0; j < K; ++j) acc += (double)shp[3 * j + ch] * o.Y[j];
-    o.clamped[ch] = !(acc > 0.0);
-    o.color[ch] = o.clamped[ch] ? 0.0 : acc;
-  }
-
-  // normal
-  const double sg = st.flip ? -1.0 : 1.0;
-  for (int i = 0; i < 3; ++i) o.nrm[i] = sg * o.RvR[3 * i + st.axis];
-
+  o.ox = ox;
+  o.oy = oy;
   const double X = o.pc[0], Yc = o.pc[1], Z = o.pc[2];
   const double fx = c.fx, fy = c.fy, cx = c.cx, cy = c.cy;
   if (!is2d) {
@@ -324,33 +341,29 @@ __device__ void geo_setup(const SceneDev &sc, int64_t g, const DevCam &c, const 
       o.A[j] = J00 * c0 + J02 * c2;
       o.A[3 + j] = J11 * c1 + J12 * c2;
     }
-    o.Sp[0] = o.A[0] * o.A[0] + o.A[1] * o.A[1] + o.A[2] * o.A[2] + (double)opt.dilation;
-    o.Sp[1] = o.A[0] * o.A[3] + o.A[1] * o.A[4] + o.A[2] * o.A[5];
-    o.Sp[2] = o.A[3] * o.A[3] + o.A[4] * o.A[4] + o.A[5] * o.A[5] + (double)opt.dilation;
-    const double det = o.Sp[0] * o.Sp[2] - o.Sp[1] * o.Sp[1];
-    o.conic[0] = o.Sp[2] / det;
-    o.conic[1] = -o.Sp[1] / det;
-    o.conic[2] = o.Sp[0] / det;
+    const double S0 = o.A[0] * o.A[0] + o.A[1] * o.A[1] + o.A[2] * o.A[2] + (double)opt.dilation;
+    const double S1 = o.A[0] * o.A[3] + o.A[1] * o.A[4] + o.A[2] * o.A[5];
+    const double S2 = o.A[3] * o.A[3] + o.A[4] * o.A[4] + o.A[5] * o.A[5] + (double)opt.dilation;
+    const double det = S0 * S2 - S1 * S1;
+    o.conic[0] = S2 / det;
+    o.conic[1] = -S1 / det;
+    o.conic[2] = S0 / det;
     o.mu2[0] = fx * X / Z + cx;
     o.mu2[1] = fy * Yc / Z + cy;
-    o.ox = frame_origin(o.mu2[0]);
-    o.oy = frame_origin(o.mu2[1]);
   } else {
-    o.ox = frame_origin(fx * X / Z + cx);
-    o.oy = frame_origin(fy * Yc / Z + cy);
-    const double cxl = cx - o.ox, cyl = cy - o.oy;
-    double Cm[9];  // columns s_x t_u, s_y t_v, p_c (camera frame)
-    for (int i = 0; i < 3; ++i) {
-      Cm[3 * i] = o.s[0] * o.RvR[3 * i];
-      Cm[3 * i + 1] = o.s[1] * o.RvR[3 * i + 1];
-      Cm[3 * i + 2] = o.pc[i];
-    }
+    // plane (u, v, 1) -> homogeneous pixel in the local frame:
+    // M = K' [s_x t_u | s_y t_v | p_c], K' = K shifted by the frame origin
+    const double cxl = cx - ox, cyl = cy - oy;
+    double M[9];
     for (int j = 0; j < 3; ++j) {
-      o.M[j] = fx * Cm[j] + cxl * Cm[6 + j];
-      o.M[3 + j] = fy * Cm[3 + j] + cyl * Cm[6 + j];
-      o.M[6 + j] = Cm[6 + j];
+      const double sj = j < 2 ? o.s[j] : 1.0;
+      const double c0 = j < 2 ? sj * o.RvR[j] : o.pc[0];
+      const double c1 = j < 2 ? sj * o.RvR[3 + j] : o.pc[1];
+      const double c2 = j < 2 ? sj * o.RvR[6 + j] : o.pc[2];
+      M[j] = fx * c0 + cxl * c2;
+      M[3 + j] = fy * c1 + cyl * c2;
+      M[6 + j] = c2;
     }
-    const double *M = o.M;
     const double a00 = M[4] * M[8] - M[5] * M[7];
     const double a01 = M[2] * M[7] - M[1] * M[8];
     const double a02 = M[1] * M[5] - M[2] * M[4];
@@ -368,10 +381,29 @@ __device__ void geo_setup(const SceneDev &sc, int64_t g, const DevCam &c, const 
   }
 }
 
+// Unit view direction (camera centre -> mean) and the distance.
+__device__ __forceinline__ void view_dir(const float *mf, const DevCam &c, double *dir,
+                                         double &dist) {
+  double dv[3];
+  for (int i = 0; i < 3; ++i) dv[i] = (double)mf[i] - c.o[i];
+  dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+  for (int i = 0; i < 3; ++i) dir[i] = dv[i] / dist;
+}
+
+__device__ __forceinline__ double col_of(const double *M9, int row, int axis) {
+  return axis == 0 ? M9[3 * row] : (axis == 1 ? M9[3 * row + 1] : M9[3 * row + 2]);
+}
+
+// flags per (view, splat): bit 0 valid, bit 1 normal negated, bits 2-3 axis
+constexpr uint8_t kValid = 1, kFlip = 2;
+
+template <int DEG>
 __global__ void __launch_bounds__(256)
 preprocess_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOpts opt,
                   Record *__restrict__ rec, uint32_t *__restrict__ tiles,
-                  uint32_t *__restrict__ zbits, int4 *__restrict__ rect) {
+                  uint32_t *__restrict__ zbits, int4 *__restrict__ rect,
+                  uint8_t *__restrict__ flags) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)V * sc.n;
   if (i >= total) return;
@@ -381,42 +413,63 @@ preprocess_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOpts o
   const bool is2d = sc.types[g] == 0;
   const float m[3] = {sc.means[3 * g], sc.means[3 * g + 1], sc.means[3 * g + 2]};
   const float s[3] = {sc.scales[3 * g], sc.scales[3 * g + 1], sc.scales[3 * g + 2]};
-  const float q[4] = {sc.rots[4 * g], sc.rots[4 * g + 1], sc.rots[4 * g + 2], sc.rots[4 * g + 3]};
-  const Structural st = structural_f32(m, s, q, sc.opac[g], is2d, c, opt.dilation);
+  const float4 q4 = reinterpret_cast<const float4 *>(sc.rots)[g];
+  const float q[4] = {q4.x, q4.y, q4.z, q4.w};
+  const float al = sc.opac[g];
+  const Structural st = structural_f32(m, s, q, al, is2d, c, opt.dilation);
   tiles[i] = st.valid ? st.tiles : 0u;
   zbits[i] = st.zbits;
   rect[i] = make_int4(st.px0, st.py0, st.px1, st.py1);
+  flags[i] = (uint8_t)((st.valid ? kValid : 0) | (st.flip ? kFlip : 0) | (st.axis << 2));
   if (!st.valid) return;
 
   Geo o;
-  geo_setup(sc, g, c, opt, st, is2d, o);
-  Record r;
+  geo_setup(m, s, q, al, is2d, c, opt, (double)st.px0, (double)st.py0, o);
+  double dir[3], dist;
+  view_dir(m, c, dir, dist);
+  double Y[K];
+  sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+  float f[3 * K];
+  load_sh<K>(sc.sh, g, f);
+  float col[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    double acc = 0.5;
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc += (double)f[3 * j + ch] * Y[j];
+    col[ch] = acc > 0.0 ? (float)acc : 0.0f;
+  }
+  const double sg = st.flip ? -1.0 : 1.0;
+  const float nx = (float)(sg * col_of(o.RvR, 0, st.axis)),
+              ny = (float)(sg * col_of(o.RvR, 1, st.axis)),
+              nz = (float)(sg * col_of(o.RvR, 2, st.axis));
   const double k2 = sqrt(0.5 * kLog2e);
   float aeff = (float)o.alpha_eff;
+  Record r;
+  r.r[0] = make_float4((float)st.px0, (float)st.py0, (float)st.px1, (float)st.py1);
   if (!is2d) {
     const float mx = (float)(o.mu2[0] - o.ox), my = (float)(o.mu2[1] - o.oy);
     const float A = (float)(0.5 * kLog2e * o.conic[0]);
     const float B = (float)(kLog2e * o.conic[1]);
     const float C = (float)(0.5 * kLog2e * o.conic[2]);
     if (!(isfinite(mx) && isfinite(my) && isfinite(A) && isfinite(B) && isfinite(C))) aeff = 0.0f;
-    r.r[0] = make_float4(1.0f, (float)o.ox, (float)o.oy, aeff);
     r.r[1] = make_float4(mx, my, A, B);
-    r.r[2] = make_float4(C, 0.0f, 0.0f, 0.0f);
-    r.r[3] = make_float4(0.0f, (float)o.color[0], (float)o.color[1], (float)o.color[2]);
-    r.r[4] = make_float4((float)o.nrm[0], (float)o.nrm[1], (float)o.nrm[2], (float)o.pc[2]);
+    r.r[2] = make_float4(C, (float)o.pc[2], 0.0f, 0.0f);
+    r.r[3] = make_float4(0.0f, col[0], col[1], col[2]);
+    r.r[4] = make_float4(nx, ny, nz, aeff);
   } else {
     float h[9];
     bool fin = true;
+#pragma unroll
     for (int j = 0; j < 9; ++j) {
       h[j] = (float)(j < 6 ? k2 * o.Hi[j] : o.Hi[j]);
       fin = fin && isfinite(h[j]);
     }
     if (!fin) aeff = 0.0f;  // edge-on: every ray misses; never active
-    r.r[0] = make_float4(0.0f, (float)o.ox, (float)o.oy, aeff);
     r.r[1] = make_float4(h[0], h[1], h[2], h[3]);
     r.r[2] = make_float4(h[4], h[5], h[6], h[7]);
-    r.r[3] = make_float4(h[8], (float)o.color[0], (float)o.color[1], (float)o.color[2]);
-    r.r[4] = make_float4((float)o.nrm[0], (float)o.nrm[1], (float)o.nrm[2], 0.0f);
+    r.r[3] = make_float4(h[8], col[0], col[1], col[2]);
+    r.r[4] = make_float4(nx, ny, nz, -aeff);  // negative sign marks a surfel
   }
   Record *dst = rec + i;
 #pragma unroll
@@ -428,181 +481,169 @@ preprocess_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOpts o
 //   3D: 0 mx, 1 my, 2 A, 3 B, 4 C, 5 depth z, 9 alpha_eff, 10-12 rgb, 13-15 n
 //   2D: 0-8 H (stored, scaled) entries, 9 alpha_eff, 10-12 rgb, 13-15 n
 // ---------------------------------------------------------------------------
+template <int DEG, bool MULTI>
 __global__ void __launch_bounds__(128)
 preprocess_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOpts opt,
-                      const uint32_t *__restrict__ tiles, const float *__restrict__ accum,
-                      float *g_means, float *g_scales, float *g_rots, float *g_opac,
-                      float *g_sh, int accumulate) {
+                      const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
+                      const float *__restrict__ accum, float *g_means, float *g_scales,
+                      float *g_rots, float *g_opac, float *g_sh, int accumulate) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= sc.n) return;
   const bool is2d = sc.types[g] == 0;
-  const int deg = sc.sh_degree;
-  const int K = (deg + 1) * (deg + 1);
   const float m[3] = {sc.means[3 * g], sc.means[3 * g + 1], sc.means[3 * g + 2]};
   const float s[3] = {sc.scales[3 * g], sc.scales[3 * g + 1], sc.scales[3 * g + 2]};
-  const float q[4] = {sc.rots[4 * g], sc.rots[4 * g + 1], sc.rots[4 * g + 2], sc.rots[4 * g + 3]};
-
-  double gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gal = 0.0;
-  double gsh[48];
-  for (int j = 0; j < 3 * K; ++j) gsh[j] = 0.0;
+  const float4 q4 = reinterpret_cast<const float4 *>(sc.rots)[g];
+  const float q[4] = {q4.x, q4.y, q4.z, q4.w};
+  const float al32 = sc.opac[g];
   const double k2 = sqrt(0.5 * kLog2e);
 
+  double gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gal = 0.0;
+
+  // ---- pass 1: geometry (record geometry, opacity, normal) ----
   for (int v = 0; v < V; ++v) {
     const int64_t i = (int64_t)v * sc.n + g;
-    if (tiles[i] == 0) continue;
+    const uint8_t fl = flags[i];
+    if (!(fl & kValid)) continue;
     float a[kGradSlots];
-    bool any = false;
     const float4 *ap = reinterpret_cast<const float4 *>(accum + i * kGradSlots);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const float4 t = ap[k];
-      a[4 * k] = t.x; a[4 * k + 1] = t.y; a[4 * k + 2] = t.z; a[4 * k + 3] = t.w;
+      a[4 * k] = t.x;
+      a[4 * k + 1] = t.y;
+      a[4 * k + 2] = t.z;
+      a[4 * k + 3] = t.w;
     }
+    bool any = false;
 #pragma unroll
     for (int k = 0; k < kGradSlots; ++k) any = any || (a[k] != 0.0f);
     if (!any) continue;
     const DevCam &c = cams[v];
-    const Structural st = structural_f32(m, s, q, sc.opac[g], is2d, c, opt.dilation);
+    const int4 rc = rect[i];
     Geo o;
-    geo_setup(sc, g, c, opt, st, is2d, o);
+    geo_setup(m, s, q, al32, is2d, c, opt, (double)rc.x, (double)rc.y, o);
+    const int axis = (fl >> 2) & 3;
 
-    double gpc[3] = {0, 0, 0};   // dL/d p_c
-    double gRvR[9];              // dL/d (R_v R)
+    double gpc[3] = {0, 0, 0};  // dL/d p_c
+    double gRvR[9];             // dL/d (R_v R)
+#pragma unroll
     for (int j = 0; j < 9; ++j) gRvR[j] = 0.0;
-    double gsv[3] = {0, 0, 0};   // dL/d s (this view)
+    double gsv[3] = {0, 0, 0};  // dL/d s (this view)
 
     // normal: n = sign * (R_v R)[:, axis]
-    const double sg = st.flip ? -1.0 : 1.0;
-    for (int r = 0; r < 3; ++r) gRvR[3 * r + st.axis] += sg * (double)a[13 + r];
+    const double sg = (fl & kFlip) ? -1.0 : 1.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double gn = sg * (double)a[13 + r];
+      gRvR[3 * r] += axis == 0 ? gn : 0.0;
+      gRvR[3 * r + 1] += axis == 1 ? gn : 0.0;
+      gRvR[3 * r + 2] += axis == 2 ? gn : 0.0;
+    }
 
     const double X = o.pc[0], Yc = o.pc[1], Z = o.pc[2];
     const double fx = c.fx, fy = c.fy;
     if (!is2d) {
       // conic entries (A, B, C stored = k c00, 2k c01, k c11 with k = log2e/2)
       const double kk = 0.5 * kLog2e;
-      const double ga = kk * a[2], gb = 2.0 * kk * a[3], gc = kk * a[4];
-      // dL/dSigma' = -Q G Q with G = [[ga, gb/2], [gb/2, gc]]
-      const double *Q = o.conic;  // (q00, q01, q11)
-      const double G00 = ga, G01 = 0.5 * gb, G11 = gc;
-      // QG
+      const double G00 = kk * a[2], G01 = kk * a[3], G11 = kk * a[4];
+      // dL/dSigma' = -Q G Q, G = [[G00, G01], [G01, G11]]
+      const double *Q = o.conic;
       const double t00 = Q[0] * G00 + Q[1] * G01, t01 = Q[0] * G01 + Q[1] * G11;
       const double t10 = Q[1] * G00 + Q[2] * G01, t11 = Q[1] * G01 + Q[2] * G11;
       const double S00 = -(t00 * Q[0] + t01 * Q[1]);
       const double S01 = -(t00 * Q[1] + t01 * Q[2]);
       const double S11 = -(t10 * Q[1] + t11 * Q[2]);
-      // Sigma' = A A^T: dL/dA = 2 S A (S symmetric)
-      double gA[6];
-      for (int j = 0; j < 3; ++j) {
-        gA[j] = 2.0 * (S00 * o.A[j] + S01 * o.A[3 + j]);
-        gA[3 + j] = 2.0 * (S01 * o.A[j] + S11 * o.A[3 + j]);
-      }
-      // A = J Cm with Cm = R_v R S (3x3), J = [[J00,0,J02],[0,J11,J12]]
       const double J00 = fx / Z, J02 = -fx * X / (Z * Z), J11 = fy / Z, J12 = -fy * Yc / (Z * Z);
       double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
+#pragma unroll
       for (int j = 0; j < 3; ++j) {
+        // Sigma' = A A^T: dL/dA = 2 S A
+        const double gA0 = 2.0 * (S00 * o.A[j] + S01 * o.A[3 + j]);
+        const double gA1 = 2.0 * (S01 * o.A[j] + S11 * o.A[3 + j]);
         const double c0 = o.RvR[j] * o.s[j], c1 = o.RvR[3 + j] * o.s[j], c2 = o.RvR[6 + j] * o.s[j];
-        gJ00 += gA[j] * c0;
-        gJ02 += gA[j] * c2;
-        gJ11 += gA[3 + j] * c1;
-        gJ12 += gA[3 + j] * c2;
-        const double gc0 = gA[j] * J00, gc1 = gA[3 + j] * J11, gc2 = gA[j] * J02 + gA[3 + j] * J12;
-        // Cm[:, j] = RvR[:, j] * s_j
+        gJ00 += gA0 * c0;
+        gJ02 += gA0 * c2;
+        gJ11 += gA1 * c1;
+        gJ12 += gA1 * c2;
+        const double gc0 = gA0 * J00, gc1 = gA1 * J11, gc2 = gA0 * J02 + gA1 * J12;
         gRvR[j] += gc0 * o.s[j];
         gRvR[3 + j] += gc1 * o.s[j];
         gRvR[6 + j] += gc2 * o.s[j];
         gsv[j] += gc0 * o.RvR[j] + gc1 * o.RvR[3 + j] + gc2 * o.RvR[6 + j];
       }
       const double iz = 1.0 / Z, iz2 = iz * iz, iz3 = iz2 * iz;
-      gpc[0] += gJ02 * (-fx * iz2);
-      gpc[1] += gJ12 * (-fy * iz2);
-      gpc[2] += gJ00 * (-fx * iz2) + gJ02 * (2.0 * fx * X * iz3) + gJ11 * (-fy * iz2) +
-                gJ12 * (2.0 * fy * Yc * iz3);
-      // projected centre
       const double gmx = a[0], gmy = a[1];
-      gpc[0] += gmx * fx * iz;
-      gpc[1] += gmy * fy * iz;
-      gpc[2] += -gmx * fx * X * iz2 - gmy * fy * Yc * iz2;
-      // depth = z
-      gpc[2] += a[5];
+      gpc[0] += gJ02 * (-fx * iz2) + gmx * fx * iz;
+      gpc[1] += gJ12 * (-fy * iz2) + gmy * fy * iz;
+      gpc[2] += gJ00 * (-fx * iz2) + gJ02 * (2.0 * fx * X * iz3) + gJ11 * (-fy * iz2) +
+                gJ12 * (2.0 * fy * Yc * iz3) - gmx * fx * X * iz2 - gmy * fy * Yc * iz2 +
+                (double)a[5];
       gal += (double)a[9];
     } else {
-      // stored h = D Hi (rows 0, 1 scaled by k2); Hi = M^{-1}
+      // stored h = D Hi (rows 0, 1 scaled by k2); Hi = M^{-1}; dL/dM = -Hi^T gH Hi^T
       double gH[9];
+#pragma unroll
       for (int j = 0; j < 9; ++j) gH[j] = (double)a[j] * (j < 6 ? k2 : 1.0);
-      // dL/dM = -Hi^T gH Hi^T
       double T1[9];  // Hi^T gH
+#pragma unroll
       for (int r = 0; r < 3; ++r)
+#pragma unroll
         for (int cc = 0; cc < 3; ++cc)
           T1[3 * r + cc] = o.Hi[r] * gH[cc] + o.Hi[3 + r] * gH[3 + cc] + o.Hi[6 + r] * gH[6 + cc];
-      double gM[9];
-      for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc)
-          gM[3 * r + cc] = -(T1[3 * r] * o.Hi[3 * cc] + T1[3 * r + 1] * o.Hi[3 * cc + 1] +
-                             T1[3 * r + 2] * o.Hi[3 * cc + 2]);
-      // M = K' Cm, K' = [[fx, 0, cxl], [0, fy, cyl], [0, 0, 1]]: dL/dCm = K'^T gM
+      // M = K' Cm: dL/dCm = K'^T gM with gM = -T1 Hi^T
       const double cxl = c.cx - o.ox, cyl = c.cy - o.oy;
-      double gC[9];
+#pragma unroll
       for (int j = 0; j < 3; ++j) {
-        gC[j] = fx * gM[j];
-        gC[3 + j] = fy * gM[3 + j];
-        gC[6 + j] = cxl * gM[j] + cyl * gM[3 + j] + gM[6 + j];
+        const double gM0 = -(T1[0] * o.Hi[3 * j] + T1[1] * o.Hi[3 * j + 1] + T1[2] * o.Hi[3 * j + 2]);
+        const double gM1 = -(T1[3] * o.Hi[3 * j] + T1[4] * o.Hi[3 * j + 1] + T1[5] * o.Hi[3 * j + 2]);
+        const double gM2 = -(T1[6] * o.Hi[3 * j] + T1[7] * o.Hi[3 * j + 1] + T1[8] * o.Hi[3 * j + 2]);
+        const double gC0 = fx * gM0, gC1 = fy * gM1;
+        const double gC2 = cxl * gM0 + cyl * gM1 + gM2;
+        if (j < 2) {  // Cm[:, j] = s_j (R_v R)[:, j]
+          gRvR[j] += gC0 * o.s[j];
+          gRvR[3 + j] += gC1 * o.s[j];
+          gRvR[6 + j] += gC2 * o.s[j];
+          gsv[j] += gC0 * o.RvR[j] + gC1 * o.RvR[3 + j] + gC2 * o.RvR[6 + j];
+        } else {  // Cm[:, 2] = p_c
+          gpc[0] += gC0;
+          gpc[1] += gC1;
+          gpc[2] += gC2;
+        }
       }
-      // Cm = [s_x RvR[:,0] | s_y RvR[:,1] | p_c]
-      for (int r = 0; r < 3; ++r) {
-        gRvR[3 * r] += gC[3 * r] * o.s[0];
-        gRvR[3 * r + 1] += gC[3 * r + 1] * o.s[1];
-        gpc[r] += gC[3 * r + 2];
-      }
-      gsv[0] += gC[0] * o.RvR[0] + gC[3] * o.RvR[3] + gC[6] * o.RvR[6];
-      gsv[1] += gC[1] * o.RvR[1] + gC[4] * o.RvR[4] + gC[7] * o.RvR[7];
-      // opacity: alpha_eff = alpha exp(-lambda sig s_z)
-      const double al = sc.opac[g];
       const double ga_eff = (double)a[9];
-      gal += ga_eff * (o.alpha_eff / al);
-      const double lam = opt.lambda_z;
-      const double dsz = o.gate_sig + o.s[2] * o.gate_sig * (1.0 - o.gate_sig) / (double)opt.temp_z;
-      gsv[2] += ga_eff * o.alpha_eff * (-lam) * dsz;
+      gal += ga_eff * (o.alpha_eff / (double)al32);
+      const double dsz =
+          o.gate_sig + o.s[2] * o.gate_sig * (1.0 - o.gate_sig) / (double)opt.temp_z;
+      gsv[2] += ga_eff * o.alpha_eff * (-(double)opt.lambda_z) * dsz;
     }
-
-    // colour: c_ch = max(0, 1/2 + sum_j f_j,ch Y_j(dir))
-    const float *shp = sc.sh + (size_t)g * K * 3;
-    double gdir[3] = {0, 0, 0};
-    for (int ch = 0; ch < 3; ++ch) {
-      if (o.clamped[ch]) continue;
-      const double gcol = (double)a[10 + ch];
-      for (int j = 0; j < K; ++j) {
-        gsh[3 * j + ch] += gcol * o.Y[j];
-        const double f = shp[3 * j + ch];
-        gdir[0] += gcol * f * o.dY[j][0];
-        gdir[1] += gcol * f * o.dY[j][1];
-        gdir[2] += gcol * f * o.dY[j][2];
-      }
-    }
-    // dir = (mu - o) / |mu - o|
-    const double dd = o.dir[0] * gdir[0] + o.dir[1] * gdir[1] + o.dir[2] * gdir[2];
-    for (int k = 0; k < 3; ++k) gmu[k] += (gdir[k] - o.dir[k] * dd) / o.dist;
 
     // p_c = V mu + t
     const double *Vd = c.Vd;
+#pragma unroll
     for (int k = 0; k < 3; ++k) gmu[k] += Vd[k] * gpc[0] + Vd[4 + k] * gpc[1] + Vd[8 + k] * gpc[2];
     // RvR = V R: dL/dR = V^T gRvR
     double gR[9];
+#pragma unroll
     for (int r = 0; r < 3; ++r)
+#pragma unroll
       for (int cc = 0; cc < 3; ++cc)
         gR[3 * r + cc] = Vd[r] * gRvR[cc] + Vd[4 + r] * gRvR[3 + cc] + Vd[8 + r] * gRvR[6 + cc];
     // R(q) for a unit quaternion q = (w, x, y, z)
     const double w = o.q[0], x = o.q[1], y = o.q[2], z = o.q[3];
-    const double gw = 2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
-    const double gx = 2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] +
-                             z * gR[6] + w * gR[7] - 2.0 * x * gR[8]);
-    const double gy = 2.0 * (-2.0 * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] -
-                             w * gR[6] + z * gR[7] - 2.0 * y * gR[8]);
-    const double gz = 2.0 * (-2.0 * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] -
-                             2.0 * z * gR[4] + y * gR[5] + x * gR[6] + y * gR[7]);
-    const double gqn[4] = {gw, gx, gy, gz};
+    const double gqn[4] = {
+        2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]),
+        2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] + z * gR[6] +
+               w * gR[7] - 2.0 * x * gR[8]),
+        2.0 * (-2.0 * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
+               z * gR[7] - 2.0 * y * gR[8]),
+        2.0 * (-2.0 * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * z * gR[4] +
+               y * gR[5] + x * gR[6] + y * gR[7])};
     // q = r / |r|
     const double dq = gqn[0] * o.q[0] + gqn[1] * o.q[1] + gqn[2] * o.q[2] + gqn[3] * o.q[3];
+#pragma unroll
     for (int k = 0; k < 4; ++k) gq[k] += (gqn[k] - o.q[k] * dq) / o.qn;
+#pragma unroll
     for (int k = 0; k < 3; ++k) gs[k] += gsv[k];
   }
 
@@ -611,34 +652,136 @@ preprocess_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOp
     if (accumulate) dst[idx] += (float)val;
     else dst[idx] = (float)val;
   };
-  for (int k = 0; k < 3; ++k) put(g_means, 3 * g + k, gmu[k]);
   for (int k = 0; k < 3; ++k) put(g_scales, 3 * g + k, gs[k]);
-  for (int k = 0; k < 4; ++k) put(g_rots, 4 * g + k, gq[k]);
+  if (g_rots) {
+    float4 *dst = reinterpret_cast<float4 *>(g_rots) + g;
+    float4 val = make_float4((float)gq[0], (float)gq[1], (float)gq[2], (float)gq[3]);
+    if (accumulate) {
+      const float4 old = *dst;
+      val.x += old.x;
+      val.y += old.y;
+      val.z += old.z;
+      val.w += old.w;
+    }
+    *dst = val;
+  }
   put(g_opac, g, gal);
-  for (int j = 0; j < 3 * K; ++j) put(g_sh, (int64_t)g * 3 * K + j, gsh[j]);
+
+  // ---- pass 2: colour, c_ch = max(0, 1/2 + sum_j f_j,ch Y_j(dir)) ----
+  float f[3 * K];
+  load_sh<K>(sc.sh, g, f);
+  float gsh[MULTI ? 3 * K : 1];
+  if constexpr (MULTI) {
+#pragma unroll
+    for (int j = 0; j < 3 * K; ++j) gsh[j] = 0.0f;
+  }
+  bool wrote = false;
+  for (int v = 0; v < V; ++v) {
+    const int64_t i = (int64_t)v * sc.n + g;
+    if (!(flags[i] & kValid)) continue;
+    const float4 gc4 = reinterpret_cast<const float4 *>(accum + i * kGradSlots)[2];  // 8..11
+    const float gcl = reinterpret_cast<const float *>(accum + i * kGradSlots)[12];
+    const float gcol[3] = {gc4.z, gc4.w, gcl};
+    if (gcol[0] == 0.0f && gcol[1] == 0.0f && gcol[2] == 0.0f) continue;
+    double dir[3], dist;
+    view_dir(m, cams[v], dir, dist);
+    double Y[K];
+    sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+    double wj[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) wj[j] = 0.0;
+    float gy[3] = {0.0f, 0.0f, 0.0f};  // dL/dc_ch where unclamped
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      double acc = 0.5;
+#pragma unroll
+      for (int j = 0; j < K; ++j) acc += (double)f[3 * j + ch] * Y[j];
+      if (!(acc > 0.0)) continue;  // clamped channel: no gradient
+      gy[ch] = gcol[ch];
+#pragma unroll
+      for (int j = 0; j < K; ++j) wj[j] += (double)gcol[ch] * (double)f[3 * j + ch];
+    }
+    if constexpr (MULTI) {
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) gsh[3 * j + ch] += (float)((double)gy[ch] * Y[j]);
+    } else if (g_sh) {
+      float *dst = g_sh + (size_t)g * 3 * K;
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          const float val = (float)((double)gy[ch] * Y[j]);
+          dst[3 * j + ch] = accumulate ? dst[3 * j + ch] + val : val;
+        }
+      wrote = true;
+    }
+    double gdir[3];
+    sh_grad_dot<DEG>(dir[0], dir[1], dir[2], wj, gdir);
+    // dir = (mu - o) / |mu - o|
+    const double dd = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gmu[k] += (gdir[k] - dir[k] * dd) / dist;
+  }
+  for (int k = 0; k < 3; ++k) put(g_means, 3 * g + k, gmu[k]);
+  if (g_sh) {
+    float *dst = g_sh + (size_t)g * 3 * K;
+    if constexpr (MULTI) {
+#pragma unroll
+      for (int j = 0; j < 3 * K; ++j) dst[j] = accumulate ? dst[j] + gsh[j] : gsh[j];
+    } else {
+      if (!wrote && !accumulate) {
+#pragma unroll
+        for (int j = 0; j < 3 * K; ++j) dst[j] = 0.0f;
+      }
+    }
+  }
 }
 
 }  // namespace
 
 void launch_preprocess(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt, Record *rec,
-                       uint32_t *tiles, uint32_t *zbits, int4 *rect, hipStream_t s) {
+                       uint32_t *tiles, uint32_t *zbits, int4 *rect, uint8_t *flags,
+                       hipStream_t s) {
   const int64_t total = (int64_t)V * sc.n;
   if (total == 0) return;
   const int bs = 256;
-  const int64_t nb = (total + bs - 1) / bs;
-  hipLaunchKernelGGL(preprocess_kernel, dim3((unsigned)nb), dim3(bs), 0, s, sc, cams, V, opt, rec,
-                     tiles, zbits, rect);
+  const dim3 grid((unsigned)((total + bs - 1) / bs));
+  switch (sc.sh_degree) {
+    case 0: hipLaunchKernelGGL(preprocess_kernel<0>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags); break;
+    case 1: hipLaunchKernelGGL(preprocess_kernel<1>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags); break;
+    case 2: hipLaunchKernelGGL(preprocess_kernel<2>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags); break;
+    default: hipLaunchKernelGGL(preprocess_kernel<3>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags); break;
+  }
+}
+
+template <int DEG>
+static void launch_bwd_deg(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt,
+                           const uint8_t *flags, const int4 *rect, const float *accum,
+                           float *g_means, float *g_scales, float *g_rots, float *g_opac,
+                           float *g_sh, int accumulate, hipStream_t s) {
+  const int bs = 128;
+  const dim3 grid((unsigned)((sc.n + bs - 1) / bs));
+  if (V == 1)
+    hipLaunchKernelGGL((preprocess_bwd_kernel<DEG, false>), grid, dim3(bs), 0, s, sc, cams, V, opt,
+                       flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate);
+  else
+    hipLaunchKernelGGL((preprocess_bwd_kernel<DEG, true>), grid, dim3(bs), 0, s, sc, cams, V, opt,
+                       flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate);
 }
 
 void launch_preprocess_bwd(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt,
-                           const uint32_t *tiles, const float *accum, float *g_means,
-                           float *g_scales, float *g_rots, float *g_opac, float *g_sh,
-                           int accumulate, hipStream_t s) {
+                           const uint8_t *flags, const int4 *rect, const float *accum,
+                           float *g_means, float *g_scales, float *g_rots, float *g_opac,
+                           float *g_sh, int accumulate, hipStream_t s) {
   if (sc.n == 0) return;
-  const int bs = 128;
-  const int64_t nb = (sc.n + bs - 1) / bs;
-  hipLaunchKernelGGL(preprocess_bwd_kernel, dim3((unsigned)nb), dim3(bs), 0, s, sc, cams, V, opt,
-                     tiles, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate);
+  switch (sc.sh_degree) {
+    case 0: launch_bwd_deg<0>(sc, cams, V, opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate, s); break;
+    case 1: launch_bwd_deg<1>(sc, cams, V, opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate, s); break;
+    case 2: launch_bwd_deg<2>(sc, cams, V, opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate, s); break;
+    default: launch_bwd_deg<3>(sc, cams, V, opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate, s); break;
+  }
 }
 
 }  // namespace hgs

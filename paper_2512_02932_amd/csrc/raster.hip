@@ -1,24 +1,34 @@
 // Per-tile compositing (forward) and its reverse pass (backward), gfx950.
 //
-// One 256-thread block per 16x16 tile.  The block's four wave64s each own an
-// 8x8 quadrant.  The tile's depth-sorted splat list is staged through LDS in
-// batches of 256 records, with coalesced loads.  Every lane of a wave
-// evaluates the same splat at each step, so the 2D/3D branch is
-// wave-uniform.
+// Work unit: one wave64 per 8x8 quadrant of a 16x16 tile, one pixel per lane,
+// launched as its own workgroup so that waves never wait for each other.  The
+// four quadrant waves of a tile are given block ids that the dispatcher sends
+// to the same XCD, so the tile's pair list and records are fetched into one
+// L2.  A wave walks its tile's depth-sorted pair list in chunks of 64: each
+// lane loads one pair's 80-byte record (the next chunk is prefetched into
+// registers while the current one is composited), tests the record's pixel
+// rectangle against the quadrant, and the hits are compacted in list order
+// into the wave's LDS slots (ballot + mbcnt).  The serial loop then visits
+// only those records, broadcast from LDS; every lane evaluates the same
+// record at each step, so the 2D/3D branch is wave-uniform.  Skipping a
+// record whose rectangle misses the quadrant changes nothing: the rectangle
+// bounds the support where alpha~ >= 1/255.
 //
 // Forward (Sec. 3.1, Eq. 1-2): d_i is the Mahalanobis distance under the
 // projected covariance (3D) or u^2 + v^2 at the ray-splat intersection (2D).
 // The contribution is alpha~ = min(0.99, alpha_eff e^{-d/2}).  A pair is
 // skipped when alpha~ < 1/255 (false for NaN).  A pixel stops before the
-// pair that would take its transmittance below 1e-4.  A block-wide vote ends
-// a tile whose pixels are all done.
+// pair that would take its transmittance below 1e-4.  A wave stops when its
+// 64 pixels are done.
 //
 // Backward: each pixel walks its list in reverse from its last blended pair.
 // It recovers T_i = T_{i+1} / (1 - alpha~_i) and carries the suffix
 // S = alpha~ f + (1 - alpha~) S of the per-pair scalar
 // f = <G_rgb, c> + G_depth depth + <G_n, n>.  dL/dalpha~ = T_i (f - S).  The
-// 16 per-pair gradients are reduced across the wave and added with one
-// vector atomic per wave into per-(view, splat) accumulators.
+// 16 per-pair gradient terms are reduced over the wave in registers (a
+// transposed reduce-scatter on the cross-lane swap and DPP paths, no LDS) and
+// added with one 16-lane vector atomic per wave into the per-(view, splat)
+// accumulators.
 
 #include "hgs_internal.h"
 
@@ -27,6 +37,7 @@ namespace hgs {
 namespace {
 
 constexpr float kLn2 = 0.69314718055994531f;
+constexpr int kWave = 64;  // one wave64 per 8x8 quadrant of a tile; also the chunk length
 
 // Exponent (in units of log2 e) of a pair, fixed operation order so the
 // forward and backward kernels reach the same bits.
@@ -40,17 +51,17 @@ struct PairEval {
 
 __device__ __forceinline__ PairEval eval_pair(bool is3d, float fxp, float fyp, const float4 &r0,
                                               const float4 &r1, const float4 &r2,
-                                              const float4 &r3, const float4 &r4) {
+                                              const float4 &r3) {
 #pragma clang fp contract(off)
   PairEval p;
-  p.xr = fxp - r0.y;
-  p.yr = fyp - r0.z;
+  p.xr = fxp - r0.x;
+  p.yr = fyp - r0.y;
   if (is3d) {
     const float dx = p.xr - r1.x, dy = p.yr - r1.y;
     const float t = __builtin_fmaf(r1.w, dy, r1.z * dx);  // A dx + B dy
     const float u = r2.x * dy;                             // C dy
     p.e = __builtin_fmaf(dx, t, u * dy);
-    p.depth = r4.w;
+    p.depth = r2.y;
     p.a0 = dx;
     p.a1 = dy;
     p.rw = 1.0f;
@@ -71,73 +82,142 @@ __device__ __forceinline__ PairEval eval_pair(bool is3d, float fxp, float fyp, c
 
 __device__ __forceinline__ float exp2_neg(float e) { return __builtin_amdgcn_exp2f(-e); }
 
-__global__ void __launch_bounds__(kBlock)
+// The next batch's record of this lane, held in five registers while the
+// current batch is composited.
+#define HGS_FETCH(rec, id, q0, q1, q2, q3, q4) \
+  do {                                        \
+    const float4 *p_ = (rec)[id].r;           \
+    q0 = p_[0];                               \
+    q1 = p_[1];                               \
+    q2 = p_[2];                               \
+    q3 = p_[3];                               \
+    q4 = p_[4];                               \
+  } while (0)
+
+// A wave's quadrant: block id -> (tile, quadrant).  Blocks 32g + 8q + x hold
+// tile 8g + x, quadrant q, so the four quadrants of a tile share x = block id
+// mod 8, the XCD the dispatcher assigns them to.
+struct Quad {
+  int tile;
+  int v;           // view
+  int qx, qy;      // top-left pixel of the quadrant
+  int px, py;      // this lane's pixel
+  float fx, fy;    // pixel sample (x + 1/2, y + 1/2)
+  bool inside;
+};
+
+__device__ __forceinline__ Quad quad_of(int W, int H, int tiles_x, int tiles_per_view) {
+  Quad q;
+  const int b = blockIdx.x;
+  q.tile = (b >> 5) * 8 + (b & 7);
+  const int quad = (b >> 3) & 3;
+  q.v = q.tile / tiles_per_view;
+  const int r = q.tile - q.v * tiles_per_view;
+  const int ty = r / tiles_x;
+  const int tx = r - ty * tiles_x;
+  q.qx = tx * kTile + (quad & 1) * 8;
+  q.qy = ty * kTile + (quad >> 1) * 8;
+  const int lane = threadIdx.x;
+  q.px = q.qx + (lane & 7);
+  q.py = q.qy + (lane >> 3);
+  q.fx = (float)q.px + 0.5f;
+  q.fy = (float)q.py + 0.5f;
+  q.inside = q.px < W && q.py < H;
+  return q;
+}
+
+// Does the record's inclusive pixel rectangle (r0) meet the quadrant?
+__device__ __forceinline__ bool meets(const float4 &r0, const Quad &q) {
+  const float x0 = (float)q.qx, y0 = (float)q.qy;
+  return r0.x <= x0 + 7.0f && r0.z >= x0 && r0.y <= y0 + 7.0f && r0.w >= y0;
+}
+
+__device__ __forceinline__ int lane_rank(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ bool is3d_of(const float4 &r4) {
+  return (__builtin_amdgcn_readfirstlane(__float_as_int(r4.w)) >> 31) == 0;
+}
+
+__global__ void __launch_bounds__(kWave)
 raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
-                  const Record *__restrict__ rec, int W, int H, int tiles_x, int tiles_per_view,
-                  DevOpts opt, RasterOut out) {
-  __shared__ float4 srec[5][kBlock];
-  const int tile = blockIdx.x;
-  const int v = tile / tiles_per_view;
-  const int t = tile - v * tiles_per_view;
-  const int ty = t / tiles_x, tx = t - ty * tiles_x;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int px = tx * kTile + (w & 1) * 8 + (lane & 7);
-  const int py = ty * kTile + (w >> 1) * 8 + (lane >> 3);
-  const bool inside = px < W && py < H;
-  const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
-  const uint2 rg = ranges[tile];
+                  const Record *__restrict__ rec, int n_tiles, int W, int H, int tiles_x,
+                  int tiles_per_view, DevOpts opt, RasterOut out) {
+  __shared__ float4 srec[5][kWave];
+  __shared__ uint32_t spos[kWave];
+  const Quad q = quad_of(W, H, tiles_x, tiles_per_view);
+  if (q.tile >= n_tiles) return;
+  const int lane = threadIdx.x;
+  const uint2 rg = ranges[q.tile];
+  const int n = (int)(rg.y - rg.x);
 
-  float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, nx = 0.0f, ny = 0.0f, nz = 0.0f;
-  uint32_t n = 0, last = 0, wc = 0;
-  bool done = !inside;
+  // T > 0 while the pixel composites; a stopped pixel keeps -T (its final
+  // transmittance, negated), so one compare tells both.
+  float T = q.inside ? 1.0f : -1.0f;
+  float cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, nx = 0.0f, ny = 0.0f, nz = 0.0f;
+  uint32_t cnt = 0, last = 0, wc = 0;
 
-  for (int64_t b = rg.x; b < (int64_t)rg.y; b += kBlock) {
-    if (__syncthreads_and(done ? 1 : 0)) break;
-    const int64_t idx = b + tid;
-    if (idx < (int64_t)rg.y) {
-      const Record *r = rec + vals[idx];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) srec[k][tid] = r->r[k];
+  // pipeline: records of chunk c in q0..q4, list entry of chunk c + 64 in nid
+  float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0, q4 = q0;
+  uint32_t nid = 0;
+  if (lane < n) HGS_FETCH(rec, vals[rg.x + lane], q0, q1, q2, q3, q4);
+  if (kWave + lane < n) nid = vals[rg.x + kWave + lane];
+  for (int c = 0; c < n; c += kWave) {
+    if (__ballot(T > 0.0f) == 0ull) break;
+    const bool hit = (c + lane < n) && meets(q0, q);
+    const uint64_t m = __ballot(hit);
+    __syncthreads();  // the previous chunk's slots have been read
+    if (hit) {
+      const int slot = lane_rank(m);
+      srec[0][slot] = q0;
+      srec[1][slot] = q1;
+      srec[2][slot] = q2;
+      srec[3][slot] = q3;
+      srec[4][slot] = q4;
+      spos[slot] = (uint32_t)(c + lane);
     }
     __syncthreads();
-    const int cnt = (int)min((int64_t)kBlock, (int64_t)rg.y - b);
-    const uint32_t pos0 = (uint32_t)(b - rg.x);
-    for (int j = 0; j < cnt; ++j) {
-      if (__ballot(!done) == 0ull) break;
-      const float4 r0 = srec[0][j], r1 = srec[1][j], r2 = srec[2][j], r3 = srec[3][j],
-                   r4 = srec[4][j];
-      const bool is3d = __builtin_amdgcn_readfirstlane(__float_as_int(r0.x)) != 0;
-      const PairEval p = eval_pair(is3d, fxp, fyp, r0, r1, r2, r3, r4);
-      const float raw = r0.w * exp2_neg(p.e);
-      if (!done && raw >= kAlphaMin) {
-        const float a = fminf(raw, kAlphaMax);
-        const float Tn = T * (1.0f - a);
-        if (Tn < kTMin) {
-          done = true;
-          wc |= 0x80000000u | (is3d ? 0u : 0x40000000u);
-        } else {
-          const float wg = a * T;
-          cr = __builtin_fmaf(wg, r3.y, cr);
-          cg = __builtin_fmaf(wg, r3.z, cg);
-          cb = __builtin_fmaf(wg, r3.w, cb);
-          dep = __builtin_fmaf(wg, p.depth, dep);
-          nx = __builtin_fmaf(wg, r4.x, nx);
-          ny = __builtin_fmaf(wg, r4.y, ny);
-          nz = __builtin_fmaf(wg, r4.z, nz);
-          T = Tn;
-          ++n;
-          wc += is3d ? 1u : (1u << 15);
-          last = pos0 + (uint32_t)j + 1u;
-        }
+    if (c + kWave + lane < n) HGS_FETCH(rec, nid, q0, q1, q2, q3, q4);
+    if (c + 2 * kWave + lane < n) nid = vals[rg.x + c + 2 * kWave + lane];
+    const int k_end = __popcll(m);
+    for (int k = 0; k < k_end; ++k) {
+      if (__ballot(T > 0.0f) == 0ull) break;
+      const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
+                   r4 = srec[4][k];
+      const uint32_t pos = spos[k];
+      const bool is3d = is3d_of(r4);
+      const PairEval p = eval_pair(is3d, q.fx, q.fy, r0, r1, r2, r3);
+      const float raw = fabsf(r4.w) * exp2_neg(p.e);
+      const float a = fminf(raw, kAlphaMax);
+      const float Tn = T * (1.0f - a);
+      const bool act = T > 0.0f && raw >= kAlphaMin;
+      const bool blend = act && Tn >= kTMin;
+      const float wg = blend ? a * T : 0.0f;
+      if (blend) {
+        cr = __builtin_fmaf(wg, r3.y, cr);
+        cg = __builtin_fmaf(wg, r3.z, cg);
+        cb = __builtin_fmaf(wg, r3.w, cb);
+        dep = __builtin_fmaf(wg, p.depth, dep);
+        nx = __builtin_fmaf(wg, r4.x, nx);
+        ny = __builtin_fmaf(wg, r4.y, ny);
+        nz = __builtin_fmaf(wg, r4.z, nz);
+        ++cnt;
+        wc += is3d ? 1u : (1u << 15);
+        last = pos + 1u;
       }
+      // blend: T <- Tn; stop (act, not blend): T <- -T
+      T = blend ? Tn : ((act && !blend) ? -T : T);
+      wc |= (act && !blend) ? (0x80000000u | (is3d ? 0u : 0x40000000u)) : 0u;
     }
-    __syncthreads();
   }
-  if (!inside) return;
+  T = fabsf(T);
+  if (!q.inside) return;
   const int64_t hw = (int64_t)H * W;
-  const int64_t pix = (int64_t)py * W + px;
-  const int64_t o1 = (int64_t)v * hw + pix;
-  const int64_t o3 = (int64_t)v * 3 * hw + pix;
+  const int64_t pix = (int64_t)q.py * W + q.px;
+  const int64_t o1 = (int64_t)q.v * hw + pix;
+  const int64_t o3 = (int64_t)q.v * 3 * hw + pix;
   if (out.rgb) {
     out.rgb[o3] = cr + T * opt.bg[0];
     out.rgb[o3 + hw] = cg + T * opt.bg[1];
@@ -152,70 +232,83 @@ raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   }
   if (out.T_final) out.T_final[o1] = T;
   if (out.last) out.last[o1] = last;
-  if (out.n_contrib) out.n_contrib[o1] = n;
+  if (out.n_contrib) out.n_contrib[o1] = cnt;
   if (out.wcount) out.wcount[o1] = wc;
 }
 
-// Reduce 16 per-lane values over the wave so that lane L ends with the
-// total of value ((L>>5)&1)*8 + ((L>>4)&1)*4 + ((L>>3)&1)*2 + ((L>>2)&1):
-// a transposed reduce-scatter (halve the value set at each xor step).
-__device__ __forceinline__ float wave_reduce_scatter16(float (&g)[16], int lane) {
-  const bool b5 = lane & 32;
+// Cross-lane helpers of the reduce-scatter.  swap32(a, b): lanes 0-31 get
+// (a, a of lane + 32), lanes 32-63 get (b of lane - 32, b); swap16 does the
+// same between the even and odd 16-lane rows.  The sum of the pair is then
+// the two-lane sum of a (lower half / even rows) or of b (upper / odd).
+__device__ __forceinline__ float swap32_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// x of the DPP partner lane: row_mirror pairs lane i with i ^ 15 inside a
+// 16-lane row, row_half_mirror i with i ^ 7 inside 8 lanes, quad_perm
+// [1,0,3,2] i with i ^ 1 and [2,3,0,1] i with i ^ 2.
+template <int kCtrl>
+__device__ __forceinline__ float dpp(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
+                                                               kCtrl, 0xf, 0xf, false));
+}
+constexpr int kRowMirror = 0x140, kRowHalfMirror = 0x141, kQuadXor1 = 0xB1, kQuadXor2 = 0x4E;
+
+// Sums each of the 16 per-lane values over the wave.  Lane l returns the
+// total of value 8 b5 + 4 b4 + 2 b3 + b2 (b_i = bit i of l); the four lanes
+// that differ only in bits 0-1 hold the same total.  Pairings used: bit 5
+// (swap32), bit 4 (swap16), l ^ 15, l ^ 7, l ^ 1, l ^ 2 -- together they span
+// all 64 lanes.
+__device__ __forceinline__ float wave_reduce_scatter16(const float (&g)[16], int lane) {
+  float s[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const float send = b5 ? g[k] : g[k + 8];
-    const float keep = b5 ? g[k + 8] : g[k];
-    g[k] = keep + __shfl_xor(send, 32);
-  }
-  const bool b4 = lane & 16;
+  for (int k = 0; k < 8; ++k) s[k] = swap32_sum(g[k], g[k + 8]);
+  float t[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const float send = b4 ? g[k] : g[k + 4];
-    const float keep = b4 ? g[k + 4] : g[k];
-    g[k] = keep + __shfl_xor(send, 16);
-  }
+  for (int k = 0; k < 4; ++k) t[k] = swap16_sum(s[k], s[k + 4]);
   const bool b3 = lane & 8;
+  float u[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const float send = b3 ? g[k] : g[k + 2];
-    const float keep = b3 ? g[k + 2] : g[k];
-    g[k] = keep + __shfl_xor(send, 8);
+    const float keep = b3 ? t[k + 2] : t[k];
+    const float send = b3 ? t[k] : t[k + 2];
+    u[k] = keep + dpp<kRowMirror>(send);
   }
   const bool b2 = lane & 4;
-  float x = (b2 ? g[1] : g[0]) + __shfl_xor(b2 ? g[0] : g[1], 4);
-  x += __shfl_xor(x, 2);
-  x += __shfl_xor(x, 1);
+  float x = (b2 ? u[1] : u[0]) + dpp<kRowHalfMirror>(b2 ? u[0] : u[1]);
+  x += dpp<kQuadXor1>(x);
+  x += dpp<kQuadXor2>(x);
   return x;
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kWave)
 raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
-                  const Record *__restrict__ rec, int W, int H, int tiles_x, int tiles_per_view,
-                  DevOpts opt, const float *__restrict__ T_final,
+                  const Record *__restrict__ rec, int n_tiles, int W, int H, int tiles_x,
+                  int tiles_per_view, DevOpts opt, const float *__restrict__ T_final,
                   const uint32_t *__restrict__ last_in, RasterGradIn gin,
                   float *__restrict__ accum) {
-  __shared__ float4 srec[5][kBlock];
-  __shared__ uint32_t sidx[kBlock];
-  __shared__ uint32_t smax[4];
-  const int tile = blockIdx.x;
-  const int v = tile / tiles_per_view;
-  const int t = tile - v * tiles_per_view;
-  const int ty = t / tiles_x, tx = t - ty * tiles_x;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int px = tx * kTile + (w & 1) * 8 + (lane & 7);
-  const int py = ty * kTile + (w >> 1) * 8 + (lane >> 3);
-  const bool inside = px < W && py < H;
-  const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
-  const uint2 rg = ranges[tile];
+  __shared__ float4 srec[5][kWave];
+  __shared__ uint32_t sid[kWave];
+  __shared__ uint32_t spos[kWave];
+  const Quad q = quad_of(W, H, tiles_x, tiles_per_view);
+  if (q.tile >= n_tiles) return;
+  const int lane = threadIdx.x;
+  const uint2 rg = ranges[q.tile];
 
   float T = 1.0f;
   uint32_t L = 0;
   float Gr = 0, Gg = 0, Gb = 0, Ga = 0, Gd = 0, Gnx = 0, Gny = 0, Gnz = 0;
-  if (inside) {
+  if (q.inside) {
     const int64_t hw = (int64_t)H * W;
-    const int64_t pix = (int64_t)py * W + px;
-    const int64_t o1 = (int64_t)v * hw + pix;
-    const int64_t o3 = (int64_t)v * 3 * hw + pix;
+    const int64_t pix = (int64_t)q.py * W + q.px;
+    const int64_t o1 = (int64_t)q.v * hw + pix;
+    const int64_t o3 = (int64_t)q.v * 3 * hw + pix;
     T = T_final[o1];
     L = last_in[o1];
     if (gin.rgb) {
@@ -237,38 +330,55 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   uint32_t wmax = L;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, d));
-  if (lane == 0) smax[w] = wmax;
-  __syncthreads();
-  const uint32_t bmax = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
-  const int qsel = lane >> 2;
+  const int n = min((int)__builtin_amdgcn_readfirstlane(wmax), (int)(rg.y - rg.x));
+  if (n <= 0) return;
   const int vidx = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
                    ((lane >> 2) & 1);
 
-  for (int end = (int)bmax; end > 0; end -= kBlock) {
-    const int start = end > kBlock ? end - kBlock : 0;
-    __syncthreads();
-    if (start + tid < end) {
-      const uint32_t id = vals[rg.x + start + tid];
-      sidx[tid] = id;
-      const Record *r = rec + id;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) srec[k][tid] = r->r[k];
+  // chunks of 64 list positions in reverse; the first is the ragged one.
+  // Pipeline: records of chunk c in q0..q4 (entry id), entry of chunk c - 64
+  // in nid.
+  float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0, q4 = q0;
+  uint32_t id = 0, nid = 0;
+  int c = (n - 1) & ~(kWave - 1);
+  if (c + lane < n) {
+    id = vals[rg.x + c + lane];
+    HGS_FETCH(rec, id, q0, q1, q2, q3, q4);
+  }
+  if (c > 0) nid = vals[rg.x + c - kWave + lane];
+  for (; c >= 0; c -= kWave) {
+    const bool hit = (c + lane < n) && meets(q0, q);
+    const uint64_t m = __ballot(hit);
+    __syncthreads();  // the previous chunk's slots have been read
+    if (hit) {
+      const int slot = lane_rank(m);
+      srec[0][slot] = q0;
+      srec[1][slot] = q1;
+      srec[2][slot] = q2;
+      srec[3][slot] = q3;
+      srec[4][slot] = q4;
+      sid[slot] = id;
+      spos[slot] = (uint32_t)(c + lane);
     }
     __syncthreads();
-    for (int j = end - 1; j >= start; --j) {
-      if ((uint32_t)j >= wmax) continue;
-      const int slot = j - start;
-      const float4 r0 = srec[0][slot], r1 = srec[1][slot], r2 = srec[2][slot],
-                   r3 = srec[3][slot], r4 = srec[4][slot];
-      const bool is3d = __builtin_amdgcn_readfirstlane(__float_as_int(r0.x)) != 0;
-      const PairEval p = eval_pair(is3d, fxp, fyp, r0, r1, r2, r3, r4);
+    if (c > 0) {  // earlier chunks: every position is below n
+      id = nid;
+      HGS_FETCH(rec, id, q0, q1, q2, q3, q4);
+      if (c > kWave) nid = vals[rg.x + c - 2 * kWave + lane];
+    }
+    for (int k = __popcll(m) - 1; k >= 0; --k) {
+      const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
+                   r4 = srec[4][k];
+      const uint32_t pos = spos[k];
+      const bool is3d = is3d_of(r4);
+      const PairEval p = eval_pair(is3d, q.fx, q.fy, r0, r1, r2, r3);
       const float G = exp2_neg(p.e);
-      const float raw = r0.w * G;
-      const bool act = ((uint32_t)j < L) && (raw >= kAlphaMin);
+      const float raw = fabsf(r4.w) * G;
+      const bool act = (pos < L) && (raw >= kAlphaMin);
       if (__ballot(act) == 0ull) continue;
       float g[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) g[k] = 0.0f;
+      for (int j = 0; j < 16; ++j) g[j] = 0.0f;
       if (act) {
         const float a = fminf(raw, kAlphaMax);
         const bool clamped = raw > kAlphaMax;
@@ -315,11 +425,13 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
       }
       const float tot = wave_reduce_scatter16(g, lane);
       if ((lane & 3) == 0 && tot != 0.0f)
-        unsafeAtomicAdd(accum + (size_t)sidx[slot] * kGradSlots + vidx, tot);
-      (void)qsel;
+        unsafeAtomicAdd(accum + (size_t)sid[k] * kGradSlots + vidx, tot);
     }
   }
 }
+
+// Blocks: 32 per group of 8 tiles (four quadrants each), see quad_of.
+unsigned quad_blocks(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 32u; }
 
 }  // namespace
 
@@ -329,8 +441,8 @@ void launch_raster_fwd(const uint2 *ranges, const uint32_t *vals, const Record *
   (void)cams;
   (void)V;
   if (n_tiles_total == 0) return;
-  hipLaunchKernelGGL(raster_fwd_kernel, dim3((unsigned)n_tiles_total), dim3(kBlock), 0, s, ranges,
-                     vals, rec, W, H, tiles_x, tiles_per_view, opt, out);
+  hipLaunchKernelGGL(raster_fwd_kernel, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
+                     ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt, out);
 }
 
 void launch_raster_bwd(const uint2 *ranges, const uint32_t *vals, const Record *rec,
@@ -338,8 +450,9 @@ void launch_raster_bwd(const uint2 *ranges, const uint32_t *vals, const Record *
                        DevOpts opt, const float *T_final, const uint32_t *last, RasterGradIn g,
                        float *accum, hipStream_t s) {
   if (n_tiles_total == 0) return;
-  hipLaunchKernelGGL(raster_bwd_kernel, dim3((unsigned)n_tiles_total), dim3(kBlock), 0, s, ranges,
-                     vals, rec, W, H, tiles_x, tiles_per_view, opt, T_final, last, g, accum);
+  hipLaunchKernelGGL(raster_bwd_kernel, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
+                     ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
+                     T_final, last, g, accum);
 }
 
 }  // namespace hgs
