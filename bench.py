@@ -77,6 +77,109 @@ def cpu_baseline(scene_np, cam, G_np, rows: int):
                       f"binary64, {cores} threads, {dt:.1f} s"}
 
 
+def _pool_get(pool, srv_or_rast, H, W):
+    free = pool.setdefault((H, W), [])
+    if free:
+        return free.pop()
+    return srv_or_rast.alloc_images(1, H, W) if hasattr(srv_or_rast, "ctx") else \
+        srv_or_rast.alloc_images(H, W)
+
+
+def serving(rast, n_warm=200, n_meas=2000, rate=200.0, check=20):
+    """Served-view latency on four resident scenes with Poisson arrivals.
+    The same request trace is replayed (a) through the batched server (one
+    graph-captured pass per batch, batches in flight on several streams) and
+    (b) as one plain render launch per request.  Latency = completion -
+    arrival, over the measured requests."""
+    import numpy as np
+    import torch
+    import scenegen as sg
+    from paper_2512_02932_amd.rasterizer import to_device
+    from paper_2512_02932_amd.serving import Server
+
+    log("[serving] generating 4 resident scenes")
+    scenes = sg.serving_scenes()
+    sids = [rast.scene_init(to_device(sc), copy_resident=True) for sc in scenes]
+    n_gauss = [int(sc["means"].shape[0]) for sc in scenes]
+    del scenes
+    reqs = sg.serving_requests(n_warm + n_meas, rate=rate, seed=45)
+    px = np.array([r["camera"]["width"] * r["camera"]["height"] for r in reqs], np.float64)
+    torch.cuda.synchronize()
+    check_ids = set(range(n_warm, n_warm + n_meas, max(1, n_meas // check)))
+
+    def run(batched):
+        pool, kept = {}, {}
+        lat = np.zeros(len(reqs))
+        out_imgs = {}
+        srv = None
+        if batched:
+            srv = Server(rast, max_requests=8, max_batches=3, max_instances=12_000_000,
+                         max_pairs=96_000_000, max_tiles=8 * 8160, use_graph=True)
+        stream = torch.cuda.current_stream()
+        t0 = time.perf_counter()
+        i = done = 0
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i]["t"] <= now:
+                cam = reqs[i]["camera"]
+                im = _pool_get(pool, srv if batched else rast, cam["height"], cam["width"])
+                if batched:
+                    srv.submit(sids[reqs[i]["scene"]], cam, im, i)
+                    kept[i] = im
+                else:
+                    rast.render_scene(sids[reqs[i]["scene"]], cam, images=im)
+                    stream.synchronize()
+                    lat[i] = time.perf_counter() - t0 - reqs[i]["t"]
+                    if i in check_ids:
+                        out_imgs[i] = im["rgb"].clone()
+                    pool[(cam["height"], cam["width"])].append(im)
+                    done += 1
+                i += 1
+            if batched:
+                for tag in srv.poll():
+                    lat[tag] = time.perf_counter() - t0 - reqs[tag]["t"]
+                    im = kept.pop(tag)
+                    if tag in check_ids:
+                        out_imgs[tag] = im["rgb"].clone()
+                    cam = reqs[tag]["camera"]
+                    pool[(cam["height"], cam["width"])].append(im)
+                    done += 1
+            elif i < len(reqs):
+                wait = reqs[i]["t"] - (time.perf_counter() - t0)
+                if wait > 2e-4:
+                    time.sleep(wait - 1e-4)
+        t_end = time.perf_counter() - t0
+        st = srv.stats() if batched else None
+        if srv is not None:
+            srv.close()
+        m = lat[n_warm:]
+        span = t_end - reqs[n_warm]["t"]
+        res = {"p50_ms": round(float(np.percentile(m, 50)) * 1e3, 3),
+               "p99_ms": round(float(np.percentile(m, 99)) * 1e3, 3),
+               "mean_ms": round(float(m.mean()) * 1e3, 3),
+               "req_per_s": round(n_meas / span, 1),
+               "mpix_per_s": round(float(px[n_warm:].sum()) / span / 1e6, 1)}
+        if st is not None:
+            res["batches"] = st["batches"]
+            res["rerendered"] = st["rerendered"]
+        return res, out_imgs
+
+    log("[serving] batched graph server")
+    b, b_imgs = run(True)
+    log(f"[serving] batched {b}")
+    log("[serving] one launch per request")
+    p, p_imgs = run(False)
+    log(f"[serving] per-request {p}")
+    diff = max(float((b_imgs[k] - p_imgs[k]).abs().max()) for k in b_imgs)
+    for sid in sids:
+        rast.scene_release(sid)
+    return {"workload": f"4 resident scenes ({'/'.join(str(n) for n in n_gauss)} Gaussians, SH3), "
+                        f"Poisson {rate:g} req/s, {n_warm} warm-up + {n_meas} measured, "
+                        "resolutions 256^2/512^2/1280x720/1920x1080, orbit r in [3,5]",
+            "batched_graph": b, "one_launch_per_request": p,
+            "max_abs_diff_batched_vs_plain": diff}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +188,8 @@ def main():
     ap.add_argument("--workload", default="knot1m_1080p", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the served-view latency measurement")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(reference dispatch for scaling HBM traffic counters)")
@@ -191,6 +296,10 @@ def main():
                    "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}},
         "roofline": roof,
     }
+    if not args.no_serving:
+        del sc, grads, images, G
+        torch.cuda.empty_cache()
+        out["serving"] = serving(rast)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline on {args.cpu_rows} rows")
         out["cpu_baseline"] = cpu_baseline(scene_np, cam, G_np, args.cpu_rows)

@@ -133,9 +133,11 @@ hgs_status hgs_scene_release(hgs_ctx *ctx, int32_t scene_id);
 
 /* Forward render of scene `scene_id` into V = n_views views that share one
  * image size (Sec. 3.1, Eq. 1-2).  The pipeline is: preprocess (cull,
- * project, SH -> RGB, screen rectangle), exclusive scan, duplicate with
- * (tile, depth) keys, LSD radix sort, tile ranges, per-16x16-tile
- * compositing.
+ * project, SH -> RGB, screen rectangle), stable radix sort of the splat
+ * instances by depth, exclusive scan of their tile counts in that order,
+ * duplicate into (tile, instance) pairs, stable radix sort of the pairs by
+ * tile, tile ranges, per-16x16-tile compositing.  The pairs end in
+ * (tile, depth, instance id) order.
  *
  * `cams` [host] has n_views entries.  If `state` is not NULL, the call
  * returns in *state a library-owned handle.  The handle keeps what the
@@ -166,7 +168,8 @@ hgs_status hgs_state_sizes(hgs_ctx *ctx, hgs_state *state, int64_t *sizes5 /* [h
 
 /* Copy one internal array of a state to host memory, for parity tests.
  * `what`:
- *   0 sorted keys   u64[D]
+ *   0 sorted keys   u64[D]  ((global tile << 32) | depth key of the pair's
+ *                            instance; composed on the host)
  *   1 sorted values u32[D]  (value = view * N + splat)
  *   2 tile ranges   u32[T,2]
  *   3 pixel rectangles of every (view, splat), i32[V*N,4]
@@ -202,10 +205,76 @@ enum {
   HGS_STAGE_RASTER_BWD = 6,
   HGS_STAGE_PREPROCESS_BWD = 7,
   HGS_STAGE_FILL = 8,
-  HGS_N_STAGES = 9
+  HGS_STAGE_DEPTH_SORT = 9,
+  HGS_N_STAGES = 10
 };
 hgs_status hgs_profile_enable(hgs_ctx *ctx, int32_t on);
 hgs_status hgs_profile_read(hgs_ctx *ctx, double *ms, int64_t *calls, int32_t reset);
+
+/* ---------------------------------------------------------------------
+ * Batched serving.
+ *
+ * A server renders forward-only requests against resident scenes (scenes
+ * created with hgs_scene_init; copy_resident = 1 keeps them valid whatever
+ * the caller does with its own buffers).  Each request is one camera of
+ * any image size.  Pending requests are admitted into "lanes" (batches in
+ * flight) as a lane frees up, within the lane's slot count and memory
+ * capacities.  A lane renders all its requests in one pipeline pass:
+ * instance ids and tile ids of all requests share one key space (per-request
+ * instance and tile offsets), and one persistent raster grid pulls
+ * (tile, quadrant) units from an atomic queue.  The pass reads its batch from
+ * a device-side slot table and keeps every count on the device (capacity-
+ * bounded, no host synchronisation), so with use_graph = 1 it is captured
+ * once per lane as a hipGraph and replayed for every batch.  Lanes run on
+ * their own streams (default priority), so the batches in flight overlap on
+ * the device.  A request's images are the same as hgs_render's for the same
+ * scene, camera and opts (each pixel's pair list is the same list in the
+ * same order).
+ *
+ * If a batch produces more (tile, splat) pairs than max_pairs, its requests
+ * are rendered again one by one with hgs_render on the lane's stream before
+ * they complete (counted in the stats); results are unaffected.
+ * ------------------------------------------------------------------- */
+typedef struct hgs_server hgs_server;
+
+typedef struct {
+  int32_t max_requests;  /* requests per batch (slot table size), >= 1 */
+  int32_t max_batches;   /* lanes: batches in flight, >= 1 */
+  int64_t max_instances; /* sum of the scene sizes of one batch, >= 1 */
+  int64_t max_pairs;     /* (tile, splat) pairs of one batch, >= 1, < 2^32 */
+  int64_t max_tiles;     /* 16x16 tiles of one batch, >= 1, < 2^31 */
+  int32_t use_graph;     /* 1: capture each lane's pass once as a hipGraph */
+} hgs_server_config;
+
+typedef struct {
+  int32_t scene_id;
+  hgs_camera camera;     /* [host] copied at submit */
+  hgs_images out;        /* device, [1,3,H,W] / [1,1,H,W]; NULL channels are
+                            not written; must stay valid until completion */
+  uint64_t tag;          /* returned by hgs_server_poll on completion */
+} hgs_request;
+
+/* Creates a server on ctx's device.  All lane buffers are allocated here
+ * (nothing is allocated per batch).  `opts` [host] may be NULL.  Errors:
+ * EINVAL on a bad config, ENOMEM, EHIP. */
+hgs_status hgs_server_create(hgs_ctx *ctx, const hgs_server_config *cfg, const hgs_opts *opts,
+                             hgs_server **out);
+/* Waits for the batches in flight, then frees the server. */
+void hgs_server_destroy(hgs_server *server);
+/* Queues a request (host only; nothing is launched).  EINVAL for a bad
+ * scene id or camera, ECAPACITY for a request that exceeds one batch's
+ * capacities on its own. */
+hgs_status hgs_server_submit(hgs_server *server, const hgs_request *req /* [host] */);
+/* Makes progress without blocking: retires the lanes whose batch has
+ * finished (their tags go to done_tags [host], up to `capacity`; the rest
+ * are returned by later calls), then admits pending requests in arrival
+ * order into free lanes and launches them.  *n_done = tags written. */
+hgs_status hgs_server_poll(hgs_server *server, uint64_t *done_tags /* [host] */,
+                           int32_t capacity, int32_t *n_done /* [host] */);
+/* Counters [host]: [0] batches launched, [1] requests completed,
+ * [2] requests re-rendered after a pair overflow, [3] requests pending,
+ * [4] lanes busy, [5] largest pair count seen in a batch. */
+hgs_status hgs_server_stats(hgs_server *server, int64_t *stats6 /* [host] */);
 
 /* Message of the last error on this host thread ("" if none). */
 const char *hgs_last_error(void);

@@ -16,10 +16,12 @@ HGS_OK, HGS_EINVAL, HGS_ENOMEM, HGS_EHIP, HGS_ECAPACITY, HGS_ESTATE = 0, -1, -2,
 
 EXPORTS = ("hgs_create", "hgs_destroy", "hgs_scene_init", "hgs_scene_release", "hgs_render",
            "hgs_render_backward", "hgs_state_free", "hgs_state_sizes", "hgs_state_debug",
-           "hgs_state_check", "hgs_last_error", "hgs_profile_enable", "hgs_profile_read")
+           "hgs_state_check", "hgs_last_error", "hgs_profile_enable", "hgs_profile_read",
+           "hgs_server_create", "hgs_server_destroy", "hgs_server_submit", "hgs_server_poll",
+           "hgs_server_stats")
 
 STAGES = ("preprocess", "scan", "duplicate", "sort", "ranges", "raster_fwd", "raster_bwd",
-          "preprocess_bwd", "fill")
+          "preprocess_bwd", "fill", "depth_sort")
 
 
 class hgs_scene_desc(C.Structure):
@@ -52,6 +54,17 @@ class hgs_grad_images(C.Structure):
 class hgs_grads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("rotations", C.c_void_p),
                 ("opacities", C.c_void_p), ("sh", C.c_void_p), ("accumulate", C.c_int32)]
+
+
+class hgs_server_config(C.Structure):
+    _fields_ = [("max_requests", C.c_int32), ("max_batches", C.c_int32),
+                ("max_instances", C.c_int64), ("max_pairs", C.c_int64),
+                ("max_tiles", C.c_int64), ("use_graph", C.c_int32)]
+
+
+class hgs_request(C.Structure):
+    _fields_ = [("scene_id", C.c_int32), ("camera", hgs_camera), ("out", hgs_images),
+                ("tag", C.c_uint64)]
 
 
 class HGSError(RuntimeError):
@@ -95,9 +108,17 @@ def load(path: str | None = None):
     lib.hgs_profile_read.argtypes = [P, P, P, C.c_int32]
     lib.hgs_last_error.argtypes = []
     lib.hgs_last_error.restype = C.c_char_p
+    lib.hgs_server_create.argtypes = [P, C.POINTER(hgs_server_config), C.POINTER(hgs_opts),
+                                      C.POINTER(P)]
+    lib.hgs_server_destroy.argtypes = [P]
+    lib.hgs_server_destroy.restype = None
+    lib.hgs_server_submit.argtypes = [P, C.POINTER(hgs_request)]
+    lib.hgs_server_poll.argtypes = [P, C.POINTER(C.c_uint64), C.c_int32, C.POINTER(C.c_int32)]
+    lib.hgs_server_stats.argtypes = [P, C.POINTER(C.c_int64)]
     for name in ("hgs_create", "hgs_scene_init", "hgs_scene_release", "hgs_render",
                  "hgs_render_backward", "hgs_state_sizes", "hgs_state_debug", "hgs_state_check",
-                 "hgs_profile_enable", "hgs_profile_read"):
+                 "hgs_profile_enable", "hgs_profile_read", "hgs_server_create",
+                 "hgs_server_submit", "hgs_server_poll", "hgs_server_stats"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -173,3 +194,33 @@ def hgs_profile_read(ctx, reset: bool = False):
     calls = (C.c_int64 * len(STAGES))()
     check(load().hgs_profile_read(ctx, ms, calls, 1 if reset else 0))
     return {name: (ms[i], calls[i]) for i, name in enumerate(STAGES)}
+
+
+def hgs_server_create(ctx, cfg: hgs_server_config, opts=None):
+    srv = C.c_void_p()
+    check(load().hgs_server_create(ctx, C.byref(cfg), C.byref(opts) if opts is not None else None,
+                                   C.byref(srv)))
+    return srv
+
+
+def hgs_server_destroy(srv):
+    load().hgs_server_destroy(srv)
+
+
+def hgs_server_submit(srv, req: hgs_request):
+    check(load().hgs_server_submit(srv, C.byref(req)))
+
+
+def hgs_server_poll(srv, capacity: int = 256):
+    """Returns the list of completed tags."""
+    tags = (C.c_uint64 * max(capacity, 1))()
+    n = C.c_int32()
+    check(load().hgs_server_poll(srv, tags, int(capacity), C.byref(n)))
+    return [int(tags[i]) for i in range(n.value)]
+
+
+def hgs_server_stats(srv):
+    """(batches, completed, rerendered, pending, lanes_busy, max_pairs)."""
+    st = (C.c_int64 * 6)()
+    check(load().hgs_server_stats(srv, st))
+    return tuple(int(x) for x in st)

@@ -10,51 +10,22 @@
 #include <string>
 #include <vector>
 
-#include "hgs.h"
-#include "hgs_internal.h"
+#include "ctx_internal.h"
 
 using namespace hgs;
 
-namespace {
+namespace hgs {
 
+namespace {
 thread_local std::string g_err;
+}  // namespace
 
 hgs_status fail(hgs_status st, const std::string &msg) {
   g_err = msg;
   return st;
 }
 
-#define HGS_HIP(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(e_ == hipErrorOutOfMemory ? HGS_ENOMEM : HGS_EHIP,                    \
-                  std::string(#expr) + ": " + hipGetErrorString(e_));                   \
-  } while (0)
-
-struct Scene {
-  bool used = false;
-  bool resident = false;
-  SceneDev dev{};
-  void *buf = nullptr;
-};
-
-}  // namespace
-
-struct StageEvent {
-  int stage;
-  hipEvent_t a, b;
-};
-
-struct hgs_ctx {
-  int device = 0;
-  std::vector<Scene> scenes;
-  bool profile = false;
-  std::vector<StageEvent> pending;
-  std::vector<hipEvent_t> event_pool;
-  double stage_ms[HGS_N_STAGES] = {0};
-  int64_t stage_calls[HGS_N_STAGES] = {0};
-};
+}  // namespace hgs
 
 struct hgs_state {
   hipStream_t stream = nullptr;
@@ -71,8 +42,8 @@ struct hgs_state {
   int4 *rect = nullptr;
   uint8_t *flags = nullptr;
   uint64_t *total = nullptr;
-  uint64_t *keys = nullptr;
-  uint32_t *vals = nullptr;
+  uint32_t *keys = nullptr;  // tile id of each sorted pair
+  uint32_t *vals = nullptr;  // instance id (view * N + splat) of each sorted pair
   uint2 *ranges = nullptr;
   float *T_final = nullptr;
   uint32_t *last = nullptr, *n_contrib = nullptr, *wcount = nullptr;
@@ -130,6 +101,10 @@ void release(hgs_state *st) {
   for (void *p : st->allocs) (void)hipFreeAsync(p, st->stream);
   st->allocs.clear();
 }
+
+}  // namespace
+
+namespace hgs {
 
 DevOpts to_dev_opts(const hgs_opts *o) {
   DevOpts d{};
@@ -220,7 +195,7 @@ hgs_status check_desc(const hgs_scene_desc *d) {
   return HGS_OK;
 }
 
-}  // namespace
+}  // namespace hgs
 
 extern "C" {
 
@@ -417,15 +392,32 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc_t(st, &st->last, (size_t)P));
   ST_HIP(dalloc_t(st, &st->n_contrib, (size_t)P));
   ST_HIP(dalloc_t(st, &st->wcount, (size_t)P));
+  // instance depth order: za/oa, zb/ob ping-pong; counts in depth order in cnt
+  uint32_t *za = nullptr, *oa = nullptr, *zb = nullptr, *ob = nullptr, *cnt = nullptr;
+  void *dsort_tmp = nullptr;
+  ST_HIP(dalloc_t(st, &za, (size_t)VN));
+  ST_HIP(dalloc_t(st, &oa, (size_t)VN));
+  ST_HIP(dalloc_t(st, &zb, (size_t)VN));
+  ST_HIP(dalloc_t(st, &ob, (size_t)VN));
+  ST_HIP(dalloc_t(st, &cnt, (size_t)VN));
+  ST_HIP(dalloc(st, &dsort_tmp, sort_tmp_bytes(VN)));
 
   {
     StageTimer t(ctx, HGS_STAGE_PREPROCESS, st->stream);
     launch_preprocess(st->scene, st->cams, n_views, st->opt, st->rec, st->tiles, st->zbits,
                       st->rect, st->flags, st->stream);
   }
+  const uint32_t *order = nullptr;
+  {
+    StageTimer t(ctx, HGS_STAGE_DEPTH_SORT, st->stream);
+    const int w = launch_radix_sort(st->zbits, nullptr, za, oa, zb, ob, VN, 32, dsort_tmp,
+                                    st->stream);
+    order = w ? ob : oa;
+  }
   {
     StageTimer t(ctx, HGS_STAGE_SCAN, st->stream);
-    launch_scan(st->tiles, st->offsets, VN, st->total, scan_tmp, st->stream);
+    launch_gather(st->tiles, order, VN, cnt, st->stream);
+    launch_scan(cnt, st->offsets, VN, st->total, scan_tmp, st->stream);
   }
   uint64_t Dh = 0;
   ST_HIP(hipMemcpyAsync(&Dh, st->total, sizeof(uint64_t), hipMemcpyDeviceToHost, st->stream));
@@ -434,30 +426,26 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   if (Dh > 0xffffffffull) return bail(fail(HGS_ECAPACITY, "more than 2^32-1 (tile, splat) pairs"));
   st->D = (int64_t)Dh;
 
-  uint64_t *kb = nullptr;
-  uint32_t *vb = nullptr;
+  uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
   void *sort_tmp = nullptr;
-  ST_HIP(dalloc_t(st, &st->keys, (size_t)st->D));
-  ST_HIP(dalloc_t(st, &st->vals, (size_t)st->D));
+  ST_HIP(dalloc_t(st, &ka, (size_t)st->D));
+  ST_HIP(dalloc_t(st, &va, (size_t)st->D));
   ST_HIP(dalloc_t(st, &kb, (size_t)st->D));
   ST_HIP(dalloc_t(st, &vb, (size_t)st->D));
   ST_HIP(dalloc(st, &sort_tmp, sort_tmp_bytes(st->D)));
   {
     StageTimer t(ctx, HGS_STAGE_DUPLICATE, st->stream);
-    launch_duplicate(st->offsets, st->tiles, st->rect, st->zbits, st->cams, n_views, st->N,
-                     st->keys, st->vals, st->stream);
+    launch_duplicate(order, st->offsets, st->tiles, st->rect, st->cams, n_views, st->N, kb, vb,
+                     st->stream);
   }
   int tile_bits = 0;
   while ((int64_t(1) << tile_bits) < n_tiles) ++tile_bits;
-  int which = 0;
   {
     StageTimer t(ctx, HGS_STAGE_SORT, st->stream);
-    which = launch_radix_sort(st->keys, st->vals, kb, vb, st->D, 32 + tile_bits, sort_tmp,
-                              st->stream);
-  }
-  if (which) {
-    std::swap(st->keys, kb);
-    std::swap(st->vals, vb);
+    const int w = launch_radix_sort(kb, vb, ka, va, kb, vb, st->D, tile_bits, sort_tmp,
+                                    st->stream);
+    st->keys = w ? kb : ka;
+    st->vals = w ? vb : va;
   }
   {
     StageTimer t(ctx, HGS_STAGE_RANGES, st->stream);
@@ -599,7 +587,19 @@ hgs_status hgs_state_debug(hgs_ctx *ctx, hgs_state *st, int32_t what, void *dst,
   const void *src = nullptr;
   int64_t bytes = 0;
   switch (what) {
-    case 0: src = st->keys; bytes = st->D * 8; break;
+    case 0: {  // 64-bit keys (tile << 32 | depth bits), composed on the host
+      if (st->D * 8 > cap) return fail(HGS_EINVAL, "destination too small");
+      HGS_HIP(hipStreamSynchronize(st->stream));
+      std::vector<uint32_t> t((size_t)st->D), v((size_t)st->D), z((size_t)VN);
+      if (st->D > 0) {
+        HGS_HIP(hipMemcpy(t.data(), st->keys, (size_t)st->D * 4, hipMemcpyDeviceToHost));
+        HGS_HIP(hipMemcpy(v.data(), st->vals, (size_t)st->D * 4, hipMemcpyDeviceToHost));
+        HGS_HIP(hipMemcpy(z.data(), st->zbits, (size_t)VN * 4, hipMemcpyDeviceToHost));
+      }
+      uint64_t *k = static_cast<uint64_t *>(dst);
+      for (int64_t i = 0; i < st->D; ++i) k[i] = ((uint64_t)t[i] << 32) | z[v[i]];
+      return HGS_OK;
+    }
     case 1: src = st->vals; bytes = st->D * 4; break;
     case 2: src = st->ranges; bytes = (int64_t)st->n_tiles * 8; break;
     case 3: src = st->rect; bytes = VN * 16; break;

@@ -60,35 +60,97 @@ struct SceneDev {
   const uint8_t *types;
 };
 
+// One request of a batched launch: a scene seen by one camera.  Its
+// instances are [inst_base, inst_base + scene.n) and its tiles start at
+// cam.tile_base.  Output images are [C, H, W] per request (NULL: not
+// written).  Slots are ordered by inst_base and by tile_base.
+struct Slot {
+  SceneDev scene;
+  DevCam cam;
+  int64_t inst_base;
+  float *rgb, *alpha, *depth, *normal;
+};
+
+// Last slot r < ns with slots[r].inst_base <= i (binary search).
+__device__ inline int slot_of_instance(const Slot *slots, int ns, int64_t i) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (slots[mid].inst_base <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Last slot r < ns with slots[r].cam.tile_base <= t (binary search).
+__device__ inline int slot_of_tile(const Slot *slots, int ns, int t) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (slots[mid].cam.tile_base <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ----- launchers (all enqueue on `s`) -----
 // flags per (view, splat): bit 0 valid, bit 1 normal negated, bits 2-3 normal axis
 void launch_preprocess(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt,
                        Record *rec, uint32_t *tiles, uint32_t *zbits, int4 *rect,
                        uint8_t *flags, hipStream_t s);
+// The same for a batch of requests: instances [0, *n_inst) of the slot
+// table (grid sized by the capacity inst_cap).
+void launch_preprocess_slots(const Slot *slots, const int *n_slots, const uint64_t *n_inst,
+                             DevOpts opt, int64_t inst_cap, Record *rec, uint32_t *tiles,
+                             uint32_t *zbits, int4 *rect, uint8_t *flags, hipStream_t s);
 void launch_preprocess_bwd(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt,
                            const uint8_t *flags, const int4 *rect, const float *accum,
                            float *g_means, float *g_scales, float *g_rots, float *g_opac,
                            float *g_sh, int accumulate, hipStream_t s);
 
+// Counts.  Every launcher below takes a host count n that sizes the grid.
+// Where it also takes n_dev (may be NULL), the kernels use min(n, *n_dev):
+// the count then lives on the device and a captured launch stays valid for
+// any count up to the capacity n.
+
 // Exclusive scan of n uint32 values; writes the 64-bit total to *total
 // (device).  `tmp` must hold scan_tmp_bytes(n) bytes.
 size_t scan_tmp_bytes(int64_t n);
 void launch_scan(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *total, void *tmp,
-                 hipStream_t s);
+                 hipStream_t s, const uint64_t *n_dev = nullptr);
 
-void launch_duplicate(const uint32_t *offsets, const uint32_t *tiles, const int4 *rect,
-                      const uint32_t *zbits, const DevCam *cams, int V, int64_t N,
-                      uint64_t *keys, uint32_t *vals, hipStream_t s);
+// out[j] = in[idx[j]] for j < n.
+void launch_gather(const uint32_t *in, const uint32_t *idx, int64_t n, uint32_t *out,
+                   hipStream_t s, const uint64_t *n_dev = nullptr);
 
-// Stable LSD radix sort of (key, value) pairs on the low `bits` bits.
-// Buffers a/b ping-pong; returns 0 if the result is in (ka, va), 1 if in (kb, vb).
+// Pairs of the V*N instances taken in the order `order` (a permutation):
+// instance order[j] writes its (global tile id, instance id) pairs at
+// offsets[j], the exclusive scan of tiles[order[.]].
+void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint32_t *tiles,
+                      const int4 *rect, const DevCam *cams, int V, int64_t N, uint32_t *keys,
+                      uint32_t *vals, hipStream_t s);
+// The same for a batch of slots, with the instance count on the device.
+// Pairs at or past pair_cap are dropped and set *overflow = 1.
+void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
+                            const uint32_t *tiles, const int4 *rect, const Slot *slots,
+                            const int *n_slots, int64_t inst_cap, const uint64_t *n_inst,
+                            uint64_t pair_cap, uint32_t *keys, uint32_t *vals,
+                            uint32_t *overflow, hipStream_t s);
+
+// Stable LSD radix sort of n (u32 key, u32 value) pairs on the low `bits`
+// bits, 8 bits per pass.  The first pass reads (k0, v0) (v0 NULL: value =
+// index) and writes (ka, va); later passes ping-pong between (ka, va) and
+// (kb, vb).  k0/v0 may alias kb/vb but not ka/va.  Returns 0 if the result
+// is in (ka, va), 1 if in (kb, vb).  `tmp` holds sort_tmp_bytes(n) bytes.
 size_t sort_tmp_bytes(int64_t n);
-int launch_radix_sort(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
-                      int bits, void *tmp, hipStream_t s);
+int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint32_t *va,
+                      uint32_t *kb, uint32_t *vb, int64_t n, int bits, void *tmp, hipStream_t s,
+                      const uint64_t *n_dev = nullptr);
 
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
-void launch_ranges(const uint64_t *keys, int64_t D, uint2 *ranges, hipStream_t s);
+// ranges[t] = [first, last + 1) of tile t in the tile-sorted keys (ranges
+// must be zeroed first).
+void launch_ranges(const uint32_t *keys, int64_t D, uint2 *ranges, hipStream_t s,
+                   const uint64_t *D_dev = nullptr);
 
 struct RasterOut {
   float *rgb, *alpha, *depth, *normal;
@@ -102,6 +164,13 @@ void launch_raster_fwd(const uint2 *ranges, const uint32_t *vals, const Record *
                        const DevCam *cams, int V, int n_tiles_total, int W, int H,
                        int tiles_x, int tiles_per_view, DevOpts opt, RasterOut out,
                        hipStream_t s);
+
+// Forward of a batch of slots on a persistent grid of n_blocks wave64s
+// that pull (tile, quadrant) units from *queue (zero at launch) up to the
+// device tile count *n_tiles.  Writes each slot's images.
+void launch_raster_fwd_queue(const uint2 *ranges, const uint32_t *vals, const Record *rec,
+                             const Slot *slots, const int *n_slots, const int *n_tiles,
+                             int n_blocks, DevOpts opt, uint32_t *queue, hipStream_t s);
 
 struct RasterGradIn {
   const float *rgb, *alpha, *depth, *normal;

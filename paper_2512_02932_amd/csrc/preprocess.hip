@@ -397,19 +397,16 @@ __device__ __forceinline__ double col_of(const double *M9, int row, int axis) {
 // flags per (view, splat): bit 0 valid, bit 1 normal negated, bits 2-3 axis
 constexpr uint8_t kValid = 1, kFlip = 2;
 
+// Splat g of scene sc seen by camera c, written as instance i.
 template <int DEG>
-__global__ void __launch_bounds__(256)
-preprocess_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOpts opt,
-                  Record *__restrict__ rec, uint32_t *__restrict__ tiles,
-                  uint32_t *__restrict__ zbits, int4 *__restrict__ rect,
-                  uint8_t *__restrict__ flags) {
+__device__ __forceinline__ void preprocess_one(const SceneDev &sc, const DevCam &c, int64_t g,
+                                               int64_t i, const DevOpts &opt,
+                                               Record *__restrict__ rec,
+                                               uint32_t *__restrict__ tiles,
+                                               uint32_t *__restrict__ zbits,
+                                               int4 *__restrict__ rect,
+                                               uint8_t *__restrict__ flags) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)V * sc.n;
-  if (i >= total) return;
-  const int v = (int)(i / sc.n);
-  const int64_t g = i - (int64_t)v * sc.n;
-  const DevCam &c = cams[v];
   const bool is2d = sc.types[g] == 0;
   const float m[3] = {sc.means[3 * g], sc.means[3 * g + 1], sc.means[3 * g + 2]};
   const float s[3] = {sc.scales[3 * g], sc.scales[3 * g + 1], sc.scales[3 * g + 2]};
@@ -474,6 +471,42 @@ preprocess_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOpts o
   Record *dst = rec + i;
 #pragma unroll
   for (int k = 0; k < 5; ++k) dst->r[k] = r.r[k];
+}
+
+// V views of one scene: instance i = v * N + g.
+template <int DEG>
+__global__ void __launch_bounds__(256)
+preprocess_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOpts opt,
+                  Record *__restrict__ rec, uint32_t *__restrict__ tiles,
+                  uint32_t *__restrict__ zbits, int4 *__restrict__ rect,
+                  uint8_t *__restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)V * sc.n;
+  if (i >= total) return;
+  const int v = (int)(i / sc.n);
+  const int64_t g = i - (int64_t)v * sc.n;
+  preprocess_one<DEG>(sc, cams[v], g, i, opt, rec, tiles, zbits, rect, flags);
+}
+
+// A batch of requests (scene, camera): instance i < *n_inst belongs to the
+// slot whose range [inst_base, inst_base + scene.n) holds it.
+__global__ void __launch_bounds__(256)
+preprocess_slots_kernel(const Slot *__restrict__ slots, const int *__restrict__ n_slots,
+                        const uint64_t *__restrict__ n_inst, DevOpts opt, int64_t inst_cap,
+                        Record *__restrict__ rec, uint32_t *__restrict__ tiles,
+                        uint32_t *__restrict__ zbits, int4 *__restrict__ rect,
+                        uint8_t *__restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ns = *n_slots;
+  if (ns <= 0 || i >= inst_cap || (uint64_t)i >= *n_inst) return;
+  const Slot &sl = slots[slot_of_instance(slots, ns, i)];
+  const int64_t g = i - sl.inst_base;
+  switch (sl.scene.sh_degree) {
+    case 0: preprocess_one<0>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
+    case 1: preprocess_one<1>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
+    case 2: preprocess_one<2>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
+    default: preprocess_one<3>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -754,6 +787,14 @@ void launch_preprocess(const SceneDev &sc, const DevCam *cams, int V, DevOpts op
     case 2: hipLaunchKernelGGL(preprocess_kernel<2>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags); break;
     default: hipLaunchKernelGGL(preprocess_kernel<3>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags); break;
   }
+}
+
+void launch_preprocess_slots(const Slot *slots, const int *n_slots, const uint64_t *n_inst,
+                             DevOpts opt, int64_t inst_cap, Record *rec, uint32_t *tiles,
+                             uint32_t *zbits, int4 *rect, uint8_t *flags, hipStream_t s) {
+  if (inst_cap <= 0) return;
+  hipLaunchKernelGGL(preprocess_slots_kernel, dim3((unsigned)((inst_cap + 255) / 256)), dim3(256),
+                     0, s, slots, n_slots, n_inst, opt, inst_cap, rec, tiles, zbits, rect, flags);
 }
 
 template <int DEG>

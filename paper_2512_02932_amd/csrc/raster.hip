@@ -106,13 +106,12 @@ struct Quad {
   bool inside;
 };
 
-__device__ __forceinline__ Quad quad_of(int W, int H, int tiles_x, int tiles_per_view) {
+// Quadrant `quad` of the view-local tile r (row-major over tiles_x columns).
+__device__ __forceinline__ Quad make_quad(int tile, int v, int r, int quad, int W, int H,
+                                          int tiles_x) {
   Quad q;
-  const int b = blockIdx.x;
-  q.tile = (b >> 5) * 8 + (b & 7);
-  const int quad = (b >> 3) & 3;
-  q.v = q.tile / tiles_per_view;
-  const int r = q.tile - q.v * tiles_per_view;
+  q.tile = tile;
+  q.v = v;
   const int ty = r / tiles_x;
   const int tx = r - ty * tiles_x;
   q.qx = tx * kTile + (quad & 1) * 8;
@@ -125,6 +124,19 @@ __device__ __forceinline__ Quad quad_of(int W, int H, int tiles_x, int tiles_per
   q.inside = q.px < W && q.py < H;
   return q;
 }
+
+__device__ __forceinline__ Quad quad_of(int W, int H, int tiles_x, int tiles_per_view) {
+  const int b = blockIdx.x;
+  const int tile = (b >> 5) * 8 + (b & 7);
+  const int v = tile / tiles_per_view;
+  return make_quad(tile, v, tile - v * tiles_per_view, (b >> 3) & 3, W, H, tiles_x);
+}
+
+// Output images of one view: channel planes of H*W pixels (NULL: skip).
+struct ViewOut {
+  float *rgb, *alpha, *depth, *normal, *T_final;
+  uint32_t *last, *n_contrib, *wcount;
+};
 
 // Does the record's inclusive pixel rectangle (r0) meet the quadrant?
 __device__ __forceinline__ bool meets(const float4 &r0, const Quad &q) {
@@ -141,16 +153,12 @@ __device__ __forceinline__ bool is3d_of(const float4 &r4) {
   return (__builtin_amdgcn_readfirstlane(__float_as_int(r4.w)) >> 31) == 0;
 }
 
-__global__ void __launch_bounds__(kWave)
-raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
-                  const Record *__restrict__ rec, int n_tiles, int W, int H, int tiles_x,
-                  int tiles_per_view, DevOpts opt, RasterOut out) {
-  __shared__ float4 srec[5][kWave];
-  __shared__ uint32_t spos[kWave];
-  const Quad q = quad_of(W, H, tiles_x, tiles_per_view);
-  if (q.tile >= n_tiles) return;
+// Composites one quadrant: the wave's 64 pixels over the tile's pair range.
+__device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const uint32_t *vals,
+                                                const Record *rec, int W, int H,
+                                                const DevOpts &opt, const ViewOut &out,
+                                                float4 (*srec)[kWave], uint32_t *spos) {
   const int lane = threadIdx.x;
-  const uint2 rg = ranges[q.tile];
   const int n = (int)(rg.y - rg.x);
 
   // T > 0 while the pixel composites; a stopped pixel keeps -T (its final
@@ -215,9 +223,8 @@ raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   T = fabsf(T);
   if (!q.inside) return;
   const int64_t hw = (int64_t)H * W;
-  const int64_t pix = (int64_t)q.py * W + q.px;
-  const int64_t o1 = (int64_t)q.v * hw + pix;
-  const int64_t o3 = (int64_t)q.v * 3 * hw + pix;
+  const int64_t o1 = (int64_t)q.py * W + q.px;
+  const int64_t o3 = o1;
   if (out.rgb) {
     out.rgb[o3] = cr + T * opt.bg[0];
     out.rgb[o3 + hw] = cg + T * opt.bg[1];
@@ -234,6 +241,62 @@ raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   if (out.last) out.last[o1] = last;
   if (out.n_contrib) out.n_contrib[o1] = cnt;
   if (out.wcount) out.wcount[o1] = wc;
+}
+
+// Views of one size: the block id picks the tile and quadrant (quad_of).
+__global__ void __launch_bounds__(kWave)
+raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
+                  const Record *__restrict__ rec, int n_tiles, int W, int H, int tiles_x,
+                  int tiles_per_view, DevOpts opt, RasterOut out) {
+  __shared__ float4 srec[5][kWave];
+  __shared__ uint32_t spos[kWave];
+  const Quad q = quad_of(W, H, tiles_x, tiles_per_view);
+  if (q.tile >= n_tiles) return;
+  const int64_t hw = (int64_t)H * W, v = q.v;
+  ViewOut vo;
+  vo.rgb = out.rgb ? out.rgb + v * 3 * hw : nullptr;
+  vo.alpha = out.alpha ? out.alpha + v * hw : nullptr;
+  vo.depth = out.depth ? out.depth + v * hw : nullptr;
+  vo.normal = out.normal ? out.normal + v * 3 * hw : nullptr;
+  vo.T_final = out.T_final ? out.T_final + v * hw : nullptr;
+  vo.last = out.last ? out.last + v * hw : nullptr;
+  vo.n_contrib = out.n_contrib ? out.n_contrib + v * hw : nullptr;
+  vo.wcount = out.wcount ? out.wcount + v * hw : nullptr;
+  raster_fwd_quad(q, ranges[q.tile], vals, rec, W, H, opt, vo, srec, spos);
+}
+
+// A batch of slots (requests of any size), persistent: each wave takes
+// work units u = 4 tile + quadrant from an atomic counter until u passes
+// 4 x the device tile count.  Every wave reaches that exit.  `queue` must be
+// zero at launch.
+__global__ void __launch_bounds__(kWave)
+raster_fwd_queue_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
+                        const Record *__restrict__ rec, const Slot *__restrict__ slots,
+                        const int *__restrict__ n_slots, const int *__restrict__ n_tiles,
+                        DevOpts opt, uint32_t *__restrict__ queue) {
+  __shared__ float4 srec[5][kWave];
+  __shared__ uint32_t spos[kWave];
+  const int ns = *n_slots;
+  const uint32_t units = 4u * (uint32_t)max(*n_tiles, 0);
+  if (ns <= 0) return;
+  for (;;) {
+    uint32_t u = 0;
+    if (threadIdx.x == 0) u = atomicAdd(queue, 1u);
+    u = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)u, 0));
+    if (u >= units) break;
+    const int tile = (int)(u >> 2);
+    const Slot &sl = slots[slot_of_tile(slots, ns, tile)];
+    const int W = sl.cam.W, H = sl.cam.H;
+    const Quad q = make_quad(tile, 0, tile - sl.cam.tile_base, (int)(u & 3u), W, H,
+                             sl.cam.tiles_x);
+    ViewOut vo{};
+    vo.rgb = sl.rgb;
+    vo.alpha = sl.alpha;
+    vo.depth = sl.depth;
+    vo.normal = sl.normal;
+    raster_fwd_quad(q, ranges[tile], vals, rec, W, H, opt, vo, srec, spos);
+    __syncthreads();  // the unit's LDS slots are free before the next unit
+  }
 }
 
 // Cross-lane helpers of the reduce-scatter.  swap32(a, b): lanes 0-31 get
@@ -443,6 +506,14 @@ void launch_raster_fwd(const uint2 *ranges, const uint32_t *vals, const Record *
   if (n_tiles_total == 0) return;
   hipLaunchKernelGGL(raster_fwd_kernel, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
                      ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt, out);
+}
+
+void launch_raster_fwd_queue(const uint2 *ranges, const uint32_t *vals, const Record *rec,
+                             const Slot *slots, const int *n_slots, const int *n_tiles,
+                             int n_blocks, DevOpts opt, uint32_t *queue, hipStream_t s) {
+  if (n_blocks <= 0) return;
+  hipLaunchKernelGGL(raster_fwd_queue_kernel, dim3((unsigned)n_blocks), dim3(kWave), 0, s, ranges,
+                     vals, rec, slots, n_slots, n_tiles, opt, queue);
 }
 
 void launch_raster_bwd(const uint2 *ranges, const uint32_t *vals, const Record *rec,

@@ -1,6 +1,13 @@
-// Integer stages of the tile pipeline, gfx950: exclusive scan,
-// duplicate-with-keys, stable LSD radix sort of (u64 key, u32 value) pairs,
-// tile-range identification and fills.
+// Integer stages of the tile pipeline, gfx950: exclusive scan, gather,
+// duplicate, stable LSD radix sort of (u32 key, u32 value) pairs, tile-range
+// identification and fills.
+//
+// The (tile, depth) order of the pairs is reached in two sorts.  The V*N
+// splat instances are sorted by their 32-bit depth key first (values are
+// instance ids, so equal depths keep index order); the pairs are then
+// duplicated in that order and stably sorted by tile id alone.  The result
+// equals one stable sort of the 64-bit keys (tile << 32 | depth) of pairs
+// duplicated in index order, with far fewer bits sorted per pair.
 //
 // The radix sort uses 8-bit digits.  A pass is three launches over
 // fixed-size chunks of 4096 pairs:
@@ -20,6 +27,14 @@ namespace {
 
 constexpr int kScanItems = 16;                       // elements per thread
 constexpr int kScanChunk = kBlock * kScanItems;      // 4096 per block
+
+// Element count of a launch: the host capacity n, or min(n, *n_dev) when the
+// count lives on the device (graph-captured launches never read it back).
+__device__ __forceinline__ int64_t eff_n(int64_t n, const uint64_t *n_dev) {
+  if (!n_dev) return n;
+  const uint64_t d = *n_dev;
+  return d < (uint64_t)n ? (int64_t)d : n;
+}
 
 // ----- block-wide exclusive scan of one value per thread (256 threads) -----
 template <typename T>
@@ -49,8 +64,10 @@ __device__ inline T block_exclusive_scan(T v, T *lds, T &total) {
 
 // Level 0: per-chunk sums (u64) of u32 input.
 __global__ void __launch_bounds__(256) scan_reduce_u32(const uint32_t *__restrict__ in, int64_t n,
+                                                       const uint64_t *__restrict__ n_dev,
                                                        uint64_t *__restrict__ sums) {
   __shared__ uint64_t lds[4];
+  n = eff_n(n, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   uint64_t acc = 0;
 #pragma unroll
@@ -104,8 +121,11 @@ __device__ inline void scan_chunk(const TI *in, TO *out, int64_t n, uint64_t off
 
 __global__ void __launch_bounds__(256) scan_down_u32(const uint32_t *__restrict__ in,
                                                      uint32_t *__restrict__ out, int64_t n,
+                                                     const uint64_t *__restrict__ n_dev,
                                                      const uint64_t *__restrict__ offs) {
   __shared__ uint64_t lds[4];
+  n = eff_n(n, n_dev);
+  if ((int64_t)blockIdx.x * kScanChunk >= n) return;
   scan_chunk<uint32_t, uint32_t>(in, out, n, offs ? offs[blockIdx.x] : 0, lds);
 }
 
@@ -154,59 +174,96 @@ size_t scan_u64_tmp(int64_t n) {
   return (size_t)(2 * nb) * sizeof(uint64_t) + scan_u64_tmp(nb);
 }
 
-// ----- duplicate with keys -----
-// One thread per (view, splat); pairs are written at offsets[i] in tile
-// row-major order of the splat's rectangle.  key = (global tile << 32) | depth
-// bits, value = view * N + splat.
-__global__ void __launch_bounds__(256)
-duplicate_kernel(const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ tiles,
-                 const int4 *__restrict__ rect, const uint32_t *__restrict__ zbits,
-                 const DevCam *__restrict__ cams, int64_t N, int64_t total,
-                 uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  if (tiles[i] == 0) return;
-  const int v = (int)(i / N);
-  const DevCam &c = cams[v];
-  const int4 r = rect[i];
-  uint32_t o = offsets[i];
-  const uint64_t z = zbits[i];
+// ----- gather and duplicate -----
+__global__ void __launch_bounds__(256) gather_u32_kernel(const uint32_t *__restrict__ in,
+                                                         const uint32_t *__restrict__ idx,
+                                                         int64_t n,
+                                                         const uint64_t *__restrict__ n_dev,
+                                                         uint32_t *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < eff_n(n, n_dev)) out[j] = in[idx[j]];
+}
+
+// One thread per instance in depth order: instance i = order[j] writes its
+// pairs at offsets[j], in tile row-major order of its rectangle.
+// key = global tile id, value = instance id i.
+__device__ __forceinline__ void emit_pairs(const DevCam &c, int4 r, uint32_t i, uint64_t o,
+                                           uint64_t cap, uint32_t *__restrict__ keys,
+                                           uint32_t *__restrict__ vals,
+                                           uint32_t *__restrict__ overflow) {
   const int tx0 = r.x >> 4, tx1 = r.z >> 4, ty0 = r.y >> 4, ty1 = r.w >> 4;
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx) {
-      const uint64_t tile = (uint64_t)(c.tile_base + ty * c.tiles_x + tx);
-      keys[o] = (tile << 32) | z;
-      vals[o] = (uint32_t)i;
+      if (o < cap) {
+        keys[o] = (uint32_t)(c.tile_base + ty * c.tiles_x + tx);
+        vals[o] = i;
+      } else if (overflow) {
+        *overflow = 1u;
+      }
       ++o;
     }
+}
+
+// Views of one scene: instance i = view * N + splat.
+__global__ void __launch_bounds__(256)
+duplicate_kernel(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
+                 const uint32_t *__restrict__ tiles, const int4 *__restrict__ rect,
+                 const DevCam *__restrict__ cams, int64_t N, int64_t total,
+                 uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= total) return;
+  const uint32_t i = order[j];
+  if (tiles[i] == 0) return;
+  emit_pairs(cams[i / N], rect[i], i, offsets[j], ~0ull, keys, vals, nullptr);
+}
+
+// A batch of slots; instance count on the device.  Pairs at or past `cap`
+// are dropped and raise *overflow.
+__global__ void __launch_bounds__(256)
+duplicate_slots_kernel(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
+                       const uint32_t *__restrict__ tiles, const int4 *__restrict__ rect,
+                       const Slot *__restrict__ slots, const int *__restrict__ n_slots,
+                       int64_t inst_cap, const uint64_t *__restrict__ n_inst, uint64_t cap,
+                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                       uint32_t *__restrict__ overflow) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= eff_n(inst_cap, n_inst)) return;
+  const uint32_t i = order[j];
+  if (tiles[i] == 0) return;
+  const Slot &sl = slots[slot_of_instance(slots, *n_slots, (int64_t)i)];
+  emit_pairs(sl.cam, rect[i], i, offsets[j], cap, keys, vals, overflow);
 }
 
 // ----- radix sort -----
 constexpr int kSortItems = 16;
 constexpr int kSortChunk = kBlock * kSortItems;  // 4096
 
-__global__ void __launch_bounds__(256) radix_hist(const uint64_t *__restrict__ keys, int64_t n,
-                                                  int shift, int64_t nb,
-                                                  uint32_t *__restrict__ hist) {
+__global__ void __launch_bounds__(256) radix_hist(const uint32_t *__restrict__ keys, int64_t n,
+                                                  const uint64_t *__restrict__ n_dev, int shift,
+                                                  int64_t nb, uint32_t *__restrict__ hist) {
   __shared__ uint32_t h[256];
+  n = eff_n(n, n_dev);
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortChunk;
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
     const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
-    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(256)
-radix_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
-              int shift, int64_t nb, const uint32_t *__restrict__ offs,
-              uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
+              const uint64_t *__restrict__ n_dev, int shift, int64_t nb,
+              const uint32_t *__restrict__ offs, uint32_t *__restrict__ kout,
+              uint32_t *__restrict__ vout) {
   __shared__ uint32_t base[256];        // running count of each digit in this chunk
   __shared__ uint32_t wcnt[4][256];     // per-wave counts of the current round
+  n = eff_n(n, n_dev);
+  if ((int64_t)blockIdx.x * kSortChunk >= n) return;  // whole block past the end
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   base[tid] = offs[(int64_t)tid * nb + blockIdx.x];
   const int64_t chunk = (int64_t)blockIdx.x * kSortChunk;
@@ -214,13 +271,12 @@ radix_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin
   for (int k = 0; k < kSortItems; ++k) {
     const int64_t i = chunk + (int64_t)k * kBlock + tid;
     const bool ok = i < n;
-    uint64_t key = 0;
-    uint32_t val = 0;
+    uint32_t key = 0, val = 0;
     if (ok) {
       key = kin[i];
-      val = vin[i];
+      val = vin ? vin[i] : (uint32_t)i;  // no input values: value = index
     }
-    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const uint32_t d = (key >> shift) & 255u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) wcnt[j][tid] = 0;
     __syncthreads();
@@ -266,13 +322,14 @@ __global__ void fill_f32_kernel(float *p, float v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
-__global__ void ranges_kernel(const uint64_t *__restrict__ keys, int64_t D,
-                              uint2 *__restrict__ ranges) {
+__global__ void ranges_kernel(const uint32_t *__restrict__ keys, int64_t D,
+                              const uint64_t *__restrict__ D_dev, uint2 *__restrict__ ranges) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  D = eff_n(D, D_dev);
   if (i >= D) return;
-  const uint32_t t = (uint32_t)(keys[i] >> 32);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[t].x = (uint32_t)i;
-  if (i == D - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = (uint32_t)(i + 1);
+  const uint32_t t = keys[i];
+  if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
+  if (i == D - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
 }  // namespace
@@ -283,29 +340,47 @@ size_t scan_tmp_bytes(int64_t n) {
 }
 
 void launch_scan(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *total, void *tmp,
-                 hipStream_t s) {
+                 hipStream_t s, const uint64_t *n_dev) {
   if (n == 0) {
     hipLaunchKernelGGL(single_total_u32, dim3(1), dim3(kBlock), 0, s, in, (int64_t)0, total);
     return;
   }
   const int64_t nb = nchunks(n);
   uint64_t *sums = (uint64_t *)tmp, *offs = sums + nb, *rest = sums + 2 * nb + 2;
-  hipLaunchKernelGGL(scan_reduce_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, sums);
+  hipLaunchKernelGGL(scan_reduce_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, n_dev, sums);
   scan_u64(sums, offs, nb, rest, s);
-  hipLaunchKernelGGL(scan_down_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n,
+  hipLaunchKernelGGL(scan_down_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, n_dev,
                      (const uint64_t *)offs);
   hipLaunchKernelGGL(scan_total, dim3(1), dim3(1), 0, s, (const uint64_t *)offs,
                      (const uint64_t *)sums, nb, total);
 }
 
-void launch_duplicate(const uint32_t *offsets, const uint32_t *tiles, const int4 *rect,
-                      const uint32_t *zbits, const DevCam *cams, int V, int64_t N,
-                      uint64_t *keys, uint32_t *vals, hipStream_t s) {
+void launch_gather(const uint32_t *in, const uint32_t *idx, int64_t n, uint32_t *out,
+                   hipStream_t s, const uint64_t *n_dev) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gather_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in,
+                     idx, n, n_dev, out);
+}
+
+void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint32_t *tiles,
+                      const int4 *rect, const DevCam *cams, int V, int64_t N, uint32_t *keys,
+                      uint32_t *vals, hipStream_t s) {
   const int64_t total = (int64_t)V * N;
   if (total == 0) return;
   const int64_t nb = (total + 255) / 256;
-  hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)nb), dim3(256), 0, s, offsets, tiles, rect,
-                     zbits, cams, N, total, keys, vals);
+  hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)nb), dim3(256), 0, s, order, offsets, tiles,
+                     rect, cams, N, total, keys, vals);
+}
+
+void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
+                            const uint32_t *tiles, const int4 *rect, const Slot *slots,
+                            const int *n_slots, int64_t inst_cap, const uint64_t *n_inst,
+                            uint64_t pair_cap, uint32_t *keys, uint32_t *vals,
+                            uint32_t *overflow, hipStream_t s) {
+  if (inst_cap <= 0) return;
+  hipLaunchKernelGGL(duplicate_slots_kernel, dim3((unsigned)((inst_cap + 255) / 256)), dim3(256),
+                     0, s, order, offsets, tiles, rect, slots, n_slots, inst_cap, n_inst, pair_cap,
+                     keys, vals, overflow);
 }
 
 size_t sort_tmp_bytes(int64_t n) {
@@ -314,27 +389,32 @@ size_t sort_tmp_bytes(int64_t n) {
   return (size_t)(2 * h) * sizeof(uint32_t) + scan_tmp_bytes(h) + 64;
 }
 
-int launch_radix_sort(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n, int bits,
-                      void *tmp, hipStream_t s) {
-  if (n <= 1) return 0;
+int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint32_t *va,
+                      uint32_t *kb, uint32_t *vb, int64_t n, int bits, void *tmp, hipStream_t s,
+                      const uint64_t *n_dev) {
+  if (n <= 0) return 0;
   const int64_t nb = (n + kSortChunk - 1) / kSortChunk;
   const int64_t h = 256 * nb;
   uint32_t *hist = (uint32_t *)tmp;
   uint32_t *offs = hist + h;
   uint64_t *total = (uint64_t *)(offs + h);
   void *stmp = (void *)(total + 1);
-  uint64_t *kin = ka, *kout = kb;
-  uint32_t *vin = va, *vout = vb;
+  const uint32_t *kin = k0, *vin = v0;
+  uint32_t *kout = ka, *vout = va;
   int which = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, (const uint64_t *)kin, n,
-                       shift, nb, hist);
+  const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL(radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n, n_dev, shift,
+                       nb, hist);
     launch_scan(hist, offs, h, total, stmp, s);
-    hipLaunchKernelGGL(radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, (const uint64_t *)kin,
-                       (const uint32_t *)vin, n, shift, nb, (const uint32_t *)offs, kout, vout);
-    std::swap(kin, kout);
-    std::swap(vin, vout);
-    which ^= 1;
+    hipLaunchKernelGGL(radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, n, n_dev,
+                       shift, nb, (const uint32_t *)offs, kout, vout);
+    which = (kout == ka) ? 0 : 1;
+    kin = kout;
+    vin = vout;
+    kout = (which == 0) ? kb : ka;
+    vout = (which == 0) ? vb : va;
   }
   return which;
 }
@@ -349,10 +429,11 @@ void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
 }
 
-void launch_ranges(const uint64_t *keys, int64_t D, uint2 *ranges, hipStream_t s) {
+void launch_ranges(const uint32_t *keys, int64_t D, uint2 *ranges, hipStream_t s,
+                   const uint64_t *D_dev) {
   if (D <= 0) return;
   hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, keys, D,
-                     ranges);
+                     D_dev, ranges);
 }
 
 }  // namespace hgs

@@ -305,3 +305,47 @@ def fd_subset(seed=33, n_each=32, crop=32):
         pick.append(cand[np.argsort(dist[cand], kind="stable")[:n_each]])
     idx = np.sort(np.concatenate(pick))
     return subset(scene, idx), crop_camera(cam, x0, y0, crop, crop)
+
+
+# ----- serving workload: four resident scenes and a Poisson request stream -----
+SERVING_RESOLUTIONS = ((256, 256), (512, 512), (1280, 720), (1920, 1080))
+
+
+def serving_scenes():
+    """The four resident scenes of the serving workload, seeds 41-44:
+    a 100k sphere (70% surfels), the 500k sphere, the 1M torus knot and a
+    3M multi-shell (60% surfels), all SH degree 3."""
+    return [scene_sphere(n=100_000, frac2d=0.7, seed=41),
+            scene_sphere(n=500_000, frac2d=0.7, seed=42),
+            scene_torus_knot(n=1_000_000, frac2d=0.5, seed=43),
+            scene_multishell(n=3_000_000, frac2d=0.6, seed=44)]
+
+
+def orbit_camera(radius, azimuth, elevation, width, height, vfov_deg=50.0):
+    """Camera on an orbit around the origin, looking at it, with vertical
+    field of view ``vfov_deg`` (f = H / (2 tan(vfov/2)))."""
+    eye = radius * np.array([np.cos(elevation) * np.sin(azimuth), np.sin(elevation),
+                             -np.cos(elevation) * np.cos(azimuth)])
+    f = height / (2.0 * np.tan(np.deg2rad(vfov_deg) / 2.0))
+    return look_at_camera(eye, width=width, height=height, fx=f)
+
+
+def serving_requests(n, rate=200.0, seed=45, n_scenes=4):
+    """``n`` requests: Poisson arrival times (s) at ``rate`` per second,
+    scene index uniform, resolution uniform over SERVING_RESOLUTIONS,
+    orbit radius U[3,5], azimuth U[0, 2 pi), elevation U[-20, 20] degrees.
+    Returns a list of dicts (t, scene, camera)."""
+    rng = _rng(seed)
+    gaps = rng.exponential(1.0 / rate, n)
+    t = np.cumsum(gaps)
+    sc = rng.integers(0, n_scenes, n)
+    res = rng.integers(0, len(SERVING_RESOLUTIONS), n)
+    rad = rng.uniform(3.0, 5.0, n)
+    az = rng.uniform(0.0, 2.0 * np.pi, n)
+    el = np.deg2rad(rng.uniform(-20.0, 20.0, n))
+    out = []
+    for i in range(n):
+        w, h = SERVING_RESOLUTIONS[res[i]]
+        out.append(dict(t=float(t[i]), scene=int(sc[i]),
+                        camera=orbit_camera(rad[i], az[i], el[i], w, h)))
+    return out

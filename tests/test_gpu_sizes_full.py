@@ -1,0 +1,158 @@
+"""Parity at the full sizes of the forward and large-batch workloads, in the
+launch configuration the benchmark uses, on outputs the oracle computes one
+by one: sampled pixels, sampled tiles and the structural arrays of sampled
+views.
+
+* 500k-Gaussian noisy sphere (70% surfels, SH3), one 1920x1080 camera,
+  forward: structural bit-exact over the whole frame, images at sampled
+  pixels.
+* 6M-Gaussian multi-shell (60% surfels, SH3), 16 cameras at 3840x2160 in
+  one launch, forward + backward: per-view structural arrays for three views,
+  the sorted list of sampled tiles, images at sampled pixels and gradients of
+  a loss on those pixels.  The oracle runs one view at a time; gradients of
+  a sum over views are the sum of per-view gradients.
+"""
+import numpy as np
+import pytest
+
+import scenegen as sg
+from gpu_common import (IMG_KEYS, PARAM_KEYS, compare_grads, compare_images,
+                        compare_structural, gpu_render, say)
+
+pytestmark = pytest.mark.gpu
+
+
+def test_sphere_500k_1080p_forward_sampled():
+    import oracle
+    scene = sg.scene_sphere()
+    cam = sg.camera_sphere()
+    rng = np.random.default_rng(11)
+    n = 3000
+    pix = np.stack([np.zeros(n, np.int64), rng.integers(0, 1080, n), rng.integers(0, 1920, n)], 1)
+    rows = np.array([[0, y, x] for y in (300, 540) for x in range(0, 1920, 3)])
+    pix = np.ascontiguousarray(np.concatenate([pix, rows]), np.int32)
+    say("[sphere500k] oracle forward at sampled pixels")
+    res = oracle.forward(scene, cam, pix)
+    say("[sphere500k] gpu render")
+    imgs, state, _ = gpu_render(scene, cam)
+    _, D = compare_structural(state, scene, cam)
+    rep = compare_images(imgs, state, res, pix)
+    say(f"[sphere500k] D={D} forward ok {rep}")
+    state.free()
+
+
+@pytest.mark.timeout(900)
+def test_multishell_6m_16x4k_fwd_bwd_sampled():
+    import torch
+    import oracle
+    from paper_2512_02932_amd.rasterizer import get_rasterizer, to_device
+
+    say("[shell6m] generating scene and cameras")
+    scene = sg.scene_multishell()
+    cams = sg.fibonacci_cameras()
+    V, H, W = len(cams), cams[0]["height"], cams[0]["width"]
+    N = scene["means"].shape[0]
+    views = (0, 7, 13)
+    rng = np.random.default_rng(12)
+
+    # sampled pixels per checked view, oracle forward one view at a time
+    samples = {}
+    for v in views:
+        pix = np.stack([np.zeros(700, np.int64), rng.integers(0, H, 700),
+                        rng.integers(0, W, 700)], 1)
+        row = np.array([[0, H // 2, x] for x in range(0, W, 8)])
+        pix = np.ascontiguousarray(np.concatenate([pix, row]), np.int32)
+        say(f"[shell6m] oracle forward, view {v}")
+        samples[v] = (pix, oracle.forward(scene, cams[v], pix))
+
+    # cotangents: N(0,1) at non-tie sampled pixels, zero elsewhere
+    rast = get_rasterizer(0)
+    sc = to_device(scene)
+    G = {k: torch.zeros((V, c, H, W), device="cuda") for k, c in
+         (("rgb", 3), ("alpha", 1), ("depth", 1), ("normal", 3))}
+    gsel = {}
+    for v in views:
+        pix, res = samples[v]
+        sel = pix[res["tie"] == 0][:300]
+        gsel[v] = sel
+        Gs = sg.upstream_grads(1, 1, len(sel), seed=20 + v)
+        ys = torch.from_numpy(sel[:, 1].astype(np.int64)).cuda()
+        xs = torch.from_numpy(sel[:, 2].astype(np.int64)).cuda()
+        for k in IMG_KEYS:
+            G[k][v][:, ys, xs] = torch.from_numpy(Gs[k][0][:, 0, :]).cuda()
+    say("[shell6m] gpu render 16 views + backward")
+    imgs, state = rast.render(sc, cams, want_state=True)
+    grads = {k: torch.zeros_like(sc[k]) for k in PARAM_KEYS}
+    rast.backward(state, G, grads)
+    torch.cuda.synchronize()
+    sz = state.sizes()
+    say(f"[shell6m] D={sz['D']}")
+
+    # structural arrays of the checked views, and sampled tile lists
+    tiles = state.debug("tiles")
+    zb = state.debug("zbits")
+    rect = state.debug("rect")
+    ranges = state.debug("ranges")
+    vals = state.debug("vals")
+    tpv = ((W + 15) // 16) * ((H + 15) // 16)
+    tiles_x = (W + 15) // 16
+    for v in views:
+        st = oracle.structural(scene, cams[v], 0.3)
+        sl = slice(v * N, (v + 1) * N)
+        np.testing.assert_array_equal(tiles[sl], st["tiles"])
+        ok = st["valid"] == 1
+        np.testing.assert_array_equal(zb[sl][ok], st["zbits"][ok])
+        np.testing.assert_array_equal(rect[sl][ok], st["rect"][ok])
+        r = st["rect"]
+        for t in rng.integers(0, tpv, 12):
+            ty, tx = divmod(int(t), tiles_x)
+            cover = ok & (r[:, 0] >> 4 <= tx) & (r[:, 2] >> 4 >= tx) & \
+                (r[:, 1] >> 4 <= ty) & (r[:, 3] >> 4 >= ty)
+            g = np.nonzero(cover)[0]
+            order = np.lexsort((g, st["zbits"][g]))
+            a, b = ranges[v * tpv + int(t)]
+            np.testing.assert_array_equal(vals[a:b], (v * N + g[order]).astype(np.uint32))
+    say("[shell6m] structural ok")
+
+    # images at sampled pixels, with per-pixel counts and transmittance
+    per_px = {k: state.debug(k) for k in ("n_contrib", "last", "T_final")}
+    for v in views:
+        pix, res = samples[v]
+        one = {k: imgs[k][v:v + 1].cpu().numpy() for k in IMG_KEYS}
+        rep = _compare_view(one, per_px, res, pix, v, H, W)
+        say(f"[shell6m] view {v} images ok {rep}")
+
+    # gradients: sum of per-view oracle backward passes
+    ref = None
+    for v in views:
+        sel = gsel[v]
+        Gp = np.zeros((len(sel), 8))
+        for k, cols in (("rgb", (0, 1, 2)), ("alpha", (3,)), ("depth", (4,)),
+                        ("normal", (5, 6, 7))):
+            g = G[k][v].cpu().numpy()
+            for j, col in enumerate(cols):
+                Gp[:, col] = g[j, sel[:, 1], sel[:, 2]]
+        say(f"[shell6m] oracle backward, view {v}")
+        r = oracle.backward(scene, cams[v], sel, Gp)
+        ref = r if ref is None else {k: ref[k] + r[k] for k in ref}
+    rep = compare_grads({k: v.cpu().numpy() for k, v in grads.items()}, ref)
+    say(f"[shell6m] backward ok {rep}")
+    state.free()
+
+
+def _compare_view(one, per_px, res, pix, v, H, W):
+    """Images of view v (one = its [1,C,H,W] slices) against the oracle at
+    pix (view column 0), plus n_contrib / last / T_final of the state."""
+    from gpu_common import IMG_TOL, gpu_at
+    tie = res["tie"] != 0
+    ok = ~tie
+    assert tie.mean() <= 0.01, f"tie fraction {tie.mean():.4f}"
+    g = gpu_at(one, pix)
+    err = np.abs(g - res["out"])
+    worst = err[ok].max()
+    assert worst <= IMG_TOL, f"max image error {worst:.3e}"
+    flat = v * H * W + pix[:, 1].astype(np.int64) * W + pix[:, 2]
+    np.testing.assert_array_equal(per_px["n_contrib"][flat][ok], res["n_contrib"][ok])
+    np.testing.assert_array_equal(per_px["last"][flat][ok], res["last"][ok])
+    assert np.abs(per_px["T_final"][flat][ok] - res["T"][ok]).max() <= IMG_TOL
+    return dict(max_err=float(worst), ties=int(tie.sum()), pixels=int(len(pix)))
