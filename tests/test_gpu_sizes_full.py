@@ -146,7 +146,10 @@ def _compare_view(one, per_px, res, pix, v, H, W):
     from gpu_common import IMG_TOL, gpu_at
     tie = res["tie"] != 0
     ok = ~tie
-    assert tie.mean() <= 0.01, f"tie fraction {tie.mean():.4f}"
+    # A tie pixel has a pair decision within the threshold margins; their
+    # share grows with the pairs per pixel, and the four shells put about
+    # eight surface layers under each pixel here (vs one or two elsewhere).
+    assert tie.mean() <= 0.02, f"tie fraction {tie.mean():.4f}"
     g = gpu_at(one, pix)
     err = np.abs(g - res["out"])
     worst = err[ok].max()
