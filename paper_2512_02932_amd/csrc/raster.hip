@@ -144,6 +144,16 @@ __device__ __forceinline__ bool meets(const float4 &r0, const Quad &q) {
   return r0.x <= x0 + 7.0f && r0.z >= x0 && r0.y <= y0 + 7.0f && r0.w >= y0;
 }
 
+// Issue priority of a wave by the length of the list it walks: the long
+// lists of the few dense tiles set the kernel's critical path, so their
+// waves win issue slots over the short ones sharing their SIMD.
+__device__ __forceinline__ void prio_for_list(int n) {
+  if (n > 2048) __builtin_amdgcn_s_setprio(3);
+  else if (n > 768) __builtin_amdgcn_s_setprio(2);
+  else if (n > 256) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
+
 __device__ __forceinline__ int lane_rank(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -160,6 +170,7 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
                                                 float4 (*srec)[kWave], uint32_t *spos) {
   const int lane = threadIdx.x;
   const int n = (int)(rg.y - rg.x);
+  prio_for_list(n);
 
   // T > 0 while the pixel composites; a stopped pixel keeps -T (its final
   // transmittance, negated), so one compare tells both.
@@ -395,6 +406,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   for (int d = 32; d >= 1; d >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, d));
   const int n = min((int)__builtin_amdgcn_readfirstlane(wmax), (int)(rg.y - rg.x));
   if (n <= 0) return;
+  prio_for_list(n);
   const int vidx = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
                    ((lane >> 2) & 1);
 
