@@ -48,7 +48,8 @@ struct hgs_state {
   float *T_final = nullptr;
   uint32_t *last = nullptr, *n_contrib = nullptr, *wcount = nullptr;
   int64_t D = 0;
-  std::vector<void *> allocs;
+  Workspace *ws = nullptr;
+  std::vector<std::pair<void **, size_t>> plan;  // buffers awaiting commit()
 };
 
 namespace {
@@ -84,11 +85,12 @@ struct StageTimer {
   }
 };
 
+// Buffers are planned with dalloc and placed by commit() in one arena of
+// the state's workspace (256-byte aligned), growing the arena if needed.
 hipError_t dalloc(hgs_state *st, void **p, size_t bytes) {
-  if (bytes == 0) bytes = 256;
-  hipError_t e = hipMallocAsync(p, bytes, st->stream);
-  if (e == hipSuccess) st->allocs.push_back(*p);
-  return e;
+  st->plan.push_back({p, bytes == 0 ? 256 : bytes});
+  *p = nullptr;
+  return hipSuccess;
 }
 
 template <typename T>
@@ -96,10 +98,65 @@ hipError_t dalloc_t(hgs_state *st, T **p, size_t count) {
   return dalloc(st, reinterpret_cast<void **>(p), count * sizeof(T));
 }
 
-void release(hgs_state *st) {
-  if (!st) return;
-  for (void *p : st->allocs) (void)hipFreeAsync(p, st->stream);
-  st->allocs.clear();
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+hipError_t commit(hgs_state *st, int which, hipStream_t s) {
+  size_t total = 0;
+  for (auto &it : st->plan) total += align256(it.second);
+  Arena &A = st->ws->arena[which];
+  if (A.cap < total) {
+    if (A.buf) {
+      const hipError_t e = hipFreeAsync(A.buf, s);
+      A.buf = nullptr;
+      A.cap = 0;
+      if (e != hipSuccess) return e;
+    }
+    const size_t cap = std::max(total, A.cap + A.cap / 2);
+    const hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&A.buf), cap, s);
+    if (e != hipSuccess) {
+      st->plan.clear();
+      return e;
+    }
+    A.cap = cap;
+  }
+  size_t off = 0;
+  for (auto &it : st->plan) {
+    *it.first = A.buf + off;
+    off += align256(it.second);
+  }
+  st->plan.clear();
+  return hipSuccess;
+}
+
+hipError_t acquire_ws(hgs_ctx *ctx, hgs_state *st) {
+  Workspace *w = nullptr;
+  if (!ctx->ws_free.empty()) {
+    w = ctx->ws_free.back();
+    ctx->ws_free.pop_back();
+  } else {
+    w = new (std::nothrow) Workspace();
+    if (!w) return hipErrorOutOfMemory;
+    ctx->ws_all.push_back(w);
+  }
+  st->ws = w;
+  if (w->has_ready && w->stream != st->stream) return hipStreamWaitEvent(st->stream, w->ready, 0);
+  return hipSuccess;
+}
+
+void release(hgs_ctx *ctx, hgs_state *st) {
+  if (!st || !st->ws) return;
+  Workspace *w = st->ws;
+  st->ws = nullptr;
+  if (!w->ready && hipEventCreateWithFlags(&w->ready, hipEventDisableTiming) != hipSuccess)
+    w->ready = nullptr;
+  if (w->ready && hipEventRecord(w->ready, st->stream) == hipSuccess) {
+    w->stream = st->stream;
+    w->has_ready = true;
+  } else {
+    (void)hipStreamSynchronize(st->stream);
+    w->has_ready = false;
+  }
+  ctx->ws_free.push_back(w);
 }
 
 }  // namespace
@@ -230,6 +287,12 @@ void hgs_destroy(hgs_ctx *ctx) {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  for (Workspace *w : ctx->ws_all) {
+    for (Arena &a : w->arena)
+      if (a.buf) (void)hipFree(a.buf);
+    if (w->ready) (void)hipEventDestroy(w->ready);
+    delete w;
+  }
   delete ctx;
 }
 
@@ -361,7 +424,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   const int64_t P = (int64_t)n_views * W * H;
 
   auto bail = [&](hgs_status s) {
-    release(st);
+    release(ctx, st);
     (void)hipStreamSynchronize(st->stream);
     delete st;
     return s;
@@ -375,9 +438,8 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   } while (0)
 
   ST_HIP(hipSetDevice(ctx->device));
+  ST_HIP(acquire_ws(ctx, st));
   ST_HIP(dalloc_t(st, &st->cams, (size_t)n_views));
-  ST_HIP(hipMemcpyAsync(st->cams, st->cams_host.data(), sizeof(DevCam) * n_views,
-                        hipMemcpyHostToDevice, st->stream));
   ST_HIP(dalloc_t(st, &st->rec, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->tiles, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->zbits, (size_t)VN));
@@ -401,6 +463,9 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc_t(st, &ob, (size_t)VN));
   ST_HIP(dalloc_t(st, &cnt, (size_t)VN));
   ST_HIP(dalloc(st, &dsort_tmp, sort_tmp_bytes(VN)));
+  ST_HIP(commit(st, 0, st->stream));
+  ST_HIP(hipMemcpyAsync(st->cams, st->cams_host.data(), sizeof(DevCam) * n_views,
+                        hipMemcpyHostToDevice, st->stream));
 
   {
     StageTimer t(ctx, HGS_STAGE_PREPROCESS, st->stream);
@@ -433,6 +498,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc_t(st, &kb, (size_t)st->D));
   ST_HIP(dalloc_t(st, &vb, (size_t)st->D));
   ST_HIP(dalloc(st, &sort_tmp, sort_tmp_bytes(st->D)));
+  ST_HIP(commit(st, 1, st->stream));
   {
     StageTimer t(ctx, HGS_STAGE_DUPLICATE, st->stream);
     launch_duplicate(order, st->offsets, st->tiles, st->rect, st->cams, n_views, st->N, kb, vb,
@@ -474,7 +540,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   if (state_out) {
     *state_out = st;
   } else {
-    release(st);
+    release(ctx, st);
     delete st;
   }
   return HGS_OK;
@@ -496,8 +562,10 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_image
     HGS_HIP(hipEventDestroy(ev));
   }
   const int64_t VN = (int64_t)st->V * st->N;
+  if (!st->ws) return fail(HGS_ESTATE, "state has no workspace");
   float *accum = nullptr;
-  HGS_HIP(hipMallocAsync((void **)&accum, (size_t)std::max<int64_t>(VN, 1) * kGradSlots * 4, s));
+  HGS_HIP(dalloc_t(st, &accum, (size_t)std::max<int64_t>(VN, 1) * kGradSlots));
+  HGS_HIP(commit(st, 2, s));
   {
     StageTimer t(ctx, HGS_STAGE_FILL, s);
     launch_fill_f32(accum, 0.0f, VN * kGradSlots, s);
@@ -521,7 +589,6 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_image
                           grads->sh, grads->accumulate, s);
   }
   HGS_HIP(hipGetLastError());
-  HGS_HIP(hipFreeAsync(accum, s));
   if (s != st->stream) {
     hipEvent_t ev;
     HGS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -565,7 +632,7 @@ hgs_status hgs_profile_read(hgs_ctx *ctx, double *ms, int64_t *calls, int32_t re
 void hgs_state_free(hgs_ctx *ctx, hgs_state *st) {
   if (!st) return;
   if (ctx) (void)hipSetDevice(ctx->device);
-  release(st);
+  if (ctx) release(ctx, st);
   delete st;
 }
 

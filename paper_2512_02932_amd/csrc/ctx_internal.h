@@ -35,6 +35,24 @@ struct StageEvent {
   hipEvent_t a, b;
 };
 
+// Device memory reused across calls: a grow-only buffer carved up anew by
+// each user.
+struct Arena {
+  char *buf = nullptr;
+  size_t cap = 0;
+};
+
+// The scratch of one render (and its backward).  A render takes one from
+// the context's pool and returns it when its state is freed, so steady-state
+// calls allocate nothing.  `ready` is recorded on the releasing stream; a
+// user on another stream waits for it first.
+struct Workspace {
+  Arena arena[3];  // 0: sized before D is known, 1: D-sized, 2: backward
+  hipEvent_t ready = nullptr;
+  hipStream_t stream = nullptr;
+  bool has_ready = false;
+};
+
 // Options with defaults filled in, as the kernels take them.
 DevOpts to_dev_opts(const hgs_opts *o);
 // Validates camera c and fills d (view index `view`); false with a reason.
@@ -50,4 +68,5 @@ struct hgs_ctx {
   std::vector<hipEvent_t> event_pool;
   double stage_ms[HGS_N_STAGES] = {0};
   int64_t stage_calls[HGS_N_STAGES] = {0};
+  std::vector<hgs::Workspace *> ws_all, ws_free;
 };
