@@ -434,14 +434,21 @@ __device__ __forceinline__ void preprocess_one(const SceneDev &sc, const DevCam 
     double acc = 0.5;
 #pragma unroll
     for (int j = 0; j < K; ++j) acc += (double)f[3 * j + ch] * Y[j];
-    col[ch] = acc > 0.0 ? (float)acc : 0.0f;
+    col[ch] = (acc > 0.0 && acc < 3.0e38) ? (float)acc : 0.0f;  // NaN, <= 0: 0
   }
   const double sg = st.flip ? -1.0 : 1.0;
-  const float nx = (float)(sg * col_of(o.RvR, 0, st.axis)),
-              ny = (float)(sg * col_of(o.RvR, 1, st.axis)),
-              nz = (float)(sg * col_of(o.RvR, 2, st.axis));
+  float nx = (float)(sg * col_of(o.RvR, 0, st.axis)),
+        ny = (float)(sg * col_of(o.RvR, 1, st.axis)),
+        nz = (float)(sg * col_of(o.RvR, 2, st.axis));
   const double k2 = sqrt(0.5 * kLog2e);
   float aeff = (float)o.alpha_eff;
+  // the raster accumulates colour and normal with weight 0 for inactive
+  // pairs, so a record's values must be finite; a non-finite one is never
+  // active
+  if (!(isfinite(nx) && isfinite(ny) && isfinite(nz) && isfinite(aeff))) {
+    aeff = 0.0f;
+    nx = ny = nz = 0.0f;
+  }
   Record r;
   r.r[0] = make_float4((float)st.px0, (float)st.py0, (float)st.px1, (float)st.py1);
   if (!is2d) {

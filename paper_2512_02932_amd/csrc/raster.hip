@@ -172,9 +172,10 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
   const int n = (int)(rg.y - rg.x);
   prio_for_list(n);
 
-  // T > 0 while the pixel composites; a stopped pixel keeps -T (its final
-  // transmittance, negated), so one compare tells both.
-  float T = q.inside ? 1.0f : -1.0f;
+  // thr is the activity threshold: 1/255 while the pixel composites, +inf
+  // once it has stopped, so one compare gives both tests.
+  float T = 1.0f;
+  float thr = q.inside ? kAlphaMin : __builtin_inff();
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, nx = 0.0f, ny = 0.0f, nz = 0.0f;
   uint32_t cnt = 0, last = 0, wc = 0;
 
@@ -184,7 +185,7 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
   if (lane < n) HGS_FETCH(rec, vals[rg.x + lane], q0, q1, q2, q3, q4);
   if (kWave + lane < n) nid = vals[rg.x + kWave + lane];
   for (int c = 0; c < n; c += kWave) {
-    if (__ballot(T > 0.0f) == 0ull) break;
+    if (__ballot(thr < 1.0f) == 0ull) break;
     const bool hit = (c + lane < n) && meets(q0, q);
     const uint64_t m = __ballot(hit);
     __syncthreads();  // the previous chunk's slots have been read
@@ -201,37 +202,60 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
     if (c + kWave + lane < n) HGS_FETCH(rec, nid, q0, q1, q2, q3, q4);
     if (c + 2 * kWave + lane < n) nid = vals[rg.x + c + 2 * kWave + lane];
     const int k_end = __popcll(m);
-    for (int k = 0; k < k_end; ++k) {
-      if (__ballot(T > 0.0f) == 0ull) break;
-      const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
-                   r4 = srec[4][k];
-      const uint32_t pos = spos[k];
-      const bool is3d = is3d_of(r4);
-      const PairEval p = eval_pair(is3d, q.fx, q.fy, r0, r1, r2, r3);
-      const float raw = fabsf(r4.w) * exp2_neg(p.e);
-      const float a = fminf(raw, kAlphaMax);
-      const float Tn = T * (1.0f - a);
-      const bool act = T > 0.0f && raw >= kAlphaMin;
-      const bool blend = act && Tn >= kTMin;
-      const float wg = blend ? a * T : 0.0f;
-      if (blend) {
+    for (int k0 = 0; k0 < k_end; k0 += 2) {
+      if (__ballot(thr < 1.0f) == 0ull) break;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int k = k0 + j;
+        if (k >= k_end) break;
+        const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
+                     r4 = srec[4][k];
+        const uint32_t pos = spos[k];
+        // both exponent forms, then a select on the type: no branch
+        const bool two = __float_as_int(r4.w) < 0;
+        float e, d;
+        {
+#pragma clang fp contract(off)
+          const float xr = q.fx - r0.x, yr = q.fy - r0.y;
+          const float dx = xr - r1.x, dy = yr - r1.y;
+          const float t = __builtin_fmaf(r1.w, dy, r1.z * dx);
+          const float u3 = r2.x * dy;
+          const float e3 = __builtin_fmaf(dx, t, u3 * dy);
+          const float U = __builtin_fmaf(r1.x, xr, __builtin_fmaf(r1.y, yr, r1.z));
+          const float V = __builtin_fmaf(r1.w, xr, __builtin_fmaf(r2.x, yr, r2.y));
+          const float Wh = __builtin_fmaf(r2.z, xr, __builtin_fmaf(r2.w, yr, r3.x));
+          const float rw = __builtin_amdgcn_rcpf(Wh);
+          const float uu = U * rw, vv = V * rw;
+          const float e2 = __builtin_fmaf(uu, uu, vv * vv);
+          e = two ? e2 : e3;
+          d = two ? rw : r2.y;
+        }
+        const float raw = fabsf(r4.w) * exp2_neg(e);
+        // active: raw >= thr (false for NaN).  An inactive pair has a = 0,
+        // so only an active pair can take T below 1e-4 (the stop); the
+        // weight is 0 unless the pair is blended, and the accumulations run
+        // unconditionally (record values are finite, see preprocess).
+        const float a = raw >= thr ? fminf(raw, kAlphaMax) : 0.0f;
+        const float Tn = T * (1.0f - a);
+        const bool stop = Tn < kTMin;
+        const float wg = stop ? 0.0f : a * T;
         cr = __builtin_fmaf(wg, r3.y, cr);
         cg = __builtin_fmaf(wg, r3.z, cg);
         cb = __builtin_fmaf(wg, r3.w, cb);
-        dep = __builtin_fmaf(wg, p.depth, dep);
+        dep = __builtin_fmaf(wg, raw >= thr ? d : 0.0f, dep);  // 1/W is inf where W = 0
         nx = __builtin_fmaf(wg, r4.x, nx);
         ny = __builtin_fmaf(wg, r4.y, ny);
         nz = __builtin_fmaf(wg, r4.z, nz);
-        ++cnt;
-        wc += is3d ? 1u : (1u << 15);
-        last = pos + 1u;
+        const bool bl = wg > 0.0f;
+        cnt += bl ? 1u : 0u;
+        wc += bl ? (two ? (1u << 15) : 1u) : 0u;
+        last = bl ? pos + 1u : last;
+        wc |= stop ? (0x80000000u | (two ? 0x40000000u : 0u)) : 0u;
+        thr = stop ? __builtin_inff() : thr;
+        T = stop ? T : Tn;
       }
-      // blend: T <- Tn; stop (act, not blend): T <- -T
-      T = blend ? Tn : ((act && !blend) ? -T : T);
-      wc |= (act && !blend) ? (0x80000000u | (is3d ? 0u : 0x40000000u)) : 0u;
     }
   }
-  T = fabsf(T);
   if (!q.inside) return;
   const int64_t hw = (int64_t)H * W;
   const int64_t o1 = (int64_t)q.py * W + q.px;
