@@ -255,21 +255,29 @@ __global__ void __launch_bounds__(256) radix_hist(const uint32_t *__restrict__ k
   hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(256)
+// Stable scatter of one chunk of kSortChunk pairs: 1024 threads (16 wave64)
+// rank the chunk in kSortChunk / 1024 rounds.  In a round each wave matches
+// equal digits with 8 ballots; a per-digit prefix over the 16 waves (in
+// wave order) and a running per-digit base carry the order across waves
+// and rounds.
+constexpr int kScatterThreads = 1024;
+constexpr int kScatterWaves = kScatterThreads / 64;
+
+__global__ void __launch_bounds__(kScatterThreads)
 radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
               const uint64_t *__restrict__ n_dev, int shift, int64_t nb,
               const uint32_t *__restrict__ offs, uint32_t *__restrict__ kout,
               uint32_t *__restrict__ vout) {
-  __shared__ uint32_t base[256];        // running count of each digit in this chunk
-  __shared__ uint32_t wcnt[4][256];     // per-wave counts of the current round
+  __shared__ uint32_t base[256];                  // running count of each digit in this chunk
+  __shared__ uint32_t wcnt[kScatterWaves][256];   // per-wave counts of the current round
   n = eff_n(n, n_dev);
   if ((int64_t)blockIdx.x * kSortChunk >= n) return;  // whole block past the end
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  base[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+  if (tid < 256) base[tid] = offs[(int64_t)tid * nb + blockIdx.x];
   const int64_t chunk = (int64_t)blockIdx.x * kSortChunk;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int k = 0; k < kSortItems; ++k) {
-    const int64_t i = chunk + (int64_t)k * kBlock + tid;
+  for (int k = 0; k < kSortChunk / kScatterThreads; ++k) {
+    const int64_t i = chunk + (int64_t)k * kScatterThreads + tid;
     const bool ok = i < n;
     uint32_t key = 0, val = 0;
     if (ok) {
@@ -278,7 +286,8 @@ radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin
     }
     const uint32_t d = (key >> shift) & 255u;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) wcnt[j][tid] = 0;
+    for (int j = 0; j < kScatterWaves * 256 / kScatterThreads; ++j)
+      (&wcnt[0][0])[j * kScatterThreads + tid] = 0;
     __syncthreads();
     // lanes of this wave with the same digit
     uint64_t peers = __ballot(ok);
@@ -292,15 +301,16 @@ radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin
     const bool leader = ok && (peers >> lane) == 1ull;  // highest lane of its group
     if (leader) wcnt[w][d] = cnt;
     __syncthreads();
-    // per digit: prefix over the waves in order
-    {
-      const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
-      const uint32_t b0 = base[tid];
-      wcnt[0][tid] = b0;
-      wcnt[1][tid] = b0 + c0;
-      wcnt[2][tid] = b0 + c0 + c1;
-      wcnt[3][tid] = b0 + c0 + c1 + c2;
-      base[tid] = b0 + c0 + c1 + c2 + c3;
+    // per digit: exclusive prefix over the waves in order
+    if (tid < 256) {
+      uint32_t b = base[tid];
+#pragma unroll
+      for (int v = 0; v < kScatterWaves; ++v) {
+        const uint32_t c = wcnt[v][tid];
+        wcnt[v][tid] = b;
+        b += c;
+      }
+      base[tid] = b;
     }
     __syncthreads();
     if (ok) {
@@ -351,8 +361,9 @@ void launch_scan(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *total, 
   scan_u64(sums, offs, nb, rest, s);
   hipLaunchKernelGGL(scan_down_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, n_dev,
                      (const uint64_t *)offs);
-  hipLaunchKernelGGL(scan_total, dim3(1), dim3(1), 0, s, (const uint64_t *)offs,
-                     (const uint64_t *)sums, nb, total);
+  if (total)
+    hipLaunchKernelGGL(scan_total, dim3(1), dim3(1), 0, s, (const uint64_t *)offs,
+                       (const uint64_t *)sums, nb, total);
 }
 
 void launch_gather(const uint32_t *in, const uint32_t *idx, int64_t n, uint32_t *out,
@@ -407,9 +418,9 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
     const int shift = 8 * p;
     hipLaunchKernelGGL(radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n, n_dev, shift,
                        nb, hist);
-    launch_scan(hist, offs, h, total, stmp, s);
-    hipLaunchKernelGGL(radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, n, n_dev,
-                       shift, nb, (const uint32_t *)offs, kout, vout);
+    launch_scan(hist, offs, h, nullptr, stmp, s);
+    hipLaunchKernelGGL(radix_scatter, dim3((unsigned)nb), dim3(kScatterThreads), 0, s, kin, vin, n,
+                       n_dev, shift, nb, (const uint32_t *)offs, kout, vout);
     which = (kout == ka) ? 0 : 1;
     kin = kout;
     vin = vout;
