@@ -11,6 +11,7 @@ sorted_pairs(st, cams)                 (key, value) list, stably sorted, + range
 forward(scene, cams, pix, ...)         binary64 per-pixel composite (Eq. 1-2)
 backward(scene, cams, pix, G, ...)     binary64 gradients (dual numbers)
 sh_basis(degree, dirs)                 real SH basis used for colour
+erank(sx, sy, sz) / type_exchange(...)  Adaptive Type Exchange (Eq. 3, P_x/P_y)
 surfel_uv(params, cam, pxy)            ray-plane (u, v, depth) of one surfel
 full_pixels(cams) / all outputs reshaped to images: render_images(...)
 """
@@ -59,6 +60,9 @@ def _load():
                                          [P, C.c_int, P, P, C.c_int64, P, C.c_int] + [P] * 5)
         _lib.oracle_sh_basis.argtypes = [C.c_int, P, C.c_int64, P]
         _lib.oracle_surfel_uv.argtypes = [P, P, P, C.c_int64, P]
+        _lib.oracle_erank.argtypes = [C.c_double, C.c_double, C.c_double]
+        _lib.oracle_erank.restype = C.c_double
+        _lib.oracle_type_exchange.argtypes = [P, P, P, C.c_int64, C.c_double, P, P, P, P, P]
     return _lib
 
 
@@ -221,6 +225,32 @@ def surfel_uv(params10, cam, pxy):
     out = np.zeros((pxy.shape[0], 3), np.float64)
     lib.oracle_surfel_uv(_p(prm), _p(pack_cams(cam)), _p(pxy), pxy.shape[0], _p(out))
     return out
+
+
+def erank(sx, sy, sz):
+    """Effective rank (Eq. 3) of scales (sx, sy, sz), binary64."""
+    return _load().oracle_erank(float(sx), float(sy), float(sz))
+
+
+def type_exchange(scales, rotations, types, theta=2.05):
+    """Adaptive Type Exchange of n primitives (binary64 decisions).
+
+    Returns dict(types u8[n], scales f32[n,3], quats f64[n,4] (unit, w >= 0
+    where the rotation was rebuilt), erank f64[n], moved i32[n] (0 none,
+    1 P_x, 2 P_y))."""
+    lib = _load()
+    s = np.ascontiguousarray(scales, np.float32)
+    r = np.ascontiguousarray(rotations, np.float32)
+    t = np.ascontiguousarray(types, np.uint8)
+    n = s.shape[0]
+    to = np.zeros(n, np.uint8)
+    so = np.zeros((n, 3), np.float32)
+    qo = np.zeros((n, 4), np.float64)
+    er = np.zeros(n, np.float64)
+    mv = np.zeros(n, np.int32)
+    lib.oracle_type_exchange(_p(s), _p(r), _p(t), n, float(theta), _p(to), _p(so), _p(qo),
+                             _p(er), _p(mv))
+    return dict(types=to, scales=so, quats=qo, erank=er, moved=mv)
 
 
 def images(res, cam, n_views=1):

@@ -1053,3 +1053,122 @@ int oracle_surfel_uv(const double *params, const float *cam, const double *pxy, 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adaptive Type Exchange (Sec. 3.2 and the appendix "Effective Rank and Type
+// Switch").  Per primitive, in binary64 from the binary32 inputs:
+//   erank = exp(-sum_i p_i log p_i), p = q / |q|_1, q = (s_x^2, s_y^2, s_z^2)
+//   (Eq. 3; 0 log 0 = 0; all-zero scales: erank = 0, no switch).
+//   3D (t != 0) with erank < theta_e: the least significant scale is moved to
+//   z by S* = P S P^T and R* = R P^T, with P = P_x when s_x is the least and
+//   P = P_y when s_y is (z before y before x on ties, so nothing moves when
+//   s_z is a least); the type becomes 2D.  The quaternion of R* is taken
+//   from the matrix (largest-diagonal branch), unit length, w >= 0.
+//   2D with erank > theta_e: the type becomes 3D, parameters unchanged.
+// Outputs: types_out u8[n], scales_out f32[n,3] (a permutation of the input
+// scales), quats_out f64[n,4] (unit; the input quaternion normalised when
+// the rotation is kept), erank f64[n], moved i32[n] (0 none, 1 P_x, 2 P_y).
+static void quat_to_mat(const double q[4], double R[9]) {
+  const double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const double w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+static void mat_to_quat(const double R[9], double q[4]) {
+  const double tr = R[0] + R[4] + R[8];
+  double w, x, y, z;
+  if (tr >= R[0] && tr >= R[4] && tr >= R[8]) {
+    const double r = std::sqrt(1.0 + tr);
+    w = 0.5 * r;
+    x = (R[7] - R[5]) / (2 * r);
+    y = (R[2] - R[6]) / (2 * r);
+    z = (R[3] - R[1]) / (2 * r);
+  } else if (R[0] >= R[4] && R[0] >= R[8]) {
+    const double r = std::sqrt(1.0 + R[0] - R[4] - R[8]);
+    x = 0.5 * r;
+    w = (R[7] - R[5]) / (2 * r);
+    y = (R[1] + R[3]) / (2 * r);
+    z = (R[2] + R[6]) / (2 * r);
+  } else if (R[4] >= R[8]) {
+    const double r = std::sqrt(1.0 - R[0] + R[4] - R[8]);
+    y = 0.5 * r;
+    w = (R[2] - R[6]) / (2 * r);
+    x = (R[1] + R[3]) / (2 * r);
+    z = (R[5] + R[7]) / (2 * r);
+  } else {
+    const double r = std::sqrt(1.0 - R[0] - R[4] + R[8]);
+    z = 0.5 * r;
+    w = (R[3] - R[1]) / (2 * r);
+    x = (R[2] + R[6]) / (2 * r);
+    y = (R[5] + R[7]) / (2 * r);
+  }
+  const double n = std::sqrt(w * w + x * x + y * y + z * z) * (w < 0 ? -1.0 : 1.0);
+  q[0] = w / n; q[1] = x / n; q[2] = y / n; q[3] = z / n;
+}
+
+extern "C" double oracle_erank(double sx, double sy, double sz) {
+  const double q[3] = {sx * sx, sy * sy, sz * sz};
+  const double sum = q[0] + q[1] + q[2];
+  if (!(sum > 0.0)) return 0.0;
+  double h = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    const double p = q[i] / sum;
+    if (p > 0.0) h -= p * std::log(p);
+  }
+  return std::exp(h);
+}
+
+extern "C" int oracle_type_exchange(const float *scales, const float *rots, const uint8_t *types,
+                                    int64_t n, double theta, uint8_t *types_out,
+                                    float *scales_out, double *quats_out, double *erank,
+                                    int32_t *moved) {
+  // P_x and P_y as row-major matrices (the appendix's definitions)
+  static const double Px[9] = {0, 1, 0, 0, 0, 1, 1, 0, 0};
+  static const double Py[9] = {0, 0, 1, 1, 0, 0, 0, 1, 0};
+  for (int64_t i = 0; i < n; ++i) {
+    const float *s = scales + 3 * i;
+    const double e = oracle_erank(s[0], s[1], s[2]);
+    erank[i] = e;
+    double q[4] = {rots[4 * i], rots[4 * i + 1], rots[4 * i + 2], rots[4 * i + 3]};
+    const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 4; ++k) quats_out[4 * i + k] = q[k] / qn;
+    for (int k = 0; k < 3; ++k) scales_out[3 * i + k] = s[k];
+    moved[i] = 0;
+    const bool is3d = types[i] != 0;
+    types_out[i] = is3d ? 1 : 0;
+    if (is3d && e > 0.0 && e < theta) {
+      types_out[i] = 0;
+      const double *P = nullptr;
+      if (s[2] <= s[0] && s[2] <= s[1]) {
+        P = nullptr;
+      } else if (s[1] <= s[0]) {
+        P = Py;
+        moved[i] = 2;
+      } else {
+        P = Px;
+        moved[i] = 1;
+      }
+      if (P) {
+        // S* = P S P^T: diagonal entries (P S P^T)_ii = s_j where P_ij = 1
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c)
+            if (P[3 * r + c] != 0.0) scales_out[3 * i + r] = s[c];
+        // R* = R P^T
+        double R[9], Rs[9];
+        quat_to_mat(q, R);
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += R[3 * r + k] * P[3 * c + k];  // (P^T)_kc = P_ck
+            Rs[3 * r + c] = acc;
+          }
+        mat_to_quat(Rs, quats_out + 4 * i);
+      }
+    } else if (!is3d && e > theta) {
+      types_out[i] = 1;
+    }
+  }
+  return 0;
+}
