@@ -196,6 +196,79 @@ def serving(rast, n_warm=200, n_meas=2000, rate=200.0, check=20):
             "max_abs_diff_batched_vs_plain": diff}
 
 
+def exchange_leg(scene_np, copies=8, replays=5):
+    """Adaptive Type Exchange, timed alone: the knot scene's own parameters
+    and a 16M-primitive set of the same scale distribution.  `copies`
+    launches, each on its own copy of the untouched parameters, are captured
+    in one graph (no host launch cost between them); the copies are restored
+    outside the events before each replay, so every launch performs the same
+    switches.  Algorithmic bytes: 13 read per primitive (scales, type), plus
+    1 written per switch, plus 44 more (rotation read and written, scales
+    written) per reparameterised one."""
+    import numpy as np
+    import torch
+    from paper_2512_02932_amd import _hgs
+    from paper_2512_02932_amd.rasterizer import get_rasterizer
+    rast = get_rasterizer(0)
+    res = {}
+    sets = {"knot1m": (scene_np["scales"], scene_np["rotations"], scene_np["types"])}
+    sets["16m"] = tuple(np.concatenate([a] * 16) for a in sets["knot1m"])
+    for name, (s, q, t) in sets.items():
+        S0, Q0, T0 = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (s, q, t))
+        n = S0.shape[0]
+        bufs = [(S0.clone(), Q0.clone(), T0.clone()) for _ in range(copies)]
+        counts = torch.zeros((copies, 2), dtype=torch.int32, device="cuda")
+
+        def launch_all():
+            st = torch.cuda.current_stream().cuda_stream
+            for j, (S, Q, T) in enumerate(bufs):
+                _hgs.hgs_type_exchange(rast.ctx, n, S.data_ptr(), Q.data_ptr(), T.data_ptr(), 2.05,
+                                       counts[j].data_ptr(), st)
+
+        def restore():
+            for S, Q, T in bufs:
+                S.copy_(S0); Q.copy_(Q0); T.copy_(T0)
+            counts.zero_()
+
+        restore()
+        launch_all()  # eager
+        torch.cuda.synchronize()
+        eager = [b[0].clone() for b in bufs[:1]]
+        sw = int(counts[0].sum())
+        moved = int(((bufs[0][0] != S0).any(1) | (bufs[0][1] != Q0).any(1)).sum())
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            restore()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            launch_all()
+        tot = 0.0
+        for _ in range(replays):
+            restore()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.replay()
+            e1.record()
+            e1.synchronize()
+            tot += e0.elapsed_time(e1)
+            assert int(counts[copies - 1].sum()) == sw and torch.equal(bufs[0][0], eager[0])
+        ms = tot / (replays * copies)
+        byt = 13 * n + sw + 44 * moved
+        gbs = byt / (ms * 1e-3) / 1e9
+        res[name] = {"n": n, "switched": sw, "reparameterised": moved, "ms": round(ms, 5),
+                     "roofline": {"bound": "hbm", "achieved": round(gbs, 1),
+                                  "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                                  "frac": round(gbs / (HBM_PEAK / 1e9), 4),
+                                  "kernel": "type_exchange_kernel<true>"}}
+        log(f"[exchange] {name}: {res[name]}")
+        del g, bufs, S0, Q0, T0, eager
+    torch.cuda.empty_cache()
+    return res
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +277,8 @@ def main():
     ap.add_argument("--workload", default="knot1m_1080p", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-exchange", action="store_true",
+                    help="skip the Adaptive Type Exchange kernel timing")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the served-view latency measurement")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -315,6 +390,8 @@ def main():
                    "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}},
         "roofline": roof,
     }
+    if not args.no_exchange:
+        out["type_exchange"] = exchange_leg(scene_np)
     if not args.no_serving:
         del sc, grads, images, G
         torch.cuda.empty_cache()

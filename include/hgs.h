@@ -211,6 +211,27 @@ enum {
 hgs_status hgs_profile_enable(hgs_ctx *ctx, int32_t on);
 hgs_status hgs_profile_read(hgs_ctx *ctx, double *ms, int64_t *calls, int32_t reset);
 
+/* Adaptive Type Exchange (Sec. 3.2, Eq. 3; appendix "Effective Rank and
+ * Type Switch"), in place on n primitives, enqueued on `stream`.
+ *   erank = exp(-sum_i p_i log p_i), p = q / |q|_1, q = (s_x^2, s_y^2, s_z^2),
+ *   evaluated in binary64 (all-zero scales give 0 and never switch).
+ *   A 3D primitive (type != 0) with erank < theta_e becomes 2D (type 0).
+ *   Before that its least significant scale is moved to z, with the
+ *   covariance unchanged: S* = P S P^T, R* = R P^T, P = P_x when s_x is the
+ *   least, P_y when s_y is (no change when s_z is a least; ties: z, then y).
+ *   The rotation is rewritten as q (x) quaternion(P^T), which has the length
+ *   of q.  A 2D primitive with erank > theta_e becomes 3D (type 1), all
+ *   parameters kept.  The paper uses theta_e = 2.05.
+ * scales f32[n,3] (activated), rotations f32[n,4] (wxyz, 16-byte aligned),
+ * types u8[n]: device, modified in place.  counts: device u32[2] or NULL;
+ * [0] += number switched 3D->2D, [1] += number switched 2D->3D.
+ * theta_e is binary64, the precision of the decision (2.05 has no binary32
+ * value).  Overlapping calls on the same arrays race.
+ * Errors: EINVAL (n < 0 or n > (2^31 - 1) * 256, NULL arrays with n > 0,
+ * misaligned rotations, non-finite theta_e), EHIP. */
+hgs_status hgs_type_exchange(hgs_ctx *ctx, int64_t n, float *scales, float *rotations,
+                             uint8_t *types, double theta_e, uint32_t *counts, void *stream);
+
 /* ---------------------------------------------------------------------
  * Batched serving.
  *

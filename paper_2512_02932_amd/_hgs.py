@@ -18,7 +18,7 @@ EXPORTS = ("hgs_create", "hgs_destroy", "hgs_scene_init", "hgs_scene_release", "
            "hgs_render_backward", "hgs_state_free", "hgs_state_sizes", "hgs_state_debug",
            "hgs_state_check", "hgs_last_error", "hgs_profile_enable", "hgs_profile_read",
            "hgs_server_create", "hgs_server_destroy", "hgs_server_submit", "hgs_server_poll",
-           "hgs_server_stats")
+           "hgs_server_stats", "hgs_type_exchange")
 
 STAGES = ("preprocess", "scan", "duplicate", "sort", "ranges", "raster_fwd", "raster_bwd",
           "preprocess_bwd", "fill", "depth_sort")
@@ -115,10 +115,12 @@ def load(path: str | None = None):
     lib.hgs_server_submit.argtypes = [P, C.POINTER(hgs_request)]
     lib.hgs_server_poll.argtypes = [P, C.POINTER(C.c_uint64), C.c_int32, C.POINTER(C.c_int32)]
     lib.hgs_server_stats.argtypes = [P, C.POINTER(C.c_int64)]
+    lib.hgs_type_exchange.argtypes = [P, C.c_int64, P, P, P, C.c_double, P, P]
     for name in ("hgs_create", "hgs_scene_init", "hgs_scene_release", "hgs_render",
                  "hgs_render_backward", "hgs_state_sizes", "hgs_state_debug", "hgs_state_check",
                  "hgs_profile_enable", "hgs_profile_read", "hgs_server_create",
-                 "hgs_server_submit", "hgs_server_poll", "hgs_server_stats"):
+                 "hgs_server_submit", "hgs_server_poll", "hgs_server_stats",
+                 "hgs_type_exchange"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -224,3 +226,10 @@ def hgs_server_stats(srv):
     st = (C.c_int64 * 6)()
     check(load().hgs_server_stats(srv, st))
     return tuple(int(x) for x in st)
+
+
+def hgs_type_exchange(ctx, n: int, scales_ptr: int, rots_ptr: int, types_ptr: int, theta: float,
+                      counts_ptr: int, stream: int):
+    check(load().hgs_type_exchange(ctx, int(n), C.c_void_p(scales_ptr), C.c_void_p(rots_ptr),
+                                   C.c_void_p(types_ptr), float(theta), C.c_void_p(counts_ptr),
+                                   C.c_void_p(stream)))

@@ -269,9 +269,12 @@ hgs_status hgs_create(int32_t device, hgs_ctx **out) {
   HGS_HIP(hipDeviceGetDefaultMemPool(&pool, device));
   uint64_t thr = UINT64_MAX;
   HGS_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+  int cus = 0;
+  HGS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
   hgs_ctx *c = new (std::nothrow) hgs_ctx();
   if (!c) return fail(HGS_ENOMEM, "host allocation failed");
   c->device = device;
+  c->n_cu = cus > 0 ? cus : 1;
   *out = c;
   return HGS_OK;
 }
@@ -681,6 +684,23 @@ hgs_status hgs_state_debug(hgs_ctx *ctx, hgs_state *st, int32_t what, void *dst,
   if (bytes > cap) return fail(HGS_EINVAL, "destination too small");
   HGS_HIP(hipStreamSynchronize(st->stream));
   if (bytes > 0) HGS_HIP(hipMemcpy(dst, src, (size_t)bytes, hipMemcpyDeviceToHost));
+  return HGS_OK;
+}
+
+hgs_status hgs_type_exchange(hgs_ctx *ctx, int64_t n, float *scales, float *rotations,
+                             uint8_t *types, double theta_e, uint32_t *counts, void *stream) {
+  if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(HGS_EINVAL, "n < 0");
+  if (n > (int64_t)INT32_MAX * 256) return fail(HGS_EINVAL, "n exceeds one launch (2^31 - 1 blocks of 256)");
+  if (n > 0 && (!scales || !rotations || !types))
+    return fail(HGS_EINVAL, "scales, rotations and types are required");
+  if (rotations && (reinterpret_cast<uintptr_t>(rotations) & 15u))
+    return fail(HGS_EINVAL, "rotations must be 16-byte aligned");
+  if (!std::isfinite(theta_e)) return fail(HGS_EINVAL, "theta_e must be finite");
+  HGS_HIP(hipSetDevice(ctx->device));
+  launch_type_exchange(n, scales, rotations, types, theta_e, counts, ctx->n_cu,
+                       (hipStream_t)stream);
+  HGS_HIP(hipGetLastError());
   return HGS_OK;
 }
 

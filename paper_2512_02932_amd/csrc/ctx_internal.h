@@ -62,6 +62,7 @@ bool make_dev_cam(const hgs_camera &c, DevCam &d, int view, std::string &why);
 
 struct hgs_ctx {
   int device = 0;
+  int n_cu = 1;  // compute units of `device`
   std::vector<hgs::Scene> scenes;
   bool profile = false;
   std::vector<hgs::StageEvent> pending;

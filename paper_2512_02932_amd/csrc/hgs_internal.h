@@ -180,4 +180,10 @@ void launch_raster_bwd(const uint2 *ranges, const uint32_t *vals, const Record *
                        DevOpts opt, const float *T_final, const uint32_t *last,
                        RasterGradIn g, float *accum, hipStream_t s);
 
+// Adaptive Type Exchange in place on n primitives (rotations: float4 per
+// primitive, 16-byte aligned).  counts (may be NULL): [0] += switched 3D->2D,
+// [1] += 2D->3D.  At most n_cu blocks.
+void launch_type_exchange(int64_t n, float *scales, float *rots, uint8_t *types, double theta,
+                          uint32_t *counts, int n_cu, hipStream_t s);
+
 }  // namespace hgs

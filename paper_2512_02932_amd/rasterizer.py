@@ -267,3 +267,23 @@ def pair_counts(state: State) -> dict:
     s2 = int((stopped & ((w >> 30) & 1)).sum())
     s3 = int(stopped.sum()) - s2
     return dict(blend_3d=b3, blend_2d=b2, fwd_3d=b3 + s3, fwd_2d=b2 + s2)
+
+
+def type_exchange(scales: torch.Tensor, rotations: torch.Tensor, types: torch.Tensor,
+                  theta_e: float = 2.05, counts: torch.Tensor | None = None):
+    """Adaptive Type Exchange in place (``hgs_type_exchange``): scales
+    float32 [N,3], rotations float32 [N,4] (wxyz), types uint8 [N], all on
+    one device.  ``counts`` (int32 [2] on that device) accumulates the number
+    of 3D->2D and 2D->3D switches; returns it."""
+    n = scales.shape[0]
+    for t, shp, dt in ((scales, (n, 3), torch.float32), (rotations, (n, 4), torch.float32),
+                       (types, (n,), torch.uint8)):
+        if tuple(t.shape) != shp or t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"expected {dt} {list(shp)} contiguous, got {t.dtype} {list(t.shape)}")
+    if counts is None:
+        counts = torch.zeros(2, dtype=torch.int32, device=scales.device)
+    rast = get_rasterizer(scales.device)
+    s = torch.cuda.current_stream(rast.device).cuda_stream
+    H.hgs_type_exchange(rast.ctx, n, _ptr(scales), _ptr(rotations), _ptr(types), theta_e,
+                        _ptr(counts), s)
+    return counts

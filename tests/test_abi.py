@@ -55,6 +55,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.hgs_state_check(None, None) == _hgs.HGS_EINVAL
     sizes = (C.c_int64 * 5)()
     assert lib.hgs_state_sizes(None, None, sizes) == _hgs.HGS_EINVAL
+    assert lib.hgs_type_exchange(None, 0, None, None, None, 2.05, None, None) == _hgs.HGS_EINVAL
     lib.hgs_state_free(None, None)  # no-op
     lib.hgs_destroy(None)           # no-op
 
