@@ -12,6 +12,7 @@ forward(scene, cams, pix, ...)         binary64 per-pixel composite (Eq. 1-2)
 backward(scene, cams, pix, G, ...)     binary64 gradients (dual numbers)
 sh_basis(degree, dirs)                 real SH basis used for colour
 erank(sx, sy, sz) / type_exchange(...)  Adaptive Type Exchange (Eq. 3, P_x/P_y)
+fdo.dwt / fdo.fdo_losses / fdo.fdo_project   Frequency-Decoupled Optimization (Alg. 1)
 surfel_uv(params, cam, pxy)            ray-plane (u, v, depth) of one surfel
 full_pixels(cams) / all outputs reshaped to images: render_images(...)
 """
@@ -261,3 +262,6 @@ def images(res, cam, n_views=1):
                 depth=o[..., 4:5].transpose(0, 3, 1, 2), normal=o[..., 5:8].transpose(0, 3, 1, 2),
                 T=res["T"].reshape(n_views, H, W), n_contrib=res["n_contrib"].reshape(n_views, H, W),
                 last=res["last"].reshape(n_views, H, W), tie=res["tie"].reshape(n_views, H, W))
+
+
+from . import fdo  # noqa: E402  (Frequency-Decoupled Optimization, binary64)
