@@ -206,7 +206,9 @@ enum {
   HGS_STAGE_PREPROCESS_BWD = 7,
   HGS_STAGE_FILL = 8,
   HGS_STAGE_DEPTH_SORT = 9,
-  HGS_N_STAGES = 10
+  HGS_STAGE_FDO_COTANGENTS = 10,
+  HGS_STAGE_FDO_PROJECT = 11,
+  HGS_N_STAGES = 12
 };
 hgs_status hgs_profile_enable(hgs_ctx *ctx, int32_t on);
 hgs_status hgs_profile_read(hgs_ctx *ctx, double *ms, int64_t *calls, int32_t reset);
@@ -231,6 +233,65 @@ hgs_status hgs_profile_read(hgs_ctx *ctx, double *ms, int64_t *calls, int32_t re
  * misaligned rotations, non-finite theta_e), EHIP. */
 hgs_status hgs_type_exchange(hgs_ctx *ctx, int64_t n, float *scales, float *rotations,
                              uint8_t *types, double theta_e, uint32_t *counts, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Frequency-Decoupled Optimization (Sec. 3.3, Alg. 1; appendices on the
+ * discrete wavelet transform and on gradient conflicts).
+ * ------------------------------------------------------------------- */
+
+/* Frequency losses of a rendered RGB image against a target and their
+ * weighted cotangents.  Level-1 Haar DWT (l = (1,1)/sqrt 2, h = (1,-1)/sqrt 2)
+ * of each [H, W] plane, zero-padded to even size: LL, LH (rows differ), HL
+ * (columns differ), HH.  L_low = mean over LL of (I^ - I)^2 in the band,
+ * L_high = the same mean for LH, HL and HH, summed.  Every band has
+ * n = n_views * 3 * ceil(H/2) * ceil(W/2) elements.
+ *   grad_low  = lambda_low  * dL_low  / dI^   [n_views, 3, H, W]
+ *   grad_high = lambda_high * dL_high / dI^   [n_views, 3, H, W]
+ *   losses[0] += L_low, losses[1] += L_high   (unweighted, binary64)
+ * The paper uses lambda_low = 0.2, lambda_high = 0.4.  render_rgb and
+ * target_rgb: device f32 [n_views, 3, H, W].  grad_low, grad_high: device,
+ * overwritten, either may be NULL.  losses: device double[2], 8-byte
+ * aligned, or NULL.  Errors: EINVAL (negative sizes, NULL images with a
+ * non-empty size, non-finite lambdas, misaligned losses), EHIP. */
+hgs_status hgs_fdo_cotangents(hgs_ctx *ctx, int32_t n_views, int32_t height, int32_t width,
+                              const float *render_rgb, const float *target_rgb, double lambda_low,
+                              double lambda_high, float *grad_low, float *grad_high,
+                              double *losses, void *stream);
+
+/* Alg. 1 for n primitives.  Inputs: the parameter gradients of the colour
+ * loss, the low-frequency loss and the high-frequency loss.  Each is an
+ * hgs_grads of device arrays shaped like hgs_scene_desc (sh with
+ * (sh_degree+1)^2 coefficients); a NULL array is zero.  g_i is the
+ * concatenation (means, scales, rotations, opacity, SH) of primitive i.
+ * If g_low . g_high < 0 (binary64 dot product), a 2D primitive (types[i]
+ * == 0) replaces g_high by its projection onto the normal of g_low (Eq. 9),
+ * and a 3D one replaces g_low by its projection onto the normal of g_high
+ * (Eq. 10).  The update g_color + g_low + g_high is written to `update`
+ * (update->accumulate != 0 adds; a NULL array there is not written).
+ * n_conflict: device u32, += number of conflicting primitives, or NULL.
+ * Errors: EINVAL (NULL structs, n < 0, sh_degree outside 0..3, NULL types
+ * with n > 0), EHIP. */
+hgs_status hgs_fdo_project(hgs_ctx *ctx, int64_t n, int32_t sh_degree, const uint8_t *types,
+                           const hgs_grads *g_color, const hgs_grads *g_low,
+                           const hgs_grads *g_high, const hgs_grads *update, uint32_t *n_conflict,
+                           void *stream);
+
+/* The backward of Alg. 1's three losses in one reverse traversal.  The
+ * cotangent sets are grad_color (all channels, like hgs_render_backward),
+ * grad_low_rgb and grad_high_rgb (device f32 [V,3,H,W] RGB cotangents,
+ * e.g. from hgs_fdo_cotangents; NULL = zero).  Each record is fetched and
+ * each pair's geometry and transmittance recomputed once for all three.
+ * The three parameter-gradient sets are formed per primitive, summed over
+ * the views, and combined by Alg. 1 (as hgs_fdo_project, with the scene's
+ * types) into `update`.  sets: NULL (workspace), or hgs_grads[3] whose
+ * arrays receive g_color, g_low, g_high before the projection
+ * (overwritten; every array required).  n_conflict as in
+ * hgs_fdo_project.  The scene's parameters must be unchanged since the
+ * forward.  Errors: EINVAL, ESTATE, ENOMEM, EHIP. */
+hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *state,
+                                   const hgs_grad_images *grad_color, const float *grad_low_rgb,
+                                   const float *grad_high_rgb, const hgs_grads *update,
+                                   const hgs_grads *sets, uint32_t *n_conflict, void *stream);
 
 /* ---------------------------------------------------------------------
  * Batched serving.

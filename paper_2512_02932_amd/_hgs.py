@@ -18,10 +18,11 @@ EXPORTS = ("hgs_create", "hgs_destroy", "hgs_scene_init", "hgs_scene_release", "
            "hgs_render_backward", "hgs_state_free", "hgs_state_sizes", "hgs_state_debug",
            "hgs_state_check", "hgs_last_error", "hgs_profile_enable", "hgs_profile_read",
            "hgs_server_create", "hgs_server_destroy", "hgs_server_submit", "hgs_server_poll",
-           "hgs_server_stats", "hgs_type_exchange")
+           "hgs_server_stats", "hgs_type_exchange", "hgs_fdo_cotangents", "hgs_fdo_project",
+           "hgs_render_backward_fdo")
 
 STAGES = ("preprocess", "scan", "duplicate", "sort", "ranges", "raster_fwd", "raster_bwd",
-          "preprocess_bwd", "fill", "depth_sort")
+          "preprocess_bwd", "fill", "depth_sort", "fdo_cotangents", "fdo_project")
 
 
 class hgs_scene_desc(C.Structure):
@@ -116,11 +117,19 @@ def load(path: str | None = None):
     lib.hgs_server_poll.argtypes = [P, C.POINTER(C.c_uint64), C.c_int32, C.POINTER(C.c_int32)]
     lib.hgs_server_stats.argtypes = [P, C.POINTER(C.c_int64)]
     lib.hgs_type_exchange.argtypes = [P, C.c_int64, P, P, P, C.c_double, P, P]
+    lib.hgs_fdo_cotangents.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_double,
+                                       C.c_double, P, P, P, P]
+    lib.hgs_fdo_project.argtypes = [P, C.c_int64, C.c_int32, P, C.POINTER(hgs_grads),
+                                    C.POINTER(hgs_grads), C.POINTER(hgs_grads),
+                                    C.POINTER(hgs_grads), P, P]
+    lib.hgs_render_backward_fdo.argtypes = [P, P, C.POINTER(hgs_grad_images), P, P,
+                                            C.POINTER(hgs_grads), P, P, P]
     for name in ("hgs_create", "hgs_scene_init", "hgs_scene_release", "hgs_render",
                  "hgs_render_backward", "hgs_state_sizes", "hgs_state_debug", "hgs_state_check",
                  "hgs_profile_enable", "hgs_profile_read", "hgs_server_create",
                  "hgs_server_submit", "hgs_server_poll", "hgs_server_stats",
-                 "hgs_type_exchange"):
+                 "hgs_type_exchange", "hgs_fdo_cotangents", "hgs_fdo_project",
+                 "hgs_render_backward_fdo"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -233,3 +242,28 @@ def hgs_type_exchange(ctx, n: int, scales_ptr: int, rots_ptr: int, types_ptr: in
     check(load().hgs_type_exchange(ctx, int(n), C.c_void_p(scales_ptr), C.c_void_p(rots_ptr),
                                    C.c_void_p(types_ptr), float(theta), C.c_void_p(counts_ptr),
                                    C.c_void_p(stream)))
+
+
+def hgs_fdo_cotangents(ctx, V: int, H: int, W: int, ren_ptr: int, tgt_ptr: int, lambda_low: float,
+                       lambda_high: float, glow_ptr: int, ghigh_ptr: int, losses_ptr: int,
+                       stream: int):
+    check(load().hgs_fdo_cotangents(ctx, int(V), int(H), int(W), C.c_void_p(ren_ptr),
+                                    C.c_void_p(tgt_ptr), float(lambda_low), float(lambda_high),
+                                    C.c_void_p(glow_ptr), C.c_void_p(ghigh_ptr),
+                                    C.c_void_p(losses_ptr), C.c_void_p(stream)))
+
+
+def hgs_fdo_project(ctx, n: int, sh_degree: int, types_ptr: int, gc, gl, gh, update,
+                    conflict_ptr: int, stream: int):
+    check(load().hgs_fdo_project(ctx, int(n), int(sh_degree), C.c_void_p(types_ptr), C.byref(gc),
+                                 C.byref(gl), C.byref(gh), C.byref(update),
+                                 C.c_void_p(conflict_ptr), C.c_void_p(stream)))
+
+
+def hgs_render_backward_fdo(ctx, state, grad_images, glow_ptr: int, ghigh_ptr: int, update, sets,
+                            conflict_ptr: int, stream: int):
+    """`sets` is None or a ctypes array of three hgs_grads."""
+    check(load().hgs_render_backward_fdo(ctx, state, C.byref(grad_images), C.c_void_p(glow_ptr),
+                                         C.c_void_p(ghigh_ptr), C.byref(update),
+                                         None if sets is None else C.cast(sets, C.c_void_p),
+                                         C.c_void_p(conflict_ptr), C.c_void_p(stream)))

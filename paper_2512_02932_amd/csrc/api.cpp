@@ -549,6 +549,18 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   return HGS_OK;
 }
 
+// Orders `waiter` after the work enqueued so far on `signaler`.
+hipError_t join_streams(hipStream_t waiter, hipStream_t signaler) {
+  if (waiter == signaler) return hipSuccess;
+  hipEvent_t ev;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(ev, signaler);
+  if (e == hipSuccess) e = hipStreamWaitEvent(waiter, ev, 0);
+  const hipError_t e2 = hipEventDestroy(ev);
+  return e != hipSuccess ? e : e2;
+}
+
 hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_images *gout,
                                const hgs_grads *grads, void *stream) {
   if (!ctx || !st) return fail(HGS_EINVAL, "ctx or state is NULL");
@@ -599,6 +611,142 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_image
     HGS_HIP(hipStreamWaitEvent(st->stream, ev, 0));
     HGS_HIP(hipEventDestroy(ev));
   }
+  return HGS_OK;
+}
+
+hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *st, const hgs_grad_images *gcolor,
+                                   const float *grad_low_rgb, const float *grad_high_rgb,
+                                   const hgs_grads *update, const hgs_grads *sets,
+                                   uint32_t *n_conflict, void *stream) {
+  if (!ctx || !st) return fail(HGS_EINVAL, "ctx or state is NULL");
+  if (!update) return fail(HGS_EINVAL, "update is NULL");
+  if (st->device != ctx->device) return fail(HGS_ESTATE, "state belongs to another context");
+  if (!st->ws) return fail(HGS_ESTATE, "state has no workspace");
+  if (sets) {
+    for (int k = 0; k < 3; ++k)
+      if (!sets[k].means || !sets[k].scales || !sets[k].rotations || !sets[k].opacities ||
+          !sets[k].sh)
+        return fail(HGS_EINVAL, "every array of the three gradient sets is required");
+  }
+  HGS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  HGS_HIP(join_streams(s, st->stream));
+  const int64_t N = st->N;
+  const int64_t VN = (int64_t)st->V * N;
+  const int64_t plane = std::max<int64_t>(VN, 1) * kGradSlots;
+  const int K = (st->scene.sh_degree + 1) * (st->scene.sh_degree + 1);
+  float *accum = nullptr;
+  HGS_HIP(dalloc_t(st, &accum, (size_t)(3 * plane)));
+  // the three parameter-gradient sets: the caller's arrays or workspace
+  float *own[3][5] = {};
+  const size_t cnt[5] = {(size_t)(3 * N), (size_t)(3 * N), (size_t)(4 * N), (size_t)N,
+                         (size_t)(3 * K * N)};
+  if (!sets)
+    for (int k = 0; k < 3; ++k)
+      for (int j = 0; j < 5; ++j) HGS_HIP(dalloc_t(st, &own[k][j], std::max<size_t>(cnt[j], 1)));
+  HGS_HIP(commit(st, 2, s));
+  float *gs[3][5];
+  for (int k = 0; k < 3; ++k) {
+    if (sets) {
+      gs[k][0] = sets[k].means;
+      gs[k][1] = sets[k].scales;
+      gs[k][2] = sets[k].rotations;
+      gs[k][3] = sets[k].opacities;
+      gs[k][4] = sets[k].sh;
+    } else {
+      for (int j = 0; j < 5; ++j) gs[k][j] = own[k][j];
+    }
+  }
+  {
+    StageTimer t(ctx, HGS_STAGE_FILL, s);
+    launch_fill_f32(accum, 0.0f, 3 * plane, s);
+  }
+  RasterGradIn gi{};
+  if (gcolor) {
+    gi.rgb = gcolor->rgb;
+    gi.alpha = gcolor->alpha;
+    gi.depth = gcolor->depth;
+    gi.normal = gcolor->normal;
+  }
+  RgbSets x{};
+  x.rgb[0] = grad_low_rgb;
+  x.rgb[1] = grad_high_rgb;
+  {
+    StageTimer t(ctx, HGS_STAGE_RASTER_BWD, s);
+    launch_raster_bwd_sets(st->ranges, st->vals, st->rec, st->n_tiles, st->W, st->H, st->tiles_x,
+                           st->tiles_per_view, st->opt, st->T_final, st->last, gi, x, accum, plane,
+                           s);
+  }
+  {
+    StageTimer t(ctx, HGS_STAGE_PREPROCESS_BWD, s);
+    for (int k = 0; k < 3; ++k)
+      launch_preprocess_bwd(st->scene, st->cams, st->V, st->opt, st->flags, st->rect,
+                            accum + k * plane, gs[k][0], gs[k][1], gs[k][2], gs[k][3], gs[k][4], 0,
+                            s);
+  }
+  {
+    StageTimer t(ctx, HGS_STAGE_FDO_PROJECT, s);
+    float *const out[5] = {update->means, update->scales, update->rotations, update->opacities,
+                           update->sh};
+    launch_fdo_project(N, K, st->scene.types, gs[0], gs[1], gs[2], out, update->accumulate,
+                       n_conflict, ctx->n_cu, s);
+  }
+  HGS_HIP(hipGetLastError());
+  HGS_HIP(join_streams(st->stream, s));
+  return HGS_OK;
+}
+
+hgs_status hgs_fdo_cotangents(hgs_ctx *ctx, int32_t n_views, int32_t height, int32_t width,
+                              const float *render_rgb, const float *target_rgb, double lambda_low,
+                              double lambda_high, float *grad_low, float *grad_high,
+                              double *losses, void *stream) {
+  if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
+  if (n_views < 0 || height < 0 || width < 0) return fail(HGS_EINVAL, "negative size");
+  const int64_t planes = (int64_t)n_views * 3;
+  if (planes * height * width > 0 && (!render_rgb || !target_rgb))
+    return fail(HGS_EINVAL, "render_rgb and target_rgb are required");
+  if (!std::isfinite(lambda_low) || !std::isfinite(lambda_high))
+    return fail(HGS_EINVAL, "lambda_low and lambda_high must be finite");
+  if (losses && (reinterpret_cast<uintptr_t>(losses) & 7u))
+    return fail(HGS_EINVAL, "losses must be 8-byte aligned");
+  HGS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  StageTimer t(ctx, HGS_STAGE_FDO_COTANGENTS, s);
+  launch_fdo_cotangents(planes, height, width, render_rgb, target_rgb, lambda_low, lambda_high,
+                        grad_low, grad_high, losses, ctx->n_cu, s);
+  HGS_HIP(hipGetLastError());
+  return HGS_OK;
+}
+
+hgs_status hgs_fdo_project(hgs_ctx *ctx, int64_t n, int32_t sh_degree, const uint8_t *types,
+                           const hgs_grads *g_color, const hgs_grads *g_low,
+                           const hgs_grads *g_high, const hgs_grads *update, uint32_t *n_conflict,
+                           void *stream) {
+  if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(HGS_EINVAL, "n < 0");
+  if (sh_degree < 0 || sh_degree > 3) return fail(HGS_EINVAL, "sh_degree must be 0..3");
+  if (!g_color || !g_low || !g_high || !update)
+    return fail(HGS_EINVAL, "g_color, g_low, g_high and update are required");
+  if (n > 0 && !types) return fail(HGS_EINVAL, "types is required");
+  HGS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  auto arr = [](const hgs_grads *g, const float **p) {
+    p[0] = g->means;
+    p[1] = g->scales;
+    p[2] = g->rotations;
+    p[3] = g->opacities;
+    p[4] = g->sh;
+  };
+  const float *c[5], *l[5], *h[5];
+  arr(g_color, c);
+  arr(g_low, l);
+  arr(g_high, h);
+  float *const out[5] = {update->means, update->scales, update->rotations, update->opacities,
+                         update->sh};
+  StageTimer t(ctx, HGS_STAGE_FDO_PROJECT, s);
+  launch_fdo_project(n, (sh_degree + 1) * (sh_degree + 1), types, c, l, h, out,
+                     update->accumulate, n_conflict, ctx->n_cu, s);
+  HGS_HIP(hipGetLastError());
   return HGS_OK;
 }
 

@@ -179,11 +179,36 @@ void launch_raster_bwd(const uint2 *ranges, const uint32_t *vals, const Record *
                        int n_tiles_total, int W, int H, int tiles_x, int tiles_per_view,
                        DevOpts opt, const float *T_final, const uint32_t *last,
                        RasterGradIn g, float *accum, hipStream_t s);
+// Two RGB-only cotangent images [V,3,H,W] (NULL = zero).
+struct RgbSets {
+  const float *rgb[2];
+};
+// The backward with three cotangent sets in one traversal: g (all channels)
+// into accum, rgb2.rgb[k] into accum + (k + 1) * plane (floats).
+void launch_raster_bwd_sets(const uint2 *ranges, const uint32_t *vals, const Record *rec,
+                            int n_tiles_total, int W, int H, int tiles_x, int tiles_per_view,
+                            DevOpts opt, const float *T_final, const uint32_t *last,
+                            RasterGradIn g, RgbSets rgb2, float *accum, int64_t plane,
+                            hipStream_t s);
 
 // Adaptive Type Exchange in place on n primitives (rotations: float4 per
 // primitive, 16-byte aligned).  counts (may be NULL): [0] += switched 3D->2D,
 // [1] += 2D->3D.  At most n_cu blocks.
 void launch_type_exchange(int64_t n, float *scales, float *rots, uint8_t *types, double theta,
                           uint32_t *counts, int n_cu, hipStream_t s);
+
+// Frequency losses of ren against tgt ([planes, H, W], planes = V * 3):
+// weighted cotangents into g_low / g_high (either may be NULL) and, if
+// losses != NULL, losses[0] += L_low, losses[1] += L_high (double, device).
+// At most n_cu blocks.
+void launch_fdo_cotangents(int64_t planes, int H, int W, const float *ren, const float *tgt,
+                           double lambda_low, double lambda_high, float *g_low, float *g_high,
+                           double *losses, int n_cu, hipStream_t s);
+// Alg. 1 per primitive.  gc, gl, gh, out: 5 pointers each (means, scales,
+// rotations, opacities, SH with sh_coeffs coefficients; NULL = zero / not
+// written).  n_conflict (may be NULL) += number of conflicting primitives.
+void launch_fdo_project(int64_t n, int sh_coeffs, const uint8_t *types, const float *const *gc,
+                        const float *const *gl, const float *const *gh, float *const *out,
+                        int accumulate, uint32_t *n_conflict, int n_cu, hipStream_t s);
 
 }  // namespace hgs

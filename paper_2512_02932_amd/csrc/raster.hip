@@ -385,12 +385,62 @@ __device__ __forceinline__ float wave_reduce_scatter16(const float (&g)[16], int
   return x;
 }
 
+// Gradients of one RGB-only cotangent set (FDO's low / high frequency
+// cotangents) for an active pair, into the 16 slots of the main set's layout:
+// the colour, alpha_eff and record-geometry slots; depth and normal slots
+// stay 0.  S is that set's suffix, advanced here.
+__device__ __forceinline__ void rgb_set_grads(float (&g)[16], float cr, float cg, float cb,
+                                              float &S, const PairEval &p, bool is3d, float a,
+                                              bool clamped, float Ti, float wg, float G,
+                                              const float4 &r1, const float4 &r2,
+                                              const float4 &r3) {
+  const float f = cr * r3.y + cg * r3.z + cb * r3.w;
+  const float dfa = f - S;
+  const float ga = Ti * dfa;
+  S = __builtin_fmaf(a, dfa, S);
+  g[10] = wg * cr;
+  g[11] = wg * cg;
+  g[12] = wg * cb;
+  g[13] = g[14] = g[15] = 0.0f;
+  const float ge = clamped ? 0.0f : -ga * a * kLn2;
+  g[9] = clamped ? 0.0f : ga * G;
+  if (is3d) {
+    const float dx = p.a0, dy = p.a1;
+    g[0] = -ge * (2.0f * r1.z * dx + r1.w * dy);
+    g[1] = -ge * (r1.w * dx + 2.0f * r2.x * dy);
+    g[2] = ge * dx * dx;
+    g[3] = ge * dx * dy;
+    g[4] = ge * dy * dy;
+    g[5] = g[6] = g[7] = g[8] = 0.0f;
+  } else {
+    const float rw = p.rw;
+    const float rw2 = rw * rw;
+    const float gU = ge * 2.0f * p.a0 * rw2;
+    const float gV = ge * 2.0f * p.a1 * rw2;
+    const float gW = -2.0f * ge * p.e * rw;
+    g[0] = gU * p.xr;
+    g[1] = gU * p.yr;
+    g[2] = gU;
+    g[3] = gV * p.xr;
+    g[4] = gV * p.yr;
+    g[5] = gV;
+    g[6] = gW * p.xr;
+    g[7] = gW * p.yr;
+    g[8] = gW;
+  }
+}
+
+// NS = 1: one cotangent set.  NS = 3: the main set plus two RGB-only sets
+// (rgb2[0], rgb2[1]) in the same reverse traversal -- one record fetch,
+// one geometry and transmittance recomputation per pair -- accumulated into
+// planes accum, accum + plane, accum + 2 plane.
+template <int NS>
 __global__ void __launch_bounds__(kWave)
 raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
                   const Record *__restrict__ rec, int n_tiles, int W, int H, int tiles_x,
                   int tiles_per_view, DevOpts opt, const float *__restrict__ T_final,
-                  const uint32_t *__restrict__ last_in, RasterGradIn gin,
-                  float *__restrict__ accum) {
+                  const uint32_t *__restrict__ last_in, RasterGradIn gin, RgbSets rgb2,
+                  float *__restrict__ accum, int64_t plane) {
   __shared__ float4 srec[5][kWave];
   __shared__ uint32_t sid[kWave];
   __shared__ uint32_t spos[kWave];
@@ -402,6 +452,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   float T = 1.0f;
   uint32_t L = 0;
   float Gr = 0, Gg = 0, Gb = 0, Ga = 0, Gd = 0, Gnx = 0, Gny = 0, Gnz = 0;
+  float Xr[2] = {0.0f, 0.0f}, Xg[2] = {0.0f, 0.0f}, Xb[2] = {0.0f, 0.0f};
   if (q.inside) {
     const int64_t hw = (int64_t)H * W;
     const int64_t pix = (int64_t)q.py * W + q.px;
@@ -421,9 +472,24 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
       Gny = gin.normal[o3 + hw];
       Gnz = gin.normal[o3 + 2 * hw];
     }
+    if constexpr (NS == 3) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (rgb2.rgb[k]) {
+          Xr[k] = rgb2.rgb[k][o3];
+          Xg[k] = rgb2.rgb[k][o3 + hw];
+          Xb[k] = rgb2.rgb[k][o3 + 2 * hw];
+        }
+      }
+    }
   }
   // suffix value beyond the last blended pair: background and alpha terms
   float S = Gr * opt.bg[0] + Gg * opt.bg[1] + Gb * opt.bg[2] - Ga;
+  float XS[2] = {0.0f, 0.0f};
+  if constexpr (NS == 3) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) XS[k] = Xr[k] * opt.bg[0] + Xg[k] * opt.bg[1] + Xb[k] * opt.bg[2];
+  }
 
   uint32_t wmax = L;
 #pragma unroll
@@ -478,17 +544,16 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
       float g[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) g[j] = 0.0f;
+      const float a = fminf(raw, kAlphaMax);
+      const bool clamped = raw > kAlphaMax;
+      const float Ti = T * __builtin_amdgcn_rcpf(1.0f - a);
+      const float wg = a * Ti;
       if (act) {
-        const float a = fminf(raw, kAlphaMax);
-        const bool clamped = raw > kAlphaMax;
-        const float Ti = T * __builtin_amdgcn_rcpf(1.0f - a);
         const float f = Gr * r3.y + Gg * r3.z + Gb * r3.w + Gd * p.depth + Gnx * r4.x +
                         Gny * r4.y + Gnz * r4.z;
         const float dfa = f - S;
         const float ga = Ti * dfa;  // dL/d alpha~
         S = __builtin_fmaf(a, dfa, S);
-        const float wg = a * Ti;
-        T = Ti;
         g[10] = wg * Gr;
         g[11] = wg * Gg;
         g[12] = wg * Gb;
@@ -525,6 +590,21 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
       const float tot = wave_reduce_scatter16(g, lane);
       if ((lane & 3) == 0 && tot != 0.0f)
         unsafeAtomicAdd(accum + (size_t)sid[k] * kGradSlots + vidx, tot);
+      if constexpr (NS == 3) {
+#pragma unroll
+        for (int set = 0; set < 2; ++set) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) g[j] = 0.0f;
+          if (act)
+            rgb_set_grads(g, Xr[set], Xg[set], Xb[set], XS[set], p, is3d, a, clamped, Ti, wg, G,
+                          r1, r2, r3);
+          const float t2 = wave_reduce_scatter16(g, lane);
+          if ((lane & 3) == 0 && t2 != 0.0f)
+            unsafeAtomicAdd(accum + (size_t)(set + 1) * plane + (size_t)sid[k] * kGradSlots + vidx,
+                            t2);
+        }
+      }
+      if (act) T = Ti;
     }
   }
 }
@@ -557,9 +637,20 @@ void launch_raster_bwd(const uint2 *ranges, const uint32_t *vals, const Record *
                        DevOpts opt, const float *T_final, const uint32_t *last, RasterGradIn g,
                        float *accum, hipStream_t s) {
   if (n_tiles_total == 0) return;
-  hipLaunchKernelGGL(raster_bwd_kernel, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
+  hipLaunchKernelGGL(raster_bwd_kernel<1>, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
                      ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
-                     T_final, last, g, accum);
+                     T_final, last, g, RgbSets{}, accum, (int64_t)0);
+}
+
+void launch_raster_bwd_sets(const uint2 *ranges, const uint32_t *vals, const Record *rec,
+                            int n_tiles_total, int W, int H, int tiles_x, int tiles_per_view,
+                            DevOpts opt, const float *T_final, const uint32_t *last,
+                            RasterGradIn g, RgbSets rgb2, float *accum, int64_t plane,
+                            hipStream_t s) {
+  if (n_tiles_total <= 0) return;
+  hipLaunchKernelGGL(raster_bwd_kernel<3>, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
+                     ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
+                     T_final, last, g, rgb2, accum, plane);
 }
 
 }  // namespace hgs

@@ -196,6 +196,40 @@ class Rasterizer:
         s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         H.hgs_render_backward(self.ctx, state.handle, gi, g, s)
 
+    def backward_fdo(self, state: State, grad_color: dict, grad_low_rgb, grad_high_rgb,
+                     update: dict, sets=None, accumulate=False, n_conflict=None, stream=None):
+        """Alg. 1's backward (``hgs_render_backward_fdo``): three cotangent
+        sets in one traversal, projected per primitive into `update`.
+        `sets`: None or a list of three gradient dicts that receive g_color,
+        g_low and g_high before the projection."""
+        gi = H.hgs_grad_images()
+        for k in ("rgb", "alpha", "depth", "normal"):
+            t = grad_color.get(k)
+            if t is not None and not t.is_contiguous():
+                raise ValueError(f"grad image {k!r} must be contiguous")
+            setattr(gi, k, _ptr(t))
+        for t in (grad_low_rgb, grad_high_rgb):
+            if t is not None and not t.is_contiguous():
+                raise ValueError("frequency cotangents must be contiguous")
+        u = _grads(update, accumulate)
+        arr = None
+        if sets is not None:
+            arr = (H.hgs_grads * 3)(*[_grads(d, False) for d in sets])
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        H.hgs_render_backward_fdo(self.ctx, state.handle, gi, _ptr(grad_low_rgb),
+                                  _ptr(grad_high_rgb), u, arr, _ptr(n_conflict), s)
+
+
+def _grads(d: dict, accumulate: bool) -> H.hgs_grads:
+    g = H.hgs_grads()
+    for k in ("means", "scales", "rotations", "opacities", "sh"):
+        t = d.get(k)
+        if t is not None and (not t.is_contiguous() or t.dtype != torch.float32):
+            raise ValueError(f"gradient {k!r} must be contiguous float32")
+        setattr(g, k, _ptr(t))
+    g.accumulate = 1 if accumulate else 0
+    return g
+
 
 _RASTERIZERS: dict[int, Rasterizer] = {}
 
@@ -287,3 +321,41 @@ def type_exchange(scales: torch.Tensor, rotations: torch.Tensor, types: torch.Te
     H.hgs_type_exchange(rast.ctx, n, _ptr(scales), _ptr(rotations), _ptr(types), theta_e,
                         _ptr(counts), s)
     return counts
+
+
+def fdo_cotangents(render_rgb: torch.Tensor, target_rgb: torch.Tensor, lambda_low: float = 0.2,
+                   lambda_high: float = 0.4, losses: torch.Tensor | None = None):
+    """Frequency losses and weighted cotangents (``hgs_fdo_cotangents``).
+    render_rgb, target_rgb: float32 [V, 3, H, W] on one device.  Returns
+    (grad_low, grad_high, losses) with losses a float64 [2] device tensor
+    (L_low, L_high) that the call adds into."""
+    if render_rgb.shape != target_rgb.shape or render_rgb.dim() != 4 or render_rgb.shape[1] != 3:
+        raise ValueError("render_rgb and target_rgb must both be [V, 3, H, W]")
+    for t in (render_rgb, target_rgb):
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("images must be contiguous float32")
+    V, _, Hh, Ww = render_rgb.shape
+    g_low = torch.empty_like(render_rgb)
+    g_high = torch.empty_like(render_rgb)
+    if losses is None:
+        losses = torch.zeros(2, dtype=torch.float64, device=render_rgb.device)
+    rast = get_rasterizer(render_rgb.device)
+    s = torch.cuda.current_stream(rast.device).cuda_stream
+    H.hgs_fdo_cotangents(rast.ctx, V, Hh, Ww, _ptr(render_rgb), _ptr(target_rgb), lambda_low,
+                         lambda_high, _ptr(g_low), _ptr(g_high), _ptr(losses), s)
+    return g_low, g_high, losses
+
+
+def fdo_project(types: torch.Tensor, sh_degree: int, g_color: dict, g_low: dict, g_high: dict,
+                update: dict | None = None, accumulate=False, n_conflict=None):
+    """Alg. 1 on three parameter-gradient dicts (``hgs_fdo_project``); returns
+    the update dict (allocated like g_color when not given)."""
+    n = types.shape[0]
+    if update is None:
+        update = {k: torch.empty_like(v) for k, v in g_color.items()}
+    rast = get_rasterizer(types.device)
+    s = torch.cuda.current_stream(rast.device).cuda_stream
+    H.hgs_fdo_project(rast.ctx, n, sh_degree, _ptr(types), _grads(g_color, False),
+                      _grads(g_low, False), _grads(g_high, False), _grads(update, accumulate),
+                      _ptr(n_conflict), s)
+    return update
