@@ -29,6 +29,11 @@ sys.path.insert(0, ROOT)
 # counts as 4 issue slots), used for the raster kernels' ALU roofline.
 OPS_FWD = {"3d": 27, "2d": 34}
 OPS_BWD = {"3d": 71, "2d": 82}
+# Each RGB-only cotangent set of the three-set backward adds per blended pair
+# its colour dot product, suffix and dL/d alpha~ (6), colour and alpha_eff
+# slots (6), the record-geometry chain (12 for 3D, 15 for 2D) and its
+# accumulating adds (9 for 3D, 13 for 2D).
+OPS_BWD_RGB = {"3d": 33, "2d": 40}
 # VALU issue peak with packed FP32 disabled: 256 CU x 64 lanes x 2.4 GHz.
 VALU_PEAK = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12
@@ -280,6 +285,81 @@ def exchange_leg(scene_np, workload, copies=8, replays=5):
     torch.cuda.empty_cache()
     return res
 
+def fdo_leg(rast, sc, cam, images, G, counts, N, K, steps, warmup, workload):
+    """Frequency-Decoupled Optimization step on the headline workload:
+    render (with state), Haar cotangents of the rendered RGB against a
+    fixed synthetic target (the render of the step plus N(0, 0.05) noise,
+    clipped), the three-set backward (colour cotangents = the headline's
+    N(0,1) cotangents) and Alg. 1's projection into one update."""
+    import numpy as np
+    import torch
+    from paper_2512_02932_amd import _hgs
+    from paper_2512_02932_amd.rasterizer import fdo_cotangents
+    H, W = cam["height"], cam["width"]
+    _, st = rast.render(sc, cam, images=images, want_state=True)
+    st.free()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    target = torch.from_numpy(np.clip(images["rgb"].cpu().numpy() +
+                                      rng.normal(0.0, 0.05, (1, 3, H, W)), 0.0, 1.0)
+                              .astype(np.float32)).cuda()
+    upd = {k: torch.empty_like(sc[k]) for k in ("means", "scales", "rotations", "opacities", "sh")}
+    losses = torch.zeros(2, dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def step():
+        _, state = rast.render(sc, cam, images=images, want_state=True)
+        gl, gh, _ = fdo_cotangents(images["rgb"], target, 0.2, 0.4, losses=losses)
+        rast.backward_fdo(state, G, gl, gh, upd, n_conflict=cnt)
+        state.free()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    cnt.zero_()
+    _hgs.hgs_profile_enable(rast.ctx, True)
+    _hgs.hgs_profile_read(rast.ctx, reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = _hgs.hgs_profile_read(rast.ctx, reset=True)
+    _hgs.hgs_profile_enable(rast.ctx, False)
+    ms = (t1 - t0) * 1e3 / steps
+    stage = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
+    P = 11 + 3 * K
+    cot_bytes = 3 * H * W * 16
+    proj_bytes = N * (3 * 4 * P + 1 + 4 * P)
+    ops = (counts["blend_3d"] * (OPS_BWD["3d"] + 2 * OPS_BWD_RGB["3d"]) +
+           counts["blend_2d"] * (OPS_BWD["2d"] + 2 * OPS_BWD_RGB["2d"]))
+
+    def hbm(kernel, byt, ms_k, key):
+        gbs = byt / (ms_k * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": round(gbs / (HBM_PEAK / 1e9), 4),
+                "traffic": measured_traffic(key, workload), "kernel": kernel}
+
+    tops = ops / (stage["raster_bwd"] * 1e-3) / 1e12
+    out = {"ms_per_step": round(ms, 4), "mpix_per_s": round(H * W / (ms * 1e-3) / 1e6, 3),
+           "conflicts_per_step": int(cnt.item()) // steps, "gaussians": N,
+           "losses_last": [float(x) / (steps + warmup) for x in losses.cpu().tolist()],
+           "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+           "preprocess_bwd_launches_per_step": 3,
+           "roofline": {
+               "raster_bwd_3set": {"bound": "alu", "achieved": round(tops, 4),
+                                   "peak": round(VALU_PEAK / 1e12, 4), "unit": "Tops/s",
+                                   "frac": round(tops / (VALU_PEAK / 1e12), 4),
+                                   "traffic": measured_traffic("raster_bwd_kernel<3>", workload),
+                                   "kernel": "raster_bwd_kernel<3>"},
+               "fdo_cotangents": hbm("fdo_cotangents_kernel", cot_bytes, stage["fdo_cotangents"],
+                                     "fdo_cotangents_kernel"),
+               "fdo_project": hbm("fdo_project_kernel<16>", proj_bytes, stage["fdo_project"],
+                                  "fdo_project_kernel<16>")}}
+    log(f"[fdo] {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,6 +368,8 @@ def main():
     ap.add_argument("--workload", default="knot1m_1080p", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rows", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fdo", action="store_true",
+                    help="skip the Frequency-Decoupled Optimization step timing")
     ap.add_argument("--no-exchange", action="store_true",
                     help="skip the Adaptive Type Exchange kernel timing")
     ap.add_argument("--no-serving", action="store_true",
@@ -365,21 +447,21 @@ def main():
     ms = (t1 - t0) * 1e3 / args.steps
     P = H * W
     value = P / (ms * 1e-3) / 1e6
-    stage_ms = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+    stage_ms = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
     log("[bench] per-launch ms: " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
     log(f"[bench] counts {counts} D={sizes['D']}")
 
     # dominant kernel (the stages are single kernels except scan/sort/ranges)
     dom = max(("raster_fwd", "raster_bwd", "preprocess", "preprocess_bwd"), key=lambda k: stage_ms[k])
     if dom in ("raster_fwd", "raster_bwd"):
+        kname = "raster_fwd_kernel" if dom == "raster_fwd" else "raster_bwd_kernel<1>"
         ops = OPS_FWD if dom == "raster_fwd" else OPS_BWD
         key = "fwd" if dom == "raster_fwd" else "blend"
         work = counts[f"{key}_3d"] * ops["3d"] + counts[f"{key}_2d"] * ops["2d"]
         achieved = work / (stage_ms[dom] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK / 1e12, 4),
                 "unit": "Tops/s", "frac": round(achieved / (VALU_PEAK / 1e12), 4),
-                "traffic": measured_traffic(f"{dom}_kernel", args.workload),
-                "kernel": f"{dom}_kernel"}
+                "traffic": measured_traffic(kname, args.workload), "kernel": kname}
     else:
         N = scene_np["means"].shape[0]
         K = scene_np["sh"].shape[1]
@@ -401,6 +483,9 @@ def main():
                    "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}},
         "roofline": roof,
     }
+    if not args.no_fdo:
+        out["fdo"] = fdo_leg(rast, sc, cam, images, G, counts, int(scene_np["means"].shape[0]),
+                             int(scene_np["sh"].shape[1]), args.steps, args.warmup, args.workload)
     if not args.no_exchange:
         out["type_exchange"] = exchange_leg(scene_np, args.workload)
     if not args.no_serving:

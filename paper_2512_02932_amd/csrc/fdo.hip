@@ -12,8 +12,9 @@
 //   grad_low  = lambda_low * LL / n            (the same on all four),
 //   grad_high = lambda_high / n * (LH s1 + HL s2 + HH s1 s2)
 // with s1 = +1 on row y, -1 on row y+1 and s2 = +1 on column x, -1 on x+1.
-// One thread per (view, channel, block): 8 bytes read and 8 written per
-// pixel and image, the bytes of a copy.
+// Threads stride over the (view, channel, block) triples, two per
+// iteration: 8 bytes read and 8 written per pixel and image, the bytes of a
+// copy.
 //
 // Projection (Alg. 1).  Per primitive i with parameter gradients g_color,
 // g_low, g_high (each the concatenation means 3, scales 3, rotations 4,
@@ -25,7 +26,9 @@
 // The update g_color + g_low + g_high is then
 //   g_color + (1 - c) g_low + g_high   (2D, c = d / |g_low|^2) or
 //   g_color + g_low + (1 - c) g_high   (3D, c = d / |g_high|^2),
-// formed in binary64 and rounded once.
+// formed in binary64 and rounded once.  Sixteen lanes share a primitive so
+// that its gradients are read as contiguous runs (one lane per SH element)
+// rather than one 192-byte run per lane.
 
 #include "hgs_internal.h"
 
@@ -57,6 +60,58 @@ __device__ __forceinline__ void block_add2(double a, double b, double *out) {
   }
 }
 
+// The residual of one 2x2 block (zero outside the image) and its offset.
+struct Block4 {
+  float a, b, c, d;
+  int64_t o;
+  bool x1, y1;
+};
+
+__device__ __forceinline__ Block4 load_block(int64_t t, int64_t per, int mw, int H, int W,
+                                             int64_t hw, const float *__restrict__ ren,
+                                             const float *__restrict__ tgt) {
+  Block4 k;
+  const int64_t pl = t / per;
+  const int rem = (int)(t - pl * per);
+  const int bi = rem / mw, bj = rem - bi * mw;
+  const int y = 2 * bi, x = 2 * bj;
+  k.y1 = y + 1 < H;
+  k.x1 = x + 1 < W;
+  k.o = pl * hw + (int64_t)y * W + x;
+  const int64_t o = k.o;
+  k.a = ren[o] - tgt[o];
+  k.b = k.x1 ? ren[o + 1] - tgt[o + 1] : 0.0f;
+  k.c = k.y1 ? ren[o + W] - tgt[o + W] : 0.0f;
+  k.d = (k.x1 && k.y1) ? ren[o + W + 1] - tgt[o + W + 1] : 0.0f;
+  return k;
+}
+
+__device__ __forceinline__ void store_block(const Block4 &k, int W, float kl, float kh,
+                                            float *__restrict__ g_low, float *__restrict__ g_high,
+                                            float &sl, float &sh) {
+  const float ll = 0.5f * ((k.a + k.b) + (k.c + k.d));
+  const float lh = 0.5f * ((k.a + k.b) - (k.c + k.d));
+  const float hl = 0.5f * ((k.a - k.b) + (k.c - k.d));
+  const float hh = 0.5f * ((k.a - k.b) - (k.c - k.d));
+  sl += ll * ll;
+  sh += lh * lh + hl * hl + hh * hh;
+  const int64_t o = k.o;
+  if (g_low) {
+    const float v = kl * ll;
+    g_low[o] = v;
+    if (k.x1) g_low[o + 1] = v;
+    if (k.y1) g_low[o + W] = v;
+    if (k.x1 && k.y1) g_low[o + W + 1] = v;
+  }
+  if (g_high) {
+    g_high[o] = kh * ((lh + hl) + hh);
+    if (k.x1) g_high[o + 1] = kh * ((lh - hl) - hh);
+    if (k.y1) g_high[o + W] = kh * ((hl - lh) - hh);
+    if (k.x1 && k.y1) g_high[o + W + 1] = kh * (hh - (lh + hl));
+  }
+}
+
+// Each thread takes two blocks per iteration (loads of both first).
 __global__ void __launch_bounds__(kFdoBlock)
 fdo_cotangents_kernel(int64_t planes, int H, int W, const float *__restrict__ ren,
                       const float *__restrict__ tgt, float kl, float kh, double inv_n,
@@ -66,38 +121,15 @@ fdo_cotangents_kernel(int64_t planes, int H, int W, const float *__restrict__ re
   const int64_t per = (int64_t)mh * mw;
   const int64_t total = planes * per;
   const int64_t hw = (int64_t)H * W;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   float sl = 0.0f, sh = 0.0f;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t pl = t / per;
-    const int rem = (int)(t - pl * per);
-    const int bi = rem / mw, bj = rem - bi * mw;
-    const int y = 2 * bi, x = 2 * bj;
-    const bool y1 = y + 1 < H, x1 = x + 1 < W;
-    const int64_t o = pl * hw + (int64_t)y * W + x;
-    const float a = ren[o] - tgt[o];
-    const float b = x1 ? ren[o + 1] - tgt[o + 1] : 0.0f;
-    const float c = y1 ? ren[o + W] - tgt[o + W] : 0.0f;
-    const float d = (x1 && y1) ? ren[o + W + 1] - tgt[o + W + 1] : 0.0f;
-    const float ll = 0.5f * ((a + b) + (c + d));
-    const float lh = 0.5f * ((a + b) - (c + d));
-    const float hl = 0.5f * ((a - b) + (c - d));
-    const float hh = 0.5f * ((a - b) - (c - d));
-    sl += ll * ll;
-    sh += lh * lh + hl * hl + hh * hh;
-    if (g_low) {
-      const float v = kl * ll;
-      g_low[o] = v;
-      if (x1) g_low[o + 1] = v;
-      if (y1) g_low[o + W] = v;
-      if (x1 && y1) g_low[o + W + 1] = v;
-    }
-    if (g_high) {
-      g_high[o] = kh * ((lh + hl) + hh);
-      if (x1) g_high[o + 1] = kh * ((lh - hl) - hh);
-      if (y1) g_high[o + W] = kh * ((hl - lh) - hh);
-      if (x1 && y1) g_high[o + W + 1] = kh * (hh - (lh + hl));
-    }
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += 2 * stride) {
+    const int64_t t2 = t + stride;
+    const Block4 p = load_block(t, per, mw, H, W, hw, ren, tgt);
+    Block4 q;
+    if (t2 < total) q = load_block(t2, per, mw, H, W, hw, ren, tgt);
+    store_block(p, W, kl, kh, g_low, g_high, sl, sh);
+    if (t2 < total) store_block(q, W, kl, kh, g_low, g_high, sl, sh);
   }
   if (losses) block_add2((double)sl * inv_n, (double)sh * inv_n, losses);
 }
@@ -107,56 +139,118 @@ struct GradSet {
   const float *m, *s, *r, *o, *sh;
 };
 
-__device__ __forceinline__ float ld(const float *p, int64_t i) { return p ? p[i] : 0.0f; }
+// 16 lanes per primitive: lane j < 11 holds parameter j of (means, scales,
+// rotations, opacity) and every lane holds SH elements j, j + 16, j + 32.
+// A wave reads four primitives' gradients as contiguous runs, each value
+// once, and keeps them in registers for the update.
+constexpr int kLanesPerPrim = 16;
 
+__device__ __forceinline__ const float *param_ptr(const GradSet &g, int j, int64_t i) {
+  if (j < 3) return g.m ? g.m + 3 * i + j : nullptr;
+  if (j < 6) return g.s ? g.s + 3 * i + (j - 3) : nullptr;
+  if (j < 10) return g.r ? g.r + 4 * i + (j - 6) : nullptr;
+  if (j == 10) return g.o ? g.o + i : nullptr;
+  return nullptr;
+}
+
+__device__ __forceinline__ float *out_ptr(float *om, float *os, float *orot, float *oo, int j,
+                                          int64_t i) {
+  if (j < 3) return om ? om + 3 * i + j : nullptr;
+  if (j < 6) return os ? os + 3 * i + (j - 3) : nullptr;
+  if (j < 10) return orot ? orot + 4 * i + (j - 6) : nullptr;
+  if (j == 10) return oo ? oo + i : nullptr;
+  return nullptr;
+}
+
+__device__ __forceinline__ float ldp(const float *p) { return p ? *p : 0.0f; }
+
+// One primitive's values held by a lane: its parameter slot j (< 11) and
+// SH elements j, j + 16, j + 32 of the three sets, and the type.
+template <int K>
+struct PrimLane {
+  static constexpr int kSH = 3 * K;
+  static constexpr int kR = (kSH + kLanesPerPrim - 1) / kLanesPerPrim;
+  float c0, l0, h0, cs[kR], ls[kR], hs[kR];
+  uint8_t t;
+  __device__ __forceinline__ void load(const GradSet &gc, const GradSet &gl, const GradSet &gh,
+                                       const uint8_t *types, int j, int64_t i) {
+    c0 = ldp(param_ptr(gc, j, i));
+    l0 = ldp(param_ptr(gl, j, i));
+    h0 = ldp(param_ptr(gh, j, i));
+    const int64_t base = (int64_t)kSH * i;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      const int e = j + kLanesPerPrim * r;
+      const bool in = e < kSH;
+      cs[r] = (in && gc.sh) ? gc.sh[base + e] : 0.0f;
+      ls[r] = (in && gl.sh) ? gl.sh[base + e] : 0.0f;
+      hs[r] = (in && gh.sh) ? gh.sh[base + e] : 0.0f;
+    }
+    t = types[i];
+  }
+  // Alg. 1 for this primitive; returns 1 on the group's first lane if it
+  // conflicts.
+  __device__ __forceinline__ uint32_t project(int j, int64_t i, float *om, float *os, float *orot,
+                                              float *oo, float *osh, int accumulate) const {
+    // d = g_low . g_high, |g_low|^2, |g_high|^2 in binary64 over the 16 lanes
+    double d = (double)l0 * h0, nl = (double)l0 * l0, nh = (double)h0 * h0;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      d = fma((double)ls[r], (double)hs[r], d);
+      nl = fma((double)ls[r], (double)ls[r], nl);
+      nh = fma((double)hs[r], (double)hs[r], nh);
+    }
+#pragma unroll
+    for (int o = kLanesPerPrim / 2; o; o >>= 1) {
+      d += __shfl_xor(d, o);
+      nl += __shfl_xor(nl, o);
+      nh += __shfl_xor(nh, o);
+    }
+    double wl = 1.0, wh = 1.0;
+    if (d < 0.0) {
+      if (t == 0)
+        wl = 1.0 - d / nl;  // Eq. 9: g_high loses its component along g_low
+      else
+        wh = 1.0 - d / nh;  // Eq. 10: g_low loses its component along g_high
+    }
+    float *dst = out_ptr(om, os, orot, oo, j, i);
+    if (dst) {
+      const float v = (float)((double)c0 + wl * (double)l0 + wh * (double)h0);
+      *dst = accumulate ? *dst + v : v;
+    }
+    if (osh) {
+      const int64_t base = (int64_t)kSH * i;
+#pragma unroll
+      for (int r = 0; r < kR; ++r) {
+        const int e = j + kLanesPerPrim * r;
+        if (e < kSH) {
+          const float v = (float)((double)cs[r] + wl * (double)ls[r] + wh * (double)hs[r]);
+          osh[base + e] = accumulate ? osh[base + e] + v : v;
+        }
+      }
+    }
+    return (d < 0.0 && j == 0) ? 1u : 0u;
+  }
+};
+
+// Each 16-lane group takes two primitives per iteration and issues all
+// their loads before either reduction.
 template <int K>
 __global__ void __launch_bounds__(kFdoBlock)
 fdo_project_kernel(int64_t n, const uint8_t *__restrict__ types, GradSet gc, GradSet gl,
                    GradSet gh, float *om, float *os, float *orot, float *oo, float *osh,
                    int accumulate, uint32_t *__restrict__ n_conflict) {
+  const int j = threadIdx.x & (kLanesPerPrim - 1);
+  const int64_t step = (int64_t)gridDim.x * (blockDim.x / kLanesPerPrim);
   uint32_t conflicts = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    // pass 1: d, |g_low|^2, |g_high|^2
-    double d = 0.0, nl = 0.0, nh = 0.0;
-    auto acc = [&](const float *pl, const float *ph, int64_t j) {
-      const double a = ld(pl, j), b = ld(ph, j);
-      d = fma(a, b, d);
-      nl = fma(a, a, nl);
-      nh = fma(b, b, nh);
-    };
-#pragma unroll
-    for (int k = 0; k < 3; ++k) acc(gl.m, gh.m, 3 * i + k);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) acc(gl.s, gh.s, 3 * i + k);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc(gl.r, gh.r, 4 * i + k);
-    acc(gl.o, gh.o, i);
-#pragma unroll 8
-    for (int k = 0; k < 3 * K; ++k) acc(gl.sh, gh.sh, (int64_t)3 * K * i + k);
-    double wl = 1.0, wh = 1.0;
-    if (d < 0.0) {
-      ++conflicts;
-      if (types[i] == 0)
-        wl = 1.0 - d / nl;  // Eq. 9: g_high loses its component along g_low
-      else
-        wh = 1.0 - d / nh;  // Eq. 10: g_low loses its component along g_high
-    }
-    // pass 2: the update
-    auto put = [&](float *dst, const float *pc, const float *pl, const float *ph, int64_t j) {
-      if (!dst) return;
-      const double v = (double)ld(pc, j) + wl * (double)ld(pl, j) + wh * (double)ld(ph, j);
-      dst[j] = accumulate ? dst[j] + (float)v : (float)v;
-    };
-#pragma unroll
-    for (int k = 0; k < 3; ++k) put(om, gc.m, gl.m, gh.m, 3 * i + k);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) put(os, gc.s, gl.s, gh.s, 3 * i + k);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) put(orot, gc.r, gl.r, gh.r, 4 * i + k);
-    put(oo, gc.o, gl.o, gh.o, i);
-#pragma unroll 8
-    for (int k = 0; k < 3 * K; ++k) put(osh, gc.sh, gl.sh, gh.sh, (int64_t)3 * K * i + k);
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanesPerPrim; i < n;
+       i += 2 * step) {
+    const int64_t i2 = i + step;
+    PrimLane<K> a, b;
+    a.load(gc, gl, gh, types, j, i);
+    if (i2 < n) b.load(gc, gl, gh, types, j, i2);
+    conflicts += a.project(j, i, om, os, orot, oo, osh, accumulate);
+    if (i2 < n) conflicts += b.project(j, i2, om, os, orot, oo, osh, accumulate);
   }
   if (!n_conflict) return;
   __shared__ uint32_t red[kFdoBlock / 64];
@@ -179,7 +273,9 @@ void launch_fdo_cotangents(int64_t planes, int H, int W, const float *ren, const
   const int64_t total = planes * per;
   if (total <= 0) return;
   const double n = (double)total;
-  int64_t grid = (total + kFdoBlock - 1) / kFdoBlock;
+  // one block per CU at most: each block ends with two same-address
+  // binary64 atomics for the losses, and those serialise
+  int64_t grid = (total + 2 * kFdoBlock - 1) / (2 * kFdoBlock);
   if (grid > n_cu) grid = n_cu;
   hipLaunchKernelGGL(fdo_cotangents_kernel, dim3((unsigned)grid), dim3(kFdoBlock), 0, s, planes,
                      H, W, ren, tgt, (float)(lambda_low / n), (float)(lambda_high / n), 1.0 / n,
@@ -193,8 +289,9 @@ void launch_fdo_project(int64_t n, int sh_coeffs, const uint8_t *types, const fl
   const GradSet c{gc[0], gc[1], gc[2], gc[3], gc[4]};
   const GradSet l{gl[0], gl[1], gl[2], gl[3], gl[4]};
   const GradSet h{gh[0], gh[1], gh[2], gh[3], gh[4]};
-  int64_t blocks = (n + kFdoBlock - 1) / kFdoBlock;
-  if (blocks > n_cu) blocks = n_cu;
+  const int64_t per_block = 2 * (kFdoBlock / kLanesPerPrim);
+  int64_t blocks = (n + per_block - 1) / per_block;
+  if (blocks > 2 * (int64_t)n_cu) blocks = 2 * (int64_t)n_cu;
   const dim3 grid((unsigned)blocks);
 #define HGS_FDO_PROJ(KK)                                                                  \
   hipLaunchKernelGGL(fdo_project_kernel<KK>, grid, dim3(kFdoBlock), 0, s, n, types, c, l, h, \
