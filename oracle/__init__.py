@@ -13,6 +13,7 @@ backward(scene, cams, pix, G, ...)     binary64 gradients (dual numbers)
 sh_basis(degree, dirs)                 real SH basis used for colour
 erank(sx, sy, sz) / type_exchange(...)  Adaptive Type Exchange (Eq. 3, P_x/P_y)
 fdo.dwt / fdo.fdo_losses / fdo.fdo_project   Frequency-Decoupled Optimization (Alg. 1)
+train.color_loss / train.adam_step       L1 + D-SSIM colour loss, Adam on raw parameters
 surfel_uv(params, cam, pxy)            ray-plane (u, v, depth) of one surfel
 full_pixels(cams) / all outputs reshaped to images: render_images(...)
 """
@@ -265,3 +266,4 @@ def images(res, cam, n_views=1):
 
 
 from . import fdo  # noqa: E402  (Frequency-Decoupled Optimization, binary64)
+from . import train  # noqa: E402  (colour loss and Adam, binary64)
