@@ -208,7 +208,9 @@ enum {
   HGS_STAGE_DEPTH_SORT = 9,
   HGS_STAGE_FDO_COTANGENTS = 10,
   HGS_STAGE_FDO_PROJECT = 11,
-  HGS_N_STAGES = 12
+  HGS_STAGE_COLOR_LOSS = 12,
+  HGS_STAGE_ADAM = 13,
+  HGS_N_STAGES = 14
 };
 hgs_status hgs_profile_enable(hgs_ctx *ctx, int32_t on);
 hgs_status hgs_profile_read(hgs_ctx *ctx, double *ms, int64_t *calls, int32_t reset);
@@ -292,6 +294,53 @@ hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *state,
                                    const hgs_grad_images *grad_color, const float *grad_low_rgb,
                                    const float *grad_high_rgb, const hgs_grads *update,
                                    const hgs_grads *sets, uint32_t *n_conflict, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Training step: the colour loss (Sec. 3.3) and the optimizer.
+ * ------------------------------------------------------------------- */
+
+/* L_color = (1 - lambda) L1 + lambda D-SSIM of a rendered RGB image against
+ * a target, the appearance loss the paper takes from 3DGS (Sec. 3.3):
+ * L1 = mean |I^ - I|, D-SSIM = 1 - mean SSIM, SSIM per pixel and channel
+ * with an 11 x 11 Gaussian window (sigma 1.5, zero padding, same size),
+ * C1 = 0.01^2, C2 = 0.03^2.  render_rgb, target_rgb: device f32
+ * [n_views, 3, H, W].  grad: device f32, same shape, receives dL_color/dI^
+ * (overwritten), or NULL.  losses: device double[2] (8-byte aligned) or
+ * NULL; losses[0] += L1, losses[1] += D-SSIM.  lambda_dssim = 0.2 in 3DGS.
+ * Uses a pooled workspace of 12 bytes per pixel and channel.
+ * Errors: EINVAL (negative sizes, NULL images with a non-empty size,
+ * lambda outside [0, 1], misaligned losses), ENOMEM, EHIP. */
+hgs_status hgs_color_loss(hgs_ctx *ctx, int32_t n_views, int32_t height, int32_t width,
+                          const float *render_rgb, const float *target_rgb, double lambda_dssim,
+                          float *grad, double *losses, void *stream);
+
+/* Adam hyper-parameters: learning rates per parameter group (SH DC and the
+ * higher SH coefficients apart), betas, eps and the 1-based step count used
+ * for bias correction.  The betas are binary64 so that 1 - beta (1e-3 for
+ * beta2 = 0.999) is exact to binary32 rounding; 0.999 itself has no
+ * binary32 value close enough for that. */
+typedef struct {
+  float lr_means, lr_scales, lr_rotations, lr_opacities, lr_sh_dc, lr_sh_rest;
+  double beta1, beta2, eps;
+  int32_t step;
+} hgs_adam_opts;
+
+/* One Adam step (Kingma and Ba) on n primitives' raw parameters: means,
+ * log-scales, quaternions, opacity logits and SH ((sh_degree+1)^2
+ * coefficients), each array shaped like hgs_scene_desc's.  grads are the
+ * gradients with respect to the activated values the renderer uses
+ * (hgs_render_backward's output, or an FDO update); the step applies the
+ * chain dL/ds_raw = exp(s_raw) dL/ds and dL/dalpha_raw =
+ * sigmoid'(alpha_raw) dL/dalpha.  raw, exp_avg and exp_avg_sq are updated
+ * in place; activated (may be NULL, and any of its arrays may be NULL)
+ * receives exp(s_raw), sigmoid(alpha_raw) and copies of the others, so it
+ * can be the scene the renderer reads.  A NULL raw array is skipped; a
+ * non-NULL one needs its gradient and both moments.  The accumulate flags
+ * are ignored.  Errors: EINVAL, EHIP. */
+hgs_status hgs_adam_step(hgs_ctx *ctx, int64_t n, int32_t sh_degree, const hgs_grads *raw,
+                         const hgs_grads *grads, const hgs_grads *exp_avg,
+                         const hgs_grads *exp_avg_sq, const hgs_grads *activated,
+                         const hgs_adam_opts *opts, void *stream);
 
 /* ---------------------------------------------------------------------
  * Batched serving.

@@ -19,10 +19,11 @@ EXPORTS = ("hgs_create", "hgs_destroy", "hgs_scene_init", "hgs_scene_release", "
            "hgs_state_check", "hgs_last_error", "hgs_profile_enable", "hgs_profile_read",
            "hgs_server_create", "hgs_server_destroy", "hgs_server_submit", "hgs_server_poll",
            "hgs_server_stats", "hgs_type_exchange", "hgs_fdo_cotangents", "hgs_fdo_project",
-           "hgs_render_backward_fdo")
+           "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step")
 
 STAGES = ("preprocess", "scan", "duplicate", "sort", "ranges", "raster_fwd", "raster_bwd",
-          "preprocess_bwd", "fill", "depth_sort", "fdo_cotangents", "fdo_project")
+          "preprocess_bwd", "fill", "depth_sort", "fdo_cotangents", "fdo_project", "color_loss",
+          "adam")
 
 
 class hgs_scene_desc(C.Structure):
@@ -50,6 +51,13 @@ class hgs_images(C.Structure):
 class hgs_grad_images(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("alpha", C.c_void_p), ("depth", C.c_void_p),
                 ("normal", C.c_void_p)]
+
+
+class hgs_adam_opts(C.Structure):
+    _fields_ = [("lr_means", C.c_float), ("lr_scales", C.c_float), ("lr_rotations", C.c_float),
+                ("lr_opacities", C.c_float), ("lr_sh_dc", C.c_float), ("lr_sh_rest", C.c_float),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("step", C.c_int32)]
 
 
 class hgs_grads(C.Structure):
@@ -124,12 +132,15 @@ def load(path: str | None = None):
                                     C.POINTER(hgs_grads), P, P]
     lib.hgs_render_backward_fdo.argtypes = [P, P, C.POINTER(hgs_grad_images), P, P,
                                             C.POINTER(hgs_grads), P, P, P]
+    lib.hgs_color_loss.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_double, P, P, P]
+    lib.hgs_adam_step.argtypes = [P, C.c_int64, C.c_int32] + [C.POINTER(hgs_grads)] * 4 + \
+        [P, C.POINTER(hgs_adam_opts), P]
     for name in ("hgs_create", "hgs_scene_init", "hgs_scene_release", "hgs_render",
                  "hgs_render_backward", "hgs_state_sizes", "hgs_state_debug", "hgs_state_check",
                  "hgs_profile_enable", "hgs_profile_read", "hgs_server_create",
                  "hgs_server_submit", "hgs_server_poll", "hgs_server_stats",
                  "hgs_type_exchange", "hgs_fdo_cotangents", "hgs_fdo_project",
-                 "hgs_render_backward_fdo"):
+                 "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -267,3 +278,18 @@ def hgs_render_backward_fdo(ctx, state, grad_images, glow_ptr: int, ghigh_ptr: i
                                          C.c_void_p(ghigh_ptr), C.byref(update),
                                          None if sets is None else C.cast(sets, C.c_void_p),
                                          C.c_void_p(conflict_ptr), C.c_void_p(stream)))
+
+
+def hgs_color_loss(ctx, V: int, H: int, W: int, ren_ptr: int, tgt_ptr: int, lam: float,
+                   grad_ptr: int, losses_ptr: int, stream: int):
+    check(load().hgs_color_loss(ctx, int(V), int(H), int(W), C.c_void_p(ren_ptr),
+                                C.c_void_p(tgt_ptr), float(lam), C.c_void_p(grad_ptr),
+                                C.c_void_p(losses_ptr), C.c_void_p(stream)))
+
+
+def hgs_adam_step(ctx, n: int, sh_degree: int, raw, grads, m, v, act, opts, stream: int):
+    """`act` may be None."""
+    check(load().hgs_adam_step(ctx, int(n), int(sh_degree), C.byref(raw), C.byref(grads),
+                               C.byref(m), C.byref(v),
+                               None if act is None else C.cast(C.pointer(act), C.c_void_p),
+                               C.byref(opts), C.c_void_p(stream)))

@@ -750,6 +750,101 @@ hgs_status hgs_fdo_project(hgs_ctx *ctx, int64_t n, int32_t sh_degree, const uin
   return HGS_OK;
 }
 
+hgs_status hgs_color_loss(hgs_ctx *ctx, int32_t n_views, int32_t height, int32_t width,
+                          const float *render_rgb, const float *target_rgb, double lambda_dssim,
+                          float *grad, double *losses, void *stream) {
+  if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
+  if (n_views < 0 || height < 0 || width < 0) return fail(HGS_EINVAL, "negative size");
+  const int64_t planes = (int64_t)n_views * 3;
+  const int64_t npx = planes * height * width;
+  if (npx > 0 && (!render_rgb || !target_rgb))
+    return fail(HGS_EINVAL, "render_rgb and target_rgb are required");
+  if (!(lambda_dssim >= 0.0 && lambda_dssim <= 1.0))
+    return fail(HGS_EINVAL, "lambda_dssim must be in [0, 1]");
+  if (losses && (reinterpret_cast<uintptr_t>(losses) & 7u))
+    return fail(HGS_EINVAL, "losses must be 8-byte aligned");
+  if (npx == 0) return HGS_OK;
+  HGS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  hgs_state tmp;  // borrows a pooled workspace for the derivative maps
+  tmp.device = ctx->device;
+  tmp.stream = s;
+  HGS_HIP(acquire_ws(ctx, &tmp));
+  float *maps = nullptr;
+  hipError_t e = dalloc_t(&tmp, &maps, (size_t)(3 * npx));
+  if (e == hipSuccess) e = commit(&tmp, 0, s);
+  if (e == hipSuccess) {
+    StageTimer t(ctx, HGS_STAGE_COLOR_LOSS, s);
+    launch_ssim_fwd(planes, height, width, render_rgb, target_rgb, maps, maps + npx,
+                    maps + 2 * npx, losses, ctx->n_cu, s);
+    if (grad)
+      launch_ssim_bwd(planes, height, width, render_rgb, target_rgb, maps, maps + npx,
+                      maps + 2 * npx, lambda_dssim, grad, ctx->n_cu, s);
+    e = hipGetLastError();
+  }
+  release(ctx, &tmp);
+  HGS_HIP(e);
+  return HGS_OK;
+}
+
+hgs_status hgs_adam_step(hgs_ctx *ctx, int64_t n, int32_t sh_degree, const hgs_grads *raw,
+                         const hgs_grads *grads, const hgs_grads *exp_avg,
+                         const hgs_grads *exp_avg_sq, const hgs_grads *activated,
+                         const hgs_adam_opts *opts, void *stream) {
+  if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
+  if (!raw || !grads || !exp_avg || !exp_avg_sq || !opts)
+    return fail(HGS_EINVAL, "raw, grads, exp_avg, exp_avg_sq and opts are required");
+  if (n < 0) return fail(HGS_EINVAL, "n < 0");
+  if (sh_degree < 0 || sh_degree > 3) return fail(HGS_EINVAL, "sh_degree must be 0..3");
+  if (opts->step < 1) return fail(HGS_EINVAL, "step must be >= 1");
+  if (!(opts->beta1 >= 0.0 && opts->beta1 < 1.0 && opts->beta2 >= 0.0 && opts->beta2 < 1.0))
+    return fail(HGS_EINVAL, "betas must be in [0, 1)");
+  if (!(opts->eps >= 0.0)) return fail(HGS_EINVAL, "eps must be >= 0");
+  const int K = (sh_degree + 1) * (sh_degree + 1);
+  AdamArgs a{};
+  auto take = [](const hgs_grads *g, int k) -> float * {
+    switch (k) {
+      case 0: return g->means;
+      case 1: return g->scales;
+      case 2: return g->rotations;
+      case 3: return g->opacities;
+      default: return g->sh;
+    }
+  };
+  const int64_t cnt[5] = {3 * n, 3 * n, 4 * n, n, 3 * K * n};
+  a.off[0] = 0;
+  for (int k = 0; k < 5; ++k) {
+    a.raw[k] = take(raw, k);
+    a.grad[k] = take(grads, k);
+    a.m[k] = take(exp_avg, k);
+    a.v[k] = take(exp_avg_sq, k);
+    a.act[k] = activated ? take(activated, k) : nullptr;
+    if (a.raw[k] && (!a.grad[k] || !a.m[k] || !a.v[k]))
+      return fail(HGS_EINVAL, "a parameter array needs its gradient and both moments");
+    a.off[k + 1] = a.off[k] + cnt[k];
+  }
+  a.lr[0] = opts->lr_means;
+  a.lr[1] = opts->lr_scales;
+  a.lr[2] = opts->lr_rotations;
+  a.lr[3] = opts->lr_opacities;
+  a.lr[4] = opts->lr_sh_dc;
+  a.lr_sh_rest = opts->lr_sh_rest;
+  a.beta1 = (float)opts->beta1;
+  a.beta2 = (float)opts->beta2;
+  a.omb1 = (float)(1.0 - opts->beta1);
+  a.omb2 = (float)(1.0 - opts->beta2);
+  a.eps = (float)opts->eps;
+  a.bc1 = (float)(1.0 / (1.0 - std::pow(opts->beta1, (double)opts->step)));
+  a.bc2 = (float)(1.0 / (1.0 - std::pow(opts->beta2, (double)opts->step)));
+  a.sh_stride = 3 * K;
+  HGS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  StageTimer t(ctx, HGS_STAGE_ADAM, s);
+  launch_adam(a, ctx->n_cu, s);
+  HGS_HIP(hipGetLastError());
+  return HGS_OK;
+}
+
 hgs_status hgs_profile_enable(hgs_ctx *ctx, int32_t on) {
   if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
   ctx->profile = on != 0;

@@ -211,4 +211,31 @@ void launch_fdo_project(int64_t n, int sh_coeffs, const uint8_t *types, const fl
                         const float *const *gl, const float *const *gh, float *const *out,
                         int accumulate, uint32_t *n_conflict, int n_cu, hipStream_t s);
 
+// Colour loss (L1 + D-SSIM).  Win11: the normalised 11-tap Gaussian
+// (sigma 1.5) of the SSIM window.  launch_ssim_fwd writes the derivative
+// maps A, B, C ([planes, H, W]) and adds mean |x - y| and 1 - mean SSIM
+// into losses[0], losses[1] (may be NULL); launch_ssim_bwd writes the
+// cotangent of (1 - lambda) L1 + lambda D-SSIM.
+struct Win11 {
+  float w[11];
+};
+Win11 gauss_win11();
+void launch_ssim_fwd(int64_t planes, int H, int W, const float *x, const float *y, float *Am,
+                     float *Bm, float *Cm, double *losses, int n_cu, hipStream_t s);
+void launch_ssim_bwd(int64_t planes, int H, int W, const float *x, const float *y,
+                     const float *Am, const float *Bm, const float *Cm, double lambda,
+                     float *grad, int n_cu, hipStream_t s);
+
+// Adam over the five parameter arrays (means, scales, rotations,
+// opacities, sh) flattened: array s holds elements [off[s], off[s+1]).
+// NULL raw or grad skips an array; NULL act does not write activated values.
+struct AdamArgs {
+  float *raw[5], *m[5], *v[5], *act[5];
+  const float *grad[5];
+  int64_t off[6];
+  float lr[5], lr_sh_rest, beta1, beta2, omb1, omb2, eps, bc1, bc2;  // omb = 1 - beta
+  int64_t sh_stride;  // 3 K: SH elements of one primitive (the first 3 are DC)
+};
+void launch_adam(const AdamArgs &a, int n_cu, hipStream_t s);
+
 }  // namespace hgs

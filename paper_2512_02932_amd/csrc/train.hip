@@ -1,0 +1,307 @@
+// Training-step kernels, gfx950: the colour loss of Sec. 3.3 and Adam.
+//
+// Colour loss.  L_color = (1 - lambda) L1 + lambda D-SSIM as 3DGS defines
+// it: L1 = mean |x - y| and D-SSIM = 1 - mean SSIM, where per pixel and
+// channel
+//   f = a1 a2 / (b1 b2),  a1 = 2 mx my + C1,  a2 = 2 (Sxy - mx my) + C2,
+//                         b1 = mx^2 + my^2 + C1,  b2 = Sxx - mx^2 + Syy - my^2 + C2,
+// with mx = G*x, my = G*y, Sxx = G*x^2, Syy = G*y^2, Sxy = G*xy under an
+// 11 x 11 Gaussian window G (sigma 1.5, normalised, zero padding, same
+// size), C1 = 0.01^2, C2 = 0.03^2.  With M the number of pixel-channels,
+//   d mean(f) / dx(p) = (1/M) [G*A + 2 x(p) G*B + y(p) G*C](p),
+//   A = df/dmx = (2 my (a2 - a1) - 2 mx f (b2 - b1)) / (b1 b2),
+//   B = df/dSxx = -f / b2,  C = df/dSxy = 2 a1 / (b1 b2),
+// since G is symmetric and the adjoint of a zero-padded same-size filter
+// is the same filter.  Two passes over 32 x 32 output tiles with a 5-pixel
+// halo in LDS, each a separable filter (rows, then columns):
+//   forward:  the five moments -> f, A, B, C (A, B, C to HBM), the sums
+//             of |x - y| and 1 - f;
+//   backward: G*A, G*B, G*C -> the cotangent of L_color.
+// Blocks stride over the tiles and add their loss sums with one binary64
+// atomic per sum per block.
+//
+// Adam (Kingma and Ba) on the raw 3DGS parameters (means, log-scales,
+// quaternions, opacity logits, SH) from the gradients with respect to the
+// activated values the rasterizer returns: dL/ds_raw = exp(s_raw) dL/ds,
+// dL/dalpha_raw = sigmoid'(alpha_raw) dL/dalpha.  One elementwise pass over
+// all parameter arrays, with bias correction, writing the raw parameters,
+// both moments and (optionally) the activated values the renderer reads.
+
+#include <cmath>
+
+#include "hgs_internal.h"
+
+namespace hgs {
+
+namespace {
+
+constexpr int kSsimTile = 32;
+constexpr int kHalo = 5;
+constexpr int kSpan = kSsimTile + 2 * kHalo;  // 42
+constexpr int kSsimThreads = 256;
+constexpr float kC1 = 0.01f * 0.01f;
+constexpr float kC2 = 0.03f * 0.03f;
+
+struct TileGrid {
+  int H, W, tiles_x, tiles_y;
+  int64_t planes;
+};
+
+__device__ __forceinline__ void tile_origin(const TileGrid &g, int64_t t, int64_t &plane, int &x0,
+                                            int &y0) {
+  const int64_t per = (int64_t)g.tiles_x * g.tiles_y;
+  plane = t / per;
+  const int r = (int)(t - plane * per);
+  y0 = (r / g.tiles_x) * kSsimTile;
+  x0 = (r % g.tiles_x) * kSsimTile;
+}
+
+// Loads n zero-padded planes of the tile with its halo into LDS.
+template <int NQ>
+__device__ __forceinline__ void load_halo(const float *const (&src)[NQ], int64_t plane_off,
+                                          const TileGrid &g, int x0, int y0,
+                                          float (&dst)[NQ][kSpan][kSpan + 1]) {
+  for (int idx = threadIdx.x; idx < kSpan * kSpan; idx += kSsimThreads) {
+    const int r = idx / kSpan, c = idx - r * kSpan;
+    const int gy = y0 - kHalo + r, gx = x0 - kHalo + c;
+    const bool in = gy >= 0 && gy < g.H && gx >= 0 && gx < g.W;
+    const int64_t o = plane_off + (int64_t)gy * g.W + gx;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) dst[q][r][c] = in ? src[q][o] : 0.0f;
+  }
+}
+
+__global__ void __launch_bounds__(kSsimThreads)
+ssim_fwd_kernel(TileGrid g, Win11 win, const float *__restrict__ xs, const float *__restrict__ ys,
+                float *__restrict__ Am, float *__restrict__ Bm, float *__restrict__ Cm,
+                double inv_m, double *__restrict__ losses) {
+  __shared__ float in[2][kSpan][kSpan + 1];
+  __shared__ float hq[5][kSpan][kSsimTile + 1];
+  const int tx = threadIdx.x & (kSsimTile - 1), ty = threadIdx.x / kSsimTile;  // 32 x 8
+  const int64_t n_tiles = g.planes * g.tiles_x * g.tiles_y;
+  const int64_t hw = (int64_t)g.H * g.W;
+  float l1 = 0.0f, ds = 0.0f;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    int64_t plane;
+    int x0, y0;
+    tile_origin(g, t, plane, x0, y0);
+    const float *src[2] = {xs, ys};
+    __syncthreads();  // the previous tile's LDS is no longer read
+    load_halo<2>(src, plane * hw, g, x0, y0, in);
+    __syncthreads();
+    // rows: five window sums at the 32 output columns of all 42 rows
+    for (int idx = threadIdx.x; idx < kSpan * kSsimTile; idx += kSsimThreads) {
+      const int r = idx / kSsimTile, c = idx - r * kSsimTile;
+      float s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+#pragma unroll
+      for (int k = 0; k < 11; ++k) {
+        const float a = in[0][r][c + k], b = in[1][r][c + k], w = win.w[k];
+        s0 += w * a;
+        s1 += w * b;
+        s2 += w * (a * a);
+        s3 += w * (b * b);
+        s4 += w * (a * b);
+      }
+      hq[0][r][c] = s0;
+      hq[1][r][c] = s1;
+      hq[2][r][c] = s2;
+      hq[3][r][c] = s3;
+      hq[4][r][c] = s4;
+    }
+    __syncthreads();
+    // columns: the moments at this thread's four output pixels
+#pragma unroll
+    for (int k4 = 0; k4 < kSsimTile / 8; ++k4) {
+      const int r0 = ty + 8 * k4;
+      const int gy = y0 + r0, gx = x0 + tx;
+      if (gy >= g.H || gx >= g.W) continue;
+      float mx = 0, my = 0, sxx = 0, syy = 0, sxy = 0;
+#pragma unroll
+      for (int k = 0; k < 11; ++k) {
+        const float w = win.w[k];
+        mx += w * hq[0][r0 + k][tx];
+        my += w * hq[1][r0 + k][tx];
+        sxx += w * hq[2][r0 + k][tx];
+        syy += w * hq[3][r0 + k][tx];
+        sxy += w * hq[4][r0 + k][tx];
+      }
+      const float a1 = 2.0f * mx * my + kC1;
+      const float a2 = 2.0f * (sxy - mx * my) + kC2;
+      const float b1 = mx * mx + my * my + kC1;
+      const float b2 = (sxx - mx * mx) + (syy - my * my) + kC2;
+      const float inv = 1.0f / (b1 * b2);
+      const float f = a1 * a2 * inv;
+      const int64_t o = plane * hw + (int64_t)gy * g.W + gx;
+      Am[o] = (2.0f * my * (a2 - a1) - 2.0f * mx * f * (b2 - b1)) * inv;
+      Bm[o] = -f / b2;
+      Cm[o] = 2.0f * a1 * inv;
+      const float xv = in[0][r0 + kHalo][tx + kHalo], yv = in[1][r0 + kHalo][tx + kHalo];
+      l1 += fabsf(xv - yv);
+      ds += 1.0f - f;
+    }
+  }
+  if (!losses) return;
+  __shared__ double red[2][kSsimThreads / 64];
+  double a = (double)l1, b = (double)ds;
+  for (int o = 32; o; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0, sb = 0;
+    for (int k = 0; k < kSsimThreads / 64; ++k) {
+      sa += red[0][k];
+      sb += red[1][k];
+    }
+    atomicAdd(losses, sa * inv_m);
+    atomicAdd(losses + 1, sb * inv_m);
+  }
+}
+
+__global__ void __launch_bounds__(kSsimThreads)
+ssim_bwd_kernel(TileGrid g, Win11 win, const float *__restrict__ xs, const float *__restrict__ ys,
+                const float *__restrict__ Am, const float *__restrict__ Bm,
+                const float *__restrict__ Cm, float k_l1, float k_ssim, float *__restrict__ grad) {
+  __shared__ float in[3][kSpan][kSpan + 1];
+  __shared__ float hq[3][kSpan][kSsimTile + 1];
+  const int tx = threadIdx.x & (kSsimTile - 1), ty = threadIdx.x / kSsimTile;
+  const int64_t n_tiles = g.planes * g.tiles_x * g.tiles_y;
+  const int64_t hw = (int64_t)g.H * g.W;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    int64_t plane;
+    int x0, y0;
+    tile_origin(g, t, plane, x0, y0);
+    const float *src[3] = {Am, Bm, Cm};
+    __syncthreads();
+    load_halo<3>(src, plane * hw, g, x0, y0, in);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kSpan * kSsimTile; idx += kSsimThreads) {
+      const int r = idx / kSsimTile, c = idx - r * kSsimTile;
+      float s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+      for (int k = 0; k < 11; ++k) {
+        const float w = win.w[k];
+        s0 += w * in[0][r][c + k];
+        s1 += w * in[1][r][c + k];
+        s2 += w * in[2][r][c + k];
+      }
+      hq[0][r][c] = s0;
+      hq[1][r][c] = s1;
+      hq[2][r][c] = s2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < kSsimTile / 8; ++k4) {
+      const int r0 = ty + 8 * k4;
+      const int gy = y0 + r0, gx = x0 + tx;
+      if (gy >= g.H || gx >= g.W) continue;
+      float ga = 0, gb = 0, gc = 0;
+#pragma unroll
+      for (int k = 0; k < 11; ++k) {
+        const float w = win.w[k];
+        ga += w * hq[0][r0 + k][tx];
+        gb += w * hq[1][r0 + k][tx];
+        gc += w * hq[2][r0 + k][tx];
+      }
+      const int64_t o = plane * hw + (int64_t)gy * g.W + gx;
+      const float xv = xs[o], yv = ys[o];
+      const float d = xv - yv;
+      const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
+      grad[o] = k_l1 * sg - k_ssim * (ga + 2.0f * xv * gb + yv * gc);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adam.  Segment s of the flattened parameter space is array s of the five
+// (means, scales, rotations, opacities, sh).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+adam_kernel(AdamArgs a) {
+  const int64_t total = a.off[5];
+  const float c1 = a.bc1, c2 = a.bc2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int s = 0;
+#pragma unroll
+    for (int k = 1; k < 5; ++k) s += e >= a.off[k] ? 1 : 0;
+    const int64_t i = e - a.off[s];
+    if (!a.raw[s] || !a.grad[s]) continue;
+    const float p = a.raw[s][i];
+    float gr = a.grad[s][i];
+    float lr = a.lr[s];
+    if (s == 1) {
+      gr *= expf(p);
+    } else if (s == 3) {  // sigmoid' = sigmoid(p) sigmoid(-p): no cancellation near 1
+      gr *= (1.0f / (1.0f + expf(-p))) * (1.0f / (1.0f + expf(p)));
+    } else if (s == 4 && (i % a.sh_stride) >= 3) {
+      lr = a.lr_sh_rest;
+    }
+    const float m = a.beta1 * a.m[s][i] + a.omb1 * gr;
+    const float v = a.beta2 * a.v[s][i] + a.omb2 * gr * gr;
+    const float mh = m * c1, vh = v * c2;
+    const float np = p - lr * mh / (sqrtf(vh) + a.eps);
+    a.m[s][i] = m;
+    a.v[s][i] = v;
+    a.raw[s][i] = np;
+    if (a.act[s]) {
+      float av = np;
+      if (s == 1) av = expf(np);
+      else if (s == 3) av = 1.0f / (1.0f + expf(-np));
+      a.act[s][i] = av;
+    }
+  }
+}
+
+}  // namespace
+
+Win11 gauss_win11() {
+  Win11 w;
+  double g[11], sum = 0.0;
+  for (int k = 0; k < 11; ++k) {
+    const double d = k - 5;
+    g[k] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
+    sum += g[k];
+  }
+  for (int k = 0; k < 11; ++k) w.w[k] = (float)(g[k] / sum);
+  return w;
+}
+
+void launch_ssim_fwd(int64_t planes, int H, int W, const float *x, const float *y, float *Am,
+                     float *Bm, float *Cm, double *losses, int n_cu, hipStream_t s) {
+  if (planes <= 0 || H <= 0 || W <= 0) return;
+  TileGrid g{H, W, (W + kSsimTile - 1) / kSsimTile, (H + kSsimTile - 1) / kSsimTile, planes};
+  const int64_t n_tiles = planes * g.tiles_x * g.tiles_y;
+  int64_t grid = n_tiles < 2 * (int64_t)n_cu ? n_tiles : 2 * (int64_t)n_cu;
+  const double m = (double)planes * H * W;
+  hipLaunchKernelGGL(ssim_fwd_kernel, dim3((unsigned)grid), dim3(kSsimThreads), 0, s, g,
+                     gauss_win11(), x, y, Am, Bm, Cm, 1.0 / m, losses);
+}
+
+void launch_ssim_bwd(int64_t planes, int H, int W, const float *x, const float *y,
+                     const float *Am, const float *Bm, const float *Cm, double lambda,
+                     float *grad, int n_cu, hipStream_t s) {
+  if (planes <= 0 || H <= 0 || W <= 0) return;
+  TileGrid g{H, W, (W + kSsimTile - 1) / kSsimTile, (H + kSsimTile - 1) / kSsimTile, planes};
+  const int64_t n_tiles = planes * g.tiles_x * g.tiles_y;
+  int64_t grid = n_tiles < 4 * (int64_t)n_cu ? n_tiles : 4 * (int64_t)n_cu;
+  const double m = (double)planes * H * W;
+  hipLaunchKernelGGL(ssim_bwd_kernel, dim3((unsigned)grid), dim3(kSsimThreads), 0, s, g,
+                     gauss_win11(), x, y, Am, Bm, Cm, (float)((1.0 - lambda) / m),
+                     (float)(lambda / m), grad);
+}
+
+void launch_adam(const AdamArgs &a, int n_cu, hipStream_t s) {
+  const int64_t total = a.off[5];
+  if (total <= 0) return;
+  int64_t grid = (total + 255) / 256;
+  if (grid > 16 * (int64_t)n_cu) grid = 16 * (int64_t)n_cu;
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)grid), dim3(256), 0, s, a);
+}
+
+}  // namespace hgs

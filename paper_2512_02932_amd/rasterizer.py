@@ -359,3 +359,45 @@ def fdo_project(types: torch.Tensor, sh_degree: int, g_color: dict, g_low: dict,
                       _grads(g_low, False), _grads(g_high, False), _grads(update, accumulate),
                       _ptr(n_conflict), s)
     return update
+
+
+def color_loss(render_rgb: torch.Tensor, target_rgb: torch.Tensor, lambda_dssim: float = 0.2,
+               losses: torch.Tensor | None = None, want_grad: bool = True):
+    """L_color = (1 - lambda) L1 + lambda D-SSIM (``hgs_color_loss``).
+    Returns (grad or None, losses) with losses a float64 [2] device tensor
+    (L1, D-SSIM) that the call adds into."""
+    if render_rgb.shape != target_rgb.shape or render_rgb.dim() != 4 or render_rgb.shape[1] != 3:
+        raise ValueError("render_rgb and target_rgb must both be [V, 3, H, W]")
+    for t in (render_rgb, target_rgb):
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("images must be contiguous float32")
+    V, _, Hh, Ww = render_rgb.shape
+    grad = torch.empty_like(render_rgb) if want_grad else None
+    if losses is None:
+        losses = torch.zeros(2, dtype=torch.float64, device=render_rgb.device)
+    rast = get_rasterizer(render_rgb.device)
+    s = torch.cuda.current_stream(rast.device).cuda_stream
+    H.hgs_color_loss(rast.ctx, V, Hh, Ww, _ptr(render_rgb), _ptr(target_rgb), lambda_dssim,
+                     _ptr(grad), _ptr(losses), s)
+    return grad, losses
+
+
+# 3DGS's default learning rates (the spatial scale of the means' rate and
+# its decay are the caller's).
+ADAM_DEFAULTS = dict(lr_means=1.6e-4, lr_scales=5e-3, lr_rotations=1e-3, lr_opacities=2.5e-2,
+                     lr_sh_dc=2.5e-3, lr_sh_rest=2.5e-3 / 20, beta1=0.9, beta2=0.999, eps=1e-15)
+
+
+def adam_step(n: int, sh_degree: int, raw: dict, grads: dict, exp_avg: dict, exp_avg_sq: dict,
+              step: int, activated: dict | None = None, **lr):
+    """One fused Adam step (``hgs_adam_step``) on raw parameter dicts."""
+    o = H.hgs_adam_opts()
+    for k, v in {**ADAM_DEFAULTS, **lr}.items():
+        setattr(o, k, float(v))
+    o.step = int(step)
+    dev = raw["means"].device
+    rast = get_rasterizer(dev)
+    s = torch.cuda.current_stream(rast.device).cuda_stream
+    H.hgs_adam_step(rast.ctx, n, sh_degree, _grads(raw, False), _grads(grads, False),
+                    _grads(exp_avg, False), _grads(exp_avg_sq, False),
+                    None if activated is None else _grads(activated, False), o, s)

@@ -1,0 +1,186 @@
+"""Training-step kernels on the GPU (hgs_color_loss, hgs_adam_step) against
+the oracle.
+
+Colour loss: the binary32 moments form b2 = s_x^2 + s_y^2 + C2 as
+S - mu^2, whose absolute error is about 1e-7 (S_xx + S_yy) <= 5e-8 against
+b2 >= C2 = 9e-4, so SSIM and its derivative maps carry relative errors up
+to ~5e-5 in flat regions: gradients are compared element-wise within 2e-4
+of the largest magnitude, L1 within 1e-6 and D-SSIM within 5e-5 relative.
+
+Adam: every quantity within a few binary32 roundings (2e-6) of the
+magnitudes of its own terms, since its sums cancel: m = b1 m0 + (1-b1) g
+against b1|m0| + (1-b1)|g|, v likewise, the parameter against |p| plus the
+update's sensitivity to m^ and v^ (and the update's own rounding), the
+activated value against the parameter's bound through the activation's
+slope.  The chained gradient of a log-scale or logit goes through exp, add
+and divide roundings, inside the same 2e-6.  Three steps with fresh
+gradients, each step starting from the GPU's binary32 state."""
+import numpy as np
+import pytest
+
+from gpu_common import PARAM_KEYS, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(V, H, W, seed):
+    rng = np.random.default_rng(seed)
+    y = rng.uniform(0.0, 1.0, (V, 3, H, W))
+    # smooth target plus a rendered image with a bit of everything
+    x = np.clip(y + rng.normal(0.0, 0.08, y.shape), 0.0, 1.0)
+    x[..., : H // 3, :] = y[..., : H // 3, :]  # identical band: sign(0) and SSIM = 1 there
+    return x.astype(np.float32), y.astype(np.float32)
+
+
+@pytest.mark.parametrize("V,H,W", [(1, 32, 48), (2, 37, 53), (1, 5, 7), (1, 1, 1), (1, 64, 33),
+                                   (1, 540, 960)])
+def test_color_loss_matches_oracle(V, H, W):
+    import torch
+    from oracle import train
+    from paper_2512_02932_amd.rasterizer import color_loss
+    x, y = _pair(V, H, W, seed=V * 7 + H * 3 + W)
+    grad, losses = color_loss(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), 0.2)
+    torch.cuda.synchronize()
+    grad, losses = grad.cpu().numpy(), losses.cpu().numpy()
+    ref = train.color_loss(x.astype(np.float64), y.astype(np.float64), 0.2)
+    assert losses[0] == pytest.approx(ref["l1"], rel=1e-6, abs=1e-12)
+    assert losses[1] == pytest.approx(ref["dssim"], rel=5e-5, abs=1e-9)
+    err = float(np.abs(grad - ref["grad"]).max())
+    scale = float(np.abs(ref["grad"]).max())
+    assert err <= 2e-4 * scale + 1e-30, (err, scale)
+    say(f"[train] colour loss {V}x{H}x{W}: L1 {losses[0]:.6f} D-SSIM {losses[1]:.6f}, "
+        f"grad err {err / max(scale, 1e-30):.2e} of max")
+
+
+def test_color_loss_of_identical_images_is_zero():
+    import torch
+    from paper_2512_02932_amd.rasterizer import color_loss
+    rng = np.random.default_rng(5)
+    x = torch.from_numpy(rng.uniform(0, 1, (1, 3, 40, 40)).astype(np.float32)).cuda()
+    grad, losses = color_loss(x, x.clone(), 0.2)
+    torch.cuda.synchronize()
+    assert abs(float(losses[0])) == 0.0
+    assert abs(float(losses[1])) <= 1e-6
+    assert float(grad.abs().max()) <= 1e-6 / (3 * 40 * 40)
+
+
+def _adam_state(n, deg, seed):
+    rng = np.random.default_rng(seed)
+    K = (deg + 1) ** 2
+    raw = {"means": rng.normal(size=(n, 3)), "scales": rng.normal(-4, 1, (n, 3)),
+           "rotations": rng.normal(size=(n, 4)), "opacities": rng.normal(size=(n,)),
+           "sh": rng.normal(0, 0.3, (n, K, 3))}
+    raw = {k: v.astype(np.float32) for k, v in raw.items()}
+    return raw, rng
+
+
+LR = dict(lr_means=1.6e-4, lr_scales=5e-3, lr_rotations=1e-3, lr_opacities=2.5e-2,
+          lr_sh_dc=2.5e-3, lr_sh_rest=2.5e-3 / 20)
+
+
+def _oracle_lr(K):
+    return {"means": LR["lr_means"], "scales": LR["lr_scales"], "rotations": LR["lr_rotations"],
+            "opacities": LR["lr_opacities"],
+            "sh": np.array([LR["lr_sh_dc"]] + [LR["lr_sh_rest"]] * (K - 1))[:, None]}
+
+
+@pytest.mark.parametrize("n,deg", [(1001, 3), (5, 0), (1, 1)])
+def test_adam_matches_oracle(n, deg):
+    import torch
+    from oracle import train
+    from paper_2512_02932_amd.rasterizer import adam_step
+    K = (deg + 1) ** 2
+    raw, rng = _adam_state(n, deg, seed=n + deg)
+    dev = {k: torch.from_numpy(v.copy()).cuda() for k, v in raw.items()}
+    m = {k: torch.zeros_like(v) for k, v in dev.items()}
+    v = {k: torch.zeros_like(x) for k, x in dev.items()}
+    act = {k: torch.zeros_like(x) for k, x in dev.items()}
+    ref_raw = {k: x.astype(np.float64) for k, x in raw.items()}
+    ref_m = {k: np.zeros_like(x) for k, x in ref_raw.items()}
+    ref_v = {k: np.zeros_like(x) for k, x in ref_raw.items()}
+    for step in range(1, 4):
+        g = {k: rng.normal(size=x.shape).astype(np.float32) for k, x in raw.items()}
+        # the oracle starts from the GPU's binary32 state of the previous
+        # step, so each step is compared on its own
+        cur = {k: t.cpu().numpy().astype(np.float64) for k, t in dev.items()}
+        cm = {k: t.cpu().numpy().astype(np.float64) for k, t in m.items()}
+        cv = {k: t.cpu().numpy().astype(np.float64) for k, t in v.items()}
+        adam_step(n, deg, dev, {k: torch.from_numpy(x).cuda() for k, x in g.items()}, m, v, step,
+                  activated=act, **LR)
+        torch.cuda.synchronize()
+        r_raw, r_m, r_v, r_act = train.adam_step(cur, g, cm, cv, step, _oracle_lr(K))
+        b1, b2, eps = 0.9, 0.999, 1e-15
+        bc1, bc2 = 1.0 / (1.0 - b1 ** step), 1.0 / (1.0 - b2 ** step)
+        u = 2e-6  # a few binary32 roundings per term
+        for k in PARAM_KEYS:
+            lr = np.broadcast_to(np.asarray(_oracle_lr(K)[k], np.float64), r_raw[k].shape)
+            gr = g[k].astype(np.float64)  # the chained raw gradient, for the bounds only
+            if k == "scales":
+                gr = gr * np.exp(cur[k])
+            elif k == "opacities":
+                sg = 1.0 / (1.0 + np.exp(-cur[k]))
+                gr = gr * sg * (1.0 - sg)
+            tol_m = u * (b1 * np.abs(cm[k]) + (1 - b1) * np.abs(gr))
+            tol_v = u * (b2 * cv[k] + (1 - b2) * gr * gr)
+            mh, vh = r_m[k] * bc1, r_v[k] * bc2
+            sq = np.sqrt(vh)
+            # the update lr m^/(sqrt v^ + eps) moves with m^ and v^; p rounds once
+            tol_p = u * np.abs(cur[k]) + lr * ((tol_m * bc1 + u * np.abs(mh)) / (sq + eps) +
+                                               np.abs(mh) * tol_v * bc2 /
+                                               np.maximum(2 * sq * (sq + eps) ** 2, 1e-300))
+            # the activated value carries the parameter's error through the
+            # activation's slope (1, exp itself, sigmoid <= 1/4)
+            slope = np.abs(r_act[k]) if k == "scales" else 1.0
+            for got, want, tol in ((dev[k], r_raw[k], tol_p), (m[k], r_m[k], tol_m),
+                                   (v[k], r_v[k], tol_v),
+                                   (act[k], r_act[k], tol_p * slope + u * np.abs(r_act[k]))):
+                gg = got.cpu().numpy().astype(np.float64)
+                bad = np.abs(gg - want) > tol + 1e-30
+                assert not bad.any(), (k, step, np.argwhere(bad)[:3].tolist(), gg[bad][:3],
+                                       want[bad][:3])
+        ref_raw = r_raw
+    say(f"[train] adam n={n} deg={deg}: 3 steps ok")
+
+
+def test_adam_skips_null_arrays_and_activated():
+    import torch
+    from paper_2512_02932_amd.rasterizer import adam_step
+    n, deg = 100, 3
+    raw, rng = _adam_state(n, deg, seed=3)
+    dev = {k: torch.from_numpy(v.copy()).cuda() for k, v in raw.items()}
+    g = {k: torch.from_numpy(rng.normal(size=x.shape).astype(np.float32)).cuda()
+         for k, x in raw.items()}
+    m = {k: torch.zeros_like(x) for k, x in dev.items()}
+    v = {k: torch.zeros_like(x) for k, x in dev.items()}
+    part = {k: t for k, t in dev.items() if k != "rotations"}
+    adam_step(n, deg, part, g, m, v, 1, **LR)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(dev["rotations"].cpu().numpy(), raw["rotations"])
+    assert float(m["rotations"].abs().max()) == 0.0
+    assert not np.array_equal(dev["means"].cpu().numpy(), raw["means"])
+
+
+def test_bad_arguments():
+    import torch
+    from paper_2512_02932_amd import _hgs as H
+    from paper_2512_02932_amd.rasterizer import get_rasterizer
+    rast = get_rasterizer(0)
+    p = torch.zeros(64, device="cuda").data_ptr()
+    with pytest.raises(H.HGSError) as e:
+        H.hgs_color_loss(rast.ctx, 1, 4, 4, p, p, 1.5, 0, 0, 0)
+    assert e.value.status == H.HGS_EINVAL
+    with pytest.raises(H.HGSError) as e:
+        H.hgs_color_loss(rast.ctx, 1, 4, 4, 0, p, 0.2, 0, 0, 0)
+    assert e.value.status == H.HGS_EINVAL
+    H.hgs_color_loss(rast.ctx, 0, 4, 4, 0, 0, 0.2, 0, 0, 0)  # empty: no-op
+    g = H.hgs_grads()
+    g.means = p
+    z = H.hgs_grads()
+    o = H.hgs_adam_opts(beta1=0.9, beta2=0.999, eps=1e-15, step=1)
+    with pytest.raises(H.HGSError) as e:
+        H.hgs_adam_step(rast.ctx, 4, 3, g, z, z, z, None, o, 0)  # means without grad/moments
+    assert e.value.status == H.HGS_EINVAL
+    o.step = 0
+    with pytest.raises(H.HGSError) as e:
+        H.hgs_adam_step(rast.ctx, 4, 3, z, z, z, z, None, o, 0)
+    assert e.value.status == H.HGS_EINVAL
