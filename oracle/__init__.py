@@ -31,7 +31,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 DEFAULT_OPTS = dict(bg=(0.0, 0.0, 0.0), dilation=0.3, lambda_z=1.0, theta_z=1.05,
-                    temp_z=0.001)
+                    temp_z=0.001, pix_off=(0.0, 0.0))
 
 
 def build(force: bool = True) -> str:
@@ -60,6 +60,8 @@ def _load():
                                         [P] * 5)
         _lib.oracle_backward.argtypes = ([P] * 6 + [C.c_int64, C.c_int] + [P] * 5 +
                                          [P, C.c_int, P, P, C.c_int64, P, C.c_int] + [P] * 5)
+        _lib.oracle_screen_grad.argtypes = ([P] * 6 + [C.c_int64, C.c_int] + [P] * 5 +
+                                            [P, C.c_int, P, P, C.c_int64, P, C.c_int, P])
         _lib.oracle_sh_basis.argtypes = [C.c_int, P, C.c_int64, P]
         _lib.oracle_surfel_uv.argtypes = [P, P, P, C.c_int64, P]
         _lib.oracle_erank.argtypes = [C.c_double, C.c_double, C.c_double]
@@ -88,8 +90,8 @@ def pack_cams(cams) -> np.ndarray:
 def _opts_vec(opts):
     o = dict(DEFAULT_OPTS)
     o.update(opts or {})
-    return np.array(list(o["bg"]) + [o["dilation"], o["lambda_z"], o["theta_z"], o["temp_z"]],
-                    np.float64)
+    return np.array(list(o["bg"]) + [o["dilation"], o["lambda_z"], o["theta_z"], o["temp_z"]] +
+                    list(o["pix_off"]), np.float64)
 
 
 def _f32(scene):
@@ -209,6 +211,44 @@ def backward(scene, cams, pix, G, opts=None, *, params64=None, threads=None):
                 opacities_abs=ap[:, 10], sh_abs=as_, means_cond=cp_[:, 0:3],
                 scales_cond=cp_[:, 3:6], rotations_cond=cp_[:, 6:10], opacities_cond=cp_[:, 10],
                 sh_cond=as_)
+
+
+def screen_grad(scene, cams, pix, G, opts=None, *, params64=None, threads=None):
+    """dL/d delta [V, N, 2] (binary64): the gradient of L = sum_p <G_p, out_p>
+    with respect to a translation of each splat's screen footprint (pixel
+    units) in each view."""
+    lib = _load()
+    m, s, r, o, sh, t = _f32(scene)
+    m6, s6, r6, o6, sh6 = _f64(scene, params64)
+    cp = pack_cams(cams)
+    pix = np.ascontiguousarray(pix, np.int32)
+    G = np.ascontiguousarray(G, np.float64)
+    n = m.shape[0]
+    V = cp.shape[0]
+    out = np.zeros((V, n, 2), np.float64)
+    lib.oracle_screen_grad(_p(m), _p(s), _p(r), _p(o), _p(sh), _p(t), n,
+                           int(scene["sh_degree"]), _p(m6), _p(s6), _p(r6), _p(o6), _p(sh6),
+                           _p(cp), V, _p(_opts_vec(opts)), _p(pix), pix.shape[0], _p(G),
+                           int(threads or os.cpu_count() or 1), _p(out))
+    return out
+
+
+def densify_stats(scene, cams, pix, G, opts=None):
+    """3DGS's densification statistics for one backward: per splat, the sum
+    over the views in which it is not culled of |dL/d(screen centre)| in
+    NDC units (the pixel-unit gradient times (W/2, H/2)), and the number of
+    those views.  Returns (grad_norm [N], count [N])."""
+    if isinstance(cams, dict):
+        cams = [cams]
+    sg = screen_grad(scene, cams, pix, G, opts)
+    st = structural(scene, cams, (opts or {}).get("dilation", DEFAULT_OPTS["dilation"]))
+    n = sg.shape[1]
+    valid = st["valid"].reshape(len(cams), n) == 1
+    norm = np.zeros(n)
+    for v, c in enumerate(cams):
+        nd = np.hypot(sg[v, :, 0] * c["width"] / 2.0, sg[v, :, 1] * c["height"] / 2.0)
+        norm += np.where(valid[v], nd, 0.0)
+    return norm, valid.sum(0).astype(np.int64)
 
 
 def sh_basis(degree, dirs):

@@ -46,6 +46,7 @@
 // so no FMA is ever formed in the structural module).
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -95,6 +96,7 @@ struct Opts {
   double bg[3];
   float dilation;
   double lambda_z, theta_z, temp_z;
+  double pix_off[2];  // offset of every pixel sample (0 for rendering; finite-difference pins)
 };
 
 Opts load_opts(const double *o) {
@@ -102,6 +104,7 @@ Opts load_opts(const double *o) {
   p.bg[0] = o[0]; p.bg[1] = o[1]; p.bg[2] = o[2];
   p.dilation = (float)o[3];
   p.lambda_z = o[4]; p.theta_z = o[5]; p.temp_z = o[6];
+  p.pix_off[0] = o[7]; p.pix_off[1] = o[8];
   return p;
 }
 
@@ -690,7 +693,7 @@ void render_pixel(const Work &w, const SplatCache &cache, int v, int x, int y,
                   const Margins &mg, PixelOut &po, std::vector<PairRec> &seq) {
   const int64_t N = w.s32->n;
   const CamD &cd = w.camd[v];
-  const double px = x + 0.5, py = y + 0.5;
+  const double px = x + 0.5 + w.opt.pix_off[0], py = y + 0.5 + w.opt.pix_off[1];
   std::vector<PairRec> cand;
   Splat<double> tmp;
   auto consider = [&](int64_t g) {
@@ -907,7 +910,7 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
       PixelOut po;
       render_pixel(w, cache, v, x, y, mg, po, seq);
       const double *Gp = G + 8 * i;
-      const double px = x + 0.5, py = y + 0.5;
+      const double px = x + 0.5 + w.opt.pix_off[0], py = y + 0.5 + w.opt.pix_off[1];
       const int m = (int)seq.size();
       // forward transmittances and per-pair scalar f_i
       std::vector<Splat<Dual>> sps(m);
@@ -1006,6 +1009,120 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
         g_sh[g * 3 * K + j] += c[3 * NP + j];
         a_sh[g * 3 * K + j] += c[3 * NP + 3 * K + j];
       }
+    }
+  }
+  return 0;
+}
+
+// Screen-space translation gradient of every (view, splat) for
+// L = sum over the listed pixels of <G, out>.  Translating splat (v, g)'s
+// screen footprint by delta means evaluating it at p - delta, so
+//   dL/d delta = - sum_p [dL/dalpha~ d alpha~/dp + dL/ddepth d depth/dp]
+// over the splat's blended pairs (alpha~ = alpha_eff exp(-d/2) unless it is
+// clamped, where it does not move).  3D: d = D^T Q D with D = p - mu', so
+// dd/dp = 2 Q D, and the depth is fixed.  2D: (u, v, kappa) solve
+// M (u, v, kappa) = -p_c with M = [s_x t_u | s_y t_v | -omega],
+// omega = ((px - cx)/fx, (py - cy)/fy, 1); differentiating M x = r in
+// omega_k gives d(u, v, kappa)/d omega_k = kappa M^{-1} e_k; d = u^2 + v^2,
+// depth = kappa.  out: [V*n, 2], binary64.
+int oracle_screen_grad(const float *m32, const float *s32, const float *r32, const float *o32,
+                       const float *sh32, const uint8_t *types, int64_t n, int sh_degree,
+                       const double *m64, const double *s64, const double *r64,
+                       const double *o64, const double *sh64, const float *cams, int V,
+                       const double *opts, const int32_t *pix, int64_t P, const double *G,
+                       int threads, double *out) {
+  Scene32 sc32{m32, s32, r32, o32, sh32, types, n, sh_degree};
+  Scene64 sc64{m64, s64, r64, o64, sh64};
+  Work w;
+  w.s32 = &sc32;
+  w.s64 = &sc64;
+  w.opt = load_opts(opts);
+  build(w, cams, V, false);
+  const Margins mg{0, 0, 0};
+  SplatCache cache;
+  if (4 * P >= n) build_cache(w, cache, threads);
+  const int nt = std::max(1, threads);
+  std::vector<std::unordered_map<int64_t, std::array<double, 2>>> acc(nt);
+  parallel_for(P, threads, [&](int t, int64_t a, int64_t b) {
+    std::vector<PairRec> seq;
+    Splat<double> tmp;
+    for (int64_t i = a; i < b; ++i) {
+      const int v = pix[3 * i], y = pix[3 * i + 1], x = pix[3 * i + 2];
+      PixelOut po;
+      render_pixel(w, cache, v, x, y, mg, po, seq);
+      const double *Gp = G + 8 * i;
+      const CamD &cd = w.camd[v];
+      const double px = x + 0.5 + w.opt.pix_off[0], py = y + 0.5 + w.opt.pix_off[1];
+      const int m = (int)seq.size();
+      std::vector<double> T(m + 1), f(m), dgx(m), dgy(m), ddx(m), ddy(m);
+      T[0] = 1.0;
+      for (int j = 0; j < m; ++j) {
+        const Splat<double> &sp = get_splat(w, cache, v, seq[j].g, tmp);
+        double d, dep;
+        eval_pair<double>(sp, cd, px, py, d, dep);
+        T[j + 1] = T[j] * (1.0 - seq[j].alpha);
+        f[j] = Gp[0] * sp.color[0] + Gp[1] * sp.color[1] + Gp[2] * sp.color[2] + Gp[4] * dep +
+               Gp[5] * sp.nrm[0] + Gp[6] * sp.nrm[1] + Gp[7] * sp.nrm[2];
+        // d(d)/dp and d(depth)/dp
+        if (!sp.is2d) {
+          const double D0 = px - sp.mu2[0], D1 = py - sp.mu2[1];
+          ddx[j] = 2.0 * (sp.conic[0] * D0 + sp.conic[1] * D1);
+          ddy[j] = 2.0 * (sp.conic[1] * D0 + sp.conic[2] * D1);
+          dgx[j] = dgy[j] = 0.0;
+        } else {
+          const double om[3] = {(px - cd.cx) / cd.fx, (py - cd.cy) / cd.fy, 1.0};
+          double u, vv, kap;
+          surfel_hit<double>(sp, om, u, vv, kap);
+          double A[3], B[3], Mo[3];
+          for (int k = 0; k < 3; ++k) {
+            A[k] = sp.sx * sp.tu[k];
+            B[k] = sp.sy * sp.tv[k];
+            Mo[k] = -om[k];
+          }
+          auto det3 = [](const double *c0, const double *c1, const double *c2) {
+            return c0[0] * (c1[1] * c2[2] - c1[2] * c2[1]) -
+                   c0[1] * (c1[0] * c2[2] - c1[2] * c2[0]) +
+                   c0[2] * (c1[0] * c2[1] - c1[1] * c2[0]);
+          };
+          const double Dm = det3(A, B, Mo);
+          double dx3[2][3];  // d(u, v, kappa)/d(px), d(py)
+          for (int k = 0; k < 2; ++k) {
+            double e[3] = {0, 0, 0};
+            e[k] = 1.0;
+            const double sc = kap / (k == 0 ? cd.fx : cd.fy);
+            dx3[k][0] = sc * det3(e, B, Mo) / Dm;
+            dx3[k][1] = sc * det3(A, e, Mo) / Dm;
+            dx3[k][2] = sc * det3(A, B, e) / Dm;
+          }
+          ddx[j] = 2.0 * u * dx3[0][0] + 2.0 * vv * dx3[0][1];
+          ddy[j] = 2.0 * u * dx3[1][0] + 2.0 * vv * dx3[1][1];
+          dgx[j] = dx3[0][2];
+          dgy[j] = dx3[1][2];
+        }
+      }
+      double Ssuf = Gp[0] * w.opt.bg[0] + Gp[1] * w.opt.bg[1] + Gp[2] * w.opt.bg[2] - Gp[3];
+      for (int j = m - 1; j >= 0; --j) {
+        const double al = seq[j].alpha;
+        const double dLda = T[j] * (f[j] - Ssuf);
+        Ssuf = f[j] * al + (1.0 - al) * Ssuf;
+        const double wgt = al * T[j];
+        const double da = seq[j].clamped ? 0.0 : -0.5 * seq[j].raw;  // d alpha~ / d d
+        const double gx = dLda * da * ddx[j] + Gp[4] * wgt * dgx[j];
+        const double gy = dLda * da * ddy[j] + Gp[4] * wgt * dgy[j];
+        auto &c = acc[t][(int64_t)v * n + seq[j].g];
+        c[0] -= gx;
+        c[1] -= gy;
+      }
+    }
+  });
+  std::memset(out, 0, sizeof(double) * (size_t)V * n * 2);
+  for (int t = 0; t < nt; ++t) {
+    std::vector<std::pair<int64_t, std::array<double, 2>>> order(acc[t].begin(), acc[t].end());
+    std::sort(order.begin(), order.end(),
+              [](const auto &a, const auto &b) { return a.first < b.first; });
+    for (const auto &e : order) {
+      out[2 * e.first] += e.second[0];
+      out[2 * e.first + 1] += e.second[1];
     }
   }
   return 0;
