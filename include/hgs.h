@@ -210,7 +210,8 @@ enum {
   HGS_STAGE_FDO_PROJECT = 11,
   HGS_STAGE_COLOR_LOSS = 12,
   HGS_STAGE_ADAM = 13,
-  HGS_N_STAGES = 14
+  HGS_STAGE_DENSIFY = 14,
+  HGS_N_STAGES = 15
 };
 hgs_status hgs_profile_enable(hgs_ctx *ctx, int32_t on);
 hgs_status hgs_profile_read(hgs_ctx *ctx, double *ms, int64_t *calls, int32_t reset);
@@ -341,6 +342,19 @@ hgs_status hgs_adam_step(hgs_ctx *ctx, int64_t n, int32_t sh_degree, const hgs_g
                          const hgs_grads *grads, const hgs_grads *exp_avg,
                          const hgs_grads *exp_avg_sq, const hgs_grads *activated,
                          const hgs_adam_opts *opts, void *stream);
+
+/* Densification statistics of 3DGS (the paper adopts its densification,
+ * appendix "Implementation Details") for the last backward run on `state`
+ * (hgs_render_backward or hgs_render_backward_fdo; with FDO, of the sum
+ * of the three losses).  Per view in which splat g is not culled:
+ *   grad_norm[g] += |dL/d delta| in NDC units, delta a translation of the
+ *                   splat's screen footprint ((W/2, H/2) times the pixel
+ *                   gradient);
+ *   count[g]     += 1.
+ * grad_norm, count: device f32 [N] (either may be NULL), added into.
+ * Errors: EINVAL, ESTATE (no backward yet, other context), EHIP. */
+hgs_status hgs_densify_stats(hgs_ctx *ctx, hgs_state *state, float *grad_norm, float *count,
+                             void *stream);
 
 /* ---------------------------------------------------------------------
  * Batched serving.

@@ -19,11 +19,11 @@ EXPORTS = ("hgs_create", "hgs_destroy", "hgs_scene_init", "hgs_scene_release", "
            "hgs_state_check", "hgs_last_error", "hgs_profile_enable", "hgs_profile_read",
            "hgs_server_create", "hgs_server_destroy", "hgs_server_submit", "hgs_server_poll",
            "hgs_server_stats", "hgs_type_exchange", "hgs_fdo_cotangents", "hgs_fdo_project",
-           "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step")
+           "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step", "hgs_densify_stats")
 
 STAGES = ("preprocess", "scan", "duplicate", "sort", "ranges", "raster_fwd", "raster_bwd",
           "preprocess_bwd", "fill", "depth_sort", "fdo_cotangents", "fdo_project", "color_loss",
-          "adam")
+          "adam", "densify")
 
 
 class hgs_scene_desc(C.Structure):
@@ -132,6 +132,7 @@ def load(path: str | None = None):
                                     C.POINTER(hgs_grads), P, P]
     lib.hgs_render_backward_fdo.argtypes = [P, P, C.POINTER(hgs_grad_images), P, P,
                                             C.POINTER(hgs_grads), P, P, P]
+    lib.hgs_densify_stats.argtypes = [P, P, P, P, P]
     lib.hgs_color_loss.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_double, P, P, P]
     lib.hgs_adam_step.argtypes = [P, C.c_int64, C.c_int32] + [C.POINTER(hgs_grads)] * 4 + \
         [P, C.POINTER(hgs_adam_opts), P]
@@ -140,7 +141,7 @@ def load(path: str | None = None):
                  "hgs_profile_enable", "hgs_profile_read", "hgs_server_create",
                  "hgs_server_submit", "hgs_server_poll", "hgs_server_stats",
                  "hgs_type_exchange", "hgs_fdo_cotangents", "hgs_fdo_project",
-                 "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step"):
+                 "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step", "hgs_densify_stats"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -293,3 +294,8 @@ def hgs_adam_step(ctx, n: int, sh_degree: int, raw, grads, m, v, act, opts, stre
                                C.byref(m), C.byref(v),
                                None if act is None else C.cast(C.pointer(act), C.c_void_p),
                                C.byref(opts), C.c_void_p(stream)))
+
+
+def hgs_densify_stats(ctx, state, norm_ptr: int, count_ptr: int, stream: int):
+    check(load().hgs_densify_stats(ctx, state, C.c_void_p(norm_ptr), C.c_void_p(count_ptr),
+                                   C.c_void_p(stream)))

@@ -48,6 +48,10 @@ struct hgs_state {
   float *T_final = nullptr;
   uint32_t *last = nullptr, *n_contrib = nullptr, *wcount = nullptr;
   int64_t D = 0;
+  // accumulator planes of the last backward on this state (workspace arena 2)
+  const float *accum_last = nullptr;
+  int accum_planes = 0;
+  int64_t accum_plane = 0;
   Workspace *ws = nullptr;
   std::vector<std::pair<void **, size_t>> plan;  // buffers awaiting commit()
 };
@@ -597,6 +601,9 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_image
     launch_raster_bwd(st->ranges, st->vals, st->rec, st->n_tiles, st->W, st->H, st->tiles_x,
                       st->tiles_per_view, st->opt, st->T_final, st->last, gi, accum, s);
   }
+  st->accum_last = accum;
+  st->accum_planes = 1;
+  st->accum_plane = VN * kGradSlots;
   {
     StageTimer t(ctx, HGS_STAGE_PREPROCESS_BWD, s);
     launch_preprocess_bwd(st->scene, st->cams, st->V, st->opt, st->flags, st->rect, accum,
@@ -677,6 +684,9 @@ hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *st, const hgs_grad_i
                            st->tiles_per_view, st->opt, st->T_final, st->last, gi, x, accum, plane,
                            s);
   }
+  st->accum_last = accum;
+  st->accum_planes = 3;
+  st->accum_plane = plane;
   {
     StageTimer t(ctx, HGS_STAGE_PREPROCESS_BWD, s);
     for (int k = 0; k < 3; ++k)
@@ -842,6 +852,24 @@ hgs_status hgs_adam_step(hgs_ctx *ctx, int64_t n, int32_t sh_degree, const hgs_g
   StageTimer t(ctx, HGS_STAGE_ADAM, s);
   launch_adam(a, ctx->n_cu, s);
   HGS_HIP(hipGetLastError());
+  return HGS_OK;
+}
+
+hgs_status hgs_densify_stats(hgs_ctx *ctx, hgs_state *st, float *grad_norm, float *count,
+                             void *stream) {
+  if (!ctx || !st) return fail(HGS_EINVAL, "ctx or state is NULL");
+  if (st->device != ctx->device) return fail(HGS_ESTATE, "state belongs to another context");
+  if (!st->accum_last) return fail(HGS_ESTATE, "no backward has run on this state");
+  HGS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  HGS_HIP(join_streams(s, st->stream));
+  {
+    StageTimer t(ctx, HGS_STAGE_DENSIFY, s);
+    launch_densify_stats(st->V, st->N, st->flags, st->rec, st->accum_last, st->accum_plane,
+                         st->accum_planes, st->W, st->H, grad_norm, count, ctx->n_cu, s);
+  }
+  HGS_HIP(hipGetLastError());
+  HGS_HIP(join_streams(st->stream, s));
   return HGS_OK;
 }
 

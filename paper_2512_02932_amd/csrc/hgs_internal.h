@@ -238,4 +238,11 @@ struct AdamArgs {
 };
 void launch_adam(const AdamArgs &a, int n_cu, hipStream_t s);
 
+// Densification statistics from n_planes accumulator planes ([V*N, 16]
+// each, `plane` floats apart): grad_norm[g] += |dL/d screen centre| in NDC
+// units and count[g] += 1 per view in which splat g is not culled.
+void launch_densify_stats(int64_t V, int64_t N, const uint8_t *flags, const Record *rec,
+                          const float *accum, int64_t plane, int n_planes, int W, int H,
+                          float *grad_norm, float *count, int n_cu, hipStream_t s);
+
 }  // namespace hgs

@@ -20,6 +20,9 @@
 // Blocks stride over the tiles and add their loss sums with one binary64
 // atomic per sum per block.
 //
+// Densification statistics: |dL/d(screen centre)| per view and splat from
+// the last backward's accumulators (below).
+//
 // Adam (Kingma and Ba) on the raw 3DGS parameters (means, log-scales,
 // quaternions, opacity logits, SH) from the gradients with respect to the
 // activated values the rasterizer returns: dL/ds_raw = exp(s_raw) dL/ds,
@@ -258,7 +261,65 @@ adam_kernel(AdamArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Densification statistics (3DGS): per (view, splat) not culled, the norm
+// of dL/d delta, delta a translation of the splat's screen footprint, in
+// NDC units, and a count of 1.  From the accumulator slots of the last
+// backward (summed over its cotangent planes):
+//   3D: dL/d delta = (slot 0, slot 1), the gradient of the pixel-space
+//       centre the exponent is measured from;
+//   2D: the record's inverse map H (pixel -> plane) becomes H T(-delta), so
+//       dL/d delta_c = - sum_k G[k][2] H[k][c] (c = x, y), where G[k][2] =
+//       slot 3k + 2 = dL/d(row k's constant term).
+// ---------------------------------------------------------------------------
+constexpr uint8_t kFlagValid = 1;  // bit 0 of the preprocess flags byte: not culled
+
+__global__ void __launch_bounds__(256)
+densify_stats_kernel(int64_t VN, int64_t N, const uint8_t *__restrict__ flags,
+                     const Record *__restrict__ rec, const float *__restrict__ accum,
+                     int64_t plane, int n_planes, float half_w, float half_h,
+                     float *__restrict__ grad_norm, float *__restrict__ count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < VN;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (!(flags[i] & kFlagValid)) continue;
+    const int64_t g = i % N;
+    float sl[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sl[k] = 0.0f;
+    for (int p = 0; p < n_planes; ++p) {
+      const float *a = accum + p * plane + i * kGradSlots;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sl[k] += a[k];
+    }
+    const float4 r4 = rec[i].r[4];
+    float gx, gy;
+    if (__float_as_uint(r4.w) >> 31) {  // 2D
+      const float4 r1 = rec[i].r[1], r2 = rec[i].r[2];
+      // H rows: (r1.x r1.y r1.z), (r1.w r2.x r2.y), (r2.z r2.w r3.x)
+      gx = -(sl[2] * r1.x + sl[5] * r1.w + sl[8] * r2.z);
+      gy = -(sl[2] * r1.y + sl[5] * r2.x + sl[8] * r2.w);
+    } else {
+      gx = sl[0];
+      gy = sl[1];
+    }
+    if (grad_norm) unsafeAtomicAdd(grad_norm + g, hypotf(gx * half_w, gy * half_h));
+    if (count) unsafeAtomicAdd(count + g, 1.0f);
+  }
+}
+
 }  // namespace
+
+void launch_densify_stats(int64_t V, int64_t N, const uint8_t *flags, const Record *rec,
+                          const float *accum, int64_t plane, int n_planes, int W, int H,
+                          float *grad_norm, float *count, int n_cu, hipStream_t s) {
+  const int64_t VN = V * N;
+  if (VN <= 0) return;
+  int64_t grid = (VN + 255) / 256;
+  if (grid > 16 * (int64_t)n_cu) grid = 16 * (int64_t)n_cu;
+  hipLaunchKernelGGL(densify_stats_kernel, dim3((unsigned)grid), dim3(256), 0, s, VN, N, flags,
+                     rec, accum, plane, n_planes, 0.5f * (float)W, 0.5f * (float)H, grad_norm,
+                     count);
+}
 
 Win11 gauss_win11() {
   Win11 w;

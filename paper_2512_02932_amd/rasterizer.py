@@ -196,6 +196,12 @@ class Rasterizer:
         s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         H.hgs_render_backward(self.ctx, state.handle, gi, g, s)
 
+    def densify_stats(self, state: State, grad_norm=None, count=None, stream=None):
+        """3DGS densification statistics of the last backward on `state`
+        (``hgs_densify_stats``): adds into float32 [N] tensors."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        H.hgs_densify_stats(self.ctx, state.handle, _ptr(grad_norm), _ptr(count), s)
+
     def backward_fdo(self, state: State, grad_color: dict, grad_low_rgb, grad_high_rgb,
                      update: dict, sets=None, accumulate=False, n_conflict=None, stream=None):
         """Alg. 1's backward (``hgs_render_backward_fdo``): three cotangent
