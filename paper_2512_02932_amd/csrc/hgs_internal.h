@@ -235,6 +235,8 @@ struct AdamArgs {
   int64_t off[6];
   float lr[5], lr_sh_rest, beta1, beta2, omb1, omb2, eps, bc1, bc2;  // omb = 1 - beta
   int64_t sh_stride;  // 3 K: SH elements of one primitive (the first 3 are DC)
+  int64_t blk[6];     // set by launch_adam: blocks [blk[s], blk[s+1]) serve array s
+  int vec[5];         // set by launch_adam: array s is 16-byte aligned throughout
 };
 void launch_adam(const AdamArgs &a, int n_cu, hipStream_t s);
 

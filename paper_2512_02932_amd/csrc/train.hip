@@ -224,39 +224,60 @@ ssim_bwd_kernel(TileGrid g, Win11 win, const float *__restrict__ xs, const float
 // Adam.  Segment s of the flattened parameter space is array s of the five
 // (means, scales, rotations, opacities, sh).
 // ---------------------------------------------------------------------------
+// One element of array s: the chained raw gradient, both moments, the new
+// raw value and its activation.
+__device__ __forceinline__ void adam_one(const AdamArgs &a, int s, int64_t i, float p, float gr,
+                                         float m0, float v0, float &np, float &m, float &v,
+                                         float &av) {
+  float lr = a.lr[s];
+  if (s == 1) {
+    gr *= expf(p);
+  } else if (s == 3) {  // sigmoid' = sigmoid(p) sigmoid(-p): no cancellation near 1
+    gr *= (1.0f / (1.0f + expf(-p))) * (1.0f / (1.0f + expf(p)));
+  } else if (s == 4 && (i % a.sh_stride) >= 3) {
+    lr = a.lr_sh_rest;
+  }
+  m = a.beta1 * m0 + a.omb1 * gr;
+  v = a.beta2 * v0 + a.omb2 * gr * gr;
+  np = p - lr * (m * a.bc1) / (sqrtf(v * a.bc2) + a.eps);
+  av = s == 1 ? expf(np) : (s == 3 ? 1.0f / (1.0f + expf(-np)) : np);
+}
+
+// Blocks [blk[s], blk[s+1]) serve array s, one float4 of it per thread
+// (16-byte loads and stores when all of that array's pointers allow them,
+// element by element otherwise and for the ragged end).
 __global__ void __launch_bounds__(256)
 adam_kernel(AdamArgs a) {
-  const int64_t total = a.off[5];
-  const float c1 = a.bc1, c2 = a.bc2;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int s = 0;
+  int s = 0;
 #pragma unroll
-    for (int k = 1; k < 5; ++k) s += e >= a.off[k] ? 1 : 0;
-    const int64_t i = e - a.off[s];
-    if (!a.raw[s] || !a.grad[s]) continue;
-    const float p = a.raw[s][i];
-    float gr = a.grad[s][i];
-    float lr = a.lr[s];
-    if (s == 1) {
-      gr *= expf(p);
-    } else if (s == 3) {  // sigmoid' = sigmoid(p) sigmoid(-p): no cancellation near 1
-      gr *= (1.0f / (1.0f + expf(-p))) * (1.0f / (1.0f + expf(p)));
-    } else if (s == 4 && (i % a.sh_stride) >= 3) {
-      lr = a.lr_sh_rest;
-    }
-    const float m = a.beta1 * a.m[s][i] + a.omb1 * gr;
-    const float v = a.beta2 * a.v[s][i] + a.omb2 * gr * gr;
-    const float mh = m * c1, vh = v * c2;
-    const float np = p - lr * mh / (sqrtf(vh) + a.eps);
-    a.m[s][i] = m;
-    a.v[s][i] = v;
-    a.raw[s][i] = np;
-    if (a.act[s]) {
-      float av = np;
-      if (s == 1) av = expf(np);
-      else if (s == 3) av = 1.0f / (1.0f + expf(-np));
-      a.act[s][i] = av;
+  for (int k = 1; k < 5; ++k) s += (int64_t)blockIdx.x >= a.blk[k] ? 1 : 0;
+  if (!a.raw[s] || !a.grad[s]) return;
+  const int64_t len = a.off[s + 1] - a.off[s];
+  const int64_t e0 = 4 * (((int64_t)blockIdx.x - a.blk[s]) * blockDim.x + threadIdx.x);
+  if (e0 >= len) return;
+  float *act = a.act[s];
+  if (a.vec[s] && e0 + 4 <= len) {
+    const float4 p4 = *reinterpret_cast<const float4 *>(a.raw[s] + e0);
+    const float4 g4 = *reinterpret_cast<const float4 *>(a.grad[s] + e0);
+    const float4 m4 = *reinterpret_cast<const float4 *>(a.m[s] + e0);
+    const float4 v4 = *reinterpret_cast<const float4 *>(a.v[s] + e0);
+    float4 np, nm, nv, av;
+    adam_one(a, s, e0, p4.x, g4.x, m4.x, v4.x, np.x, nm.x, nv.x, av.x);
+    adam_one(a, s, e0 + 1, p4.y, g4.y, m4.y, v4.y, np.y, nm.y, nv.y, av.y);
+    adam_one(a, s, e0 + 2, p4.z, g4.z, m4.z, v4.z, np.z, nm.z, nv.z, av.z);
+    adam_one(a, s, e0 + 3, p4.w, g4.w, m4.w, v4.w, np.w, nm.w, nv.w, av.w);
+    *reinterpret_cast<float4 *>(a.raw[s] + e0) = np;
+    *reinterpret_cast<float4 *>(a.m[s] + e0) = nm;
+    *reinterpret_cast<float4 *>(a.v[s] + e0) = nv;
+    if (act) *reinterpret_cast<float4 *>(act + e0) = av;
+  } else {
+    for (int64_t i = e0; i < e0 + 4 && i < len; ++i) {
+      float np, nm, nv, av;
+      adam_one(a, s, i, a.raw[s][i], a.grad[s][i], a.m[s][i], a.v[s][i], np, nm, nv, av);
+      a.raw[s][i] = np;
+      a.m[s][i] = nm;
+      a.v[s][i] = nv;
+      if (act) act[i] = av;
     }
   }
 }
@@ -338,7 +359,8 @@ void launch_ssim_fwd(int64_t planes, int H, int W, const float *x, const float *
   if (planes <= 0 || H <= 0 || W <= 0) return;
   TileGrid g{H, W, (W + kSsimTile - 1) / kSsimTile, (H + kSsimTile - 1) / kSsimTile, planes};
   const int64_t n_tiles = planes * g.tiles_x * g.tiles_y;
-  int64_t grid = n_tiles < 2 * (int64_t)n_cu ? n_tiles : 2 * (int64_t)n_cu;
+  // 42 KB of LDS per block: three blocks per CU
+  int64_t grid = n_tiles < 3 * (int64_t)n_cu ? n_tiles : 3 * (int64_t)n_cu;
   const double m = (double)planes * H * W;
   hipLaunchKernelGGL(ssim_fwd_kernel, dim3((unsigned)grid), dim3(kSsimThreads), 0, s, g,
                      gauss_win11(), x, y, Am, Bm, Cm, 1.0 / m, losses);
@@ -357,12 +379,20 @@ void launch_ssim_bwd(int64_t planes, int H, int W, const float *x, const float *
                      (float)(lambda / m), grad);
 }
 
-void launch_adam(const AdamArgs &a, int n_cu, hipStream_t s) {
-  const int64_t total = a.off[5];
-  if (total <= 0) return;
-  int64_t grid = (total + 255) / 256;
-  if (grid > 16 * (int64_t)n_cu) grid = 16 * (int64_t)n_cu;
-  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)grid), dim3(256), 0, s, a);
+void launch_adam(const AdamArgs &a0, int n_cu, hipStream_t s) {
+  (void)n_cu;
+  AdamArgs a = a0;
+  auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+  a.blk[0] = 0;
+  for (int k = 0; k < 5; ++k) {
+    const int64_t len = a.off[k + 1] - a.off[k];
+    const int64_t quads = (len + 3) / 4;
+    a.blk[k + 1] = a.blk[k] + (a.raw[k] && a.grad[k] ? (quads + 255) / 256 : 0);
+    a.vec[k] = al16(a.raw[k]) && al16(a.grad[k]) && al16(a.m[k]) && al16(a.v[k]) &&
+               (!a.act[k] || al16(a.act[k]));
+  }
+  if (a.blk[5] <= 0) return;
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)a.blk[5]), dim3(256), 0, s, a);
 }
 
 }  // namespace hgs
