@@ -110,12 +110,13 @@ def _pool_get(pool, srv_or_rast, H, W):
         srv_or_rast.alloc_images(H, W)
 
 
-def serving(rast, n_warm=200, n_meas=2000, rate=200.0, check=20):
-    """Served-view latency on four resident scenes with Poisson arrivals.
-    The same request trace is replayed (a) through the batched server (one
-    graph-captured pass per batch, batches in flight on several streams) and
-    (b) as one plain render launch per request.  Latency = completion -
-    arrival, over the measured requests."""
+def serving(rast, n_warm=200, n_meas=2000, rates=(200.0, 800.0), check=20):
+    """Served-view latency on four resident scenes with Poisson arrivals, at
+    a light and a heavy load.  At each rate the same request trace is
+    replayed (a) through the batched server (one graph-captured pass per
+    batch, batches in flight on several streams) and (b) as one plain render
+    launch per request.  Latency = completion - arrival, over the measured
+    requests."""
     import numpy as np
     import torch
     import scenegen as sg
@@ -127,6 +128,26 @@ def serving(rast, n_warm=200, n_meas=2000, rate=200.0, check=20):
     sids = [rast.scene_init(to_device(sc), copy_resident=True) for sc in scenes]
     n_gauss = [int(sc["means"].shape[0]) for sc in scenes]
     del scenes
+    results = {}
+    for rate in rates:
+        results[rate] = _serve_rate(rast, sids, n_warm, n_meas, rate, check)
+    for sid in sids:
+        rast.scene_release(sid)
+    base = results[rates[0]]
+    out = {"workload": f"4 resident scenes ({'/'.join(str(n) for n in n_gauss)} Gaussians, SH3), "
+                       f"Poisson arrivals, {n_warm} warm-up + {n_meas} measured requests per rate, "
+                       "resolutions 256^2/512^2/1280x720/1920x1080, orbit r in [3,5]",
+           "rate_req_per_s": rates[0], **base}
+    for rate in rates[1:]:
+        out[f"at_{int(rate)}_req_per_s"] = results[rate]
+    return out
+
+
+def _serve_rate(rast, sids, n_warm, n_meas, rate, check):
+    import numpy as np
+    import torch
+    import scenegen as sg
+    from paper_2512_02932_amd.serving import Server
     reqs = sg.serving_requests(n_warm + n_meas, rate=rate, seed=45)
     px = np.array([r["camera"]["width"] * r["camera"]["height"] for r in reqs], np.float64)
     torch.cuda.synchronize()
@@ -185,21 +206,14 @@ def serving(rast, n_warm=200, n_meas=2000, rate=200.0, check=20):
             res["rerendered"] = st["rerendered"]
         return res, out_imgs
 
-    log("[serving] batched graph server")
+    log(f"[serving] {rate:g} req/s: batched graph server")
     b, b_imgs = run(True)
     log(f"[serving] batched {b}")
-    log("[serving] one launch per request")
+    log(f"[serving] {rate:g} req/s: one launch per request")
     p, p_imgs = run(False)
     log(f"[serving] per-request {p}")
     diff = max(float((b_imgs[k] - p_imgs[k]).abs().max()) for k in b_imgs)
-    for sid in sids:
-        rast.scene_release(sid)
-    return {"workload": f"4 resident scenes ({'/'.join(str(n) for n in n_gauss)} Gaussians, SH3), "
-                        f"Poisson {rate:g} req/s, {n_warm} warm-up + {n_meas} measured, "
-                        "resolutions 256^2/512^2/1280x720/1920x1080, orbit r in [3,5]",
-            "batched_graph": b, "one_launch_per_request": p,
-            "max_abs_diff_batched_vs_plain": diff}
-
+    return {"batched_graph": b, "one_launch_per_request": p, "max_abs_diff_batched_vs_plain": diff}
 
 def exchange_leg(scene_np, workload, copies=8, replays=5):
     """Adaptive Type Exchange, timed alone on the knot scene's own
