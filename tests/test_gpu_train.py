@@ -261,3 +261,80 @@ def test_densify_stats_needs_a_backward():
         rast.densify_stats(state, torch.zeros(100, device="cuda"))
     assert e.value.status == H.HGS_ESTATE
     state.free()
+
+
+# ---------------------------------------------------------------------------
+# Full size: the launch configuration the benchmark times (1M hybrid
+# Gaussians, SH3, 1920x1080).
+# ---------------------------------------------------------------------------
+def test_full_size_color_loss_1080p():
+    test_color_loss_matches_oracle(1, 1080, 1920)
+
+
+def test_full_size_adam_1m():
+    import torch
+    from oracle import train
+    from paper_2512_02932_amd.rasterizer import adam_step
+    n, deg = 1_000_000, 3
+    K = (deg + 1) ** 2
+    raw, rng = _adam_state(n, deg, seed=77)
+    dev = {k: torch.from_numpy(v.copy()).cuda() for k, v in raw.items()}
+    m = {k: torch.zeros_like(v) for k, v in dev.items()}
+    v = {k: torch.zeros_like(x) for k, x in dev.items()}
+    act = {k: torch.zeros_like(x) for k, x in dev.items()}
+    g = {k: rng.normal(size=x.shape).astype(np.float32) for k, x in raw.items()}
+    adam_step(n, deg, dev, {k: torch.from_numpy(x).cuda() for k, x in g.items()}, m, v, 1,
+              activated=act, **LR)
+    torch.cuda.synchronize()
+    z = {k: np.zeros(x.shape) for k, x in raw.items()}
+    r_raw, r_m, r_v, r_act = train.adam_step({k: x.astype(np.float64) for k, x in raw.items()},
+                                             g, z, z, 1, _oracle_lr(K))
+    for k in PARAM_KEYS:
+        lr = np.broadcast_to(np.asarray(_oracle_lr(K)[k], np.float64), r_raw[k].shape)
+        # first step from zero moments: m = (1-b1) g, v = (1-b2) g^2, p - lr g/|g|
+        for got, want, tol in ((dev[k], r_raw[k], 2e-6 * np.abs(raw[k]) + 2e-6 * lr),
+                               (m[k], r_m[k], 2e-6 * np.abs(r_m[k])),
+                               (v[k], r_v[k], 2e-6 * np.abs(r_v[k]))):
+            gg = got.cpu().numpy().astype(np.float64)
+            assert (np.abs(gg - want) <= tol + 1e-30).all(), k
+    say("[train] adam at 1M SH3: ok")
+
+
+def test_full_size_densify_1m_1080p_sampled():
+    """Cotangents on 1500 sampled non-tie pixels of the 1080p image; the
+    oracle evaluates those pixels only."""
+    import torch
+    import oracle
+    import scenegen as sg
+    from gpu_common import IMG_KEYS, pack_G_all
+    from paper_2512_02932_amd.rasterizer import get_rasterizer, to_device
+    scene = sg.scene_torus_knot()
+    cam = sg.camera_torus_knot_1080p()
+    N = scene["means"].shape[0]
+    rng = np.random.default_rng(9)
+    pix = np.stack([np.zeros(4000, np.int64), rng.integers(0, 1080, 4000),
+                    rng.integers(0, 1920, 4000)], 1).astype(np.int32)
+    res = oracle.forward(scene, cam, pix)
+    sel = pix[res["tie"] == 0][:1500]
+    G = {k: np.zeros((1, c, 1080, 1920), np.float32)
+         for k, c in (("rgb", 3), ("alpha", 1), ("depth", 1), ("normal", 3))}
+    Gs = sg.upstream_grads(1, 1, len(sel), seed=11)
+    for k in IMG_KEYS:
+        G[k][0][:, sel[:, 1], sel[:, 2]] = Gs[k][0][:, 0, :]
+    rast = get_rasterizer(0)
+    sc = to_device(scene)
+    _, state = rast.render(sc, cam, want_state=True)
+    grads = {k: torch.zeros_like(sc[k]) for k in PARAM_KEYS}
+    rast.backward(state, {k: torch.from_numpy(v).cuda() for k, v in G.items()}, grads)
+    norm = torch.zeros(N, device="cuda")
+    cnt = torch.zeros(N, device="cuda")
+    rast.densify_stats(state, norm, cnt)
+    torch.cuda.synchronize()
+    state.free()
+    ref_norm, ref_cnt = oracle.densify_stats(scene, cam, sel, pack_G_all(G, sel))
+    np.testing.assert_array_equal(cnt.cpu().numpy(), ref_cnt)
+    got = norm.cpu().numpy()
+    bad = np.abs(got - ref_norm) > 2e-3 * ref_norm + 2e-5 * ref_norm.max()
+    assert not bad.any(), (int(bad.sum()), got[bad][:5], ref_norm[bad][:5])
+    say(f"[train] densify at 1M / 1080p: {int((ref_norm > 0).sum())} splats touched by the "
+        f"sampled cotangents, {int(ref_cnt.sum())} visible")
