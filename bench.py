@@ -215,6 +215,30 @@ def _serve_rate(rast, sids, n_warm, n_meas, rate, check):
     diff = max(float((b_imgs[k] - p_imgs[k]).abs().max()) for k in b_imgs)
     return {"batched_graph": b, "one_launch_per_request": p, "max_abs_diff_batched_vs_plain": diff}
 
+def time_steps(rast, step, steps, prof_steps=5):
+    """Whole-step time of `steps` steps with stage profiling off, then the
+    per-launch stage times (HIP events on the launch stream) from
+    `prof_steps` further steps with it on, so the events are not part of
+    the timed work.  Returns (ms per step, {stage: ms per launch})."""
+    import torch
+    from paper_2512_02932_amd import _hgs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _hgs.hgs_profile_enable(rast.ctx, True)
+    _hgs.hgs_profile_read(rast.ctx, reset=True)
+    for _ in range(prof_steps):
+        step()
+    torch.cuda.synchronize()
+    prof = _hgs.hgs_profile_read(rast.ctx, reset=True)
+    _hgs.hgs_profile_enable(rast.ctx, False)
+    stage = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
+    return (t1 - t0) * 1e3 / steps, stage
+
+
 def exchange_leg(scene_np, workload, copies=8, replays=5):
     """Adaptive Type Exchange, timed alone on the knot scene's own
     parameters and on a 16M-primitive set of the same scale distribution.
@@ -331,17 +355,8 @@ def fdo_leg(rast, sc, cam, images, G, counts, N, K, steps, warmup, workload):
         step()
     torch.cuda.synchronize()
     cnt.zero_()
-    _hgs.hgs_profile_enable(rast.ctx, True)
-    _hgs.hgs_profile_read(rast.ctx, reset=True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = _hgs.hgs_profile_read(rast.ctx, reset=True)
-    _hgs.hgs_profile_enable(rast.ctx, False)
-    ms = (t1 - t0) * 1e3 / steps
-    stage = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
+    ms, stage = time_steps(rast, step, steps)
+    n_conf = int(cnt.item()) // (steps + 5)
     P = 11 + 3 * K
     cot_bytes = 3 * H * W * 16
     proj_bytes = N * (3 * 4 * P + 1 + 4 * P)
@@ -356,7 +371,7 @@ def fdo_leg(rast, sc, cam, images, G, counts, N, K, steps, warmup, workload):
 
     tops = ops / (stage["raster_bwd"] * 1e-3) / 1e12
     out = {"ms_per_step": round(ms, 4), "mpix_per_s": round(H * W / (ms * 1e-3) / 1e6, 3),
-           "conflicts_per_step": int(cnt.item()) // steps, "gaussians": N,
+           "conflicts_per_step": n_conf, "gaussians": N,
            "losses_last": [float(x) / (steps + warmup) for x in losses.cpu().tolist()],
            "stage_ms": {k: round(v, 4) for k, v in stage.items()},
            "preprocess_bwd_launches_per_step": 3,
@@ -426,18 +441,9 @@ def train_leg(rast, scene_np, cam, steps, warmup, workload):
     torch.cuda.synchronize()
     l0 = losses.cpu().numpy() / max(warmup, 1)
     losses.zero_()
-    _hgs.hgs_profile_enable(rast.ctx, True)
-    _hgs.hgs_profile_read(rast.ctx, reset=True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = _hgs.hgs_profile_read(rast.ctx, reset=True)
-    _hgs.hgs_profile_enable(rast.ctx, False)
-    ms = (t1 - t0) * 1e3 / steps
-    stage = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1] > 0}
-    l1 = losses.cpu().numpy() / steps
+    ms, stage = time_steps(rast, step, steps)
+    stage = {k: round(v, 4) for k, v in stage.items()}
+    l1 = losses.cpu().numpy() / (steps + 5)
     K = (deg + 1) ** 2
     adam_bytes = N * (11 + 3 * K) * 4 * 8  # raw, grad, m, v read; raw, m, v, activated written
     ssim_bytes = 3 * H * W * (8 + 12 + 12 + 8 + 4)  # images, A/B/C out and in, images, grad
@@ -530,17 +536,8 @@ def main():
     st.free()
     torch.cuda.synchronize()
 
-    _hgs.hgs_profile_enable(rast.ctx, True)
-    _hgs.hgs_profile_read(rast.ctx, reset=True)
     log(f"[bench] timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = _hgs.hgs_profile_read(rast.ctx, reset=True)
-    _hgs.hgs_profile_enable(rast.ctx, False)
+    ms, stage_ms = time_steps(rast, step, args.steps)
 
     if args.calib_copy_mb > 0:
         n = args.calib_copy_mb * (1 << 20) // 4
@@ -551,10 +548,8 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calib_copy_mb} MiB done")
 
-    ms = (t1 - t0) * 1e3 / args.steps
     P = H * W
     value = P / (ms * 1e-3) / 1e6
-    stage_ms = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
     log("[bench] per-launch ms: " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
     log(f"[bench] counts {counts} D={sizes['D']}")
 
