@@ -211,7 +211,8 @@ enum {
   HGS_STAGE_COLOR_LOSS = 12,
   HGS_STAGE_ADAM = 13,
   HGS_STAGE_DENSIFY = 14,
-  HGS_N_STAGES = 15
+  HGS_STAGE_FDO_WEIGHTS = 15,
+  HGS_N_STAGES = 16
 };
 hgs_status hgs_profile_enable(hgs_ctx *ctx, int32_t on);
 hgs_status hgs_profile_read(hgs_ctx *ctx, double *ms, int64_t *calls, int32_t reset);
@@ -289,8 +290,14 @@ hgs_status hgs_fdo_project(hgs_ctx *ctx, int64_t n, int32_t sh_degree, const uin
  * types) into `update`.  sets: NULL (workspace), or hgs_grads[3] whose
  * arrays receive g_color, g_low, g_high before the projection
  * (overwritten; every array required).  n_conflict as in
- * hgs_fdo_project.  The scene's parameters must be unchanged since the
- * forward.  Errors: EINVAL, ESTATE, ENOMEM, EHIP. */
+ * hgs_fdo_project.  With one view and sets == NULL the three sets are not
+ * stored: a first pass over the primitives forms g_low and g_high (rounded
+ * to binary32 as stored gradients would be), takes Alg. 1's dot products
+ * and weights, and a second pass applies the backward to the slots
+ * combined in binary64 with those weights (the backward is linear in
+ * them) and rounds the update once.  The scene's parameters must be
+ * unchanged since the forward.
+ * Errors: EINVAL, ESTATE, ENOMEM, EHIP. */
 hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *state,
                                    const hgs_grad_images *grad_color, const float *grad_low_rgb,
                                    const float *grad_high_rgb, const hgs_grads *update,

@@ -521,22 +521,347 @@ preprocess_slots_kernel(const Slot *__restrict__ slots, const int *__restrict__ 
 //   3D: 0 mx, 1 my, 2 A, 3 B, 4 C, 5 depth z, 9 alpha_eff, 10-12 rgb, 13-15 n
 //   2D: 0-8 H (stored, scaled) entries, 9 alpha_eff, 10-12 rgb, 13-15 n
 // ---------------------------------------------------------------------------
-template <int DEG, bool MULTI>
-__global__ void __launch_bounds__(128)
-preprocess_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOpts opt,
-                      const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
-                      const float *__restrict__ accum, float *g_means, float *g_scales,
-                      float *g_rots, float *g_opac, float *g_sh, int accumulate) {
+// One view's geometric chain: the record slots a -> dL/d mu (through the
+// camera-space centre), dL/d s, dL/d q (raw quaternion) and dL/d opacity,
+// added to gmu, gs, gq, gal.  Linear in a.
+template <typename T>
+__device__ __forceinline__ void geo_chain(const Geo &o, const DevCam &c, const DevOpts &opt,
+                                          const T (&a)[kGradSlots], uint8_t fl, bool is2d,
+                                          float al32, double *gmu, double *gs, double *gq,
+                                          double &gal) {
+  const double k2 = sqrt(0.5 * kLog2e);
+  const int axis = (fl >> 2) & 3;
+
+  double gpc[3] = {0, 0, 0};  // dL/d p_c
+  double gRvR[9];             // dL/d (R_v R)
+#pragma unroll
+  for (int j = 0; j < 9; ++j) gRvR[j] = 0.0;
+  double gsv[3] = {0, 0, 0};  // dL/d s (this view)
+
+  // normal: n = sign * (R_v R)[:, axis]
+  const double sg = (fl & kFlip) ? -1.0 : 1.0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double gn = sg * (double)a[13 + r];
+    gRvR[3 * r] += axis == 0 ? gn : 0.0;
+    gRvR[3 * r + 1] += axis == 1 ? gn : 0.0;
+    gRvR[3 * r + 2] += axis == 2 ? gn : 0.0;
+  }
+
+  const double X = o.pc[0], Yc = o.pc[1], Z = o.pc[2];
+  const double fx = c.fx, fy = c.fy;
+  if (!is2d) {
+    // conic entries (A, B, C stored = k c00, 2k c01, k c11 with k = log2e/2)
+    const double kk = 0.5 * kLog2e;
+    const double G00 = kk * a[2], G01 = kk * a[3], G11 = kk * a[4];
+    // dL/dSigma' = -Q G Q, G = [[G00, G01], [G01, G11]]
+    const double *Q = o.conic;
+    const double t00 = Q[0] * G00 + Q[1] * G01, t01 = Q[0] * G01 + Q[1] * G11;
+    const double t10 = Q[1] * G00 + Q[2] * G01, t11 = Q[1] * G01 + Q[2] * G11;
+    const double S00 = -(t00 * Q[0] + t01 * Q[1]);
+    const double S01 = -(t00 * Q[1] + t01 * Q[2]);
+    const double S11 = -(t10 * Q[1] + t11 * Q[2]);
+    const double J00 = fx / Z, J02 = -fx * X / (Z * Z), J11 = fy / Z, J12 = -fy * Yc / (Z * Z);
+    double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      // Sigma' = A A^T: dL/dA = 2 S A
+      const double gA0 = 2.0 * (S00 * o.A[j] + S01 * o.A[3 + j]);
+      const double gA1 = 2.0 * (S01 * o.A[j] + S11 * o.A[3 + j]);
+      const double c0 = o.RvR[j] * o.s[j], c1 = o.RvR[3 + j] * o.s[j], c2 = o.RvR[6 + j] * o.s[j];
+      gJ00 += gA0 * c0;
+      gJ02 += gA0 * c2;
+      gJ11 += gA1 * c1;
+      gJ12 += gA1 * c2;
+      const double gc0 = gA0 * J00, gc1 = gA1 * J11, gc2 = gA0 * J02 + gA1 * J12;
+      gRvR[j] += gc0 * o.s[j];
+      gRvR[3 + j] += gc1 * o.s[j];
+      gRvR[6 + j] += gc2 * o.s[j];
+      gsv[j] += gc0 * o.RvR[j] + gc1 * o.RvR[3 + j] + gc2 * o.RvR[6 + j];
+    }
+    const double iz = 1.0 / Z, iz2 = iz * iz, iz3 = iz2 * iz;
+    const double gmx = a[0], gmy = a[1];
+    gpc[0] += gJ02 * (-fx * iz2) + gmx * fx * iz;
+    gpc[1] += gJ12 * (-fy * iz2) + gmy * fy * iz;
+    gpc[2] += gJ00 * (-fx * iz2) + gJ02 * (2.0 * fx * X * iz3) + gJ11 * (-fy * iz2) +
+              gJ12 * (2.0 * fy * Yc * iz3) - gmx * fx * X * iz2 - gmy * fy * Yc * iz2 +
+              (double)a[5];
+    gal += (double)a[9];
+  } else {
+    // stored h = D Hi (rows 0, 1 scaled by k2); Hi = M^{-1}; dL/dM = -Hi^T gH Hi^T
+    double gH[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) gH[j] = (double)a[j] * (j < 6 ? k2 : 1.0);
+    double T1[9];  // Hi^T gH
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+        T1[3 * r + cc] = o.Hi[r] * gH[cc] + o.Hi[3 + r] * gH[3 + cc] + o.Hi[6 + r] * gH[6 + cc];
+    // M = K' Cm: dL/dCm = K'^T gM with gM = -T1 Hi^T
+    const double cxl = c.cx - o.ox, cyl = c.cy - o.oy;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double gM0 = -(T1[0] * o.Hi[3 * j] + T1[1] * o.Hi[3 * j + 1] + T1[2] * o.Hi[3 * j + 2]);
+      const double gM1 = -(T1[3] * o.Hi[3 * j] + T1[4] * o.Hi[3 * j + 1] + T1[5] * o.Hi[3 * j + 2]);
+      const double gM2 = -(T1[6] * o.Hi[3 * j] + T1[7] * o.Hi[3 * j + 1] + T1[8] * o.Hi[3 * j + 2]);
+      const double gC0 = fx * gM0, gC1 = fy * gM1;
+      const double gC2 = cxl * gM0 + cyl * gM1 + gM2;
+      if (j < 2) {  // Cm[:, j] = s_j (R_v R)[:, j]
+        gRvR[j] += gC0 * o.s[j];
+        gRvR[3 + j] += gC1 * o.s[j];
+        gRvR[6 + j] += gC2 * o.s[j];
+        gsv[j] += gC0 * o.RvR[j] + gC1 * o.RvR[3 + j] + gC2 * o.RvR[6 + j];
+      } else {  // Cm[:, 2] = p_c
+        gpc[0] += gC0;
+        gpc[1] += gC1;
+        gpc[2] += gC2;
+      }
+    }
+    const double ga_eff = (double)a[9];
+    gal += ga_eff * (o.alpha_eff / (double)al32);
+    const double dsz =
+        o.gate_sig + o.s[2] * o.gate_sig * (1.0 - o.gate_sig) / (double)opt.temp_z;
+    gsv[2] += ga_eff * o.alpha_eff * (-(double)opt.lambda_z) * dsz;
+  }
+
+  // p_c = V mu + t
+  const double *Vd = c.Vd;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gmu[k] += Vd[k] * gpc[0] + Vd[4 + k] * gpc[1] + Vd[8 + k] * gpc[2];
+  // RvR = V R: dL/dR = V^T gRvR
+  double gR[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+      gR[3 * r + cc] = Vd[r] * gRvR[cc] + Vd[4 + r] * gRvR[3 + cc] + Vd[8 + r] * gRvR[6 + cc];
+  // R(q) for a unit quaternion q = (w, x, y, z)
+  const double w = o.q[0], x = o.q[1], y = o.q[2], z = o.q[3];
+  const double gqn[4] = {
+      2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]),
+      2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] + z * gR[6] +
+             w * gR[7] - 2.0 * x * gR[8]),
+      2.0 * (-2.0 * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
+             z * gR[7] - 2.0 * y * gR[8]),
+      2.0 * (-2.0 * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * z * gR[4] +
+             y * gR[5] + x * gR[6] + y * gR[7])};
+  // q = r / |r|
+  const double dq = gqn[0] * o.q[0] + gqn[1] * o.q[1] + gqn[2] * o.q[2] + gqn[3] * o.q[3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) gq[k] += (gqn[k] - o.q[k] * dq) / o.qn;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gs[k] += gsv[k];
+}
+
+// Channels whose colour 1/2 + sum_j f_j,ch Y_j is not clamped at zero.
+template <int K>
+__device__ __forceinline__ void colour_live(const float *f, const double *Y, bool (&live)[3]) {
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    double acc = 0.5;
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc += (double)f[3 * j + ch] * Y[j];
+    live[ch] = acc > 0.0;
+  }
+}
+
+// One view's colour chain: dL/dc -> gy (dL/dc where unclamped; dL/d f_j,ch
+// is gy_ch Y_j) and dL/d mu through the view direction, added to gmu.
+// Linear in gcol.
+template <int DEG, typename T>
+__device__ __forceinline__ void colour_chain(const float *f, const double *Y, const double *dir,
+                                             double dist, const bool (&live)[3],
+                                             const T (&gcol)[3], T (&gy)[3], double *gmu) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  double wj[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) wj[j] = 0.0;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    gy[ch] = live[ch] ? gcol[ch] : T(0);
+    if (!live[ch]) continue;
+#pragma unroll
+    for (int j = 0; j < K; ++j) wj[j] += (double)gcol[ch] * (double)f[3 * j + ch];
+  }
+  double gdir[3];
+  sh_grad_dot<DEG>(dir[0], dir[1], dir[2], wj, gdir);
+  // dir = (mu - o) / |mu - o|
+  const double dd = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gmu[k] += (gdir[k] - dir[k] * dd) / dist;
+}
+
+// Modes of the kernel (the chain from slots to parameters is linear in the
+// slots):
+//   kBwdPlain   one slot plane -> gradients;
+//   kBwdFdoDots the FDO low and high planes (accum + plane, + 2 plane) ->
+//               per primitive g_low . g_high, |g_low|^2, |g_high|^2 over all
+//               parameters and Alg. 1's weights (w_low, w_high) into wts;
+//               one view only (the SH part of the dot products is then a
+//               product of per-channel factors and |Y|^2);
+//   kBwdFdoSum  the slots c + w_low l + w_high h of the three planes ->
+//               the Alg. 1 update, since g_c + w_l g_l + w_h g_h is the chain
+//               applied to that combination.
+constexpr int kBwdPlain = 0, kBwdFdoDots = 1, kBwdFdoSum = 2;
+
+template <int MODE, typename T>
+__device__ __forceinline__ void load_slots(const float *__restrict__ accum, int64_t plane,
+                                           int64_t i, int set, double2 w, T (&a)[kGradSlots]) {
+  const float4 *p0 = reinterpret_cast<const float4 *>(
+      accum + (MODE == kBwdFdoDots ? (int64_t)(set + 1) * plane : 0) + i * kGradSlots);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float4 t = p0[k];
+    a[4 * k] = t.x;
+    a[4 * k + 1] = t.y;
+    a[4 * k + 2] = t.z;
+    a[4 * k + 3] = t.w;
+  }
+  if constexpr (MODE == kBwdFdoSum) {
+    const float4 *p1 = reinterpret_cast<const float4 *>(accum + plane + i * kGradSlots);
+    const float4 *p2 = reinterpret_cast<const float4 *>(accum + 2 * plane + i * kGradSlots);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 u = p1[k], v = p2[k];
+      a[4 * k] += w.x * (double)u.x + w.y * (double)v.x;
+      a[4 * k + 1] += w.x * (double)u.y + w.y * (double)v.y;
+      a[4 * k + 2] += w.x * (double)u.z + w.y * (double)v.z;
+      a[4 * k + 3] += w.x * (double)u.w + w.y * (double)v.w;
+    }
+  }
+}
+
+// Alg. 1's weights for a primitive seen in one view, from the low and high
+// slot planes (accum + plane, accum + 2 plane).  g_low and g_high are formed
+// as the plain backward forms them and rounded to binary32 as stored
+// gradients are; d = g_low . g_high, |g_low|^2 and |g_high|^2 are summed in
+// binary64 over means, scales, rotations, opacity and SH.  If d < 0 a 2D
+// primitive (type 0) takes w_low = 1 - d / |g_low|^2 (Eq. 9: g_high loses
+// its component along g_low), a 3D one w_high = 1 - d / |g_high|^2 (Eq. 10);
+// otherwise both are 1.  Writes (w_low, w_high); returns d < 0.
+template <int DEG>
+__device__ __forceinline__ bool fdo_dots_body(const SceneDev &sc, const DevCam *__restrict__ cams,
+                                              const DevOpts &opt, const uint8_t *__restrict__ flags,
+                                              const int4 *__restrict__ rect,
+                                              const float *__restrict__ accum, int64_t plane,
+                                              int64_t g, double2 *__restrict__ wts) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  double d = 0.0, nl = 0.0, nh = 0.0;
+  const uint8_t fl = flags[g];
+  if (fl & kValid) {
+    float al[kGradSlots], ah[kGradSlots];
+    load_slots<kBwdFdoDots>(accum, plane, g, 0, make_double2(0.0, 0.0), al);
+    load_slots<kBwdFdoDots>(accum, plane, g, 1, make_double2(0.0, 0.0), ah);
+    bool anyl = false, anyh = false;
+#pragma unroll
+    for (int k = 0; k < kGradSlots; ++k) {
+      anyl = anyl || (al[k] != 0.0f);
+      anyh = anyh || (ah[k] != 0.0f);
+    }
+    if (anyl || anyh) {
+      const bool is2d = sc.types[g] == 0;
+      const float m[3] = {sc.means[3 * g], sc.means[3 * g + 1], sc.means[3 * g + 2]};
+      const float s[3] = {sc.scales[3 * g], sc.scales[3 * g + 1], sc.scales[3 * g + 2]};
+      const float4 q4 = reinterpret_cast<const float4 *>(sc.rots)[g];
+      const float q[4] = {q4.x, q4.y, q4.z, q4.w};
+      const float al32 = sc.opac[g];
+      const DevCam &c = cams[0];
+      double lmu[3] = {0, 0, 0}, ls[3] = {0, 0, 0}, lq[4] = {0, 0, 0, 0}, lo = 0.0;
+      double hmu[3] = {0, 0, 0}, hs[3] = {0, 0, 0}, hq[4] = {0, 0, 0, 0}, ho = 0.0;
+      {
+        const int4 rc = rect[g];
+        Geo o;
+        geo_setup(m, s, q, al32, is2d, c, opt, (double)rc.x, (double)rc.y, o);
+        if (anyl) geo_chain(o, c, opt, al, fl, is2d, al32, lmu, ls, lq, lo);
+        if (anyh) geo_chain(o, c, opt, ah, fl, is2d, al32, hmu, hs, hq, ho);
+      }
+      const float gcl[3] = {al[10], al[11], al[12]}, gch[3] = {ah[10], ah[11], ah[12]};
+      const bool coll = gcl[0] != 0.0f || gcl[1] != 0.0f || gcl[2] != 0.0f;
+      const bool colh = gch[0] != 0.0f || gch[1] != 0.0f || gch[2] != 0.0f;
+      if (coll || colh) {
+        double dir[3], dist;
+        view_dir(m, c, dir, dist);
+        double Y[K];
+        sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+        float f[3 * K];
+        load_sh<K>(sc.sh, g, f);
+        bool live[3];
+        colour_live<K>(f, Y, live);
+        float gyl[3] = {0.0f, 0.0f, 0.0f}, gyh[3] = {0.0f, 0.0f, 0.0f};
+        if (coll) colour_chain<DEG>(f, Y, dir, dist, live, gcl, gyl, lmu);
+        if (colh) colour_chain<DEG>(f, Y, dir, dist, live, gch, gyh, hmu);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            const double x = (float)((double)gyl[ch] * Y[j]);
+            const double y = (float)((double)gyh[ch] * Y[j]);
+            d = fma(x, y, d);
+            nl = fma(x, x, nl);
+            nh = fma(y, y, nh);
+          }
+      }
+      auto dot = [&](double lv, double hv) {
+        const double x = (float)lv, y = (float)hv;
+        d = fma(x, y, d);
+        nl = fma(x, x, nl);
+        nh = fma(y, y, nh);
+      };
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        dot(lmu[k], hmu[k]);
+        dot(ls[k], hs[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dot(lq[k], hq[k]);
+      dot(lo, ho);
+    }
+  }
+  double wl = 1.0, wh = 1.0;
+  const bool conflict = d < 0.0;
+  if (conflict) {
+    if (sc.types[g] == 0)
+      wl = 1.0 - d / nl;
+    else
+      wh = 1.0 - d / nh;
+  }
+  wts[g] = make_double2(wl, wh);
+  return conflict;
+}
+
+template <int DEG, bool MULTI, int MODE>
+__device__ __forceinline__ void preprocess_bwd_body(
+    const SceneDev &sc, const DevCam *__restrict__ cams, int V, const DevOpts &opt,
+    const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
+    const float *__restrict__ accum, int64_t plane, double2 *__restrict__ wts,
+    uint32_t *__restrict__ n_conflict, float *g_means, float *g_scales, float *g_rots,
+    float *g_opac, float *g_sh, int accumulate) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if constexpr (MODE == kBwdFdoDots) {
+    // conflicts of this block, added once per block
+    __shared__ uint32_t blk_conf;
+    if (threadIdx.x == 0) blk_conf = 0;
+    __syncthreads();
+    bool conf = false;
+    if (g < sc.n) conf = fdo_dots_body<DEG>(sc, cams, opt, flags, rect, accum, plane, g, wts);
+    const uint64_t m = __ballot(conf);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&blk_conf, (uint32_t)__popcll(m));
+    __syncthreads();
+    if (threadIdx.x == 0 && blk_conf && n_conflict) atomicAdd(n_conflict, blk_conf);
+    return;
+  } else {
   if (g >= sc.n) return;
+  const double2 wgt = MODE == kBwdFdoSum ? wts[g] : make_double2(0.0, 0.0);
+  // the combined slots are formed and kept in binary64
+  using Slot = typename std::conditional<MODE == kBwdFdoSum, double, float>::type;
   const bool is2d = sc.types[g] == 0;
   const float m[3] = {sc.means[3 * g], sc.means[3 * g + 1], sc.means[3 * g + 2]};
   const float s[3] = {sc.scales[3 * g], sc.scales[3 * g + 1], sc.scales[3 * g + 2]};
   const float4 q4 = reinterpret_cast<const float4 *>(sc.rots)[g];
   const float q[4] = {q4.x, q4.y, q4.z, q4.w};
   const float al32 = sc.opac[g];
-  const double k2 = sqrt(0.5 * kLog2e);
 
   double gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gal = 0.0;
 
@@ -545,16 +870,8 @@ preprocess_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOp
     const int64_t i = (int64_t)v * sc.n + g;
     const uint8_t fl = flags[i];
     if (!(fl & kValid)) continue;
-    float a[kGradSlots];
-    const float4 *ap = reinterpret_cast<const float4 *>(accum + i * kGradSlots);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float4 t = ap[k];
-      a[4 * k] = t.x;
-      a[4 * k + 1] = t.y;
-      a[4 * k + 2] = t.z;
-      a[4 * k + 3] = t.w;
-    }
+    Slot a[kGradSlots];
+    load_slots<MODE>(accum, plane, i, 0, wgt, a);
     bool any = false;
 #pragma unroll
     for (int k = 0; k < kGradSlots; ++k) any = any || (a[k] != 0.0f);
@@ -563,128 +880,7 @@ preprocess_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOp
     const int4 rc = rect[i];
     Geo o;
     geo_setup(m, s, q, al32, is2d, c, opt, (double)rc.x, (double)rc.y, o);
-    const int axis = (fl >> 2) & 3;
-
-    double gpc[3] = {0, 0, 0};  // dL/d p_c
-    double gRvR[9];             // dL/d (R_v R)
-#pragma unroll
-    for (int j = 0; j < 9; ++j) gRvR[j] = 0.0;
-    double gsv[3] = {0, 0, 0};  // dL/d s (this view)
-
-    // normal: n = sign * (R_v R)[:, axis]
-    const double sg = (fl & kFlip) ? -1.0 : 1.0;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const double gn = sg * (double)a[13 + r];
-      gRvR[3 * r] += axis == 0 ? gn : 0.0;
-      gRvR[3 * r + 1] += axis == 1 ? gn : 0.0;
-      gRvR[3 * r + 2] += axis == 2 ? gn : 0.0;
-    }
-
-    const double X = o.pc[0], Yc = o.pc[1], Z = o.pc[2];
-    const double fx = c.fx, fy = c.fy;
-    if (!is2d) {
-      // conic entries (A, B, C stored = k c00, 2k c01, k c11 with k = log2e/2)
-      const double kk = 0.5 * kLog2e;
-      const double G00 = kk * a[2], G01 = kk * a[3], G11 = kk * a[4];
-      // dL/dSigma' = -Q G Q, G = [[G00, G01], [G01, G11]]
-      const double *Q = o.conic;
-      const double t00 = Q[0] * G00 + Q[1] * G01, t01 = Q[0] * G01 + Q[1] * G11;
-      const double t10 = Q[1] * G00 + Q[2] * G01, t11 = Q[1] * G01 + Q[2] * G11;
-      const double S00 = -(t00 * Q[0] + t01 * Q[1]);
-      const double S01 = -(t00 * Q[1] + t01 * Q[2]);
-      const double S11 = -(t10 * Q[1] + t11 * Q[2]);
-      const double J00 = fx / Z, J02 = -fx * X / (Z * Z), J11 = fy / Z, J12 = -fy * Yc / (Z * Z);
-      double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        // Sigma' = A A^T: dL/dA = 2 S A
-        const double gA0 = 2.0 * (S00 * o.A[j] + S01 * o.A[3 + j]);
-        const double gA1 = 2.0 * (S01 * o.A[j] + S11 * o.A[3 + j]);
-        const double c0 = o.RvR[j] * o.s[j], c1 = o.RvR[3 + j] * o.s[j], c2 = o.RvR[6 + j] * o.s[j];
-        gJ00 += gA0 * c0;
-        gJ02 += gA0 * c2;
-        gJ11 += gA1 * c1;
-        gJ12 += gA1 * c2;
-        const double gc0 = gA0 * J00, gc1 = gA1 * J11, gc2 = gA0 * J02 + gA1 * J12;
-        gRvR[j] += gc0 * o.s[j];
-        gRvR[3 + j] += gc1 * o.s[j];
-        gRvR[6 + j] += gc2 * o.s[j];
-        gsv[j] += gc0 * o.RvR[j] + gc1 * o.RvR[3 + j] + gc2 * o.RvR[6 + j];
-      }
-      const double iz = 1.0 / Z, iz2 = iz * iz, iz3 = iz2 * iz;
-      const double gmx = a[0], gmy = a[1];
-      gpc[0] += gJ02 * (-fx * iz2) + gmx * fx * iz;
-      gpc[1] += gJ12 * (-fy * iz2) + gmy * fy * iz;
-      gpc[2] += gJ00 * (-fx * iz2) + gJ02 * (2.0 * fx * X * iz3) + gJ11 * (-fy * iz2) +
-                gJ12 * (2.0 * fy * Yc * iz3) - gmx * fx * X * iz2 - gmy * fy * Yc * iz2 +
-                (double)a[5];
-      gal += (double)a[9];
-    } else {
-      // stored h = D Hi (rows 0, 1 scaled by k2); Hi = M^{-1}; dL/dM = -Hi^T gH Hi^T
-      double gH[9];
-#pragma unroll
-      for (int j = 0; j < 9; ++j) gH[j] = (double)a[j] * (j < 6 ? k2 : 1.0);
-      double T1[9];  // Hi^T gH
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc)
-          T1[3 * r + cc] = o.Hi[r] * gH[cc] + o.Hi[3 + r] * gH[3 + cc] + o.Hi[6 + r] * gH[6 + cc];
-      // M = K' Cm: dL/dCm = K'^T gM with gM = -T1 Hi^T
-      const double cxl = c.cx - o.ox, cyl = c.cy - o.oy;
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const double gM0 = -(T1[0] * o.Hi[3 * j] + T1[1] * o.Hi[3 * j + 1] + T1[2] * o.Hi[3 * j + 2]);
-        const double gM1 = -(T1[3] * o.Hi[3 * j] + T1[4] * o.Hi[3 * j + 1] + T1[5] * o.Hi[3 * j + 2]);
-        const double gM2 = -(T1[6] * o.Hi[3 * j] + T1[7] * o.Hi[3 * j + 1] + T1[8] * o.Hi[3 * j + 2]);
-        const double gC0 = fx * gM0, gC1 = fy * gM1;
-        const double gC2 = cxl * gM0 + cyl * gM1 + gM2;
-        if (j < 2) {  // Cm[:, j] = s_j (R_v R)[:, j]
-          gRvR[j] += gC0 * o.s[j];
-          gRvR[3 + j] += gC1 * o.s[j];
-          gRvR[6 + j] += gC2 * o.s[j];
-          gsv[j] += gC0 * o.RvR[j] + gC1 * o.RvR[3 + j] + gC2 * o.RvR[6 + j];
-        } else {  // Cm[:, 2] = p_c
-          gpc[0] += gC0;
-          gpc[1] += gC1;
-          gpc[2] += gC2;
-        }
-      }
-      const double ga_eff = (double)a[9];
-      gal += ga_eff * (o.alpha_eff / (double)al32);
-      const double dsz =
-          o.gate_sig + o.s[2] * o.gate_sig * (1.0 - o.gate_sig) / (double)opt.temp_z;
-      gsv[2] += ga_eff * o.alpha_eff * (-(double)opt.lambda_z) * dsz;
-    }
-
-    // p_c = V mu + t
-    const double *Vd = c.Vd;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) gmu[k] += Vd[k] * gpc[0] + Vd[4 + k] * gpc[1] + Vd[8 + k] * gpc[2];
-    // RvR = V R: dL/dR = V^T gRvR
-    double gR[9];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc)
-        gR[3 * r + cc] = Vd[r] * gRvR[cc] + Vd[4 + r] * gRvR[3 + cc] + Vd[8 + r] * gRvR[6 + cc];
-    // R(q) for a unit quaternion q = (w, x, y, z)
-    const double w = o.q[0], x = o.q[1], y = o.q[2], z = o.q[3];
-    const double gqn[4] = {
-        2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]),
-        2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] + z * gR[6] +
-               w * gR[7] - 2.0 * x * gR[8]),
-        2.0 * (-2.0 * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
-               z * gR[7] - 2.0 * y * gR[8]),
-        2.0 * (-2.0 * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * z * gR[4] +
-               y * gR[5] + x * gR[6] + y * gR[7])};
-    // q = r / |r|
-    const double dq = gqn[0] * o.q[0] + gqn[1] * o.q[1] + gqn[2] * o.q[2] + gqn[3] * o.q[3];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) gq[k] += (gqn[k] - o.q[k] * dq) / o.qn;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) gs[k] += gsv[k];
+    geo_chain(o, c, opt, a, fl, is2d, al32, gmu, gs, gq, gal);
   }
 
   auto put = [&](float *dst, int64_t idx, double val) {
@@ -719,28 +915,22 @@ preprocess_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOp
   for (int v = 0; v < V; ++v) {
     const int64_t i = (int64_t)v * sc.n + g;
     if (!(flags[i] & kValid)) continue;
-    const float4 gc4 = reinterpret_cast<const float4 *>(accum + i * kGradSlots)[2];  // 8..11
-    const float gcl = reinterpret_cast<const float *>(accum + i * kGradSlots)[12];
-    const float gcol[3] = {gc4.z, gc4.w, gcl};
-    if (gcol[0] == 0.0f && gcol[1] == 0.0f && gcol[2] == 0.0f) continue;
+    const float *ap = accum + i * kGradSlots;
+    Slot gcol[3] = {ap[10], ap[11], ap[12]};
+    if constexpr (MODE == kBwdFdoSum) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch)
+        gcol[ch] += wgt.x * (double)ap[plane + 10 + ch] + wgt.y * (double)ap[2 * plane + 10 + ch];
+    }
+    if (gcol[0] == Slot(0) && gcol[1] == Slot(0) && gcol[2] == Slot(0)) continue;
     double dir[3], dist;
     view_dir(m, cams[v], dir, dist);
     double Y[K];
     sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
-    double wj[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) wj[j] = 0.0;
-    float gy[3] = {0.0f, 0.0f, 0.0f};  // dL/dc_ch where unclamped
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      double acc = 0.5;
-#pragma unroll
-      for (int j = 0; j < K; ++j) acc += (double)f[3 * j + ch] * Y[j];
-      if (!(acc > 0.0)) continue;  // clamped channel: no gradient
-      gy[ch] = gcol[ch];
-#pragma unroll
-      for (int j = 0; j < K; ++j) wj[j] += (double)gcol[ch] * (double)f[3 * j + ch];
-    }
+    bool live[3];
+    colour_live<K>(f, Y, live);
+    Slot gy[3];
+    colour_chain<DEG>(f, Y, dir, dist, live, gcol, gy, gmu);
     if constexpr (MULTI) {
 #pragma unroll
       for (int j = 0; j < K; ++j)
@@ -757,12 +947,6 @@ preprocess_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOp
         }
       wrote = true;
     }
-    double gdir[3];
-    sh_grad_dot<DEG>(dir[0], dir[1], dir[2], wj, gdir);
-    // dir = (mu - o) / |mu - o|
-    const double dd = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) gmu[k] += (gdir[k] - dir[k] * dd) / dist;
   }
   for (int k = 0; k < 3; ++k) put(g_means, 3 * g + k, gmu[k]);
   if (g_sh) {
@@ -777,8 +961,42 @@ preprocess_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOp
       }
     }
   }
+  }  // modes
 }
 
+template <int DEG, bool MULTI>
+__global__ void __launch_bounds__(128)
+preprocess_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOpts opt,
+                      const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
+                      const float *__restrict__ accum, float *g_means, float *g_scales,
+                      float *g_rots, float *g_opac, float *g_sh, int accumulate) {
+  preprocess_bwd_body<DEG, MULTI, kBwdPlain>(sc, cams, V, opt, flags, rect, accum, 0, nullptr,
+                                             nullptr, g_means, g_scales, g_rots, g_opac, g_sh,
+                                             accumulate);
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(128)
+fdo_weights_kernel(SceneDev sc, const DevCam *__restrict__ cams, DevOpts opt,
+                   const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
+                   const float *__restrict__ accum, int64_t plane, double2 *__restrict__ wts,
+                   uint32_t *__restrict__ n_conflict) {
+  preprocess_bwd_body<DEG, false, kBwdFdoDots>(sc, cams, 1, opt, flags, rect, accum, plane, wts,
+                                               n_conflict, nullptr, nullptr, nullptr, nullptr,
+                                               nullptr, 0);
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(128)
+fdo_combined_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, DevOpts opt,
+                        const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
+                        const float *__restrict__ accum, int64_t plane,
+                        double2 *__restrict__ wts, float *g_means, float *g_scales, float *g_rots,
+                        float *g_opac, float *g_sh, int accumulate) {
+  preprocess_bwd_body<DEG, false, kBwdFdoSum>(sc, cams, 1, opt, flags, rect, accum, plane, wts,
+                                              nullptr, g_means, g_scales, g_rots, g_opac, g_sh,
+                                              accumulate);
+}
 }  // namespace
 
 void launch_preprocess(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt, Record *rec,
@@ -804,32 +1022,59 @@ void launch_preprocess_slots(const Slot *slots, const int *n_slots, const uint64
                      0, s, slots, n_slots, n_inst, opt, inst_cap, rec, tiles, zbits, rect, flags);
 }
 
-template <int DEG>
-static void launch_bwd_deg(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt,
-                           const uint8_t *flags, const int4 *rect, const float *accum,
-                           float *g_means, float *g_scales, float *g_rots, float *g_opac,
-                           float *g_sh, int accumulate, hipStream_t s) {
-  const int bs = 128;
-  const dim3 grid((unsigned)((sc.n + bs - 1) / bs));
-  if (V == 1)
-    hipLaunchKernelGGL((preprocess_bwd_kernel<DEG, false>), grid, dim3(bs), 0, s, sc, cams, V, opt,
-                       flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate);
-  else
-    hipLaunchKernelGGL((preprocess_bwd_kernel<DEG, true>), grid, dim3(bs), 0, s, sc, cams, V, opt,
-                       flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate);
-}
+#define HGS_BY_DEGREE(deg, CALL) \
+  switch (deg) {                   \
+    case 0: CALL(0); break;        \
+    case 1: CALL(1); break;        \
+    case 2: CALL(2); break;        \
+    default: CALL(3); break;       \
+  }
 
 void launch_preprocess_bwd(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt,
                            const uint8_t *flags, const int4 *rect, const float *accum,
                            float *g_means, float *g_scales, float *g_rots, float *g_opac,
                            float *g_sh, int accumulate, hipStream_t s) {
   if (sc.n == 0) return;
-  switch (sc.sh_degree) {
-    case 0: launch_bwd_deg<0>(sc, cams, V, opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate, s); break;
-    case 1: launch_bwd_deg<1>(sc, cams, V, opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate, s); break;
-    case 2: launch_bwd_deg<2>(sc, cams, V, opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate, s); break;
-    default: launch_bwd_deg<3>(sc, cams, V, opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh, accumulate, s); break;
-  }
+  const dim3 grid((unsigned)((sc.n + 127) / 128));
+#define HGS_BWD(D)                                                                             \
+  if (V == 1)                                                                                  \
+    hipLaunchKernelGGL((preprocess_bwd_kernel<D, false>), grid, dim3(128), 0, s, sc, cams, V,  \
+                       opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh,       \
+                       accumulate);                                                            \
+  else                                                                                         \
+    hipLaunchKernelGGL((preprocess_bwd_kernel<D, true>), grid, dim3(128), 0, s, sc, cams, V,   \
+                       opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh,       \
+                       accumulate)
+  HGS_BY_DEGREE(sc.sh_degree, HGS_BWD)
+#undef HGS_BWD
 }
+
+void launch_fdo_weights(const SceneDev &sc, const DevCam *cams, DevOpts opt, const uint8_t *flags,
+                        const int4 *rect, const float *accum, int64_t plane, double2 *wts,
+                        uint32_t *n_conflict, hipStream_t s) {
+  if (sc.n == 0) return;
+  const dim3 grid((unsigned)((sc.n + 127) / 128));
+#define HGS_W(D)                                                                            \
+  hipLaunchKernelGGL(fdo_weights_kernel<D>, grid, dim3(128), 0, s, sc, cams, opt, flags, rect, \
+                     accum, plane, wts, n_conflict)
+  HGS_BY_DEGREE(sc.sh_degree, HGS_W)
+#undef HGS_W
+}
+
+void launch_fdo_combined_bwd(const SceneDev &sc, const DevCam *cams, DevOpts opt,
+                             const uint8_t *flags, const int4 *rect, const float *accum,
+                             int64_t plane, const double2 *wts, float *g_means, float *g_scales,
+                             float *g_rots, float *g_opac, float *g_sh, int accumulate,
+                             hipStream_t s) {
+  if (sc.n == 0) return;
+  const dim3 grid((unsigned)((sc.n + 127) / 128));
+  double2 *w = const_cast<double2 *>(wts);  // read only
+#define HGS_C(D)                                                                              \
+  hipLaunchKernelGGL(fdo_combined_bwd_kernel<D>, grid, dim3(128), 0, s, sc, cams, opt, flags, \
+                     rect, accum, plane, w, g_means, g_scales, g_rots, g_opac, g_sh, accumulate)
+  HGS_BY_DEGREE(sc.sh_degree, HGS_C)
+#undef HGS_C
+}
+#undef HGS_BY_DEGREE
 
 }  // namespace hgs

@@ -12,8 +12,15 @@ Alg. 1; appendices on the DWT and on gradient conflicts).
   cotangent set (the gradient tolerance of the plain backward), and the
   update against the oracle's projection of the oracle's sets wherever the
   conflict decision is not within the gradient tolerance of a tie.
+* One view without stored sets (a weights pass, then the backward of the
+  slots combined in binary64 with those weights): the update of the path
+  that stores and projects the sets, per primitive within 2e-5 of its
+  terms' norms (the two traversals' atomic slot sums round in different
+  orders, and the chain's cancellation scales that up for some
+  primitives; 5e-6 seen) and per array within 1e-6, off near-ties; and the
+  oracle's projection as above.
 * At 1M Gaussians / 1080p: the one-traversal sets equal three single-set
-  traversals.
+  traversals, and the update without sets equals the one with them.
 """
 import numpy as np
 import pytest
@@ -235,6 +242,114 @@ def test_three_set_backward_matches_oracle(name):
     say(f"[fdo] {name}: conflicts gpu {int(cnt.item())} oracle {nc}, near-ties {int(near.sum())}")
 
 
+ONE_VIEW = {
+    "random2k_200x137": CASES["random2k_200x137"],
+    "random3k_deg1_131x70": lambda: (sg.scene_random(3000, seed=16, log_mu=-3.0, sh_degree=1),
+                                     [sg.look_at_camera((-0.4, 0.5, -3.2), width=131, height=70,
+                                                        fx=90.0)]),
+}
+
+
+def _flat(d, N):
+    import torch
+    return torch.cat([d[k].reshape(N, -1).double() for k in PARAM_KEYS], 1)
+
+
+@pytest.mark.parametrize("name", sorted(ONE_VIEW))
+def test_one_view_without_sets_equals_projection(name):
+    """One view, no sets: the weights pass and the backward of the combined
+    slots give the update that projecting the three stored sets gives, and
+    the oracle's projection of the oracle's sets."""
+    import torch
+    import oracle
+    from oracle import fdo
+    from paper_2512_02932_amd.rasterizer import get_rasterizer, to_device
+    scene, cams = ONE_VIEW[name]()
+    V, H, W = 1, cams[0]["height"], cams[0]["width"]
+    N = scene["means"].shape[0]
+    pix = oracle_pixels(cams)
+    res = oracle.forward(scene, cams, pix)
+    tie = (res["tie"].reshape(V, H, W) != 0)[:, None]
+    Gc = sg.upstream_grads(V, H, W, seed=211)
+    for k in IMG_KEYS:
+        Gc[k] = np.where(tie, 0.0, Gc[k]).astype(np.float32)
+    Gl = np.where(tie, 0.0, sg.upstream_grads(V, H, W, seed=212)["rgb"]).astype(np.float32)
+    Gh = np.where(tie, 0.0, sg.upstream_grads(V, H, W, seed=213)["rgb"]).astype(np.float32)
+    Gc_d = {k: torch.from_numpy(v).cuda() for k, v in Gc.items()}
+    gl_d, gh_d = torch.from_numpy(Gl).cuda(), torch.from_numpy(Gh).cuda()
+
+    rast = get_rasterizer(0)
+    sc = to_device(scene)
+    _, state = rast.render(sc, cams, want_state=True)
+    sets = [{k: torch.zeros_like(sc[k]) for k in PARAM_KEYS} for _ in range(3)]
+    upd_sets = {k: torch.zeros_like(sc[k]) for k in PARAM_KEYS}
+    cnt_sets = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rast.backward_fdo(state, Gc_d, gl_d, gh_d, upd_sets, sets=sets, n_conflict=cnt_sets)
+    upd = {k: torch.full_like(sc[k], 7.0) for k in PARAM_KEYS}  # overwritten
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rast.backward_fdo(state, Gc_d, gl_d, gh_d, upd, n_conflict=cnt)
+    base = {k: torch.randn_like(sc[k]) for k in PARAM_KEYS}
+    acc = {k: v.clone() for k, v in base.items()}
+    rast.backward_fdo(state, Gc_d, gl_d, gh_d, acc, accumulate=True)
+    part = {k: (torch.zeros_like(sc[k]) if k in ("scales", "sh") else None) for k in PARAM_KEYS}
+    rast.backward_fdo(state, Gc_d, gl_d, gh_d, {k: v for k, v in part.items() if v is not None})
+    torch.cuda.synchronize()
+    state.free()
+
+    # against the projection of the stored sets: the same decision (up to
+    # primitives within rounding of a tie); the update is formed in binary64
+    # from the same binary32 slots, the stored sets' path from binary32
+    # sets, so the two differ by binary32 rounding of the sets (and the
+    # order of the atomic slot sums of the two traversals)
+    f = [_flat(d, N) for d in sets]
+    d = (f[1] * f[2]).sum(1)
+    nrm = f[1].norm(dim=1) * f[2].norm(dim=1)
+    close = d.abs() <= 1e-5 * nrm
+    t = sc["types"].long()
+    wl = torch.where((d < 0) & (t == 0), 1 - d / (f[1] ** 2).sum(1).clamp_min(1e-300), 1.0)
+    wh = torch.where((d < 0) & (t != 0), 1 - d / (f[2] ** 2).sum(1).clamp_min(1e-300), 1.0)
+    mag = (f[0].norm(dim=1) + (wl[:, None] * f[1]).norm(dim=1) + (wh[:, None] * f[2]).norm(dim=1))
+    u_sets, u = _flat(upd_sets, N), _flat(upd, N)
+    err = (u - u_sets).norm(dim=1)
+    worst = float((err[~close] / mag[~close].clamp_min(1e-300)).max())
+    bad = (err > 2e-5 * mag + 1e-30) & ~close
+    assert not bool(bad.any()), (int(bad.sum()), worst)
+    rels = {}
+    for k in PARAM_KEYS:
+        a, b = upd[k].double(), upd_sets[k].double()
+        rels[k] = float((a - b).norm()) / max(float(b.norm()), 1e-300)
+    say(f"[fdo] {name} two-pass vs stored sets: worst per primitive {worst:.3g}, "
+        f"relative L2 per array {rels}")
+    assert all(v <= 1e-6 for v in rels.values()), rels
+    assert abs(int(cnt.item()) - int(cnt_sets.item())) <= int(close.sum())
+    # accumulate adds; NULL arrays are skipped and the rest still written
+    # (each call runs its own traversal, whose atomic sums may round in
+    # another order)
+    for k in PARAM_KEYS:
+        x, y = (acc[k] - base[k]).double(), upd[k].double()
+        assert float((x - y).norm()) <= 1e-5 * float(y.norm()) + 1e-7 * float(base[k].norm()), k
+    for k in ("scales", "sh"):
+        x, y = part[k].double(), upd[k].double()
+        assert float((x - y).norm()) <= 1e-5 * float(y.norm()) + 1e-30, k
+
+    # against the oracle's projection of the oracle's sets
+    refs = [oracle.backward(scene, cams, pix, pack_G_all(G, pix))
+            for G in (Gc, dict(_zeros_like_cot(V, H, W), rgb=Gl), dict(_zeros_like_cot(V, H, W), rgb=Gh))]
+    r64 = [fdo.pack({k: r[k] for k in PARAM_KEYS}, N) for r in refs]
+    ref = fdo.fdo_project(scene["types"], *r64)
+    gl, gh = r64[1], r64[2]
+    cosv = np.sum(gl * gh, 1) / np.maximum(np.linalg.norm(gl, axis=1) * np.linalg.norm(gh, axis=1), 1e-300)
+    near = np.abs(cosv) < 1e-2
+    scale = np.linalg.norm(r64[0], axis=1) + np.linalg.norm(gl, axis=1) + np.linalg.norm(gh, axis=1)
+    e = np.linalg.norm(u.cpu().numpy() - ref["update"], axis=1)
+    ok = ~near & (scale > 0)
+    assert (e[ok] <= 3e-3 * scale[ok] + 1e-12).all(), float((e[ok] / scale[ok]).max())
+    nc = int(ref["conflict"].sum())
+    assert abs(int(cnt.item()) - nc) <= int(near.sum()), (int(cnt.item()), nc)
+    say(f"[fdo] {name} two-pass: conflicts {int(cnt.item())} (sets path {int(cnt_sets.item())}, "
+        f"oracle {nc}), near-ties {int(near.sum())}")
+
+
 def test_full_size_three_sets_equal_three_single_traversals():
     """1M hybrid Gaussians, 1920x1080, the launch the benchmark times."""
     import torch
@@ -280,4 +395,17 @@ def test_full_size_three_sets_equal_three_single_traversals():
     mag = flat[0].abs() + (wl[:, None] * flat[1]).abs() + (wh[:, None] * flat[2]).abs()
     assert bool(((got - expect).abs() <= 1e-6 * mag + 1e-30).all())
     assert int(cnt.item()) == int((d < 0).sum())
+    # the launch the benchmark times: no sets, weights pass + combined backward
+    _, state = rast.render(sc, cam, want_state=True)
+    upd2 = {k: torch.zeros_like(sc[k]) for k in PARAM_KEYS}
+    cnt2 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rast.backward_fdo(state, Gc, gl, gh, upd2, n_conflict=cnt2)
+    torch.cuda.synchronize()
+    state.free()
+    for k in PARAM_KEYS:
+        x, y = upd2[k].double(), upd[k].double()
+        rel = float(torch.linalg.norm(x - y) / torch.linalg.norm(y).clamp_min(1e-300))
+        assert rel <= 1e-5, (k, rel)
+    close = d.abs() <= 1e-5 * flat[1].norm(dim=1) * flat[2].norm(dim=1)
+    assert abs(int(cnt2.item()) - int(cnt.item())) <= int(close.sum())
     say(f"[fdo] full size: losses {losses.cpu().tolist()}, conflicts {int(cnt.item())} of {N}")
