@@ -387,8 +387,9 @@ __device__ __forceinline__ float wave_reduce_scatter16(const float (&g)[16], int
 
 // Gradients of one RGB-only cotangent set (FDO's low / high frequency
 // cotangents) for an active pair, into the 16 slots of the main set's layout:
-// the colour, alpha_eff and record-geometry slots; depth and normal slots
-// stay 0.  S is that set's suffix, advanced here.
+// the colour, alpha_eff and record-geometry slots.  g must be zero on entry;
+// the depth and normal slots (and slots 5-8 of a 3D pair) are left so.  S is
+// that set's suffix, advanced here.
 __device__ __forceinline__ void rgb_set_grads(float (&g)[16], float cr, float cg, float cb,
                                               float &S, const PairEval &p, bool is3d, float a,
                                               bool clamped, float Ti, float wg, float G,
@@ -401,33 +402,45 @@ __device__ __forceinline__ void rgb_set_grads(float (&g)[16], float cr, float cg
   g[10] = wg * cr;
   g[11] = wg * cg;
   g[12] = wg * cb;
-  g[13] = g[14] = g[15] = 0.0f;
   const float ge = clamped ? 0.0f : -ga * a * kLn2;
   g[9] = clamped ? 0.0f : ga * G;
+  // geometry slots in scalars, then stored once with constant indices (a
+  // store per branch lets the compiler merge them into one store at a
+  // selected index, which keeps g in scratch memory)
+  float x0, x1, x2, x3, x4, x5, x6, x7, x8;
   if (is3d) {
     const float dx = p.a0, dy = p.a1;
-    g[0] = -ge * (2.0f * r1.z * dx + r1.w * dy);
-    g[1] = -ge * (r1.w * dx + 2.0f * r2.x * dy);
-    g[2] = ge * dx * dx;
-    g[3] = ge * dx * dy;
-    g[4] = ge * dy * dy;
-    g[5] = g[6] = g[7] = g[8] = 0.0f;
+    x0 = -ge * (2.0f * r1.z * dx + r1.w * dy);
+    x1 = -ge * (r1.w * dx + 2.0f * r2.x * dy);
+    x2 = ge * dx * dx;
+    x3 = ge * dx * dy;
+    x4 = ge * dy * dy;
+    x5 = x6 = x7 = x8 = 0.0f;
   } else {
     const float rw = p.rw;
     const float rw2 = rw * rw;
     const float gU = ge * 2.0f * p.a0 * rw2;
     const float gV = ge * 2.0f * p.a1 * rw2;
     const float gW = -2.0f * ge * p.e * rw;
-    g[0] = gU * p.xr;
-    g[1] = gU * p.yr;
-    g[2] = gU;
-    g[3] = gV * p.xr;
-    g[4] = gV * p.yr;
-    g[5] = gV;
-    g[6] = gW * p.xr;
-    g[7] = gW * p.yr;
-    g[8] = gW;
+    x0 = gU * p.xr;
+    x1 = gU * p.yr;
+    x2 = gU;
+    x3 = gV * p.xr;
+    x4 = gV * p.yr;
+    x5 = gV;
+    x6 = gW * p.xr;
+    x7 = gW * p.yr;
+    x8 = gW;
   }
+  g[0] = x0;
+  g[1] = x1;
+  g[2] = x2;
+  g[3] = x3;
+  g[4] = x4;
+  g[5] = x5;
+  g[6] = x6;
+  g[7] = x7;
+  g[8] = x8;
 }
 
 // NS = 1: one cotangent set.  NS = 3: the main set plus two RGB-only sets
