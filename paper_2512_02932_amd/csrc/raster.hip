@@ -385,28 +385,15 @@ __device__ __forceinline__ float wave_reduce_scatter16(const float (&g)[16], int
   return x;
 }
 
-// Gradients of one RGB-only cotangent set (FDO's low / high frequency
-// cotangents) for an active pair, into the 16 slots of the main set's layout:
-// the colour, alpha_eff and record-geometry slots.  g must be zero on entry;
-// the depth and normal slots (and slots 5-8 of a 3D pair) are left so.  S is
-// that set's suffix, advanced here.
-__device__ __forceinline__ void rgb_set_grads(float (&g)[16], float cr, float cg, float cb,
-                                              float &S, const PairEval &p, bool is3d, float a,
-                                              bool clamped, float Ti, float wg, float G,
-                                              const float4 &r1, const float4 &r2,
-                                              const float4 &r3) {
-  const float f = cr * r3.y + cg * r3.z + cb * r3.w;
-  const float dfa = f - S;
-  const float ga = Ti * dfa;
-  S = __builtin_fmaf(a, dfa, S);
-  g[10] = wg * cr;
-  g[11] = wg * cg;
-  g[12] = wg * cb;
-  const float ge = clamped ? 0.0f : -ga * a * kLn2;
-  g[9] = clamped ? 0.0f : ga * G;
-  // geometry slots in scalars, then stored once with constant indices (a
-  // store per branch lets the compiler merge them into one store at a
-  // selected index, which keeps g in scratch memory)
+// Record-geometry slots 0-8 of a pair from dL/de (ge) and, for a 2D pair,
+// the depth weight gdz = dL/d depth (3D: slot 5 is the depth slot, written
+// by the caller).  The slots are formed in scalars and stored once with
+// constant indices (stores in both branches of the 2D/3D split are
+// otherwise merged by the compiler into one store at a selected index,
+// which moves g to scratch memory).
+__device__ __forceinline__ void pair_geometry_grads(float (&g)[16], const PairEval &p, bool is3d,
+                                                    float ge, float gdz, const float4 &r1,
+                                                    const float4 &r2) {
   float x0, x1, x2, x3, x4, x5, x6, x7, x8;
   if (is3d) {
     const float dx = p.a0, dy = p.a1;
@@ -415,13 +402,14 @@ __device__ __forceinline__ void rgb_set_grads(float (&g)[16], float cr, float cg
     x2 = ge * dx * dx;
     x3 = ge * dx * dy;
     x4 = ge * dy * dy;
-    x5 = x6 = x7 = x8 = 0.0f;
+    x5 = g[5];
+    x6 = x7 = x8 = 0.0f;
   } else {
     const float rw = p.rw;
     const float rw2 = rw * rw;
     const float gU = ge * 2.0f * p.a0 * rw2;
     const float gV = ge * 2.0f * p.a1 * rw2;
-    const float gW = -2.0f * ge * p.e * rw;
+    const float gW = -2.0f * ge * p.e * rw - gdz * rw2;
     x0 = gU * p.xr;
     x1 = gU * p.yr;
     x2 = gU;
@@ -441,6 +429,29 @@ __device__ __forceinline__ void rgb_set_grads(float (&g)[16], float cr, float cg
   g[6] = x6;
   g[7] = x7;
   g[8] = x8;
+}
+
+// Gradients of one RGB-only cotangent set (FDO's low / high frequency
+// cotangents) for an active pair, into the 16 slots of the main set's layout:
+// the colour, alpha_eff and record-geometry slots; the depth and normal
+// slots are 0 (g[5] must be 0 on entry).  S is that set's suffix, advanced
+// where the pair is active; inactive lanes get zero gradients.
+__device__ __forceinline__ void rgb_set_grads(float (&g)[16], float cr, float cg, float cb,
+                                              float &S, const PairEval &p, bool is3d, bool act,
+                                              bool live, float a, float Ti, float wg, float G,
+                                              const float4 &r1, const float4 &r2,
+                                              const float4 &r3) {
+  const float f = cr * r3.y + cg * r3.z + cb * r3.w;
+  const float dfa = f - S;
+  const float ga = act ? Ti * dfa : 0.0f;
+  S = act ? __builtin_fmaf(a, dfa, S) : S;
+  g[10] = wg * cr;
+  g[11] = wg * cg;
+  g[12] = wg * cb;
+  g[13] = g[14] = g[15] = 0.0f;
+  const float ge = live ? -ga * a * kLn2 : 0.0f;
+  g[9] = live ? ga * G : 0.0f;
+  pair_geometry_grads(g, p, is3d, ge, 0.0f, r1, r2);
 }
 
 // NS = 1: one cotangent set.  NS = 3: the main set plus two RGB-only sets
@@ -554,51 +565,37 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
       const float raw = fabsf(r4.w) * G;
       const bool act = (pos < L) && (raw >= kAlphaMin);
       if (__ballot(act) == 0ull) continue;
-      float g[16];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) g[j] = 0.0f;
+      // Every lane runs the same instructions; an inactive lane's weights
+      // (wg, ga, ge) are 0, and a 2D pair's intersection, which can be
+      // non-finite where the pair does not contribute, is replaced there by
+      // finite values, so its gradient terms are exact zeros.
+      PairEval ps = p;
+      if (!is3d) {
+        ps.e = act ? p.e : 0.0f;
+        ps.rw = act ? p.rw : 0.0f;
+        ps.depth = act ? p.depth : 0.0f;
+      }
       const float a = fminf(raw, kAlphaMax);
-      const bool clamped = raw > kAlphaMax;
+      const bool live = act && !(raw > kAlphaMax);  // not clamped: the exponent's path
       const float Ti = T * __builtin_amdgcn_rcpf(1.0f - a);
-      const float wg = a * Ti;
-      if (act) {
-        const float f = Gr * r3.y + Gg * r3.z + Gb * r3.w + Gd * p.depth + Gnx * r4.x +
+      const float wg = act ? a * Ti : 0.0f;
+      float g[16];
+      {
+        const float f = Gr * r3.y + Gg * r3.z + Gb * r3.w + Gd * ps.depth + Gnx * r4.x +
                         Gny * r4.y + Gnz * r4.z;
         const float dfa = f - S;
-        const float ga = Ti * dfa;  // dL/d alpha~
-        S = __builtin_fmaf(a, dfa, S);
+        const float ga = act ? Ti * dfa : 0.0f;  // dL/d alpha~
+        S = act ? __builtin_fmaf(a, dfa, S) : S;
         g[10] = wg * Gr;
         g[11] = wg * Gg;
         g[12] = wg * Gb;
         g[13] = wg * Gnx;
         g[14] = wg * Gny;
         g[15] = wg * Gnz;
-        const float ge = clamped ? 0.0f : -ga * a * kLn2;  // dL/de
-        g[9] = clamped ? 0.0f : ga * G;                    // dL/d alpha_eff
-        if (is3d) {
-          const float dx = p.a0, dy = p.a1;
-          g[0] = -ge * (2.0f * r1.z * dx + r1.w * dy);
-          g[1] = -ge * (r1.w * dx + 2.0f * r2.x * dy);
-          g[2] = ge * dx * dx;
-          g[3] = ge * dx * dy;
-          g[4] = ge * dy * dy;
-          g[5] = wg * Gd;
-        } else {
-          const float rw = p.rw;
-          const float rw2 = rw * rw;
-          const float gU = ge * 2.0f * p.a0 * rw2;
-          const float gV = ge * 2.0f * p.a1 * rw2;
-          const float gW = -2.0f * ge * p.e * rw - wg * Gd * rw2;
-          g[0] = gU * p.xr;
-          g[1] = gU * p.yr;
-          g[2] = gU;
-          g[3] = gV * p.xr;
-          g[4] = gV * p.yr;
-          g[5] = gV;
-          g[6] = gW * p.xr;
-          g[7] = gW * p.yr;
-          g[8] = gW;
-        }
+        const float ge = live ? -ga * a * kLn2 : 0.0f;  // dL/de
+        g[9] = live ? ga * G : 0.0f;                    // dL/d alpha_eff
+        g[5] = wg * Gd;                                  // 3D: depth slot
+        pair_geometry_grads(g, ps, is3d, ge, wg * Gd, r1, r2);
       }
       const float tot = wave_reduce_scatter16(g, lane);
       if ((lane & 3) == 0 && tot != 0.0f)
@@ -606,18 +603,16 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
       if constexpr (NS == 3) {
 #pragma unroll
         for (int set = 0; set < 2; ++set) {
-#pragma unroll
-          for (int j = 0; j < 16; ++j) g[j] = 0.0f;
-          if (act)
-            rgb_set_grads(g, Xr[set], Xg[set], Xb[set], XS[set], p, is3d, a, clamped, Ti, wg, G,
-                          r1, r2, r3);
+          g[5] = 0.0f;
+          rgb_set_grads(g, Xr[set], Xg[set], Xb[set], XS[set], ps, is3d, act, live, a, Ti, wg, G,
+                        r1, r2, r3);
           const float t2 = wave_reduce_scatter16(g, lane);
           if ((lane & 3) == 0 && t2 != 0.0f)
             unsafeAtomicAdd(accum + (size_t)(set + 1) * plane + (size_t)sid[k] * kGradSlots + vidx,
                             t2);
         }
       }
-      if (act) T = Ti;
+      T = act ? Ti : T;
     }
   }
 }
