@@ -138,10 +138,34 @@ struct ViewOut {
   uint32_t *last, *n_contrib, *wcount;
 };
 
-// Does the record's inclusive pixel rectangle (r0) meet the quadrant?
-__device__ __forceinline__ bool meets(const float4 &r0, const Quad &q) {
-  const float x0 = (float)q.qx, y0 = (float)q.qy;
-  return r0.x <= x0 + 7.0f && r0.z >= x0 && r0.y <= y0 + 7.0f && r0.w >= y0;
+// Can the record reach alpha~ >= 1/255 at a pixel of the quadrant?  Its
+// inclusive pixel rectangle (r0) must meet the quadrant.  For a 3D record
+// the exponent e = A dx^2 + B dx dy + C dy^2 (positive definite) is also
+// minimised over the box spanned by the quadrant's pixel samples (the
+// minimum of a convex quadratic over a box: 0 if the centre is inside, else
+// the least of the four edge minima, each at its clamped stationary point);
+// the record is dropped only if that lower bound of e at every sample
+// exceeds log2(alpha_eff * 255) by more than a margin that covers the
+// rounding of the binary32 evaluation in eval_pair.  Dropping a record that
+// contributes to no pixel of the quadrant changes nothing.
+__device__ __forceinline__ bool meets(const float4 &r0, const float4 &r1, const float4 &r2,
+                                      const float4 &r4, const Quad &q) {
+  const float qx = (float)q.qx, qy = (float)q.qy;
+  if (!(r0.x <= qx + 7.0f && r0.z >= qx && r0.y <= qy + 7.0f && r0.w >= qy)) return false;
+  if (__float_as_uint(r4.w) >> 31) return true;  // 2D: the rectangle only
+  const float A = r1.z, B = r1.w, C = r2.x;
+  if (!(A > 0.0f && C > 0.0f)) return true;
+  // sample box in the record's frame, as eval_pair forms dx, dy
+  const float x0 = ((qx + 0.5f) - r0.x) - r1.x, x1 = ((qx + 7.5f) - r0.x) - r1.x;
+  const float y0 = ((qy + 0.5f) - r0.y) - r1.y, y1 = ((qy + 7.5f) - r0.y) - r1.y;
+  if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
+  const float hA = -0.5f * B * __builtin_amdgcn_rcpf(A), hC = -0.5f * B * __builtin_amdgcn_rcpf(C);
+  auto at = [&](float x, float y) { return x * (A * x + B * y) + C * y * y; };
+  const float ya = fminf(fmaxf(hC * x0, y0), y1), yb = fminf(fmaxf(hC * x1, y0), y1);
+  const float xa = fminf(fmaxf(hA * y0, x0), x1), xb = fminf(fmaxf(hA * y1, x0), x1);
+  const float emin = fminf(fminf(at(x0, ya), at(x1, yb)), fminf(at(xa, y0), at(xb, y1)));
+  const float lim = __builtin_amdgcn_logf(fabsf(r4.w) * 255.0f);
+  return !(emin > lim + 1e-3f + 1e-4f * fabsf(lim));
 }
 
 // Issue priority of a wave by the length of the list it walks: the long
@@ -186,7 +210,7 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
   if (kWave + lane < n) nid = vals[rg.x + kWave + lane];
   for (int c = 0; c < n; c += kWave) {
     if (__ballot(thr < 1.0f) == 0ull) break;
-    const bool hit = (c + lane < n) && meets(q0, q);
+    const bool hit = (c + lane < n) && meets(q0, q1, q2, q4, q);
     const uint64_t m = __ballot(hit);
     __syncthreads();  // the previous chunk's slots have been read
     if (hit) {
@@ -536,7 +560,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   }
   if (c > 0) nid = vals[rg.x + c - kWave + lane];
   for (; c >= 0; c -= kWave) {
-    const bool hit = (c + lane < n) && meets(q0, q);
+    const bool hit = (c + lane < n) && meets(q0, q1, q2, q4, q);
     const uint64_t m = __ballot(hit);
     __syncthreads();  // the previous chunk's slots have been read
     if (hit) {
