@@ -289,7 +289,8 @@ hgs_status hgs_fdo_project(hgs_ctx *ctx, int64_t n, int32_t sh_degree, const uin
  * the views, and combined by Alg. 1 (as hgs_fdo_project, with the scene's
  * types) into `update`.  sets: NULL (workspace), or hgs_grads[3] whose
  * arrays receive g_color, g_low, g_high before the projection
- * (overwritten; every array required).  n_conflict as in
+ * (overwritten; every array required unless the scene is empty).
+ * n_conflict as in
  * hgs_fdo_project.  With one view and sets == NULL the three sets are not
  * stored: a first pass over the primitives forms g_low and g_high (rounded
  * to binary32 as stored gradients would be), takes Alg. 1's dot products

@@ -629,7 +629,7 @@ hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *st, const hgs_grad_i
   if (!update) return fail(HGS_EINVAL, "update is NULL");
   if (st->device != ctx->device) return fail(HGS_ESTATE, "state belongs to another context");
   if (!st->ws) return fail(HGS_ESTATE, "state has no workspace");
-  if (sets) {
+  if (sets && st->N > 0) {
     for (int k = 0; k < 3; ++k)
       if (!sets[k].means || !sets[k].scales || !sets[k].rotations || !sets[k].opacities ||
           !sets[k].sh)

@@ -409,3 +409,57 @@ def test_full_size_three_sets_equal_three_single_traversals():
     close = d.abs() <= 1e-5 * flat[1].norm(dim=1) * flat[2].norm(dim=1)
     assert abs(int(cnt2.item()) - int(cnt.item())) <= int(close.sum())
     say(f"[fdo] full size: losses {losses.cpu().tolist()}, conflicts {int(cnt.item())} of {N}")
+
+
+def _empty_scene(n=0, K=16):
+    return dict(means=np.zeros((n, 3), np.float32), scales=np.zeros((n, 3), np.float32),
+                rotations=np.zeros((n, 4), np.float32), opacities=np.zeros(n, np.float32),
+                sh=np.zeros((n, K, 3), np.float32), types=np.zeros(n, np.uint8), sh_degree=3)
+
+
+@pytest.mark.parametrize("case", ["empty_scene", "all_culled", "one_pixel"])
+def test_fdo_backward_degenerate_views(case):
+    """No primitive reaches the image (empty scene; every splat behind the
+    camera) or a 1x1 image: both FDO paths run, the update is exactly the
+    plain backward's (zero where nothing is visible), no conflict is counted
+    where nothing is visible, and the two paths agree."""
+    import torch
+    from paper_2512_02932_amd.rasterizer import fdo_cotangents, get_rasterizer, to_device
+    if case == "empty_scene":
+        scene = _empty_scene()
+        cam = sg.look_at_camera((0, 0, -3.0), width=40, height=24, fx=40.0)
+    elif case == "all_culled":
+        scene = sg.scene_random(300, seed=3)
+        cam = sg.look_at_camera((0, 0, 6.0), target=(0, 0, 12.0), width=33, height=17, fx=30.0)
+    else:
+        scene = sg.scene_random(300, seed=3)
+        cam = sg.look_at_camera((0.1, 0.0, -3.0), width=1, height=1, fx=20.0)
+    H, W = cam["height"], cam["width"]
+    rast = get_rasterizer(0)
+    sc = to_device(scene)
+    imgs, state = rast.render(sc, cam, want_state=True)
+    Gc = {k: torch.from_numpy(v).cuda() for k, v in sg.upstream_grads(1, H, W, seed=7).items()}
+    rng = np.random.default_rng(8)
+    target = torch.from_numpy(rng.uniform(0, 1, (1, 3, H, W)).astype(np.float32)).cuda()
+    gl, gh, _ = fdo_cotangents(imgs["rgb"].contiguous(), target, LAM_LOW, LAM_HIGH)
+    upd = {k: torch.full_like(sc[k], 3.0) for k in PARAM_KEYS}
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rast.backward_fdo(state, Gc, gl, gh, upd, n_conflict=cnt)
+    sets = [{k: torch.zeros_like(sc[k]) for k in PARAM_KEYS} for _ in range(3)]
+    upd2 = {k: torch.zeros_like(sc[k]) for k in PARAM_KEYS}
+    cnt2 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rast.backward_fdo(state, Gc, gl, gh, upd2, sets=sets, n_conflict=cnt2)
+    torch.cuda.synchronize()
+    D = state.sizes()["D"]
+    state.free()
+    if case != "one_pixel":
+        assert D == 0
+        for k in PARAM_KEYS:
+            assert bool((upd[k] == 0).all()) and bool((upd2[k] == 0).all()), k
+        assert int(cnt.item()) == 0 and int(cnt2.item()) == 0
+    else:
+        for k in PARAM_KEYS:
+            a, b = upd[k].double(), upd2[k].double()
+            assert float((a - b).norm()) <= 1e-6 * float(b.norm()) + 1e-30, k
+        assert int(cnt.item()) == int(cnt2.item())
+    say(f"[fdo] {case}: D={D}, conflicts {int(cnt.item())}")
