@@ -271,6 +271,16 @@ __device__ __forceinline__ void adam_one(const AdamArgs &a, int s, int64_t i, fl
   av = s == 1 ? expf(np) : (s == 3 ? 1.0f / (1.0f + expf(-np)) : np);
 }
 
+// Four floats read once: a nontemporal load, so that the four input streams
+// do not displace the lines the four output streams are being written to
+// (0.35 -> 0.33 ms at 1M Gaussians, SH3; nontemporal stores made no
+// difference).
+typedef float v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 load_stream(const float *p) {
+  const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(p));
+  return make_float4(t.x, t.y, t.z, t.w);
+}
+
 // Blocks [blk[s], blk[s+1]) serve array s, one float4 of it per thread
 // (16-byte loads and stores when all of that array's pointers allow them,
 // element by element otherwise and for the ragged end).
@@ -285,10 +295,10 @@ adam_kernel(AdamArgs a) {
   if (e0 >= len) return;
   float *act = a.act[s];
   if (a.vec[s] && e0 + 4 <= len) {
-    const float4 p4 = *reinterpret_cast<const float4 *>(a.raw[s] + e0);
-    const float4 g4 = *reinterpret_cast<const float4 *>(a.grad[s] + e0);
-    const float4 m4 = *reinterpret_cast<const float4 *>(a.m[s] + e0);
-    const float4 v4 = *reinterpret_cast<const float4 *>(a.v[s] + e0);
+    const float4 p4 = load_stream(a.raw[s] + e0);
+    const float4 g4 = load_stream(a.grad[s] + e0);
+    const float4 m4 = load_stream(a.m[s] + e0);
+    const float4 v4 = load_stream(a.v[s] + e0);
     float4 np, nm, nv, av;
     adam_one(a, s, e0, p4.x, g4.x, m4.x, v4.x, np.x, nm.x, nv.x, av.x);
     adam_one(a, s, e0 + 1, p4.y, g4.y, m4.y, v4.y, np.y, nm.y, nv.y, av.y);
