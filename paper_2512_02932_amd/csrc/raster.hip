@@ -478,6 +478,11 @@ __device__ __forceinline__ void rgb_set_grads(float (&g)[16], float cr, float cg
   pair_geometry_grads(g, p, is3d, ge, 0.0f, r1, r2);
 }
 
+// Destination of a reduced gradient total: accumulator plane and slot.
+struct PackDst {
+  int plane, slot;
+};
+
 // NS = 1: one cotangent set.  NS = 3: the main set plus two RGB-only sets
 // (rgb2[0], rgb2[1]) in the same reverse traversal -- one record fetch,
 // one geometry and transmittance recomputation per pair -- accumulated into
@@ -547,6 +552,17 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   prio_for_list(n);
   const int vidx = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
                    ((lane >> 2) & 1);
+  // Three-set kernel, 3D pair: destination (plane, slot) of this lane's
+  // total in the two packed reductions.  A: the main set, whose slots 6-8
+  // (zero for a 3D pair) carry RGB set 1's colour slots 10-12.  B: set 1's
+  // slots 0-4 and 9, then set 2's slots 0-4, 9, 10-12; entry 15 is unused.
+  const PackDst packA = vidx >= 6 && vidx <= 8 ? PackDst{1, vidx + 4} : PackDst{0, vidx};
+  const PackDst packB = vidx <= 4    ? PackDst{1, vidx}
+                        : vidx == 5  ? PackDst{1, 9}
+                        : vidx <= 10 ? PackDst{2, vidx - 6}
+                        : vidx == 11 ? PackDst{2, 9}
+                        : vidx <= 14 ? PackDst{2, vidx - 2}
+                                     : PackDst{0, -1};
 
   // chunks of 64 list positions in reverse; the first is the ragged one.
   // Pipeline: records of chunk c in q0..q4 (entry id), entry of chunk c - 64
@@ -621,19 +637,41 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
         g[5] = wg * Gd;                                  // 3D: depth slot
         pair_geometry_grads(g, ps, is3d, ge, wg * Gd, r1, r2);
       }
-      const float tot = wave_reduce_scatter16(g, lane);
-      if ((lane & 3) == 0 && tot != 0.0f)
-        unsafeAtomicAdd(accum + (size_t)sid[k] * kGradSlots + vidx, tot);
-      if constexpr (NS == 3) {
+      const size_t rec_off = (size_t)sid[k] * kGradSlots;
+      if (NS == 3 && is3d) {
+        // A 3D pair has 13 non-zero main slots and 9 per RGB set: two
+        // reductions carry all 31 (layout at packA / packB).
+        float g1[16], g2[16];
+        g1[5] = 0.0f;
+        g2[5] = 0.0f;
+        rgb_set_grads(g1, Xr[0], Xg[0], Xb[0], XS[0], ps, is3d, act, live, a, Ti, wg, G, r1, r2,
+                      r3);
+        rgb_set_grads(g2, Xr[1], Xg[1], Xb[1], XS[1], ps, is3d, act, live, a, Ti, wg, G, r1, r2,
+                      r3);
+        g[6] = g1[10];
+        g[7] = g1[11];
+        g[8] = g1[12];
+        const float h[16] = {g1[0], g1[1], g1[2], g1[3],  g1[4],  g1[9],  g2[0],  g2[1],
+                             g2[2], g2[3], g2[4], g2[9], g2[10], g2[11], g2[12], 0.0f};
+        const float ta = wave_reduce_scatter16(g, lane);
+        const float tb = wave_reduce_scatter16(h, lane);
+        if ((lane & 3) == 0 && ta != 0.0f)
+          unsafeAtomicAdd(accum + packA.plane * plane + rec_off + packA.slot, ta);
+        if ((lane & 3) == 0 && tb != 0.0f && packB.slot >= 0)
+          unsafeAtomicAdd(accum + packB.plane * plane + rec_off + packB.slot, tb);
+      } else {
+        const float tot = wave_reduce_scatter16(g, lane);
+        if ((lane & 3) == 0 && tot != 0.0f) unsafeAtomicAdd(accum + rec_off + vidx, tot);
+        if constexpr (NS == 3) {
 #pragma unroll
-        for (int set = 0; set < 2; ++set) {
-          g[5] = 0.0f;
-          rgb_set_grads(g, Xr[set], Xg[set], Xb[set], XS[set], ps, is3d, act, live, a, Ti, wg, G,
-                        r1, r2, r3);
-          const float t2 = wave_reduce_scatter16(g, lane);
-          if ((lane & 3) == 0 && t2 != 0.0f)
-            unsafeAtomicAdd(accum + (size_t)(set + 1) * plane + (size_t)sid[k] * kGradSlots + vidx,
-                            t2);
+          for (int set = 0; set < 2; ++set) {
+            g[5] = 0.0f;
+            rgb_set_grads(g, Xr[set], Xg[set], Xb[set], XS[set], ps, is3d, act, live, a, Ti, wg,
+                          G, r1, r2, r3);
+            const float t2 = wave_reduce_scatter16(g, lane);
+            if ((lane & 3) == 0 && t2 != 0.0f)
+              unsafeAtomicAdd(accum + (size_t)(set + 1) * plane + rec_off + vidx, t2);
+          }
         }
       }
       T = act ? Ti : T;
