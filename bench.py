@@ -332,8 +332,8 @@ def fdo_leg(rast, sc, cam, images, G, counts, N, K, steps, warmup, workload):
     fixed synthetic target (the render of the step plus N(0, 0.05) noise,
     clipped), the three-set backward (colour cotangents = the headline's
     N(0,1) cotangents) and Alg. 1's projection into one update (one view
-    and no stored sets: a weights pass, then one backward of the combined
-    slots)."""
+    and no stored sets: per Gaussian, the Alg. 1 weights and one backward
+    of the slots combined with them)."""
     import numpy as np
     import torch
     from paper_2512_02932_amd import _hgs
@@ -364,10 +364,10 @@ def fdo_leg(rast, sc, cam, images, G, counts, N, K, steps, warmup, workload):
     n_conf = int(cnt.item()) // (steps + 5)
     P = 11 + 3 * K
     cot_bytes = 3 * H * W * 16
-    # weights pass per primitive: the low and high slot records (2 x 64 B),
-    # means, scales, rotation, opacity, type, flag, rect (62 B), SH (4 * 3K)
-    # read; (w_low, w_high) written (16 B)
-    w_bytes = N * (2 * 64 + 62 + 4 * 3 * K + 16)
+    # one-view FDO preprocess backward per Gaussian: the three slot records
+    # (3 x 64 B), means, scales, rotation, opacity, type, flag, rect (62 B)
+    # and SH (4 * 3K) read; the update (4 * (11 + 3K)) written
+    w_bytes = N * (3 * 64 + 62 + 4 * 3 * K + 4 * (11 + 3 * K))
     ops = (counts["blend_3d"] * (OPS_BWD["3d"] + 2 * OPS_BWD_RGB["3d"]) +
            counts["blend_2d"] * (OPS_BWD["2d"] + 2 * OPS_BWD_RGB["2d"]))
 
@@ -382,7 +382,7 @@ def fdo_leg(rast, sc, cam, images, G, counts, N, K, steps, warmup, workload):
            "conflicts_per_step": n_conf, "gaussians": N,
            "losses_last": [float(x) / (steps + warmup) for x in losses.cpu().tolist()],
            "stage_ms": {k: round(v, 4) for k, v in stage.items()},
-           "preprocess_bwd_launches_per_step": 1,
+           "preprocess_bwd_launches_per_step": 1,  # fdo_fused_bwd_kernel
            "roofline": {
                "raster_bwd_3set": {"bound": "alu", "achieved": round(tops, 4),
                                    "peak": round(VALU_PEAK / 1e12, 4), "unit": "Tops/s",
@@ -391,8 +391,9 @@ def fdo_leg(rast, sc, cam, images, G, counts, N, K, steps, warmup, workload):
                                    "kernel": "raster_bwd_kernel<3>"},
                "fdo_cotangents": hbm("fdo_cotangents_kernel", cot_bytes, stage["fdo_cotangents"],
                                      "fdo_cotangents_kernel"),
-               "fdo_weights": hbm(f"fdo_weights_kernel<{DEG_OF_K[K]}>", w_bytes,
-                                  stage["fdo_weights"], f"fdo_weights_kernel<{DEG_OF_K[K]}>")}}
+               "fdo_preprocess_bwd": hbm(f"fdo_fused_bwd_kernel<{DEG_OF_K[K]}>", w_bytes,
+                                         stage["fdo_preprocess_bwd"],
+                                         f"fdo_fused_bwd_kernel<{DEG_OF_K[K]}>")}}
     log(f"[fdo] {out}")
     return out
 

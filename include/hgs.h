@@ -211,7 +211,7 @@ enum {
   HGS_STAGE_COLOR_LOSS = 12,
   HGS_STAGE_ADAM = 13,
   HGS_STAGE_DENSIFY = 14,
-  HGS_STAGE_FDO_WEIGHTS = 15,
+  HGS_STAGE_FDO_PREPROCESS_BWD = 15,
   HGS_N_STAGES = 16
 };
 hgs_status hgs_profile_enable(hgs_ctx *ctx, int32_t on);
@@ -292,11 +292,11 @@ hgs_status hgs_fdo_project(hgs_ctx *ctx, int64_t n, int32_t sh_degree, const uin
  * (overwritten; every array required unless the scene is empty).
  * n_conflict as in
  * hgs_fdo_project.  With one view and sets == NULL the three sets are not
- * stored: a first pass over the primitives forms g_low and g_high (rounded
- * to binary32 as stored gradients would be), takes Alg. 1's dot products
- * and weights, and a second pass applies the backward to the slots
- * combined in binary64 with those weights (the backward is linear in
- * them) and rounds the update once.  The scene's parameters must be
+ * stored: per primitive, g_low and g_high are formed (rounded to binary32
+ * as stored gradients would be) for Alg. 1's dot products and weights, and
+ * the backward is then applied once to the slots combined in binary64
+ * with those weights (the backward is linear in them); the update is
+ * rounded once.  The scene's parameters must be
  * unchanged since the forward.
  * Errors: EINVAL, ESTATE, ENOMEM, EHIP. */
 hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *state,

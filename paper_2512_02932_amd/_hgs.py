@@ -23,7 +23,7 @@ EXPORTS = ("hgs_create", "hgs_destroy", "hgs_scene_init", "hgs_scene_release", "
 
 STAGES = ("preprocess", "scan", "duplicate", "sort", "ranges", "raster_fwd", "raster_bwd",
           "preprocess_bwd", "fill", "depth_sort", "fdo_cotangents", "fdo_project", "color_loss",
-          "adam", "densify", "fdo_weights")
+          "adam", "densify", "fdo_preprocess_bwd")
 
 
 class hgs_scene_desc(C.Structure):

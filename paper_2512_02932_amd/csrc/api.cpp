@@ -644,17 +644,15 @@ hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *st, const hgs_grad_i
   const int K = (st->scene.sh_degree + 1) * (st->scene.sh_degree + 1);
   float *accum = nullptr;
   HGS_HIP(dalloc_t(st, &accum, (size_t)(3 * plane)));
-  // One view and no sets asked for: Alg. 1's weights from a pass over the
-  // slots, then one chain of the combined slots (the chain is linear in
-  // them); the three sets are never stored.
-  const bool two_pass = !sets && st->V == 1;
-  double2 *wts = nullptr;
-  if (two_pass) HGS_HIP(dalloc_t(st, &wts, (size_t)std::max<int64_t>(N, 1)));
+  // One view and no sets asked for: per primitive, Alg. 1's weights, then
+  // one chain of the slots combined with them (the chain is linear in the
+  // slots); the three sets are never stored.
+  const bool one_view = !sets && st->V == 1;
   // the three parameter-gradient sets: the caller's arrays or workspace
   float *own[3][5] = {};
   const size_t cnt[5] = {(size_t)(3 * N), (size_t)(3 * N), (size_t)(4 * N), (size_t)N,
                          (size_t)(3 * K * N)};
-  if (!sets && !two_pass)
+  if (!sets && !one_view)
     for (int k = 0; k < 3; ++k)
       for (int j = 0; j < 5; ++j) HGS_HIP(dalloc_t(st, &own[k][j], std::max<size_t>(cnt[j], 1)));
   HGS_HIP(commit(st, 2, s));
@@ -693,18 +691,11 @@ hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *st, const hgs_grad_i
   st->accum_last = accum;
   st->accum_planes = 3;
   st->accum_plane = plane;
-  if (two_pass) {
-    {
-      StageTimer t(ctx, HGS_STAGE_FDO_WEIGHTS, s);
-      launch_fdo_weights(st->scene, st->cams, st->opt, st->flags, st->rect, accum, plane, wts,
-                         n_conflict, s);
-    }
-    {
-      StageTimer t(ctx, HGS_STAGE_PREPROCESS_BWD, s);
-      launch_fdo_combined_bwd(st->scene, st->cams, st->opt, st->flags, st->rect, accum, plane, wts,
-                              update->means, update->scales, update->rotations, update->opacities,
-                              update->sh, update->accumulate, s);
-    }
+  if (one_view) {
+    StageTimer t(ctx, HGS_STAGE_FDO_PREPROCESS_BWD, s);
+    launch_fdo_fused_bwd(st->scene, st->cams, st->opt, st->flags, st->rect, accum, plane,
+                         n_conflict, update->means, update->scales, update->rotations,
+                         update->opacities, update->sh, update->accumulate, s);
     HGS_HIP(hipGetLastError());
     HGS_HIP(join_streams(st->stream, s));
     return HGS_OK;

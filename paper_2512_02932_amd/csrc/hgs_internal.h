@@ -105,23 +105,17 @@ void launch_preprocess_bwd(const SceneDev &sc, const DevCam *cams, int V, DevOpt
                            const uint8_t *flags, const int4 *rect, const float *accum,
                            float *g_means, float *g_scales, float *g_rots, float *g_opac,
                            float *g_sh, int accumulate, hipStream_t s);
-// FDO with one view, in two passes over the primitives (the chain from
-// slots to parameter gradients is linear in the slots).  Planes at accum,
-// accum + plane, accum + 2 plane hold the colour, low and high slots.
-// launch_fdo_weights writes Alg. 1's per-primitive (w_low, w_high) into wts
-// (binary64)
-// and adds the number of conflicting primitives to *n_conflict (may be
-// NULL); launch_fdo_combined_bwd then writes (or adds, if accumulate) the
-// update g_color + w_low g_low + w_high g_high as the chain of the slots
-// c + w_low l + w_high h.
-void launch_fdo_weights(const SceneDev &sc, const DevCam *cams, DevOpts opt, const uint8_t *flags,
-                        const int4 *rect, const float *accum, int64_t plane, double2 *wts,
-                        uint32_t *n_conflict, hipStream_t s);
-void launch_fdo_combined_bwd(const SceneDev &sc, const DevCam *cams, DevOpts opt,
-                             const uint8_t *flags, const int4 *rect, const float *accum,
-                             int64_t plane, const double2 *wts, float *g_means, float *g_scales,
-                             float *g_rots, float *g_opac, float *g_sh, int accumulate,
-                             hipStream_t s);
+// FDO with one view.  Planes at accum, accum + plane, accum + 2 plane hold
+// the colour, low and high slots.  One thread per primitive forms its
+// Alg. 1 weights (w_low, w_high) from g_low and g_high, adds the number of
+// conflicting primitives to *n_conflict (may be NULL), and writes (or adds,
+// if accumulate) the update g_color + w_low g_low + w_high g_high as the
+// chain of the slots c + w_low l + w_high h (the chain is linear in them).
+void launch_fdo_fused_bwd(const SceneDev &sc, const DevCam *cams, DevOpts opt,
+                          const uint8_t *flags, const int4 *rect, const float *accum,
+                          int64_t plane, uint32_t *n_conflict, float *g_means, float *g_scales,
+                          float *g_rots, float *g_opac, float *g_sh, int accumulate,
+                          hipStream_t s);
 
 // Counts.  Every launcher below takes a host count n that sizes the grid.
 // Where it also takes n_dev (may be NULL), the kernels use min(n, *n_dev):

@@ -692,24 +692,20 @@ __device__ __forceinline__ void colour_chain(const float *f, const double *Y, co
   for (int k = 0; k < 3; ++k) gmu[k] += (gdir[k] - dir[k] * dd) / dist;
 }
 
-// Modes of the kernel (the chain from slots to parameters is linear in the
-// slots):
-//   kBwdPlain   one slot plane -> gradients;
-//   kBwdFdoDots the FDO low and high planes (accum + plane, + 2 plane) ->
-//               per primitive g_low . g_high, |g_low|^2, |g_high|^2 over all
-//               parameters and Alg. 1's weights (w_low, w_high) into wts;
-//               one view only (the SH part of the dot products is then a
-//               product of per-channel factors and |Y|^2);
-//   kBwdFdoSum  the slots c + w_low l + w_high h of the three planes ->
-//               the Alg. 1 update, since g_c + w_l g_l + w_h g_h is the chain
-//               applied to that combination.
-constexpr int kBwdPlain = 0, kBwdFdoDots = 1, kBwdFdoSum = 2;
+// Modes of the kernel:
+//   kBwdPlain  one slot plane -> gradients;
+//   kBwdFdo    FDO with one view: the colour, low and high planes at accum,
+//              accum + plane, accum + 2 plane.  The thread first forms its
+//              primitive's Alg. 1 weights (w_low, w_high) from g_low and
+//              g_high (fdo_weights), then runs the chain once on the slots
+//              c + w_low l + w_high h: the chain is linear in the slots, so
+//              that is the update g_c + w_l g_l + w_h g_h.
+constexpr int kBwdPlain = 0, kBwdFdo = 1;
 
-template <int MODE, typename T>
-__device__ __forceinline__ void load_slots(const float *__restrict__ accum, int64_t plane,
-                                           int64_t i, int set, double2 w, T (&a)[kGradSlots]) {
-  const float4 *p0 = reinterpret_cast<const float4 *>(
-      accum + (MODE == kBwdFdoDots ? (int64_t)(set + 1) * plane : 0) + i * kGradSlots);
+// One plane's 16 slots of (view, splat) i.
+__device__ __forceinline__ void load_plane(const float *__restrict__ p, int64_t i,
+                                           float (&a)[kGradSlots]) {
+  const float4 *p0 = reinterpret_cast<const float4 *>(p + i * kGradSlots);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const float4 t = p0[k];
@@ -718,7 +714,18 @@ __device__ __forceinline__ void load_slots(const float *__restrict__ accum, int6
     a[4 * k + 2] = t.z;
     a[4 * k + 3] = t.w;
   }
-  if constexpr (MODE == kBwdFdoSum) {
+}
+
+// The slots the chain takes: one plane (plain), or the FDO planes combined
+// in binary64 with the weights w.
+template <int MODE, typename T>
+__device__ __forceinline__ void load_slots(const float *__restrict__ accum, int64_t plane,
+                                           int64_t i, double2 w, T (&a)[kGradSlots]) {
+  float c[kGradSlots];
+  load_plane(accum, i, c);
+#pragma unroll
+  for (int k = 0; k < kGradSlots; ++k) a[k] = c[k];
+  if constexpr (MODE == kBwdFdo) {
     const float4 *p1 = reinterpret_cast<const float4 *>(accum + plane + i * kGradSlots);
     const float4 *p2 = reinterpret_cast<const float4 *>(accum + 2 * plane + i * kGradSlots);
 #pragma unroll
@@ -739,20 +746,20 @@ __device__ __forceinline__ void load_slots(const float *__restrict__ accum, int6
 // binary64 over means, scales, rotations, opacity and SH.  If d < 0 a 2D
 // primitive (type 0) takes w_low = 1 - d / |g_low|^2 (Eq. 9: g_high loses
 // its component along g_low), a 3D one w_high = 1 - d / |g_high|^2 (Eq. 10);
-// otherwise both are 1.  Writes (w_low, w_high); returns d < 0.
+// otherwise both are 1.  Sets w = (w_low, w_high); returns d < 0.
 template <int DEG>
-__device__ __forceinline__ bool fdo_dots_body(const SceneDev &sc, const DevCam *__restrict__ cams,
+__device__ __forceinline__ bool fdo_weights(const SceneDev &sc, const DevCam *__restrict__ cams,
                                               const DevOpts &opt, const uint8_t *__restrict__ flags,
                                               const int4 *__restrict__ rect,
                                               const float *__restrict__ accum, int64_t plane,
-                                              int64_t g, double2 *__restrict__ wts) {
+                                              int64_t g, double2 &w) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   double d = 0.0, nl = 0.0, nh = 0.0;
   const uint8_t fl = flags[g];
   if (fl & kValid) {
     float al[kGradSlots], ah[kGradSlots];
-    load_slots<kBwdFdoDots>(accum, plane, g, 0, make_double2(0.0, 0.0), al);
-    load_slots<kBwdFdoDots>(accum, plane, g, 1, make_double2(0.0, 0.0), ah);
+    load_plane(accum + plane, g, al);
+    load_plane(accum + 2 * plane, g, ah);
     bool anyl = false, anyh = false;
 #pragma unroll
     for (int k = 0; k < kGradSlots; ++k) {
@@ -826,7 +833,7 @@ __device__ __forceinline__ bool fdo_dots_body(const SceneDev &sc, const DevCam *
     else
       wh = 1.0 - d / nh;
   }
-  wts[g] = make_double2(wl, wh);
+  w = make_double2(wl, wh);
   return conflict;
 }
 
@@ -834,28 +841,27 @@ template <int DEG, bool MULTI, int MODE>
 __device__ __forceinline__ void preprocess_bwd_body(
     const SceneDev &sc, const DevCam *__restrict__ cams, int V, const DevOpts &opt,
     const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
-    const float *__restrict__ accum, int64_t plane, double2 *__restrict__ wts,
-    uint32_t *__restrict__ n_conflict, float *g_means, float *g_scales, float *g_rots,
+    const float *__restrict__ accum, int64_t plane, uint32_t *__restrict__ n_conflict,
+    float *g_means, float *g_scales, float *g_rots,
     float *g_opac, float *g_sh, int accumulate) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if constexpr (MODE == kBwdFdoDots) {
+  double2 wgt = make_double2(0.0, 0.0);
+  if constexpr (MODE == kBwdFdo) {
     // conflicts of this block, added once per block
     __shared__ uint32_t blk_conf;
     if (threadIdx.x == 0) blk_conf = 0;
     __syncthreads();
     bool conf = false;
-    if (g < sc.n) conf = fdo_dots_body<DEG>(sc, cams, opt, flags, rect, accum, plane, g, wts);
+    if (g < sc.n) conf = fdo_weights<DEG>(sc, cams, opt, flags, rect, accum, plane, g, wgt);
     const uint64_t m = __ballot(conf);
     if ((threadIdx.x & 63) == 0 && m) atomicAdd(&blk_conf, (uint32_t)__popcll(m));
     __syncthreads();
     if (threadIdx.x == 0 && blk_conf && n_conflict) atomicAdd(n_conflict, blk_conf);
-    return;
-  } else {
+  }
   if (g >= sc.n) return;
-  const double2 wgt = MODE == kBwdFdoSum ? wts[g] : make_double2(0.0, 0.0);
   // the combined slots are formed and kept in binary64
-  using Slot = typename std::conditional<MODE == kBwdFdoSum, double, float>::type;
+  using Slot = typename std::conditional<MODE == kBwdFdo, double, float>::type;
   const bool is2d = sc.types[g] == 0;
   const float m[3] = {sc.means[3 * g], sc.means[3 * g + 1], sc.means[3 * g + 2]};
   const float s[3] = {sc.scales[3 * g], sc.scales[3 * g + 1], sc.scales[3 * g + 2]};
@@ -871,7 +877,7 @@ __device__ __forceinline__ void preprocess_bwd_body(
     const uint8_t fl = flags[i];
     if (!(fl & kValid)) continue;
     Slot a[kGradSlots];
-    load_slots<MODE>(accum, plane, i, 0, wgt, a);
+    load_slots<MODE>(accum, plane, i, wgt, a);
     bool any = false;
 #pragma unroll
     for (int k = 0; k < kGradSlots; ++k) any = any || (a[k] != 0.0f);
@@ -917,7 +923,7 @@ __device__ __forceinline__ void preprocess_bwd_body(
     if (!(flags[i] & kValid)) continue;
     const float *ap = accum + i * kGradSlots;
     Slot gcol[3] = {ap[10], ap[11], ap[12]};
-    if constexpr (MODE == kBwdFdoSum) {
+    if constexpr (MODE == kBwdFdo) {
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch)
         gcol[ch] += wgt.x * (double)ap[plane + 10 + ch] + wgt.y * (double)ap[2 * plane + 10 + ch];
@@ -961,7 +967,6 @@ __device__ __forceinline__ void preprocess_bwd_body(
       }
     }
   }
-  }  // modes
 }
 
 template <int DEG, bool MULTI>
@@ -971,31 +976,19 @@ preprocess_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOp
                       const float *__restrict__ accum, float *g_means, float *g_scales,
                       float *g_rots, float *g_opac, float *g_sh, int accumulate) {
   preprocess_bwd_body<DEG, MULTI, kBwdPlain>(sc, cams, V, opt, flags, rect, accum, 0, nullptr,
-                                             nullptr, g_means, g_scales, g_rots, g_opac, g_sh,
-                                             accumulate);
+                                             g_means, g_scales, g_rots, g_opac, g_sh, accumulate);
 }
 
 template <int DEG>
 __global__ void __launch_bounds__(128)
-fdo_weights_kernel(SceneDev sc, const DevCam *__restrict__ cams, DevOpts opt,
-                   const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
-                   const float *__restrict__ accum, int64_t plane, double2 *__restrict__ wts,
-                   uint32_t *__restrict__ n_conflict) {
-  preprocess_bwd_body<DEG, false, kBwdFdoDots>(sc, cams, 1, opt, flags, rect, accum, plane, wts,
-                                               n_conflict, nullptr, nullptr, nullptr, nullptr,
-                                               nullptr, 0);
-}
-
-template <int DEG>
-__global__ void __launch_bounds__(128)
-fdo_combined_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, DevOpts opt,
-                        const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
-                        const float *__restrict__ accum, int64_t plane,
-                        double2 *__restrict__ wts, float *g_means, float *g_scales, float *g_rots,
-                        float *g_opac, float *g_sh, int accumulate) {
-  preprocess_bwd_body<DEG, false, kBwdFdoSum>(sc, cams, 1, opt, flags, rect, accum, plane, wts,
-                                              nullptr, g_means, g_scales, g_rots, g_opac, g_sh,
-                                              accumulate);
+fdo_fused_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, DevOpts opt,
+                     const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
+                     const float *__restrict__ accum, int64_t plane,
+                     uint32_t *__restrict__ n_conflict, float *g_means, float *g_scales,
+                     float *g_rots, float *g_opac, float *g_sh, int accumulate) {
+  preprocess_bwd_body<DEG, false, kBwdFdo>(sc, cams, 1, opt, flags, rect, accum, plane,
+                                           n_conflict, g_means, g_scales, g_rots, g_opac, g_sh,
+                                           accumulate);
 }
 }  // namespace
 
@@ -1049,31 +1042,19 @@ void launch_preprocess_bwd(const SceneDev &sc, const DevCam *cams, int V, DevOpt
 #undef HGS_BWD
 }
 
-void launch_fdo_weights(const SceneDev &sc, const DevCam *cams, DevOpts opt, const uint8_t *flags,
-                        const int4 *rect, const float *accum, int64_t plane, double2 *wts,
-                        uint32_t *n_conflict, hipStream_t s) {
+void launch_fdo_fused_bwd(const SceneDev &sc, const DevCam *cams, DevOpts opt,
+                          const uint8_t *flags, const int4 *rect, const float *accum,
+                          int64_t plane, uint32_t *n_conflict, float *g_means, float *g_scales,
+                          float *g_rots, float *g_opac, float *g_sh, int accumulate,
+                          hipStream_t s) {
   if (sc.n == 0) return;
   const dim3 grid((unsigned)((sc.n + 127) / 128));
-#define HGS_W(D)                                                                            \
-  hipLaunchKernelGGL(fdo_weights_kernel<D>, grid, dim3(128), 0, s, sc, cams, opt, flags, rect, \
-                     accum, plane, wts, n_conflict)
-  HGS_BY_DEGREE(sc.sh_degree, HGS_W)
-#undef HGS_W
-}
-
-void launch_fdo_combined_bwd(const SceneDev &sc, const DevCam *cams, DevOpts opt,
-                             const uint8_t *flags, const int4 *rect, const float *accum,
-                             int64_t plane, const double2 *wts, float *g_means, float *g_scales,
-                             float *g_rots, float *g_opac, float *g_sh, int accumulate,
-                             hipStream_t s) {
-  if (sc.n == 0) return;
-  const dim3 grid((unsigned)((sc.n + 127) / 128));
-  double2 *w = const_cast<double2 *>(wts);  // read only
-#define HGS_C(D)                                                                              \
-  hipLaunchKernelGGL(fdo_combined_bwd_kernel<D>, grid, dim3(128), 0, s, sc, cams, opt, flags, \
-                     rect, accum, plane, w, g_means, g_scales, g_rots, g_opac, g_sh, accumulate)
-  HGS_BY_DEGREE(sc.sh_degree, HGS_C)
-#undef HGS_C
+#define HGS_F(D)                                                                              \
+  hipLaunchKernelGGL(fdo_fused_bwd_kernel<D>, grid, dim3(128), 0, s, sc, cams, opt, flags, rect, \
+                     accum, plane, n_conflict, g_means, g_scales, g_rots, g_opac, g_sh,         \
+                     accumulate)
+  HGS_BY_DEGREE(sc.sh_degree, HGS_F)
+#undef HGS_F
 }
 #undef HGS_BY_DEGREE
 

@@ -12,8 +12,8 @@ Alg. 1; appendices on the DWT and on gradient conflicts).
   cotangent set (the gradient tolerance of the plain backward), and the
   update against the oracle's projection of the oracle's sets wherever the
   conflict decision is not within the gradient tolerance of a tie.
-* One view without stored sets (a weights pass, then the backward of the
-  slots combined in binary64 with those weights): the update of the path
+* One view without stored sets (per primitive, the weights, then the
+  backward of the slots combined in binary64 with those weights): the update of the path
   that stores and projects the sets, per primitive within 2e-5 of its
   terms' norms (the two traversals' atomic slot sums round in different
   orders, and the chain's cancellation scales that up for some
@@ -257,8 +257,8 @@ def _flat(d, N):
 
 @pytest.mark.parametrize("name", sorted(ONE_VIEW))
 def test_one_view_without_sets_equals_projection(name):
-    """One view, no sets: the weights pass and the backward of the combined
-    slots give the update that projecting the three stored sets gives, and
+    """One view, no sets: the per-primitive weights and the backward of the
+    combined slots give the update that projecting the three stored sets gives, and
     the oracle's projection of the oracle's sets."""
     import torch
     import oracle
@@ -318,7 +318,7 @@ def test_one_view_without_sets_equals_projection(name):
     for k in PARAM_KEYS:
         a, b = upd[k].double(), upd_sets[k].double()
         rels[k] = float((a - b).norm()) / max(float(b.norm()), 1e-300)
-    say(f"[fdo] {name} two-pass vs stored sets: worst per primitive {worst:.3g}, "
+    say(f"[fdo] {name} one-view path vs stored sets: worst per primitive {worst:.3g}, "
         f"relative L2 per array {rels}")
     assert all(v <= 1e-6 for v in rels.values()), rels
     assert abs(int(cnt.item()) - int(cnt_sets.item())) <= int(close.sum())
@@ -346,7 +346,7 @@ def test_one_view_without_sets_equals_projection(name):
     assert (e[ok] <= 3e-3 * scale[ok] + 1e-12).all(), float((e[ok] / scale[ok]).max())
     nc = int(ref["conflict"].sum())
     assert abs(int(cnt.item()) - nc) <= int(near.sum()), (int(cnt.item()), nc)
-    say(f"[fdo] {name} two-pass: conflicts {int(cnt.item())} (sets path {int(cnt_sets.item())}, "
+    say(f"[fdo] {name} one-view path: conflicts {int(cnt.item())} (sets path {int(cnt_sets.item())}, "
         f"oracle {nc}), near-ties {int(near.sum())}")
 
 
@@ -395,7 +395,7 @@ def test_full_size_three_sets_equal_three_single_traversals():
     mag = flat[0].abs() + (wl[:, None] * flat[1]).abs() + (wh[:, None] * flat[2]).abs()
     assert bool(((got - expect).abs() <= 1e-6 * mag + 1e-30).all())
     assert int(cnt.item()) == int((d < 0).sum())
-    # the launch the benchmark times: no sets, weights pass + combined backward
+    # the launch the benchmark times: no sets, weights and combined backward
     _, state = rast.render(sc, cam, want_state=True)
     upd2 = {k: torch.zeros_like(sc[k]) for k in PARAM_KEYS}
     cnt2 = torch.zeros(1, dtype=torch.int32, device="cuda")
