@@ -138,6 +138,41 @@ struct ViewOut {
   uint32_t *last, *n_contrib, *wcount;
 };
 
+// 2D record: U, V, W (rows of the inverse map, affine in the local pixel
+// frame) span intervals over the box of the quadrant's pixel samples, with
+// their extremes at the corners; each interval is widened by the rounding
+// of a binary32 evaluation.  If W's interval excludes 0, the exponent
+// e = (U^2 + V^2) / W^2 is at least (min U^2 + min V^2) / max W^2 at every
+// sample, and the record is dropped if that bound exceeds
+// log2(alpha_eff * 255) by a margin.
+__device__ __forceinline__ bool meets_2d(const float4 &r0, const float4 &r1, const float4 &r2,
+                                         const float4 &r3, const float4 &r4, float qx, float qy) {
+  const float xa = (qx + 0.5f) - r0.x, xb = (qx + 7.5f) - r0.x;
+  const float ya = (qy + 0.5f) - r0.y, yb = (qy + 7.5f) - r0.y;
+  const float mx = fmaxf(fabsf(xa), fabsf(xb)), my = fmaxf(fabsf(ya), fabsf(yb));
+  auto span = [&](float a, float b, float c, float &lo, float &hi) {
+    const float t0 = __builtin_fmaf(a, xa, __builtin_fmaf(b, ya, c));
+    const float t1 = __builtin_fmaf(a, xb, __builtin_fmaf(b, ya, c));
+    const float t2 = __builtin_fmaf(a, xa, __builtin_fmaf(b, yb, c));
+    const float t3 = __builtin_fmaf(a, xb, __builtin_fmaf(b, yb, c));
+    const float pad = 1e-6f * (fabsf(a) * mx + fabsf(b) * my + fabsf(c));
+    lo = fminf(fminf(t0, t1), fminf(t2, t3)) - pad;
+    hi = fmaxf(fmaxf(t0, t1), fmaxf(t2, t3)) + pad;
+  };
+  auto sqmin = [](float lo, float hi) {
+    return (lo <= 0.0f && hi >= 0.0f) ? 0.0f : fminf(lo * lo, hi * hi);
+  };
+  float ul, uh, vl, vh, wl, wh;
+  span(r1.x, r1.y, r1.z, ul, uh);
+  span(r1.w, r2.x, r2.y, vl, vh);
+  span(r2.z, r2.w, r3.x, wl, wh);
+  if (!(wl > 0.0f || wh < 0.0f)) return true;  // W may vanish (or NaN): keep
+  const float w2 = fmaxf(wl * wl, wh * wh);
+  const float elb = (sqmin(ul, uh) + sqmin(vl, vh)) / w2;
+  const float lim = __builtin_amdgcn_logf(fabsf(r4.w) * 255.0f);
+  return !(elb > lim + 1e-3f + 1e-3f * fabsf(lim));
+}
+
 // Can the record reach alpha~ >= 1/255 at a pixel of the quadrant?  Its
 // inclusive pixel rectangle (r0) must meet the quadrant.  For a 3D record
 // the exponent e = A dx^2 + B dx dy + C dy^2 (positive definite) is also
@@ -149,10 +184,10 @@ struct ViewOut {
 // rounding of the binary32 evaluation in eval_pair.  Dropping a record that
 // contributes to no pixel of the quadrant changes nothing.
 __device__ __forceinline__ bool meets(const float4 &r0, const float4 &r1, const float4 &r2,
-                                      const float4 &r4, const Quad &q) {
+                                      const float4 &r3, const float4 &r4, const Quad &q) {
   const float qx = (float)q.qx, qy = (float)q.qy;
   if (!(r0.x <= qx + 7.0f && r0.z >= qx && r0.y <= qy + 7.0f && r0.w >= qy)) return false;
-  if (__float_as_uint(r4.w) >> 31) return true;  // 2D: the rectangle only
+  if (__float_as_uint(r4.w) >> 31) return meets_2d(r0, r1, r2, r3, r4, qx, qy);
   const float A = r1.z, B = r1.w, C = r2.x;
   if (!(A > 0.0f && C > 0.0f)) return true;
   // sample box in the record's frame, as eval_pair forms dx, dy
@@ -210,7 +245,7 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
   if (kWave + lane < n) nid = vals[rg.x + kWave + lane];
   for (int c = 0; c < n; c += kWave) {
     if (__ballot(thr < 1.0f) == 0ull) break;
-    const bool hit = (c + lane < n) && meets(q0, q1, q2, q4, q);
+    const bool hit = (c + lane < n) && meets(q0, q1, q2, q3, q4, q);
     const uint64_t m = __ballot(hit);
     __syncthreads();  // the previous chunk's slots have been read
     if (hit) {
@@ -576,7 +611,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   }
   if (c > 0) nid = vals[rg.x + c - kWave + lane];
   for (; c >= 0; c -= kWave) {
-    const bool hit = (c + lane < n) && meets(q0, q1, q2, q4, q);
+    const bool hit = (c + lane < n) && meets(q0, q1, q2, q3, q4, q);
     const uint64_t m = __ballot(hit);
     __syncthreads();  // the previous chunk's slots have been read
     if (hit) {
