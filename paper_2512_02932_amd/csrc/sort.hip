@@ -27,6 +27,7 @@ namespace {
 
 constexpr int kScanItems = 16;                       // elements per thread
 constexpr int kScanChunk = kBlock * kScanItems;      // 4096 per block
+constexpr int64_t kFlatChunks = 2048;  // up to 8M elements: two launches per scan
 
 // Element count of a launch: the host capacity n, or min(n, *n_dev) when the
 // count lives on the device (graph-captured launches never read it back).
@@ -134,6 +135,28 @@ __global__ void __launch_bounds__(256) scan_down_u64(const uint64_t *__restrict_
                                                      const uint64_t *__restrict__ offs) {
   __shared__ uint64_t lds[4];
   scan_chunk<uint64_t, uint64_t>(in, out, n, offs ? offs[blockIdx.x] : 0, lds);
+}
+
+// Exclusive scan of one chunk when the chunk sums are few (nb <= kFlatChunks):
+// each block adds up the sums of the chunks before it itself, so no scan of
+// the sums is launched.  Block 0 also writes the grand total (sums of chunks
+// past the device count are 0) if `total` is given.
+__global__ void __launch_bounds__(256) scan_down_flat_u32(const uint32_t *__restrict__ in,
+                                                          uint32_t *__restrict__ out, int64_t n,
+                                                          const uint64_t *__restrict__ n_dev,
+                                                          const uint64_t *__restrict__ sums,
+                                                          int64_t nb, uint64_t *__restrict__ total) {
+  __shared__ uint64_t lds[4];
+  n = eff_n(n, n_dev);
+  if ((int64_t)blockIdx.x * kScanChunk >= n && !(blockIdx.x == 0 && total)) return;
+  // block b: the sum of chunks 0 .. b-1; block 0 (offset 0): all nb chunks
+  const int64_t upto = (blockIdx.x == 0 && total) ? nb : (int64_t)blockIdx.x;
+  uint64_t acc = 0;
+  for (int64_t j = threadIdx.x; j < upto; j += kBlock) acc += sums[j];
+  uint64_t sum;
+  block_exclusive_scan<uint64_t>(acc, lds, sum);
+  if (blockIdx.x == 0 && total && threadIdx.x == 0) *total = sum;
+  scan_chunk<uint32_t, uint32_t>(in, out, n, blockIdx.x == 0 ? 0 : sum, lds);
 }
 
 __global__ void scan_total(const uint64_t *__restrict__ excl, const uint64_t *__restrict__ sums,
@@ -358,6 +381,11 @@ void launch_scan(const uint32_t *in, uint32_t *out, int64_t n, uint64_t *total, 
   const int64_t nb = nchunks(n);
   uint64_t *sums = (uint64_t *)tmp, *offs = sums + nb, *rest = sums + 2 * nb + 2;
   hipLaunchKernelGGL(scan_reduce_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, n_dev, sums);
+  if (nb <= kFlatChunks) {
+    hipLaunchKernelGGL(scan_down_flat_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n,
+                       n_dev, (const uint64_t *)sums, nb, total);
+    return;
+  }
   scan_u64(sums, offs, nb, rest, s);
   hipLaunchKernelGGL(scan_down_u32, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, n_dev,
                      (const uint64_t *)offs);
