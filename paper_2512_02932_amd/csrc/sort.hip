@@ -355,6 +355,12 @@ __global__ void fill_f32_kernel(float *p, float v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
+// 16-byte stores for a 16-byte aligned array (n4 float4s).
+__global__ void fill_f32x4_kernel(float4 *p, float v, int64_t n4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n4) p[i] = make_float4(v, v, v, v);
+}
+
 __global__ void ranges_kernel(const uint32_t *__restrict__ keys, int64_t D,
                               const uint64_t *__restrict__ D_dev, uint2 *__restrict__ ranges) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -465,6 +471,14 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
 
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
   if (n <= 0) return;
+  if ((reinterpret_cast<uintptr_t>(p) & 15u) == 0 && n >= 4) {
+    const int64_t n4 = n / 4, tail = n - 4 * n4;
+    hipLaunchKernelGGL(fill_f32x4_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<float4 *>(p), v, n4);
+    if (tail)
+      hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(256), 0, s, p + 4 * n4, v, tail);
+    return;
+  }
   hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
 }
 
