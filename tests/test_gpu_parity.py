@@ -31,6 +31,12 @@ CASES = {
                                                    fx=150.0)),
     # three views in one launch, sphere surface (70% surfels), SH degree 3
     "sphere20k_3views": lambda: (sg.scene_sphere(20_000, seed=14), _cams_multi()),
+    # strongly anisotropic splats (scale log-sd 1.4: needles and slivers,
+    # many at grazing angles) seen obliquely: exercises the quadrant culling
+    # of 3D ellipses and the interval bound on surfels near their limits
+    "aniso1500_173x131": lambda: (sg.scene_random(1500, seed=21, log_mu=-3.0, log_sigma=1.4),
+                                  sg.look_at_camera((1.8, 1.2, -2.6), width=173, height=131,
+                                                    fx=140.0)),
     # torus knot at reduced resolution (surface-like depth complexity)
     "knot60k_320x213": lambda: (sg.scene_torus_knot(60_000, seed=15),
                                 sg.camera_torus_knot(width=320, height=213, f=240.0)),
