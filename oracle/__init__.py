@@ -31,7 +31,12 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 DEFAULT_OPTS = dict(bg=(0.0, 0.0, 0.0), dilation=0.3, lambda_z=1.0, theta_z=1.05,
-                    temp_z=0.001, pix_off=(0.0, 0.0))
+                    temp_z=0.001, pix_off=(0.0, 0.0), alpha_min=1.0 / 255.0, alpha_max=0.99,
+                    t_min=1e-4)
+# Tie margins (relative): activity |raw - alpha_min|, stop |T' - t_min|, clamp
+# |raw - alpha_max|.  A decision this close to its threshold may go either way
+# in a binary32 evaluation.
+DEFAULT_MARGINS = (1e-4, 1e-3, 1e-3)
 
 
 def build(force: bool = True) -> str:
@@ -51,17 +56,19 @@ def _load():
             build(force=True)
         _lib = C.CDLL(_LIB)
         P = C.c_void_p
-        _lib.oracle_structural.argtypes = [P] * 5 + [C.c_int64, P, C.c_int, C.c_float] + [P] * 5
+        _lib.oracle_structural.argtypes = ([P] * 5 + [C.c_int64, P, C.c_int, C.c_float,
+                                                      C.c_double] + [P] * 5)
         _lib.oracle_sorted_pairs.argtypes = [P, P, P, C.c_int64, P, C.c_int, P, P, C.c_int64, P,
                                              C.c_int64]
         _lib.oracle_sorted_pairs.restype = C.c_int64
         _lib.oracle_forward.argtypes = ([P] * 6 + [C.c_int64, C.c_int] + [P] * 5 +
-                                        [P, C.c_int, P, P, P, C.c_int64, C.c_int, C.c_int] +
-                                        [P] * 5)
+                                        [P, C.c_int, P, P, P, C.c_int64, P, C.c_int, C.c_int] +
+                                        [P] * 6)
         _lib.oracle_backward.argtypes = ([P] * 6 + [C.c_int64, C.c_int] + [P] * 5 +
-                                         [P, C.c_int, P, P, C.c_int64, P, C.c_int] + [P] * 5)
+                                         [P, C.c_int, P, P, P, C.c_int64, P, P, C.c_int] +
+                                         [P] * 6)
         _lib.oracle_screen_grad.argtypes = ([P] * 6 + [C.c_int64, C.c_int] + [P] * 5 +
-                                            [P, C.c_int, P, P, C.c_int64, P, C.c_int, P])
+                                            [P, C.c_int, P, P, P, C.c_int64, P, P, C.c_int, P])
         _lib.oracle_sh_basis.argtypes = [C.c_int, P, C.c_int64, P]
         _lib.oracle_surfel_uv.argtypes = [P, P, P, C.c_int64, P]
         _lib.oracle_erank.argtypes = [C.c_double, C.c_double, C.c_double]
@@ -91,7 +98,7 @@ def _opts_vec(opts):
     o = dict(DEFAULT_OPTS)
     o.update(opts or {})
     return np.array(list(o["bg"]) + [o["dilation"], o["lambda_z"], o["theta_z"], o["temp_z"]] +
-                    list(o["pix_off"]), np.float64)
+                    list(o["pix_off"]) + [o["alpha_min"], o["alpha_max"], o["t_min"]], np.float64)
 
 
 def _f32(scene):
@@ -106,7 +113,7 @@ def _f64(scene, params64=None):
             ("means", "scales", "rotations", "opacities", "sh")]
 
 
-def structural(scene, cams, dilation=0.3):
+def structural(scene, cams, dilation=0.3, alpha_min=1.0 / 255.0):
     lib = _load()
     m, s, r, o, _, t = _f32(scene)
     n = m.shape[0]
@@ -118,7 +125,7 @@ def structural(scene, cams, dilation=0.3):
     zb = np.zeros(V * n, np.uint32)
     flip = np.zeros(V * n, np.uint8)
     lib.oracle_structural(_p(m), _p(s), _p(r), _p(o), _p(t), n, _p(cp), V, float(dilation),
-                          _p(valid), _p(rect), _p(tiles), _p(zb), _p(flip))
+                          float(alpha_min), _p(valid), _p(rect), _p(tiles), _p(zb), _p(flip))
     return dict(valid=valid, rect=rect, tiles=tiles, zbits=zb, flip=flip, n=n)
 
 
@@ -150,49 +157,67 @@ def full_pixels(cam, view=0):
                                 np.int32)
 
 
+def _flip_arr(flip, P):
+    if flip is None:
+        return None
+    f = np.ascontiguousarray(np.broadcast_to(np.asarray(flip, np.uint32), (P,)), np.uint32)
+    return f
+
+
 def forward(scene, cams, pix, opts=None, *, params64=None, brute=False, threads=None,
-            margins=(1e-4, 1e-3, 1e-3)):
+            margins=DEFAULT_MARGINS, flip=None):
     """Binary64 forward at pixels ``pix`` ([P,3] = view, y, x).
 
     Returns dict(out=[P,8] (r,g,b,alpha,depth,nx,ny,nz), T=[P], n_contrib=[P],
-    last=[P], tie=[P] bit flags (1 alpha threshold, 2 stop, 4 clamp),
-    wcount=[2] (active pairs up to and including the stop, per type 2D/3D)).
+    last=[P], tie=[P] bit flags (1 activity threshold, 2 stop, 4 clamp),
+    nflags=[P] (activity and stop ties met), wcount=[2] (active pairs up to
+    and including the stop, per type 2D/3D)).  ``flip`` ([P] or a scalar):
+    bit k takes the other outcome of the k-th activity or stop tie of the
+    pixel, a branch that a binary32 evaluation may legitimately follow.
     """
     lib = _load()
     m, s, r, o, sh, t = _f32(scene)
     m6, s6, r6, o6, sh6 = _f64(scene, params64)
     cp = pack_cams(cams)
-    pix = np.ascontiguousarray(pix, np.int32)
+    pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 3)
     P = pix.shape[0]
     out = np.zeros((P, 8), np.float64)
     T = np.zeros(P, np.float64)
     cnt = np.zeros((P, 2), np.int32)
     tie = np.zeros(P, np.uint8)
+    nfl = np.zeros(P, np.int32)
     wc = np.zeros(2, np.int64)
     ov = _opts_vec(opts)
     mg = np.asarray(margins, np.float64)
+    fl = _flip_arr(flip, P)
     lib.oracle_forward(_p(m), _p(s), _p(r), _p(o), _p(sh), _p(t), m.shape[0],
                        int(scene["sh_degree"]), _p(m6), _p(s6), _p(r6), _p(o6), _p(sh6), _p(cp),
-                       cp.shape[0], _p(ov), _p(mg), _p(pix), P, int(brute),
+                       cp.shape[0], _p(ov), _p(mg), _p(pix), P,
+                       None if fl is None else _p(fl), int(brute),
                        int(threads or os.cpu_count() or 1), _p(out), _p(T), _p(cnt), _p(tie),
-                       _p(wc))
-    return dict(out=out, T=T, n_contrib=cnt[:, 0], last=cnt[:, 1], tie=tie, wcount=wc)
+                       _p(nfl), _p(wc))
+    return dict(out=out, T=T, n_contrib=cnt[:, 0], last=cnt[:, 1], tie=tie, nflags=nfl,
+                wcount=wc)
 
 
-def backward(scene, cams, pix, G, opts=None, *, params64=None, threads=None):
-    """Binary64 gradients of L = sum_p <G_p, out_p> over pixels ``pix``.
+def backward(scene, cams, pix, G, opts=None, *, params64=None, threads=None,
+             margins=DEFAULT_MARGINS, flip=None):
+    """Binary64 gradients of L = sum_p <G_p, out_p> over pixels ``pix``, on
+    the branches ``flip`` (see :func:`forward`).
 
     Returns dict of gradients (means [N,3], scales [N,3], rotations [N,4],
     opacities [N], sh [N,K,3]) and, as tolerance scales, the same keys with
-    suffix ``_abs`` (sums of the absolute per-pair terms) and ``_cond`` (the
-    condition scale of a binary32 evaluation; SH terms are products, so
-    ``sh_cond`` equals ``sh_abs``).
+    suffixes ``_abs`` (sums of the absolute per-pair terms), ``_cond`` (the
+    rounding bound of a binary32 evaluation of the dL/dalpha~ path, in units
+    of the binary32 unit roundoff; SH terms are products, so ``sh_cond`` is
+    zero) and ``_tie`` (the difference between the clamped and unclamped
+    branches at clamp ties; zero for SH).
     """
     lib = _load()
     m, s, r, o, sh, t = _f32(scene)
     m6, s6, r6, o6, sh6 = _f64(scene, params64)
     cp = pack_cams(cams)
-    pix = np.ascontiguousarray(pix, np.int32)
+    pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 3)
     G = np.ascontiguousarray(G, np.float64)
     n = m.shape[0]
     K = sh.shape[1]
@@ -201,22 +226,31 @@ def backward(scene, cams, pix, G, opts=None, *, params64=None, threads=None):
     gs = np.zeros((n, K, 3), np.float64)
     as_ = np.zeros((n, K, 3), np.float64)
     cp_ = np.zeros((n, 11), np.float64)
+    xp = np.zeros((n, 11), np.float64)
+    mg = np.asarray(margins, np.float64)
+    fl = _flip_arr(flip, pix.shape[0])
     lib.oracle_backward(_p(m), _p(s), _p(r), _p(o), _p(sh), _p(t), n, int(scene["sh_degree"]),
                         _p(m6), _p(s6), _p(r6), _p(o6), _p(sh6), _p(cp), cp.shape[0],
-                        _p(_opts_vec(opts)), _p(pix), pix.shape[0], _p(G),
+                        _p(_opts_vec(opts)), _p(mg), _p(pix), pix.shape[0],
+                        None if fl is None else _p(fl), _p(G),
                         int(threads or os.cpu_count() or 1), _p(gp), _p(gs), _p(ap), _p(as_),
-                        _p(cp_))
-    return dict(means=gp[:, 0:3], scales=gp[:, 3:6], rotations=gp[:, 6:10], opacities=gp[:, 10],
-                sh=gs, means_abs=ap[:, 0:3], scales_abs=ap[:, 3:6], rotations_abs=ap[:, 6:10],
-                opacities_abs=ap[:, 10], sh_abs=as_, means_cond=cp_[:, 0:3],
-                scales_cond=cp_[:, 3:6], rotations_cond=cp_[:, 6:10], opacities_cond=cp_[:, 10],
-                sh_cond=as_)
+                        _p(cp_), _p(xp))
+    z = np.zeros_like(gs)
+    out = dict(sh=gs, sh_abs=as_, sh_cond=z, sh_tie=z)
+    for key, sl in (("means", slice(0, 3)), ("scales", slice(3, 6)), ("rotations", slice(6, 10)),
+                    ("opacities", 10)):
+        out[key] = gp[:, sl]
+        out[key + "_abs"] = ap[:, sl]
+        out[key + "_cond"] = cp_[:, sl]
+        out[key + "_tie"] = xp[:, sl]
+    return out
 
 
-def screen_grad(scene, cams, pix, G, opts=None, *, params64=None, threads=None):
+def screen_grad(scene, cams, pix, G, opts=None, *, params64=None, threads=None,
+                margins=DEFAULT_MARGINS, flip=None):
     """dL/d delta [V, N, 2] (binary64): the gradient of L = sum_p <G_p, out_p>
     with respect to a translation of each splat's screen footprint (pixel
-    units) in each view."""
+    units) in each view, on the tie branches ``flip`` (see :func:`forward`)."""
     lib = _load()
     m, s, r, o, sh, t = _f32(scene)
     m6, s6, r6, o6, sh6 = _f64(scene, params64)
@@ -226,22 +260,27 @@ def screen_grad(scene, cams, pix, G, opts=None, *, params64=None, threads=None):
     n = m.shape[0]
     V = cp.shape[0]
     out = np.zeros((V, n, 2), np.float64)
+    mg = np.asarray(margins, np.float64)
+    fl = _flip_arr(flip, pix.shape[0])
     lib.oracle_screen_grad(_p(m), _p(s), _p(r), _p(o), _p(sh), _p(t), n,
                            int(scene["sh_degree"]), _p(m6), _p(s6), _p(r6), _p(o6), _p(sh6),
-                           _p(cp), V, _p(_opts_vec(opts)), _p(pix), pix.shape[0], _p(G),
+                           _p(cp), V, _p(_opts_vec(opts)), _p(mg), _p(pix), pix.shape[0],
+                           None if fl is None else _p(fl), _p(G),
                            int(threads or os.cpu_count() or 1), _p(out))
     return out
 
 
-def densify_stats(scene, cams, pix, G, opts=None):
+def densify_stats(scene, cams, pix, G, opts=None, *, flip=None):
     """3DGS's densification statistics for one backward: per splat, the sum
     over the views in which it is not culled of |dL/d(screen centre)| in
     NDC units (the pixel-unit gradient times (W/2, H/2)), and the number of
     those views.  Returns (grad_norm [N], count [N])."""
     if isinstance(cams, dict):
         cams = [cams]
-    sg = screen_grad(scene, cams, pix, G, opts)
-    st = structural(scene, cams, (opts or {}).get("dilation", DEFAULT_OPTS["dilation"]))
+    sg = screen_grad(scene, cams, pix, G, opts, flip=flip)
+    o = dict(DEFAULT_OPTS)
+    o.update(opts or {})
+    st = structural(scene, cams, o["dilation"], o["alpha_min"])
     n = sg.shape[1]
     valid = st["valid"].reshape(len(cams), n) == 1
     norm = np.zeros(n)

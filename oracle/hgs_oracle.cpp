@@ -60,9 +60,10 @@ namespace {
 // Method constants (thresholds taken from the prior-art rasterizer that the
 // paper builds on, Sec. 4 "Implementation").
 // ---------------------------------------------------------------------------
-constexpr double kAlphaMin = 1.0 / 255.0;
-constexpr double kAlphaMax = 0.99;
-constexpr double kTMin = 1e-4;
+// Defaults of the three thresholds; every call takes them as options.
+constexpr double kAlphaMin = 1.0 / 255.0;  // skip a pair below this contribution
+constexpr double kAlphaMax = 0.99;         // clamp a contribution at this value
+constexpr double kTMin = 1e-4;             // stop before T falls below this
 
 struct Scene32 {
   const float *means, *scales, *rots, *opac, *sh;
@@ -97,6 +98,7 @@ struct Opts {
   float dilation;
   double lambda_z, theta_z, temp_z;
   double pix_off[2];  // offset of every pixel sample (0 for rendering; finite-difference pins)
+  double amin, amax, tmin;  // skip, clamp and stop thresholds
 };
 
 Opts load_opts(const double *o) {
@@ -105,6 +107,7 @@ Opts load_opts(const double *o) {
   p.dilation = (float)o[3];
   p.lambda_z = o[4]; p.theta_z = o[5]; p.temp_z = o[6];
   p.pix_off[0] = o[7]; p.pix_off[1] = o[8];
+  p.amin = o[9]; p.amax = o[10]; p.tmin = o[11];
   return p;
 }
 
@@ -119,11 +122,27 @@ struct Struct {
   uint8_t flip;                // 1 if the normal is negated to face the camera
 };
 
-// Smallest binary32 value >= 2 ln 255: radius^2 of the alpha = 1 support.
-constexpr float kRR0 = 11.0825272f;
 constexpr float kPad = 1.00390625f;  // 1 + 2^-8
 
-Struct structural(const Scene32 &s, int64_t g, const Cam &c, float delta) {
+// Inputs of the structural decisions besides the scene and camera.
+struct StructCfg {
+  float delta;  // screen-space dilation of 3D splats
+  float amin;   // skip threshold, binary32
+  float rr0;    // smallest binary32 >= 2 ln(1 / amin): radius^2 of the alpha = 1 support
+};
+
+StructCfg struct_cfg(float delta, double amin) {
+  StructCfg c;
+  c.delta = delta;
+  c.amin = (float)amin;
+  const double r = 2.0 * std::log(1.0 / (double)c.amin);
+  float f = (float)r;
+  if ((double)f < r) f = std::nextafter(f, INFINITY);
+  c.rr0 = f;
+  return c;
+}
+
+Struct structural(const Scene32 &s, int64_t g, const Cam &c, const StructCfg &cfg) {
   Struct o{};
   o.valid = 0;
   const float *V = c.V;
@@ -139,7 +158,7 @@ Struct structural(const Scene32 &s, int64_t g, const Cam &c, float delta) {
   const float yc = ((V[4] * mx + V[5] * my) + V[6] * mz) + V[7];
   const float zc = ((V[8] * mx + V[9] * my) + V[10] * mz) + V[11];
   if (!(zc > c.znear)) return o;
-  if (!(al >= 1.0f / 255.0f)) return o;
+  if (!(al >= cfg.amin)) return o;
 
   // Rotation from the (not necessarily unit) quaternion (w, x, y, z).
   const float n2 = ((rw * rw + rx * rx) + ry * ry) + rz * rz;
@@ -157,8 +176,8 @@ Struct structural(const Scene32 &s, int64_t g, const Cam &c, float delta) {
   R[2][2] = 1.0f - k2 * (rx * rx + ry * ry);
 
   // Support radius^2 from the unmodulated opacity (a Pade bound on
-  // 2 ln(255 alpha), never below it for alpha <= 1).
-  const float rr = kRR0 + 4.0f * ((al - 1.0f) / (al + 1.0f));
+  // 2 ln(alpha / amin), never below it for alpha <= 1).
+  const float rr = cfg.rr0 + 4.0f * ((al - 1.0f) / (al + 1.0f));
 
   const float sc[3] = {sx, sy, sz};
   // Camera-space scaled axes: C[i][j] = (R_v (R e_j s_j))_i.
@@ -181,9 +200,9 @@ Struct structural(const Scene32 &s, int64_t g, const Cam &c, float delta) {
       A0[j] = a0 * (C[0][j] - u * C[2][j]);
       A1[j] = a1 * (C[1][j] - v * C[2][j]);
     }
-    const float S00 = ((A0[0] * A0[0] + A0[1] * A0[1]) + A0[2] * A0[2]) + delta;
+    const float S00 = ((A0[0] * A0[0] + A0[1] * A0[1]) + A0[2] * A0[2]) + cfg.delta;
     const float S01 = (A0[0] * A1[0] + A0[1] * A1[1]) + A0[2] * A1[2];
-    const float S11 = ((A1[0] * A1[0] + A1[1] * A1[1]) + A1[2] * A1[2]) + delta;
+    const float S11 = ((A1[0] * A1[0] + A1[1] * A1[1]) + A1[2] * A1[2]) + cfg.delta;
     const float det = S00 * S11 - S01 * S01;
     if (!(det > 0.0f)) return o;
     const float mu_x = c.fx * u + c.cx, mu_y = c.fy * v + c.cy;
@@ -566,10 +585,13 @@ void eval_pair(const Splat<S> &sp, const CamD &c, double px, double py, S &d, S 
   }
 }
 
+// A decision taken within rounding of its threshold ("tie") may go either way
+// in a binary32 evaluation, and both outcomes are correct results of the
+// method.  The margins say how close counts as a tie.
 struct Margins {
-  double alpha_rel;  // tie if |alpha~ - 1/255| <= alpha_rel / 255
-  double t_rel;      // tie if |T' - 1e-4| <= t_rel * 1e-4
-  double clamp_rel;  // gradient tie if |alpha~ - 0.99| <= clamp_rel * 0.99
+  double alpha_rel;  // activity tie if |raw - amin| <= alpha_rel * amin
+  double t_rel;      // stop tie if |T' - tmin| <= t_rel * tmin
+  double clamp_rel;  // clamp tie (gradient only) if |raw - amax| <= clamp_rel * amax
 };
 
 // Per-view binning of splats by tile (candidate lookup only; the order of
@@ -601,7 +623,8 @@ void build(Work &w, const float *cams, int V, bool brute) {
   for (int v = 0; v < V; ++v) {
     w.cams[v] = load_cam(cams + 23 * v);
     w.camd[v] = cam_d(w.cams[v]);
-    for (int64_t g = 0; g < N; ++g) w.st[(size_t)v * N + g] = structural(*w.s32, g, w.cams[v], w.opt.dilation);
+    const StructCfg cfg = struct_cfg(w.opt.dilation, w.opt.amin);
+    for (int64_t g = 0; g < N; ++g) w.st[(size_t)v * N + g] = structural(*w.s32, g, w.cams[v], cfg);
     Bins &b = w.bins[v];
     b.tiles_x = (w.cams[v].W + 15) / 16;
     b.tiles_y = (w.cams[v].H + 15) / 16;
@@ -651,6 +674,7 @@ struct PixelOut {
   double rgb[3], depth, nrm[3], T;
   int n_contrib, last;
   uint8_t tie;
+  int nflags;  // activity and stop ties met along the way
   int64_t wcount[2];
 };
 
@@ -689,10 +713,15 @@ const Splat<double> &get_splat(const Work &w, const SplatCache &c, int v, int64_
 // One pixel (Eq. 2): gather the candidates, order them by (depth key, index),
 // skip inactive pairs, composite front to back until the transmittance would
 // fall below the floor.  The blended pairs are returned through `seq`.
+// Activity and stop decisions that fall within the tie margins are numbered
+// in the order they are met; bit k of `flip` takes the other outcome of tie
+// k (a branch of the composite that a binary32 evaluation may legitimately
+// follow).  flip = 0 is the binary64 decision everywhere.
 void render_pixel(const Work &w, const SplatCache &cache, int v, int x, int y,
-                  const Margins &mg, PixelOut &po, std::vector<PairRec> &seq) {
+                  const Margins &mg, uint32_t flip, PixelOut &po, std::vector<PairRec> &seq) {
   const int64_t N = w.s32->n;
   const CamD &cd = w.camd[v];
+  const double amin = w.opt.amin, amax = w.opt.amax, tmin = w.opt.tmin;
   const double px = x + 0.5 + w.opt.pix_off[0], py = y + 0.5 + w.opt.pix_off[1];
   std::vector<PairRec> cand;
   Splat<double> tmp;
@@ -704,7 +733,7 @@ void render_pixel(const Work &w, const SplatCache &cache, int v, int x, int y,
     double d, dep;
     eval_pair<double>(sp, cd, px, py, d, dep);
     const double raw = sp.alpha_eff * std::exp(-0.5 * d);
-    cand.push_back(PairRec{st.zbits, g, raw, std::min(kAlphaMax, raw), raw > kAlphaMax});
+    cand.push_back(PairRec{st.zbits, g, raw, std::min(amax, raw), raw > amax});
   };
   if (w.brute) {
     for (int64_t g = 0; g < N; ++g) consider(g);
@@ -717,6 +746,7 @@ void render_pixel(const Work &w, const SplatCache &cache, int v, int x, int y,
   });
   double T = 1.0;
   po.tie = 0;
+  po.nflags = 0;
   po.rgb[0] = po.rgb[1] = po.rgb[2] = 0.0;
   po.depth = 0.0;
   po.nrm[0] = po.nrm[1] = po.nrm[2] = 0.0;
@@ -724,14 +754,21 @@ void render_pixel(const Work &w, const SplatCache &cache, int v, int x, int y,
   po.wcount[0] = po.wcount[1] = 0;
   int64_t last_g = -1;
   seq.clear();
+  auto decide = [&](bool outcome, bool tie, uint8_t bit) {
+    if (!tie) return outcome;
+    po.tie |= bit;
+    const bool flipped = po.nflags < 32 && ((flip >> po.nflags) & 1u);
+    po.nflags += 1;
+    return flipped ? !outcome : outcome;
+  };
   for (const PairRec &pr : cand) {
-    if (std::fabs(pr.raw - kAlphaMin) <= mg.alpha_rel * kAlphaMin) po.tie |= 1;
-    if (!(pr.raw >= kAlphaMin)) continue;  // false for NaN (std::min would hide it)
+    // active iff raw >= amin (false for NaN; std::min would hide it)
+    const bool active = decide(pr.raw >= amin, std::fabs(pr.raw - amin) <= mg.alpha_rel * amin, 1);
+    if (!active) continue;
     po.wcount[w.s32->types[pr.g] == 0 ? 0 : 1] += 1;
     const double Tn = T * (1.0 - pr.alpha);
-    if (std::fabs(Tn - kTMin) <= mg.t_rel * kTMin) po.tie |= 2;
-    if (Tn < kTMin) break;
-    if (std::fabs(pr.raw - kAlphaMax) <= mg.clamp_rel * kAlphaMax) po.tie |= 4;
+    if (decide(Tn < tmin, std::fabs(Tn - tmin) <= mg.t_rel * tmin, 2)) break;
+    if (std::fabs(pr.raw - amax) <= mg.clamp_rel * amax) po.tie |= 4;
     const Splat<double> &sp = get_splat(w, cache, v, pr.g, tmp);
     double d, dep;
     eval_pair<double>(sp, cd, px, py, d, dep);
@@ -766,14 +803,15 @@ extern "C" {
 // Structural decisions for every (view, splat).
 int oracle_structural(const float *means, const float *scales, const float *rots,
                       const float *opac, const uint8_t *types, int64_t n,
-                      const float *cams, int V, float dilation,
+                      const float *cams, int V, float dilation, double alpha_min,
                       uint8_t *valid, int32_t *rect, uint32_t *tiles, uint32_t *zbits,
                       uint8_t *flip) {
   Scene32 s{means, scales, rots, opac, nullptr, types, n, 0};
+  const StructCfg cfg = struct_cfg(dilation, alpha_min);
   for (int v = 0; v < V; ++v) {
     Cam c = load_cam(cams + 23 * v);
     for (int64_t g = 0; g < n; ++g) {
-      Struct st = structural(s, g, c, dilation);
+      Struct st = structural(s, g, c, cfg);
       const size_t i = (size_t)v * n + g;
       valid[i] = st.valid;
       rect[4 * i] = st.px0; rect[4 * i + 1] = st.py0; rect[4 * i + 2] = st.px1; rect[4 * i + 3] = st.py1;
@@ -823,14 +861,17 @@ int64_t oracle_sorted_pairs(const uint8_t *valid, const int32_t *rect, const uin
 // Forward at a list of pixels.  pix = [P,3] (view, y, x).  out8 = [P,8]
 // (r, g, b, alpha, depth, nx, ny, nz); tfin = [P]; counts = [P,2]
 // (n_contrib, last); tie = [P]; wcount = [2] summed over pixels.
-// opts = [bg r, g, b, dilation, lambda_z, theta_z, temp_z];
-// margins = [alpha_rel, t_rel, clamp_rel].
+// opts = [bg r, g, b, dilation, lambda_z, theta_z, temp_z, pixel offset x, y,
+// alpha_min, alpha_max, t_min]; margins = [alpha_rel, t_rel, clamp_rel].
+// flip = [P] tie branches (see render_pixel) or NULL; nflags = [P] number of
+// activity / stop ties met, or NULL.
 int oracle_forward(const float *m32, const float *s32, const float *r32, const float *o32,
                    const float *sh32, const uint8_t *types, int64_t n, int sh_degree,
                    const double *m64, const double *s64, const double *r64, const double *o64,
                    const double *sh64, const float *cams, int V, const double *opts,
-                   const double *margins, const int32_t *pix, int64_t P, int brute, int threads,
-                   double *out8, double *tfin, int32_t *counts, uint8_t *tie, int64_t *wcount) {
+                   const double *margins, const int32_t *pix, int64_t P, const uint32_t *flip,
+                   int brute, int threads, double *out8, double *tfin, int32_t *counts,
+                   uint8_t *tie, int32_t *nflags, int64_t *wcount) {
   Scene32 sc32{m32, s32, r32, o32, sh32, types, n, sh_degree};
   Scene64 sc64{m64, s64, r64, o64, sh64};
   Work w;
@@ -846,7 +887,8 @@ int oracle_forward(const float *m32, const float *s32, const float *r32, const f
     std::vector<PairRec> seq;
     for (int64_t i = a; i < b; ++i) {
       PixelOut po;
-      render_pixel(w, cache, pix[3 * i], pix[3 * i + 2], pix[3 * i + 1], mg, po, seq);
+      render_pixel(w, cache, pix[3 * i], pix[3 * i + 2], pix[3 * i + 1], mg, flip ? flip[i] : 0u,
+                   po, seq);
       double *o = out8 + 8 * i;
       o[0] = po.rgb[0]; o[1] = po.rgb[1]; o[2] = po.rgb[2];
       o[3] = 1.0 - po.T;
@@ -856,6 +898,7 @@ int oracle_forward(const float *m32, const float *s32, const float *r32, const f
       counts[2 * i] = po.n_contrib;
       counts[2 * i + 1] = po.last;
       tie[i] = po.tie;
+      if (nflags) nflags[i] = po.nflags;
       wc[2 * t] += po.wcount[0];
       wc[2 * t + 1] += po.wcount[1];
     }
@@ -866,18 +909,45 @@ int oracle_forward(const float *m32, const float *s32, const float *r32, const f
 }
 
 // Backward of L = sum over listed pixels of <G, out> (G = [P,8] in the
-// order of out8).  Outputs dL/d(params) in binary64, plus two tolerance
-// scales of the same shapes: the sums of the absolute per-pair terms
-// (a_params, a_sh), and a condition scale of a binary32 evaluation
-// (c_params) in which the dL/dalpha~ = T (f - S) factor is counted as
-// T (|f| + |S|).
+// order of out8), on the branch of each pixel selected by flip (NULL: the
+// binary64 decisions; margins as in oracle_forward).  Outputs dL/d(params)
+// in binary64, plus tolerance scales of the same shapes:
+//   a_params, a_sh  sums of the absolute per-pair terms;
+//   c_params        a bound on the rounding of a binary32 evaluation of the
+//                   dL/dalpha~ path, in units of the binary32 unit roundoff
+//                   (see below);
+//   x_params        per element, the sum over clamp ties (pairs whose
+//                   contribution is within the clamp margin of alpha_max)
+//                   of |dL/dalpha~ d(alpha_eff e^{-d/2})/dtheta|: the
+//                   difference between the clamped and the unclamped
+//                   branch, either of which a binary32 evaluation may take.
+//
+// The rounding bound.  A binary32 reverse pass forms dL/dalpha~_i =
+// T_i (f_i - S_i) from T_i recovered by dividing the final transmittance by
+// (1 - alpha~_j) for j >= i, and from the suffix S accumulated over the
+// pairs behind i.  Each of the m forward products, the m - i divisions and
+// the m - i accumulation steps contributes a relative rounding of a few
+// units of the largest magnitude it carries, and an error da_j in a
+// contribution moves (1 - alpha~_j) by da_j / (1 - alpha~_j), with
+// da_j / alpha~_j a few units times (1 + the exponent's magnitude).  So per
+// pair
+//   c_i = T_i (F_i + Shat_i) n_eff |d alpha~_i / d theta|_mag,
+//   n_eff = m + 2 + sum over unclamped blended j of alpha~_j (1 + e_j) / (1 - alpha~_j),
+// where F_i is the sum of |terms| of f_i, Shat_i the largest |S_j| and F_j
+// behind i (the background term included), e_j the exponent's magnitude in
+// log2 units, and |d alpha~/d theta|_mag the derivative of alpha~ with the
+// exponent's terms taken by magnitude (3D: the entrywise conic and offset
+// magnitudes; 2D: |d alpha~/d theta|).  A test multiplies c by a few units
+// of binary32 roundoff.  The other per-pair terms are products, bounded
+// relative to a_params.
 int oracle_backward(const float *m32, const float *s32, const float *r32, const float *o32,
                     const float *sh32, const uint8_t *types, int64_t n, int sh_degree,
                     const double *m64, const double *s64, const double *r64, const double *o64,
                     const double *sh64, const float *cams, int V, const double *opts,
-                    const int32_t *pix, int64_t P, const double *G, int threads,
+                    const double *margins, const int32_t *pix, int64_t P, const uint32_t *flip,
+                    const double *G, int threads,
                     double *g_params /* [n,11] */, double *g_sh /* [n,K,3] */,
-                    double *a_params, double *a_sh, double *c_params) {
+                    double *a_params, double *a_sh, double *c_params, double *x_params) {
   Scene32 sc32{m32, s32, r32, o32, sh32, types, n, sh_degree};
   Scene64 sc64{m64, s64, r64, o64, sh64};
   Work w;
@@ -885,14 +955,16 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
   w.s64 = &sc64;
   w.opt = load_opts(opts);
   build(w, cams, V, false);
-  const Margins mg{0, 0, 0};
+  const Margins mg{margins[0], margins[1], margins[2]};
   SplatCache cache;
   if (4 * P >= n) build_cache(w, cache, threads);
   const int K = (sh_degree + 1) * (sh_degree + 1);
   const int nt = std::max(1, threads);
+  const double amax = w.opt.amax;
   // Per-thread sparse accumulators: splat -> slot of [NP params | NP abs |
-  // 3K sh | 3K sh abs].  Merged in thread order (deterministic).
-  const size_t slot = (size_t)3 * NP + (size_t)6 * K;
+  // NP cond | NP clamp-tie | 3K sh | 3K sh abs].  Merged in thread order
+  // (deterministic).
+  const size_t slot = (size_t)4 * NP + (size_t)6 * K;
   std::vector<std::unordered_map<int64_t, size_t>> where(nt);
   std::vector<std::vector<double>> acc(nt);
   parallel_for(P, threads, [&](int t, int64_t a, int64_t b) {
@@ -908,49 +980,61 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
     for (int64_t i = a; i < b; ++i) {
       const int v = pix[3 * i], y = pix[3 * i + 1], x = pix[3 * i + 2];
       PixelOut po;
-      render_pixel(w, cache, v, x, y, mg, po, seq);
+      render_pixel(w, cache, v, x, y, mg, flip ? flip[i] : 0u, po, seq);
       const double *Gp = G + 8 * i;
       const double px = x + 0.5 + w.opt.pix_off[0], py = y + 0.5 + w.opt.pix_off[1];
       const int m = (int)seq.size();
       // forward transmittances and per-pair scalar f_i
       std::vector<Splat<Dual>> sps(m);
       std::vector<Dual> dd(m), dep(m), aa(m);
-      std::vector<double> T(m + 1), f(m);
+      std::vector<double> T(m + 1), f(m), Fa(m);
       T[0] = 1.0;
+      double n_eff = m + 2.0;
       for (int j = 0; j < m; ++j) {
         const int64_t g = seq[j].g;
         const Struct &st = w.st[(size_t)v * n + g];
         setup_splat<Dual>(sc32, sc64, g, w.camd[v], w.opt, st, sps[j]);
         eval_pair<Dual>(sps[j], w.camd[v], px, py, dd[j], dep[j]);
-        aa[j] = seq[j].clamped ? Dual(kAlphaMax) : sps[j].alpha_eff * dexp(-0.5 * dd[j]);
+        aa[j] = seq[j].clamped ? Dual(amax) : sps[j].alpha_eff * dexp(-0.5 * dd[j]);
         T[j + 1] = T[j] * (1.0 - seq[j].alpha);
-        f[j] = Gp[0] * val(sps[j].color[0]) + Gp[1] * val(sps[j].color[1]) +
-               Gp[2] * val(sps[j].color[2]) + Gp[4] * val(dep[j]) + Gp[5] * val(sps[j].nrm[0]) +
-               Gp[6] * val(sps[j].nrm[1]) + Gp[7] * val(sps[j].nrm[2]);
+        const double terms[7] = {Gp[0] * val(sps[j].color[0]), Gp[1] * val(sps[j].color[1]),
+                                 Gp[2] * val(sps[j].color[2]), Gp[4] * val(dep[j]),
+                                 Gp[5] * val(sps[j].nrm[0]), Gp[6] * val(sps[j].nrm[1]),
+                                 Gp[7] * val(sps[j].nrm[2])};
+        f[j] = 0.0;
+        Fa[j] = 0.0;
+        for (int k = 0; k < 7; ++k) {
+          f[j] += terms[k];
+          Fa[j] += std::fabs(terms[k]);
+        }
+        if (!seq[j].clamped) {
+          const double e_mag = 0.5 * std::fabs(dd[j].v) / std::log(2.0);
+          n_eff += seq[j].alpha * (1.0 + e_mag) / (1.0 - seq[j].alpha);
+        }
       }
       // alpha = 1 - T_final and rgb += T_final * bg: background term
       const double fbg = Gp[0] * w.opt.bg[0] + Gp[1] * w.opt.bg[1] + Gp[2] * w.opt.bg[2] - Gp[3];
       double Ssuf = fbg;  // S_m
+      double Shat = std::fabs(Gp[0] * w.opt.bg[0]) + std::fabs(Gp[1] * w.opt.bg[1]) +
+                    std::fabs(Gp[2] * w.opt.bg[2]) + std::fabs(Gp[3]);
       for (int j = m - 1; j >= 0; --j) {
         const int64_t g = seq[j].g;
         const double al = seq[j].alpha;
         const double dLda = T[j] * (f[j] - Ssuf);
-        const double Sprev = Ssuf;
         Ssuf = f[j] * al + (1.0 - al) * Ssuf;
         const double wgt = al * T[j];
         const Splat<Dual> &sp = sps[j];
         double *c = cell(g);
-        double *gg = c, *ga = c + NP, *gcnd = c + 2 * NP, *gs = c + 3 * NP,
-               *as = c + 3 * NP + 3 * K;
-        // Tolerance scale: dL/dalpha~ = T (f - S) is a difference, so the
-        // error of evaluating it in binary32 scales with T (|f| + |S|), not
-        // with |T (f - S)|.  The other terms are products.
-        const double cond_a = T[j] * (std::fabs(f[j]) + std::fabs(Sprev));
-        // For 3D pairs, d(alpha~)/d(theta) goes through the screen-space
-        // quantities of Eq. 1 (offset D = p - mu', conic Q).  Evaluated in
-        // binary32, its error scales with the entrywise magnitudes
-        // sum_ab |D_a D_b| |dQ_ab| + 2 sum_a |(Q D)_a| |dmu'_a|, not with
-        // the magnitude of their (possibly cancelling) sum.
+        double *gg = c, *ga = c + NP, *gcnd = c + 2 * NP, *gx = c + 3 * NP, *gs = c + 4 * NP,
+               *as = c + 4 * NP + 3 * K;
+        const double cond_a = T[j] * (Fa[j] + Shat) * n_eff;
+        Shat = std::max(Shat, std::max(std::fabs(Ssuf), Fa[j]));
+        const bool clamp_tie = std::fabs(seq[j].raw - amax) <= mg.clamp_rel * amax;
+        Dual unc;
+        if (clamp_tie) unc = sp.alpha_eff * dexp(-0.5 * dd[j]);
+        // 3D: d(alpha~)/d(theta) goes through the screen-space quantities of
+        // Eq. 1 (offset D = p - mu', conic Q); its magnitude form takes
+        // sum_ab |D_a D_b| |dQ_ab| + 2 sum_a |(Q D)_a| |dmu'_a|.
         double D0 = 0, D1 = 0, QD0 = 0, QD1 = 0, gexp = 0;
         if (!sp.is2d) {
           D0 = px - sp.mu2[0].v;
@@ -976,7 +1060,7 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
             da = std::fabs(sp.alpha_eff.d[q]) * gexp + al * 0.5 * cd;
           }
           gcnd[q] += cond_a * da;
-          for (int k = 1; k < 8; ++k) gcnd[q] += std::fabs(terms[k]);
+          if (clamp_tie) gx[q] += std::fabs(dLda * unc.d[q]);
         }
         for (int ch = 0; ch < 3; ++ch) {
           if (sp.clamped[ch]) continue;
@@ -992,6 +1076,7 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
   std::memset(g_params, 0, sizeof(double) * n * NP);
   std::memset(a_params, 0, sizeof(double) * n * NP);
   std::memset(c_params, 0, sizeof(double) * n * NP);
+  std::memset(x_params, 0, sizeof(double) * n * NP);
   std::memset(g_sh, 0, sizeof(double) * n * K * 3);
   std::memset(a_sh, 0, sizeof(double) * n * K * 3);
   for (int t = 0; t < nt; ++t) {
@@ -1004,10 +1089,11 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
         g_params[g * NP + q] += c[q];
         a_params[g * NP + q] += c[NP + q];
         c_params[g * NP + q] += c[2 * NP + q];
+        x_params[g * NP + q] += c[3 * NP + q];
       }
       for (int j = 0; j < 3 * K; ++j) {
-        g_sh[g * 3 * K + j] += c[3 * NP + j];
-        a_sh[g * 3 * K + j] += c[3 * NP + 3 * K + j];
+        g_sh[g * 3 * K + j] += c[4 * NP + j];
+        a_sh[g * 3 * K + j] += c[4 * NP + 3 * K + j];
       }
     }
   }
@@ -1024,13 +1110,14 @@ int oracle_backward(const float *m32, const float *s32, const float *r32, const 
 // M (u, v, kappa) = -p_c with M = [s_x t_u | s_y t_v | -omega],
 // omega = ((px - cx)/fx, (py - cy)/fy, 1); differentiating M x = r in
 // omega_k gives d(u, v, kappa)/d omega_k = kappa M^{-1} e_k; d = u^2 + v^2,
-// depth = kappa.  out: [V*n, 2], binary64.
+// depth = kappa.  Tie branches as in oracle_backward.  out: [V*n, 2],
+// binary64.
 int oracle_screen_grad(const float *m32, const float *s32, const float *r32, const float *o32,
                        const float *sh32, const uint8_t *types, int64_t n, int sh_degree,
                        const double *m64, const double *s64, const double *r64,
                        const double *o64, const double *sh64, const float *cams, int V,
-                       const double *opts, const int32_t *pix, int64_t P, const double *G,
-                       int threads, double *out) {
+                       const double *opts, const double *margins, const int32_t *pix, int64_t P,
+                       const uint32_t *flip, const double *G, int threads, double *out) {
   Scene32 sc32{m32, s32, r32, o32, sh32, types, n, sh_degree};
   Scene64 sc64{m64, s64, r64, o64, sh64};
   Work w;
@@ -1038,7 +1125,7 @@ int oracle_screen_grad(const float *m32, const float *s32, const float *r32, con
   w.s64 = &sc64;
   w.opt = load_opts(opts);
   build(w, cams, V, false);
-  const Margins mg{0, 0, 0};
+  const Margins mg{margins[0], margins[1], margins[2]};
   SplatCache cache;
   if (4 * P >= n) build_cache(w, cache, threads);
   const int nt = std::max(1, threads);
@@ -1049,7 +1136,7 @@ int oracle_screen_grad(const float *m32, const float *s32, const float *r32, con
     for (int64_t i = a; i < b; ++i) {
       const int v = pix[3 * i], y = pix[3 * i + 1], x = pix[3 * i + 2];
       PixelOut po;
-      render_pixel(w, cache, v, x, y, mg, po, seq);
+      render_pixel(w, cache, v, x, y, mg, flip ? flip[i] : 0u, po, seq);
       const double *Gp = G + 8 * i;
       const CamD &cd = w.camd[v];
       const double px = x + 0.5 + w.opt.pix_off[0], py = y + 0.5 + w.opt.pix_off[1];
@@ -1153,7 +1240,7 @@ int oracle_surfel_uv(const double *params, const float *cam, const double *pxy, 
   double o64 = 0.5, sh[3] = {0.0, 0.0, 0.0};
   Scene32 s{m32, s32f, r32, &o32, nullptr, &t, 1, 0};
   Scene64 p{params, params + 3, params + 6, &o64, sh};
-  Opts opt{{0, 0, 0}, 0.0f, 1.0, 1.05, 0.001};
+  Opts opt{{0, 0, 0}, 0.0f, 1.0, 1.05, 0.001, {0.0, 0.0}, kAlphaMin, kAlphaMax, kTMin};
   Struct st{};
   Splat<double> sp;
   setup_splat<double>(s, p, 0, cd, opt, st, sp);

@@ -261,6 +261,23 @@ def scene_random(n, seed, *, frac2d=0.5, box=1.0, log_mu=-3.0, log_sigma=0.6,
     return _finish(types, means, log_s, q, opac, sh)
 
 
+def scene_gate(n, seed, *, theta_z, temp_z, log_mu=-3.0, box=1.0):
+    """A random scene (half surfels) whose surfels carry a third scale s_z
+    in the region of the scale-modulation gate (Sec. 3.2, Eq. 6-7): 40% of
+    them uniform in theta_z +/- 5 temp_z, 20% far above the gate, uniform in
+    [1.5 theta_z, 3 theta_z], and the rest at s_z = 0 (their initial value)."""
+    sc = scene_random(n, seed, log_mu=log_mu, box=box)
+    rng = _rng(seed + 1000)
+    idx = np.nonzero(sc["types"] == 0)[0]
+    pick = rng.permutation(idx)
+    n_in, n_far = int(0.4 * len(idx)), int(0.2 * len(idx))
+    sz = sc["scales"][:, 2].copy()
+    sz[pick[:n_in]] = rng.uniform(theta_z - 5 * temp_z, theta_z + 5 * temp_z, n_in)
+    sz[pick[n_in:n_in + n_far]] = rng.uniform(1.5 * theta_z, 3.0 * theta_z, n_far)
+    sc["scales"][:, 2] = sz.astype(np.float32)
+    return sc
+
+
 def upstream_grads(n_views, height, width, seed):
     """N(0,1) cotangents for every output channel: rgb, alpha, depth, normal."""
     rng = _rng(seed)

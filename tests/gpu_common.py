@@ -6,10 +6,13 @@ import numpy as np
 
 IMG_KEYS = ("rgb", "alpha", "depth", "normal")
 PARAM_KEYS = ("means", "scales", "rotations", "opacities", "sh")
-IMG_TOL = 1e-4      # max-abs on images, non-tie pixels
+IMG_TOL = 1e-4      # max-abs on images
 GRAD_RTOL = 1e-3    # per element, relative to |ref| + sum|terms|
-GRAD_COND = 1e-5    # per element, times the binary32 condition scale (~170 ulp)
+# Per element, times the oracle's rounding bound of the dL/dalpha~ path
+# (counted in binary32 unit roundoffs, u = 2^-24): eight units per step.
+GRAD_COND = 8.0 * 2.0 ** -24
 GRAD_L2 = 1e-3      # per tensor relative L2
+MAX_TIE_BITS = 4    # branches tried per tie pixel: 2^4 outcome combinations
 
 
 def say(*a):
@@ -63,8 +66,9 @@ def gpu_at(imgs, pix):
 def compare_structural(state, scene_np, cams, opts=None):
     """Bit-exact: culls, rects, tiles, depth keys, sorted pairs, ranges."""
     import oracle
-    dil = (opts or {}).get("dilation", 0.3)
-    st = oracle.structural(scene_np, cams, dil)
+    o = dict(oracle.DEFAULT_OPTS)
+    o.update(opts or {})
+    st = oracle.structural(scene_np, cams, o["dilation"], o["alpha_min"])
     tiles = state.debug("tiles")
     np.testing.assert_array_equal(tiles, st["tiles"])
     valid = st["valid"] == 1
@@ -77,43 +81,109 @@ def compare_structural(state, scene_np, cams, opts=None):
     return st, len(keys)
 
 
-def compare_images(imgs, state, res, pix, max_tie_frac=0.01):
-    """GPU vs oracle at pixels `pix`: images within IMG_TOL, n_contrib and
-    last bit-exact, on pixels without a near-threshold decision."""
-    tie = res["tie"] != 0
-    ok = ~tie
-    assert tie.mean() <= max_tie_frac, f"tie fraction {tie.mean():.4f}"
-    g = gpu_at(imgs, pix)
-    err = np.abs(g - res["out"])
-    worst = err[ok].max() if ok.any() else 0.0
-    assert worst <= IMG_TOL, f"max image error {worst:.3e}"
-    V = int(pix[:, 0].max()) + 1
+def gpu_counts(state, imgs, pix):
+    """GPU n_contrib, last and T_final at pixels `pix` ([P,3] view, y, x)."""
     HW = state.sizes()["HW"]
-    Hh = imgs["alpha"].shape[2]
     Ww = imgs["alpha"].shape[3]
     flat = pix[:, 0].astype(np.int64) * HW + pix[:, 1].astype(np.int64) * Ww + pix[:, 2]
-    nc = state.debug("n_contrib")[flat]
-    last = state.debug("last")[flat]
-    T = state.debug("T_final")[flat]
-    np.testing.assert_array_equal(nc[ok], res["n_contrib"][ok])
-    np.testing.assert_array_equal(last[ok], res["last"][ok])
-    assert np.abs(T[ok] - res["T"][ok]).max() <= IMG_TOL
-    return dict(max_err=float(worst), ties=int(tie.sum()), pixels=int(len(pix)), V=V, H=Hh)
+    return (state.debug("n_contrib")[flat].astype(np.int64),
+            state.debug("last")[flat].astype(np.int64),
+            state.debug("T_final")[flat].astype(np.float64))
 
 
-def compare_grads(gg, ref):
-    """Per element |g - ref| <= 1e-3 (|ref| + sum|terms|) + 1e-5 cond, where
-    cond bounds the rounding of a binary32 evaluation (the dL/dalpha~ factor
-    T (f - S) counted as T (|f| + |S|)); and per tensor relative L2 <= 1e-3."""
+def gpu_pixels(state, imgs, pix):
+    """The GPU's outputs at `pix`: dict(out [P,8], n_contrib, last, T)."""
+    nc, last, T = gpu_counts(state, imgs, pix)
+    return dict(out=gpu_at(imgs, pix), n_contrib=nc, last=last, T=T)
+
+
+def resolve_ties(scene, cams, pix, res, gpu, opts=None):
+    """Tie pixels: a pixel where an activity (alpha_min) or stop (t_min)
+    decision lies within rounding of its threshold has two correct outcomes
+    of that decision (Eq. 2 with either choice).  For each tie pixel the
+    oracle evaluates the branches (every combination of its first
+    MAX_TIE_BITS ties) and the one the GPU took is identified by its
+    n_contrib, last, T_final and images; the oracle's outputs of that branch
+    replace the binary64 decision's.  `gpu` is gpu_pixels(...) at `pix`.
+    Returns (res with the branches substituted, flip [P] of the branches,
+    report).  A tie pixel whose GPU result matches no branch is left as it
+    is, and the comparison that follows fails there."""
+    import oracle
+    res = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in res.items()}
+    flip = np.zeros(len(pix), np.uint32)
+    idx = np.flatnonzero((res["tie"] & 3) != 0)
+    rep = dict(tie_pixels=int(len(idx)), other_branch=0, unmatched=0)
+    if len(idx) == 0:
+        return res, flip, rep
+    sub = np.ascontiguousarray(pix[idx])
+    g_out = gpu["out"][idx]
+    chosen = np.full(len(idx), -1, np.int64)
+    for mask in range(2 ** MAX_TIE_BITS):
+        r = oracle.forward(scene, cams, sub, opts, flip=mask)
+        used = mask < (1 << np.minimum(r["nflags"], 31).astype(np.int64))
+        ok = used & (chosen < 0) & (np.abs(r["out"] - g_out).max(1) <= IMG_TOL)
+        if gpu.get("n_contrib") is not None:  # images only (no state) otherwise
+            ok &= ((r["n_contrib"] == gpu["n_contrib"][idx]) & (r["last"] == gpu["last"][idx]) &
+                   (np.abs(r["T"] - gpu["T"][idx]) <= IMG_TOL))
+        chosen[ok] = mask
+        for k in ("out", "T", "n_contrib", "last"):
+            res[k][idx[ok]] = r[k][ok]
+        if (chosen >= 0).all():
+            break
+    flip[idx[chosen > 0]] = chosen[chosen > 0]
+    rep["other_branch"] = int((chosen > 0).sum())
+    rep["unmatched"] = int((chosen < 0).sum())
+    return res, flip, rep
+
+
+def check_pixels(scene, cams, pix, res, gpu, opts=None):
+    """resolve_ties, then every pixel of `pix`: images within IMG_TOL,
+    n_contrib and last bit-exact, T_final within IMG_TOL.  Returns
+    (res on the GPU's branches, flip, report)."""
+    res, flip, trep = resolve_ties(scene, cams, pix, res, gpu, opts)
+    err = np.abs(gpu["out"] - res["out"])
+    worst = float(err.max()) if len(pix) else 0.0
+    assert worst <= IMG_TOL, (f"max image error {worst:.3e}", trep,
+                              pix[np.argmax(err.max(1))].tolist())
+    if gpu.get("n_contrib") is not None:
+        np.testing.assert_array_equal(gpu["n_contrib"], res["n_contrib"])
+        np.testing.assert_array_equal(gpu["last"], res["last"])
+        assert np.abs(gpu["T"] - res["T"]).max(initial=0.0) <= IMG_TOL
+    rep = dict(max_err=worst, pixels=int(len(pix)),
+               clamp_ties=int(((res["tie"] & 4) != 0).sum()), **trep)
+    return res, flip, rep
+
+
+def compare_images(imgs, state, res, pix, scene, cams, opts=None):
+    """GPU vs oracle at every pixel of `pix`, tie pixels on the branch the
+    GPU took (check_pixels).  Returns (res on the GPU's branches, flip,
+    report)."""
+    return check_pixels(scene, cams, pix, res, gpu_pixels(state, imgs, pix), opts)
+
+
+def compare_grads(gg, ref, keys=PARAM_KEYS):
+    """Per element
+        |g - ref| <= 1e-3 (|ref| + sum|terms|) + GRAD_COND cond + tie,
+    where cond is the oracle's rounding bound of a binary32 evaluation of the
+    dL/dalpha~ path and tie the spread between the two branches of clamp
+    ties; per tensor relative L2 <= 1e-3.  The report counts, per tensor, the
+    elements that pass only through the cond or tie allowance, and the
+    elements carrying at least 1% of the tensor's largest magnitude that
+    miss a plain 1e-3 |ref| bound (those must pass through the allowances)."""
     report = {}
-    for k in PARAM_KEYS:
+    for k in keys:
         g = np.asarray(gg[k], np.float64).reshape(ref[k].shape)
         r = ref[k]
-        scale = np.abs(r) + ref[k + "_abs"]
-        bad = np.abs(g - r) > GRAD_RTOL * scale + GRAD_COND * ref[k + "_cond"] + 1e-9
+        err = np.abs(g - r)
+        base = GRAD_RTOL * (np.abs(r) + ref[k + "_abs"]) + 1e-9
+        allow = GRAD_COND * ref[k + "_cond"] + ref[k + "_tie"]
+        bad = err > base + allow
         den = np.linalg.norm(r)
         rel = float(np.linalg.norm(g - r) / den) if den > 0 else float(np.linalg.norm(g))
-        report[k] = (int(bad.sum()), rel)
+        big = np.abs(r) >= 1e-2 * np.abs(r).max(initial=0.0)
+        report[k] = dict(bad=int(bad.sum()), rel_l2=rel, via_allowance=int((err > base).sum()),
+                         big_over_plain=int((big & (err > GRAD_RTOL * np.abs(r))).sum()),
+                         n=int(r.size))
         assert bad.sum() == 0, (k, int(bad.sum()), np.argwhere(bad)[:5].tolist(),
                                 g[bad][:5].tolist(), r[bad][:5].tolist())
         assert rel <= GRAD_L2, (k, rel)

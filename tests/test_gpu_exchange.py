@@ -199,7 +199,7 @@ def test_exchange_full_size_scene_then_render_matches_oracle():
     import torch
     import oracle
     from paper_2512_02932_amd.rasterizer import get_rasterizer, to_device
-    from gpu_common import compare_images, gpu_at
+    from gpu_common import compare_images
     scene = sg.scene_torus_knot(n=1_000_000, frac2d=0.5, seed=3)
     gs, gq, gt, ref = _compare(scene["scales"], scene["rotations"], scene["types"], 2.05)
     # small render of the exchanged scene
@@ -215,6 +215,6 @@ def test_exchange_full_size_scene_then_render_matches_oracle():
                     rng.integers(0, 320, 600)], 1).astype(np.int32)
     # the oracle renders the exchanged parameters as the GPU holds them
     res = oracle.forward(ex, cam, pix)
-    rep = compare_images(imgs, state, res, pix, max_tie_frac=0.02)
+    _, _, rep = compare_images(imgs, state, res, pix, ex, cam)
     say(f"[exchange] render after exchange: {rep}")
     state.free()

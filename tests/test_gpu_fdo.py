@@ -26,7 +26,8 @@ import numpy as np
 import pytest
 
 import scenegen as sg
-from gpu_common import IMG_KEYS, PARAM_KEYS, compare_grads, oracle_pixels, pack_G_all, say
+from gpu_common import (IMG_KEYS, PARAM_KEYS, compare_grads, compare_images, oracle_pixels,
+                        pack_G_all, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -193,16 +194,17 @@ def test_three_set_backward_matches_oracle(name):
     N = scene["means"].shape[0]
     pix = oracle_pixels(cams)
     res = oracle.forward(scene, cams, pix)
-    tie = (res["tie"].reshape(V, H, W) != 0)[:, None]
     Gc = sg.upstream_grads(V, H, W, seed=201)
-    for k in IMG_KEYS:
-        Gc[k] = np.where(tie, 0.0, Gc[k]).astype(np.float32)
-    Gl = np.where(tie, 0.0, sg.upstream_grads(V, H, W, seed=202)["rgb"]).astype(np.float32)
-    Gh = np.where(tie, 0.0, sg.upstream_grads(V, H, W, seed=203)["rgb"]).astype(np.float32)
+    Gl = sg.upstream_grads(V, H, W, seed=202)["rgb"]
+    Gh = sg.upstream_grads(V, H, W, seed=203)["rgb"]
 
     rast = get_rasterizer(0)
     sc = to_device(scene)
-    _, state = rast.render(sc, cams, want_state=True)
+    imgs, state = rast.render(sc, cams, want_state=True)
+    torch.cuda.synchronize()
+    # the oracle's sets on the branches the GPU took at tie pixels
+    _, flip, _ = compare_images({k: v.cpu().numpy() for k, v in imgs.items()}, state, res, pix,
+                                scene, cams)
     sets = [{k: torch.zeros_like(sc[k]) for k in PARAM_KEYS} for _ in range(3)]
     upd = {k: torch.zeros_like(sc[k]) for k in PARAM_KEYS}
     cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -221,7 +223,7 @@ def test_three_set_backward_matches_oracle(name):
 
     refs = []
     for G in (Gc, dict(_zeros_like_cot(V, H, W), rgb=Gl), dict(_zeros_like_cot(V, H, W), rgb=Gh)):
-        ref = oracle.backward(scene, cams, pix, pack_G_all(G, pix))
+        ref = oracle.backward(scene, cams, pix, pack_G_all(G, pix), flip=flip)
         refs.append(ref)
     reps = [compare_grads(g, r) for g, r in zip(got, refs)]
     say(f"[fdo] {name}: sets ok {reps[1]} {reps[2]}")
@@ -269,18 +271,18 @@ def test_one_view_without_sets_equals_projection(name):
     N = scene["means"].shape[0]
     pix = oracle_pixels(cams)
     res = oracle.forward(scene, cams, pix)
-    tie = (res["tie"].reshape(V, H, W) != 0)[:, None]
     Gc = sg.upstream_grads(V, H, W, seed=211)
-    for k in IMG_KEYS:
-        Gc[k] = np.where(tie, 0.0, Gc[k]).astype(np.float32)
-    Gl = np.where(tie, 0.0, sg.upstream_grads(V, H, W, seed=212)["rgb"]).astype(np.float32)
-    Gh = np.where(tie, 0.0, sg.upstream_grads(V, H, W, seed=213)["rgb"]).astype(np.float32)
+    Gl = sg.upstream_grads(V, H, W, seed=212)["rgb"]
+    Gh = sg.upstream_grads(V, H, W, seed=213)["rgb"]
     Gc_d = {k: torch.from_numpy(v).cuda() for k, v in Gc.items()}
     gl_d, gh_d = torch.from_numpy(Gl).cuda(), torch.from_numpy(Gh).cuda()
 
     rast = get_rasterizer(0)
     sc = to_device(scene)
-    _, state = rast.render(sc, cams, want_state=True)
+    imgs, state = rast.render(sc, cams, want_state=True)
+    torch.cuda.synchronize()
+    _, flip, _ = compare_images({k: v.cpu().numpy() for k, v in imgs.items()}, state, res, pix,
+                                scene, cams)
     sets = [{k: torch.zeros_like(sc[k]) for k in PARAM_KEYS} for _ in range(3)]
     upd_sets = {k: torch.zeros_like(sc[k]) for k in PARAM_KEYS}
     cnt_sets = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -333,7 +335,7 @@ def test_one_view_without_sets_equals_projection(name):
         assert float((x - y).norm()) <= 1e-5 * float(y.norm()) + 1e-30, k
 
     # against the oracle's projection of the oracle's sets
-    refs = [oracle.backward(scene, cams, pix, pack_G_all(G, pix))
+    refs = [oracle.backward(scene, cams, pix, pack_G_all(G, pix), flip=flip)
             for G in (Gc, dict(_zeros_like_cot(V, H, W), rgb=Gl), dict(_zeros_like_cot(V, H, W), rgb=Gh))]
     r64 = [fdo.pack({k: r[k] for k in PARAM_KEYS}, N) for r in refs]
     ref = fdo.fdo_project(scene["types"], *r64)

@@ -1,18 +1,19 @@
 """GPU (HIP, gfx950) path vs the CPU oracle, through the C ABI.
 
 Structural outputs (rects, tiles, depth keys, sorted (key, value) pairs,
-tile ranges) must match bit for bit.  n_contrib, last and T_final are
-compared on pixels where no pair sits within a rounding margin of the 1/255
-or 1e-4 thresholds ("tie" pixels, flagged by the oracle and bounded in
-number).  Images must agree within 1e-4 there; gradients within 1e-3 of
-the oracle's per-element scale.
+tile ranges) must match bit for bit.  Every pixel is checked: where an
+activity or stop decision sits within rounding of its threshold ("tie"
+pixels) the oracle evaluates both outcomes and the GPU must match one of
+them, with n_contrib and last bit-exact and images within 1e-4; gradients
+are compared with the oracle's backward on the branch the GPU took, within
+1e-3 of the oracle's per-element scale plus its binary32 rounding bound.
 """
 import numpy as np
 import pytest
 
 import scenegen as sg
 from tests.gpu_common import (IMG_KEYS, compare_grads, compare_images, compare_structural,
-                              gpu_at, gpu_render, oracle_pixels, pack_G_all, say)
+                              gpu_render, oracle_pixels, pack_G_all, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -56,9 +57,6 @@ def case(request):
     pix = oracle_pixels(cams)
     res = oracle.forward(scene, cams, pix)
     G = sg.upstream_grads(V, H, W, seed=101)
-    tie = res["tie"].reshape(V, H, W) != 0
-    for k in IMG_KEYS:
-        G[k] = np.where(tie[:, None], 0.0, G[k]).astype(np.float32)
     say(f"[case {name}] gpu render + backward")
     imgs, state, grads = gpu_render(scene, cams, G=G)
     return dict(name=name, scene=scene, cams=cams, pix=pix, res=res, G=G, imgs=imgs,
@@ -72,15 +70,18 @@ def test_structural_bit_exact(case):
 
 
 def test_forward_matches_oracle(case):
-    rep = compare_images(case["imgs"], case["state"], case["res"], case["pix"])
+    _, _, rep = compare_images(case["imgs"], case["state"], case["res"], case["pix"],
+                               case["scene"], case["cams"])
     say(f"[{case['name']}] forward ok {rep}")
     assert case["imgs"]["alpha"].max() > 0.5
 
 
 def test_backward_matches_oracle(case):
     import oracle
+    _, flip, _ = compare_images(case["imgs"], case["state"], case["res"], case["pix"],
+                                case["scene"], case["cams"])
     Gp = pack_G_all(case["G"], case["pix"])
-    ref = oracle.backward(case["scene"], case["cams"], case["pix"], Gp)
+    ref = oracle.backward(case["scene"], case["cams"], case["pix"], Gp, flip=flip)
     rep = compare_grads(case["grads"], ref)
     say(f"[{case['name']}] backward ok {rep}")
 
@@ -94,39 +95,49 @@ def test_forward_is_deterministic(case):
 
 
 # ---------------------------------------------------------------------------
-# Full-size headline workload: 1M hybrid Gaussians (torus knot, 50/50),
-# SH degree 3, 1920x1080 - in the launch configuration the benchmark times.
+# Full-size training workload: 1M hybrid Gaussians (torus knot, 50/50), SH
+# degree 3, at 1600x1064 as the workload states it and at 1920x1080 (the
+# headline metric's size), in the launch configuration the benchmark times.
 # Every structural output is compared in full; images and gradients on
-# sampled pixels the oracle computes one by one.
+# sampled pixels the oracle computes one by one (ties on the GPU's branch).
 # ---------------------------------------------------------------------------
-def test_full_size_1m_1080p_sampled():
+FULL_CAMS = {"1920x1080": lambda: sg.camera_torus_knot_1080p(),
+             "1600x1064": lambda: sg.camera_torus_knot()}
+
+
+@pytest.mark.parametrize("size", sorted(FULL_CAMS))
+def test_full_size_1m_sampled(size):
     import oracle
     scene = sg.scene_torus_knot()
-    cam = sg.camera_torus_knot_1080p()
+    cam = FULL_CAMS[size]()
+    Hh, Ww = cam["height"], cam["width"]
     rng = np.random.default_rng(7)
     # sampled pixels: random over the image plus two full rows through the knot
     n = 3000
-    pix = np.stack([np.zeros(n, np.int64), rng.integers(0, 1080, n), rng.integers(0, 1920, n)], 1)
-    rows = np.array([[0, y, x] for y in (540, 700) for x in range(0, 1920, 3)])
+    pix = np.stack([np.zeros(n, np.int64), rng.integers(0, Hh, n), rng.integers(0, Ww, n)], 1)
+    rows = np.array([[0, y, x] for y in (Hh // 2, (Hh * 2) // 3) for x in range(0, Ww, 3)])
     pix = np.ascontiguousarray(np.concatenate([pix, rows]), np.int32)
-    say("[full] oracle forward at sampled pixels")
+    say(f"[full {size}] oracle forward at sampled pixels")
     res = oracle.forward(scene, cam, pix)
-    G = {k: np.zeros((1, c, 1080, 1920), np.float32)
+    G = {k: np.zeros((1, c, Hh, Ww), np.float32)
          for k, c in (("rgb", 3), ("alpha", 1), ("depth", 1), ("normal", 3))}
-    gsel = pix[(res["tie"] == 0)][:1500]
+    # cotangents on 1500 distinct sampled pixels (ties included), zero elsewhere
+    _, first = np.unique(pix[:, 1].astype(np.int64) * Ww + pix[:, 2], return_index=True)
+    gi = np.sort(first)[:1500]
+    gsel = pix[gi]
     Gs = sg.upstream_grads(1, 1, len(gsel), seed=3)
     for k in IMG_KEYS:
         G[k][0][:, gsel[:, 1], gsel[:, 2]] = Gs[k][0][:, 0, :]
-    say("[full] gpu render + backward")
+    say(f"[full {size}] gpu render + backward")
     imgs, state, grads = gpu_render(scene, cam, G=G)
-    say("[full] structural compare")
+    say(f"[full {size}] structural compare")
     _, D = compare_structural(state, scene, cam)
-    say(f"[full] D={D}; image compare")
-    rep = compare_images(imgs, state, res, pix)
-    say(f"[full] forward ok {rep}; oracle backward at {len(gsel)} pixels")
-    ref = oracle.backward(scene, cam, gsel, pack_G_all(G, gsel))
+    say(f"[full {size}] D={D}; image compare")
+    _, flip, rep = compare_images(imgs, state, res, pix, scene, cam)
+    say(f"[full {size}] forward ok {rep}; oracle backward at {len(gsel)} pixels")
+    ref = oracle.backward(scene, cam, gsel, pack_G_all(G, gsel), flip=flip[gi])
     rep = compare_grads(grads, ref)
-    say(f"[full] backward ok {rep}")
+    say(f"[full {size}] backward ok {rep}")
     state.free()
 
 
@@ -162,8 +173,7 @@ def test_all_culled_and_tiny_images():
         imgs, st, _ = gpu_render(sc, cam)
         pix = oracle_pixels(cam)
         res = oracle.forward(sc, cam, pix)
-        ok = res["tie"] == 0
-        assert np.abs(gpu_at(imgs, pix)[ok] - res["out"][ok]).max(initial=0) <= 1e-4
+        compare_images(imgs, st, res, pix, sc, cam)
         compare_structural(st, sc, [cam])
         st.free()
 

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import scenegen as sg
-from gpu_common import IMG_KEYS, say
+from gpu_common import IMG_KEYS, check_pixels, say
 
 pytestmark = pytest.mark.gpu
 
@@ -151,14 +151,13 @@ def test_served_images_match_oracle_on_samples(env):
         pix = np.stack([np.zeros(400, np.int32), rng.integers(0, H, 400),
                         rng.integers(0, W, 400)], 1).astype(np.int32)
         res = oracle.forward(_scenes()[si], cam, pix)
-        ok = res["tie"] == 0
         o = out[i]
         g = np.stack([o["rgb"][0, 0], o["rgb"][0, 1], o["rgb"][0, 2], o["alpha"][0, 0],
                       o["depth"][0, 0], o["normal"][0, 0], o["normal"][0, 1],
                       o["normal"][0, 2]], -1)[pix[:, 1], pix[:, 2]]
-        err = np.abs(g - res["out"])[ok].max()
-        say(f"[serving] request {i}: oracle max err {err:.2e}, ties {int((~ok).sum())}")
-        assert err <= 1e-4
+        # every sampled pixel; a tie pixel must match one of its branches
+        _, _, rep = check_pixels(_scenes()[si], cam, pix, res, dict(out=g.astype(np.float64)))
+        say(f"[serving] request {i}: oracle {rep}")
 
 
 def test_submit_rejects_oversized_and_bad_requests(env):

@@ -16,8 +16,8 @@ import numpy as np
 import pytest
 
 import scenegen as sg
-from gpu_common import (IMG_KEYS, PARAM_KEYS, compare_grads, compare_images,
-                        compare_structural, gpu_render, say)
+from gpu_common import (IMG_KEYS, PARAM_KEYS, check_pixels, compare_grads, compare_images,
+                        compare_structural, gpu_at, gpu_render, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -36,7 +36,7 @@ def test_sphere_500k_1080p_forward_sampled():
     say("[sphere500k] gpu render")
     imgs, state, _ = gpu_render(scene, cam)
     _, D = compare_structural(state, scene, cam)
-    rep = compare_images(imgs, state, res, pix)
+    _, _, rep = compare_images(imgs, state, res, pix, scene, cam)
     say(f"[sphere500k] D={D} forward ok {rep}")
     state.free()
 
@@ -65,7 +65,8 @@ def test_multishell_6m_16x4k_fwd_bwd_sampled():
         say(f"[shell6m] oracle forward, view {v}")
         samples[v] = (pix, oracle.forward(scene, cams[v], pix))
 
-    # cotangents: N(0,1) at non-tie sampled pixels, zero elsewhere
+    # cotangents: N(0,1) at 300 distinct sampled pixels (ties included), zero
+    # elsewhere
     rast = get_rasterizer(0)
     sc = to_device(scene)
     G = {k: torch.zeros((V, c, H, W), device="cuda") for k, c in
@@ -73,8 +74,9 @@ def test_multishell_6m_16x4k_fwd_bwd_sampled():
     gsel = {}
     for v in views:
         pix, res = samples[v]
-        sel = pix[res["tie"] == 0][:300]
-        gsel[v] = sel
+        _, first = np.unique(pix[:, 1].astype(np.int64) * W + pix[:, 2], return_index=True)
+        gsel[v] = np.sort(first)[:300]
+        sel = pix[gsel[v]]
         Gs = sg.upstream_grads(1, 1, len(sel), seed=20 + v)
         ys = torch.from_numpy(sel[:, 1].astype(np.int64)).cuda()
         xs = torch.from_numpy(sel[:, 2].astype(np.int64)).cuda()
@@ -116,16 +118,21 @@ def test_multishell_6m_16x4k_fwd_bwd_sampled():
 
     # images at sampled pixels, with per-pixel counts and transmittance
     per_px = {k: state.debug(k) for k in ("n_contrib", "last", "T_final")}
+    flips = {}
     for v in views:
         pix, res = samples[v]
         one = {k: imgs[k][v:v + 1].cpu().numpy() for k in IMG_KEYS}
-        rep = _compare_view(one, per_px, res, pix, v, H, W)
+        flat = v * H * W + pix[:, 1].astype(np.int64) * W + pix[:, 2]
+        gpu = dict(out=gpu_at(one, pix), n_contrib=per_px["n_contrib"][flat].astype(np.int64),
+                   last=per_px["last"][flat].astype(np.int64),
+                   T=per_px["T_final"][flat].astype(np.float64))
+        _, flips[v], rep = check_pixels(scene, cams[v], pix, res, gpu)
         say(f"[shell6m] view {v} images ok {rep}")
 
     # gradients: sum of per-view oracle backward passes
     ref = None
     for v in views:
-        sel = gsel[v]
+        sel = samples[v][0][gsel[v]]
         Gp = np.zeros((len(sel), 8))
         for k, cols in (("rgb", (0, 1, 2)), ("alpha", (3,)), ("depth", (4,)),
                         ("normal", (5, 6, 7))):
@@ -133,29 +140,8 @@ def test_multishell_6m_16x4k_fwd_bwd_sampled():
             for j, col in enumerate(cols):
                 Gp[:, col] = g[j, sel[:, 1], sel[:, 2]]
         say(f"[shell6m] oracle backward, view {v}")
-        r = oracle.backward(scene, cams[v], sel, Gp)
+        r = oracle.backward(scene, cams[v], sel, Gp, flip=flips[v][gsel[v]])
         ref = r if ref is None else {k: ref[k] + r[k] for k in ref}
     rep = compare_grads({k: v.cpu().numpy() for k, v in grads.items()}, ref)
     say(f"[shell6m] backward ok {rep}")
     state.free()
-
-
-def _compare_view(one, per_px, res, pix, v, H, W):
-    """Images of view v (one = its [1,C,H,W] slices) against the oracle at
-    pix (view column 0), plus n_contrib / last / T_final of the state."""
-    from gpu_common import IMG_TOL, gpu_at
-    tie = res["tie"] != 0
-    ok = ~tie
-    # A tie pixel has a pair decision within the threshold margins; their
-    # share grows with the pairs per pixel, and the four shells put about
-    # eight surface layers under each pixel here (vs one or two elsewhere).
-    assert tie.mean() <= 0.02, f"tie fraction {tie.mean():.4f}"
-    g = gpu_at(one, pix)
-    err = np.abs(g - res["out"])
-    worst = err[ok].max()
-    assert worst <= IMG_TOL, f"max image error {worst:.3e}"
-    flat = v * H * W + pix[:, 1].astype(np.int64) * W + pix[:, 2]
-    np.testing.assert_array_equal(per_px["n_contrib"][flat][ok], res["n_contrib"][ok])
-    np.testing.assert_array_equal(per_px["last"][flat][ok], res["last"][ok])
-    assert np.abs(per_px["T_final"][flat][ok] - res["T"][ok]).max() <= IMG_TOL
-    return dict(max_err=float(worst), ties=int(tie.sum()), pixels=int(len(pix)))

@@ -208,22 +208,22 @@ def test_densify_stats_match_oracle(name, fdo):
     import torch
     import oracle
     import scenegen as sg
-    from gpu_common import IMG_KEYS, oracle_pixels, pack_G_all
+    from gpu_common import compare_images, oracle_pixels, pack_G_all
     from paper_2512_02932_amd.rasterizer import get_rasterizer, to_device
     scene, cams = DENSIFY_CASES[name]()
     V, H, W = len(cams), cams[0]["height"], cams[0]["width"]
     N = scene["means"].shape[0]
     pix = oracle_pixels(cams)
     res = oracle.forward(scene, cams, pix)
-    tie = (res["tie"].reshape(V, H, W) != 0)[:, None]
     G = sg.upstream_grads(V, H, W, seed=301)
-    for k in IMG_KEYS:
-        G[k] = np.where(tie, 0.0, G[k]).astype(np.float32)
-    Gl = np.where(tie, 0.0, sg.upstream_grads(V, H, W, seed=302)["rgb"]).astype(np.float32)
-    Gh = np.where(tie, 0.0, sg.upstream_grads(V, H, W, seed=303)["rgb"]).astype(np.float32)
+    Gl = sg.upstream_grads(V, H, W, seed=302)["rgb"]
+    Gh = sg.upstream_grads(V, H, W, seed=303)["rgb"]
     rast = get_rasterizer(0)
     sc = to_device(scene)
-    _, state = rast.render(sc, cams, want_state=True)
+    imgs, state = rast.render(sc, cams, want_state=True)
+    torch.cuda.synchronize()
+    _, flip, _ = compare_images({k: v.cpu().numpy() for k, v in imgs.items()}, state, res, pix,
+                                scene, cams)
     gdev = {k: torch.from_numpy(v).cuda() for k, v in G.items()}
     grads = {k: torch.zeros_like(sc[k]) for k in PARAM_KEYS}
     if fdo:
@@ -239,7 +239,7 @@ def test_densify_stats_match_oracle(name, fdo):
     rast.densify_stats(state, norm, cnt)  # adds: twice the statistic
     torch.cuda.synchronize()
     state.free()
-    ref_norm, ref_cnt = oracle.densify_stats(scene, cams, pix, pack_G_all(Gtot, pix))
+    ref_norm, ref_cnt = oracle.densify_stats(scene, cams, pix, pack_G_all(Gtot, pix), flip=flip)
     np.testing.assert_array_equal(cnt.cpu().numpy(), 2 * ref_cnt)
     got = norm.cpu().numpy() / 2
     bad = np.abs(got - ref_norm) > 2e-3 * ref_norm + 2e-5 * ref_norm.max()
@@ -301,12 +301,13 @@ def test_full_size_adam_1m():
 
 
 def test_full_size_densify_1m_1080p_sampled():
-    """Cotangents on 1500 sampled non-tie pixels of the 1080p image; the
-    oracle evaluates those pixels only."""
+    """Cotangents on 1500 distinct sampled pixels of the 1080p image (tie
+    pixels included, on the branch the GPU took); the oracle evaluates those
+    pixels only."""
     import torch
     import oracle
     import scenegen as sg
-    from gpu_common import IMG_KEYS, pack_G_all
+    from gpu_common import IMG_KEYS, compare_images, pack_G_all
     from paper_2512_02932_amd.rasterizer import get_rasterizer, to_device
     scene = sg.scene_torus_knot()
     cam = sg.camera_torus_knot_1080p()
@@ -314,8 +315,10 @@ def test_full_size_densify_1m_1080p_sampled():
     rng = np.random.default_rng(9)
     pix = np.stack([np.zeros(4000, np.int64), rng.integers(0, 1080, 4000),
                     rng.integers(0, 1920, 4000)], 1).astype(np.int32)
+    _, first = np.unique(pix[:, 1].astype(np.int64) * 1920 + pix[:, 2], return_index=True)
+    pix = np.ascontiguousarray(pix[np.sort(first)[:1500]])
     res = oracle.forward(scene, cam, pix)
-    sel = pix[res["tie"] == 0][:1500]
+    sel = pix
     G = {k: np.zeros((1, c, 1080, 1920), np.float32)
          for k, c in (("rgb", 3), ("alpha", 1), ("depth", 1), ("normal", 3))}
     Gs = sg.upstream_grads(1, 1, len(sel), seed=11)
@@ -323,7 +326,10 @@ def test_full_size_densify_1m_1080p_sampled():
         G[k][0][:, sel[:, 1], sel[:, 2]] = Gs[k][0][:, 0, :]
     rast = get_rasterizer(0)
     sc = to_device(scene)
-    _, state = rast.render(sc, cam, want_state=True)
+    imgs, state = rast.render(sc, cam, want_state=True)
+    torch.cuda.synchronize()
+    _, flip, _ = compare_images({k: v.cpu().numpy() for k, v in imgs.items()}, state, res, pix,
+                                scene, cam)
     grads = {k: torch.zeros_like(sc[k]) for k in PARAM_KEYS}
     rast.backward(state, {k: torch.from_numpy(v).cuda() for k, v in G.items()}, grads)
     norm = torch.zeros(N, device="cuda")
@@ -331,7 +337,7 @@ def test_full_size_densify_1m_1080p_sampled():
     rast.densify_stats(state, norm, cnt)
     torch.cuda.synchronize()
     state.free()
-    ref_norm, ref_cnt = oracle.densify_stats(scene, cam, sel, pack_G_all(G, sel))
+    ref_norm, ref_cnt = oracle.densify_stats(scene, cam, sel, pack_G_all(G, sel), flip=flip)
     np.testing.assert_array_equal(cnt.cpu().numpy(), ref_cnt)
     got = norm.cpu().numpy()
     bad = np.abs(got - ref_norm) > 2e-3 * ref_norm + 2e-5 * ref_norm.max()

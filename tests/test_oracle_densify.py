@@ -70,18 +70,88 @@ def test_sum_over_splats_matches_global_shift(O):
     assert (np.abs(sgrad).sum(1) > 0).sum() > 10
 
 
-def test_densify_stats_units_and_counts(O):
-    sc = sg.scene_random(60, seed=32, frac2d=0.5, log_mu=-2.5, log_sigma=0.3)
-    cams = [sg.look_at_camera(e, width=40, height=30, fx=40.0)
-            for e in [(0.0, 0.0, -3.5), (1.5, 0.3, -3.0)]]
+def _ndc_to_pix(v, size):
+    """Pixel coordinate of NDC coordinate v (3DGS's convention: NDC -1 and 1
+    are the outer edges of pixels 0 and size - 1)."""
+    return ((v + 1.0) * size - 1.0) * 0.5
+
+
+def test_densify_stats_are_ndc_central_differences(O):
+    """The statistic per splat is the sum over the views that do not cull it
+    of the Euclidean norm of dL/d(translation of its footprint in NDC
+    units).  Pinned by central differences of the oracle forward under a
+    translation of h NDC units, converted to pixels through the NDC
+    definition, per splat: the splats' footprints are disjoint and the
+    cotangent of each pass is restricted to one splat's rectangle.  One
+    view culls one of the splats (its footprint leaves the image)."""
+    pos = [(-0.7, -0.35, 0.0), (0.0, -0.35, 0.1), (0.7, -0.35, -0.1), (-0.35, 0.35, 0.05),
+           (0.4, 0.37, 0.0)]
+    q = [(0.9, 0.2, -0.3, 0.1), (0.8, 0.5, 0.2, -0.1), (1.0, 0.0, 0.0, 0.0),
+         (0.7, -0.3, 0.4, 0.2), (0.6, 0.1, 0.1, 0.7)]
+    sc = make_scene(pos, [[0.09, 0.06, 0.05], [0.08, 0.07, 0.0], [0.07, 0.05, 0.06],
+                          [0.08, 0.06, 0.0], [0.06, 0.09, 0.04]], q,
+                    [0.8, 0.7, 0.9, 0.75, 0.85], np.full((5, 1, 3), 0.4), [1, 0, 1, 0, 1])
+    cams = [sg.look_at_camera((0.05, 0.02, -3.0), width=64, height=48, fx=55.0),
+            sg.look_at_camera((1.0, 0.1, -2.8), target=(1.0, 0.1, 0.0), width=56, height=44,
+                              fx=60.0)]
+    n = sc["means"].shape[0]
     pix = np.concatenate([O.full_pixels(c, v) for v, c in enumerate(cams)])
-    G = np.random.default_rng(3).normal(size=(len(pix), 8))
+    G = np.random.default_rng(5).normal(size=(len(pix), 8))
     norm, cnt = O.densify_stats(sc, cams, pix, G)
-    sgrad = O.screen_grad(sc, cams, pix, G)
-    st = O.structural(sc, cams, 0.3)
-    valid = st["valid"].reshape(2, -1) == 1
-    np.testing.assert_array_equal(cnt, valid.sum(0))
-    expect = sum(np.where(valid[v], np.hypot(sgrad[v, :, 0] * 20.0, sgrad[v, :, 1] * 15.0), 0.0)
-                 for v in range(2))
-    np.testing.assert_allclose(norm, expect, rtol=1e-14)
-    assert (cnt == 2).sum() > 10 and norm.max() > 0
+
+    ref = np.zeros(n)
+    ref_cnt = np.zeros(n, np.int64)
+    for v, c in enumerate(cams):
+        st = O.structural(sc, c, 0.3)
+        r = st["rect"]
+        pv = O.full_pixels(c)
+        Gv = G[pix[:, 0] == v]
+        res = O.forward(sc, c, pv)
+        a = res["out"][:, 3]
+        clean = ~((np.abs(a - 1 / 255) < 2 / 255) | (a > 0.95) | (res["tie"] != 0))
+        inside = [(st["valid"][g] == 1) & (pv[:, 2] >= r[g, 0]) & (pv[:, 2] <= r[g, 2]) &
+                  (pv[:, 1] >= r[g, 1]) & (pv[:, 1] <= r[g, 3]) for g in range(n)]
+        # disjoint footprints: no pixel lies in two rectangles
+        assert (np.sum(inside, 0) <= 1).all()
+        W, H = c["width"], c["height"]
+        h = 1e-6
+        dx = _ndc_to_pix(h, W) - _ndc_to_pix(0.0, W)
+        dy = _ndc_to_pix(h, H) - _ndc_to_pix(0.0, H)
+        for g in range(n):
+            if st["valid"][g] != 1:
+                continue
+            ref_cnt[g] += 1
+            Gg = np.where((inside[g] & clean)[:, None], Gv, 0.0)
+
+            def L(off):
+                return float(np.sum(O.forward(sc, c, pv, {"pix_off": off})["out"] * Gg))
+            # translating the footprint by +d is sampling it at p - d
+            fx = (L((-dx, 0.0)) - L((dx, 0.0))) / (2 * h)
+            fy = (L((0.0, -dy)) - L((0.0, dy))) / (2 * h)
+            ref[g] += np.hypot(fx, fy)
+        # the statistic of this view alone, with the same restriction
+        Gc = np.where(np.any([ins & clean for ins in inside], 0)[:, None], Gv, 0.0)
+        nv, cv = O.densify_stats(sc, c, pv, Gc)
+        np.testing.assert_array_equal(cv, st["valid"])
+    # one splat culled in the second view
+    assert sorted(ref_cnt.tolist()) == [1, 2, 2, 2, 2]
+    np.testing.assert_array_equal(cnt, ref_cnt)
+    # the full statistic uses every pixel; restrict the cotangents for it too
+    Gr = np.zeros_like(G)
+    for v, c in enumerate(cams):
+        st = O.structural(sc, c, 0.3)
+        r = st["rect"]
+        pv = O.full_pixels(c)
+        res = O.forward(sc, c, pv)
+        a = res["out"][:, 3]
+        clean = ~((np.abs(a - 1 / 255) < 2 / 255) | (a > 0.95) | (res["tie"] != 0))
+        keep = np.zeros(len(pv), bool)
+        for g in range(n):
+            if st["valid"][g] == 1:
+                keep |= ((pv[:, 2] >= r[g, 0]) & (pv[:, 2] <= r[g, 2]) & (pv[:, 1] >= r[g, 1]) &
+                         (pv[:, 1] <= r[g, 3]))
+        sel = pix[:, 0] == v
+        Gr[sel] = np.where((keep & clean)[:, None], G[sel], 0.0)
+    norm, cnt = O.densify_stats(sc, cams, pix, Gr)
+    assert norm.min() > 0
+    np.testing.assert_allclose(norm, ref, rtol=1e-5)

@@ -257,6 +257,89 @@ def test_stack_closed_form_counts(oracle_lib):
 
 
 # ---------------------------------------------------------------------------
+# Tie branches (Eq. 2 with either outcome of a decision taken within rounding
+# of its threshold), closed forms on stacks of fronto-parallel surfels
+# centred on one pixel, each contributing exactly its opacity there.
+# ---------------------------------------------------------------------------
+def _stack(alphas, f=64.0):
+    n = len(alphas)
+    zs = 1.0 + 0.1 * np.arange(n)
+    mu = np.stack([0.5 * zs / f, 0.5 * zs / f, zs], 1)  # projects to pixel centre (32.5, 32.5)
+    return make_scene(mu, np.tile([0.05, 0.05, 0.0], (n, 1)), np.tile([1, 0, 0, 0], (n, 1)),
+                      alphas, np.zeros((n, 1, 3)), np.zeros(n))
+
+
+def test_stop_tie_branches_closed_form(oracle_lib):
+    # (1 - a)^10 = 1e-4 up to the rounding of a: the 10th pair's stop test is a tie
+    a = np.float32(1.0 - 1e-4 ** 0.1)
+    sc = _stack(np.full(14, a))
+    cam = axis_camera(z=0.0, f=64.0, W=64, H=64)
+    pix = np.array([[0, 32, 32]], np.int32)
+    a64 = float(a)
+    outs = {}
+    for flip in (0, 1):
+        r = oracle_lib.forward(sc, cam, pix, flip=flip)
+        assert r["tie"][0] & 2 and r["nflags"][0] == 1
+        k = int(r["n_contrib"][0])
+        outs[k] = r
+        w = a64 * (1 - a64) ** np.arange(k)
+        np.testing.assert_allclose(r["T"][0], (1 - a64) ** k, rtol=1e-13)
+        np.testing.assert_allclose(r["out"][0, :3], 0.5 * w.sum(), rtol=1e-13)
+        assert r["last"][0] == k
+    # the two branches stop before the 10th and before the 11th pair
+    assert sorted(outs) == [9, 10]
+    # the binary64 decision is the branch flip = 0 takes
+    T10 = (1 - a64) ** 10
+    assert oracle_lib.forward(sc, cam, pix)["n_contrib"][0] == (9 if T10 < 1e-4 else 10)
+
+
+def test_activity_tie_branches_closed_form(oracle_lib):
+    # a pair of contribution binary32(1/255) at the pixel sample, behind one
+    # of 0.5: active in binary64 (1/255 rounds up), inactive on the flipped branch
+    amin32 = np.float32(1.0 / 255.0)
+    sc = _stack(np.array([0.5, amin32, 0.25], np.float32))
+    cam = axis_camera(z=0.0, f=64.0, W=64, H=64)
+    pix = np.array([[0, 32, 32]], np.int32)
+    r0 = oracle_lib.forward(sc, cam, pix)
+    r1 = oracle_lib.forward(sc, cam, pix, flip=1)
+    assert r0["tie"][0] & 1 and r0["nflags"][0] == 1
+    a = [0.5, float(amin32), 0.25]
+    assert r0["n_contrib"][0] == 3 and r1["n_contrib"][0] == 2
+    np.testing.assert_allclose(r0["T"][0], (1 - a[0]) * (1 - a[1]) * (1 - a[2]), rtol=1e-14)
+    np.testing.assert_allclose(r1["T"][0], (1 - a[0]) * (1 - a[2]), rtol=1e-14)
+    assert r0["last"][0] == 3 and r1["last"][0] == 3
+    # gradients follow the branch: the skipped pair gets none on flip = 1
+    G = np.zeros((1, 8))
+    G[0, 3] = 1.0
+    g0 = oracle_lib.backward(sc, cam, pix, G)
+    g1 = oracle_lib.backward(sc, cam, pix, G, flip=1)
+    assert g0["opacities"][1] != 0.0 and g1["opacities"][1] == 0.0
+    # d alpha / d a_0 = prod of (1 - a_j) over the other blended pairs
+    np.testing.assert_allclose(g1["opacities"][0], (1 - a[2]), rtol=1e-12)
+    np.testing.assert_allclose(g0["opacities"][0], (1 - a[1]) * (1 - a[2]), rtol=1e-12)
+
+
+def test_clamp_tie_spread_closed_form(oracle_lib):
+    # one surfel of opacity binary32(0.99) centred on the pixel sample:
+    # raw = 0.99000001 > 0.99 is clamped (zero derivative), within the clamp
+    # margin; the unclamped branch has d alpha~ / d alpha = e^0 = 1
+    sc = _stack(np.array([0.99], np.float32))
+    cam = axis_camera(z=0.0, f=64.0, W=64, H=64)
+    pix = np.array([[0, 32, 32]], np.int32)
+    r = oracle_lib.forward(sc, cam, pix)
+    assert r["tie"][0] & 4 and r["nflags"][0] == 0
+    G = np.zeros((1, 8))
+    G[0, 3] = 1.0  # L = alpha = alpha~, so dL/d alpha~ = 1
+    g = oracle_lib.backward(sc, cam, pix, G)
+    assert g["opacities"][0] == 0.0
+    np.testing.assert_allclose(g["opacities_tie"][0], 1.0, rtol=1e-15)
+    # away from the clamp there is no spread
+    sc2 = _stack(np.array([0.9], np.float32))
+    g2 = oracle_lib.backward(sc2, cam, pix, G)
+    assert g2["opacities_tie"][0] == 0.0 and g2["opacities"][0] == pytest.approx(1.0)
+
+
+# ---------------------------------------------------------------------------
 # P5 / P6 / P12: order invariance, brute force vs binned, conservative rects,
 # sorted keys vs numpy's stable sort.
 # ---------------------------------------------------------------------------
@@ -497,7 +580,7 @@ def _loss(oracle_lib, sc, cam, pix, Gp, p64, opts=None):
     return float((r["out"] * Gp).sum()), r
 
 
-def _fd_check(oracle_lib, sc, cam, opts=None, seed=0, n_sh=60, rtol=2e-5):
+def _fd_check(oracle_lib, sc, cam, opts=None, seed=0, n_sh=60, rtol=1e-6):
     pix = oracle_lib.full_pixels(cam)
     G = sg.upstream_grads(1, cam["height"], cam["width"], seed)
     Gp = pack_G(G)
