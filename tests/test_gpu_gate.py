@@ -211,7 +211,7 @@ def test_train_step_moves_surfel_sz_through_gate():
     finite_z = surf & np.isfinite(raw["scales"][:, 2])
     assert finite_z.sum() > 200
     # the scene the renderer reads is the activation of the raw parameters
-    act0 = {k: v.copy() for k, v in scene.items()}
+    act0 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in scene.items()}
     act0["scales"] = np.exp(raw["scales"]).astype(np.float32)
     act0["opacities"] = (1.0 / (1.0 + np.exp(-raw["opacities"].astype(np.float64)))).astype(np.float32)
 
