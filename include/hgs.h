@@ -323,6 +323,25 @@ hgs_status hgs_color_loss(hgs_ctx *ctx, int32_t n_views, int32_t height, int32_t
                           const float *render_rgb, const float *target_rgb, double lambda_dssim,
                           float *grad, double *losses, void *stream);
 
+/* The colour loss of hgs_color_loss (same arguments, same kernels, same
+ * results) for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc.  Its derivative maps live in one fixed device array of
+ * 3 * HGS_NOALLOC_MAX_ELEMS floats (96 MiB) that each GPU the library runs on
+ * holds until the process ends; the call allocates nothing and calls no
+ * allocating routine.  n_views * 3 * height * width must not exceed
+ * HGS_NOALLOC_MAX_ELEMS (one 1920x1080 RGB view fits), else ECAPACITY.
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (other streams, other contexts, other host threads) race and must be
+ * ordered by the caller.  Nothing in the array needs to start at zero (the
+ * maps are written in full before they are read).  Errors: as
+ * hgs_color_loss, plus ECAPACITY; ESTATE if the array of ctx's device could
+ * not be resolved when ctx was created. */
+#define HGS_NOALLOC_MAX_ELEMS 8388608
+hgs_status hgs_color_loss_noalloc(hgs_ctx *ctx, int32_t n_views, int32_t height, int32_t width,
+                                  const float *render_rgb, const float *target_rgb,
+                                  double lambda_dssim, float *grad, double *losses, void *stream);
+
 /* Adam hyper-parameters: learning rates per parameter group (SH DC and the
  * higher SH coefficients apart), betas, eps and the 1-based step count used
  * for bias correction.  The betas are binary64 so that 1 - beta (1e-3 for

@@ -19,7 +19,8 @@ EXPORTS = ("hgs_create", "hgs_destroy", "hgs_scene_init", "hgs_scene_release", "
            "hgs_state_check", "hgs_last_error", "hgs_profile_enable", "hgs_profile_read",
            "hgs_server_create", "hgs_server_destroy", "hgs_server_submit", "hgs_server_poll",
            "hgs_server_stats", "hgs_type_exchange", "hgs_fdo_cotangents", "hgs_fdo_project",
-           "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step", "hgs_densify_stats")
+           "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step", "hgs_densify_stats",
+           "hgs_color_loss_noalloc")
 
 STAGES = ("preprocess", "scan", "duplicate", "sort", "ranges", "raster_fwd", "raster_bwd",
           "preprocess_bwd", "fill", "depth_sort", "fdo_cotangents", "fdo_project", "color_loss",
@@ -134,6 +135,7 @@ def load(path: str | None = None):
                                             C.POINTER(hgs_grads), P, P, P]
     lib.hgs_densify_stats.argtypes = [P, P, P, P, P]
     lib.hgs_color_loss.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_double, P, P, P]
+    lib.hgs_color_loss_noalloc.argtypes = lib.hgs_color_loss.argtypes
     lib.hgs_adam_step.argtypes = [P, C.c_int64, C.c_int32] + [C.POINTER(hgs_grads)] * 4 + \
         [P, C.POINTER(hgs_adam_opts), P]
     for name in ("hgs_create", "hgs_scene_init", "hgs_scene_release", "hgs_render",
@@ -141,7 +143,8 @@ def load(path: str | None = None):
                  "hgs_profile_enable", "hgs_profile_read", "hgs_server_create",
                  "hgs_server_submit", "hgs_server_poll", "hgs_server_stats",
                  "hgs_type_exchange", "hgs_fdo_cotangents", "hgs_fdo_project",
-                 "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step", "hgs_densify_stats"):
+                 "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step", "hgs_densify_stats",
+                 "hgs_color_loss_noalloc"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -286,6 +289,16 @@ def hgs_color_loss(ctx, V: int, H: int, W: int, ren_ptr: int, tgt_ptr: int, lam:
     check(load().hgs_color_loss(ctx, int(V), int(H), int(W), C.c_void_p(ren_ptr),
                                 C.c_void_p(tgt_ptr), float(lam), C.c_void_p(grad_ptr),
                                 C.c_void_p(losses_ptr), C.c_void_p(stream)))
+
+
+def hgs_color_loss_noalloc(ctx, V: int, H: int, W: int, ren_ptr: int, tgt_ptr: int, lam: float,
+                           grad_ptr: int, losses_ptr: int, stream: int):
+    check(load().hgs_color_loss_noalloc(ctx, int(V), int(H), int(W), C.c_void_p(ren_ptr),
+                                        C.c_void_p(tgt_ptr), float(lam), C.c_void_p(grad_ptr),
+                                        C.c_void_p(losses_ptr), C.c_void_p(stream)))
+
+
+NOALLOC_MAX_ELEMS = 8388608  # HGS_NOALLOC_MAX_ELEMS
 
 
 def hgs_adam_step(ctx, n: int, sh_degree: int, raw, grads, m, v, act, opts, stream: int):

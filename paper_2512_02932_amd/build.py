@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhgs.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["preprocess.hip", "sort.hip", "raster.hip", "exchange.hip", "fdo.hip", "train.hip", "api.cpp", "server.cpp"]
+SOURCES = ["preprocess.hip", "sort.hip", "raster.hip", "exchange.hip", "fdo.hip", "train.hip", "api.cpp", "server.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -275,6 +275,8 @@ hgs_status hgs_create(int32_t device, hgs_ctx **out) {
   HGS_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
   int cus = 0;
   HGS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  // the fixed array of hgs_color_loss_noalloc on this device
+  HGS_HIP(noalloc_setup(device));
   hgs_ctx *c = new (std::nothrow) hgs_ctx();
   if (!c) return fail(HGS_ENOMEM, "host allocation failed");
   c->device = device;

@@ -53,6 +53,10 @@ struct Workspace {
   bool has_ready = false;
 };
 
+// Resolves, with `device` current, the device address of the fixed array
+// that hgs_color_loss_noalloc uses on that device (once per device).
+hipError_t noalloc_setup(int device);
+
 // Options with defaults filled in, as the kernels take them.
 DevOpts to_dev_opts(const hgs_opts *o);
 // Validates camera c and fills d (view index `view`); false with a reason.

@@ -368,23 +368,31 @@ def fdo_project(types: torch.Tensor, sh_degree: int, g_color: dict, g_low: dict,
 
 
 def color_loss(render_rgb: torch.Tensor, target_rgb: torch.Tensor, lambda_dssim: float = 0.2,
-               losses: torch.Tensor | None = None, want_grad: bool = True):
-    """L_color = (1 - lambda) L1 + lambda D-SSIM (``hgs_color_loss``).
-    Returns (grad or None, losses) with losses a float64 [2] device tensor
-    (L1, D-SSIM) that the call adds into."""
+               losses: torch.Tensor | None = None, want_grad: bool = True,
+               grad: torch.Tensor | None = None, noalloc: bool = False):
+    """L_color = (1 - lambda) L1 + lambda D-SSIM (``hgs_color_loss``, or
+    ``hgs_color_loss_noalloc`` with noalloc=True: no device allocation in
+    the library).  Returns (grad or None, losses) with losses a float64 [2]
+    device tensor (L1, D-SSIM) that the call adds into; `grad` may be given
+    (same shape as the images) to receive the cotangent."""
     if render_rgb.shape != target_rgb.shape or render_rgb.dim() != 4 or render_rgb.shape[1] != 3:
         raise ValueError("render_rgb and target_rgb must both be [V, 3, H, W]")
     for t in (render_rgb, target_rgb):
         if t.dtype != torch.float32 or not t.is_contiguous():
             raise ValueError("images must be contiguous float32")
     V, _, Hh, Ww = render_rgb.shape
-    grad = torch.empty_like(render_rgb) if want_grad else None
+    if grad is None and want_grad:
+        grad = torch.empty_like(render_rgb)
+    if grad is not None and (grad.shape != render_rgb.shape or grad.dtype != torch.float32 or
+                             not grad.is_contiguous()):
+        raise ValueError("grad must be a contiguous float32 tensor shaped like the images")
     if losses is None:
         losses = torch.zeros(2, dtype=torch.float64, device=render_rgb.device)
     rast = get_rasterizer(render_rgb.device)
     s = torch.cuda.current_stream(rast.device).cuda_stream
-    H.hgs_color_loss(rast.ctx, V, Hh, Ww, _ptr(render_rgb), _ptr(target_rgb), lambda_dssim,
-                     _ptr(grad), _ptr(losses), s)
+    fn = H.hgs_color_loss_noalloc if noalloc else H.hgs_color_loss
+    fn(rast.ctx, V, Hh, Ww, _ptr(render_rgb), _ptr(target_rgb), lambda_dssim, _ptr(grad),
+       _ptr(losses), s)
     return grad, losses
 
 
