@@ -26,9 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Per-pair VALU lane-operations of the minimal formulas (a transcendental
-# counts as 4 issue slots), used for the raster kernels' ALU roofline.
+# counts as 4 issue slots), used for the raster kernels' ALU roofline.  The
+# pinned counts are those of the binary32 formulas the kernels evaluate
+# (record-local frame); the survey counts are the plan's estimates (forward
+# 27 / 45, backward about three times the forward), reported beside them.
 OPS_FWD = {"3d": 27, "2d": 34}
 OPS_BWD = {"3d": 71, "2d": 82}
+OPS_FWD_SURVEY = {"3d": 27, "2d": 45}
+OPS_BWD_SURVEY = {"3d": 81, "2d": 135}
 # Each RGB-only cotangent set of the three-set backward adds per blended pair
 # its colour dot product, suffix and dL/d alpha~ (6), colour and alpha_eff
 # slots (6), the record-geometry chain (12 for 3D, 15 for 2D) and its
@@ -38,48 +43,90 @@ OPS_BWD_RGB = {"3d": 33, "2d": 40}
 VALU_PEAK = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12
 
+# name: (scene builder, camera builder, backward?, description)
 WORKLOADS = {
-    # name: (scene builder, camera builder, description)
-    "knot1m_1080p": ("scene_torus_knot", "camera_torus_knot_1080p",
+    "knot1m_1080p": ("scene_torus_knot", "camera_torus_knot_1080p", True,
                      "torus-knot 1M hybrid Gaussians (50% surfels), SH3, 1920x1080, fwd+bwd"),
-    "knot1m_1600x1064": ("scene_torus_knot", "camera_torus_knot",
+    "knot1m_1600x1064": ("scene_torus_knot", "camera_torus_knot", True,
                          "torus-knot 1M hybrid Gaussians (50% surfels), SH3, 1600x1064, fwd+bwd"),
+    "cube10k_256": ("scene_uniform_cube", "camera_cube", False,
+                    "uniform cube 10k Gaussians (5k surfels), SH0, 256x256, forward"),
+    "sphere500k_1080p": ("scene_sphere", "camera_sphere", False,
+                         "noisy sphere 500k Gaussians (70% surfels), SH3, 1920x1080, forward"),
+    "multishell6m_16x4k": ("scene_multishell", "fibonacci_cameras", True,
+                           "multi-shell 6M Gaussians (60% surfels), SH3, 16 views of 3840x2160 "
+                           "in one launch, fwd+bwd"),
 }
+# the per-config legs of the default run (the headline is knot1m_1080p)
+CONFIG_LEGS = ("cube10k_256", "sphere500k_1080p", "knot1m_1600x1064", "multishell6m_16x4k")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(scene_np, cam, G_np, rows: int):
-    """The CPU oracle (binary64, as it stands) on a band of `rows` image rows
-    through the centre of the image: forward + backward."""
+def _cpu_info():
+    """CPU model, logical CPUs of the host and CPUs this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline(scene_np, cam, G_np, rows_all: int = 160, rows_one: int = 12, repeats: int = 3):
+    """The CPU oracle (binary64, as it stands) on bands of image rows through
+    the centre of the image, forward + backward: median of `repeats` runs
+    with every core this job may use (at most 16, the host share of one GPU)
+    on `rows_all` rows, and median of `repeats` runs on one thread on
+    `rows_one` rows."""
     import numpy as np
     import oracle
     oracle.build(force=False)
     H, W = cam["height"], cam["width"]
-    y0 = H // 2 - rows // 2
-    ys = np.arange(y0, y0 + rows)
-    pix = np.stack(np.meshgrid([0], ys, np.arange(W), indexing="ij"), -1).reshape(-1, 3)
-    pix = np.ascontiguousarray(pix, np.int32)
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
-    v, y, x = pix[:, 0], pix[:, 1], pix[:, 2]
-    Gp = np.stack([G_np["rgb"][v, 0, y, x], G_np["rgb"][v, 1, y, x], G_np["rgb"][v, 2, y, x],
-                   G_np["alpha"][v, 0, y, x], G_np["depth"][v, 0, y, x],
-                   G_np["normal"][v, 0, y, x], G_np["normal"][v, 1, y, x],
-                   G_np["normal"][v, 2, y, x]], 1).astype(np.float64)
-    t0 = time.perf_counter()
-    oracle.forward(scene_np, cam, pix, threads=cores)
-    oracle.backward(scene_np, cam, pix, Gp, threads=cores)
-    dt = time.perf_counter() - t0
-    return {"value": round(len(pix) / dt / 1e6, 6), "unit": "Mpixels/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"rows {y0}..{y0 + rows - 1} of {W}x{H} ({len(pix)} px), forward+backward, "
-                      f"binary64, {cores} threads, {dt:.1f} s"}
+    model, n_host, usable = _cpu_info()
+    cores = max(1, min(usable, 16))
+
+    def band(rows):
+        y0 = H // 2 - rows // 2
+        ys = np.arange(y0, y0 + rows)
+        pix = np.stack(np.meshgrid([0], ys, np.arange(W), indexing="ij"), -1).reshape(-1, 3)
+        pix = np.ascontiguousarray(pix, np.int32)
+        v, y, x = pix[:, 0], pix[:, 1], pix[:, 2]
+        Gp = np.stack([G_np["rgb"][v, 0, y, x], G_np["rgb"][v, 1, y, x], G_np["rgb"][v, 2, y, x],
+                       G_np["alpha"][v, 0, y, x], G_np["depth"][v, 0, y, x],
+                       G_np["normal"][v, 0, y, x], G_np["normal"][v, 1, y, x],
+                       G_np["normal"][v, 2, y, x]], 1).astype(np.float64)
+        return pix, Gp, y0
+
+    def run(rows, threads):
+        pix, Gp, y0 = band(rows)
+        times = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            oracle.forward(scene_np, cam, pix, threads=threads)
+            oracle.backward(scene_np, cam, pix, Gp, threads=threads)
+            times.append(time.perf_counter() - t0)
+        dt = float(np.median(times))
+        return dict(value=round(len(pix) / dt / 1e6, 6), unit="Mpixels/s", threads=threads,
+                    sample=f"rows {y0}..{y0 + rows - 1} of {W}x{H} ({len(pix)} px)",
+                    seconds=[round(t, 2) for t in times])
+
+    all_c = run(rows_all, cores)
+    one = run(rows_one, 1)
+    return {"value": all_c["value"], "unit": "Mpixels/s", "cores": cores, "kind": "oracle",
+            "sample": f"{all_c['sample']}, forward+backward, binary64, {cores} threads, median of "
+                      f"{repeats} ({all_c['seconds']} s)",
+            "single_thread": one, "cpu_model": model, "host_logical_cpus": n_host,
+            "cpus_usable": usable}
 
 
 def measured_traffic(kernel, workload):
@@ -237,6 +284,136 @@ def time_steps(rast, step, steps, prof_steps=5):
     _hgs.hgs_profile_enable(rast.ctx, False)
     stage = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
     return (t1 - t0) * 1e3 / steps, stage
+
+
+def stage_roofline(N, K, V, D, P, T_tot, counts, stage_ms, ms_step, backward):
+    """Per-stage algorithmic bytes and VALU lane-ops of one step (the
+    accounting of the method's work, not of this implementation's), the
+    least time each needs at the chip's peaks, and the fractions
+        f_s = max(B_s / BW, Ops_s / VALU) / T_s,
+        f   = sum_s max(B_s / BW, Ops_s / VALU) / T_step.
+    The sort is charged its single-pass lower bound, 24 bytes per pair."""
+    fwd = counts["fwd_3d"] * OPS_FWD["3d"] + counts["fwd_2d"] * OPS_FWD["2d"]
+    bwd = counts["blend_3d"] * OPS_BWD["3d"] + counts["blend_2d"] * OPS_BWD["2d"]
+    model = {
+        "preprocess": (("preprocess",), N * (45 + 12 * K) + V * N * (72 + 4 + 4 + 8),
+                       V * N * (250 + 6 * K)),
+        "scan": (("scan",), 8 * V * N, 0),
+        "duplicate": (("duplicate",), 16 * V * N + 12 * D, 0),
+        "sort": (("depth_sort", "sort"), 24 * D, 0),
+        "ranges": (("ranges",), 8 * D + 8 * T_tot, 0),
+        "raster_fwd": (("raster_fwd",), 72 * D + 44 * P, fwd),
+    }
+    if backward:
+        model["raster_bwd"] = (("fill", "raster_bwd"), 72 * D + 44 * P + 64 * D, bwd)
+        model["preprocess_bwd"] = (("preprocess_bwd",), V * N * (72 + 64) + 2 * N * (45 + 12 * K),
+                                   V * N * (600 + 6 * K))
+    out, least = {}, 0.0
+    for name, (keys, byt, ops) in model.items():
+        t = sum(stage_ms.get(k, 0.0) for k in keys)
+        tb, to = byt / HBM_PEAK * 1e3, ops / VALU_PEAK * 1e3
+        tmin = max(tb, to)
+        least += tmin
+        out[name] = {"ms": round(t, 4), "bytes": int(byt), "ops": int(ops),
+                     "bound": "hbm" if tb >= to else "alu",
+                     "frac": round(tmin / t, 4) if t > 0 else None}
+    return {"stages": out, "combined_frac": round(least / ms_step, 4),
+            "least_ms": round(least, 4), "peaks": {"hbm_GBps": HBM_PEAK / 1e9,
+                                                   "valu_Tops": round(VALU_PEAK / 1e12, 4)},
+            "note": "f = sum over stages of max(bytes / HBM peak, VALU lane-ops / VALU peak), "
+                    "divided by the measured step time"}
+
+
+def dominant_roofline(stage_ms, counts, N, K, V, workload):
+    """The roofline object of the longest kernel among raster forward,
+    raster backward, preprocess and preprocess backward."""
+    cands = [k for k in ("raster_fwd", "raster_bwd", "preprocess", "preprocess_bwd")
+             if k in stage_ms]
+    dom = max(cands, key=lambda k: stage_ms[k])
+    if dom in ("raster_fwd", "raster_bwd"):
+        kname = "raster_fwd_kernel" if dom == "raster_fwd" else "raster_bwd_kernel<1>"
+        ops, ops_s = (OPS_FWD, OPS_FWD_SURVEY) if dom == "raster_fwd" else (OPS_BWD, OPS_BWD_SURVEY)
+        key = "fwd" if dom == "raster_fwd" else "blend"
+        work = counts[f"{key}_3d"] * ops["3d"] + counts[f"{key}_2d"] * ops["2d"]
+        work_s = counts[f"{key}_3d"] * ops_s["3d"] + counts[f"{key}_2d"] * ops_s["2d"]
+        achieved = work / (stage_ms[dom] * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK / 1e12, 4),
+                "unit": "Tops/s", "frac": round(achieved / (VALU_PEAK / 1e12), 4),
+                "traffic": measured_traffic(kname, workload), "kernel": kname,
+                "ops_per_pair": ops, "pairs": {k: counts[f"{key}_{k}"] for k in ("3d", "2d")},
+                "frac_survey_ops": round(work_s / (stage_ms[dom] * 1e-3) / VALU_PEAK, 4),
+                "launch_ms": round(stage_ms[dom], 4)}
+    byt = (N * (45 + 12 * K) + V * N * 88) if dom == "preprocess" else \
+        (V * N * 136 + 2 * N * (45 + 12 * K))
+    achieved = byt / (stage_ms[dom] * 1e-3) / 1e9
+    kname = f"{dom}_kernel<3>" if dom == "preprocess" else f"{dom}_kernel<3, {'false' if V == 1 else 'true'}>"
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s", "frac": round(achieved / (HBM_PEAK / 1e9), 4),
+            "traffic": measured_traffic(kname, workload), "kernel": kname,
+            "launch_ms": round(stage_ms[dom], 4)}
+
+
+def render_leg(rast, name, steps, warmup):
+    """One workload: `steps` timed steps (render, and for the backward
+    workloads render_backward with N(0,1) cotangents on every channel), with
+    the inputs resident in HBM.  Returns the leg's record and the objects
+    the headline's further legs reuse."""
+    import torch
+    import scenegen as sg
+    from paper_2512_02932_amd.rasterizer import pair_counts, to_device
+    scene_fn, cam_fn, backward, desc = WORKLOADS[name]
+    log(f"[{name}] generating")
+    scene_np = getattr(sg, scene_fn)()
+    cams = getattr(sg, cam_fn)()
+    cam_list = cams if isinstance(cams, list) else [cams]
+    V = len(cam_list)
+    H, W = cam_list[0]["height"], cam_list[0]["width"]
+    sc = to_device(scene_np, "cuda")
+    N = int(scene_np["means"].shape[0])
+    K = int(scene_np["sh"].shape[1])
+    G_np = G = grads = None
+    if backward:
+        G_np = sg.upstream_grads(V, H, W, seed=3)
+        G = {k: torch.from_numpy(v).cuda() for k, v in G_np.items()}
+        grads = {k: torch.empty_like(sc[k]) for k in ("means", "scales", "rotations", "opacities", "sh")}
+    images = rast.alloc_images(V, H, W)
+    torch.cuda.synchronize()
+
+    def step():
+        _, state = rast.render(sc, cams, images=images, want_state=backward)
+        if backward:
+            rast.backward(state, G, grads)
+            state.free()
+
+    log(f"[{name}] warmup {warmup}")
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    # work accounting of this workload (identical every step), and a check
+    # that the pairs fit the render's capacity
+    _, st = rast.render(sc, cams, images=images, want_state=True)
+    st.check()
+    counts = pair_counts(st)
+    sizes = st.sizes()
+    st.free()
+    torch.cuda.synchronize()
+    log(f"[{name}] timing {steps} steps")
+    ms, stage_ms = time_steps(rast, step, steps)
+    P = V * H * W
+    T_tot = int(sizes["n_tiles"])
+    D = int(sizes["D"])
+    rec = {"workload": desc, "gaussians": N, "views": V, "width": W, "height": H,
+           "sh_degree": int(round(K ** 0.5)) - 1, "backward": backward, "steps": steps,
+           "ms_per_step": round(ms, 4), "mpix_per_s": round(P / (ms * 1e-3) / 1e6, 3),
+           "pairs_D": D, "tiles": T_tot, "pair_counts": counts,
+           "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+           "stage_roofline": stage_roofline(N, K, V, D, P, T_tot, counts, stage_ms, ms, backward),
+           "roofline": dominant_roofline(stage_ms, counts, N, K, V, name)}
+    log(f"[{name}] {rec['mpix_per_s']} Mpix/s, {rec['ms_per_step']} ms/step, "
+        f"combined f {rec['stage_roofline']['combined_frac']}")
+    keep = dict(scene_np=scene_np, cam=cams, sc=sc, G=G, G_np=G_np, images=images, grads=grads,
+                counts=counts)
+    return rec, keep
 
 
 def exchange_leg(scene_np, workload, copies=8, replays=5):
@@ -406,12 +583,14 @@ def train_leg(rast, scene_np, cam, steps, warmup, workload):
     initial render plus N(0, 0.05), clipped); the three-set backward and
     projection; the densification statistics; one fused Adam step on the raw
     parameters, writing the activated scene the next render reads.  The
-    type exchange (every 500 iterations) is timed apart."""
+    type exchange (every 500 iterations) is timed apart.
+    Timed twice: eager (one launch sequence per iteration), and the same
+    iteration captured once into a HIP graph and replayed (the colour loss
+    then uses its entry point that allocates nothing; Adam's bias-correction
+    step count is the captured one)."""
     import numpy as np
     import torch
-    from paper_2512_02932_amd import _hgs
-    from paper_2512_02932_amd.rasterizer import (adam_step, color_loss, fdo_cotangents,
-                                                 to_device)
+    from paper_2512_02932_amd.rasterizer import adam_step, color_loss, fdo_cotangents, to_device
     H, W = cam["height"], cam["width"]
     N = int(scene_np["means"].shape[0])
     deg = int(scene_np["sh_degree"])
@@ -433,17 +612,21 @@ def train_leg(rast, scene_np, cam, steps, warmup, workload):
     losses = torch.zeros(4, dtype=torch.float64, device="cuda")
     gnorm = torch.zeros(N, device="cuda")
     gcnt = torch.zeros(N, device="cuda")
+    gcol = torch.empty_like(images["rgb"])
     it = [0]
 
-    def step():
-        it[0] += 1
+    def body(noalloc):
         _, state = rast.render(sc, cam, images=images, want_state=True)
-        gcol, _ = color_loss(images["rgb"], target, 0.2, losses=losses[0:2])
+        color_loss(images["rgb"], target, 0.2, losses=losses[0:2], grad=gcol, noalloc=noalloc)
         gl, gh, _ = fdo_cotangents(images["rgb"], target, 0.2, 0.4, losses=losses[2:4])
         rast.backward_fdo(state, {"rgb": gcol}, gl, gh, upd)
         rast.densify_stats(state, gnorm, gcnt)
         adam_step(N, deg, raw, upd, m, v, it[0], activated=act)
-        state.free()
+        return state
+
+    def step():
+        it[0] += 1
+        body(False).free()
 
     for _ in range(warmup):
         step()
@@ -453,10 +636,34 @@ def train_leg(rast, scene_np, cam, steps, warmup, workload):
     ms, stage = time_steps(rast, step, steps)
     stage = {k: round(v, 4) for k, v in stage.items()}
     l1 = losses.cpu().numpy() / (steps + 5)
+
+    # the same iteration as one graph, replayed
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        it[0] += 1
+        body(True).free()  # sizes the workspaces on the capture stream
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    it[0] += 1
+    with torch.cuda.graph(g, stream=s):
+        st_c = body(True)
+    for _ in range(2):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+    del g
+    st_c.free()
+
     K = (deg + 1) ** 2
     adam_bytes = N * (11 + 3 * K) * 4 * 8  # raw, grad, m, v read; raw, m, v, activated written
     ssim_bytes = 3 * H * W * (8 + 12 + 12 + 8 + 4)  # images, A/B/C out and in, images, grad
     out = {"ms_per_iteration": round(ms, 4), "iterations_per_s": round(1e3 / ms, 2),
+           "graph_ms_per_iteration": round(ms_graph, 4),
+           "graph_iterations_per_s": round(1e3 / ms_graph, 2),
            "gaussians": N, "width": W, "height": H,
            "losses_warmup_mean": {"l1": float(l0[0]), "dssim": float(l0[1]),
                                   "low": float(l0[2]), "high": float(l0[3])},
@@ -480,13 +687,34 @@ def train_leg(rast, scene_np, cam, steps, warmup, workload):
     return out
 
 
+def _reap_children():
+    """Ends any child process still alive (none is expected), so the run
+    leaves nothing behind; returns what was found."""
+    try:
+        import psutil
+    except ImportError:
+        return []
+    found = []
+    for ch in psutil.Process().children(recursive=True):
+        try:
+            found.append(f"{ch.pid}:{' '.join(ch.cmdline())[:80]}")
+            ch.terminate()
+        except psutil.Error:
+            pass
+    if found:
+        psutil.wait_procs(psutil.Process().children(recursive=True), timeout=5)
+    return found
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="knot1m_1080p", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-rows", type=int, default=400)
+    ap.add_argument("--legs", default=",".join(CONFIG_LEGS),
+                    help="comma-separated per-config legs to time after the headline "
+                         "('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-train", action="store_true",
                     help="skip the training-iteration timing")
@@ -505,48 +733,15 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    import scenegen as sg
-    from paper_2512_02932_amd import _hgs
-    from paper_2512_02932_amd.rasterizer import get_rasterizer, pair_counts, to_device
+    from paper_2512_02932_amd.rasterizer import get_rasterizer
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
-    scene_fn, cam_fn, desc = WORKLOADS[args.workload]
-    log(f"[bench] generating {args.workload}")
-    scene_np = getattr(sg, scene_fn)()
-    cam = getattr(sg, cam_fn)()
-    H, W = cam["height"], cam["width"]
-    G_np = sg.upstream_grads(1, H, W, seed=3)
-
     rast = get_rasterizer(0)
-    sc = to_device(scene_np, "cuda")
-    G = {k: torch.from_numpy(v).cuda() for k, v in G_np.items()}
-    grads = {k: torch.empty_like(sc[k]) for k in ("means", "scales", "rotations", "opacities", "sh")}
-    images = rast.alloc_images(1, H, W)
-    torch.cuda.synchronize()
-
-    def step():
-        _, state = rast.render(sc, cam, images=images, want_state=True)
-        rast.backward(state, G, grads)
-        state.free()
-
-    log(f"[bench] warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    # work accounting of this workload (identical every step)
-    _, st = rast.render(sc, cam, images=images, want_state=True)
-    counts = pair_counts(st)
-    sizes = st.sizes()
-    st.free()
-    torch.cuda.synchronize()
-
-    log(f"[bench] timing {args.steps} steps")
-    ms, stage_ms = time_steps(rast, step, args.steps)
+    head, keep = render_leg(rast, args.workload, args.steps, args.warmup)
+    scene_np, cam, sc = keep["scene_np"], keep["cam"], keep["sc"]
 
     if args.calib_copy_mb > 0:
         n = args.calib_copy_mb * (1 << 20) // 4
@@ -556,58 +751,48 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calib_copy_mb} MiB done")
-
-    P = H * W
-    value = P / (ms * 1e-3) / 1e6
-    log("[bench] per-launch ms: " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
-    log(f"[bench] counts {counts} D={sizes['D']}")
-
-    # dominant kernel (the stages are single kernels except scan/sort/ranges)
-    dom = max(("raster_fwd", "raster_bwd", "preprocess", "preprocess_bwd"), key=lambda k: stage_ms[k])
-    if dom in ("raster_fwd", "raster_bwd"):
-        kname = "raster_fwd_kernel" if dom == "raster_fwd" else "raster_bwd_kernel<1>"
-        ops = OPS_FWD if dom == "raster_fwd" else OPS_BWD
-        key = "fwd" if dom == "raster_fwd" else "blend"
-        work = counts[f"{key}_3d"] * ops["3d"] + counts[f"{key}_2d"] * ops["2d"]
-        achieved = work / (stage_ms[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK / 1e12, 4),
-                "unit": "Tops/s", "frac": round(achieved / (VALU_PEAK / 1e12), 4),
-                "traffic": measured_traffic(kname, args.workload), "kernel": kname}
-    else:
-        N = scene_np["means"].shape[0]
-        K = scene_np["sh"].shape[1]
-        byt = (N * (45 + 12 * K) + N * 88) if dom == "preprocess" else (N * 136 + 2 * N * (45 + 12 * K))
-        achieved = byt / (stage_ms[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": round(achieved / (HBM_PEAK / 1e9), 4),
-                "traffic": measured_traffic(f"{dom}_kernel<3>" if dom == "preprocess"
-                                            else f"{dom}_kernel<3, false>", args.workload),
-                "kernel": f"{dom}_kernel"}
+        del src, dst
 
     out = {
         "metric": "fwd+bwd Mpixels/s @1M hybrid Gaussians 1080p; served-view p50/p99 ms",
-        "value": round(value, 3), "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "value": head["mpix_per_s"], "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": desc, "gaussians": int(scene_np["means"].shape[0]),
-                   "width": W, "height": H, "sh_degree": 3, "pairs_D": int(sizes["D"]),
-                   "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}},
-        "roofline": roof,
+        "config": {"workload": head["workload"], "gaussians": head["gaussians"],
+                   "width": head["width"], "height": head["height"], "sh_degree": head["sh_degree"],
+                   "pairs_D": head["pairs_D"], "stage_ms": head["stage_ms"]},
+        "roofline": head["roofline"],
+        "stage_roofline": head["stage_roofline"],
     }
-    if not args.no_fdo:
-        out["fdo"] = fdo_leg(rast, sc, cam, images, G, counts, int(scene_np["means"].shape[0]),
-                             int(scene_np["sh"].shape[1]), args.steps, args.warmup, args.workload)
-    if not args.no_train:
+    if not args.no_fdo and head["backward"] and head["views"] == 1:
+        out["fdo"] = fdo_leg(rast, sc, cam, keep["images"], keep["G"], keep["counts"],
+                             head["gaussians"], int(scene_np["sh"].shape[1]), args.steps,
+                             args.warmup, args.workload)
+    if not args.no_train and head["views"] == 1:
         out["train_step"] = train_leg(rast, scene_np, cam, args.steps, args.warmup, args.workload)
     if not args.no_exchange:
         out["type_exchange"] = exchange_leg(scene_np, args.workload)
+    G_np = keep["G_np"]
+    del keep, sc
+    torch.cuda.empty_cache()
+    legs = [x for x in args.legs.split(",") if x and x != args.workload]
+    if legs:
+        out["configs"] = {}
+        for name in legs:
+            rec, k2 = render_leg(rast, name, min(args.steps, 10 if name.startswith("multishell")
+                                                  else args.steps), min(args.warmup, 2))
+            del k2
+            torch.cuda.empty_cache()
+            out["configs"][name] = rec
     if not args.no_serving:
-        del sc, grads, images, G
-        torch.cuda.empty_cache()
         out["serving"] = serving(rast)
-    if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline on {args.cpu_rows} rows")
-        out["cpu_baseline"] = cpu_baseline(scene_np, cam, G_np, args.cpu_rows)
+    if not args.no_cpu_baseline and G_np is not None:
+        log("[bench] cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(scene_np, cam, G_np)
+    torch.cuda.synchronize()
+    left = _reap_children()
+    if left:
+        log(f"[bench] ended child processes: {left}")
     print(json.dumps(out), flush=True)
 
 

@@ -58,7 +58,7 @@ enum {
   HGS_EINVAL = -1,    /* bad argument (null pointer, size out of range, ...) */
   HGS_ENOMEM = -2,    /* device or host allocation failed */
   HGS_EHIP = -3,      /* a HIP runtime call failed */
-  HGS_ECAPACITY = -4, /* more (tile, splat) pairs than 2^32 - 1 */
+  HGS_ECAPACITY = -4, /* more (tile, splat) pairs than a capacity */
   HGS_ESTATE = -5     /* state used in the wrong way (e.g. backward twice) */
 };
 
@@ -89,17 +89,38 @@ typedef struct {
 
 /* [host] Render options.  Defaults: bg = 0, dilation = 0.3 px^2,
  * lambda_z = 1, theta_z = 1.05, temp_z = 0.001 (Eq. 7's constants are the
- * paper's, appendix "Implementation Details"). */
+ * paper's, appendix "Implementation Details"), alpha_min = 1/255,
+ * alpha_max = 0.99, t_min = 1e-4, out_mask = 0.
+ * The compositing thresholds of Eq. 2, which the paper inherits from the
+ * rasterizer it builds on (Sec. 4, "Implementation"): a pair whose
+ * alpha_eff exp(-d/2) is below alpha_min is skipped (and a primitive whose
+ * opacity is below it is culled; the screen rectangles bound the support
+ * alpha_eff exp(-d/2) >= alpha_min); a contribution is clamped at
+ * alpha_max; a pixel stops before the pair that would take its
+ * transmittance below t_min.  Requires 0 < alpha_min <= alpha_max < 1 and
+ * 0 < t_min < 1.
+ * out_mask selects the output channels: bit 0 rgb, 1 alpha, 2 depth,
+ * 3 normal.  A channel whose bit is set needs its hgs_images pointer (NULL
+ * is EINVAL); a clear bit leaves the channel unwritten whatever its
+ * pointer.  out_mask = 0 writes every channel whose pointer is not NULL. */
 typedef struct {
   float bg[3];
   float dilation;
   float lambda_z, theta_z, temp_z;
+  float alpha_min, alpha_max, t_min;
+  uint32_t out_mask;
 } hgs_opts;
+
+#define HGS_OUT_RGB 1u
+#define HGS_OUT_ALPHA 2u
+#define HGS_OUT_DEPTH 4u
+#define HGS_OUT_NORMAL 8u
 
 /* Output images, each [V,C,H,W]: rgb C=3, alpha C=1 (= 1 - T_final),
  * depth C=1 (sum of weight x camera z), normal C=3 (sum of weight x
- * camera-space unit normal facing the camera).  Any pointer may be NULL,
- * and that channel is then not written. */
+ * camera-space unit normal facing the camera).  A pointer may be NULL for a
+ * channel that opts.out_mask does not select (with out_mask = 0, any
+ * pointer may be NULL and that channel is then not written). */
 typedef struct {
   float *rgb, *alpha, *depth, *normal;
 } hgs_images;
@@ -145,8 +166,22 @@ hgs_status hgs_scene_release(hgs_ctx *ctx, int32_t scene_id);
  * transmittance and the last contributor per pixel.  Free it with
  * hgs_state_free.  Opts may be NULL (defaults).
  *
- * The call synchronises `stream` once, to read the number of (tile, splat)
- * pairs and size the sort buffers. */
+ * The call only enqueues work on `stream`: the pair count D stays on the
+ * device, and the pair buffers and sort grids are sized by a pair
+ * capacity.  The capacity is the context's (hgs_set_pair_capacity) or, by
+ * default, one learned per pooled workspace: the first render on a
+ * workspace synchronises `stream` once to read D, and later renders grow the
+ * capacity from the D of that workspace's previous render once it has
+ * finished, without waiting for it.  Pairs beyond the capacity are dropped
+ * on the device; such a render's images are incomplete and
+ * hgs_state_check reports ECAPACITY (and enlarges the learned capacity).
+ * A render may be captured into a HIP graph on `stream` if the capacity is
+ * known (a render of the same sizes has run on the context, or a fixed
+ * capacity is set), its workspaces need not grow (same sizes as before) and
+ * n_views <= 64; the state of a captured render must stay alive while the
+ * graph is replayed (its buffers are the graph's), and everything on it
+ * must use that stream.  Errors: EINVAL, ENOMEM, EHIP, ECAPACITY (more
+ * than 2^32 - 1 pairs on the first render of a workspace). */
 hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, int32_t n_views,
                       const hgs_opts *opts, const hgs_images *out, hgs_state **state,
                       void *stream);
@@ -162,8 +197,14 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *state, const hgs_grad_im
 
 void hgs_state_free(hgs_ctx *ctx, hgs_state *state);
 
-/* Sizes kept in a state: [0] V*N, [1] number of (tile, splat) pairs D,
- * [2] total tiles, [3] pixels per view (H*W), [4] V. */
+/* Fixes the pair capacity of every later render on ctx (max_pairs in
+ * [1, 2^32 - 1]), or returns to the learned capacity (max_pairs = 0, the
+ * default).  A fixed capacity never synchronises; see hgs_render. */
+hgs_status hgs_set_pair_capacity(hgs_ctx *ctx, int64_t max_pairs);
+
+/* Sizes kept in a state: [0] V*N, [1] number of (tile, splat) pairs D in
+ * the sorted list (at most the capacity), [2] total tiles, [3] pixels per
+ * view (H*W), [4] V.  Synchronises the state's stream the first time. */
 hgs_status hgs_state_sizes(hgs_ctx *ctx, hgs_state *state, int64_t *sizes5 /* [host] */);
 
 /* Copy one internal array of a state to host memory, for parity tests.
@@ -187,7 +228,9 @@ hgs_status hgs_state_sizes(hgs_ctx *ctx, hgs_state *state, int64_t *sizes5 /* [h
 hgs_status hgs_state_debug(hgs_ctx *ctx, hgs_state *state, int32_t what, void *dst_host,
                            int64_t capacity);
 
-/* Synchronise the state's stream and report any asynchronous error. */
+/* Synchronise the state's stream and report any asynchronous error, or
+ * ECAPACITY if the render produced more pairs than its capacity (the next
+ * render on this context is given room for them). */
 hgs_status hgs_state_check(hgs_ctx *ctx, hgs_state *state);
 
 /* Per-stage timing.  While enabled, every render/backward call records a

@@ -20,7 +20,7 @@ EXPORTS = ("hgs_create", "hgs_destroy", "hgs_scene_init", "hgs_scene_release", "
            "hgs_server_create", "hgs_server_destroy", "hgs_server_submit", "hgs_server_poll",
            "hgs_server_stats", "hgs_type_exchange", "hgs_fdo_cotangents", "hgs_fdo_project",
            "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step", "hgs_densify_stats",
-           "hgs_color_loss_noalloc")
+           "hgs_color_loss_noalloc", "hgs_set_pair_capacity")
 
 STAGES = ("preprocess", "scan", "duplicate", "sort", "ranges", "raster_fwd", "raster_bwd",
           "preprocess_bwd", "fill", "depth_sort", "fdo_cotangents", "fdo_project", "color_loss",
@@ -41,7 +41,11 @@ class hgs_camera(C.Structure):
 
 class hgs_opts(C.Structure):
     _fields_ = [("bg", C.c_float * 3), ("dilation", C.c_float), ("lambda_z", C.c_float),
-                ("theta_z", C.c_float), ("temp_z", C.c_float)]
+                ("theta_z", C.c_float), ("temp_z", C.c_float), ("alpha_min", C.c_float),
+                ("alpha_max", C.c_float), ("t_min", C.c_float), ("out_mask", C.c_uint32)]
+
+
+OUT_RGB, OUT_ALPHA, OUT_DEPTH, OUT_NORMAL = 1, 2, 4, 8
 
 
 class hgs_images(C.Structure):
@@ -136,6 +140,7 @@ def load(path: str | None = None):
     lib.hgs_densify_stats.argtypes = [P, P, P, P, P]
     lib.hgs_color_loss.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_double, P, P, P]
     lib.hgs_color_loss_noalloc.argtypes = lib.hgs_color_loss.argtypes
+    lib.hgs_set_pair_capacity.argtypes = [P, C.c_int64]
     lib.hgs_adam_step.argtypes = [P, C.c_int64, C.c_int32] + [C.POINTER(hgs_grads)] * 4 + \
         [P, C.POINTER(hgs_adam_opts), P]
     for name in ("hgs_create", "hgs_scene_init", "hgs_scene_release", "hgs_render",
@@ -144,7 +149,7 @@ def load(path: str | None = None):
                  "hgs_server_submit", "hgs_server_poll", "hgs_server_stats",
                  "hgs_type_exchange", "hgs_fdo_cotangents", "hgs_fdo_project",
                  "hgs_render_backward_fdo", "hgs_color_loss", "hgs_adam_step", "hgs_densify_stats",
-                 "hgs_color_loss_noalloc"):
+                 "hgs_color_loss_noalloc", "hgs_set_pair_capacity"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -208,6 +213,10 @@ def hgs_state_debug(ctx, state, what: int, dst_ptr: int, capacity: int):
 
 def hgs_state_check(ctx, state):
     check(load().hgs_state_check(ctx, state))
+
+
+def hgs_set_pair_capacity(ctx, max_pairs: int):
+    check(load().hgs_set_pair_capacity(ctx, int(max_pairs)))
 
 
 def hgs_profile_enable(ctx, on: bool):

@@ -41,13 +41,18 @@ struct hgs_state {
   uint32_t *tiles = nullptr, *zbits = nullptr, *offsets = nullptr;
   int4 *rect = nullptr;
   uint8_t *flags = nullptr;
-  uint64_t *total = nullptr;
+  uint64_t *total = nullptr;     // device: pair count D (the scan total)
+  uint32_t *overflow = nullptr;  // device: bit 0 D exceeded the pair capacity, bit 1 sort error
+  int64_t cap = 0;               // pair capacity of this render
+  bool overflowed = false;
+  bool sort_failed = false;      // a radix pass's look-back gave up (never expected)
   uint32_t *keys = nullptr;  // tile id of each sorted pair
   uint32_t *vals = nullptr;  // instance id (view * N + splat) of each sorted pair
   uint2 *ranges = nullptr;
   float *T_final = nullptr;
   uint32_t *last = nullptr, *n_contrib = nullptr, *wcount = nullptr;
-  int64_t D = 0;
+  int64_t D = -1;        // pairs in the sorted list, min(D_total, cap), once read back
+  int64_t D_total = -1;  // pairs the render produced (may exceed cap)
   // accumulator planes of the last backward on this state (workspace arena 2)
   const float *accum_last = nullptr;
   int accum_planes = 0;
@@ -90,7 +95,8 @@ struct StageTimer {
 };
 
 // Buffers are planned with dalloc and placed by commit() in one arena of
-// the state's workspace (256-byte aligned), growing the arena if needed.
+// the state's workspace (256-byte aligned), growing the arena if needed
+// (never under graph capture: no_grow).
 hipError_t dalloc(hgs_state *st, void **p, size_t bytes) {
   st->plan.push_back({p, bytes == 0 ? 256 : bytes});
   *p = nullptr;
@@ -104,10 +110,20 @@ hipError_t dalloc_t(hgs_state *st, T **p, size_t count) {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-hipError_t commit(hgs_state *st, int which, hipStream_t s) {
+// Pair capacity for an observed pair count: half again of headroom.
+int64_t grow_cap(uint64_t D) {
+  const uint64_t c = D + D / 2 + 65536;
+  return (int64_t)(c < 0xffffffffull ? c : 0xffffffffull);
+}
+
+hipError_t commit(hgs_state *st, int which, hipStream_t s, bool no_grow = false) {
   size_t total = 0;
   for (auto &it : st->plan) total += align256(it.second);
   Arena &A = st->ws->arena[which];
+  if (A.cap < total && no_grow) {
+    st->plan.clear();
+    return hipErrorNotSupported;  // a captured call may not allocate
+  }
   if (A.cap < total) {
     if (A.buf) {
       const hipError_t e = hipFreeAsync(A.buf, s);
@@ -147,10 +163,23 @@ hipError_t acquire_ws(hgs_ctx *ctx, hgs_state *st) {
   return hipSuccess;
 }
 
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
 void release(hgs_ctx *ctx, hgs_state *st) {
   if (!st || !st->ws) return;
   Workspace *w = st->ws;
   st->ws = nullptr;
+  if (capturing(st->stream)) {
+    // no host-side stream work under capture: the next user of this
+    // workspace must use the same stream
+    w->stream = st->stream;
+    w->has_ready = false;
+    ctx->ws_free.push_back(w);
+    return;
+  }
   if (!w->ready && hipEventCreateWithFlags(&w->ready, hipEventDisableTiming) != hipSuccess)
     w->ready = nullptr;
   if (w->ready && hipEventRecord(w->ready, st->stream) == hipSuccess) {
@@ -175,13 +204,42 @@ DevOpts to_dev_opts(const hgs_opts *o) {
     d.lambda_z = o->lambda_z;
     d.theta_z = o->theta_z;
     d.temp_z = o->temp_z;
+    d.alpha_min = o->alpha_min;
+    d.alpha_max = o->alpha_max;
+    d.t_min = o->t_min;
+    d.out_mask = o->out_mask;
   } else {
     d.dilation = 0.3f;
     d.lambda_z = 1.0f;
     d.theta_z = 1.05f;
     d.temp_z = 0.001f;
+    d.alpha_min = 1.0f / 255.0f;
+    d.alpha_max = 0.99f;
+    d.t_min = 1e-4f;
+    d.out_mask = 0u;
   }
+  // radius^2 of the support of an opaque splat, 2 ln(1 / alpha_min), rounded
+  // up to binary32 so the screen rectangle never undercuts it
+  const double r = 2.0 * std::log(1.0 / (double)d.alpha_min);
+  float f = (float)r;
+  if ((double)f < r) f = std::nextafter(f, INFINITY);
+  d.rr0 = f;
+  d.inv_amin = (float)(1.0 / (double)d.alpha_min);
   return d;
+}
+
+hgs_status check_opts(const hgs_opts *o) {
+  if (!o) return HGS_OK;
+  if (!(o->dilation >= 0.0f && std::isfinite(o->dilation) && o->temp_z > 0.0f &&
+        std::isfinite(o->lambda_z) && std::isfinite(o->theta_z) && std::isfinite(o->temp_z) &&
+        std::isfinite(o->bg[0]) && std::isfinite(o->bg[1]) && std::isfinite(o->bg[2])))
+    return fail(HGS_EINVAL, "bad opts (dilation >= 0, temp_z > 0, all finite)");
+  if (!(o->alpha_min > 0.0f && o->alpha_min <= o->alpha_max && o->alpha_max < 1.0f))
+    return fail(HGS_EINVAL, "bad opts: need 0 < alpha_min <= alpha_max < 1");
+  if (!(o->t_min > 0.0f && o->t_min < 1.0f))
+    return fail(HGS_EINVAL, "bad opts: need 0 < t_min < 1");
+  if (o->out_mask & ~0xfu) return fail(HGS_EINVAL, "bad opts: out_mask has bits above 3");
+  return HGS_OK;
 }
 
 bool make_dev_cam(const hgs_camera &c, DevCam &d, int view, std::string &why) {
@@ -256,6 +314,26 @@ hgs_status check_desc(const hgs_scene_desc *d) {
   return HGS_OK;
 }
 
+// Synchronises the state's stream and reads its pair count and overflow
+// flag once.
+hipError_t read_pairs(hgs_state *st, bool &over) {
+  if (st->D < 0) {
+    hipError_t e = hipStreamSynchronize(st->stream);
+    if (e != hipSuccess) return e;
+    uint64_t tot = 0;
+    uint32_t ov = 0;
+    e = hipMemcpy(&tot, st->total, sizeof(tot), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&ov, st->overflow, sizeof(ov), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    st->D_total = (int64_t)tot;
+    st->D = std::min<int64_t>((int64_t)tot, st->cap);
+    st->overflowed = (ov & 1u) != 0 || (int64_t)tot > st->cap;
+    st->sort_failed = (ov & 2u) != 0;
+  }
+  over = st->overflowed;
+  return hipSuccess;
+}
+
 }  // namespace hgs
 
 extern "C" {
@@ -300,6 +378,8 @@ void hgs_destroy(hgs_ctx *ctx) {
     for (Arena &a : w->arena)
       if (a.buf) (void)hipFree(a.buf);
     if (w->ready) (void)hipEventDestroy(w->ready);
+    if (w->status_ev) (void)hipEventDestroy(w->status_ev);
+    if (w->status_host) (void)hipHostFree(w->status_host);
     delete w;
   }
   delete ctx;
@@ -388,10 +468,27 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   if (!cams || n_views < 1) return fail(HGS_EINVAL, "need at least one camera");
   if (n_views > 4096) return fail(HGS_EINVAL, "too many views");
   const Scene &sc = ctx->scenes[scene_id];
-  if (opts && !(opts->dilation >= 0.0f && std::isfinite(opts->dilation) &&
-                opts->temp_z > 0.0f && std::isfinite(opts->lambda_z) &&
-                std::isfinite(opts->theta_z) && std::isfinite(opts->temp_z)))
-    return fail(HGS_EINVAL, "bad opts (dilation >= 0, temp_z > 0, finite)");
+  {
+    const hgs_status os = check_opts(opts);
+    if (os != HGS_OK) return os;
+  }
+  RasterOut ro{};
+  {
+    const uint32_t mask = opts ? opts->out_mask : 0u;
+    float *const ptr[4] = {out ? out->rgb : nullptr, out ? out->alpha : nullptr,
+                           out ? out->depth : nullptr, out ? out->normal : nullptr};
+    float *sel[4];
+    for (int c = 0; c < 4; ++c) {
+      const bool want = mask == 0u ? ptr[c] != nullptr : ((mask >> c) & 1u) != 0u;
+      if (want && !ptr[c])
+        return fail(HGS_EINVAL, "opts.out_mask selects an output channel whose pointer is NULL");
+      sel[c] = want ? ptr[c] : nullptr;
+    }
+    ro.rgb = sel[0];
+    ro.alpha = sel[1];
+    ro.depth = sel[2];
+    ro.normal = sel[3];
+  }
   const int W = cams[0].width, H = cams[0].height;
   hgs_state *st = new (std::nothrow) hgs_state();
   if (!st) return fail(HGS_ENOMEM, "host allocation failed");
@@ -433,8 +530,9 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   const int64_t P = (int64_t)n_views * W * H;
 
   auto bail = [&](hgs_status s) {
+    const bool cap = capturing(st->stream);
     release(ctx, st);
-    (void)hipStreamSynchronize(st->stream);
+    if (!cap) (void)hipStreamSynchronize(st->stream);
     delete st;
     return s;
   };
@@ -447,6 +545,11 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   } while (0)
 
   ST_HIP(hipSetDevice(ctx->device));
+  const bool cap_mode = capturing(st->stream);
+  if (cap_mode && n_views > kCamsPerUpload * 8) {
+    delete st;
+    return fail(HGS_EINVAL, "a captured render takes at most 64 views");
+  }
   ST_HIP(acquire_ws(ctx, st));
   ST_HIP(dalloc_t(st, &st->cams, (size_t)n_views));
   ST_HIP(dalloc_t(st, &st->rec, (size_t)VN));
@@ -456,6 +559,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc_t(st, &st->flags, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->offsets, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->total, (size_t)1));
+  ST_HIP(dalloc_t(st, &st->overflow, (size_t)1));
   void *scan_tmp = nullptr;
   ST_HIP(dalloc(st, &scan_tmp, scan_tmp_bytes(VN)));
   ST_HIP(dalloc_t(st, &st->ranges, (size_t)n_tiles));
@@ -472,9 +576,14 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc_t(st, &ob, (size_t)VN));
   ST_HIP(dalloc_t(st, &cnt, (size_t)VN));
   ST_HIP(dalloc(st, &dsort_tmp, sort_tmp_bytes(VN)));
-  ST_HIP(commit(st, 0, st->stream));
-  ST_HIP(hipMemcpyAsync(st->cams, st->cams_host.data(), sizeof(DevCam) * n_views,
-                        hipMemcpyHostToDevice, st->stream));
+  ST_HIP(commit(st, 0, st->stream, cap_mode));
+  if (n_views <= kCamsPerUpload * 8) {
+    launch_upload_cams(st->cams_host.data(), n_views, st->cams, st->stream);
+  } else {
+    ST_HIP(hipMemcpyAsync(st->cams, st->cams_host.data(), sizeof(DevCam) * n_views,
+                          hipMemcpyHostToDevice, st->stream));
+  }
+  launch_fill_u32(st->overflow, 0u, 1, st->stream);
 
   {
     StageTimer t(ctx, HGS_STAGE_PREPROCESS, st->stream);
@@ -483,58 +592,74 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   }
   const uint32_t *order = nullptr;
   {
+    // instances in depth order; the last pass also gathers their tile counts
     StageTimer t(ctx, HGS_STAGE_DEPTH_SORT, st->stream);
     const int w = launch_radix_sort(st->zbits, nullptr, za, oa, zb, ob, VN, 32, dsort_tmp,
-                                    st->stream);
+                                    st->stream, nullptr, st->tiles, cnt, st->overflow);
     order = w ? ob : oa;
   }
   {
     StageTimer t(ctx, HGS_STAGE_SCAN, st->stream);
-    launch_gather(st->tiles, order, VN, cnt, st->stream);
     launch_scan(cnt, st->offsets, VN, st->total, scan_tmp, st->stream);
   }
-  uint64_t Dh = 0;
-  ST_HIP(hipMemcpyAsync(&Dh, st->total, sizeof(uint64_t), hipMemcpyDeviceToHost, st->stream));
-  ST_HIP(hipStreamSynchronize(st->stream));
-  ST_HIP(hipGetLastError());
-  if (Dh > 0xffffffffull) return bail(fail(HGS_ECAPACITY, "more than 2^32-1 (tile, splat) pairs"));
-  st->D = (int64_t)Dh;
+  // pair capacity: fixed, or learned by this workspace (see Workspace)
+  Workspace *ws = st->ws;
+  int64_t cap = ctx->pair_cap;
+  if (cap <= 0) {
+    if (ws->shape_vn != VN || ws->shape_tiles != n_tiles) ws->pair_cap = 0;
+    if (!cap_mode && ws->pair_cap > 0 && ws->status_pending &&
+        hipEventQuery(ws->status_ev) == hipSuccess) {
+      ws->status_pending = false;
+      const uint64_t last = ws->status_host[0];
+      if ((double)last > 0.8 * (double)ws->pair_cap) ws->pair_cap = grow_cap(last);
+    }
+    if (ws->pair_cap <= 0) {
+      if (cap_mode)
+        return bail(fail(HGS_EINVAL, "a captured render needs a known pair capacity: render "
+                                     "once outside capture or call hgs_set_pair_capacity"));
+      uint64_t Dh = 0;
+      ST_HIP(hipMemcpyAsync(&Dh, st->total, sizeof(uint64_t), hipMemcpyDeviceToHost, st->stream));
+      ST_HIP(hipStreamSynchronize(st->stream));
+      ST_HIP(hipGetLastError());
+      if (Dh > 0xffffffffull)
+        return bail(fail(HGS_ECAPACITY, "more than 2^32-1 (tile, splat) pairs"));
+      ws->pair_cap = grow_cap(Dh);
+      ws->shape_vn = VN;
+      ws->shape_tiles = n_tiles;
+      ws->status_pending = false;
+    }
+    cap = ws->pair_cap;
+  }
+  st->cap = cap;
 
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
   void *sort_tmp = nullptr;
-  ST_HIP(dalloc_t(st, &ka, (size_t)st->D));
-  ST_HIP(dalloc_t(st, &va, (size_t)st->D));
-  ST_HIP(dalloc_t(st, &kb, (size_t)st->D));
-  ST_HIP(dalloc_t(st, &vb, (size_t)st->D));
-  ST_HIP(dalloc(st, &sort_tmp, sort_tmp_bytes(st->D)));
-  ST_HIP(commit(st, 1, st->stream));
+  ST_HIP(dalloc_t(st, &ka, (size_t)cap));
+  ST_HIP(dalloc_t(st, &va, (size_t)cap));
+  ST_HIP(dalloc_t(st, &kb, (size_t)cap));
+  ST_HIP(dalloc_t(st, &vb, (size_t)cap));
+  ST_HIP(dalloc(st, &sort_tmp, sort_tmp_bytes(cap)));
+  ST_HIP(commit(st, 1, st->stream, cap_mode));
   {
     StageTimer t(ctx, HGS_STAGE_DUPLICATE, st->stream);
-    launch_duplicate(order, st->offsets, st->tiles, st->rect, st->cams, n_views, st->N, kb, vb,
-                     st->stream);
+    launch_duplicate(order, st->offsets, st->tiles, st->rect, st->cams, n_views, st->N,
+                     (uint64_t)cap, kb, vb, st->overflow, st->stream);
   }
   int tile_bits = 0;
   while ((int64_t(1) << tile_bits) < n_tiles) ++tile_bits;
   {
     StageTimer t(ctx, HGS_STAGE_SORT, st->stream);
-    const int w = launch_radix_sort(kb, vb, ka, va, kb, vb, st->D, tile_bits, sort_tmp,
-                                    st->stream);
+    const int w = launch_radix_sort(kb, vb, ka, va, kb, vb, cap, tile_bits, sort_tmp,
+                                    st->stream, st->total, nullptr, nullptr, st->overflow);
     st->keys = w ? kb : ka;
     st->vals = w ? vb : va;
   }
   {
     StageTimer t(ctx, HGS_STAGE_RANGES, st->stream);
     launch_fill_u32(reinterpret_cast<uint32_t *>(st->ranges), 0u, 2 * n_tiles, st->stream);
-    launch_ranges(st->keys, st->D, st->ranges, st->stream);
+    launch_ranges(st->keys, cap, st->ranges, st->stream, st->total);
   }
 
-  RasterOut ro{};
-  if (out) {
-    ro.rgb = out->rgb;
-    ro.alpha = out->alpha;
-    ro.depth = out->depth;
-    ro.normal = out->normal;
-  }
   ro.T_final = st->T_final;
   ro.last = st->last;
   ro.n_contrib = st->n_contrib;
@@ -543,6 +668,20 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
     StageTimer t(ctx, HGS_STAGE_RASTER_FWD, st->stream);
     launch_raster_fwd(st->ranges, st->vals, st->rec, st->cams, n_views, st->n_tiles, W, H,
                       st->tiles_x, st->tiles_per_view, st->opt, ro, st->stream);
+  }
+  if (!cap_mode && ctx->pair_cap <= 0) {
+    // the pair count and overflow flag of this render, for the next render
+    // on this workspace (read without waiting)
+    if (!ws->status_host) {
+      void *h = nullptr;
+      ST_HIP(hipHostMalloc(&h, 2 * sizeof(uint64_t), hipHostMallocDefault));
+      ws->status_host = static_cast<uint64_t *>(h);
+    }
+    if (!ws->status_ev) ST_HIP(hipEventCreateWithFlags(&ws->status_ev, hipEventDisableTiming));
+    ST_HIP(hipMemcpyAsync(ws->status_host, st->total, sizeof(uint64_t), hipMemcpyDeviceToHost,
+                          st->stream));
+    ST_HIP(hipEventRecord(ws->status_ev, st->stream));
+    ws->status_pending = true;
   }
   ST_HIP(hipGetLastError());
 #undef ST_HIP
@@ -586,7 +725,7 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_image
   if (!st->ws) return fail(HGS_ESTATE, "state has no workspace");
   float *accum = nullptr;
   HGS_HIP(dalloc_t(st, &accum, (size_t)std::max<int64_t>(VN, 1) * kGradSlots));
-  HGS_HIP(commit(st, 2, s));
+  HGS_HIP(commit(st, 2, s, capturing(s)));
   {
     StageTimer t(ctx, HGS_STAGE_FILL, s);
     launch_fill_f32(accum, 0.0f, VN * kGradSlots, s);
@@ -657,7 +796,7 @@ hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *st, const hgs_grad_i
   if (!sets && !one_view)
     for (int k = 0; k < 3; ++k)
       for (int j = 0; j < 5; ++j) HGS_HIP(dalloc_t(st, &own[k][j], std::max<size_t>(cnt[j], 1)));
-  HGS_HIP(commit(st, 2, s));
+  HGS_HIP(commit(st, 2, s, capturing(s)));
   float *gs[3][5];
   for (int k = 0; k < 3; ++k) {
     if (sets) {
@@ -797,7 +936,7 @@ hgs_status hgs_color_loss(hgs_ctx *ctx, int32_t n_views, int32_t height, int32_t
   HGS_HIP(acquire_ws(ctx, &tmp));
   float *maps = nullptr;
   hipError_t e = dalloc_t(&tmp, &maps, (size_t)(3 * npx));
-  if (e == hipSuccess) e = commit(&tmp, 0, s);
+  if (e == hipSuccess) e = commit(&tmp, 0, s, capturing(s));
   if (e == hipSuccess) {
     StageTimer t(ctx, HGS_STAGE_COLOR_LOSS, s);
     launch_ssim_fwd(planes, height, width, render_rgb, target_rgb, maps, maps + npx,
@@ -927,6 +1066,9 @@ void hgs_state_free(hgs_ctx *ctx, hgs_state *st) {
 
 hgs_status hgs_state_sizes(hgs_ctx *ctx, hgs_state *st, int64_t *sizes5) {
   if (!ctx || !st || !sizes5) return fail(HGS_EINVAL, "NULL argument");
+  HGS_HIP(hipSetDevice(ctx->device));
+  bool over = false;
+  HGS_HIP(read_pairs(st, over));
   sizes5[0] = (int64_t)st->V * st->N;
   sizes5[1] = st->D;
   sizes5[2] = st->n_tiles;
@@ -938,6 +1080,8 @@ hgs_status hgs_state_sizes(hgs_ctx *ctx, hgs_state *st, int64_t *sizes5) {
 hgs_status hgs_state_debug(hgs_ctx *ctx, hgs_state *st, int32_t what, void *dst, int64_t cap) {
   if (!ctx || !st || !dst) return fail(HGS_EINVAL, "NULL argument");
   HGS_HIP(hipSetDevice(ctx->device));
+  bool over = false;
+  HGS_HIP(read_pairs(st, over));
   const int64_t VN = (int64_t)st->V * st->N;
   const int64_t P = (int64_t)st->V * st->W * st->H;
   const void *src = nullptr;
@@ -993,8 +1137,27 @@ hgs_status hgs_type_exchange(hgs_ctx *ctx, int64_t n, float *scales, float *rota
 hgs_status hgs_state_check(hgs_ctx *ctx, hgs_state *st) {
   if (!ctx || !st) return fail(HGS_EINVAL, "NULL argument");
   HGS_HIP(hipSetDevice(ctx->device));
-  HGS_HIP(hipStreamSynchronize(st->stream));
+  bool over = false;
+  HGS_HIP(read_pairs(st, over));
   HGS_HIP(hipGetLastError());
+  if (st->sort_failed) return fail(HGS_EHIP, "a radix sort pass did not complete its look-back");
+  if (over) {
+    // the next render on this context gets room for this pair count
+    const uint64_t need = (uint64_t)st->D_total;
+    if (ctx->pair_cap <= 0)
+      for (Workspace *w : ctx->ws_all) w->pair_cap = std::max<int64_t>(w->pair_cap, grow_cap(need));
+    return fail(HGS_ECAPACITY, "the render produced " + std::to_string(need) +
+                                   " (tile, splat) pairs, more than its capacity of " +
+                                   std::to_string(st->cap) + "; its images are incomplete");
+  }
+  return HGS_OK;
+}
+
+hgs_status hgs_set_pair_capacity(hgs_ctx *ctx, int64_t max_pairs) {
+  if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
+  if (max_pairs < 0 || max_pairs > (int64_t)0xffffffffLL)
+    return fail(HGS_EINVAL, "max_pairs must be in [0, 2^32 - 1]");
+  ctx->pair_cap = max_pairs;
   return HGS_OK;
 }
 

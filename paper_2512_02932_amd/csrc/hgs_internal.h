@@ -8,9 +8,6 @@ namespace hgs {
 
 constexpr int kTile = 16;            // 16x16 pixel tiles
 constexpr int kBlock = 256;          // one thread per pixel of a tile
-constexpr float kAlphaMin = 1.0f / 255.0f;
-constexpr float kAlphaMax = 0.99f;
-constexpr float kTMin = 1e-4f;
 constexpr int kGradSlots = 16;       // per-(view, splat) gradient accumulator
 
 // One view, as the kernels see it.  The float fields are the caller's
@@ -28,11 +25,16 @@ struct DevCam {
   double o[3];          // camera centre, -R^{-1} t
 };
 
+// Render options as the kernels take them.  rr0 is the smallest binary32
+// >= 2 ln(1 / alpha_min) (the radius^2 of the support of an opaque splat),
+// inv_amin = 1 / alpha_min rounded to binary32 (culling bounds only).
 struct DevOpts {
   float bg[3];
   float dilation;
   float lambda_z, theta_z, temp_z;
-  float pad;
+  float alpha_min, alpha_max, t_min;
+  float rr0, inv_amin;
+  uint32_t out_mask;
 };
 
 // Per-(view, splat) record read by the raster kernels: five float4, the
@@ -135,9 +137,17 @@ void launch_gather(const uint32_t *in, const uint32_t *idx, int64_t n, uint32_t 
 // Pairs of the V*N instances taken in the order `order` (a permutation):
 // instance order[j] writes its (global tile id, instance id) pairs at
 // offsets[j], the exclusive scan of tiles[order[.]].
+// Pairs at or past pair_cap are dropped and set *overflow = 1 (overflow may
+// be NULL only if the caller knows the pairs fit).
 void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint32_t *tiles,
-                      const int4 *rect, const DevCam *cams, int V, int64_t N, uint32_t *keys,
-                      uint32_t *vals, hipStream_t s);
+                      const int4 *rect, const DevCam *cams, int V, int64_t N, uint64_t pair_cap,
+                      uint32_t *keys, uint32_t *vals, uint32_t *overflow, hipStream_t s);
+
+// Copies n host cameras to dst through kernel arguments (up to
+// kCamsPerUpload per launch), so that a captured graph carries the camera
+// values themselves rather than a host address.
+constexpr int kCamsPerUpload = 8;
+void launch_upload_cams(const DevCam *host, int n, DevCam *dst, hipStream_t s);
 // The same for a batch of slots, with the instance count on the device.
 // Pairs at or past pair_cap are dropped and set *overflow = 1.
 void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
@@ -147,14 +157,18 @@ void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
                             uint32_t *overflow, hipStream_t s);
 
 // Stable LSD radix sort of n (u32 key, u32 value) pairs on the low `bits`
-// bits, 8 bits per pass.  The first pass reads (k0, v0) (v0 NULL: value =
-// index) and writes (ka, va); later passes ping-pong between (ka, va) and
-// (kb, vb).  k0/v0 may alias kb/vb but not ka/va.  Returns 0 if the result
-// is in (ka, va), 1 if in (kb, vb).  `tmp` holds sort_tmp_bytes(n) bytes.
+// bits (at most 32), 8 bits per pass.  The first pass reads (k0, v0) (v0
+// NULL: value = index) and writes (ka, va); later passes ping-pong between
+// (ka, va) and (kb, vb).  k0/v0 may alias kb/vb but not ka/va.  Returns 0 if
+// the result is in (ka, va), 1 if in (kb, vb).  `tmp` holds
+// sort_tmp_bytes(n) bytes.  If gather_dst is given, the last pass also
+// writes gather_dst[j] = gather_src[value j] of the sorted order.  err (may
+// be NULL): bit 1 is set if a pass's look-back gave up (never expected).
 size_t sort_tmp_bytes(int64_t n);
 int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint32_t *va,
                       uint32_t *kb, uint32_t *vb, int64_t n, int bits, void *tmp, hipStream_t s,
-                      const uint64_t *n_dev = nullptr);
+                      const uint64_t *n_dev = nullptr, const uint32_t *gather_src = nullptr,
+                      uint32_t *gather_dst = nullptr, uint32_t *err = nullptr);
 
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);

@@ -26,7 +26,6 @@ namespace hgs {
 
 namespace {
 
-constexpr float kRR0 = 11.0825272f;     // smallest binary32 >= 2 ln 255
 constexpr float kPad = 1.00390625f;     // 1 + 2^-8
 constexpr double kLog2e = 1.4426950408889634;
 
@@ -45,7 +44,7 @@ struct Structural {
 // ---------------------------------------------------------------------------
 __host__ __device__ Structural structural_f32(const float *m, const float *sc, const float *q,
                                               float al, bool is2d, const DevCam &c,
-                                              float delta) {
+                                              float delta, float amin, float rr0) {
 #pragma clang fp contract(off)
   Structural o;
   o.valid = 0;
@@ -59,7 +58,7 @@ __host__ __device__ Structural structural_f32(const float *m, const float *sc, c
   const float yc = ((V[4] * m[0] + V[5] * m[1]) + V[6] * m[2]) + V[7];
   const float zc = ((V[8] * m[0] + V[9] * m[1]) + V[10] * m[2]) + V[11];
   if (!(zc > c.znear)) return o;
-  if (!(al >= kAlphaMin)) return o;
+  if (!(al >= amin)) return o;
 
   const float qw = q[0], qx = q[1], qy = q[2], qz = q[3];
   const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
@@ -76,7 +75,7 @@ __host__ __device__ Structural structural_f32(const float *m, const float *sc, c
   R[7] = k2 * (qy * qz + qw * qx);
   R[8] = 1.0f - k2 * (qx * qx + qy * qy);
 
-  const float rr = kRR0 + 4.0f * ((al - 1.0f) / (al + 1.0f));
+  const float rr = rr0 + 4.0f * ((al - 1.0f) / (al + 1.0f));
 
   // camera-space scaled axes, column j = R_v (R e_j s_j)
   float C[9];
@@ -413,7 +412,7 @@ __device__ __forceinline__ void preprocess_one(const SceneDev &sc, const DevCam 
   const float4 q4 = reinterpret_cast<const float4 *>(sc.rots)[g];
   const float q[4] = {q4.x, q4.y, q4.z, q4.w};
   const float al = sc.opac[g];
-  const Structural st = structural_f32(m, s, q, al, is2d, c, opt.dilation);
+  const Structural st = structural_f32(m, s, q, al, is2d, c, opt.dilation, opt.alpha_min, opt.rr0);
   tiles[i] = st.valid ? st.tiles : 0u;
   zbits[i] = st.zbits;
   rect[i] = make_int4(st.px0, st.py0, st.px1, st.py1);

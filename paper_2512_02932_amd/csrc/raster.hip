@@ -12,14 +12,15 @@
 // only those records, broadcast from LDS; every lane evaluates the same
 // record at each step, so the 2D/3D branch is wave-uniform.  Skipping a
 // record whose rectangle misses the quadrant changes nothing: the rectangle
-// bounds the support where alpha~ >= 1/255.
+// bounds the support where alpha~ >= alpha_min.
 //
 // Forward (Sec. 3.1, Eq. 1-2): d_i is the Mahalanobis distance under the
 // projected covariance (3D) or u^2 + v^2 at the ray-splat intersection (2D).
-// The contribution is alpha~ = min(0.99, alpha_eff e^{-d/2}).  A pair is
-// skipped when alpha~ < 1/255 (false for NaN).  A pixel stops before the
-// pair that would take its transmittance below 1e-4.  A wave stops when its
-// 64 pixels are done.
+// The contribution is alpha~ = min(alpha_max, alpha_eff e^{-d/2}).  A pair
+// is skipped when alpha~ < alpha_min (false for NaN).  A pixel stops before
+// the pair that would take its transmittance below t_min (defaults 0.99,
+// 1/255 and 1e-4, the thresholds of the rasterizer the paper builds on).
+// A wave stops when its 64 pixels are done.
 //
 // Backward: each pixel walks its list in reverse from its last blended pair.
 // It recovers T_i = T_{i+1} / (1 - alpha~_i) and carries the suffix
@@ -144,9 +145,10 @@ struct ViewOut {
 // of a binary32 evaluation.  If W's interval excludes 0, the exponent
 // e = (U^2 + V^2) / W^2 is at least (min U^2 + min V^2) / max W^2 at every
 // sample, and the record is dropped if that bound exceeds
-// log2(alpha_eff * 255) by a margin.
+// log2(alpha_eff / alpha_min) by a margin.
 __device__ __forceinline__ bool meets_2d(const float4 &r0, const float4 &r1, const float4 &r2,
-                                         const float4 &r3, const float4 &r4, float qx, float qy) {
+                                         const float4 &r3, const float4 &r4, float qx, float qy,
+                                         float inv_amin) {
   const float xa = (qx + 0.5f) - r0.x, xb = (qx + 7.5f) - r0.x;
   const float ya = (qy + 0.5f) - r0.y, yb = (qy + 7.5f) - r0.y;
   const float mx = fmaxf(fabsf(xa), fabsf(xb)), my = fmaxf(fabsf(ya), fabsf(yb));
@@ -169,25 +171,26 @@ __device__ __forceinline__ bool meets_2d(const float4 &r0, const float4 &r1, con
   if (!(wl > 0.0f || wh < 0.0f)) return true;  // W may vanish (or NaN): keep
   const float w2 = fmaxf(wl * wl, wh * wh);
   const float elb = (sqmin(ul, uh) + sqmin(vl, vh)) / w2;
-  const float lim = __builtin_amdgcn_logf(fabsf(r4.w) * 255.0f);
+  const float lim = __builtin_amdgcn_logf(fabsf(r4.w) * inv_amin);
   return !(elb > lim + 1e-3f + 1e-3f * fabsf(lim));
 }
 
-// Can the record reach alpha~ >= 1/255 at a pixel of the quadrant?  Its
+// Can the record reach alpha~ >= alpha_min at a pixel of the quadrant?  Its
 // inclusive pixel rectangle (r0) must meet the quadrant.  For a 3D record
 // the exponent e = A dx^2 + B dx dy + C dy^2 (positive definite) is also
 // minimised over the box spanned by the quadrant's pixel samples (the
 // minimum of a convex quadratic over a box: 0 if the centre is inside, else
 // the least of the four edge minima, each at its clamped stationary point);
 // the record is dropped only if that lower bound of e at every sample
-// exceeds log2(alpha_eff * 255) by more than a margin that covers the
+// exceeds log2(alpha_eff / alpha_min) by more than a margin that covers the
 // rounding of the binary32 evaluation in eval_pair.  Dropping a record that
 // contributes to no pixel of the quadrant changes nothing.
 __device__ __forceinline__ bool meets(const float4 &r0, const float4 &r1, const float4 &r2,
-                                      const float4 &r3, const float4 &r4, const Quad &q) {
+                                      const float4 &r3, const float4 &r4, const Quad &q,
+                                      float inv_amin) {
   const float qx = (float)q.qx, qy = (float)q.qy;
   if (!(r0.x <= qx + 7.0f && r0.z >= qx && r0.y <= qy + 7.0f && r0.w >= qy)) return false;
-  if (__float_as_uint(r4.w) >> 31) return meets_2d(r0, r1, r2, r3, r4, qx, qy);
+  if (__float_as_uint(r4.w) >> 31) return meets_2d(r0, r1, r2, r3, r4, qx, qy, inv_amin);
   const float A = r1.z, B = r1.w, C = r2.x;
   if (!(A > 0.0f && C > 0.0f)) return true;
   // sample box in the record's frame, as eval_pair forms dx, dy
@@ -199,7 +202,7 @@ __device__ __forceinline__ bool meets(const float4 &r0, const float4 &r1, const 
   const float ya = fminf(fmaxf(hC * x0, y0), y1), yb = fminf(fmaxf(hC * x1, y0), y1);
   const float xa = fminf(fmaxf(hA * y0, x0), x1), xb = fminf(fmaxf(hA * y1, x0), x1);
   const float emin = fminf(fminf(at(x0, ya), at(x1, yb)), fminf(at(xa, y0), at(xb, y1)));
-  const float lim = __builtin_amdgcn_logf(fabsf(r4.w) * 255.0f);
+  const float lim = __builtin_amdgcn_logf(fabsf(r4.w) * inv_amin);
   return !(emin > lim + 1e-3f + 1e-4f * fabsf(lim));
 }
 
@@ -231,10 +234,11 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
   const int n = (int)(rg.y - rg.x);
   prio_for_list(n);
 
-  // thr is the activity threshold: 1/255 while the pixel composites, +inf
+  // thr is the activity threshold: alpha_min while the pixel composites, +inf
   // once it has stopped, so one compare gives both tests.
   float T = 1.0f;
-  float thr = q.inside ? kAlphaMin : __builtin_inff();
+  float thr = q.inside ? opt.alpha_min : __builtin_inff();
+  const float amax = opt.alpha_max, tmin = opt.t_min, inv_amin = opt.inv_amin;
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, nx = 0.0f, ny = 0.0f, nz = 0.0f;
   uint32_t cnt = 0, last = 0, wc = 0;
 
@@ -245,7 +249,7 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
   if (kWave + lane < n) nid = vals[rg.x + kWave + lane];
   for (int c = 0; c < n; c += kWave) {
     if (__ballot(thr < 1.0f) == 0ull) break;
-    const bool hit = (c + lane < n) && meets(q0, q1, q2, q3, q4, q);
+    const bool hit = (c + lane < n) && meets(q0, q1, q2, q3, q4, q, inv_amin);
     const uint64_t m = __ballot(hit);
     __syncthreads();  // the previous chunk's slots have been read
     if (hit) {
@@ -291,12 +295,12 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
         }
         const float raw = fabsf(r4.w) * exp2_neg(e);
         // active: raw >= thr (false for NaN).  An inactive pair has a = 0,
-        // so only an active pair can take T below 1e-4 (the stop); the
+        // so only an active pair can take T below t_min (the stop); the
         // weight is 0 unless the pair is blended, and the accumulations run
         // unconditionally (record values are finite, see preprocess).
-        const float a = raw >= thr ? fminf(raw, kAlphaMax) : 0.0f;
+        const float a = raw >= thr ? fminf(raw, amax) : 0.0f;
         const float Tn = T * (1.0f - a);
-        const bool stop = Tn < kTMin;
+        const bool stop = Tn < tmin;
         const float wg = stop ? 0.0f : a * T;
         cr = __builtin_fmaf(wg, r3.y, cr);
         cg = __builtin_fmaf(wg, r3.z, cg);
@@ -611,7 +615,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   }
   if (c > 0) nid = vals[rg.x + c - kWave + lane];
   for (; c >= 0; c -= kWave) {
-    const bool hit = (c + lane < n) && meets(q0, q1, q2, q3, q4, q);
+    const bool hit = (c + lane < n) && meets(q0, q1, q2, q3, q4, q, opt.inv_amin);
     const uint64_t m = __ballot(hit);
     __syncthreads();  // the previous chunk's slots have been read
     if (hit) {
@@ -638,7 +642,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
       const PairEval p = eval_pair(is3d, q.fx, q.fy, r0, r1, r2, r3);
       const float G = exp2_neg(p.e);
       const float raw = fabsf(r4.w) * G;
-      const bool act = (pos < L) && (raw >= kAlphaMin);
+      const bool act = (pos < L) && (raw >= opt.alpha_min);
       if (__ballot(act) == 0ull) continue;
       // Every lane runs the same instructions; an inactive lane's weights
       // (wg, ga, ge) are 0, and a 2D pair's intersection, which can be
@@ -650,8 +654,8 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
         ps.rw = act ? p.rw : 0.0f;
         ps.depth = act ? p.depth : 0.0f;
       }
-      const float a = fminf(raw, kAlphaMax);
-      const bool live = act && !(raw > kAlphaMax);  // not clamped: the exponent's path
+      const float a = fminf(raw, opt.alpha_max);
+      const bool live = act && !(raw > opt.alpha_max);  // not clamped: the exponent's path
       const float Ti = T * __builtin_amdgcn_rcpf(1.0f - a);
       const float wg = act ? a * Ti : 0.0f;
       float g[16];

@@ -30,7 +30,7 @@ constexpr size_t kSlotOffset = 256;
 // Written by the pass and copied back to pinned host memory at its end.
 struct BatchStatus {
   uint64_t pairs;     // D of the batch (exact, also when above capacity)
-  uint32_t overflow;  // 1 if pairs were dropped
+  uint32_t overflow;  // bit 0: pairs were dropped; bit 1: a sort pass failed
   uint32_t pad;
 };
 
@@ -112,14 +112,14 @@ void enqueue_pass(const hgs_server *sv, Lane &L) {
   launch_preprocess_slots(slots, n_slots, n_inst, sv->opt, I, L.rec, L.tiles, L.zbits, L.rect,
                           L.flags, s);
   const int w = launch_radix_sort(L.zbits, nullptr, L.za, L.oa, L.zb, L.ob, I, 32, L.sort_tmp, s,
-                                  n_inst);
+                                  n_inst, L.tiles, L.cnt, &L.status_dev->overflow);
   const uint32_t *order = w ? L.ob : L.oa;
-  launch_gather(L.tiles, order, I, L.cnt, s, n_inst);
   launch_scan(L.cnt, L.offsets, I, pairs, L.scan_tmp, s, n_inst);
   launch_duplicate_slots(order, L.offsets, L.tiles, L.rect, slots, n_slots, I, n_inst,
                          (uint64_t)P, L.kb, L.vb, &L.status_dev->overflow, s);
   const int w2 = launch_radix_sort(L.kb, L.vb, L.ka, L.va, L.kb, L.vb, P, sv->tile_bits,
-                                   L.sort_tmp, s, pairs);
+                                   L.sort_tmp, s, pairs, nullptr, nullptr,
+                                   &L.status_dev->overflow);
   const uint32_t *keys = w2 ? L.kb : L.ka;
   const uint32_t *vals = w2 ? L.vb : L.va;
   launch_ranges(keys, P, L.ranges, s, pairs);
@@ -261,10 +261,10 @@ hgs_status hgs_server_create(hgs_ctx *ctx, const hgs_server_config *cfg, const h
     return fail(HGS_EINVAL,
                 "bad server config (1 <= max_requests <= 4096, 1 <= max_batches <= 16, "
                 "instances and pairs in [1, 2^32), tiles in [1, 2^31))");
-  if (opts && !(opts->dilation >= 0.0f && std::isfinite(opts->dilation) && opts->temp_z > 0.0f &&
-                std::isfinite(opts->lambda_z) && std::isfinite(opts->theta_z) &&
-                std::isfinite(opts->temp_z)))
-    return fail(HGS_EINVAL, "bad opts (dilation >= 0, temp_z > 0, finite)");
+  {
+    const hgs_status os = check_opts(opts);
+    if (os != HGS_OK) return os;
+  }
   HGS_HIP(hipSetDevice(ctx->device));
   hgs_server *sv = new (std::nothrow) hgs_server();
   if (!sv) return fail(HGS_ENOMEM, "host allocation failed");
@@ -311,6 +311,19 @@ hgs_status hgs_server_submit(hgs_server *sv, const hgs_request *req) {
     return fail(HGS_EINVAL, "bad scene id");
   Pending p;
   p.req = *req;
+  {
+    // channels the server's options select (out_mask = 0: the non-NULL ones)
+    const uint32_t mask = sv->opt.out_mask;
+    float **ch[4] = {&p.req.out.rgb, &p.req.out.alpha, &p.req.out.depth, &p.req.out.normal};
+    for (int c = 0; c < 4; ++c) {
+      if (mask == 0u) continue;
+      if (((mask >> c) & 1u) == 0u) {
+        *ch[c] = nullptr;
+      } else if (!*ch[c]) {
+        return fail(HGS_EINVAL, "the server's out_mask selects an output channel whose pointer is NULL");
+      }
+    }
+  }
   std::string why;
   if (!make_dev_cam(req->camera, p.cam, 0, why)) return fail(HGS_EINVAL, why);
   p.n = ctx->scenes[req->scene_id].dev.n;

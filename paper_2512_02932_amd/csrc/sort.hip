@@ -9,15 +9,10 @@
 // equals one stable sort of the 64-bit keys (tile << 32 | depth) of pairs
 // duplicated in index order, with far fewer bits sorted per pair.
 //
-// The radix sort uses 8-bit digits.  A pass is three launches over
-// fixed-size chunks of 4096 pairs:
-//   * a per-chunk digit histogram (LDS atomics);
-//   * an exclusive scan of the histogram table in digit-major order;
-//   * a stable scatter.
-// Within a chunk, elements are ranked in input order 256 at a time.  Each
-// wave64 matches equal digits with 8 ballots, the four waves are combined in
-// LDS, and a running per-digit base carries the count across rounds.
-// Stability across chunks follows from the digit-major scan.
+// The radix sort uses 8-bit digits: one up-front launch counts the digits
+// of every pass, and each pass is a single launch that ranks 4096-key
+// chunks (16 wave64 per chunk, wave ballots for equal digits) and finds
+// each chunk's place by a decoupled look-back over the chunks before it.
 
 #include "hgs_internal.h"
 
@@ -227,17 +222,31 @@ __device__ __forceinline__ void emit_pairs(const DevCam &c, int4 r, uint32_t i, 
     }
 }
 
-// Views of one scene: instance i = view * N + splat.
+// Views of one scene: instance i = view * N + splat.  Pairs at or past
+// `cap` are dropped and raise *overflow.
 __global__ void __launch_bounds__(256)
 duplicate_kernel(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
                  const uint32_t *__restrict__ tiles, const int4 *__restrict__ rect,
-                 const DevCam *__restrict__ cams, int64_t N, int64_t total,
-                 uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+                 const DevCam *__restrict__ cams, int64_t N, int64_t total, uint64_t cap,
+                 uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                 uint32_t *__restrict__ overflow) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= total) return;
   const uint32_t i = order[j];
   if (tiles[i] == 0) return;
-  emit_pairs(cams[i / N], rect[i], i, offsets[j], ~0ull, keys, vals, nullptr);
+  emit_pairs(cams[i / N], rect[i], i, offsets[j], cap, keys, vals, overflow);
+}
+
+struct CamPack {
+  DevCam c[kCamsPerUpload];
+};
+
+__global__ void upload_cams_kernel(CamPack p, int n, DevCam *__restrict__ dst) {
+  // 8-byte words of n cameras (DevCam is 8-byte aligned)
+  constexpr int kWords = (int)(sizeof(DevCam) / 8);
+  static_assert(sizeof(DevCam) % 8 == 0, "DevCam is copied in 8-byte words");
+  for (int k = threadIdx.x; k < n * kWords; k += blockDim.x)
+    reinterpret_cast<uint2 *>(dst)[k] = reinterpret_cast<const uint2 *>(p.c)[k];
 }
 
 // A batch of slots; instance count on the device.  Pairs at or past `cap`
@@ -257,93 +266,206 @@ duplicate_slots_kernel(const uint32_t *__restrict__ order, const uint32_t *__res
   emit_pairs(sl.cam, rect[i], i, offsets[j], cap, keys, vals, overflow);
 }
 
-// ----- radix sort -----
-constexpr int kSortItems = 8;
-// 2048 keys per chunk: the 1M-key depth sort then has 490 blocks, enough
-// to fill the chip (123 us per depth sort at 1M keys, 132 with 4096).
-constexpr int kSortChunk = kBlock * kSortItems;
+// ----- radix sort: one sweep per digit -----
+//
+// An up-front kernel counts the digits of every pass at once (the global
+// digit totals of a pass do not depend on the order the earlier passes
+// leave).  Each pass is then one kernel over chunks of kOsChunk keys.  A
+// chunk takes a ticket from an atomic counter (tickets follow the order in
+// which blocks start, so a chunk only ever waits for chunks that are
+// already running), ranks its keys in input order, publishes its per-digit
+// counts, and looks back over the earlier chunks' published counts (each a
+// 64-bit word: 2 flag bits, aggregate or inclusive prefix, and the value)
+// until it meets an inclusive prefix.  Its keys then go to
+//   global digit offset + prefix of earlier chunks + rank within the chunk.
+// A pass whose digit is the same for every key is the identity and only
+// copies.  Status tables alternate between passes; each chunk clears its
+// row of the other table for the next pass, and the up-front kernel clears
+// the first pass's table.  A look-back that does not complete within a
+// bounded number of waits sets bit 1 of *err and gives up (the order is
+// then wrong but every wave ends).
+constexpr int kOsThreads = 1024;
+constexpr int kOsWaves = kOsThreads / 64;
+constexpr int kOsRows = 4;                        // keys per thread
+constexpr int kOsChunk = kOsThreads * kOsRows;    // 4096 keys per chunk
+constexpr int kMaxPasses = 4;
+constexpr int kOsWords = kMaxPasses * 256 + kMaxPasses + 1;  // hist, tickets, spare
+constexpr size_t kOsHead = 4352;                  // bytes before the status tables
+constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+constexpr int kSpinLimit = 1 << 22;
+constexpr int kOsMaxBlocks = 1024;  // persistent grid of a pass (two per CU and more)
 
-__global__ void __launch_bounds__(256) radix_hist(const uint32_t *__restrict__ keys, int64_t n,
-                                                  const uint64_t *__restrict__ n_dev, int shift,
-                                                  int64_t nb, uint32_t *__restrict__ hist) {
-  __shared__ uint32_t h[256];
+__device__ __forceinline__ int64_t os_chunks(int64_t n) { return (n + kOsChunk - 1) / kOsChunk; }
+
+// Digit counts of all passes (atomics into hist[pass][256], zeroed before),
+// and the first pass's status table cleared.
+__global__ void __launch_bounds__(256)
+radix_hist_all(const uint32_t *__restrict__ keys, int64_t n, const uint64_t *__restrict__ n_dev,
+               int passes, uint32_t *__restrict__ hist, uint64_t *__restrict__ st0) {
+  __shared__ uint32_t h[kMaxPasses][256];
   n = eff_n(n, n_dev);
-  h[threadIdx.x] = 0;
+  for (int k = threadIdx.x; k < kMaxPasses * 256; k += 256) (&h[0][0])[k] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortChunk;
-#pragma unroll
-  for (int k = 0; k < kSortItems; ++k) {
-    const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const uint32_t k = keys[i];
+    for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255u], 1u);
   }
+  const int64_t rows = os_chunks(n) * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < rows; i += stride) st0[i] = 0;
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  for (int p = 0; p < passes; ++p) {
+    const uint32_t c = h[p][threadIdx.x];
+    if (c) atomicAdd(&hist[p * 256 + threadIdx.x], c);
+  }
 }
 
-// Stable scatter of one chunk of kSortChunk pairs: 1024 threads (16 wave64)
-// rank the chunk in kSortChunk / 1024 rounds.  In a round each wave matches
-// equal digits with 8 ballots; a per-digit prefix over the 16 waves (in
-// wave order) and a running per-digit base carry the order across waves
-// and rounds.
-constexpr int kScatterThreads = 1024;
-constexpr int kScatterWaves = kScatterThreads / 64;
-
-__global__ void __launch_bounds__(kScatterThreads)
-radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
-              const uint64_t *__restrict__ n_dev, int shift, int64_t nb,
-              const uint32_t *__restrict__ offs, uint32_t *__restrict__ kout,
-              uint32_t *__restrict__ vout) {
-  __shared__ uint32_t base[256];                  // running count of each digit in this chunk
-  __shared__ uint32_t wcnt[kScatterWaves][256];   // per-wave counts of the current round
-  n = eff_n(n, n_dev);
-  if ((int64_t)blockIdx.x * kSortChunk >= n) return;  // whole block past the end
+// One pass, on a persistent grid: each block takes chunk tickets until they
+// run out.  kIdx: the values are the keys' input indices (no vin).
+// gsrc/gdst (may be NULL): also writes gdst[pos] = gsrc[value].
+template <bool kIdx>
+__global__ void __launch_bounds__(kOsThreads)
+radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
+               const uint64_t *__restrict__ n_dev, int pass, uint32_t *__restrict__ words,
+               uint64_t *__restrict__ st_cur, uint64_t *__restrict__ st_next,
+               uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+               const uint32_t *__restrict__ gsrc, uint32_t *__restrict__ gdst,
+               uint32_t *__restrict__ err) {
+  __shared__ uint32_t s_whist[kOsWaves][256];  // per-wave digit counts, then offsets
+  __shared__ uint32_t s_gex[256];              // global exclusive digit offsets
+  __shared__ uint32_t s_base[256];             // + the earlier chunks of this one
+  __shared__ uint32_t s_wtot[4];
+  __shared__ uint32_t s_ticket;
+  __shared__ int s_trivial;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid < 256) base[tid] = offs[(int64_t)tid * nb + blockIdx.x];
-  const int64_t chunk = (int64_t)blockIdx.x * kSortChunk;
+  const int shift = 8 * pass;
+  n = eff_n(n, n_dev);
+  const int64_t nch = os_chunks(n);
+  if ((int64_t)blockIdx.x >= nch) return;  // more blocks than chunks
+  if (tid == 0) s_trivial = 0;
+  // global exclusive digit offsets of this pass
+  uint32_t g = 0, gx = 0;
+  if (tid < 256) {
+    g = words[pass * 256 + tid];
+    gx = g;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(gx, d, 64);
+      if (lane >= d) gx += y;
+    }
+    if (lane == 63) s_wtot[w] = gx;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    uint32_t off = 0;
+    for (int k = 0; k < w; ++k) off += s_wtot[k];
+    s_gex[tid] = off + gx - g;
+    if ((int64_t)g == n) s_trivial = 1;
+  }
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int k = 0; k < kSortChunk / kScatterThreads; ++k) {
-    const int64_t i = chunk + (int64_t)k * kScatterThreads + tid;
-    const bool ok = i < n;
-    uint32_t key = 0, val = 0;
-    if (ok) {
-      key = kin[i];
-      val = vin ? vin[i] : (uint32_t)i;  // no input values: value = index
-    }
-    const uint32_t d = (key >> shift) & 255u;
-#pragma unroll
-    for (int j = 0; j < kScatterWaves * 256 / kScatterThreads; ++j)
-      (&wcnt[0][0])[j * kScatterThreads + tid] = 0;
+
+  for (;;) {
+    if (tid == 0) s_ticket = atomicAdd(&words[kMaxPasses * 256 + pass], 1u);
+    for (int k = tid; k < kOsWaves * 256; k += kOsThreads) (&s_whist[0][0])[k] = 0;
     __syncthreads();
-    // lanes of this wave with the same digit
-    uint64_t peers = __ballot(ok);
+    const int64_t chunk = (int64_t)s_ticket;
+    if (chunk >= nch) return;  // block-uniform
+    if (tid < 256) st_next[chunk * 256 + tid] = 0;  // the next pass's row
+    const int64_t c0 = chunk * kOsChunk;
+
+    if (s_trivial) {  // one digit for all keys: the identity
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t m = __ballot((d >> b) & 1u);
-      peers &= ((d >> b) & 1u) ? m : ~m;
-    }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-    const uint32_t cnt = (uint32_t)__popcll(peers);
-    const bool leader = ok && (peers >> lane) == 1ull;  // highest lane of its group
-    if (leader) wcnt[w][d] = cnt;
-    __syncthreads();
-    // per digit: exclusive prefix over the waves in order
-    if (tid < 256) {
-      uint32_t b = base[tid];
-#pragma unroll
-      for (int v = 0; v < kScatterWaves; ++v) {
-        const uint32_t c = wcnt[v][tid];
-        wcnt[v][tid] = b;
-        b += c;
+      for (int j = 0; j < kOsRows; ++j) {
+        const int64_t i = c0 + (int64_t)j * kOsThreads + tid;
+        if (i < n) {
+          const uint32_t v = kIdx ? (uint32_t)i : vin[i];
+          kout[i] = kin[i];
+          vout[i] = v;
+          if (gdst) gdst[i] = gsrc[v];
+        }
       }
-      base[tid] = b;
+      __syncthreads();  // s_ticket is read before the next ticket overwrites it
+      continue;
+    }
+
+    // each wave owns 256 consecutive keys, as kOsRows rows of 64
+    const int64_t wb = c0 + (int64_t)w * (64 * kOsRows);
+    uint32_t key[kOsRows], val[kOsRows], rank[kOsRows];
+    bool ok[kOsRows];
+#pragma unroll
+    for (int j = 0; j < kOsRows; ++j) {
+      const int64_t i = wb + (int64_t)j * 64 + lane;
+      ok[j] = i < n;
+      key[j] = ok[j] ? kin[i] : 0u;
+      val[j] = ok[j] ? (kIdx ? (uint32_t)i : vin[i]) : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kOsRows; ++j) {
+      const uint32_t d = (key[j] >> shift) & 255u;
+      uint64_t peers = __ballot(ok[j]);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t m = __ballot((d >> b) & 1u);
+        peers &= ((d >> b) & 1u) ? m : ~m;
+      }
+      const uint32_t prev = ok[j] ? s_whist[w][d] : 0u;
+      rank[j] = prev + (uint32_t)__popcll(peers & lt_mask);
+      // the highest lane of each group advances the wave's count; the reads
+      // above are issued by the whole wave before this write
+      if (ok[j] && (peers >> lane) == 1ull) s_whist[w][d] = prev + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    if (ok) {
-      const uint32_t pos = wcnt[w][d] + rank;
-      kout[pos] = key;
-      vout[pos] = val;
+    if (tid < 256) {
+      uint32_t run = 0;
+#pragma unroll
+      for (int v = 0; v < kOsWaves; ++v) {
+        const uint32_t c = s_whist[v][tid];
+        s_whist[v][tid] = run;
+        run += c;
+      }
+      uint64_t *me = st_cur + chunk * 256 + tid;
+      uint64_t excl = 0;
+      if (chunk == 0) {
+        __hip_atomic_store(me, kFlagInc | (uint64_t)run, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        __hip_atomic_store(me, kFlagAgg | (uint64_t)run, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        int64_t j = chunk - 1;
+        int spins = 0;
+        while (j >= 0) {
+          const uint64_t v = __hip_atomic_load(st_cur + j * 256 + tid, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+          const uint64_t f = v & ~kValMask;
+          if (f == 0) {
+            if (++spins > kSpinLimit) {
+              if (err) atomicOr(err, 2u);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          excl += v & kValMask;
+          if (f == kFlagInc) break;
+          --j;
+        }
+        __hip_atomic_store(me, kFlagInc | (excl + run), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+      s_base[tid] = s_gex[tid] + (uint32_t)excl;
     }
     __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kOsRows; ++j) {
+      if (!ok[j]) continue;
+      const uint32_t d = (key[j] >> shift) & 255u;
+      const uint32_t pos = s_base[d] + s_whist[w][d] + rank[j];
+      kout[pos] = key[j];
+      vout[pos] = val[j];
+      if (gdst) gdst[pos] = gsrc[val[j]];
+    }
+    __syncthreads();  // LDS is read before the next chunk clears it
   }
 }
 
@@ -410,13 +532,22 @@ void launch_gather(const uint32_t *in, const uint32_t *idx, int64_t n, uint32_t 
 }
 
 void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint32_t *tiles,
-                      const int4 *rect, const DevCam *cams, int V, int64_t N, uint32_t *keys,
-                      uint32_t *vals, hipStream_t s) {
+                      const int4 *rect, const DevCam *cams, int V, int64_t N, uint64_t pair_cap,
+                      uint32_t *keys, uint32_t *vals, uint32_t *overflow, hipStream_t s) {
   const int64_t total = (int64_t)V * N;
   if (total == 0) return;
   const int64_t nb = (total + 255) / 256;
   hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)nb), dim3(256), 0, s, order, offsets, tiles,
-                     rect, cams, N, total, keys, vals);
+                     rect, cams, N, total, pair_cap, keys, vals, overflow);
+}
+
+void launch_upload_cams(const DevCam *host, int n, DevCam *dst, hipStream_t s) {
+  for (int b = 0; b < n; b += kCamsPerUpload) {
+    CamPack p;
+    const int m = n - b < kCamsPerUpload ? n - b : kCamsPerUpload;
+    for (int k = 0; k < m; ++k) p.c[k] = host[b + k];
+    hipLaunchKernelGGL(upload_cams_kernel, dim3(1), dim3(256), 0, s, p, m, dst + b);
+  }
 }
 
 void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
@@ -431,32 +562,40 @@ void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
 }
 
 size_t sort_tmp_bytes(int64_t n) {
-  const int64_t nb = (n + kSortChunk - 1) / kSortChunk;
-  const int64_t h = 256 * std::max<int64_t>(nb, 1);
-  return (size_t)(2 * h) * sizeof(uint32_t) + scan_tmp_bytes(h) + 64;
+  const int64_t nch = std::max<int64_t>((n + kOsChunk - 1) / kOsChunk, 1);
+  return kOsHead + (size_t)(2 * nch * 256) * sizeof(uint64_t);
 }
 
 int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint32_t *va,
                       uint32_t *kb, uint32_t *vb, int64_t n, int bits, void *tmp, hipStream_t s,
-                      const uint64_t *n_dev) {
+                      const uint64_t *n_dev, const uint32_t *gather_src, uint32_t *gather_dst,
+                      uint32_t *err) {
   if (n <= 0) return 0;
-  const int64_t nb = (n + kSortChunk - 1) / kSortChunk;
-  const int64_t h = 256 * nb;
-  uint32_t *hist = (uint32_t *)tmp;
-  uint32_t *offs = hist + h;
-  uint64_t *total = (uint64_t *)(offs + h);
-  void *stmp = (void *)(total + 1);
+  const int64_t nch = (n + kOsChunk - 1) / kOsChunk;
+  uint32_t *words = (uint32_t *)tmp;
+  uint64_t *st[2] = {(uint64_t *)((char *)tmp + kOsHead),
+                     (uint64_t *)((char *)tmp + kOsHead) + nch * 256};
+  const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
+  launch_fill_u32(words, 0u, kOsWords, s);
+  const int64_t hb = std::min<int64_t>(std::max<int64_t>(nch, 1), 2048);
+  hipLaunchKernelGGL(radix_hist_all, dim3((unsigned)hb), dim3(256), 0, s, k0, n, n_dev, passes,
+                     words, st[0]);
   const uint32_t *kin = k0, *vin = v0;
   uint32_t *kout = ka, *vout = va;
   int which = 0;
-  const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
   for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
-    hipLaunchKernelGGL(radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n, n_dev, shift,
-                       nb, hist);
-    launch_scan(hist, offs, h, nullptr, stmp, s);
-    hipLaunchKernelGGL(radix_scatter, dim3((unsigned)nb), dim3(kScatterThreads), 0, s, kin, vin, n,
-                       n_dev, shift, nb, (const uint32_t *)offs, kout, vout);
+    const bool lastp = p == passes - 1;
+    const uint32_t *gs = lastp ? gather_src : nullptr;
+    uint32_t *gd = lastp ? gather_dst : nullptr;
+    const unsigned grid = (unsigned)std::min<int64_t>(nch, kOsMaxBlocks);
+    if (vin == nullptr)
+      hipLaunchKernelGGL(radix_onesweep<true>, dim3(grid), dim3(kOsThreads), 0, s, kin,
+                         vin, n, n_dev, p, words, st[p & 1], st[(p + 1) & 1], kout, vout, gs, gd,
+                         err);
+    else
+      hipLaunchKernelGGL(radix_onesweep<false>, dim3(grid), dim3(kOsThreads), 0, s, kin,
+                         vin, n, n_dev, p, words, st[p & 1], st[(p + 1) & 1], kout, vout, gs, gd,
+                         err);
     which = (kout == ka) ? 0 : 1;
     kin = kout;
     vin = vout;

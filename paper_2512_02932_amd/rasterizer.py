@@ -19,7 +19,8 @@ import torch
 from . import _hgs as H
 
 SCENE_KEYS = ("means", "scales", "rotations", "opacities", "sh", "types")
-DEFAULT_OPTS = dict(bg=(0.0, 0.0, 0.0), dilation=0.3, lambda_z=1.0, theta_z=1.05, temp_z=0.001)
+DEFAULT_OPTS = dict(bg=(0.0, 0.0, 0.0), dilation=0.3, lambda_z=1.0, theta_z=1.05, temp_z=0.001,
+                    alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, out_mask=0)
 
 DEBUG = dict(keys=(0, np.uint64, 1), vals=(1, np.uint32, 1), ranges=(2, np.uint32, 2),
              rect=(3, np.int32, 4), tiles=(4, np.uint32, 1), zbits=(5, np.uint32, 1),
@@ -57,8 +58,9 @@ def make_opts(opts: dict | None) -> H.hgs_opts:
     r = H.hgs_opts()
     for i in range(3):
         r.bg[i] = float(o["bg"][i])
-    r.dilation, r.lambda_z, r.theta_z, r.temp_z = (float(o[k]) for k in
-                                                   ("dilation", "lambda_z", "theta_z", "temp_z"))
+    for k in ("dilation", "lambda_z", "theta_z", "temp_z", "alpha_min", "alpha_max", "t_min"):
+        setattr(r, k, float(o[k]))
+    r.out_mask = int(o["out_mask"])
     return r
 
 
@@ -111,6 +113,11 @@ class State:
         out = out[:count]
         return out[:, 0] if width == 1 else out
 
+    def check(self):
+        """Synchronises and raises HGSError (ECAPACITY) if the render
+        produced more pairs than its capacity (``hgs_state_check``)."""
+        H.hgs_state_check(self.rast.ctx, self.handle)
+
     def free(self):
         if self.handle is not None:
             H.hgs_state_free(self.rast.ctx, self.handle)
@@ -137,6 +144,10 @@ class Rasterizer:
         if self.ctx is not None:
             H.hgs_destroy(self.ctx)
             self.ctx = None
+
+    def set_pair_capacity(self, max_pairs: int):
+        """Fixed pair capacity of later renders (0: learned, the default)."""
+        H.hgs_set_pair_capacity(self.ctx, max_pairs)
 
     # ----- scenes -----
     def scene_init(self, scene: dict, copy_resident: bool) -> int:
@@ -330,19 +341,24 @@ def type_exchange(scales: torch.Tensor, rotations: torch.Tensor, types: torch.Te
 
 
 def fdo_cotangents(render_rgb: torch.Tensor, target_rgb: torch.Tensor, lambda_low: float = 0.2,
-                   lambda_high: float = 0.4, losses: torch.Tensor | None = None):
+                   lambda_high: float = 0.4, losses: torch.Tensor | None = None,
+                   grad_low: torch.Tensor | None = None, grad_high: torch.Tensor | None = None):
     """Frequency losses and weighted cotangents (``hgs_fdo_cotangents``).
     render_rgb, target_rgb: float32 [V, 3, H, W] on one device.  Returns
     (grad_low, grad_high, losses) with losses a float64 [2] device tensor
-    (L_low, L_high) that the call adds into."""
+    (L_low, L_high) that the call adds into; grad_low / grad_high may be
+    given (shaped like the images) to receive the cotangents."""
     if render_rgb.shape != target_rgb.shape or render_rgb.dim() != 4 or render_rgb.shape[1] != 3:
         raise ValueError("render_rgb and target_rgb must both be [V, 3, H, W]")
     for t in (render_rgb, target_rgb):
         if t.dtype != torch.float32 or not t.is_contiguous():
             raise ValueError("images must be contiguous float32")
     V, _, Hh, Ww = render_rgb.shape
-    g_low = torch.empty_like(render_rgb)
-    g_high = torch.empty_like(render_rgb)
+    g_low = torch.empty_like(render_rgb) if grad_low is None else grad_low
+    g_high = torch.empty_like(render_rgb) if grad_high is None else grad_high
+    for t in (g_low, g_high):
+        if t.shape != render_rgb.shape or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("grad_low / grad_high must be contiguous float32 like the images")
     if losses is None:
         losses = torch.zeros(2, dtype=torch.float64, device=render_rgb.device)
     rast = get_rasterizer(render_rgb.device)

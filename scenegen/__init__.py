@@ -305,17 +305,25 @@ def crop_camera(cam, x0, y0, width, height):
 
 
 def fd_subset(seed=33, n_each=32, crop=32):
-    """Finite-difference workload: a 32x32 window at the centre of the
-    torus-knot camera, keeping the 32 surfels and 32 3D Gaussians whose
-    centres lie at the smallest angle from the optical axis (the axis passes
-    through the window centre).  Selection only; no rendering arithmetic."""
+    """Finite-difference workload: a 32x32 window of the torus-knot camera
+    centred on the image of the knot's curve point at phi = 0, keeping the
+    32 surfels and 32 3D Gaussians whose projected centres are nearest the
+    window centre.  (The knot winds around the optical axis, so a window at
+    the image centre would see nothing.)  Selection only; no rendering
+    arithmetic."""
     scene = scene_torus_knot(n=200_000, seed=seed)
     cam = camera_torus_knot()
-    x0 = int(cam["cx"]) - crop // 2
-    y0 = int(cam["cy"]) - crop // 2
     V = cam["viewmat"].astype(np.float64)
+    c0 = torus_knot_points(np.zeros(1), np.zeros(1), tube=0.0)[0][0]
+    p0 = V[:3, :3] @ c0 + V[:3, 3]
+    u0 = cam["fx"] * p0[0] / p0[2] + cam["cx"]
+    v0 = cam["fy"] * p0[1] / p0[2] + cam["cy"]
+    x0 = int(round(u0)) - crop // 2
+    y0 = int(round(v0)) - crop // 2
     pc = scene["means"].astype(np.float64) @ V[:3, :3].T + V[:3, 3]
-    dist = (pc[:, 0] ** 2 + pc[:, 1] ** 2) / pc[:, 2] ** 2
+    u = cam["fx"] * pc[:, 0] / pc[:, 2] + cam["cx"]
+    v = cam["fy"] * pc[:, 1] / pc[:, 2] + cam["cy"]
+    dist = (u - (x0 + crop / 2)) ** 2 + (v - (y0 + crop / 2)) ** 2
     pick = []
     for t in (0, 1):
         cand = np.nonzero(scene["types"] == t)[0]

@@ -1,5 +1,6 @@
 """Shared helpers of the GPU parity tests: run the HIP path through the C ABI
 and the oracle on the same seeded inputs, and compare."""
+import os
 import sys
 
 import numpy as np
@@ -16,8 +17,14 @@ MAX_TIE_BITS = 4    # branches tried per tie pixel: 2^4 outcome combinations
 
 
 def say(*a):
+    """Prints a progress or report line; with HGS_PARITY_LOG set, also
+    appends it to that file (the parity summary of a run)."""
     print(*a, flush=True)
     sys.stdout.flush()
+    path = os.environ.get("HGS_PARITY_LOG")
+    if path:
+        with open(path, "a") as f:
+            f.write(" ".join(str(x) for x in a) + "\n")
 
 
 def gpu_render(scene_np, cams, opts=None, G=None, want_state=True):
@@ -27,6 +34,8 @@ def gpu_render(scene_np, cams, opts=None, G=None, want_state=True):
     rast = get_rasterizer(0)
     sc = to_device(scene_np, "cuda")
     images, state = rast.render(sc, cams, opts, want_state=want_state)
+    if state is not None:
+        state.check()  # the pairs fit the capacity: the images are complete
     grads = None
     if G is not None:
         gi = {k: torch.from_numpy(np.ascontiguousarray(G[k], np.float32)).cuda() for k in IMG_KEYS}

@@ -42,3 +42,28 @@ def rel_l2(g, ref):
     ref = np.asarray(ref, np.float64)
     den = np.linalg.norm(ref)
     return float(np.linalg.norm(np.asarray(g, np.float64) - ref) / (den if den > 0 else 1.0))
+
+
+def central_fd(loss, base, key, g, j, ref_counts):
+    """Fourth-order central difference of loss(params) with respect to
+    base[key][g, j] at two step sizes, h and 2h with h = 1e-5 max(|x|, 1e-2):
+    (-L(x+2h) + 8 L(x+h) - 8 L(x-h) + L(x-2h)) / 12h.  loss(params) returns
+    (value, record); ref_counts(record) must equal ref_counts at the
+    unperturbed point at every evaluation, else the coordinate crosses a
+    discrete decision and None is returned.  Returns (fd_h, fd_2h)."""
+    n = base[key].shape[0]
+    x0 = float(base[key].reshape(n, -1)[g, j])
+    h = 1e-5 * max(abs(x0), 1e-2)
+    vals = {}
+    for m in (-4, -2, -1, 1, 2, 4):
+        p = {k: v.copy() for k, v in base.items()}
+        p[key].reshape(n, -1)[g, j] = x0 + m * h
+        val, rec = loss(p)
+        if not ref_counts(rec):
+            return None
+        vals[m] = val
+
+    def stencil(s):
+        return (-vals[2 * s] + 8 * vals[s] - 8 * vals[-s] + vals[-2 * s]) / (12 * s * h)
+
+    return stencil(1), stencil(2)

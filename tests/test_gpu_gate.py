@@ -25,7 +25,7 @@ import scenegen as sg
 from gpu_common import (IMG_KEYS, PARAM_KEYS, GRAD_COND, GRAD_RTOL, compare_grads,
                         compare_images, compare_structural, gpu_render, oracle_pixels, pack_G_all,
                         say)
-from helpers import axis_camera, make_scene
+from helpers import axis_camera, central_fd, make_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -133,15 +133,18 @@ def test_edge_on_surfel_vanishes_on_gpu():
 
 def test_fd_subset_through_hip():
     """The torus-knot workload's finite-difference subset (64 Gaussians, 32x32
-    crop): the GPU against the oracle's analytic gradient, and against binary64
-    central differences of the oracle forward (h = 1e-6 relative), on the
-    coordinates whose perturbation changes no per-pixel decision."""
+    window on the knot): the GPU against the oracle's analytic gradient, and
+    against binary64 fourth-order central differences of the oracle forward
+    (two step sizes), on the coordinates whose perturbation changes no
+    per-pixel decision."""
     import oracle
     sc, cam = sg.fd_subset()
     pix = oracle_pixels(cam)
     G = sg.upstream_grads(1, cam["height"], cam["width"], seed=3)
     imgs, state, grads = gpu_render(sc, cam, G=G)
     res = oracle.forward(sc, cam, pix)
+    # the window sees the knot
+    assert float(imgs["alpha"].mean()) > 0.3 and int(res["n_contrib"].sum()) > 5000
     compare_structural(state, sc, cam)
     _, flip, rep = compare_images(imgs, state, res, pix, sc, cam)
     Gp = pack_G_all(G, pix)
@@ -158,34 +161,30 @@ def test_fd_subset_through_hip():
         return float((r["out"] * Gp).sum()), r
 
     _, r0 = loss(base)
+    same = lambda r: (np.array_equal(r["n_contrib"], r0["n_contrib"]) and
+                      np.array_equal(r["tie"], r0["tie"]))
     rng = np.random.default_rng(4)
     coords = [(k, int(gi), int(j)) for k, w in (("means", 3), ("scales", 3), ("rotations", 4),
                                                ("opacities", 1))
               for gi, j in zip(rng.integers(0, n, 40), rng.integers(0, w, 40))]
     coords += [("sh", int(gi), int(j)) for gi, j in zip(rng.integers(0, n, 30),
                                                         rng.integers(0, sc["sh"].shape[1] * 3, 30))]
-    checked = skipped = 0
+    checked = skipped = live = 0
     for k, gi, j in coords:
-        p = {kk: vv.copy() for kk, vv in base.items()}
-        arr = p[k].reshape(n, -1)
-        x0 = arr[gi, j]
-        h = 1e-6 * max(abs(x0), 1e-2)
-        arr[gi, j] = x0 + h
-        lp, rp = loss(p)
-        arr[gi, j] = x0 - h
-        lm, rm = loss(p)
-        if not all(np.array_equal(r["n_contrib"], r0["n_contrib"]) and
-                   np.array_equal(r["tie"], r0["tie"]) for r in (rp, rm)):
+        fds = central_fd(loss, base, k, gi, j, same)
+        if fds is None:
             skipped += 1
             continue
-        fd = (lp - lm) / (2 * h)
+        fd, fd2 = fds
         got = float(grads[k].reshape(n, -1)[gi, j])
         tol = (GRAD_RTOL * (abs(fd) + ref[k + "_abs"].reshape(n, -1)[gi, j]) +
-               GRAD_COND * ref[k + "_cond"].reshape(n, -1)[gi, j] + 1e-7)
+               GRAD_COND * ref[k + "_cond"].reshape(n, -1)[gi, j] + 2 * abs(fd - fd2) + 1e-7)
         assert abs(got - fd) <= tol, (k, gi, j, got, fd, tol)
         checked += 1
-    say(f"[fd-subset] GPU vs central differences: {checked} coordinates, {skipped} skipped")
-    assert checked >= 150
+        live += abs(fd) > 1e-3
+    say(f"[fd-subset] GPU vs central differences: {checked} coordinates ({live} with |dL/dx| > "
+        f"1e-3), {skipped} skipped")
+    assert checked >= 150 and live >= 100
 
 
 def test_train_step_moves_surfel_sz_through_gate():
@@ -248,7 +247,8 @@ def test_train_step_moves_surfel_sz_through_gate():
     sure = finite_z & (np.abs(rz) > tol)
     assert sure.sum() >= 30, int(sure.sum())
     np.testing.assert_allclose(new_sz[sure], r_raw["scales"][sure, 2], rtol=0, atol=1e-6)
-    moved = np.abs(new_sz - raw["scales"][:, 2]) > 1e-3
+    with np.errstate(invalid="ignore"):  # -inf - -inf where s_z = 0
+        moved = np.abs(new_sz - raw["scales"][:, 2]) > 1e-3
     assert (moved & finite_z).sum() >= 30
     say(f"[train-gate] s_z moved by Adam for {int((moved & finite_z).sum())} surfels "
         f"({int(sure.sum())} compared with the oracle)")
