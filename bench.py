@@ -391,7 +391,11 @@ def render_leg(rast, name, steps, warmup):
     torch.cuda.synchronize()
     # work accounting of this workload (identical every step), and a check
     # that the pairs fit the render's capacity
+    from paper_2512_02932_amd import _hgs
+    _hgs.hgs_profile_enable(rast.ctx, True)  # the forward records its pair counts
     _, st = rast.render(sc, cams, images=images, want_state=True)
+    _hgs.hgs_profile_enable(rast.ctx, False)
+    _hgs.hgs_profile_read(rast.ctx, reset=True)
     st.check()
     counts = pair_counts(st)
     sizes = st.sizes()

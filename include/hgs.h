@@ -223,7 +223,9 @@ hgs_status hgs_state_sizes(hgs_ctx *ctx, hgs_state *state, int64_t *sizes5 /* [h
  *   8 n_contrib     u32[V,H,W]
  *   9 pair counts   u32[V,H,W]  (bits 0-14 blended 3D pairs, 15-29 blended
  *                               2D pairs, bit 30 the pair that stopped the
- *                               pixel was 2D, bit 31 the pixel stopped)
+ *                               pixel was 2D, bit 31 the pixel stopped;
+ *                               recorded only by a render made while
+ *                               profiling is enabled, else EINVAL)
  * `capacity` is the size of dst in bytes.  The call synchronises. */
 hgs_status hgs_state_debug(hgs_ctx *ctx, hgs_state *state, int32_t what, void *dst_host,
                            int64_t capacity);

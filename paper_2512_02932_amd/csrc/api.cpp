@@ -46,6 +46,8 @@ struct hgs_state {
   int64_t cap = 0;               // pair capacity of this render
   bool overflowed = false;
   bool sort_failed = false;      // a radix pass's look-back gave up (never expected)
+  bool has_wcount = false;       // the forward recorded the pair counts (profiling on)
+  uint64_t *bmask = nullptr;  // blend masks of the forward (raster_mask_words)
   uint32_t *keys = nullptr;  // tile id of each sorted pair
   uint32_t *vals = nullptr;  // instance id (view * N + splat) of each sorted pair
   uint2 *ranges = nullptr;
@@ -639,6 +641,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc_t(st, &kb, (size_t)cap));
   ST_HIP(dalloc_t(st, &vb, (size_t)cap));
   ST_HIP(dalloc(st, &sort_tmp, sort_tmp_bytes(cap)));
+  ST_HIP(dalloc_t(st, &st->bmask, (size_t)raster_mask_words(cap, n_tiles)));
   ST_HIP(commit(st, 1, st->stream, cap_mode));
   {
     StageTimer t(ctx, HGS_STAGE_DUPLICATE, st->stream);
@@ -663,11 +666,12 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ro.T_final = st->T_final;
   ro.last = st->last;
   ro.n_contrib = st->n_contrib;
-  ro.wcount = st->wcount;
+  ro.wcount = ctx->profile ? st->wcount : nullptr;  // work accounting while profiling
+  st->has_wcount = ctx->profile;
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_FWD, st->stream);
     launch_raster_fwd(st->ranges, st->vals, st->rec, st->cams, n_views, st->n_tiles, W, H,
-                      st->tiles_x, st->tiles_per_view, st->opt, ro, st->stream);
+                      st->tiles_x, st->tiles_per_view, st->opt, ro, st->bmask, st->stream);
   }
   if (!cap_mode && ctx->pair_cap <= 0) {
     // the pair count and overflow flag of this render, for the next render
@@ -740,7 +744,8 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_image
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_BWD, s);
     launch_raster_bwd(st->ranges, st->vals, st->rec, st->n_tiles, st->W, st->H, st->tiles_x,
-                      st->tiles_per_view, st->opt, st->T_final, st->last, gi, accum, s);
+                      st->tiles_per_view, st->opt, st->T_final, st->last, st->bmask, gi, accum,
+                      s);
   }
   st->accum_last = accum;
   st->accum_planes = 1;
@@ -826,8 +831,8 @@ hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *st, const hgs_grad_i
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_BWD, s);
     launch_raster_bwd_sets(st->ranges, st->vals, st->rec, st->n_tiles, st->W, st->H, st->tiles_x,
-                           st->tiles_per_view, st->opt, st->T_final, st->last, gi, x, accum, plane,
-                           s);
+                           st->tiles_per_view, st->opt, st->T_final, st->last, st->bmask, gi, x,
+                           accum, plane, s);
   }
   st->accum_last = accum;
   st->accum_planes = 3;
@@ -1108,7 +1113,13 @@ hgs_status hgs_state_debug(hgs_ctx *ctx, hgs_state *st, int32_t what, void *dst,
     case 6: src = st->T_final; bytes = P * 4; break;
     case 7: src = st->last; bytes = P * 4; break;
     case 8: src = st->n_contrib; bytes = P * 4; break;
-    case 9: src = st->wcount; bytes = P * 4; break;
+    case 9:
+      if (!st->has_wcount)
+        return fail(HGS_EINVAL, "pair counts are recorded only by renders made while profiling "
+                                "is enabled (hgs_profile_enable)");
+      src = st->wcount;
+      bytes = P * 4;
+      break;
     default: return fail(HGS_EINVAL, "unknown debug array");
   }
   if (bytes > cap) return fail(HGS_EINVAL, "destination too small");

@@ -185,10 +185,15 @@ struct RasterOut {
   // stopping pair was 2D, bit 31 the pixel stopped (work accounting)
   uint32_t *wcount;
 };
+// bmask (may be NULL): receives the blend masks the backward walks,
+// raster_mask_words(D capacity, tiles) 64-bit words.
+inline int64_t raster_mask_words(int64_t pairs, int64_t tiles) {
+  return 4 * ((pairs >> 6) + tiles + 1);
+}
 void launch_raster_fwd(const uint2 *ranges, const uint32_t *vals, const Record *rec,
                        const DevCam *cams, int V, int n_tiles_total, int W, int H,
                        int tiles_x, int tiles_per_view, DevOpts opt, RasterOut out,
-                       hipStream_t s);
+                       uint64_t *bmask, hipStream_t s);
 
 // Forward of a batch of slots on a persistent grid of n_blocks wave64s
 // that pull (tile, quadrant) units from *queue (zero at launch) up to the
@@ -203,7 +208,7 @@ struct RasterGradIn {
 void launch_raster_bwd(const uint2 *ranges, const uint32_t *vals, const Record *rec,
                        int n_tiles_total, int W, int H, int tiles_x, int tiles_per_view,
                        DevOpts opt, const float *T_final, const uint32_t *last,
-                       RasterGradIn g, float *accum, hipStream_t s);
+                       const uint64_t *bmask, RasterGradIn g, float *accum, hipStream_t s);
 // Two RGB-only cotangent images [V,3,H,W] (NULL = zero).
 struct RgbSets {
   const float *rgb[2];
@@ -213,8 +218,8 @@ struct RgbSets {
 void launch_raster_bwd_sets(const uint2 *ranges, const uint32_t *vals, const Record *rec,
                             int n_tiles_total, int W, int H, int tiles_x, int tiles_per_view,
                             DevOpts opt, const float *T_final, const uint32_t *last,
-                            RasterGradIn g, RgbSets rgb2, float *accum, int64_t plane,
-                            hipStream_t s);
+                            const uint64_t *bmask, RasterGradIn g, RgbSets rgb2, float *accum,
+                            int64_t plane, hipStream_t s);
 
 // Adaptive Type Exchange in place on n primitives (rotations: float4 per
 // primitive, 16-byte aligned).  counts (may be NULL): [0] += switched 3D->2D,

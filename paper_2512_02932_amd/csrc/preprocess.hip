@@ -502,16 +502,20 @@ preprocess_slots_kernel(const Slot *__restrict__ slots, const int *__restrict__ 
                         Record *__restrict__ rec, uint32_t *__restrict__ tiles,
                         uint32_t *__restrict__ zbits, int4 *__restrict__ rect,
                         uint8_t *__restrict__ flags) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int ns = *n_slots;
-  if (ns <= 0 || i >= inst_cap || (uint64_t)i >= *n_inst) return;
-  const Slot &sl = slots[slot_of_instance(slots, ns, i)];
-  const int64_t g = i - sl.inst_base;
-  switch (sl.scene.sh_degree) {
-    case 0: preprocess_one<0>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
-    case 1: preprocess_one<1>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
-    case 2: preprocess_one<2>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
-    default: preprocess_one<3>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
+  const uint64_t cnt = *n_inst < (uint64_t)inst_cap ? *n_inst : (uint64_t)inst_cap;
+  if (ns <= 0) return;
+  // grid-stride: the grid is sized for a typical batch, not the capacity
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; (uint64_t)i < cnt;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const Slot &sl = slots[slot_of_instance(slots, ns, i)];
+    const int64_t g = i - sl.inst_base;
+    switch (sl.scene.sh_degree) {
+      case 0: preprocess_one<0>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
+      case 1: preprocess_one<1>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
+      case 2: preprocess_one<2>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
+      default: preprocess_one<3>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
+    }
   }
 }
 
@@ -1010,8 +1014,9 @@ void launch_preprocess_slots(const Slot *slots, const int *n_slots, const uint64
                              DevOpts opt, int64_t inst_cap, Record *rec, uint32_t *tiles,
                              uint32_t *zbits, int4 *rect, uint8_t *flags, hipStream_t s) {
   if (inst_cap <= 0) return;
-  hipLaunchKernelGGL(preprocess_slots_kernel, dim3((unsigned)((inst_cap + 255) / 256)), dim3(256),
-                     0, s, slots, n_slots, n_inst, opt, inst_cap, rec, tiles, zbits, rect, flags);
+  const int64_t blocks = std::min<int64_t>((inst_cap + 255) / 256, 4096);
+  hipLaunchKernelGGL(preprocess_slots_kernel, dim3((unsigned)blocks), dim3(256), 0, s, slots,
+                     n_slots, n_inst, opt, inst_cap, rec, tiles, zbits, rect, flags);
 }
 
 #define HGS_BY_DEGREE(deg, CALL) \

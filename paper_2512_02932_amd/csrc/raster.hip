@@ -101,6 +101,7 @@ __device__ __forceinline__ float exp2_neg(float e) { return __builtin_amdgcn_exp
 struct Quad {
   int tile;
   int v;           // view
+  int quad;        // 0..3: (x half, y half) of the tile
   int qx, qy;      // top-left pixel of the quadrant
   int px, py;      // this lane's pixel
   float fx, fy;    // pixel sample (x + 1/2, y + 1/2)
@@ -113,6 +114,7 @@ __device__ __forceinline__ Quad make_quad(int tile, int v, int r, int quad, int 
   Quad q;
   q.tile = tile;
   q.v = v;
+  q.quad = quad;
   const int ty = r / tiles_x;
   const int tx = r - ty * tiles_x;
   q.qx = tx * kTile + (quad & 1) * 8;
@@ -131,6 +133,22 @@ __device__ __forceinline__ Quad quad_of(int W, int H, int tiles_x, int tiles_per
   const int tile = (b >> 5) * 8 + (b & 7);
   const int v = tile / tiles_per_view;
   return make_quad(tile, v, tile - v * tiles_per_view, (b >> 3) & 3, W, H, tiles_x);
+}
+
+// Blend masks: for each quadrant wave, one 64-bit word per chunk of 64
+// positions of its tile's pair list, bit j set if the pair at position
+// 64 c + j was blended at one or more of the quadrant's pixels.  The forward
+// writes them and the backward walks only those pairs (a pair blended at no
+// pixel of the quadrant contributes nothing to its gradients).  Tile t with
+// pair range [a, a + n) owns the words [4 (a / 64 + t), 4 (a / 64 + t) +
+// 4 ceil(n / 64)), quadrant q the q-th run of ceil(n / 64): since
+// floor(a / 64) + floor(n / 64) <= floor((a + n) / 64), the regions of
+// consecutive tiles never overlap, and all fit in 4 (D / 64 + T + 1) words.
+__device__ __forceinline__ uint64_t *quad_mask_words(uint64_t *bmask, uint2 rg, int tile,
+                                                     int quad) {
+  const uint32_t n = rg.y - rg.x;
+  const uint64_t base = 4ull * ((uint64_t)(rg.x >> 6) + (uint64_t)tile);
+  return bmask + base + (uint64_t)quad * ((n + 63u) >> 6);
 }
 
 // Output images of one view: channel planes of H*W pixels (NULL: skip).
@@ -226,10 +244,13 @@ __device__ __forceinline__ bool is3d_of(const float4 &r4) {
 }
 
 // Composites one quadrant: the wave's 64 pixels over the tile's pair range.
+// kAcct: also count blended pairs by type for the work accounting (wcount).
+template <bool kAcct>
 __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const uint32_t *vals,
                                                 const Record *rec, int W, int H,
                                                 const DevOpts &opt, const ViewOut &out,
-                                                float4 (*srec)[kWave], uint32_t *spos) {
+                                                uint64_t *wm, float4 (*srec)[kWave],
+                                                uint32_t *spos) {
   const int lane = threadIdx.x;
   const int n = (int)(rg.y - rg.x);
   prio_for_list(n);
@@ -239,6 +260,7 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
   float T = 1.0f;
   float thr = q.inside ? opt.alpha_min : __builtin_inff();
   const float amax = opt.alpha_max, tmin = opt.t_min, inv_amin = opt.inv_amin;
+  int lastk = -1;  // compacted slot of this lane's last blended pair in the chunk
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, nx = 0.0f, ny = 0.0f, nz = 0.0f;
   uint32_t cnt = 0, last = 0, wc = 0;
 
@@ -265,6 +287,7 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
     if (c + kWave + lane < n) HGS_FETCH(rec, nid, q0, q1, q2, q3, q4);
     if (c + 2 * kWave + lane < n) nid = vals[rg.x + c + 2 * kWave + lane];
     const int k_end = __popcll(m);
+    uint64_t used = 0;  // compacted slots blended at one or more lanes
     for (int k0 = 0; k0 < k_end; k0 += 2) {
       if (__ballot(thr < 1.0f) == 0ull) break;
 #pragma unroll
@@ -273,7 +296,6 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
         if (k >= k_end) break;
         const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
                      r4 = srec[4][k];
-        const uint32_t pos = spos[k];
         // both exponent forms, then a select on the type: no branch
         const bool two = __float_as_int(r4.w) < 0;
         float e, d;
@@ -298,7 +320,9 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
         // so only an active pair can take T below t_min (the stop); the
         // weight is 0 unless the pair is blended, and the accumulations run
         // unconditionally (record values are finite, see preprocess).
-        const float a = raw >= thr ? fminf(raw, amax) : 0.0f;
+        // min(raw, alpha_max) as a select: equal to fminf for numbers, and
+        // raw >= thr is false for NaN
+        const float a = raw >= thr ? (raw < amax ? raw : amax) : 0.0f;
         const float Tn = T * (1.0f - a);
         const bool stop = Tn < tmin;
         const float wg = stop ? 0.0f : a * T;
@@ -310,13 +334,22 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
         ny = __builtin_fmaf(wg, r4.y, ny);
         nz = __builtin_fmaf(wg, r4.z, nz);
         const bool bl = wg > 0.0f;
+        used |= (__ballot(bl) != 0ull) ? (1ull << k) : 0ull;
         cnt += bl ? 1u : 0u;
-        wc += bl ? (two ? (1u << 15) : 1u) : 0u;
-        last = bl ? pos + 1u : last;
-        wc |= stop ? (0x80000000u | (two ? 0x40000000u : 0u)) : 0u;
+        lastk = bl ? k : lastk;
+        if constexpr (kAcct) {
+          wc += bl ? (two ? (1u << 15) : 1u) : 0u;
+          wc |= stop ? (0x80000000u | (two ? 0x40000000u : 0u)) : 0u;
+        }
         thr = stop ? __builtin_inff() : thr;
         T = stop ? T : Tn;
       }
+    }
+    if (lastk >= 0) last = spos[lastk] + 1u;
+    lastk = -1;
+    if (wm) {  // the chunk's positions blended in this quadrant
+      const uint64_t pm = __ballot(hit && ((used >> lane_rank(m)) & 1ull));
+      if (lane == 0) wm[c >> 6] = pm;
     }
   }
   if (!q.inside) return;
@@ -338,14 +371,15 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
   if (out.T_final) out.T_final[o1] = T;
   if (out.last) out.last[o1] = last;
   if (out.n_contrib) out.n_contrib[o1] = cnt;
-  if (out.wcount) out.wcount[o1] = wc;
+  if (kAcct && out.wcount) out.wcount[o1] = wc;
 }
 
 // Views of one size: the block id picks the tile and quadrant (quad_of).
+template <bool kAcct>
 __global__ void __launch_bounds__(kWave)
 raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
                   const Record *__restrict__ rec, int n_tiles, int W, int H, int tiles_x,
-                  int tiles_per_view, DevOpts opt, RasterOut out) {
+                  int tiles_per_view, DevOpts opt, RasterOut out, uint64_t *__restrict__ bmask) {
   __shared__ float4 srec[5][kWave];
   __shared__ uint32_t spos[kWave];
   const Quad q = quad_of(W, H, tiles_x, tiles_per_view);
@@ -360,7 +394,10 @@ raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   vo.last = out.last ? out.last + v * hw : nullptr;
   vo.n_contrib = out.n_contrib ? out.n_contrib + v * hw : nullptr;
   vo.wcount = out.wcount ? out.wcount + v * hw : nullptr;
-  raster_fwd_quad(q, ranges[q.tile], vals, rec, W, H, opt, vo, srec, spos);
+  const uint2 rg = ranges[q.tile];
+  raster_fwd_quad<kAcct>(q, rg, vals, rec, W, H, opt, vo,
+                         bmask ? quad_mask_words(bmask, rg, q.tile, q.quad) : nullptr, srec,
+                         spos);
 }
 
 // A batch of slots (requests of any size), persistent: each wave takes
@@ -392,7 +429,7 @@ raster_fwd_queue_kernel(const uint2 *__restrict__ ranges, const uint32_t *__rest
     vo.alpha = sl.alpha;
     vo.depth = sl.depth;
     vo.normal = sl.normal;
-    raster_fwd_quad(q, ranges[tile], vals, rec, W, H, opt, vo, srec, spos);
+    raster_fwd_quad<false>(q, ranges[tile], vals, rec, W, H, opt, vo, nullptr, srec, spos);
     __syncthreads();  // the unit's LDS slots are free before the next unit
   }
 }
@@ -532,7 +569,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
                   const Record *__restrict__ rec, int n_tiles, int W, int H, int tiles_x,
                   int tiles_per_view, DevOpts opt, const float *__restrict__ T_final,
                   const uint32_t *__restrict__ last_in, RasterGradIn gin, RgbSets rgb2,
-                  float *__restrict__ accum, int64_t plane) {
+                  float *__restrict__ accum, int64_t plane, const uint64_t *__restrict__ bmask) {
   __shared__ float4 srec[5][kWave];
   __shared__ uint32_t sid[kWave];
   __shared__ uint32_t spos[kWave];
@@ -603,19 +640,22 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
                         : vidx <= 14 ? PackDst{2, vidx - 2}
                                      : PackDst{0, -1};
 
-  // chunks of 64 list positions in reverse; the first is the ragged one.
-  // Pipeline: records of chunk c in q0..q4 (entry id), entry of chunk c - 64
-  // in nid.
+  // chunks of 64 list positions in reverse, the first the ragged one; only
+  // the positions the forward blended in this quadrant (its blend mask).
+  // Pipeline: records of chunk c in q0..q4 (entry id), entries of chunk
+  // c - 64 in nid.
+  const uint64_t *wm = quad_mask_words(const_cast<uint64_t *>(bmask), rg, q.tile, q.quad);
   float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0, q4 = q0;
   uint32_t id = 0, nid = 0;
   int c = (n - 1) & ~(kWave - 1);
-  if (c + lane < n) {
+  bool hit = (c + lane < n) && ((wm[c >> 6] >> lane) & 1ull);
+  if (hit) {
     id = vals[rg.x + c + lane];
     HGS_FETCH(rec, id, q0, q1, q2, q3, q4);
   }
-  if (c > 0) nid = vals[rg.x + c - kWave + lane];
+  bool hit_n = c > 0 && ((wm[(c >> 6) - 1] >> lane) & 1ull);
+  if (hit_n) nid = vals[rg.x + c - kWave + lane];
   for (; c >= 0; c -= kWave) {
-    const bool hit = (c + lane < n) && meets(q0, q1, q2, q3, q4, q, opt.inv_amin);
     const uint64_t m = __ballot(hit);
     __syncthreads();  // the previous chunk's slots have been read
     if (hit) {
@@ -630,9 +670,11 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
     }
     __syncthreads();
     if (c > 0) {  // earlier chunks: every position is below n
+      hit = hit_n;
       id = nid;
-      HGS_FETCH(rec, id, q0, q1, q2, q3, q4);
-      if (c > kWave) nid = vals[rg.x + c - 2 * kWave + lane];
+      if (hit) HGS_FETCH(rec, id, q0, q1, q2, q3, q4);
+      hit_n = c > kWave && ((wm[(c >> 6) - 2] >> lane) & 1ull);
+      if (hit_n) nid = vals[rg.x + c - 2 * kWave + lane];
     }
     for (int k = __popcll(m) - 1; k >= 0; --k) {
       const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
@@ -654,7 +696,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
         ps.rw = act ? p.rw : 0.0f;
         ps.depth = act ? p.depth : 0.0f;
       }
-      const float a = fminf(raw, opt.alpha_max);
+      const float a = raw < opt.alpha_max ? raw : opt.alpha_max;  // as the forward forms it
       const bool live = act && !(raw > opt.alpha_max);  // not clamped: the exponent's path
       const float Ti = T * __builtin_amdgcn_rcpf(1.0f - a);
       const float wg = act ? a * Ti : 0.0f;
@@ -725,12 +767,19 @@ unsigned quad_blocks(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 32u; 
 
 void launch_raster_fwd(const uint2 *ranges, const uint32_t *vals, const Record *rec,
                        const DevCam *cams, int V, int n_tiles_total, int W, int H, int tiles_x,
-                       int tiles_per_view, DevOpts opt, RasterOut out, hipStream_t s) {
+                       int tiles_per_view, DevOpts opt, RasterOut out, uint64_t *bmask,
+                       hipStream_t s) {
   (void)cams;
   (void)V;
   if (n_tiles_total == 0) return;
-  hipLaunchKernelGGL(raster_fwd_kernel, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
-                     ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt, out);
+  if (out.wcount)
+    hipLaunchKernelGGL(raster_fwd_kernel<true>, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0,
+                       s, ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
+                       out, bmask);
+  else
+    hipLaunchKernelGGL(raster_fwd_kernel<false>, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0,
+                       s, ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
+                       out, bmask);
 }
 
 void launch_raster_fwd_queue(const uint2 *ranges, const uint32_t *vals, const Record *rec,
@@ -743,23 +792,23 @@ void launch_raster_fwd_queue(const uint2 *ranges, const uint32_t *vals, const Re
 
 void launch_raster_bwd(const uint2 *ranges, const uint32_t *vals, const Record *rec,
                        int n_tiles_total, int W, int H, int tiles_x, int tiles_per_view,
-                       DevOpts opt, const float *T_final, const uint32_t *last, RasterGradIn g,
-                       float *accum, hipStream_t s) {
+                       DevOpts opt, const float *T_final, const uint32_t *last,
+                       const uint64_t *bmask, RasterGradIn g, float *accum, hipStream_t s) {
   if (n_tiles_total == 0) return;
   hipLaunchKernelGGL(raster_bwd_kernel<1>, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
                      ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
-                     T_final, last, g, RgbSets{}, accum, (int64_t)0);
+                     T_final, last, g, RgbSets{}, accum, (int64_t)0, bmask);
 }
 
 void launch_raster_bwd_sets(const uint2 *ranges, const uint32_t *vals, const Record *rec,
                             int n_tiles_total, int W, int H, int tiles_x, int tiles_per_view,
                             DevOpts opt, const float *T_final, const uint32_t *last,
-                            RasterGradIn g, RgbSets rgb2, float *accum, int64_t plane,
-                            hipStream_t s) {
+                            const uint64_t *bmask, RasterGradIn g, RgbSets rgb2, float *accum,
+                            int64_t plane, hipStream_t s) {
   if (n_tiles_total <= 0) return;
   hipLaunchKernelGGL(raster_bwd_kernel<3>, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
                      ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
-                     T_final, last, g, rgb2, accum, plane);
+                     T_final, last, g, rgb2, accum, plane, bmask);
 }
 
 }  // namespace hgs

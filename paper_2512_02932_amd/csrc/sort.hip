@@ -10,7 +10,7 @@
 // duplicated in index order, with far fewer bits sorted per pair.
 //
 // The radix sort uses 8-bit digits: one up-front launch counts the digits
-// of every pass, and each pass is a single launch that ranks 4096-key
+// of every pass, and each pass is a single launch that ranks 8192-key
 // chunks (16 wave64 per chunk, wave ballots for equal digits) and finds
 // each chunk's place by a decoupled look-back over the chunks before it.
 
@@ -258,12 +258,14 @@ duplicate_slots_kernel(const uint32_t *__restrict__ order, const uint32_t *__res
                        int64_t inst_cap, const uint64_t *__restrict__ n_inst, uint64_t cap,
                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
                        uint32_t *__restrict__ overflow) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= eff_n(inst_cap, n_inst)) return;
-  const uint32_t i = order[j];
-  if (tiles[i] == 0) return;
-  const Slot &sl = slots[slot_of_instance(slots, *n_slots, (int64_t)i)];
-  emit_pairs(sl.cam, rect[i], i, offsets[j], cap, keys, vals, overflow);
+  const int64_t cnt = eff_n(inst_cap, n_inst);
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < cnt;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t i = order[j];
+    if (tiles[i] == 0) continue;
+    const Slot &sl = slots[slot_of_instance(slots, *n_slots, (int64_t)i)];
+    emit_pairs(sl.cam, rect[i], i, offsets[j], cap, keys, vals, overflow);
+  }
 }
 
 // ----- radix sort: one sweep per digit -----
@@ -286,14 +288,15 @@ duplicate_slots_kernel(const uint32_t *__restrict__ order, const uint32_t *__res
 // then wrong but every wave ends).
 constexpr int kOsThreads = 1024;
 constexpr int kOsWaves = kOsThreads / 64;
-constexpr int kOsRows = 4;                        // keys per thread
-constexpr int kOsChunk = kOsThreads * kOsRows;    // 4096 keys per chunk
+constexpr int kOsRows = 8;                        // keys per thread
+constexpr int kOsChunk = kOsThreads * kOsRows;    // 8192 keys per chunk
+constexpr int kPartWin = 12;  // look-back words per thread per round (4 parts: 48 per digit)
 constexpr int kMaxPasses = 4;
 constexpr int kOsWords = kMaxPasses * 256 + kMaxPasses + 1;  // hist, tickets, spare
 constexpr size_t kOsHead = 4352;                  // bytes before the status tables
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
-constexpr int kSpinLimit = 1 << 22;
+constexpr int kSpinLimit = 1 << 16;  // look-back rounds before giving up
 constexpr int kOsMaxBlocks = 1024;  // persistent grid of a pass (two per CU and more)
 
 __device__ __forceinline__ int64_t os_chunks(int64_t n) { return (n + kOsChunk - 1) / kOsChunk; }
@@ -338,6 +341,15 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
   __shared__ uint32_t s_wtot[4];
   __shared__ uint32_t s_ticket;
   __shared__ int s_trivial;
+  __shared__ uint32_t s_run[256];         // this chunk's digit counts
+  __shared__ int64_t s_lj[256];           // look-back position per digit
+  __shared__ uint64_t s_lex[256];         // prefix gathered so far per digit
+  __shared__ int s_ldone[256];
+  __shared__ uint4 s_lpart[4][256];       // a round's part results
+  __shared__ int s_lany;
+  __shared__ uint32_t s_cex[256];         // chunk-local exclusive digit offsets
+  __shared__ uint32_t s_key[kOsChunk];    // the chunk in digit order
+  __shared__ uint32_t s_val[kOsChunk];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int shift = 8 * pass;
   n = eff_n(n, n_dev);
@@ -389,7 +401,7 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
       continue;
     }
 
-    // each wave owns 256 consecutive keys, as kOsRows rows of 64
+    // each wave owns 64 kOsRows consecutive keys, as kOsRows rows of 64
     const int64_t wb = c0 + (int64_t)w * (64 * kOsRows);
     uint32_t key[kOsRows], val[kOsRows], rank[kOsRows];
     bool ok[kOsRows];
@@ -424,46 +436,122 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
         s_whist[v][tid] = run;
         run += c;
       }
+      s_run[tid] = run;
       uint64_t *me = st_cur + chunk * 256 + tid;
-      uint64_t excl = 0;
-      if (chunk == 0) {
-        __hip_atomic_store(me, kFlagInc | (uint64_t)run, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        __hip_atomic_store(me, kFlagAgg | (uint64_t)run, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        int64_t j = chunk - 1;
-        int spins = 0;
-        while (j >= 0) {
-          const uint64_t v = __hip_atomic_load(st_cur + j * 256 + tid, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-          const uint64_t f = v & ~kValMask;
-          if (f == 0) {
-            if (++spins > kSpinLimit) {
-              if (err) atomicOr(err, 2u);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          excl += v & kValMask;
-          if (f == kFlagInc) break;
-          --j;
-        }
-        __hip_atomic_store(me, kFlagInc | (excl + run), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      }
-      s_base[tid] = s_gex[tid] + (uint32_t)excl;
+      __hip_atomic_store(me, (chunk == 0 ? kFlagInc : kFlagAgg) | (uint64_t)run, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      s_lj[tid] = chunk - 1;
+      s_lex[tid] = 0;
+      s_ldone[tid] = chunk == 0 ? 1 : 0;
     }
     __syncthreads();
+    // Look-back, all 16 waves: digit d = tid % 256 is read by four parts
+    // p = tid / 256, each reading kPartWin words of the 4 kPartWin words
+    // before the digit's current position; the parts are combined in order.
+    for (int spins = 0;; ++spins) {
+      if (s_lany == 0 && spins > 0) break;
+      const int d = tid & 255, part = tid >> 8;
+      if (!s_ldone[d]) {
+        const int64_t j0 = s_lj[d] - (int64_t)part * kPartWin;
+        uint64_t v[kPartWin];
+#pragma unroll
+        for (int k = 0; k < kPartWin; ++k) {
+          const int64_t jj = j0 - k < 0 ? 0 : j0 - k;
+          v[k] = __hip_atomic_load(st_cur + jj * 256 + d, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        uint64_t sum = 0;
+        uint32_t cnt = 0, state = 0;  // 0 all aggregates, 1 inclusive found, 2 stalled
+#pragma unroll
+        for (int k = 0; k < kPartWin; ++k) {
+          if (state != 0) continue;
+          const uint64_t f = v[k] & ~kValMask;
+          if (f == 0) {
+            state = 2;
+            continue;
+          }
+          sum += v[k] & kValMask;
+          ++cnt;
+          if (f == kFlagInc) state = 1;
+        }
+        s_lpart[part][d] = make_uint4((uint32_t)sum, (uint32_t)(sum >> 32), cnt, state);
+      }
+      __syncthreads();
+      if (tid == 0) s_lany = 0;
+      __syncthreads();
+      if (tid < 256 && !s_ldone[tid]) {
+        uint64_t ex = s_lex[tid];
+        int64_t j = s_lj[tid];
+        bool done = false, stall = false;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (done || stall) continue;
+          const uint4 r = s_lpart[q][tid];
+          ex += (uint64_t)r.x | ((uint64_t)r.y << 32);
+          j -= r.z;
+          done = r.w == 1;
+          stall = r.w == 2;
+        }
+        if (!done && spins > kSpinLimit) {
+          if (err) atomicOr(err, 2u);
+          done = true;
+        }
+        s_lex[tid] = ex;
+        s_lj[tid] = j;
+        s_ldone[tid] = done ? 1 : 0;
+        if (!done) {
+          s_lany = 1;
+          if (stall) __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __syncthreads();
+    }
+    // chunk-local exclusive offsets of the digits
+    uint32_t r = 0, rx = 0;
+    if (tid < 256) {
+      const uint64_t excl = s_lex[tid];
+      r = s_run[tid];
+      if (chunk > 0)
+        __hip_atomic_store(st_cur + chunk * 256 + tid, kFlagInc | (excl + r), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      s_base[tid] = s_gex[tid] + (uint32_t)excl;
+      rx = r;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(rx, d, 64);
+        if (lane >= d) rx += y;
+      }
+      if (lane == 63) s_wtot[w] = rx;
+    }
+    __syncthreads();
+    if (tid < 256) {
+      uint32_t off = 0;
+      for (int k = 0; k < w; ++k) off += s_wtot[k];
+      s_cex[tid] = off + rx - r;
+    }
+    __syncthreads();
+    // the chunk sorted by digit in LDS, so that each digit's run is written
+    // out by consecutive threads (coalesced) rather than key by key
 #pragma unroll
     for (int j = 0; j < kOsRows; ++j) {
       if (!ok[j]) continue;
       const uint32_t d = (key[j] >> shift) & 255u;
-      const uint32_t pos = s_base[d] + s_whist[w][d] + rank[j];
-      kout[pos] = key[j];
-      vout[pos] = val[j];
-      if (gdst) gdst[pos] = gsrc[val[j]];
+      const uint32_t lp = s_cex[d] + s_whist[w][d] + rank[j];
+      s_key[lp] = key[j];
+      s_val[lp] = val[j];
+    }
+    __syncthreads();
+    const int cn = (int)(n - c0 < kOsChunk ? n - c0 : kOsChunk);
+#pragma unroll
+    for (int j = 0; j < kOsRows; ++j) {
+      const int e = j * kOsThreads + tid;
+      if (e >= cn) continue;
+      const uint32_t k = s_key[e], v = s_val[e];
+      const uint32_t d = (k >> shift) & 255u;
+      const uint32_t pos = s_base[d] + (uint32_t)e - s_cex[d];
+      kout[pos] = k;
+      vout[pos] = v;
+      if (gdst) gdst[pos] = gsrc[v];
     }
     __syncthreads();  // LDS is read before the next chunk clears it
   }
@@ -487,12 +575,13 @@ __global__ void fill_f32x4_kernel(float4 *p, float v, int64_t n4) {
 
 __global__ void ranges_kernel(const uint32_t *__restrict__ keys, int64_t D,
                               const uint64_t *__restrict__ D_dev, uint2 *__restrict__ ranges) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   D = eff_n(D, D_dev);
-  if (i >= D) return;
-  const uint32_t t = keys[i];
-  if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
-  if (i == D - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t t = keys[i];
+    if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
+    if (i == D - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+  }
 }
 
 }  // namespace
@@ -556,9 +645,10 @@ void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
                             uint64_t pair_cap, uint32_t *keys, uint32_t *vals,
                             uint32_t *overflow, hipStream_t s) {
   if (inst_cap <= 0) return;
-  hipLaunchKernelGGL(duplicate_slots_kernel, dim3((unsigned)((inst_cap + 255) / 256)), dim3(256),
-                     0, s, order, offsets, tiles, rect, slots, n_slots, inst_cap, n_inst, pair_cap,
-                     keys, vals, overflow);
+  const int64_t blocks = std::min<int64_t>((inst_cap + 255) / 256, 4096);
+  hipLaunchKernelGGL(duplicate_slots_kernel, dim3((unsigned)blocks), dim3(256), 0, s, order,
+                     offsets, tiles, rect, slots, n_slots, inst_cap, n_inst, pair_cap, keys, vals,
+                     overflow);
 }
 
 size_t sort_tmp_bytes(int64_t n) {
@@ -577,7 +667,9 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
                      (uint64_t *)((char *)tmp + kOsHead) + nch * 256};
   const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
   launch_fill_u32(words, 0u, kOsWords, s);
-  const int64_t hb = std::min<int64_t>(std::max<int64_t>(nch, 1), 2048);
+  // few blocks: each adds its 256-bin histograms to the global table with
+  // atomics on the same 4 x 256 addresses as every other block
+  const int64_t hb = std::min<int64_t>((n + 4095) / 4096, 256);
   hipLaunchKernelGGL(radix_hist_all, dim3((unsigned)hb), dim3(256), 0, s, k0, n, n_dev, passes,
                      words, st[0]);
   const uint32_t *kin = k0, *vin = v0;
@@ -626,8 +718,10 @@ void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
 void launch_ranges(const uint32_t *keys, int64_t D, uint2 *ranges, hipStream_t s,
                    const uint64_t *D_dev) {
   if (D <= 0) return;
-  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, keys, D,
-                     D_dev, ranges);
+  // a capacity-sized count (D_dev given) strides over a bounded grid
+  const int64_t blocks = D_dev ? std::min<int64_t>((D + 255) / 256, 8192) : (D + 255) / 256;
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)blocks), dim3(256), 0, s, keys, D, D_dev,
+                     ranges);
 }
 
 }  // namespace hgs
