@@ -188,7 +188,7 @@ struct RasterOut {
 // bmask (may be NULL): receives the blend masks the backward walks,
 // raster_mask_words(D capacity, tiles) 64-bit words.
 inline int64_t raster_mask_words(int64_t pairs, int64_t tiles) {
-  return 4 * ((pairs >> 6) + tiles + 1);
+  return 8 * ((pairs >> 6) + tiles + 1);
 }
 void launch_raster_fwd(const uint2 *ranges, const uint32_t *vals, const Record *rec,
                        const DevCam *cams, int V, int n_tiles_total, int W, int H,

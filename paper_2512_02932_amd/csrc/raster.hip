@@ -1,10 +1,11 @@
 // Per-tile compositing (forward) and its reverse pass (backward), gfx950.
 //
 // Work unit: one wave64 per 8x8 quadrant of a 16x16 tile, one pixel per lane,
-// launched as its own workgroup so that waves never wait for each other.  The
-// four quadrant waves of a tile are given block ids that the dispatcher sends
-// to the same XCD, so the tile's pair list and records are fetched into one
-// L2.  A wave walks its tile's depth-sorted pair list in chunks of 64: each
+// launched as its own workgroup so that waves never wait for each other; in
+// the forward, tiles with a long pair list get two waves per quadrant, each
+// on half of it (8x4 pixels).  The waves of a tile are given block ids that the dispatcher
+// sends to the same XCD, so the tile's pair list and records are fetched
+// into one L2.  A wave walks its tile's depth-sorted pair list in chunks of 64: each
 // lane loads one pair's 80-byte record (the next chunk is prefetched into
 // registers while the current one is composited), tests the record's pixel
 // rectangle against the quadrant, and the hits are compacted in list order
@@ -95,60 +96,93 @@ __device__ __forceinline__ float exp2_neg(float e) { return __builtin_amdgcn_exp
     q4 = p_[4];                               \
   } while (0)
 
-// A wave's quadrant: block id -> (tile, quadrant).  Blocks 32g + 8q + x hold
-// tile 8g + x, quadrant q, so the four quadrants of a tile share x = block id
-// mod 8, the XCD the dispatcher assigns them to.
 struct Quad {
   int tile;
   int v;           // view
-  int quad;        // 0..3: (x half, y half) of the tile
-  int qx, qy;      // top-left pixel of the quadrant
+  int sub;         // 0..7: quadrant * 2 + half, the wave's blend-mask region
+  int qx, qy;      // top-left pixel of the wave's box
+  int rows;        // 8 (a quadrant) or 4 (half a quadrant of a long-list tile)
   int px, py;      // this lane's pixel
   float fx, fy;    // pixel sample (x + 1/2, y + 1/2)
   bool inside;
 };
 
-// Quadrant `quad` of the view-local tile r (row-major over tiles_x columns).
+// Tiles whose pair list is at least this long are walked by two waves per
+// quadrant, each on 8 x 4 pixels (lanes 32-63 idle) and culling against its
+// own half: the densest tiles set the kernel's critical path, and a half
+// meets fewer splats than the whole quadrant.
+constexpr uint32_t kSplitLen = 768;
+
+// Quadrant `quad` of the view-local tile r (row-major over tiles_x columns);
+// with split, its half `half` (rows 4 half .. 4 half + 3).
 __device__ __forceinline__ Quad make_quad(int tile, int v, int r, int quad, int W, int H,
-                                          int tiles_x) {
+                                          int tiles_x, bool split = false, int half = 0) {
   Quad q;
   q.tile = tile;
   q.v = v;
-  q.quad = quad;
+  q.sub = quad * 2 + (split ? half : 0);
   const int ty = r / tiles_x;
   const int tx = r - ty * tiles_x;
+  q.rows = split ? 4 : 8;
   q.qx = tx * kTile + (quad & 1) * 8;
-  q.qy = ty * kTile + (quad >> 1) * 8;
+  q.qy = ty * kTile + (quad >> 1) * 8 + (split ? 4 * half : 0);
   const int lane = threadIdx.x;
   q.px = q.qx + (lane & 7);
   q.py = q.qy + (lane >> 3);
   q.fx = (float)q.px + 0.5f;
   q.fy = (float)q.py + 0.5f;
-  q.inside = q.px < W && q.py < H;
+  q.inside = q.px < W && q.py < H && (lane >> 3) < q.rows;
   return q;
 }
 
-__device__ __forceinline__ Quad quad_of(int W, int H, int tiles_x, int tiles_per_view) {
+// Forward: blocks 64g + 8j + x hold tile 8g + x, quadrant j / 2, half j % 2,
+// so the eight waves of a tile share x = block id mod 8, the XCD the
+// dispatcher assigns them to.  Returns false for the second-half wave of a
+// tile that is not split (that wave has nothing to do).
+__device__ __forceinline__ bool quad_of(const uint2 *ranges, int n_tiles, int W, int H,
+                                        int tiles_x, int tiles_per_view, Quad &q, uint2 &rg) {
   const int b = blockIdx.x;
-  const int tile = (b >> 5) * 8 + (b & 7);
+  const int tile = (b >> 6) * 8 + (b & 7);
+  if (tile >= n_tiles) return false;
+  const int j = (b >> 3) & 7;
+  rg = ranges[tile];
+  const bool split = rg.y - rg.x >= kSplitLen;
+  if (!split && (j & 1)) return false;
   const int v = tile / tiles_per_view;
-  return make_quad(tile, v, tile - v * tiles_per_view, (b >> 3) & 3, W, H, tiles_x);
+  q = make_quad(tile, v, tile - v * tiles_per_view, j >> 1, W, H, tiles_x, split, j & 1);
+  return true;
 }
 
-// Blend masks: for each quadrant wave, one 64-bit word per chunk of 64
-// positions of its tile's pair list, bit j set if the pair at position
-// 64 c + j was blended at one or more of the quadrant's pixels.  The forward
-// writes them and the backward walks only those pairs (a pair blended at no
-// pixel of the quadrant contributes nothing to its gradients).  Tile t with
-// pair range [a, a + n) owns the words [4 (a / 64 + t), 4 (a / 64 + t) +
-// 4 ceil(n / 64)), quadrant q the q-th run of ceil(n / 64): since
-// floor(a / 64) + floor(n / 64) <= floor((a + n) / 64), the regions of
-// consecutive tiles never overlap, and all fit in 4 (D / 64 + T + 1) words.
+// Backward: whole quadrants (the backward is bound by its total work, and a
+// half quadrant repeats a pair's per-pair cost for half the pixels).
+// Blocks 32g + 8q + x hold tile 8g + x, quadrant q.
+__device__ __forceinline__ bool quad_of_full(const uint2 *ranges, int n_tiles, int W, int H,
+                                             int tiles_x, int tiles_per_view, Quad &q,
+                                             uint2 &rg) {
+  const int b = blockIdx.x;
+  const int tile = (b >> 5) * 8 + (b & 7);
+  if (tile >= n_tiles) return false;
+  rg = ranges[tile];
+  const int v = tile / tiles_per_view;
+  q = make_quad(tile, v, tile - v * tiles_per_view, (b >> 3) & 3, W, H, tiles_x);
+  return true;
+}
+
+// Blend masks: for each wave (quadrant, or half quadrant of a split tile),
+// one 64-bit word per chunk of 64 positions of its tile's pair list, bit j
+// set if the pair at position 64 c + j was blended at one or more of the
+// wave's pixels.  The forward writes them and the backward walks only those
+// pairs (a pair blended at no pixel of the wave contributes nothing to its
+// gradients).  Tile t with pair range [a, a + n) owns the words
+// [8 (a / 64 + t), 8 (a / 64 + t) + 8 ceil(n / 64)), wave region s = 2
+// quadrant + half the s-th run of ceil(n / 64): since floor(a / 64) +
+// floor(n / 64) <= floor((a + n) / 64), the regions of consecutive tiles
+// never overlap, and all fit in 8 (D / 64 + T + 1) words.
 __device__ __forceinline__ uint64_t *quad_mask_words(uint64_t *bmask, uint2 rg, int tile,
-                                                     int quad) {
+                                                     int sub) {
   const uint32_t n = rg.y - rg.x;
-  const uint64_t base = 4ull * ((uint64_t)(rg.x >> 6) + (uint64_t)tile);
-  return bmask + base + (uint64_t)quad * ((n + 63u) >> 6);
+  const uint64_t base = 8ull * ((uint64_t)(rg.x >> 6) + (uint64_t)tile);
+  return bmask + base + (uint64_t)sub * ((n + 63u) >> 6);
 }
 
 // Output images of one view: channel planes of H*W pixels (NULL: skip).
@@ -166,9 +200,9 @@ struct ViewOut {
 // log2(alpha_eff / alpha_min) by a margin.
 __device__ __forceinline__ bool meets_2d(const float4 &r0, const float4 &r1, const float4 &r2,
                                          const float4 &r3, const float4 &r4, float qx, float qy,
-                                         float inv_amin) {
+                                         float ylast, float inv_amin) {
   const float xa = (qx + 0.5f) - r0.x, xb = (qx + 7.5f) - r0.x;
-  const float ya = (qy + 0.5f) - r0.y, yb = (qy + 7.5f) - r0.y;
+  const float ya = (qy + 0.5f) - r0.y, yb = (ylast + 0.5f) - r0.y;
   const float mx = fmaxf(fabsf(xa), fabsf(xb)), my = fmaxf(fabsf(ya), fabsf(yb));
   auto span = [&](float a, float b, float c, float &lo, float &hi) {
     const float t0 = __builtin_fmaf(a, xa, __builtin_fmaf(b, ya, c));
@@ -206,14 +240,14 @@ __device__ __forceinline__ bool meets_2d(const float4 &r0, const float4 &r1, con
 __device__ __forceinline__ bool meets(const float4 &r0, const float4 &r1, const float4 &r2,
                                       const float4 &r3, const float4 &r4, const Quad &q,
                                       float inv_amin) {
-  const float qx = (float)q.qx, qy = (float)q.qy;
-  if (!(r0.x <= qx + 7.0f && r0.z >= qx && r0.y <= qy + 7.0f && r0.w >= qy)) return false;
-  if (__float_as_uint(r4.w) >> 31) return meets_2d(r0, r1, r2, r3, r4, qx, qy, inv_amin);
+  const float qx = (float)q.qx, qy = (float)q.qy, ylast = (float)(q.qy + q.rows - 1);
+  if (!(r0.x <= qx + 7.0f && r0.z >= qx && r0.y <= ylast && r0.w >= qy)) return false;
+  if (__float_as_uint(r4.w) >> 31) return meets_2d(r0, r1, r2, r3, r4, qx, qy, ylast, inv_amin);
   const float A = r1.z, B = r1.w, C = r2.x;
   if (!(A > 0.0f && C > 0.0f)) return true;
   // sample box in the record's frame, as eval_pair forms dx, dy
   const float x0 = ((qx + 0.5f) - r0.x) - r1.x, x1 = ((qx + 7.5f) - r0.x) - r1.x;
-  const float y0 = ((qy + 0.5f) - r0.y) - r1.y, y1 = ((qy + 7.5f) - r0.y) - r1.y;
+  const float y0 = ((qy + 0.5f) - r0.y) - r1.y, y1 = ((ylast + 0.5f) - r0.y) - r1.y;
   if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
   const float hA = -0.5f * B * __builtin_amdgcn_rcpf(A), hC = -0.5f * B * __builtin_amdgcn_rcpf(C);
   auto at = [&](float x, float y) { return x * (A * x + B * y) + C * y * y; };
@@ -382,8 +416,9 @@ raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
                   int tiles_per_view, DevOpts opt, RasterOut out, uint64_t *__restrict__ bmask) {
   __shared__ float4 srec[5][kWave];
   __shared__ uint32_t spos[kWave];
-  const Quad q = quad_of(W, H, tiles_x, tiles_per_view);
-  if (q.tile >= n_tiles) return;
+  Quad q;
+  uint2 rg;
+  if (!quad_of(ranges, n_tiles, W, H, tiles_x, tiles_per_view, q, rg)) return;
   const int64_t hw = (int64_t)H * W, v = q.v;
   ViewOut vo;
   vo.rgb = out.rgb ? out.rgb + v * 3 * hw : nullptr;
@@ -394,9 +429,8 @@ raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   vo.last = out.last ? out.last + v * hw : nullptr;
   vo.n_contrib = out.n_contrib ? out.n_contrib + v * hw : nullptr;
   vo.wcount = out.wcount ? out.wcount + v * hw : nullptr;
-  const uint2 rg = ranges[q.tile];
   raster_fwd_quad<kAcct>(q, rg, vals, rec, W, H, opt, vo,
-                         bmask ? quad_mask_words(bmask, rg, q.tile, q.quad) : nullptr, srec,
+                         bmask ? quad_mask_words(bmask, rg, q.tile, q.sub) : nullptr, srec,
                          spos);
 }
 
@@ -573,10 +607,10 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   __shared__ float4 srec[5][kWave];
   __shared__ uint32_t sid[kWave];
   __shared__ uint32_t spos[kWave];
-  const Quad q = quad_of(W, H, tiles_x, tiles_per_view);
-  if (q.tile >= n_tiles) return;
+  Quad q;
+  uint2 rg;
+  if (!quad_of_full(ranges, n_tiles, W, H, tiles_x, tiles_per_view, q, rg)) return;
   const int lane = threadIdx.x;
-  const uint2 rg = ranges[q.tile];
 
   float T = 1.0f;
   uint32_t L = 0;
@@ -644,16 +678,21 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   // the positions the forward blended in this quadrant (its blend mask).
   // Pipeline: records of chunk c in q0..q4 (entry id), entries of chunk
   // c - 64 in nid.
-  const uint64_t *wm = quad_mask_words(const_cast<uint64_t *>(bmask), rg, q.tile, q.quad);
+  // a split tile's quadrant: the union of its two halves' masks
+  const uint64_t *wm = quad_mask_words(const_cast<uint64_t *>(bmask), rg, q.tile, q.sub);
+  const uint64_t *wm2 = rg.y - rg.x >= kSplitLen
+                            ? quad_mask_words(const_cast<uint64_t *>(bmask), rg, q.tile, q.sub + 1)
+                            : wm;
+  auto mask_at = [&](int w) { return wm[w] | wm2[w]; };
   float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0, q4 = q0;
   uint32_t id = 0, nid = 0;
   int c = (n - 1) & ~(kWave - 1);
-  bool hit = (c + lane < n) && ((wm[c >> 6] >> lane) & 1ull);
+  bool hit = (c + lane < n) && ((mask_at(c >> 6) >> lane) & 1ull);
   if (hit) {
     id = vals[rg.x + c + lane];
     HGS_FETCH(rec, id, q0, q1, q2, q3, q4);
   }
-  bool hit_n = c > 0 && ((wm[(c >> 6) - 1] >> lane) & 1ull);
+  bool hit_n = c > 0 && ((mask_at((c >> 6) - 1) >> lane) & 1ull);
   if (hit_n) nid = vals[rg.x + c - kWave + lane];
   for (; c >= 0; c -= kWave) {
     const uint64_t m = __ballot(hit);
@@ -673,7 +712,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
       hit = hit_n;
       id = nid;
       if (hit) HGS_FETCH(rec, id, q0, q1, q2, q3, q4);
-      hit_n = c > kWave && ((wm[(c >> 6) - 2] >> lane) & 1ull);
+      hit_n = c > kWave && ((mask_at((c >> 6) - 2) >> lane) & 1ull);
       if (hit_n) nid = vals[rg.x + c - 2 * kWave + lane];
     }
     for (int k = __popcll(m) - 1; k >= 0; --k) {
@@ -760,8 +799,10 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   }
 }
 
-// Blocks: 32 per group of 8 tiles (four quadrants each), see quad_of.
-unsigned quad_blocks(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 32u; }
+// Blocks: 64 per group of 8 tiles (four quadrants of two halves each) for
+// the forward, see quad_of; 32 (four quadrants) for the backward.
+unsigned quad_blocks(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 64u; }
+unsigned quad_blocks_full(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 32u; }
 
 }  // namespace
 
@@ -795,7 +836,7 @@ void launch_raster_bwd(const uint2 *ranges, const uint32_t *vals, const Record *
                        DevOpts opt, const float *T_final, const uint32_t *last,
                        const uint64_t *bmask, RasterGradIn g, float *accum, hipStream_t s) {
   if (n_tiles_total == 0) return;
-  hipLaunchKernelGGL(raster_bwd_kernel<1>, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
+  hipLaunchKernelGGL(raster_bwd_kernel<1>, dim3(quad_blocks_full(n_tiles_total)), dim3(kWave), 0, s,
                      ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
                      T_final, last, g, RgbSets{}, accum, (int64_t)0, bmask);
 }
@@ -806,7 +847,7 @@ void launch_raster_bwd_sets(const uint2 *ranges, const uint32_t *vals, const Rec
                             const uint64_t *bmask, RasterGradIn g, RgbSets rgb2, float *accum,
                             int64_t plane, hipStream_t s) {
   if (n_tiles_total <= 0) return;
-  hipLaunchKernelGGL(raster_bwd_kernel<3>, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
+  hipLaunchKernelGGL(raster_bwd_kernel<3>, dim3(quad_blocks_full(n_tiles_total)), dim3(kWave), 0, s,
                      ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
                      T_final, last, g, rgb2, accum, plane, bmask);
 }
