@@ -562,6 +562,9 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc_t(st, &st->offsets, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->total, (size_t)1));
   ST_HIP(dalloc_t(st, &st->overflow, (size_t)1));
+  uint32_t *dwords = nullptr, *twords = nullptr;  // digit counts of the two sorts
+  ST_HIP(dalloc_t(st, &dwords, (size_t)kSortWords));
+  ST_HIP(dalloc_t(st, &twords, (size_t)kSortWords));
   void *scan_tmp = nullptr;
   ST_HIP(dalloc(st, &scan_tmp, scan_tmp_bytes(VN)));
   ST_HIP(dalloc_t(st, &st->ranges, (size_t)n_tiles));
@@ -579,13 +582,20 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc_t(st, &cnt, (size_t)VN));
   ST_HIP(dalloc(st, &dsort_tmp, sort_tmp_bytes(VN)));
   ST_HIP(commit(st, 0, st->stream, cap_mode));
+  ZeroList zl;  // cleared by the camera upload's launch
+  zl.p[0] = st->overflow;
+  zl.n[0] = 1;
+  zl.p[1] = dwords;
+  zl.n[1] = kSortWords;
+  zl.p[2] = twords;
+  zl.n[2] = kSortWords;
   if (n_views <= kCamsPerUpload * 8) {
-    launch_upload_cams(st->cams_host.data(), n_views, st->cams, st->stream);
+    launch_upload_cams(st->cams_host.data(), n_views, st->cams, st->stream, zl);
   } else {
     ST_HIP(hipMemcpyAsync(st->cams, st->cams_host.data(), sizeof(DevCam) * n_views,
                           hipMemcpyHostToDevice, st->stream));
+    for (int a = 0; a < ZeroList::kMax; ++a) launch_fill_u32(zl.p[a], 0u, zl.n[a], st->stream);
   }
-  launch_fill_u32(st->overflow, 0u, 1, st->stream);
 
   {
     StageTimer t(ctx, HGS_STAGE_PREPROCESS, st->stream);
@@ -597,7 +607,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
     // instances in depth order; the last pass also gathers their tile counts
     StageTimer t(ctx, HGS_STAGE_DEPTH_SORT, st->stream);
     const int w = launch_radix_sort(st->zbits, nullptr, za, oa, zb, ob, VN, 32, dsort_tmp,
-                                    st->stream, nullptr, st->tiles, cnt, st->overflow);
+                                    st->stream, nullptr, st->tiles, cnt, st->overflow, dwords);
     order = w ? ob : oa;
   }
   {
@@ -653,7 +663,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   {
     StageTimer t(ctx, HGS_STAGE_SORT, st->stream);
     const int w = launch_radix_sort(kb, vb, ka, va, kb, vb, cap, tile_bits, sort_tmp,
-                                    st->stream, st->total, nullptr, nullptr, st->overflow);
+                                    st->stream, st->total, nullptr, nullptr, st->overflow, twords);
     st->keys = w ? kb : ka;
     st->vals = w ? vb : va;
   }

@@ -147,7 +147,14 @@ void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint
 // kCamsPerUpload per launch), so that a captured graph carries the camera
 // values themselves rather than a host address.
 constexpr int kCamsPerUpload = 8;
-void launch_upload_cams(const DevCam *host, int n, DevCam *dst, hipStream_t s);
+// Up to kMax small uint32 arrays cleared by the same launch.
+struct ZeroList {
+  static constexpr int kMax = 3;
+  uint32_t *p[kMax] = {nullptr, nullptr, nullptr};
+  int n[kMax] = {0, 0, 0};
+};
+void launch_upload_cams(const DevCam *host, int n, DevCam *dst, hipStream_t s,
+                        ZeroList z = ZeroList{});
 // The same for a batch of slots, with the instance count on the device.
 // Pairs at or past pair_cap are dropped and set *overflow = 1.
 void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
@@ -164,11 +171,16 @@ void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
 // sort_tmp_bytes(n) bytes.  If gather_dst is given, the last pass also
 // writes gather_dst[j] = gather_src[value j] of the sorted order.  err (may
 // be NULL): bit 1 is set if a pass's look-back gave up (never expected).
+// zeroed_words (may be NULL): kSortWords uint32 the caller has cleared on
+// the stream, used for the sort's digit counts and tickets instead of the
+// head of tmp (which is then not cleared by a launch of its own).
+constexpr int kSortWords = 4 * 256 + 4 + 1;
 size_t sort_tmp_bytes(int64_t n);
 int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint32_t *va,
                       uint32_t *kb, uint32_t *vb, int64_t n, int bits, void *tmp, hipStream_t s,
                       const uint64_t *n_dev = nullptr, const uint32_t *gather_src = nullptr,
-                      uint32_t *gather_dst = nullptr, uint32_t *err = nullptr);
+                      uint32_t *gather_dst = nullptr, uint32_t *err = nullptr,
+                      uint32_t *zeroed_words = nullptr);
 
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);

@@ -241,12 +241,16 @@ struct CamPack {
   DevCam c[kCamsPerUpload];
 };
 
-__global__ void upload_cams_kernel(CamPack p, int n, DevCam *__restrict__ dst) {
+__global__ void upload_cams_kernel(CamPack p, int n, DevCam *__restrict__ dst, ZeroList z) {
   // 8-byte words of n cameras (DevCam is 8-byte aligned)
   constexpr int kWords = (int)(sizeof(DevCam) / 8);
   static_assert(sizeof(DevCam) % 8 == 0, "DevCam is copied in 8-byte words");
   for (int k = threadIdx.x; k < n * kWords; k += blockDim.x)
     reinterpret_cast<uint2 *>(dst)[k] = reinterpret_cast<const uint2 *>(p.c)[k];
+  // small arrays the render needs cleared (counters, flags), in the same launch
+#pragma unroll
+  for (int a = 0; a < ZeroList::kMax; ++a)
+    for (int k = threadIdx.x; k < z.n[a]; k += blockDim.x) z.p[a][k] = 0u;
 }
 
 // A batch of slots; instance count on the device.  Pairs at or past `cap`
@@ -292,7 +296,8 @@ constexpr int kOsRows = 8;                        // keys per thread
 constexpr int kOsChunk = kOsThreads * kOsRows;    // 8192 keys per chunk
 constexpr int kPartWin = 12;  // look-back words per thread per round (4 parts: 48 per digit)
 constexpr int kMaxPasses = 4;
-constexpr int kOsWords = kMaxPasses * 256 + kMaxPasses + 1;  // hist, tickets, spare
+constexpr int kOsWords = kSortWords;  // hist [pass][256], tickets [pass], spare
+static_assert(kSortWords == kMaxPasses * 256 + kMaxPasses + 1, "sort words layout");
 constexpr size_t kOsHead = 4352;                  // bytes before the status tables
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
@@ -302,25 +307,60 @@ constexpr int kOsMaxBlocks = 1024;  // persistent grid of a pass (two per CU and
 __device__ __forceinline__ int64_t os_chunks(int64_t n) { return (n + kOsChunk - 1) / kOsChunk; }
 
 // Digit counts of all passes (atomics into hist[pass][256], zeroed before),
-// and the first pass's status table cleared.
-__global__ void __launch_bounds__(256)
+// and the first pass's status table cleared.  Each thread counts groups of 8
+// consecutive keys and adds runs of equal digits with one LDS atomic: the
+// pairs of one splat are adjacent and share their depth digits, so most runs
+// are long.  kVec: keys is 16-byte aligned (two 16-byte loads per group).
+constexpr int kHistThreads = 1024;
+constexpr int kHistMaxBlocks = 512;
+template <bool kVec>
+__global__ void __launch_bounds__(kHistThreads)
 radix_hist_all(const uint32_t *__restrict__ keys, int64_t n, const uint64_t *__restrict__ n_dev,
                int passes, uint32_t *__restrict__ hist, uint64_t *__restrict__ st0) {
   __shared__ uint32_t h[kMaxPasses][256];
   n = eff_n(n, n_dev);
-  for (int k = threadIdx.x; k < kMaxPasses * 256; k += 256) (&h[0][0])[k] = 0;
+  for (int k = threadIdx.x; k < kMaxPasses * 256; k += kHistThreads) (&h[0][0])[k] = 0;
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-    const uint32_t k = keys[i];
-    for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255u], 1u);
+  const int64_t stride = (int64_t)gridDim.x * kHistThreads;
+  const int64_t groups = (n + 7) >> 3;
+  for (int64_t g = (int64_t)blockIdx.x * kHistThreads + threadIdx.x; g < groups; g += stride) {
+    const int64_t i0 = g << 3;
+    const int m = n - i0 < 8 ? (int)(n - i0) : 8;
+    uint32_t k[8];
+    if (kVec && m == 8) {
+      const uint4 a = reinterpret_cast<const uint4 *>(keys)[2 * g];
+      const uint4 b = reinterpret_cast<const uint4 *>(keys)[2 * g + 1];
+      k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
+      k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) k[j] = j < m ? keys[i0 + j] : 0u;
+    }
+    for (int p = 0; p < passes; ++p) {
+      const int sh = 8 * p;
+      uint32_t d = (k[0] >> sh) & 255u, c = 1;
+#pragma unroll
+      for (int j = 1; j < 8; ++j) {
+        if (j < m) {
+          const uint32_t e = (k[j] >> sh) & 255u;
+          if (e != d) {
+            atomicAdd(&h[p][d], c);
+            d = e;
+            c = 0;
+          }
+          ++c;
+        }
+      }
+      atomicAdd(&h[p][d], c);
+    }
   }
   const int64_t rows = os_chunks(n) * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < rows; i += stride) st0[i] = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kHistThreads + threadIdx.x; i < rows; i += stride)
+    st0[i] = 0;
   __syncthreads();
-  for (int p = 0; p < passes; ++p) {
-    const uint32_t c = h[p][threadIdx.x];
-    if (c) atomicAdd(&hist[p * 256 + threadIdx.x], c);
+  for (int k = threadIdx.x; k < passes * 256; k += kHistThreads) {
+    const uint32_t c = (&h[0][0])[k];
+    if (c) atomicAdd(&hist[k], c);
   }
 }
 
@@ -630,12 +670,13 @@ void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint
                      rect, cams, N, total, pair_cap, keys, vals, overflow);
 }
 
-void launch_upload_cams(const DevCam *host, int n, DevCam *dst, hipStream_t s) {
+void launch_upload_cams(const DevCam *host, int n, DevCam *dst, hipStream_t s, ZeroList z) {
   for (int b = 0; b < n; b += kCamsPerUpload) {
     CamPack p;
     const int m = n - b < kCamsPerUpload ? n - b : kCamsPerUpload;
     for (int k = 0; k < m; ++k) p.c[k] = host[b + k];
-    hipLaunchKernelGGL(upload_cams_kernel, dim3(1), dim3(256), 0, s, p, m, dst + b);
+    hipLaunchKernelGGL(upload_cams_kernel, dim3(1), dim3(256), 0, s, p, m, dst + b,
+                       b == 0 ? z : ZeroList{});
   }
 }
 
@@ -659,19 +700,24 @@ size_t sort_tmp_bytes(int64_t n) {
 int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint32_t *va,
                       uint32_t *kb, uint32_t *vb, int64_t n, int bits, void *tmp, hipStream_t s,
                       const uint64_t *n_dev, const uint32_t *gather_src, uint32_t *gather_dst,
-                      uint32_t *err) {
+                      uint32_t *err, uint32_t *zeroed_words) {
   if (n <= 0) return 0;
   const int64_t nch = (n + kOsChunk - 1) / kOsChunk;
-  uint32_t *words = (uint32_t *)tmp;
+  uint32_t *words = zeroed_words ? zeroed_words : (uint32_t *)tmp;
   uint64_t *st[2] = {(uint64_t *)((char *)tmp + kOsHead),
                      (uint64_t *)((char *)tmp + kOsHead) + nch * 256};
   const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
-  launch_fill_u32(words, 0u, kOsWords, s);
-  // few blocks: each adds its 256-bin histograms to the global table with
-  // atomics on the same 4 x 256 addresses as every other block
-  const int64_t hb = std::min<int64_t>((n + 4095) / 4096, 256);
-  hipLaunchKernelGGL(radix_hist_all, dim3((unsigned)hb), dim3(256), 0, s, k0, n, n_dev, passes,
-                     words, st[0]);
+  if (!zeroed_words) launch_fill_u32(words, 0u, kOsWords, s);
+  // two blocks per CU at most: each adds its histograms to the global table
+  // with atomics on the same passes x 256 addresses as every other block
+  const int64_t hb =
+      std::min<int64_t>((n + 8 * kHistThreads - 1) / (8 * kHistThreads), kHistMaxBlocks);
+  if (((uintptr_t)k0 & 15) == 0)
+    hipLaunchKernelGGL(radix_hist_all<true>, dim3((unsigned)hb), dim3(kHistThreads), 0, s, k0,
+                       n, n_dev, passes, words, st[0]);
+  else
+    hipLaunchKernelGGL(radix_hist_all<false>, dim3((unsigned)hb), dim3(kHistThreads), 0, s, k0,
+                       n, n_dev, passes, words, st[0]);
   const uint32_t *kin = k0, *vin = v0;
   uint32_t *kout = ka, *vout = va;
   int which = 0;
