@@ -273,6 +273,105 @@ __device__ __forceinline__ void load_sh(const float *__restrict__ sh, int64_t g,
   }
 }
 
+// SH rows of a block in LDS.  A splat's 3K coefficients are contiguous in
+// memory, so a thread reading or writing its own splat's row touches a
+// different cache line per lane on every access; the block instead moves
+// the rows of its splats [g0, g0 + nb) between memory and LDS with
+// consecutive lanes on consecutive 16-byte words, and each thread then works
+// on its own row at rows + t * kRow.  kRow pads 3K so that the rows of eight
+// consecutive lanes start on different LDS banks for 16-byte accesses (or is
+// odd for 4-byte ones).
+template <int K>
+struct ShRows {
+  static constexpr int kN = 3 * K;
+  static constexpr int kRow = (kN % 2) ? kN : (kN % 32 == 16 ? kN + 4 : kN);
+};
+
+template <int K, int NT>
+__device__ __forceinline__ void sh_rows_load(const float *__restrict__ sh, int64_t g0, int nb,
+                                             float *rows) {
+  constexpr int N = ShRows<K>::kN, R = ShRows<K>::kRow;
+  const float *src = sh + g0 * N;
+  const int total = nb * N;
+  int done = 0;
+  if ((((uintptr_t)src) & 15) == 0) {
+    const int n4 = total >> 2;
+    for (int e4 = threadIdx.x; e4 < n4; e4 += NT) {
+      const float4 t = reinterpret_cast<const float4 *>(src)[e4];
+      if constexpr (N % 4 == 0) {
+        const int r = (4 * e4) / N;
+        *reinterpret_cast<float4 *>(rows + r * R + (4 * e4 - r * N)) = t;
+      } else {
+        const float v[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = 4 * e4 + u;
+          const int r = e / N;
+          rows[r * R + (e - r * N)] = v[u];
+        }
+      }
+    }
+    done = 4 * n4;
+  }
+  for (int e = done + threadIdx.x; e < total; e += NT) {
+    const int r = e / N;
+    rows[r * R + (e - r * N)] = src[e];
+  }
+}
+
+// The rows back to memory (dst = rows, or dst + rows with accumulate).
+template <int K, int NT>
+__device__ __forceinline__ void sh_rows_store(float *__restrict__ dst_sh, int64_t g0, int nb,
+                                              const float *rows, int accumulate) {
+  constexpr int N = ShRows<K>::kN, R = ShRows<K>::kRow;
+  float *dst = dst_sh + g0 * N;
+  const int total = nb * N;
+  int done = 0;
+  if constexpr (N % 4 == 0) {
+    if ((((uintptr_t)dst) & 15) == 0) {
+      const int n4 = total >> 2;
+      for (int e4 = threadIdx.x; e4 < n4; e4 += NT) {
+        const int r = (4 * e4) / N;
+        float4 t = *reinterpret_cast<const float4 *>(rows + r * R + (4 * e4 - r * N));
+        float4 *d = reinterpret_cast<float4 *>(dst) + e4;
+        if (accumulate) {
+          const float4 o = *d;
+          t.x = o.x + t.x;
+          t.y = o.y + t.y;
+          t.z = o.z + t.z;
+          t.w = o.w + t.w;
+        }
+        *d = t;
+      }
+      done = 4 * n4;
+    }
+  }
+  for (int e = done + threadIdx.x; e < total; e += NT) {
+    const int r = e / N;
+    const float v = rows[r * R + (e - r * N)];
+    dst[e] = accumulate ? dst[e] + v : v;
+  }
+}
+
+// A thread's row into registers.
+template <int K>
+__device__ __forceinline__ void sh_row_read(const float *row, float *f) {
+  constexpr int N = ShRows<K>::kN;
+  if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < N / 4; ++i) {
+      const float4 t = reinterpret_cast<const float4 *>(row)[i];
+      f[4 * i] = t.x;
+      f[4 * i + 1] = t.y;
+      f[4 * i + 2] = t.z;
+      f[4 * i + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) f[i] = row[i];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Continuous per-(view, splat) quantities, binary64.
 // ---------------------------------------------------------------------------
@@ -755,7 +854,7 @@ __device__ __forceinline__ bool fdo_weights(const SceneDev &sc, const DevCam *__
                                               const DevOpts &opt, const uint8_t *__restrict__ flags,
                                               const int4 *__restrict__ rect,
                                               const float *__restrict__ accum, int64_t plane,
-                                              int64_t g, double2 &w) {
+                                              int64_t g, const float *shrow, double2 &w) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   double d = 0.0, nl = 0.0, nh = 0.0;
   const uint8_t fl = flags[g];
@@ -795,7 +894,7 @@ __device__ __forceinline__ bool fdo_weights(const SceneDev &sc, const DevCam *__
         double Y[K];
         sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
         float f[3 * K];
-        load_sh<K>(sc.sh, g, f);
+        sh_row_read<K>(shrow, f);
         bool live[3];
         colour_live<K>(f, Y, live);
         float gyl[3] = {0.0f, 0.0f, 0.0f}, gyh[3] = {0.0f, 0.0f, 0.0f};
@@ -840,29 +939,16 @@ __device__ __forceinline__ bool fdo_weights(const SceneDev &sc, const DevCam *__
   return conflict;
 }
 
-template <int DEG, bool MULTI, int MODE>
-__device__ __forceinline__ void preprocess_bwd_body(
+// The chain of splat g; its SH coefficients are read from, and dL/dSH
+// written to, its LDS row.
+template <int DEG, int MODE>
+__device__ __forceinline__ void preprocess_bwd_one(
     const SceneDev &sc, const DevCam *__restrict__ cams, int V, const DevOpts &opt,
     const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
-    const float *__restrict__ accum, int64_t plane, uint32_t *__restrict__ n_conflict,
-    float *g_means, float *g_scales, float *g_rots,
-    float *g_opac, float *g_sh, int accumulate) {
+    const float *__restrict__ accum, int64_t plane, double2 wgt, int64_t g, float *row,
+    float *g_means, float *g_scales, float *g_rots, float *g_opac, bool want_sh,
+    int accumulate) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double2 wgt = make_double2(0.0, 0.0);
-  if constexpr (MODE == kBwdFdo) {
-    // conflicts of this block, added once per block
-    __shared__ uint32_t blk_conf;
-    if (threadIdx.x == 0) blk_conf = 0;
-    __syncthreads();
-    bool conf = false;
-    if (g < sc.n) conf = fdo_weights<DEG>(sc, cams, opt, flags, rect, accum, plane, g, wgt);
-    const uint64_t m = __ballot(conf);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&blk_conf, (uint32_t)__popcll(m));
-    __syncthreads();
-    if (threadIdx.x == 0 && blk_conf && n_conflict) atomicAdd(n_conflict, blk_conf);
-  }
-  if (g >= sc.n) return;
   // the combined slots are formed and kept in binary64
   using Slot = typename std::conditional<MODE == kBwdFdo, double, float>::type;
   const bool is2d = sc.types[g] == 0;
@@ -913,14 +999,11 @@ __device__ __forceinline__ void preprocess_bwd_body(
   put(g_opac, g, gal);
 
   // ---- pass 2: colour, c_ch = max(0, 1/2 + sum_j f_j,ch Y_j(dir)) ----
+  // dL/dSH is summed over the views in the row, in place of the SH values
   float f[3 * K];
-  load_sh<K>(sc.sh, g, f);
-  float gsh[MULTI ? 3 * K : 1];
-  if constexpr (MULTI) {
+  sh_row_read<K>(row, f);
 #pragma unroll
-    for (int j = 0; j < 3 * K; ++j) gsh[j] = 0.0f;
-  }
-  bool wrote = false;
+  for (int j = 0; j < 3 * K; ++j) row[j] = 0.0f;
   for (int v = 0; v < V; ++v) {
     const int64_t i = (int64_t)v * sc.n + g;
     if (!(flags[i] & kValid)) continue;
@@ -940,58 +1023,75 @@ __device__ __forceinline__ void preprocess_bwd_body(
     colour_live<K>(f, Y, live);
     Slot gy[3];
     colour_chain<DEG>(f, Y, dir, dist, live, gcol, gy, gmu);
-    if constexpr (MULTI) {
+    if (want_sh) {
 #pragma unroll
       for (int j = 0; j < K; ++j)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) gsh[3 * j + ch] += (float)((double)gy[ch] * Y[j]);
-    } else if (g_sh) {
-      float *dst = g_sh + (size_t)g * 3 * K;
-#pragma unroll
-      for (int j = 0; j < K; ++j)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          const float val = (float)((double)gy[ch] * Y[j]);
-          dst[3 * j + ch] = accumulate ? dst[3 * j + ch] + val : val;
-        }
-      wrote = true;
+        for (int ch = 0; ch < 3; ++ch) row[3 * j + ch] += (float)((double)gy[ch] * Y[j]);
     }
   }
   for (int k = 0; k < 3; ++k) put(g_means, 3 * g + k, gmu[k]);
+}
+
+
+constexpr int kBwdThreads = 128;
+
+template <int DEG, int MODE>
+__device__ __forceinline__ void preprocess_bwd_body(
+    const SceneDev &sc, const DevCam *__restrict__ cams, int V, const DevOpts &opt,
+    const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
+    const float *__restrict__ accum, int64_t plane, uint32_t *__restrict__ n_conflict,
+    float *g_means, float *g_scales, float *g_rots,
+    float *g_opac, float *g_sh, int accumulate) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ float s_rows[kBwdThreads * ShRows<K>::kRow];
+  const int64_t g0 = (int64_t)blockIdx.x * kBwdThreads;
+  const int64_t g = g0 + threadIdx.x;
+  const int nb = (int)(sc.n - g0 < kBwdThreads ? sc.n - g0 : kBwdThreads);
+  sh_rows_load<K, kBwdThreads>(sc.sh, g0, nb, s_rows);
+  __syncthreads();
+  float *row = s_rows + threadIdx.x * ShRows<K>::kRow;
+  double2 wgt = make_double2(0.0, 0.0);
+  if constexpr (MODE == kBwdFdo) {
+    // conflicts of this block, added once per block
+    __shared__ uint32_t blk_conf;
+    if (threadIdx.x == 0) blk_conf = 0;
+    __syncthreads();
+    bool conf = false;
+    if (g < sc.n) conf = fdo_weights<DEG>(sc, cams, opt, flags, rect, accum, plane, g, row, wgt);
+    const uint64_t m = __ballot(conf);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&blk_conf, (uint32_t)__popcll(m));
+    __syncthreads();
+    if (threadIdx.x == 0 && blk_conf && n_conflict) atomicAdd(n_conflict, blk_conf);
+  }
+  if (g < sc.n) preprocess_bwd_one<DEG, MODE>(sc, cams, V, opt, flags, rect, accum, plane, wgt,
+                                             g, row, g_means, g_scales, g_rots, g_opac,
+                                             g_sh != nullptr, accumulate);
   if (g_sh) {
-    float *dst = g_sh + (size_t)g * 3 * K;
-    if constexpr (MULTI) {
-#pragma unroll
-      for (int j = 0; j < 3 * K; ++j) dst[j] = accumulate ? dst[j] + gsh[j] : gsh[j];
-    } else {
-      if (!wrote && !accumulate) {
-#pragma unroll
-        for (int j = 0; j < 3 * K; ++j) dst[j] = 0.0f;
-      }
-    }
+    __syncthreads();
+    sh_rows_store<K, kBwdThreads>(g_sh, g0, nb, s_rows, accumulate);
   }
 }
 
-template <int DEG, bool MULTI>
-__global__ void __launch_bounds__(128)
+template <int DEG>
+__global__ void __launch_bounds__(kBwdThreads)
 preprocess_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOpts opt,
                       const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
                       const float *__restrict__ accum, float *g_means, float *g_scales,
                       float *g_rots, float *g_opac, float *g_sh, int accumulate) {
-  preprocess_bwd_body<DEG, MULTI, kBwdPlain>(sc, cams, V, opt, flags, rect, accum, 0, nullptr,
-                                             g_means, g_scales, g_rots, g_opac, g_sh, accumulate);
+  preprocess_bwd_body<DEG, kBwdPlain>(sc, cams, V, opt, flags, rect, accum, 0, nullptr, g_means,
+                                      g_scales, g_rots, g_opac, g_sh, accumulate);
 }
 
 template <int DEG>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(kBwdThreads)
 fdo_fused_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, DevOpts opt,
                      const uint8_t *__restrict__ flags, const int4 *__restrict__ rect,
                      const float *__restrict__ accum, int64_t plane,
                      uint32_t *__restrict__ n_conflict, float *g_means, float *g_scales,
                      float *g_rots, float *g_opac, float *g_sh, int accumulate) {
-  preprocess_bwd_body<DEG, false, kBwdFdo>(sc, cams, 1, opt, flags, rect, accum, plane,
-                                           n_conflict, g_means, g_scales, g_rots, g_opac, g_sh,
-                                           accumulate);
+  preprocess_bwd_body<DEG, kBwdFdo>(sc, cams, 1, opt, flags, rect, accum, plane, n_conflict,
+                                    g_means, g_scales, g_rots, g_opac, g_sh, accumulate);
 }
 }  // namespace
 
@@ -1032,16 +1132,11 @@ void launch_preprocess_bwd(const SceneDev &sc, const DevCam *cams, int V, DevOpt
                            float *g_means, float *g_scales, float *g_rots, float *g_opac,
                            float *g_sh, int accumulate, hipStream_t s) {
   if (sc.n == 0) return;
-  const dim3 grid((unsigned)((sc.n + 127) / 128));
-#define HGS_BWD(D)                                                                             \
-  if (V == 1)                                                                                  \
-    hipLaunchKernelGGL((preprocess_bwd_kernel<D, false>), grid, dim3(128), 0, s, sc, cams, V,  \
-                       opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh,       \
-                       accumulate);                                                            \
-  else                                                                                         \
-    hipLaunchKernelGGL((preprocess_bwd_kernel<D, true>), grid, dim3(128), 0, s, sc, cams, V,   \
-                       opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh,       \
-                       accumulate)
+  const dim3 grid((unsigned)((sc.n + kBwdThreads - 1) / kBwdThreads));
+#define HGS_BWD(D)                                                                            \
+  hipLaunchKernelGGL(preprocess_bwd_kernel<D>, grid, dim3(kBwdThreads), 0, s, sc, cams, V,    \
+                     opt, flags, rect, accum, g_means, g_scales, g_rots, g_opac, g_sh,        \
+                     accumulate)
   HGS_BY_DEGREE(sc.sh_degree, HGS_BWD)
 #undef HGS_BWD
 }
@@ -1052,9 +1147,9 @@ void launch_fdo_fused_bwd(const SceneDev &sc, const DevCam *cams, DevOpts opt,
                           float *g_rots, float *g_opac, float *g_sh, int accumulate,
                           hipStream_t s) {
   if (sc.n == 0) return;
-  const dim3 grid((unsigned)((sc.n + 127) / 128));
+  const dim3 grid((unsigned)((sc.n + kBwdThreads - 1) / kBwdThreads));
 #define HGS_F(D)                                                                              \
-  hipLaunchKernelGGL(fdo_fused_bwd_kernel<D>, grid, dim3(128), 0, s, sc, cams, opt, flags, rect, \
+  hipLaunchKernelGGL(fdo_fused_bwd_kernel<D>, grid, dim3(kBwdThreads), 0, s, sc, cams, opt, flags, rect, \
                      accum, plane, n_conflict, g_means, g_scales, g_rots, g_opac, g_sh,         \
                      accumulate)
   HGS_BY_DEGREE(sc.sh_degree, HGS_F)
