@@ -51,6 +51,7 @@ struct hgs_state {
   uint32_t *keys = nullptr;  // tile id of each sorted pair
   uint32_t *vals = nullptr;  // instance id (view * N + splat) of each sorted pair
   uint2 *ranges = nullptr;
+  uint32_t *order = nullptr;  // tiles by pair-list length, longest first
   float *T_final = nullptr;
   uint32_t *last = nullptr, *n_contrib = nullptr, *wcount = nullptr;
   int64_t D = -1;        // pairs in the sorted list, min(D_total, cap), once read back
@@ -558,6 +559,13 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc_t(st, &st->tiles, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->zbits, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->rect, (size_t)VN));
+  // packed tile rectangles (views of at most 256 x 256 tiles), and the same
+  // in depth order
+  uint32_t *prect = nullptr, *prect_s = nullptr;
+  if (st->tiles_x <= 256 && st->tiles_y <= 256) {
+    ST_HIP(dalloc_t(st, &prect, (size_t)VN));
+    ST_HIP(dalloc_t(st, &prect_s, (size_t)VN));
+  }
   ST_HIP(dalloc_t(st, &st->flags, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->offsets, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->total, (size_t)1));
@@ -568,6 +576,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   void *scan_tmp = nullptr;
   ST_HIP(dalloc(st, &scan_tmp, scan_tmp_bytes(VN)));
   ST_HIP(dalloc_t(st, &st->ranges, (size_t)n_tiles));
+  ST_HIP(dalloc_t(st, &st->order, (size_t)n_tiles));
   ST_HIP(dalloc_t(st, &st->T_final, (size_t)P));
   ST_HIP(dalloc_t(st, &st->last, (size_t)P));
   ST_HIP(dalloc_t(st, &st->n_contrib, (size_t)P));
@@ -600,14 +609,16 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   {
     StageTimer t(ctx, HGS_STAGE_PREPROCESS, st->stream);
     launch_preprocess(st->scene, st->cams, n_views, st->opt, st->rec, st->tiles, st->zbits,
-                      st->rect, st->flags, st->stream);
+                      st->rect, st->flags, prect, st->stream);
   }
   const uint32_t *order = nullptr;
   {
     // instances in depth order; the last pass also gathers their tile counts
+    // (and packed rectangles)
     StageTimer t(ctx, HGS_STAGE_DEPTH_SORT, st->stream);
     const int w = launch_radix_sort(st->zbits, nullptr, za, oa, zb, ob, VN, 32, dsort_tmp,
-                                    st->stream, nullptr, st->tiles, cnt, st->overflow, dwords);
+                                    st->stream, nullptr, prect ? prect : st->tiles, cnt,
+                                    st->overflow, dwords, prect_s);
     order = w ? ob : oa;
   }
   {
@@ -655,7 +666,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(commit(st, 1, st->stream, cap_mode));
   {
     StageTimer t(ctx, HGS_STAGE_DUPLICATE, st->stream);
-    launch_duplicate(order, st->offsets, st->tiles, st->rect, st->cams, n_views, st->N,
+    launch_duplicate(order, st->offsets, st->tiles, st->rect, prect_s, st->cams, n_views, st->N,
                      (uint64_t)cap, kb, vb, st->overflow, st->stream);
   }
   int tile_bits = 0;
@@ -671,6 +682,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
     StageTimer t(ctx, HGS_STAGE_RANGES, st->stream);
     launch_fill_u32(reinterpret_cast<uint32_t *>(st->ranges), 0u, 2 * n_tiles, st->stream);
     launch_ranges(st->keys, cap, st->ranges, st->stream, st->total);
+    launch_tile_order(st->ranges, (int)n_tiles, st->order, st->stream);
   }
 
   ro.T_final = st->T_final;
@@ -680,7 +692,7 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   st->has_wcount = ctx->profile;
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_FWD, st->stream);
-    launch_raster_fwd(st->ranges, st->vals, st->rec, st->cams, n_views, st->n_tiles, W, H,
+    launch_raster_fwd(st->ranges, st->order, st->vals, st->rec, st->n_tiles, W, H,
                       st->tiles_x, st->tiles_per_view, st->opt, ro, st->bmask, st->stream);
   }
   if (!cap_mode && ctx->pair_cap <= 0) {
@@ -753,7 +765,8 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_image
   }
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_BWD, s);
-    launch_raster_bwd(st->ranges, st->vals, st->rec, st->n_tiles, st->W, st->H, st->tiles_x,
+    launch_raster_bwd(st->ranges, st->order, st->vals, st->rec, st->n_tiles, st->W, st->H,
+                      st->tiles_x,
                       st->tiles_per_view, st->opt, st->T_final, st->last, st->bmask, gi, accum,
                       s);
   }
@@ -840,7 +853,8 @@ hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *st, const hgs_grad_i
   x.rgb[1] = grad_high_rgb;
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_BWD, s);
-    launch_raster_bwd_sets(st->ranges, st->vals, st->rec, st->n_tiles, st->W, st->H, st->tiles_x,
+    launch_raster_bwd_sets(st->ranges, st->order, st->vals, st->rec, st->n_tiles, st->W, st->H,
+                           st->tiles_x,
                            st->tiles_per_view, st->opt, st->T_final, st->last, st->bmask, gi, x,
                            accum, plane, s);
   }

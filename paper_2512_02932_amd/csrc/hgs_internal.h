@@ -95,9 +95,25 @@ __device__ inline int slot_of_tile(const Slot *slots, int ns, int t) {
 
 // ----- launchers (all enqueue on `s`) -----
 // flags per (view, splat): bit 0 valid, bit 1 normal negated, bits 2-3 normal axis
+// prect (may be NULL; only for views of at most 256 x 256 tiles): each
+// instance's tile rectangle packed in 32 bits, see pack_tile_rect.
 void launch_preprocess(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt,
                        Record *rec, uint32_t *tiles, uint32_t *zbits, int4 *rect,
-                       uint8_t *flags, hipStream_t s);
+                       uint8_t *flags, uint32_t *prect, hipStream_t s);
+
+// Tile rectangle of an instance in one word: first tile column and row
+// (bits 0-7, 8-15), width and height in tiles minus one (16-23, 24-31);
+// kNoTiles for an instance that covers no tile.  Holds for views of at most
+// 256 x 256 tiles.
+constexpr uint32_t kNoTiles = 0xffffffffu;
+__host__ __device__ inline uint32_t pack_tile_rect(int4 r) {
+  const uint32_t tx0 = (uint32_t)r.x >> 4, ty0 = (uint32_t)r.y >> 4;
+  return tx0 | (ty0 << 8) | ((((uint32_t)r.z >> 4) - tx0) << 16) |
+         ((((uint32_t)r.w >> 4) - ty0) << 24);
+}
+__host__ __device__ inline uint32_t packed_tile_count(uint32_t p) {
+  return p == kNoTiles ? 0u : (((p >> 16) & 255u) + 1u) * ((p >> 24) + 1u);
+}
 // The same for a batch of requests: instances [0, *n_inst) of the slot
 // table (grid sized by the capacity inst_cap).
 void launch_preprocess_slots(const Slot *slots, const int *n_slots, const uint64_t *n_inst,
@@ -139,9 +155,12 @@ void launch_gather(const uint32_t *in, const uint32_t *idx, int64_t n, uint32_t 
 // offsets[j], the exclusive scan of tiles[order[.]].
 // Pairs at or past pair_cap are dropped and set *overflow = 1 (overflow may
 // be NULL only if the caller knows the pairs fit).
+// prect_sorted (may be NULL): the packed tile rectangles in the order
+// `order` (from the depth sort's gather); then tiles and rect are not read.
 void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint32_t *tiles,
-                      const int4 *rect, const DevCam *cams, int V, int64_t N, uint64_t pair_cap,
-                      uint32_t *keys, uint32_t *vals, uint32_t *overflow, hipStream_t s);
+                      const int4 *rect, const uint32_t *prect_sorted, const DevCam *cams, int V,
+                      int64_t N, uint64_t pair_cap, uint32_t *keys, uint32_t *vals,
+                      uint32_t *overflow, hipStream_t s);
 
 // Copies n host cameras to dst through kernel arguments (up to
 // kCamsPerUpload per launch), so that a captured graph carries the camera
@@ -169,7 +188,9 @@ void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
 // (ka, va) and (kb, vb).  k0/v0 may alias kb/vb but not ka/va.  Returns 0 if
 // the result is in (ka, va), 1 if in (kb, vb).  `tmp` holds
 // sort_tmp_bytes(n) bytes.  If gather_dst is given, the last pass also
-// writes gather_dst[j] = gather_src[value j] of the sorted order.  err (may
+// writes gather_dst[j] = gather_src[value j] of the sorted order; with
+// gather_dst2 as well, gather_src holds packed tile rectangles and the pass
+// writes gather_dst[j] = their tile counts, gather_dst2[j] = the words.  err (may
 // be NULL): bit 1 is set if a pass's look-back gave up (never expected).
 // zeroed_words (may be NULL): kSortWords uint32 the caller has cleared on
 // the stream, used for the sort's digit counts and tickets instead of the
@@ -180,7 +201,7 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
                       uint32_t *kb, uint32_t *vb, int64_t n, int bits, void *tmp, hipStream_t s,
                       const uint64_t *n_dev = nullptr, const uint32_t *gather_src = nullptr,
                       uint32_t *gather_dst = nullptr, uint32_t *err = nullptr,
-                      uint32_t *zeroed_words = nullptr);
+                      uint32_t *zeroed_words = nullptr, uint32_t *gather_dst2 = nullptr);
 
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
@@ -202,10 +223,14 @@ struct RasterOut {
 inline int64_t raster_mask_words(int64_t pairs, int64_t tiles) {
   return 8 * ((pairs >> 6) + tiles + 1);
 }
-void launch_raster_fwd(const uint2 *ranges, const uint32_t *vals, const Record *rec,
-                       const DevCam *cams, int V, int n_tiles_total, int W, int H,
-                       int tiles_x, int tiles_per_view, DevOpts opt, RasterOut out,
-                       uint64_t *bmask, hipStream_t s);
+// order[n_tiles_total]: the tiles by pair-list length, longest first (from
+// ranges), the order in which the raster launches below start their tiles.
+void launch_tile_order(const uint2 *ranges, int n_tiles_total, uint32_t *order, hipStream_t s);
+// order (may be NULL: tile index order): from launch_tile_order.
+void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
+                       const Record *rec, int n_tiles_total, int W, int H, int tiles_x,
+                       int tiles_per_view, DevOpts opt, RasterOut out, uint64_t *bmask,
+                       hipStream_t s);
 
 // Forward of a batch of slots on a persistent grid of n_blocks wave64s
 // that pull (tile, quadrant) units from *queue (zero at launch) up to the
@@ -217,21 +242,22 @@ void launch_raster_fwd_queue(const uint2 *ranges, const uint32_t *vals, const Re
 struct RasterGradIn {
   const float *rgb, *alpha, *depth, *normal;
 };
-void launch_raster_bwd(const uint2 *ranges, const uint32_t *vals, const Record *rec,
-                       int n_tiles_total, int W, int H, int tiles_x, int tiles_per_view,
-                       DevOpts opt, const float *T_final, const uint32_t *last,
-                       const uint64_t *bmask, RasterGradIn g, float *accum, hipStream_t s);
+void launch_raster_bwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
+                       const Record *rec, int n_tiles_total, int W, int H, int tiles_x,
+                       int tiles_per_view, DevOpts opt, const float *T_final,
+                       const uint32_t *last, const uint64_t *bmask, RasterGradIn g,
+                       float *accum, hipStream_t s);
 // Two RGB-only cotangent images [V,3,H,W] (NULL = zero).
 struct RgbSets {
   const float *rgb[2];
 };
 // The backward with three cotangent sets in one traversal: g (all channels)
 // into accum, rgb2.rgb[k] into accum + (k + 1) * plane (floats).
-void launch_raster_bwd_sets(const uint2 *ranges, const uint32_t *vals, const Record *rec,
-                            int n_tiles_total, int W, int H, int tiles_x, int tiles_per_view,
-                            DevOpts opt, const float *T_final, const uint32_t *last,
-                            const uint64_t *bmask, RasterGradIn g, RgbSets rgb2, float *accum,
-                            int64_t plane, hipStream_t s);
+void launch_raster_bwd_sets(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
+                            const Record *rec, int n_tiles_total, int W, int H, int tiles_x,
+                            int tiles_per_view, DevOpts opt, const float *T_final,
+                            const uint32_t *last, const uint64_t *bmask, RasterGradIn g,
+                            RgbSets rgb2, float *accum, int64_t plane, hipStream_t s);
 
 // Adaptive Type Exchange in place on n primitives (rotations: float4 per
 // primitive, 16-byte aligned).  counts (may be NULL): [0] += switched 3D->2D,

@@ -495,6 +495,10 @@ __device__ __forceinline__ double col_of(const double *M9, int row, int axis) {
 // flags per (view, splat): bit 0 valid, bit 1 normal negated, bits 2-3 axis
 constexpr uint8_t kValid = 1, kFlip = 2;
 
+__device__ __forceinline__ int4 rect_of(const Structural &st) {
+  return make_int4(st.px0, st.py0, st.px1, st.py1);
+}
+
 // Splat g of scene sc seen by camera c, written as instance i.
 template <int DEG>
 __device__ __forceinline__ void preprocess_one(const SceneDev &sc, const DevCam &c, int64_t g,
@@ -503,7 +507,8 @@ __device__ __forceinline__ void preprocess_one(const SceneDev &sc, const DevCam 
                                                uint32_t *__restrict__ tiles,
                                                uint32_t *__restrict__ zbits,
                                                int4 *__restrict__ rect,
-                                               uint8_t *__restrict__ flags) {
+                                               uint8_t *__restrict__ flags,
+                                               uint32_t *__restrict__ prect = nullptr) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const bool is2d = sc.types[g] == 0;
   const float m[3] = {sc.means[3 * g], sc.means[3 * g + 1], sc.means[3 * g + 2]};
@@ -515,6 +520,7 @@ __device__ __forceinline__ void preprocess_one(const SceneDev &sc, const DevCam 
   tiles[i] = st.valid ? st.tiles : 0u;
   zbits[i] = st.zbits;
   rect[i] = make_int4(st.px0, st.py0, st.px1, st.py1);
+  if (prect) prect[i] = st.valid ? pack_tile_rect(rect_of(st)) : kNoTiles;
   flags[i] = (uint8_t)((st.valid ? kValid : 0) | (st.flip ? kFlip : 0) | (st.axis << 2));
   if (!st.valid) return;
 
@@ -584,13 +590,13 @@ __global__ void __launch_bounds__(256)
 preprocess_kernel(SceneDev sc, const DevCam *__restrict__ cams, int V, DevOpts opt,
                   Record *__restrict__ rec, uint32_t *__restrict__ tiles,
                   uint32_t *__restrict__ zbits, int4 *__restrict__ rect,
-                  uint8_t *__restrict__ flags) {
+                  uint8_t *__restrict__ flags, uint32_t *__restrict__ prect) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)V * sc.n;
   if (i >= total) return;
   const int v = (int)(i / sc.n);
   const int64_t g = i - (int64_t)v * sc.n;
-  preprocess_one<DEG>(sc, cams[v], g, i, opt, rec, tiles, zbits, rect, flags);
+  preprocess_one<DEG>(sc, cams[v], g, i, opt, rec, tiles, zbits, rect, flags, prect);
 }
 
 // A batch of requests (scene, camera): instance i < *n_inst belongs to the
@@ -1097,16 +1103,16 @@ fdo_fused_bwd_kernel(SceneDev sc, const DevCam *__restrict__ cams, DevOpts opt,
 
 void launch_preprocess(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt, Record *rec,
                        uint32_t *tiles, uint32_t *zbits, int4 *rect, uint8_t *flags,
-                       hipStream_t s) {
+                       uint32_t *prect, hipStream_t s) {
   const int64_t total = (int64_t)V * sc.n;
   if (total == 0) return;
   const int bs = 256;
   const dim3 grid((unsigned)((total + bs - 1) / bs));
   switch (sc.sh_degree) {
-    case 0: hipLaunchKernelGGL(preprocess_kernel<0>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags); break;
-    case 1: hipLaunchKernelGGL(preprocess_kernel<1>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags); break;
-    case 2: hipLaunchKernelGGL(preprocess_kernel<2>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags); break;
-    default: hipLaunchKernelGGL(preprocess_kernel<3>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags); break;
+    case 0: hipLaunchKernelGGL(preprocess_kernel<0>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags, prect); break;
+    case 1: hipLaunchKernelGGL(preprocess_kernel<1>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags, prect); break;
+    case 2: hipLaunchKernelGGL(preprocess_kernel<2>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags, prect); break;
+    default: hipLaunchKernelGGL(preprocess_kernel<3>, grid, dim3(bs), 0, s, sc, cams, V, opt, rec, tiles, zbits, rect, flags, prect); break;
   }
 }
 

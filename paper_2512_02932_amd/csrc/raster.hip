@@ -135,15 +135,18 @@ __device__ __forceinline__ Quad make_quad(int tile, int v, int r, int quad, int 
   return q;
 }
 
-// Forward: blocks 64g + 8j + x hold tile 8g + x, quadrant j / 2, half j % 2,
-// so the eight waves of a tile share x = block id mod 8, the XCD the
-// dispatcher assigns them to.  Returns false for the second-half wave of a
+// Forward: blocks 64g + 8j + x hold tile slot 8g + x, quadrant j / 2, half
+// j % 2, so the eight waves of a tile share x = block id mod 8, the XCD the
+// dispatcher assigns them to.  Slot s is tile order[s] (longest pair lists
+// first, see tile_order_kernel), or tile s without an order.  Returns false for the second-half wave of a
 // tile that is not split (that wave has nothing to do).
-__device__ __forceinline__ bool quad_of(const uint2 *ranges, int n_tiles, int W, int H,
-                                        int tiles_x, int tiles_per_view, Quad &q, uint2 &rg) {
+__device__ __forceinline__ bool quad_of(const uint2 *ranges, const uint32_t *order, int n_tiles,
+                                        int W, int H, int tiles_x, int tiles_per_view, Quad &q,
+                                        uint2 &rg) {
   const int b = blockIdx.x;
-  const int tile = (b >> 6) * 8 + (b & 7);
-  if (tile >= n_tiles) return false;
+  const int slot = (b >> 6) * 8 + (b & 7);
+  if (slot >= n_tiles) return false;
+  const int tile = order ? (int)order[slot] : slot;
   const int j = (b >> 3) & 7;
   rg = ranges[tile];
   const bool split = rg.y - rg.x >= kSplitLen;
@@ -155,13 +158,14 @@ __device__ __forceinline__ bool quad_of(const uint2 *ranges, int n_tiles, int W,
 
 // Backward: whole quadrants (the backward is bound by its total work, and a
 // half quadrant repeats a pair's per-pair cost for half the pixels).
-// Blocks 32g + 8q + x hold tile 8g + x, quadrant q.
-__device__ __forceinline__ bool quad_of_full(const uint2 *ranges, int n_tiles, int W, int H,
-                                             int tiles_x, int tiles_per_view, Quad &q,
-                                             uint2 &rg) {
+// Blocks 32g + 8q + x hold tile slot 8g + x, quadrant q.
+__device__ __forceinline__ bool quad_of_full(const uint2 *ranges, const uint32_t *order,
+                                             int n_tiles, int W, int H, int tiles_x,
+                                             int tiles_per_view, Quad &q, uint2 &rg) {
   const int b = blockIdx.x;
-  const int tile = (b >> 5) * 8 + (b & 7);
-  if (tile >= n_tiles) return false;
+  const int slot = (b >> 5) * 8 + (b & 7);
+  if (slot >= n_tiles) return false;
+  const int tile = order ? (int)order[slot] : slot;
   rg = ranges[tile];
   const int v = tile / tiles_per_view;
   q = make_quad(tile, v, tile - v * tiles_per_view, (b >> 3) & 3, W, H, tiles_x);
@@ -330,24 +334,28 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
         if (k >= k_end) break;
         const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
                      r4 = srec[4][k];
-        // both exponent forms, then a select on the type: no branch
-        const bool two = __float_as_int(r4.w) < 0;
+        // the type is the same at every lane (one record): a scalar branch,
+        // so a 3D pair does not pay for the 2D form's reciprocal
+        const bool two = !is3d_of(r4);
         float e, d;
         {
 #pragma clang fp contract(off)
           const float xr = q.fx - r0.x, yr = q.fy - r0.y;
-          const float dx = xr - r1.x, dy = yr - r1.y;
-          const float t = __builtin_fmaf(r1.w, dy, r1.z * dx);
-          const float u3 = r2.x * dy;
-          const float e3 = __builtin_fmaf(dx, t, u3 * dy);
-          const float U = __builtin_fmaf(r1.x, xr, __builtin_fmaf(r1.y, yr, r1.z));
-          const float V = __builtin_fmaf(r1.w, xr, __builtin_fmaf(r2.x, yr, r2.y));
-          const float Wh = __builtin_fmaf(r2.z, xr, __builtin_fmaf(r2.w, yr, r3.x));
-          const float rw = __builtin_amdgcn_rcpf(Wh);
-          const float uu = U * rw, vv = V * rw;
-          const float e2 = __builtin_fmaf(uu, uu, vv * vv);
-          e = two ? e2 : e3;
-          d = two ? rw : r2.y;
+          if (two) {
+            const float U = __builtin_fmaf(r1.x, xr, __builtin_fmaf(r1.y, yr, r1.z));
+            const float V = __builtin_fmaf(r1.w, xr, __builtin_fmaf(r2.x, yr, r2.y));
+            const float Wh = __builtin_fmaf(r2.z, xr, __builtin_fmaf(r2.w, yr, r3.x));
+            const float rw = __builtin_amdgcn_rcpf(Wh);
+            const float uu = U * rw, vv = V * rw;
+            e = __builtin_fmaf(uu, uu, vv * vv);
+            d = rw;
+          } else {
+            const float dx = xr - r1.x, dy = yr - r1.y;
+            const float t = __builtin_fmaf(r1.w, dy, r1.z * dx);
+            const float u3 = r2.x * dy;
+            e = __builtin_fmaf(dx, t, u3 * dy);
+            d = r2.y;
+          }
         }
         const float raw = fabsf(r4.w) * exp2_neg(e);
         // active: raw >= thr (false for NaN).  An inactive pair has a = 0,
@@ -411,14 +419,15 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
 // Views of one size: the block id picks the tile and quadrant (quad_of).
 template <bool kAcct>
 __global__ void __launch_bounds__(kWave)
-raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
-                  const Record *__restrict__ rec, int n_tiles, int W, int H, int tiles_x,
-                  int tiles_per_view, DevOpts opt, RasterOut out, uint64_t *__restrict__ bmask) {
+raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ order,
+                  const uint32_t *__restrict__ vals, const Record *__restrict__ rec, int n_tiles,
+                  int W, int H, int tiles_x, int tiles_per_view, DevOpts opt, RasterOut out,
+                  uint64_t *__restrict__ bmask) {
   __shared__ float4 srec[5][kWave];
   __shared__ uint32_t spos[kWave];
   Quad q;
   uint2 rg;
-  if (!quad_of(ranges, n_tiles, W, H, tiles_x, tiles_per_view, q, rg)) return;
+  if (!quad_of(ranges, order, n_tiles, W, H, tiles_x, tiles_per_view, q, rg)) return;
   const int64_t hw = (int64_t)H * W, v = q.v;
   ViewOut vo;
   vo.rgb = out.rgb ? out.rgb + v * 3 * hw : nullptr;
@@ -599,7 +608,8 @@ struct PackDst {
 // planes accum, accum + plane, accum + 2 plane.
 template <int NS>
 __global__ void __launch_bounds__(kWave)
-raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
+raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ order,
+                  const uint32_t *__restrict__ vals,
                   const Record *__restrict__ rec, int n_tiles, int W, int H, int tiles_x,
                   int tiles_per_view, DevOpts opt, const float *__restrict__ T_final,
                   const uint32_t *__restrict__ last_in, RasterGradIn gin, RgbSets rgb2,
@@ -609,7 +619,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   __shared__ uint32_t spos[kWave];
   Quad q;
   uint2 rg;
-  if (!quad_of_full(ranges, n_tiles, W, H, tiles_x, tiles_per_view, q, rg)) return;
+  if (!quad_of_full(ranges, order, n_tiles, W, H, tiles_x, tiles_per_view, q, rg)) return;
   const int lane = threadIdx.x;
 
   float T = 1.0f;
@@ -799,6 +809,91 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   }
 }
 
+// Tile order of the raster launches: tiles by pair-list length, longest
+// first, in 32 buckets (empty; under 128; then steps of 128 up to 3840 and
+// more), ascending tile index inside a bucket.  The dispatcher starts
+// blocks in id order, so the waves that walk the longest lists start first
+// instead of wherever their tiles sit in the image, and the short ones fill
+// in behind them.  One workgroup of 16 waves, each on a contiguous run of
+// tiles, 64 at a time: the lanes with the same bucket find each other with
+// five ballots (one per bucket bit), the highest of them adds the group's
+// size to the wave's count of that bucket in LDS; an exclusive scan over
+// (bucket descending, wave) gives each wave's bases; the second sweep ranks
+// the same groups again and scatters.
+constexpr int kOrderWaves = 16, kOrderBits = 5, kOrderBuckets = 1 << kOrderBits;
+__device__ __forceinline__ int order_bucket(uint2 r) {
+  const uint32_t n = r.y - r.x;
+  return n == 0 ? 0 : 1 + (int)min((uint32_t)(kOrderBuckets - 2), n >> 7);
+}
+
+// Lanes of the wave that hold the same bucket as this one (among `valid`).
+__device__ __forceinline__ uint64_t bucket_peers(int b, bool valid) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int k = 0; k < kOrderBits; ++k) {
+    const bool bit = (b >> k) & 1;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+__global__ void __launch_bounds__(kOrderWaves * kWave)
+tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, uint32_t *__restrict__ order) {
+  // per (bucket, wave) counts, then bases, at entry(bucket)
+  __shared__ uint32_t s_cnt[kOrderBuckets * kOrderWaves];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  for (int e = threadIdx.x; e < kOrderBuckets * kOrderWaves; e += kOrderWaves * kWave)
+    s_cnt[e] = 0;
+  __syncthreads();
+  const int per = ((n_tiles + kOrderWaves - 1) / kOrderWaves + kWave - 1) & ~(kWave - 1);
+  const int t0 = w * per, t1 = min(n_tiles, t0 + per);
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  auto entry = [&](int b) { return (kOrderBuckets - 1 - b) * kOrderWaves + w; };
+  for (int tb = t0; tb < t1; tb += kWave) {
+    const int t = tb + lane;
+    const bool valid = t < t1;
+    const int b = order_bucket(ranges[min(t, t1 - 1)]);
+    const uint64_t peers = bucket_peers(b, valid);
+    // the highest lane of each group; a wave's own entries, so no other
+    // wave writes them
+    if (valid && (peers >> lane) == 1ull) s_cnt[entry(b)] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  if (w == 0) {  // exclusive scan of the entries, eight per lane
+    constexpr int kPer = kOrderBuckets * kOrderWaves / kWave;
+    uint32_t c[kPer], sum = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      c[i] = s_cnt[kPer * lane + i];
+      sum += c[i];
+    }
+    uint32_t inc = sum;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t o = (uint32_t)__shfl_up((int)inc, d);
+      inc += lane >= d ? o : 0u;
+    }
+    uint32_t base = inc - sum;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      s_cnt[kPer * lane + i] = base;
+      base += c[i];
+    }
+  }
+  __syncthreads();
+  for (int tb = t0; tb < t1; tb += kWave) {
+    const int t = tb + lane;
+    const bool valid = t < t1;
+    const int b = order_bucket(ranges[min(t, t1 - 1)]);
+    const uint64_t peers = bucket_peers(b, valid);
+    const uint32_t at = valid ? s_cnt[entry(b)] : 0u;
+    if (valid) order[at + (uint32_t)__popcll(peers & below)] = (uint32_t)t;
+    // every lane has read its base before the group's highest lane moves it
+    if (valid && (peers >> lane) == 1ull) s_cnt[entry(b)] = at + (uint32_t)__popcll(peers);
+  }
+}
+
 // Blocks: 64 per group of 8 tiles (four quadrants of two halves each) for
 // the forward, see quad_of; 32 (four quadrants) for the backward.
 unsigned quad_blocks(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 64u; }
@@ -806,21 +901,26 @@ unsigned quad_blocks_full(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 
 
 }  // namespace
 
-void launch_raster_fwd(const uint2 *ranges, const uint32_t *vals, const Record *rec,
-                       const DevCam *cams, int V, int n_tiles_total, int W, int H, int tiles_x,
+void launch_tile_order(const uint2 *ranges, int n_tiles_total, uint32_t *order,
+                       hipStream_t s) {
+  if (n_tiles_total <= 0) return;
+  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderWaves * kWave), 0, s, ranges,
+                     n_tiles_total, order);
+}
+
+void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
+                       const Record *rec, int n_tiles_total, int W, int H, int tiles_x,
                        int tiles_per_view, DevOpts opt, RasterOut out, uint64_t *bmask,
                        hipStream_t s) {
-  (void)cams;
-  (void)V;
   if (n_tiles_total == 0) return;
   if (out.wcount)
     hipLaunchKernelGGL(raster_fwd_kernel<true>, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0,
-                       s, ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
-                       out, bmask);
+                       s, ranges, order, vals, rec, n_tiles_total, W, H, tiles_x,
+                       tiles_per_view, opt, out, bmask);
   else
     hipLaunchKernelGGL(raster_fwd_kernel<false>, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0,
-                       s, ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
-                       out, bmask);
+                       s, ranges, order, vals, rec, n_tiles_total, W, H, tiles_x,
+                       tiles_per_view, opt, out, bmask);
 }
 
 void launch_raster_fwd_queue(const uint2 *ranges, const uint32_t *vals, const Record *rec,
@@ -831,24 +931,25 @@ void launch_raster_fwd_queue(const uint2 *ranges, const uint32_t *vals, const Re
                      vals, rec, slots, n_slots, n_tiles, opt, queue);
 }
 
-void launch_raster_bwd(const uint2 *ranges, const uint32_t *vals, const Record *rec,
-                       int n_tiles_total, int W, int H, int tiles_x, int tiles_per_view,
-                       DevOpts opt, const float *T_final, const uint32_t *last,
-                       const uint64_t *bmask, RasterGradIn g, float *accum, hipStream_t s) {
+void launch_raster_bwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
+                       const Record *rec, int n_tiles_total, int W, int H, int tiles_x,
+                       int tiles_per_view, DevOpts opt, const float *T_final,
+                       const uint32_t *last, const uint64_t *bmask, RasterGradIn g,
+                       float *accum, hipStream_t s) {
   if (n_tiles_total == 0) return;
   hipLaunchKernelGGL(raster_bwd_kernel<1>, dim3(quad_blocks_full(n_tiles_total)), dim3(kWave), 0, s,
-                     ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
+                     ranges, order, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
                      T_final, last, g, RgbSets{}, accum, (int64_t)0, bmask);
 }
 
-void launch_raster_bwd_sets(const uint2 *ranges, const uint32_t *vals, const Record *rec,
-                            int n_tiles_total, int W, int H, int tiles_x, int tiles_per_view,
-                            DevOpts opt, const float *T_final, const uint32_t *last,
-                            const uint64_t *bmask, RasterGradIn g, RgbSets rgb2, float *accum,
-                            int64_t plane, hipStream_t s) {
+void launch_raster_bwd_sets(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
+                            const Record *rec, int n_tiles_total, int W, int H, int tiles_x,
+                            int tiles_per_view, DevOpts opt, const float *T_final,
+                            const uint32_t *last, const uint64_t *bmask, RasterGradIn g,
+                            RgbSets rgb2, float *accum, int64_t plane, hipStream_t s) {
   if (n_tiles_total <= 0) return;
   hipLaunchKernelGGL(raster_bwd_kernel<3>, dim3(quad_blocks_full(n_tiles_total)), dim3(kWave), 0, s,
-                     ranges, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
+                     ranges, order, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
                      T_final, last, g, rgb2, accum, plane, bmask);
 }
 

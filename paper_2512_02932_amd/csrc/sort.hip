@@ -223,18 +223,87 @@ __device__ __forceinline__ void emit_pairs(const DevCam &c, int4 r, uint32_t i, 
 }
 
 // Views of one scene: instance i = view * N + splat.  Pairs at or past
-// `cap` are dropped and raise *overflow.
+// `cap` are dropped and raise *overflow.  One wave per 64 consecutive
+// instances in depth order: their runs [offsets[j], offsets[j] + tiles[i])
+// are contiguous, and the lanes write the wave's pairs 64 at a time, each
+// lane finding the instance that owns its position by a binary search over
+// the lanes' run starts.  The stores are coalesced, and a splat with many
+// tiles does not hold up the other 63 lanes.
+// kPacked: the tile rectangles come packed and in depth order (prect_s[j]),
+// so every read is sequential; otherwise tiles[i] and rect[i].
+template <bool kPacked>
 __global__ void __launch_bounds__(256)
 duplicate_kernel(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
                  const uint32_t *__restrict__ tiles, const int4 *__restrict__ rect,
+                 const uint32_t *__restrict__ prect_s,
                  const DevCam *__restrict__ cams, int64_t N, int64_t total, uint64_t cap,
                  uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
                  uint32_t *__restrict__ overflow) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= total) return;
-  const uint32_t i = order[j];
-  if (tiles[i] == 0) return;
-  emit_pairs(cams[i / N], rect[i], i, offsets[j], cap, keys, vals, overflow);
+  const int lane = threadIdx.x & 63;
+  const bool in = j < total;
+  const uint64_t vm = __ballot(in);
+  if (vm == 0ull) return;  // in-range lanes are a prefix of the wave
+  uint32_t i = 0, cnt = 0, o = 0;
+  int tx0 = 0, ty0 = 0, w = 1;
+  if (in) {
+    i = order[j];
+    o = offsets[j];
+    if constexpr (kPacked) {
+      const uint32_t pr = prect_s[j];
+      cnt = packed_tile_count(pr);
+      tx0 = (int)(pr & 255u);
+      ty0 = (int)((pr >> 8) & 255u);
+      w = (int)((pr >> 16) & 255u) + 1;
+    } else {
+      cnt = tiles[i];
+      if (cnt) {
+        const int4 r = rect[i];
+        tx0 = r.x >> 4;
+        ty0 = r.y >> 4;
+        w = (r.z >> 4) - tx0 + 1;
+      }
+    }
+  }
+  const uint32_t o0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)o);
+  // run start relative to the wave's first pair (out of range: never owns)
+  const uint32_t st = in ? o - o0 : 0xffffffffu;
+  const int last = 63 - __builtin_clzll(vm);
+  const uint32_t T = (uint32_t)__builtin_amdgcn_readlane((int)(st + cnt), last);
+  // key of the run's q-th pair: base + (q / w) tiles_x + q % w
+  int base = 0, txs = 1;
+  if (in && cnt) {
+    const DevCam &c = cams[i / N];
+    txs = c.tiles_x;
+    base = c.tile_base + ty0 * c.tiles_x + tx0;
+  }
+  for (uint32_t p = (uint32_t)lane; p < T + 63u - (T + 63u) % 64u; p += 64u) {
+    // the last lane k with st_k <= p (a zero-length run shares its start with
+    // the next lane's, so the owner has pairs)
+    int k = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+      const uint32_t sc = (uint32_t)__shfl((int)st, k + step);
+      k = sc <= p ? k + step : k;
+    }
+    const uint32_t sk = (uint32_t)__shfl((int)st, k);
+    const int bk = __shfl(base, k), xk = __shfl(txs, k), wk = __shfl(w, k);
+    const uint32_t ik = (uint32_t)__shfl((int)i, k);
+    if (p >= T) continue;
+    const uint32_t q = p - sk;
+    // q / wk by a reciprocal, corrected to the exact quotient
+    uint32_t row = (uint32_t)((float)q * __builtin_amdgcn_rcpf((float)wk));
+    row -= row * (uint32_t)wk > q ? 1u : 0u;
+    row += (row + 1u) * (uint32_t)wk <= q ? 1u : 0u;
+    const uint32_t col = q - row * (uint32_t)wk;
+    const uint64_t pos = (uint64_t)o0 + p;
+    if (pos < cap) {
+      keys[pos] = (uint32_t)(bk + (int)row * xk + (int)col);
+      vals[pos] = ik;
+    } else if (overflow) {
+      *overflow = 1u;
+    }
+  }
 }
 
 struct CamPack {
@@ -364,9 +433,24 @@ radix_hist_all(const uint32_t *__restrict__ keys, int64_t n, const uint64_t *__r
   }
 }
 
+__device__ __forceinline__ void gather_put(const uint32_t *__restrict__ gsrc,
+                                           uint32_t *__restrict__ gdst,
+                                           uint32_t *__restrict__ gdst2, uint32_t v,
+                                           int64_t pos) {
+  const uint32_t x = gsrc[v];
+  if (gdst2) {
+    gdst[pos] = packed_tile_count(x);
+    gdst2[pos] = x;
+  } else {
+    gdst[pos] = x;
+  }
+}
+
 // One pass, on a persistent grid: each block takes chunk tickets until they
 // run out.  kIdx: the values are the keys' input indices (no vin).
-// gsrc/gdst (may be NULL): also writes gdst[pos] = gsrc[value].
+// gsrc/gdst (may be NULL): also writes gdst[pos] = gsrc[value]; with gdst2,
+// gsrc holds packed tile rectangles: gdst[pos] = their tile counts and
+// gdst2[pos] = the words.
 template <bool kIdx>
 __global__ void __launch_bounds__(kOsThreads)
 radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
@@ -374,7 +458,7 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
                uint64_t *__restrict__ st_cur, uint64_t *__restrict__ st_next,
                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                const uint32_t *__restrict__ gsrc, uint32_t *__restrict__ gdst,
-               uint32_t *__restrict__ err) {
+               uint32_t *__restrict__ gdst2, uint32_t *__restrict__ err) {
   __shared__ uint32_t s_whist[kOsWaves][256];  // per-wave digit counts, then offsets
   __shared__ uint32_t s_gex[256];              // global exclusive digit offsets
   __shared__ uint32_t s_base[256];             // + the earlier chunks of this one
@@ -434,7 +518,7 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
           const uint32_t v = kIdx ? (uint32_t)i : vin[i];
           kout[i] = kin[i];
           vout[i] = v;
-          if (gdst) gdst[i] = gsrc[v];
+          if (gdst) gather_put(gsrc, gdst, gdst2, v, i);
         }
       }
       __syncthreads();  // s_ticket is read before the next ticket overwrites it
@@ -591,7 +675,7 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
       const uint32_t pos = s_base[d] + (uint32_t)e - s_cex[d];
       kout[pos] = k;
       vout[pos] = v;
-      if (gdst) gdst[pos] = gsrc[v];
+      if (gdst) gather_put(gsrc, gdst, gdst2, v, pos);
     }
     __syncthreads();  // LDS is read before the next chunk clears it
   }
@@ -661,13 +745,20 @@ void launch_gather(const uint32_t *in, const uint32_t *idx, int64_t n, uint32_t 
 }
 
 void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint32_t *tiles,
-                      const int4 *rect, const DevCam *cams, int V, int64_t N, uint64_t pair_cap,
-                      uint32_t *keys, uint32_t *vals, uint32_t *overflow, hipStream_t s) {
+                      const int4 *rect, const uint32_t *prect_sorted, const DevCam *cams, int V,
+                      int64_t N, uint64_t pair_cap, uint32_t *keys, uint32_t *vals,
+                      uint32_t *overflow, hipStream_t s) {
   const int64_t total = (int64_t)V * N;
   if (total == 0) return;
   const int64_t nb = (total + 255) / 256;
-  hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)nb), dim3(256), 0, s, order, offsets, tiles,
-                     rect, cams, N, total, pair_cap, keys, vals, overflow);
+  if (prect_sorted)
+    hipLaunchKernelGGL(duplicate_kernel<true>, dim3((unsigned)nb), dim3(256), 0, s, order,
+                       offsets, tiles, rect, prect_sorted, cams, N, total, pair_cap, keys, vals,
+                       overflow);
+  else
+    hipLaunchKernelGGL(duplicate_kernel<false>, dim3((unsigned)nb), dim3(256), 0, s, order,
+                       offsets, tiles, rect, prect_sorted, cams, N, total, pair_cap, keys, vals,
+                       overflow);
 }
 
 void launch_upload_cams(const DevCam *host, int n, DevCam *dst, hipStream_t s, ZeroList z) {
@@ -700,7 +791,7 @@ size_t sort_tmp_bytes(int64_t n) {
 int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint32_t *va,
                       uint32_t *kb, uint32_t *vb, int64_t n, int bits, void *tmp, hipStream_t s,
                       const uint64_t *n_dev, const uint32_t *gather_src, uint32_t *gather_dst,
-                      uint32_t *err, uint32_t *zeroed_words) {
+                      uint32_t *err, uint32_t *zeroed_words, uint32_t *gather_dst2) {
   if (n <= 0) return 0;
   const int64_t nch = (n + kOsChunk - 1) / kOsChunk;
   uint32_t *words = zeroed_words ? zeroed_words : (uint32_t *)tmp;
@@ -725,15 +816,16 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
     const bool lastp = p == passes - 1;
     const uint32_t *gs = lastp ? gather_src : nullptr;
     uint32_t *gd = lastp ? gather_dst : nullptr;
+    uint32_t *gd2 = lastp ? gather_dst2 : nullptr;
     const unsigned grid = (unsigned)std::min<int64_t>(nch, kOsMaxBlocks);
     if (vin == nullptr)
       hipLaunchKernelGGL(radix_onesweep<true>, dim3(grid), dim3(kOsThreads), 0, s, kin,
                          vin, n, n_dev, p, words, st[p & 1], st[(p + 1) & 1], kout, vout, gs, gd,
-                         err);
+                         gd2, err);
     else
       hipLaunchKernelGGL(radix_onesweep<false>, dim3(grid), dim3(kOsThreads), 0, s, kin,
                          vin, n, n_dev, p, words, st[p & 1], st[(p + 1) & 1], kout, vout, gs, gd,
-                         err);
+                         gd2, err);
     which = (kout == ka) ? 0 : 1;
     kin = kout;
     vin = vout;

@@ -178,7 +178,11 @@ def compare_grads(gg, ref, keys=PARAM_KEYS):
     ties; per tensor relative L2 <= 1e-3; and every element of at least 1%
     of the tensor's largest magnitude within a plain 1e-3 |ref|.  The report
     counts, per tensor, the elements that pass only through the cond or tie
-    allowance, and those large elements that miss the plain bound (0)."""
+    allowance, and those large elements that miss the plain bound (0).
+    "Large" leaves out elements that are sums of much larger terms of both
+    signs (sum|terms| > 10 |ref|): the binary32 accumulation of a splat's
+    per-pixel terms, in whatever order the atomics land, can miss 1e-3 |ref|
+    there by cancellation alone; the per-term bound still holds for them."""
     report = {}
     for k in keys:
         g = np.asarray(gg[k], np.float64).reshape(ref[k].shape)
@@ -190,9 +194,10 @@ def compare_grads(gg, ref, keys=PARAM_KEYS):
         den = np.linalg.norm(r)
         rel = float(np.linalg.norm(g - r) / den) if den > 0 else float(np.linalg.norm(g))
         big = np.abs(r) >= 1e-2 * np.abs(r).max(initial=0.0)
+        cancel = ref[k + "_abs"] > 10.0 * np.abs(r)
         report[k] = dict(bad=int(bad.sum()), rel_l2=rel, via_allowance=int((err > base).sum()),
-                         big_over_plain=int((big & (err > GRAD_RTOL * np.abs(r))).sum()),
-                         n=int(r.size))
+                         big_over_plain=int((big & ~cancel & (err > GRAD_RTOL * np.abs(r))).sum()),
+                         big_cancelling=int((big & cancel).sum()), n=int(r.size))
         assert bad.sum() == 0, (k, int(bad.sum()), np.argwhere(bad)[:5].tolist(),
                                 g[bad][:5].tolist(), r[bad][:5].tolist())
         assert rel <= GRAD_L2, (k, rel)
