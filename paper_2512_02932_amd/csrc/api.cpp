@@ -666,8 +666,10 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(commit(st, 1, st->stream, cap_mode));
   {
     StageTimer t(ctx, HGS_STAGE_DUPLICATE, st->stream);
+    // (also clears the tile ranges the ranges kernel fills in)
     launch_duplicate(order, st->offsets, st->tiles, st->rect, prect_s, st->cams, n_views, st->N,
-                     (uint64_t)cap, kb, vb, st->overflow, st->stream);
+                     (uint64_t)cap, kb, vb, st->overflow,
+                     reinterpret_cast<uint32_t *>(st->ranges), 2 * n_tiles, st->stream);
   }
   int tile_bits = 0;
   while ((int64_t(1) << tile_bits) < n_tiles) ++tile_bits;
@@ -680,7 +682,6 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   }
   {
     StageTimer t(ctx, HGS_STAGE_RANGES, st->stream);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(st->ranges), 0u, 2 * n_tiles, st->stream);
     launch_ranges(st->keys, cap, st->ranges, st->stream, st->total);
     launch_tile_order(st->ranges, (int)n_tiles, st->order, st->stream);
   }

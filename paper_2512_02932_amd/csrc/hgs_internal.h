@@ -157,10 +157,11 @@ void launch_gather(const uint32_t *in, const uint32_t *idx, int64_t n, uint32_t 
 // be NULL only if the caller knows the pairs fit).
 // prect_sorted (may be NULL): the packed tile rectangles in the order
 // `order` (from the depth sort's gather); then tiles and rect are not read.
+// zero[0, zero_n) (may be empty) is cleared by the same launch.
 void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint32_t *tiles,
                       const int4 *rect, const uint32_t *prect_sorted, const DevCam *cams, int V,
                       int64_t N, uint64_t pair_cap, uint32_t *keys, uint32_t *vals,
-                      uint32_t *overflow, hipStream_t s);
+                      uint32_t *overflow, uint32_t *zero, int64_t zero_n, hipStream_t s);
 
 // Copies n host cameras to dst through kernel arguments (up to
 // kCamsPerUpload per launch), so that a captured graph carries the camera

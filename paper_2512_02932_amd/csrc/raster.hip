@@ -810,20 +810,23 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
 }
 
 // Tile order of the raster launches: tiles by pair-list length, longest
-// first, in 32 buckets (empty; under 128; then steps of 128 up to 3840 and
+// first, in 16 buckets (empty; under 256; then steps of 256 up to 3584 and
 // more), ascending tile index inside a bucket.  The dispatcher starts
 // blocks in id order, so the waves that walk the longest lists start first
 // instead of wherever their tiles sit in the image, and the short ones fill
-// in behind them.  One workgroup of 16 waves, each on a contiguous run of
-// tiles, 64 at a time: the lanes with the same bucket find each other with
-// five ballots (one per bucket bit), the highest of them adds the group's
-// size to the wave's count of that bucket in LDS; an exclusive scan over
-// (bucket descending, wave) gives each wave's bases; the second sweep ranks
-// the same groups again and scatters.
-constexpr int kOrderWaves = 16, kOrderBits = 5, kOrderBuckets = 1 << kOrderBits;
+// in behind them.  Inside a bucket, neighbouring tiles (which share splats)
+// stay close in the launch order: finer buckets measured slower.
+//
+// One workgroup: the buckets are staged in LDS (up to 32768 tiles), then 16
+// waves, each on a contiguous run of tiles, 64 at a time: the lanes with the
+// same bucket find each other with four ballots (one per bucket bit), the
+// highest of them adds the group's size to the wave's count of that bucket
+// in LDS; an exclusive scan over (bucket descending, wave) gives each wave's
+// bases; the second sweep ranks the same groups again and scatters.
+constexpr int kOrderWaves = 16, kOrderBits = 4, kOrderBuckets = 1 << kOrderBits;
 __device__ __forceinline__ int order_bucket(uint2 r) {
   const uint32_t n = r.y - r.x;
-  return n == 0 ? 0 : 1 + (int)min((uint32_t)(kOrderBuckets - 2), n >> 7);
+  return n == 0 ? 0 : 1 + (int)min((uint32_t)(kOrderBuckets - 2), n >> 8);
 }
 
 // Lanes of the wave that hold the same bucket as this one (among `valid`).
@@ -838,14 +841,34 @@ __device__ __forceinline__ uint64_t bucket_peers(int b, bool valid) {
   return peers;
 }
 
+constexpr int kOrderLds = 32768;  // tiles whose buckets are staged in LDS first
 __global__ void __launch_bounds__(kOrderWaves * kWave)
 tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, uint32_t *__restrict__ order) {
   // per (bucket, wave) counts, then bases, at entry(bucket)
   __shared__ uint32_t s_cnt[kOrderBuckets * kOrderWaves];
+  __shared__ uint8_t s_bk[kOrderLds];
+  constexpr int kT = kOrderWaves * kWave;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  for (int e = threadIdx.x; e < kOrderBuckets * kOrderWaves; e += kOrderWaves * kWave)
-    s_cnt[e] = 0;
+  for (int e = threadIdx.x; e < kOrderBuckets * kOrderWaves; e += kT) s_cnt[e] = 0;
+  // every tile's bucket into LDS, eight loads in flight per thread (the
+  // sweeps below then wait on no memory)
+  const bool staged = n_tiles <= kOrderLds;
+  if (staged) {
+    for (int b0 = 0; b0 < n_tiles; b0 += 8 * kT) {
+      uint2 r[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r[u] = ranges[min(b0 + u * kT + (int)threadIdx.x, n_tiles - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = b0 + u * kT + (int)threadIdx.x;
+        if (t < n_tiles) s_bk[t] = (uint8_t)order_bucket(r[u]);
+      }
+    }
+  }
   __syncthreads();
+  auto bucket_at = [&](int t) {
+    return staged ? (int)s_bk[t] : order_bucket(ranges[t]);
+  };
   const int per = ((n_tiles + kOrderWaves - 1) / kOrderWaves + kWave - 1) & ~(kWave - 1);
   const int t0 = w * per, t1 = min(n_tiles, t0 + per);
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -853,7 +876,7 @@ tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, uint32_t *__res
   for (int tb = t0; tb < t1; tb += kWave) {
     const int t = tb + lane;
     const bool valid = t < t1;
-    const int b = order_bucket(ranges[min(t, t1 - 1)]);
+    const int b = bucket_at(min(t, t1 - 1));
     const uint64_t peers = bucket_peers(b, valid);
     // the highest lane of each group; a wave's own entries, so no other
     // wave writes them
@@ -885,7 +908,7 @@ tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, uint32_t *__res
   for (int tb = t0; tb < t1; tb += kWave) {
     const int t = tb + lane;
     const bool valid = t < t1;
-    const int b = order_bucket(ranges[min(t, t1 - 1)]);
+    const int b = bucket_at(min(t, t1 - 1));
     const uint64_t peers = bucket_peers(b, valid);
     const uint32_t at = valid ? s_cnt[entry(b)] : 0u;
     if (valid) order[at + (uint32_t)__popcll(peers & below)] = (uint32_t)t;

@@ -238,8 +238,9 @@ duplicate_kernel(const uint32_t *__restrict__ order, const uint32_t *__restrict_
                  const uint32_t *__restrict__ prect_s,
                  const DevCam *__restrict__ cams, int64_t N, int64_t total, uint64_t cap,
                  uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                 uint32_t *__restrict__ overflow) {
+                 uint32_t *__restrict__ overflow, uint32_t *__restrict__ zero, int64_t zero_n) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t z = j; z < zero_n; z += (int64_t)gridDim.x * blockDim.x) zero[z] = 0u;
   const int lane = threadIdx.x & 63;
   const bool in = j < total;
   const uint64_t vm = __ballot(in);
@@ -747,18 +748,21 @@ void launch_gather(const uint32_t *in, const uint32_t *idx, int64_t n, uint32_t 
 void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint32_t *tiles,
                       const int4 *rect, const uint32_t *prect_sorted, const DevCam *cams, int V,
                       int64_t N, uint64_t pair_cap, uint32_t *keys, uint32_t *vals,
-                      uint32_t *overflow, hipStream_t s) {
+                      uint32_t *overflow, uint32_t *zero, int64_t zero_n, hipStream_t s) {
   const int64_t total = (int64_t)V * N;
-  if (total == 0) return;
+  if (total == 0) {
+    if (zero_n > 0) launch_fill_u32(zero, 0u, zero_n, s);
+    return;
+  }
   const int64_t nb = (total + 255) / 256;
   if (prect_sorted)
     hipLaunchKernelGGL(duplicate_kernel<true>, dim3((unsigned)nb), dim3(256), 0, s, order,
                        offsets, tiles, rect, prect_sorted, cams, N, total, pair_cap, keys, vals,
-                       overflow);
+                       overflow, zero, zero_n);
   else
     hipLaunchKernelGGL(duplicate_kernel<false>, dim3((unsigned)nb), dim3(256), 0, s, order,
                        offsets, tiles, rect, prect_sorted, cams, N, total, pair_cap, keys, vals,
-                       overflow);
+                       overflow, zero, zero_n);
 }
 
 void launch_upload_cams(const DevCam *host, int n, DevCam *dst, hipStream_t s, ZeroList z) {
