@@ -297,7 +297,10 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
   // once it has stopped, so one compare gives both tests.
   float T = 1.0f;
   float thr = q.inside ? opt.alpha_min : __builtin_inff();
-  const float amax = opt.alpha_max, tmin = opt.t_min, inv_amin = opt.inv_amin;
+  // alpha_max as bits: for numbers >= +0 (raw always is, where it counts)
+  // the integer min of the bit patterns is the float min, in one op
+  const int amax_bits = __float_as_int(opt.alpha_max);
+  const float tmin = opt.t_min, inv_amin = opt.inv_amin;
   int lastk = -1;  // compacted slot of this lane's last blended pair in the chunk
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, nx = 0.0f, ny = 0.0f, nz = 0.0f;
   uint32_t cnt = 0, last = 0, wc = 0;
@@ -334,6 +337,9 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
         if (k >= k_end) break;
         const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
                      r4 = srec[4][k];
+        // r3.x is used by the 2D branch only; naming it here keeps r3 one
+        // 16-byte LDS read instead of pieces with an address of their own
+        asm volatile("" ::"v"(r3.x));
         // the type is the same at every lane (one record): a scalar branch,
         // so a 3D pair does not pay for the 2D form's reciprocal
         const bool two = !is3d_of(r4);
@@ -362,9 +368,8 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
         // so only an active pair can take T below t_min (the stop); the
         // weight is 0 unless the pair is blended, and the accumulations run
         // unconditionally (record values are finite, see preprocess).
-        // min(raw, alpha_max) as a select: equal to fminf for numbers, and
-        // raw >= thr is false for NaN
-        const float a = raw >= thr ? (raw < amax ? raw : amax) : 0.0f;
+        // raw >= thr is false for NaN, so the min only sees numbers >= +0
+        const float a = raw >= thr ? __int_as_float(min(__float_as_int(raw), amax_bits)) : 0.0f;
         const float Tn = T * (1.0f - a);
         const bool stop = Tn < tmin;
         const float wg = stop ? 0.0f : a * T;
