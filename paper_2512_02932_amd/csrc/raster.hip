@@ -669,6 +669,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
     for (int k = 0; k < 2; ++k) XS[k] = Xr[k] * opt.bg[0] + Xg[k] * opt.bg[1] + Xb[k] * opt.bg[2];
   }
 
+  const int amax_bits = __float_as_int(opt.alpha_max);
   uint32_t wmax = L;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, d));
@@ -733,7 +734,10 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
     for (int k = __popcll(m) - 1; k >= 0; --k) {
       const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
                    r4 = srec[4][k];
-      const uint32_t pos = spos[k];
+      const uint32_t pos = spos[k], sk = sid[k];
+      // fields only the 2D branch uses, named here so that each record row
+      // stays one 16-byte LDS read
+      asm volatile("" ::"v"(r2.z), "v"(r2.w), "v"(r3.x));
       const bool is3d = is3d_of(r4);
       const PairEval p = eval_pair(is3d, q.fx, q.fy, r0, r1, r2, r3);
       const float G = exp2_neg(p.e);
@@ -750,7 +754,9 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
         ps.rw = act ? p.rw : 0.0f;
         ps.depth = act ? p.depth : 0.0f;
       }
-      const float a = raw < opt.alpha_max ? raw : opt.alpha_max;  // as the forward forms it
+      // as the forward forms it (the integer min of the bit patterns, equal to
+      // the float min for raw >= +0; a NaN raw, never active, gets alpha_max)
+      const float a = __int_as_float(min(__float_as_int(raw), amax_bits));
       const bool live = act && !(raw > opt.alpha_max);  // not clamped: the exponent's path
       const float Ti = T * __builtin_amdgcn_rcpf(1.0f - a);
       const float wg = act ? a * Ti : 0.0f;
@@ -772,7 +778,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
         g[5] = wg * Gd;                                  // 3D: depth slot
         pair_geometry_grads(g, ps, is3d, ge, wg * Gd, r1, r2);
       }
-      const size_t rec_off = (size_t)sid[k] * kGradSlots;
+      const size_t rec_off = (size_t)sk * kGradSlots;
       if (NS == 3 && is3d) {
         // A 3D pair has 13 non-zero main slots and 9 per RGB set: two
         // reductions carry all 31 (layout at packA / packB).
