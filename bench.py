@@ -331,7 +331,7 @@ def dominant_roofline(stage_ms, counts, N, K, V, workload):
              if k in stage_ms]
     dom = max(cands, key=lambda k: stage_ms[k])
     if dom in ("raster_fwd", "raster_bwd"):
-        kname = "raster_fwd_kernel" if dom == "raster_fwd" else "raster_bwd_kernel<1>"
+        kname = "raster_fwd_kernel<false>" if dom == "raster_fwd" else "raster_bwd_kernel<1>"
         ops, ops_s = (OPS_FWD, OPS_FWD_SURVEY) if dom == "raster_fwd" else (OPS_BWD, OPS_BWD_SURVEY)
         key = "fwd" if dom == "raster_fwd" else "blend"
         work = counts[f"{key}_3d"] * ops["3d"] + counts[f"{key}_2d"] * ops["2d"]
@@ -346,7 +346,7 @@ def dominant_roofline(stage_ms, counts, N, K, V, workload):
     byt = (N * (45 + 12 * K) + V * N * 88) if dom == "preprocess" else \
         (V * N * 136 + 2 * N * (45 + 12 * K))
     achieved = byt / (stage_ms[dom] * 1e-3) / 1e9
-    kname = f"{dom}_kernel<3>" if dom == "preprocess" else f"{dom}_kernel<3, {'false' if V == 1 else 'true'}>"
+    kname = f"{dom}_kernel<{DEG_OF_K[K]}>"
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK / 1e9,
             "unit": "GB/s", "frac": round(achieved / (HBM_PEAK / 1e9), 4),
             "traffic": measured_traffic(kname, workload), "kernel": kname,
