@@ -559,13 +559,10 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc_t(st, &st->tiles, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->zbits, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->rect, (size_t)VN));
-  // packed tile rectangles (views of at most 256 x 256 tiles), and the same
-  // in depth order
+  // packed tile rectangles, and the same in depth order
   uint32_t *prect = nullptr, *prect_s = nullptr;
-  if (st->tiles_x <= 256 && st->tiles_y <= 256) {
-    ST_HIP(dalloc_t(st, &prect, (size_t)VN));
-    ST_HIP(dalloc_t(st, &prect_s, (size_t)VN));
-  }
+  ST_HIP(dalloc_t(st, &prect, (size_t)VN));
+  ST_HIP(dalloc_t(st, &prect_s, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->flags, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->offsets, (size_t)VN));
   ST_HIP(dalloc_t(st, &st->total, (size_t)1));
@@ -617,8 +614,8 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
     // (and packed rectangles)
     StageTimer t(ctx, HGS_STAGE_DEPTH_SORT, st->stream);
     const int w = launch_radix_sort(st->zbits, nullptr, za, oa, zb, ob, VN, 32, dsort_tmp,
-                                    st->stream, nullptr, prect ? prect : st->tiles, cnt,
-                                    st->overflow, dwords, prect_s);
+                                    st->stream, nullptr, prect, cnt, st->overflow, dwords,
+                                    prect_s, st->tiles);
     order = w ? ob : oa;
   }
   {

@@ -95,17 +95,21 @@ __device__ inline int slot_of_tile(const Slot *slots, int ns, int t) {
 
 // ----- launchers (all enqueue on `s`) -----
 // flags per (view, splat): bit 0 valid, bit 1 normal negated, bits 2-3 normal axis
-// prect (may be NULL; only for views of at most 256 x 256 tiles): each
-// instance's tile rectangle packed in 32 bits, see pack_tile_rect.
+// prect (may be NULL): each instance's tile rectangle packed in 32 bits,
+// see pack_tile_rect.
 void launch_preprocess(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt,
                        Record *rec, uint32_t *tiles, uint32_t *zbits, int4 *rect,
                        uint8_t *flags, uint32_t *prect, hipStream_t s);
 
 // Tile rectangle of an instance in one word: first tile column and row
 // (bits 0-7, 8-15), width and height in tiles minus one (16-23, 24-31);
-// kNoTiles for an instance that covers no tile.  Holds for views of at most
-// 256 x 256 tiles.
-constexpr uint32_t kNoTiles = 0xffffffffu;
+// kNoTiles for an instance that covers no tile, kWideRect for one whose
+// rectangle reaches past tile column or row 255 (its count and rectangle
+// are then read from the tiles and rect arrays).
+constexpr uint32_t kNoTiles = 0xffffffffu, kWideRect = 0xfffffffeu;
+__host__ __device__ inline bool tile_rect_packs(int4 r) {
+  return (r.z >> 4) <= 255 && (r.w >> 4) <= 255;
+}
 __host__ __device__ inline uint32_t pack_tile_rect(int4 r) {
   const uint32_t tx0 = (uint32_t)r.x >> 4, ty0 = (uint32_t)r.y >> 4;
   return tx0 | (ty0 << 8) | ((((uint32_t)r.z >> 4) - tx0) << 16) |
@@ -118,7 +122,8 @@ __host__ __device__ inline uint32_t packed_tile_count(uint32_t p) {
 // table (grid sized by the capacity inst_cap).
 void launch_preprocess_slots(const Slot *slots, const int *n_slots, const uint64_t *n_inst,
                              DevOpts opt, int64_t inst_cap, Record *rec, uint32_t *tiles,
-                             uint32_t *zbits, int4 *rect, uint8_t *flags, hipStream_t s);
+                             uint32_t *zbits, int4 *rect, uint8_t *flags, uint32_t *prect,
+                             hipStream_t s);
 void launch_preprocess_bwd(const SceneDev &sc, const DevCam *cams, int V, DevOpts opt,
                            const uint8_t *flags, const int4 *rect, const float *accum,
                            float *g_means, float *g_scales, float *g_rots, float *g_opac,
@@ -155,8 +160,8 @@ void launch_gather(const uint32_t *in, const uint32_t *idx, int64_t n, uint32_t 
 // offsets[j], the exclusive scan of tiles[order[.]].
 // Pairs at or past pair_cap are dropped and set *overflow = 1 (overflow may
 // be NULL only if the caller knows the pairs fit).
-// prect_sorted (may be NULL): the packed tile rectangles in the order
-// `order` (from the depth sort's gather); then tiles and rect are not read.
+// prect_sorted: the packed tile rectangles in the order `order` (from the
+// depth sort's gather); tiles and rect are read only for kWideRect entries.
 // zero[0, zero_n) (may be empty) is cleared by the same launch.
 void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint32_t *tiles,
                       const int4 *rect, const uint32_t *prect_sorted, const DevCam *cams, int V,
@@ -178,10 +183,10 @@ void launch_upload_cams(const DevCam *host, int n, DevCam *dst, hipStream_t s,
 // The same for a batch of slots, with the instance count on the device.
 // Pairs at or past pair_cap are dropped and set *overflow = 1.
 void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
-                            const uint32_t *tiles, const int4 *rect, const Slot *slots,
-                            const int *n_slots, int64_t inst_cap, const uint64_t *n_inst,
-                            uint64_t pair_cap, uint32_t *keys, uint32_t *vals,
-                            uint32_t *overflow, hipStream_t s);
+                            const uint32_t *tiles, const int4 *rect, const uint32_t *prect_sorted,
+                            const Slot *slots, const int *n_slots, int64_t inst_cap,
+                            const uint64_t *n_inst, uint64_t pair_cap, uint32_t *keys,
+                            uint32_t *vals, uint32_t *overflow, hipStream_t s);
 
 // Stable LSD radix sort of n (u32 key, u32 value) pairs on the low `bits`
 // bits (at most 32), 8 bits per pass.  The first pass reads (k0, v0) (v0
@@ -191,7 +196,8 @@ void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
 // sort_tmp_bytes(n) bytes.  If gather_dst is given, the last pass also
 // writes gather_dst[j] = gather_src[value j] of the sorted order; with
 // gather_dst2 as well, gather_src holds packed tile rectangles and the pass
-// writes gather_dst[j] = their tile counts, gather_dst2[j] = the words.  err (may
+// writes gather_dst[j] = their tile counts (from gather_tiles for kWideRect
+// words), gather_dst2[j] = the words.  err (may
 // be NULL): bit 1 is set if a pass's look-back gave up (never expected).
 // zeroed_words (may be NULL): kSortWords uint32 the caller has cleared on
 // the stream, used for the sort's digit counts and tickets instead of the
@@ -202,7 +208,8 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
                       uint32_t *kb, uint32_t *vb, int64_t n, int bits, void *tmp, hipStream_t s,
                       const uint64_t *n_dev = nullptr, const uint32_t *gather_src = nullptr,
                       uint32_t *gather_dst = nullptr, uint32_t *err = nullptr,
-                      uint32_t *zeroed_words = nullptr, uint32_t *gather_dst2 = nullptr);
+                      uint32_t *zeroed_words = nullptr, uint32_t *gather_dst2 = nullptr,
+                      const uint32_t *gather_tiles = nullptr);
 
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
@@ -226,7 +233,11 @@ inline int64_t raster_mask_words(int64_t pairs, int64_t tiles) {
 }
 // order[n_tiles_total]: the tiles by pair-list length, longest first (from
 // ranges), the order in which the raster launches below start their tiles.
-void launch_tile_order(const uint2 *ranges, int n_tiles_total, uint32_t *order, hipStream_t s);
+// n_tiles_dev (may be NULL): the tile count on the device (at most
+// n_tiles_total).  n_split (may be NULL): receives how many tiles, at the
+// front of the order, the forward splits into half-quadrant waves.
+void launch_tile_order(const uint2 *ranges, int n_tiles_total, uint32_t *order, hipStream_t s,
+                       const int *n_tiles_dev = nullptr, uint32_t *n_split = nullptr);
 // order (may be NULL: tile index order): from launch_tile_order.
 void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
                        const Record *rec, int n_tiles_total, int W, int H, int tiles_x,
@@ -234,11 +245,14 @@ void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_
                        hipStream_t s);
 
 // Forward of a batch of slots on a persistent grid of n_blocks wave64s
-// that pull (tile, quadrant) units from *queue (zero at launch) up to the
-// device tile count *n_tiles.  Writes each slot's images.
+// that pull work units from *queue (zero at launch) over the device tile
+// count *n_tiles: with order and n_split (from launch_tile_order), the
+// per-view forward's waves in that order, else (tile, quadrant).  Writes
+// each slot's images.
 void launch_raster_fwd_queue(const uint2 *ranges, const uint32_t *vals, const Record *rec,
                              const Slot *slots, const int *n_slots, const int *n_tiles,
-                             int n_blocks, DevOpts opt, uint32_t *queue, hipStream_t s);
+                             int n_blocks, DevOpts opt, uint32_t *queue, hipStream_t s,
+                             const uint32_t *order = nullptr, const uint32_t *n_split = nullptr);
 
 struct RasterGradIn {
   const float *rgb, *alpha, *depth, *normal;

@@ -520,7 +520,10 @@ __device__ __forceinline__ void preprocess_one(const SceneDev &sc, const DevCam 
   tiles[i] = st.valid ? st.tiles : 0u;
   zbits[i] = st.zbits;
   rect[i] = make_int4(st.px0, st.py0, st.px1, st.py1);
-  if (prect) prect[i] = st.valid ? pack_tile_rect(rect_of(st)) : kNoTiles;
+  if (prect) {
+    const int4 r = rect_of(st);
+    prect[i] = !st.valid ? kNoTiles : (tile_rect_packs(r) ? pack_tile_rect(r) : kWideRect);
+  }
   flags[i] = (uint8_t)((st.valid ? kValid : 0) | (st.flip ? kFlip : 0) | (st.axis << 2));
   if (!st.valid) return;
 
@@ -606,7 +609,7 @@ preprocess_slots_kernel(const Slot *__restrict__ slots, const int *__restrict__ 
                         const uint64_t *__restrict__ n_inst, DevOpts opt, int64_t inst_cap,
                         Record *__restrict__ rec, uint32_t *__restrict__ tiles,
                         uint32_t *__restrict__ zbits, int4 *__restrict__ rect,
-                        uint8_t *__restrict__ flags) {
+                        uint8_t *__restrict__ flags, uint32_t *__restrict__ prect) {
   const int ns = *n_slots;
   const uint64_t cnt = *n_inst < (uint64_t)inst_cap ? *n_inst : (uint64_t)inst_cap;
   if (ns <= 0) return;
@@ -616,10 +619,10 @@ preprocess_slots_kernel(const Slot *__restrict__ slots, const int *__restrict__ 
     const Slot &sl = slots[slot_of_instance(slots, ns, i)];
     const int64_t g = i - sl.inst_base;
     switch (sl.scene.sh_degree) {
-      case 0: preprocess_one<0>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
-      case 1: preprocess_one<1>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
-      case 2: preprocess_one<2>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
-      default: preprocess_one<3>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags); break;
+      case 0: preprocess_one<0>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags, prect); break;
+      case 1: preprocess_one<1>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags, prect); break;
+      case 2: preprocess_one<2>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags, prect); break;
+      default: preprocess_one<3>(sl.scene, sl.cam, g, i, opt, rec, tiles, zbits, rect, flags, prect); break;
     }
   }
 }
@@ -1118,11 +1121,12 @@ void launch_preprocess(const SceneDev &sc, const DevCam *cams, int V, DevOpts op
 
 void launch_preprocess_slots(const Slot *slots, const int *n_slots, const uint64_t *n_inst,
                              DevOpts opt, int64_t inst_cap, Record *rec, uint32_t *tiles,
-                             uint32_t *zbits, int4 *rect, uint8_t *flags, hipStream_t s) {
+                             uint32_t *zbits, int4 *rect, uint8_t *flags, uint32_t *prect,
+                             hipStream_t s) {
   if (inst_cap <= 0) return;
   const int64_t blocks = std::min<int64_t>((inst_cap + 255) / 256, 4096);
   hipLaunchKernelGGL(preprocess_slots_kernel, dim3((unsigned)blocks), dim3(256), 0, s, slots,
-                     n_slots, n_inst, opt, inst_cap, rec, tiles, zbits, rect, flags);
+                     n_slots, n_inst, opt, inst_cap, rec, tiles, zbits, rect, flags, prect);
 }
 
 #define HGS_BY_DEGREE(deg, CALL) \

@@ -448,30 +448,46 @@ raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
                          spos);
 }
 
-// A batch of slots (requests of any size), persistent: each wave takes
-// work units u = 4 tile + quadrant from an atomic counter until u passes
-// 4 x the device tile count.  Every wave reaches that exit.  `queue` must be
-// zero at launch.
+// A batch of slots (requests of any size), persistent: each wave takes work
+// units from an atomic counter until they run out; every wave reaches that
+// exit.  With a tile order (order, n_split from tile_order_kernel), the
+// units are the waves of the per-view forward in that order: 8 per split
+// tile (quadrant x half) for the first *n_split tiles, then 4 per tile;
+// without one, u = 4 tile + quadrant.  `queue` must be zero at launch.
 __global__ void __launch_bounds__(kWave)
-raster_fwd_queue_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
+raster_fwd_queue_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ order,
+                        const uint32_t *__restrict__ n_split, const uint32_t *__restrict__ vals,
                         const Record *__restrict__ rec, const Slot *__restrict__ slots,
                         const int *__restrict__ n_slots, const int *__restrict__ n_tiles,
                         DevOpts opt, uint32_t *__restrict__ queue) {
   __shared__ float4 srec[5][kWave];
   __shared__ uint32_t spos[kWave];
   const int ns = *n_slots;
-  const uint32_t units = 4u * (uint32_t)max(*n_tiles, 0);
+  const uint32_t nt = (uint32_t)max(*n_tiles, 0);
+  const uint32_t nsp = order ? min(*n_split, nt) : 0u;
+  const uint32_t units = 8u * nsp + 4u * (nt - nsp);
   if (ns <= 0) return;
   for (;;) {
     uint32_t u = 0;
     if (threadIdx.x == 0) u = atomicAdd(queue, 1u);
     u = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)u, 0));
     if (u >= units) break;
-    const int tile = (int)(u >> 2);
+    uint32_t slot_i, quad, half = 0;
+    bool split = false;
+    if (u < 8u * nsp) {
+      slot_i = u >> 3;
+      quad = (u >> 1) & 3u;
+      half = u & 1u;
+      split = true;
+    } else {
+      slot_i = nsp + ((u - 8u * nsp) >> 2);
+      quad = (u - 8u * nsp) & 3u;
+    }
+    const int tile = order ? (int)order[slot_i] : (int)slot_i;
     const Slot &sl = slots[slot_of_tile(slots, ns, tile)];
     const int W = sl.cam.W, H = sl.cam.H;
-    const Quad q = make_quad(tile, 0, tile - sl.cam.tile_base, (int)(u & 3u), W, H,
-                             sl.cam.tiles_x);
+    const Quad q = make_quad(tile, 0, tile - sl.cam.tile_base, (int)quad, W, H, sl.cam.tiles_x,
+                             split, (int)half);
     ViewOut vo{};
     vo.rgb = sl.rgb;
     vo.alpha = sl.alpha;
@@ -839,6 +855,9 @@ __device__ __forceinline__ int order_bucket(uint2 r) {
   const uint32_t n = r.y - r.x;
   return n == 0 ? 0 : 1 + (int)min((uint32_t)(kOrderBuckets - 2), n >> 8);
 }
+// the first bucket whose tiles are split (lists of kSplitLen and more)
+constexpr int kSplitBucket = 1 + (int)(kSplitLen >> 8);
+static_assert((kSplitLen & 255u) == 0, "split threshold on a bucket boundary");
 
 // Lanes of the wave that hold the same bucket as this one (among `valid`).
 __device__ __forceinline__ uint64_t bucket_peers(int b, bool valid) {
@@ -854,7 +873,9 @@ __device__ __forceinline__ uint64_t bucket_peers(int b, bool valid) {
 
 constexpr int kOrderLds = 32768;  // tiles whose buckets are staged in LDS first
 __global__ void __launch_bounds__(kOrderWaves * kWave)
-tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, uint32_t *__restrict__ order) {
+tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, const int *__restrict__ n_dev,
+                  uint32_t *__restrict__ order, uint32_t *__restrict__ n_split) {
+  if (n_dev) n_tiles = min(n_tiles, max(*n_dev, 0));
   // per (bucket, wave) counts, then bases, at entry(bucket)
   __shared__ uint32_t s_cnt[kOrderBuckets * kOrderWaves];
   __shared__ uint8_t s_bk[kOrderLds];
@@ -916,6 +937,11 @@ tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, uint32_t *__res
     }
   }
   __syncthreads();
+  // tiles whose forward splits each quadrant in two come first: those of
+  // the buckets from kSplitBucket up, as many as the base of the entry
+  // (kSplitBucket - 1, wave 0)
+  if (n_split && threadIdx.x == 0)
+    *n_split = s_cnt[(kOrderBuckets - kSplitBucket) * kOrderWaves];
   for (int tb = t0; tb < t1; tb += kWave) {
     const int t = tb + lane;
     const bool valid = t < t1;
@@ -936,10 +962,10 @@ unsigned quad_blocks_full(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 
 }  // namespace
 
 void launch_tile_order(const uint2 *ranges, int n_tiles_total, uint32_t *order,
-                       hipStream_t s) {
+                       hipStream_t s, const int *n_tiles_dev, uint32_t *n_split) {
   if (n_tiles_total <= 0) return;
   hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderWaves * kWave), 0, s, ranges,
-                     n_tiles_total, order);
+                     n_tiles_total, n_tiles_dev, order, n_split);
 }
 
 void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
@@ -959,10 +985,11 @@ void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_
 
 void launch_raster_fwd_queue(const uint2 *ranges, const uint32_t *vals, const Record *rec,
                              const Slot *slots, const int *n_slots, const int *n_tiles,
-                             int n_blocks, DevOpts opt, uint32_t *queue, hipStream_t s) {
+                             int n_blocks, DevOpts opt, uint32_t *queue, hipStream_t s,
+                             const uint32_t *order, const uint32_t *n_split) {
   if (n_blocks <= 0) return;
   hipLaunchKernelGGL(raster_fwd_queue_kernel, dim3((unsigned)n_blocks), dim3(kWave), 0, s, ranges,
-                     vals, rec, slots, n_slots, n_tiles, opt, queue);
+                     order, n_split, vals, rec, slots, n_slots, n_tiles, opt, queue);
 }
 
 void launch_raster_bwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,

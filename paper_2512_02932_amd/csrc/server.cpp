@@ -53,11 +53,13 @@ struct Lane {
   Record *rec = nullptr;
   uint32_t *tiles = nullptr, *zbits = nullptr, *za = nullptr, *oa = nullptr, *zb = nullptr,
            *ob = nullptr, *cnt = nullptr, *offsets = nullptr;
+  uint32_t *prect = nullptr, *prect_s = nullptr;  // packed tile rectangles (depth order)
   int4 *rect = nullptr;
   uint8_t *flags = nullptr;
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
   uint2 *ranges = nullptr;
-  uint32_t *queue = nullptr;
+  uint32_t *order = nullptr;  // tiles by pair-list length, longest first
+  uint32_t *queue = nullptr;  // [0] the raster's unit counter, [1] split tiles
   void *scan_tmp = nullptr, *sort_tmp = nullptr;
   std::vector<void *> allocs;
   bool busy = false;
@@ -110,21 +112,23 @@ void enqueue_pass(const hgs_server *sv, Lane &L) {
   launch_fill_u32(L.queue, 0u, 1, s);
   launch_fill_u32(&L.status_dev->overflow, 0u, 1, s);
   launch_preprocess_slots(slots, n_slots, n_inst, sv->opt, I, L.rec, L.tiles, L.zbits, L.rect,
-                          L.flags, s);
+                          L.flags, L.prect, s);
   const int w = launch_radix_sort(L.zbits, nullptr, L.za, L.oa, L.zb, L.ob, I, 32, L.sort_tmp, s,
-                                  n_inst, L.tiles, L.cnt, &L.status_dev->overflow);
+                                  n_inst, L.prect, L.cnt, &L.status_dev->overflow, nullptr,
+                                  L.prect_s, L.tiles);
   const uint32_t *order = w ? L.ob : L.oa;
   launch_scan(L.cnt, L.offsets, I, pairs, L.scan_tmp, s, n_inst);
-  launch_duplicate_slots(order, L.offsets, L.tiles, L.rect, slots, n_slots, I, n_inst,
-                         (uint64_t)P, L.kb, L.vb, &L.status_dev->overflow, s);
+  launch_duplicate_slots(order, L.offsets, L.tiles, L.rect, L.prect_s, slots, n_slots, I,
+                         n_inst, (uint64_t)P, L.kb, L.vb, &L.status_dev->overflow, s);
   const int w2 = launch_radix_sort(L.kb, L.vb, L.ka, L.va, L.kb, L.vb, P, sv->tile_bits,
                                    L.sort_tmp, s, pairs, nullptr, nullptr,
                                    &L.status_dev->overflow);
   const uint32_t *keys = w2 ? L.kb : L.ka;
   const uint32_t *vals = w2 ? L.vb : L.va;
   launch_ranges(keys, P, L.ranges, s, pairs);
+  launch_tile_order(L.ranges, (int)T, L.order, s, n_tiles, L.queue + 1);
   launch_raster_fwd_queue(L.ranges, vals, L.rec, slots, n_slots, n_tiles, sv->raster_blocks,
-                          sv->opt, L.queue, s);
+                          sv->opt, L.queue, s, L.order, L.queue + 1);
   (void)hipMemcpyAsync(L.status_host, L.status_dev, sizeof(BatchStatus), hipMemcpyDeviceToHost,
                        s);
 }
@@ -151,13 +155,16 @@ hgs_status lane_init(hgs_server *sv, Lane &L) {
   HGS_HIP(lalloc(L, &L.cnt, (size_t)I));
   HGS_HIP(lalloc(L, &L.offsets, (size_t)I));
   HGS_HIP(lalloc(L, &L.rect, (size_t)I));
+  HGS_HIP(lalloc(L, &L.prect, (size_t)I));
+  HGS_HIP(lalloc(L, &L.prect_s, (size_t)I));
   HGS_HIP(lalloc(L, &L.flags, (size_t)I));
   HGS_HIP(lalloc(L, &L.ka, (size_t)P));
   HGS_HIP(lalloc(L, &L.va, (size_t)P));
   HGS_HIP(lalloc(L, &L.kb, (size_t)P));
   HGS_HIP(lalloc(L, &L.vb, (size_t)P));
   HGS_HIP(lalloc(L, &L.ranges, (size_t)T));
-  HGS_HIP(lalloc(L, &L.queue, 1));
+  HGS_HIP(lalloc(L, &L.order, (size_t)T));
+  HGS_HIP(lalloc(L, &L.queue, 2));
   HGS_HIP(lalloc(L, reinterpret_cast<char **>(&L.scan_tmp), scan_tmp_bytes(I)));
   HGS_HIP(lalloc(L, reinterpret_cast<char **>(&L.sort_tmp),
                  sort_tmp_bytes(std::max<int64_t>(I, P))));

@@ -202,46 +202,29 @@ __global__ void __launch_bounds__(256) gather_u32_kernel(const uint32_t *__restr
   if (j < eff_n(n, n_dev)) out[j] = in[idx[j]];
 }
 
-// One thread per instance in depth order: instance i = order[j] writes its
-// pairs at offsets[j], in tile row-major order of its rectangle.
-// key = global tile id, value = instance id i.
-__device__ __forceinline__ void emit_pairs(const DevCam &c, int4 r, uint32_t i, uint64_t o,
-                                           uint64_t cap, uint32_t *__restrict__ keys,
-                                           uint32_t *__restrict__ vals,
-                                           uint32_t *__restrict__ overflow) {
-  const int tx0 = r.x >> 4, tx1 = r.z >> 4, ty0 = r.y >> 4, ty1 = r.w >> 4;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      if (o < cap) {
-        keys[o] = (uint32_t)(c.tile_base + ty * c.tiles_x + tx);
-        vals[o] = i;
-      } else if (overflow) {
-        *overflow = 1u;
-      }
-      ++o;
-    }
-}
-
-// Views of one scene: instance i = view * N + splat.  Pairs at or past
-// `cap` are dropped and raise *overflow.  One wave per 64 consecutive
-// instances in depth order: their runs [offsets[j], offsets[j] + tiles[i])
+// Pairs of the wave of 64 consecutive entries j0 .. j0 + 63 (below
+// `total`) of the depth order.  Their runs [offsets[j], offsets[j] + count)
 // are contiguous, and the lanes write the wave's pairs 64 at a time, each
-// lane finding the instance that owns its position by a binary search over
-// the lanes' run starts.  The stores are coalesced, and a splat with many
-// tiles does not hold up the other 63 lanes.
-// kPacked: the tile rectangles come packed and in depth order (prect_s[j]),
-// so every read is sequential; otherwise tiles[i] and rect[i].
-template <bool kPacked>
-__global__ void __launch_bounds__(256)
-duplicate_kernel(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
-                 const uint32_t *__restrict__ tiles, const int4 *__restrict__ rect,
-                 const uint32_t *__restrict__ prect_s,
-                 const DevCam *__restrict__ cams, int64_t N, int64_t total, uint64_t cap,
-                 uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                 uint32_t *__restrict__ overflow, uint32_t *__restrict__ zero, int64_t zero_n) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t z = j; z < zero_n; z += (int64_t)gridDim.x * blockDim.x) zero[z] = 0u;
+// lane finding the entry that owns its position by a binary search over the
+// lanes' run starts: the stores are coalesced, and a splat with many tiles
+// does not hold up the other 63 lanes.  The tile rectangles come packed and
+// in depth order (prect_s[j]), so the reads are sequential; an instance
+// whose rectangle does not fit the packed form (kWideRect) reads tiles[i]
+// and rect[i].  cam_of(i) gives an instance's camera.  Pairs at or past
+// `cap` are dropped and raise *overflow.
+template <class CamOf>
+__device__ __forceinline__ void duplicate_wave(int64_t j0, int64_t total,
+                                               const uint32_t *__restrict__ order,
+                                               const uint32_t *__restrict__ offsets,
+                                               const uint32_t *__restrict__ tiles,
+                                               const int4 *__restrict__ rect,
+                                               const uint32_t *__restrict__ prect_s,
+                                               CamOf cam_of, uint64_t cap,
+                                               uint32_t *__restrict__ keys,
+                                               uint32_t *__restrict__ vals,
+                                               uint32_t *__restrict__ overflow) {
   const int lane = threadIdx.x & 63;
+  const int64_t j = j0 + lane;
   const bool in = j < total;
   const uint64_t vm = __ballot(in);
   if (vm == 0ull) return;  // in-range lanes are a prefix of the wave
@@ -250,20 +233,18 @@ duplicate_kernel(const uint32_t *__restrict__ order, const uint32_t *__restrict_
   if (in) {
     i = order[j];
     o = offsets[j];
-    if constexpr (kPacked) {
-      const uint32_t pr = prect_s[j];
+    const uint32_t pr = prect_s[j];
+    if (pr == kWideRect) {
+      cnt = tiles[i];
+      const int4 r = rect[i];
+      tx0 = r.x >> 4;
+      ty0 = r.y >> 4;
+      w = (r.z >> 4) - tx0 + 1;
+    } else {
       cnt = packed_tile_count(pr);
       tx0 = (int)(pr & 255u);
       ty0 = (int)((pr >> 8) & 255u);
       w = (int)((pr >> 16) & 255u) + 1;
-    } else {
-      cnt = tiles[i];
-      if (cnt) {
-        const int4 r = rect[i];
-        tx0 = r.x >> 4;
-        ty0 = r.y >> 4;
-        w = (r.z >> 4) - tx0 + 1;
-      }
     }
   }
   const uint32_t o0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)o);
@@ -274,7 +255,7 @@ duplicate_kernel(const uint32_t *__restrict__ order, const uint32_t *__restrict_
   // key of the run's q-th pair: base + (q / w) tiles_x + q % w
   int base = 0, txs = 1;
   if (in && cnt) {
-    const DevCam &c = cams[i / N];
+    const DevCam &c = cam_of(i);
     txs = c.tiles_x;
     base = c.tile_base + ty0 * c.tiles_x + tx0;
   }
@@ -307,6 +288,22 @@ duplicate_kernel(const uint32_t *__restrict__ order, const uint32_t *__restrict_
   }
 }
 
+// Views of one scene: instance i = view * N + splat, one wave per 64
+// entries.  zero[0, zero_n) is cleared by the same launch.
+__global__ void __launch_bounds__(256)
+duplicate_kernel(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
+                 const uint32_t *__restrict__ tiles, const int4 *__restrict__ rect,
+                 const uint32_t *__restrict__ prect_s, const DevCam *__restrict__ cams,
+                 int64_t N, int64_t total, uint64_t cap, uint32_t *__restrict__ keys,
+                 uint32_t *__restrict__ vals, uint32_t *__restrict__ overflow,
+                 uint32_t *__restrict__ zero, int64_t zero_n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t z = t; z < zero_n; z += (int64_t)gridDim.x * blockDim.x) zero[z] = 0u;
+  duplicate_wave(t & ~int64_t(63), total, order, offsets, tiles, rect, prect_s,
+                 [&](uint32_t i) -> const DevCam & { return cams[i / N]; }, cap, keys, vals,
+                 overflow);
+}
+
 struct CamPack {
   DevCam c[kCamsPerUpload];
 };
@@ -323,23 +320,27 @@ __global__ void upload_cams_kernel(CamPack p, int n, DevCam *__restrict__ dst, Z
     for (int k = threadIdx.x; k < z.n[a]; k += blockDim.x) z.p[a][k] = 0u;
 }
 
-// A batch of slots; instance count on the device.  Pairs at or past `cap`
-// are dropped and raise *overflow.
+// A batch of slots; instance count on the device (the grid strides over
+// waves of 64 entries).  Pairs at or past `cap` are dropped and raise
+// *overflow.
 __global__ void __launch_bounds__(256)
 duplicate_slots_kernel(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
                        const uint32_t *__restrict__ tiles, const int4 *__restrict__ rect,
-                       const Slot *__restrict__ slots, const int *__restrict__ n_slots,
-                       int64_t inst_cap, const uint64_t *__restrict__ n_inst, uint64_t cap,
+                       const uint32_t *__restrict__ prect_s, const Slot *__restrict__ slots,
+                       const int *__restrict__ n_slots, int64_t inst_cap,
+                       const uint64_t *__restrict__ n_inst, uint64_t cap,
                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
                        uint32_t *__restrict__ overflow) {
   const int64_t cnt = eff_n(inst_cap, n_inst);
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < cnt;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t i = order[j];
-    if (tiles[i] == 0) continue;
-    const Slot &sl = slots[slot_of_instance(slots, *n_slots, (int64_t)i)];
-    emit_pairs(sl.cam, rect[i], i, offsets[j], cap, keys, vals, overflow);
-  }
+  const int ns = *n_slots;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~int64_t(63); j0 < cnt;
+       j0 += stride)
+    duplicate_wave(j0, cnt, order, offsets, tiles, rect, prect_s,
+                   [&](uint32_t i) -> const DevCam & {
+                     return slots[slot_of_instance(slots, ns, (int64_t)i)].cam;
+                   },
+                   cap, keys, vals, overflow);
 }
 
 // ----- radix sort: one sweep per digit -----
@@ -435,12 +436,13 @@ radix_hist_all(const uint32_t *__restrict__ keys, int64_t n, const uint64_t *__r
 }
 
 __device__ __forceinline__ void gather_put(const uint32_t *__restrict__ gsrc,
+                                           const uint32_t *__restrict__ gtiles,
                                            uint32_t *__restrict__ gdst,
                                            uint32_t *__restrict__ gdst2, uint32_t v,
                                            int64_t pos) {
   const uint32_t x = gsrc[v];
   if (gdst2) {
-    gdst[pos] = packed_tile_count(x);
+    gdst[pos] = x == kWideRect ? gtiles[v] : packed_tile_count(x);
     gdst2[pos] = x;
   } else {
     gdst[pos] = x;
@@ -450,16 +452,17 @@ __device__ __forceinline__ void gather_put(const uint32_t *__restrict__ gsrc,
 // One pass, on a persistent grid: each block takes chunk tickets until they
 // run out.  kIdx: the values are the keys' input indices (no vin).
 // gsrc/gdst (may be NULL): also writes gdst[pos] = gsrc[value]; with gdst2,
-// gsrc holds packed tile rectangles: gdst[pos] = their tile counts and
-// gdst2[pos] = the words.
+// gsrc holds packed tile rectangles: gdst[pos] = their tile counts (from
+// gtiles for a kWideRect word) and gdst2[pos] = the words.
 template <bool kIdx>
 __global__ void __launch_bounds__(kOsThreads)
 radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
                const uint64_t *__restrict__ n_dev, int pass, uint32_t *__restrict__ words,
                uint64_t *__restrict__ st_cur, uint64_t *__restrict__ st_next,
                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-               const uint32_t *__restrict__ gsrc, uint32_t *__restrict__ gdst,
-               uint32_t *__restrict__ gdst2, uint32_t *__restrict__ err) {
+               const uint32_t *__restrict__ gsrc, const uint32_t *__restrict__ gtiles,
+               uint32_t *__restrict__ gdst, uint32_t *__restrict__ gdst2,
+               uint32_t *__restrict__ err) {
   __shared__ uint32_t s_whist[kOsWaves][256];  // per-wave digit counts, then offsets
   __shared__ uint32_t s_gex[256];              // global exclusive digit offsets
   __shared__ uint32_t s_base[256];             // + the earlier chunks of this one
@@ -519,7 +522,7 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
           const uint32_t v = kIdx ? (uint32_t)i : vin[i];
           kout[i] = kin[i];
           vout[i] = v;
-          if (gdst) gather_put(gsrc, gdst, gdst2, v, i);
+          if (gdst) gather_put(gsrc, gtiles, gdst, gdst2, v, i);
         }
       }
       __syncthreads();  // s_ticket is read before the next ticket overwrites it
@@ -676,7 +679,7 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
       const uint32_t pos = s_base[d] + (uint32_t)e - s_cex[d];
       kout[pos] = k;
       vout[pos] = v;
-      if (gdst) gather_put(gsrc, gdst, gdst2, v, pos);
+      if (gdst) gather_put(gsrc, gtiles, gdst, gdst2, v, pos);
     }
     __syncthreads();  // LDS is read before the next chunk clears it
   }
@@ -755,14 +758,9 @@ void launch_duplicate(const uint32_t *order, const uint32_t *offsets, const uint
     return;
   }
   const int64_t nb = (total + 255) / 256;
-  if (prect_sorted)
-    hipLaunchKernelGGL(duplicate_kernel<true>, dim3((unsigned)nb), dim3(256), 0, s, order,
-                       offsets, tiles, rect, prect_sorted, cams, N, total, pair_cap, keys, vals,
-                       overflow, zero, zero_n);
-  else
-    hipLaunchKernelGGL(duplicate_kernel<false>, dim3((unsigned)nb), dim3(256), 0, s, order,
-                       offsets, tiles, rect, prect_sorted, cams, N, total, pair_cap, keys, vals,
-                       overflow, zero, zero_n);
+  hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)nb), dim3(256), 0, s, order, offsets, tiles,
+                     rect, prect_sorted, cams, N, total, pair_cap, keys, vals, overflow, zero,
+                     zero_n);
 }
 
 void launch_upload_cams(const DevCam *host, int n, DevCam *dst, hipStream_t s, ZeroList z) {
@@ -776,15 +774,15 @@ void launch_upload_cams(const DevCam *host, int n, DevCam *dst, hipStream_t s, Z
 }
 
 void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
-                            const uint32_t *tiles, const int4 *rect, const Slot *slots,
-                            const int *n_slots, int64_t inst_cap, const uint64_t *n_inst,
-                            uint64_t pair_cap, uint32_t *keys, uint32_t *vals,
-                            uint32_t *overflow, hipStream_t s) {
+                            const uint32_t *tiles, const int4 *rect, const uint32_t *prect_sorted,
+                            const Slot *slots, const int *n_slots, int64_t inst_cap,
+                            const uint64_t *n_inst, uint64_t pair_cap, uint32_t *keys,
+                            uint32_t *vals, uint32_t *overflow, hipStream_t s) {
   if (inst_cap <= 0) return;
   const int64_t blocks = std::min<int64_t>((inst_cap + 255) / 256, 4096);
   hipLaunchKernelGGL(duplicate_slots_kernel, dim3((unsigned)blocks), dim3(256), 0, s, order,
-                     offsets, tiles, rect, slots, n_slots, inst_cap, n_inst, pair_cap, keys, vals,
-                     overflow);
+                     offsets, tiles, rect, prect_sorted, slots, n_slots, inst_cap, n_inst,
+                     pair_cap, keys, vals, overflow);
 }
 
 size_t sort_tmp_bytes(int64_t n) {
@@ -795,7 +793,8 @@ size_t sort_tmp_bytes(int64_t n) {
 int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint32_t *va,
                       uint32_t *kb, uint32_t *vb, int64_t n, int bits, void *tmp, hipStream_t s,
                       const uint64_t *n_dev, const uint32_t *gather_src, uint32_t *gather_dst,
-                      uint32_t *err, uint32_t *zeroed_words, uint32_t *gather_dst2) {
+                      uint32_t *err, uint32_t *zeroed_words, uint32_t *gather_dst2,
+                      const uint32_t *gather_tiles) {
   if (n <= 0) return 0;
   const int64_t nch = (n + kOsChunk - 1) / kOsChunk;
   uint32_t *words = zeroed_words ? zeroed_words : (uint32_t *)tmp;
@@ -821,15 +820,16 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
     const uint32_t *gs = lastp ? gather_src : nullptr;
     uint32_t *gd = lastp ? gather_dst : nullptr;
     uint32_t *gd2 = lastp ? gather_dst2 : nullptr;
+    const uint32_t *gt = lastp ? gather_tiles : nullptr;
     const unsigned grid = (unsigned)std::min<int64_t>(nch, kOsMaxBlocks);
     if (vin == nullptr)
       hipLaunchKernelGGL(radix_onesweep<true>, dim3(grid), dim3(kOsThreads), 0, s, kin,
-                         vin, n, n_dev, p, words, st[p & 1], st[(p + 1) & 1], kout, vout, gs, gd,
-                         gd2, err);
+                         vin, n, n_dev, p, words, st[p & 1], st[(p + 1) & 1], kout, vout, gs, gt,
+                         gd, gd2, err);
     else
       hipLaunchKernelGGL(radix_onesweep<false>, dim3(grid), dim3(kOsThreads), 0, s, kin,
-                         vin, n, n_dev, p, words, st[p & 1], st[(p + 1) & 1], kout, vout, gs, gd,
-                         gd2, err);
+                         vin, n, n_dev, p, words, st[p & 1], st[(p + 1) & 1], kout, vout, gs, gt,
+                         gd, gd2, err);
     which = (kout == ka) ? 0 : 1;
     kin = kout;
     vin = vout;

@@ -41,6 +41,12 @@ CASES = {
     # torus knot at reduced resolution (surface-like depth complexity)
     "knot60k_320x213": lambda: (sg.scene_torus_knot(60_000, seed=15),
                                 sg.camera_torus_knot(width=320, height=213, f=240.0)),
+    # a strip 258 tiles wide: the tile rectangles of splats past tile column
+    # 255 do not fit the packed 8-bit form, so the duplicate reads theirs
+    # unpacked (the per-instance fallback) beside packed ones
+    "strip3k_4128x40": lambda: (sg.scene_random(3000, seed=31, log_mu=-3.0),
+                                sg.look_at_camera((0.0, 0.1, -3.5), width=4128, height=40,
+                                                  fx=1500.0)),
 }
 
 

@@ -29,6 +29,9 @@ def _requests():
         w, h = sizes[i % len(sizes)]
         cam = sg.orbit_camera(3.0 + 0.2 * i, 0.6 * i, 0.05 * (i % 5) - 0.1, w, h)
         reqs.append((i % 3, cam))
+    # the 40k knot in 64 x 64 pixels: thousands of pairs per tile, so the
+    # served forward runs split (half-quadrant) work units
+    reqs.append((2, sg.orbit_camera(3.0, 0.4, 0.1, 64, 64)))
     return reqs
 
 
@@ -145,7 +148,7 @@ def test_served_images_match_oracle_on_samples(env):
     out, _ = _serve(rast, sids, reqs, max_requests=4, max_batches=2, max_instances=200_000,
                     max_pairs=4_000_000, max_tiles=4096, use_graph=True)
     rng = np.random.default_rng(7)
-    for i in (0, 3, 6):
+    for i in (0, 3, 6, 10):
         si, cam = reqs[i]
         H, W = cam["height"], cam["width"]
         pix = np.stack([np.zeros(400, np.int32), rng.integers(0, H, 400),
