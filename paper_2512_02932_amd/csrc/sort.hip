@@ -10,8 +10,8 @@
 // duplicated in index order, with far fewer bits sorted per pair.
 //
 // The radix sort uses 8-bit digits: one up-front launch counts the digits
-// of every pass, and each pass is a single launch that ranks 8192-key
-// chunks (16 wave64 per chunk, wave ballots for equal digits) and finds
+// of every pass, and each pass is a single launch that ranks 8192- or
+// 4096-key chunks (16 wave64 per chunk, wave ballots for equal digits) and finds
 // each chunk's place by a decoupled look-back over the chunks before it.
 
 #include "hgs_internal.h"
@@ -347,7 +347,7 @@ duplicate_slots_kernel(const uint32_t *__restrict__ order, const uint32_t *__res
 //
 // An up-front kernel counts the digits of every pass at once (the global
 // digit totals of a pass do not depend on the order the earlier passes
-// leave).  Each pass is then one kernel over chunks of kOsChunk keys.  A
+// leave).  Each pass is then one kernel over chunks of 8192 (or 4096) keys.  A
 // chunk takes a ticket from an atomic counter (tickets follow the order in
 // which blocks start, so a chunk only ever waits for chunks that are
 // already running), ranks its keys in input order, publishes its per-digit
@@ -363,8 +363,12 @@ duplicate_slots_kernel(const uint32_t *__restrict__ order, const uint32_t *__res
 // then wrong but every wave ends).
 constexpr int kOsThreads = 1024;
 constexpr int kOsWaves = kOsThreads / 64;
-constexpr int kOsRows = 8;                        // keys per thread
-constexpr int kOsChunk = kOsThreads * kOsRows;    // 8192 keys per chunk
+// Keys per thread: 8 (8192-key chunks), or 4 (4096-key chunks) for a sort
+// whose small-chunk count still fits one resident block per CU
+// (kSmallChunkCap): a pass costs about one chunk's latency per round of
+// resident chunks, so more, shorter chunks finish sooner there.
+constexpr int kOsRowsBig = 8, kOsRowsSmall = 4;
+constexpr int64_t kSmallChunkCap = 256;
 constexpr int kPartWin = 12;  // look-back words per thread per round (4 parts: 48 per digit)
 constexpr int kMaxPasses = 4;
 constexpr int kOsWords = kSortWords;  // hist [pass][256], tickets [pass], spare
@@ -375,7 +379,7 @@ constexpr uint64_t kValMask = (1ull << 62) - 1;
 constexpr int kSpinLimit = 1 << 16;  // look-back rounds before giving up
 constexpr int kOsMaxBlocks = 1024;  // persistent grid of a pass (two per CU and more)
 
-__device__ __forceinline__ int64_t os_chunks(int64_t n) { return (n + kOsChunk - 1) / kOsChunk; }
+
 
 // Digit counts of all passes (atomics into hist[pass][256], zeroed before),
 // and the first pass's status table cleared.  Each thread counts groups of 8
@@ -387,7 +391,8 @@ constexpr int kHistMaxBlocks = 512;
 template <bool kVec>
 __global__ void __launch_bounds__(kHistThreads)
 radix_hist_all(const uint32_t *__restrict__ keys, int64_t n, const uint64_t *__restrict__ n_dev,
-               int passes, uint32_t *__restrict__ hist, uint64_t *__restrict__ st0) {
+               int passes, int chunk, uint32_t *__restrict__ hist,
+               uint64_t *__restrict__ st0) {
   __shared__ uint32_t h[kMaxPasses][256];
   n = eff_n(n, n_dev);
   for (int k = threadIdx.x; k < kMaxPasses * 256; k += kHistThreads) (&h[0][0])[k] = 0;
@@ -425,7 +430,7 @@ radix_hist_all(const uint32_t *__restrict__ keys, int64_t n, const uint64_t *__r
       atomicAdd(&h[p][d], c);
     }
   }
-  const int64_t rows = os_chunks(n) * 256;
+  const int64_t rows = (n + chunk - 1) / chunk * 256;
   for (int64_t i = (int64_t)blockIdx.x * kHistThreads + threadIdx.x; i < rows; i += stride)
     st0[i] = 0;
   __syncthreads();
@@ -454,7 +459,7 @@ __device__ __forceinline__ void gather_put(const uint32_t *__restrict__ gsrc,
 // gsrc/gdst (may be NULL): also writes gdst[pos] = gsrc[value]; with gdst2,
 // gsrc holds packed tile rectangles: gdst[pos] = their tile counts (from
 // gtiles for a kWideRect word) and gdst2[pos] = the words.
-template <bool kIdx>
+template <bool kIdx, int kRows>
 __global__ void __launch_bounds__(kOsThreads)
 radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
                const uint64_t *__restrict__ n_dev, int pass, uint32_t *__restrict__ words,
@@ -476,12 +481,13 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
   __shared__ uint4 s_lpart[4][256];       // a round's part results
   __shared__ int s_lany;
   __shared__ uint32_t s_cex[256];         // chunk-local exclusive digit offsets
-  __shared__ uint32_t s_key[kOsChunk];    // the chunk in digit order
-  __shared__ uint32_t s_val[kOsChunk];
+  constexpr int kChunk = kOsThreads * kRows;
+  __shared__ uint32_t s_key[kChunk];      // the chunk in digit order
+  __shared__ uint32_t s_val[kChunk];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int shift = 8 * pass;
   n = eff_n(n, n_dev);
-  const int64_t nch = os_chunks(n);
+  const int64_t nch = (n + kChunk - 1) / kChunk;
   if ((int64_t)blockIdx.x >= nch) return;  // more blocks than chunks
   if (tid == 0) s_trivial = 0;
   // global exclusive digit offsets of this pass
@@ -512,11 +518,11 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
     const int64_t chunk = (int64_t)s_ticket;
     if (chunk >= nch) return;  // block-uniform
     if (tid < 256) st_next[chunk * 256 + tid] = 0;  // the next pass's row
-    const int64_t c0 = chunk * kOsChunk;
+    const int64_t c0 = chunk * kChunk;
 
     if (s_trivial) {  // one digit for all keys: the identity
 #pragma unroll
-      for (int j = 0; j < kOsRows; ++j) {
+      for (int j = 0; j < kRows; ++j) {
         const int64_t i = c0 + (int64_t)j * kOsThreads + tid;
         if (i < n) {
           const uint32_t v = kIdx ? (uint32_t)i : vin[i];
@@ -529,19 +535,19 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
       continue;
     }
 
-    // each wave owns 64 kOsRows consecutive keys, as kOsRows rows of 64
-    const int64_t wb = c0 + (int64_t)w * (64 * kOsRows);
-    uint32_t key[kOsRows], val[kOsRows], rank[kOsRows];
-    bool ok[kOsRows];
+    // each wave owns 64 kRows consecutive keys, as kRows rows of 64
+    const int64_t wb = c0 + (int64_t)w * (64 * kRows);
+    uint32_t key[kRows], val[kRows], rank[kRows];
+    bool ok[kRows];
 #pragma unroll
-    for (int j = 0; j < kOsRows; ++j) {
+    for (int j = 0; j < kRows; ++j) {
       const int64_t i = wb + (int64_t)j * 64 + lane;
       ok[j] = i < n;
       key[j] = ok[j] ? kin[i] : 0u;
       val[j] = ok[j] ? (kIdx ? (uint32_t)i : vin[i]) : 0u;
     }
 #pragma unroll
-    for (int j = 0; j < kOsRows; ++j) {
+    for (int j = 0; j < kRows; ++j) {
       const uint32_t d = (key[j] >> shift) & 255u;
       uint64_t peers = __ballot(ok[j]);
 #pragma unroll
@@ -661,7 +667,7 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
     // the chunk sorted by digit in LDS, so that each digit's run is written
     // out by consecutive threads (coalesced) rather than key by key
 #pragma unroll
-    for (int j = 0; j < kOsRows; ++j) {
+    for (int j = 0; j < kRows; ++j) {
       if (!ok[j]) continue;
       const uint32_t d = (key[j] >> shift) & 255u;
       const uint32_t lp = s_cex[d] + s_whist[w][d] + rank[j];
@@ -669,9 +675,9 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
       s_val[lp] = val[j];
     }
     __syncthreads();
-    const int cn = (int)(n - c0 < kOsChunk ? n - c0 : kOsChunk);
+    const int cn = (int)(n - c0 < kChunk ? n - c0 : kChunk);
 #pragma unroll
-    for (int j = 0; j < kOsRows; ++j) {
+    for (int j = 0; j < kRows; ++j) {
       const int e = j * kOsThreads + tid;
       if (e >= cn) continue;
       const uint32_t k = s_key[e], v = s_val[e];
@@ -785,9 +791,36 @@ void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
                      pair_cap, keys, vals, overflow);
 }
 
+// chunk size of a sort of n keys (capacity n)
+static int sort_rows(int64_t n) {
+  const int64_t small = kOsThreads * kOsRowsSmall;
+  return (n + small - 1) / small <= kSmallChunkCap ? kOsRowsSmall : kOsRowsBig;
+}
+
+// Enough for a sort of any m <= n keys (either chunk size).
 size_t sort_tmp_bytes(int64_t n) {
-  const int64_t nch = std::max<int64_t>((n + kOsChunk - 1) / kOsChunk, 1);
+  const int64_t big = (int64_t)kOsThreads * kOsRowsBig, small = (int64_t)kOsThreads * kOsRowsSmall;
+  const int64_t nch = std::max<int64_t>(
+      std::max<int64_t>((n + big - 1) / big, std::min<int64_t>((n + small - 1) / small,
+                                                               kSmallChunkCap)),
+      1);
   return kOsHead + (size_t)(2 * nch * 256) * sizeof(uint64_t);
+}
+
+template <int kRows>
+static void launch_pass(bool idx, unsigned grid, hipStream_t s, const uint32_t *kin,
+                        const uint32_t *vin, int64_t n, const uint64_t *n_dev, int p,
+                        uint32_t *words, uint64_t *st_cur, uint64_t *st_next, uint32_t *kout,
+                        uint32_t *vout, const uint32_t *gs, const uint32_t *gt, uint32_t *gd,
+                        uint32_t *gd2, uint32_t *err) {
+  if (idx)
+    hipLaunchKernelGGL((radix_onesweep<true, kRows>), dim3(grid), dim3(kOsThreads), 0, s, kin,
+                       vin, n, n_dev, p, words, st_cur, st_next, kout, vout, gs, gt, gd, gd2,
+                       err);
+  else
+    hipLaunchKernelGGL((radix_onesweep<false, kRows>), dim3(grid), dim3(kOsThreads), 0, s, kin,
+                       vin, n, n_dev, p, words, st_cur, st_next, kout, vout, gs, gt, gd, gd2,
+                       err);
 }
 
 int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint32_t *va,
@@ -796,7 +829,9 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
                       uint32_t *err, uint32_t *zeroed_words, uint32_t *gather_dst2,
                       const uint32_t *gather_tiles) {
   if (n <= 0) return 0;
-  const int64_t nch = (n + kOsChunk - 1) / kOsChunk;
+  const int rows = sort_rows(n);
+  const int chunk = kOsThreads * rows;
+  const int64_t nch = (n + chunk - 1) / chunk;
   uint32_t *words = zeroed_words ? zeroed_words : (uint32_t *)tmp;
   uint64_t *st[2] = {(uint64_t *)((char *)tmp + kOsHead),
                      (uint64_t *)((char *)tmp + kOsHead) + nch * 256};
@@ -808,10 +843,10 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
       std::min<int64_t>((n + 8 * kHistThreads - 1) / (8 * kHistThreads), kHistMaxBlocks);
   if (((uintptr_t)k0 & 15) == 0)
     hipLaunchKernelGGL(radix_hist_all<true>, dim3((unsigned)hb), dim3(kHistThreads), 0, s, k0,
-                       n, n_dev, passes, words, st[0]);
+                       n, n_dev, passes, chunk, words, st[0]);
   else
     hipLaunchKernelGGL(radix_hist_all<false>, dim3((unsigned)hb), dim3(kHistThreads), 0, s, k0,
-                       n, n_dev, passes, words, st[0]);
+                       n, n_dev, passes, chunk, words, st[0]);
   const uint32_t *kin = k0, *vin = v0;
   uint32_t *kout = ka, *vout = va;
   int which = 0;
@@ -822,14 +857,12 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
     uint32_t *gd2 = lastp ? gather_dst2 : nullptr;
     const uint32_t *gt = lastp ? gather_tiles : nullptr;
     const unsigned grid = (unsigned)std::min<int64_t>(nch, kOsMaxBlocks);
-    if (vin == nullptr)
-      hipLaunchKernelGGL(radix_onesweep<true>, dim3(grid), dim3(kOsThreads), 0, s, kin,
-                         vin, n, n_dev, p, words, st[p & 1], st[(p + 1) & 1], kout, vout, gs, gt,
-                         gd, gd2, err);
+    if (rows == kOsRowsSmall)
+      launch_pass<kOsRowsSmall>(vin == nullptr, grid, s, kin, vin, n, n_dev, p, words, st[p & 1],
+                                st[(p + 1) & 1], kout, vout, gs, gt, gd, gd2, err);
     else
-      hipLaunchKernelGGL(radix_onesweep<false>, dim3(grid), dim3(kOsThreads), 0, s, kin,
-                         vin, n, n_dev, p, words, st[p & 1], st[(p + 1) & 1], kout, vout, gs, gt,
-                         gd, gd2, err);
+      launch_pass<kOsRowsBig>(vin == nullptr, grid, s, kin, vin, n, n_dev, p, words, st[p & 1],
+                              st[(p + 1) & 1], kout, vout, gs, gt, gd, gd2, err);
     which = (kout == ka) ? 0 : 1;
     kin = kout;
     vin = vout;
