@@ -611,11 +611,12 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   const uint32_t *order = nullptr;
   {
     // instances in depth order; the last pass also gathers their tile counts
-    // (and packed rectangles)
+    // (and packed rectangles).  Culled instances have key 0 and no pairs, so
+    // their place in the order does not matter (zero_free)
     StageTimer t(ctx, HGS_STAGE_DEPTH_SORT, st->stream);
     const int w = launch_radix_sort(st->zbits, nullptr, za, oa, zb, ob, VN, 32, dsort_tmp,
                                     st->stream, nullptr, prect, cnt, st->overflow, dwords,
-                                    prect_s, st->tiles);
+                                    prect_s, st->tiles, /*zero_free=*/true);
     order = w ? ob : oa;
   }
   {

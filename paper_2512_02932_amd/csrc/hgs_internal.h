@@ -189,10 +189,14 @@ void launch_duplicate_slots(const uint32_t *order, const uint32_t *offsets,
                             uint32_t *vals, uint32_t *overflow, hipStream_t s);
 
 // Stable LSD radix sort of n (u32 key, u32 value) pairs on the low `bits`
-// bits (at most 32), 8 bits per pass.  The first pass reads (k0, v0) (v0
-// NULL: value = index) and writes (ka, va); later passes ping-pong between
-// (ka, va) and (kb, vb).  k0/v0 may alias kb/vb but not ka/va.  Returns 0 if
-// the result is in (ka, va), 1 if in (kb, vb).  `tmp` holds
+// bits (at most 32), 8 bits per pass.  The passes read (k0, v0) (v0 NULL:
+// value = index) and ping-pong between (ka, va) and (kb, vb).  k0/v0 may
+// alias kb/vb but not ka/va; when they alias neither, a pass whose digit is
+// the same for every key is skipped on the device.  Returns 0 if the result
+// is in (ka, va), 1 if in (kb, vb) (fixed by the number of passes).
+// zero_free: keys equal to 0 are don't-care (their place among the other
+// keys may be anything), so a pass whose digit is the same for every other
+// key is skipped as well; the other keys' order is exact.  `tmp` holds
 // sort_tmp_bytes(n) bytes.  If gather_dst is given, the last pass also
 // writes gather_dst[j] = gather_src[value j] of the sorted order; with
 // gather_dst2 as well, gather_src holds packed tile rectangles and the pass
@@ -209,7 +213,7 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
                       const uint64_t *n_dev = nullptr, const uint32_t *gather_src = nullptr,
                       uint32_t *gather_dst = nullptr, uint32_t *err = nullptr,
                       uint32_t *zeroed_words = nullptr, uint32_t *gather_dst2 = nullptr,
-                      const uint32_t *gather_tiles = nullptr);
+                      const uint32_t *gather_tiles = nullptr, bool zero_free = false);
 
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);

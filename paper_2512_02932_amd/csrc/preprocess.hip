@@ -397,7 +397,11 @@ __device__ __forceinline__ void geo_setup(const float *mf, const float *sf, cons
   for (int i = 0; i < 3; ++i) o.s[i] = sf[i];
   const double r[4] = {qf[0], qf[1], qf[2], qf[3]};
   o.qn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
-  for (int i = 0; i < 4; ++i) o.q[i] = r[i] / o.qn;
+  // one binary64 division per divisor, then products (a division is a
+  // long dependent sequence on the GPU; the results stay within binary64
+  // rounding of the quotients)
+  const double iqn = 1.0 / o.qn;
+  for (int i = 0; i < 4; ++i) o.q[i] = r[i] * iqn;
   const double w = o.q[0], x = o.q[1], y = o.q[2], z = o.q[3];
   double R[9];
   R[0] = 1.0 - 2.0 * (y * y + z * z);
@@ -433,7 +437,9 @@ __device__ __forceinline__ void geo_setup(const float *mf, const float *sf, cons
   const double fx = c.fx, fy = c.fy, cx = c.cx, cy = c.cy;
   if (!is2d) {
     // A = J R_v R S (2x3): Sigma' = A A^T + delta I
-    const double J00 = fx / Z, J02 = -fx * X / (Z * Z), J11 = fy / Z, J12 = -fy * Yc / (Z * Z);
+    const double iz = 1.0 / Z;
+    const double J00 = fx * iz, J02 = -fx * X * (iz * iz), J11 = fy * iz,
+                 J12 = -fy * Yc * (iz * iz);
     for (int j = 0; j < 3; ++j) {
       const double c0 = o.RvR[j] * o.s[j], c1 = o.RvR[3 + j] * o.s[j], c2 = o.RvR[6 + j] * o.s[j];
       o.A[j] = J00 * c0 + J02 * c2;
@@ -443,11 +449,12 @@ __device__ __forceinline__ void geo_setup(const float *mf, const float *sf, cons
     const double S1 = o.A[0] * o.A[3] + o.A[1] * o.A[4] + o.A[2] * o.A[5];
     const double S2 = o.A[3] * o.A[3] + o.A[4] * o.A[4] + o.A[5] * o.A[5] + (double)opt.dilation;
     const double det = S0 * S2 - S1 * S1;
-    o.conic[0] = S2 / det;
-    o.conic[1] = -S1 / det;
-    o.conic[2] = S0 / det;
-    o.mu2[0] = fx * X / Z + cx;
-    o.mu2[1] = fy * Yc / Z + cy;
+    const double idet = 1.0 / det;
+    o.conic[0] = S2 * idet;
+    o.conic[1] = -S1 * idet;
+    o.conic[2] = S0 * idet;
+    o.mu2[0] = fx * X * iz + cx;
+    o.mu2[1] = fy * Yc * iz + cy;
   } else {
     // plane (u, v, 1) -> homogeneous pixel in the local frame:
     // M = K' [s_x t_u | s_y t_v | p_c], K' = K shifted by the frame origin
@@ -485,7 +492,8 @@ __device__ __forceinline__ void view_dir(const float *mf, const DevCam &c, doubl
   double dv[3];
   for (int i = 0; i < 3; ++i) dv[i] = (double)mf[i] - c.o[i];
   dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-  for (int i = 0; i < 3; ++i) dir[i] = dv[i] / dist;
+  const double idist = 1.0 / dist;
+  for (int i = 0; i < 3; ++i) dir[i] = dv[i] * idist;
 }
 
 __device__ __forceinline__ double col_of(const double *M9, int row, int axis) {
@@ -672,7 +680,8 @@ __device__ __forceinline__ void geo_chain(const Geo &o, const DevCam &c, const D
     const double S00 = -(t00 * Q[0] + t01 * Q[1]);
     const double S01 = -(t00 * Q[1] + t01 * Q[2]);
     const double S11 = -(t10 * Q[1] + t11 * Q[2]);
-    const double J00 = fx / Z, J02 = -fx * X / (Z * Z), J11 = fy / Z, J12 = -fy * Yc / (Z * Z);
+    const double iz = 1.0 / Z, iz2 = iz * iz, iz3 = iz2 * iz;
+    const double J00 = fx * iz, J02 = -fx * X * iz2, J11 = fy * iz, J12 = -fy * Yc * iz2;
     double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -690,7 +699,6 @@ __device__ __forceinline__ void geo_chain(const Geo &o, const DevCam &c, const D
       gRvR[6 + j] += gc2 * o.s[j];
       gsv[j] += gc0 * o.RvR[j] + gc1 * o.RvR[3 + j] + gc2 * o.RvR[6 + j];
     }
-    const double iz = 1.0 / Z, iz2 = iz * iz, iz3 = iz2 * iz;
     const double gmx = a[0], gmy = a[1];
     gpc[0] += gJ02 * (-fx * iz2) + gmx * fx * iz;
     gpc[1] += gJ12 * (-fy * iz2) + gmy * fy * iz;
@@ -759,8 +767,9 @@ __device__ __forceinline__ void geo_chain(const Geo &o, const DevCam &c, const D
              y * gR[5] + x * gR[6] + y * gR[7])};
   // q = r / |r|
   const double dq = gqn[0] * o.q[0] + gqn[1] * o.q[1] + gqn[2] * o.q[2] + gqn[3] * o.q[3];
+  const double iqn = 1.0 / o.qn;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) gq[k] += (gqn[k] - o.q[k] * dq) / o.qn;
+  for (int k = 0; k < 4; ++k) gq[k] += (gqn[k] - o.q[k] * dq) * iqn;
 #pragma unroll
   for (int k = 0; k < 3; ++k) gs[k] += gsv[k];
 }
@@ -799,8 +808,9 @@ __device__ __forceinline__ void colour_chain(const float *f, const double *Y, co
   sh_grad_dot<DEG>(dir[0], dir[1], dir[2], wj, gdir);
   // dir = (mu - o) / |mu - o|
   const double dd = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
+  const double idist = 1.0 / dist;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) gmu[k] += (gdir[k] - dir[k] * dd) / dist;
+  for (int k = 0; k < 3; ++k) gmu[k] += (gdir[k] - dir[k] * dd) * idist;
 }
 
 // Modes of the kernel:

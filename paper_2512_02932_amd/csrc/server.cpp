@@ -115,7 +115,7 @@ void enqueue_pass(const hgs_server *sv, Lane &L) {
                           L.flags, L.prect, s);
   const int w = launch_radix_sort(L.zbits, nullptr, L.za, L.oa, L.zb, L.ob, I, 32, L.sort_tmp, s,
                                   n_inst, L.prect, L.cnt, &L.status_dev->overflow, nullptr,
-                                  L.prect_s, L.tiles);
+                                  L.prect_s, L.tiles, /*zero_free=*/true);
   const uint32_t *order = w ? L.ob : L.oa;
   launch_scan(L.cnt, L.offsets, I, pairs, L.scan_tmp, s, n_inst);
   launch_duplicate_slots(order, L.offsets, L.tiles, L.rect, L.prect_s, slots, n_slots, I,

@@ -371,7 +371,8 @@ constexpr int kOsRowsBig = 8, kOsRowsSmall = 4;
 constexpr int64_t kSmallChunkCap = 256;
 constexpr int kPartWin = 12;  // look-back words per thread per round (4 parts: 48 per digit)
 constexpr int kMaxPasses = 4;
-constexpr int kOsWords = kSortWords;  // hist [pass][256], tickets [pass], spare
+constexpr int kOsWords = kSortWords;  // hist [pass][256], tickets [pass], zero keys
+constexpr int kZeroWord = kMaxPasses * 256 + kMaxPasses;  // count of keys equal to 0
 static_assert(kSortWords == kMaxPasses * 256 + kMaxPasses + 1, "sort words layout");
 constexpr size_t kOsHead = 4352;                  // bytes before the status tables
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62;
@@ -394,9 +395,12 @@ radix_hist_all(const uint32_t *__restrict__ keys, int64_t n, const uint64_t *__r
                int passes, int chunk, uint32_t *__restrict__ hist,
                uint64_t *__restrict__ st0) {
   __shared__ uint32_t h[kMaxPasses][256];
+  __shared__ uint32_t s_zero;  // keys equal to 0
   n = eff_n(n, n_dev);
   for (int k = threadIdx.x; k < kMaxPasses * 256; k += kHistThreads) (&h[0][0])[k] = 0;
+  if (threadIdx.x == 0) s_zero = 0;
   __syncthreads();
+  uint32_t zeros = 0;
   const int64_t stride = (int64_t)gridDim.x * kHistThreads;
   const int64_t groups = (n + 7) >> 3;
   for (int64_t g = (int64_t)blockIdx.x * kHistThreads + threadIdx.x; g < groups; g += stride) {
@@ -412,6 +416,8 @@ radix_hist_all(const uint32_t *__restrict__ keys, int64_t n, const uint64_t *__r
 #pragma unroll
       for (int j = 0; j < 8; ++j) k[j] = j < m ? keys[i0 + j] : 0u;
     }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) zeros += (j < m && k[j] == 0u) ? 1u : 0u;
     for (int p = 0; p < passes; ++p) {
       const int sh = 8 * p;
       uint32_t d = (k[0] >> sh) & 255u, c = 1;
@@ -433,11 +439,13 @@ radix_hist_all(const uint32_t *__restrict__ keys, int64_t n, const uint64_t *__r
   const int64_t rows = (n + chunk - 1) / chunk * 256;
   for (int64_t i = (int64_t)blockIdx.x * kHistThreads + threadIdx.x; i < rows; i += stride)
     st0[i] = 0;
+  if (zeros) atomicAdd(&s_zero, zeros);
   __syncthreads();
   for (int k = threadIdx.x; k < passes * 256; k += kHistThreads) {
     const uint32_t c = (&h[0][0])[k];
     if (c) atomicAdd(&hist[k], c);
   }
+  if (threadIdx.x == 0 && s_zero) atomicAdd(&hist[kZeroWord], s_zero);
 }
 
 __device__ __forceinline__ void gather_put(const uint32_t *__restrict__ gsrc,
@@ -454,20 +462,39 @@ __device__ __forceinline__ void gather_put(const uint32_t *__restrict__ gsrc,
   }
 }
 
+// The buffers of one sort.  k0/v0 the input (v0 NULL: the values are the
+// keys' input indices), (ka, va) and (kb, vb) the ping-pong pair, st[2] the
+// status tables.  skip: passes whose digit is the same for every key are
+// skipped on the device (k0 must then alias neither ka nor kb); with
+// zero_free, for every key other than 0 (keys equal to 0 then keep their
+// relative order but not their place among the others).
+struct SortIO {
+  const uint32_t *k0, *v0;
+  uint32_t *kbuf[2], *vbuf[2];
+  uint64_t *st[2];
+  int passes;
+  int skip;
+  int zero_free;  // keys equal to 0 are don't-care: they may end anywhere
+};
+
 // One pass, on a persistent grid: each block takes chunk tickets until they
-// run out.  kIdx: the values are the keys' input indices (no vin).
-// gsrc/gdst (may be NULL): also writes gdst[pos] = gsrc[value]; with gdst2,
-// gsrc holds packed tile rectangles: gdst[pos] = their tile counts (from
-// gtiles for a kWideRect word) and gdst2[pos] = the words.
-template <bool kIdx, int kRows>
+// run out.  Its input, output and status tables follow from the passes that
+// do work: without skipping, pass p reads the input (p = 0) or buffer
+// (p - 1) & 1 and writes buffer p & 1.  With skipping, a pass whose digit is
+// constant (all the keys in one bucket of the up-front histogram) exits at
+// once, and the k-th of the M passes that remain writes buffer
+// E ^ ((M - 1 - k) & 1), E = (passes - 1) & 1, so the last one leaves the
+// result where the host expects it; if every pass is constant the last one
+// copies the input there.  Only the pass that writes the result does the
+// gather: gsrc/gdst (may be NULL) write gdst[pos] = gsrc[value]; with
+// gdst2, gsrc holds packed tile rectangles: gdst[pos] = their tile counts
+// (from gtiles for a kWideRect word) and gdst2[pos] = the words.
+template <int kRows>
 __global__ void __launch_bounds__(kOsThreads)
-radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
-               const uint64_t *__restrict__ n_dev, int pass, uint32_t *__restrict__ words,
-               uint64_t *__restrict__ st_cur, uint64_t *__restrict__ st_next,
-               uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-               const uint32_t *__restrict__ gsrc, const uint32_t *__restrict__ gtiles,
-               uint32_t *__restrict__ gdst, uint32_t *__restrict__ gdst2,
-               uint32_t *__restrict__ err) {
+radix_onesweep(SortIO io, int64_t n, const uint64_t *__restrict__ n_dev, int pass,
+               uint32_t *__restrict__ words, const uint32_t *__restrict__ gsrc_in,
+               const uint32_t *__restrict__ gtiles, uint32_t *__restrict__ gdst_in,
+               uint32_t *__restrict__ gdst2, uint32_t *__restrict__ err) {
   __shared__ uint32_t s_whist[kOsWaves][256];  // per-wave digit counts, then offsets
   __shared__ uint32_t s_gex[256];              // global exclusive digit offsets
   __shared__ uint32_t s_base[256];             // + the earlier chunks of this one
@@ -484,12 +511,47 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
   constexpr int kChunk = kOsThreads * kRows;
   __shared__ uint32_t s_key[kChunk];      // the chunk in digit order
   __shared__ uint32_t s_val[kChunk];
+  __shared__ uint32_t s_const;             // bit q: pass q's digit is constant
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int shift = 8 * pass;
   n = eff_n(n, n_dev);
   const int64_t nch = (n + kChunk - 1) / kChunk;
   if ((int64_t)blockIdx.x >= nch) return;  // more blocks than chunks
-  if (tid == 0) s_trivial = 0;
+  if (tid == 0) {
+    s_trivial = 0;
+    s_const = 0;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    const int64_t nz = io.zero_free ? (int64_t)words[kZeroWord] : 0;
+    for (int q = 0; q < io.passes; ++q) {
+      const int64_t c = (int64_t)words[q * 256 + tid] - (tid == 0 ? nz : 0);
+      if (c == n - nz) atomicOr(&s_const, 1u << q);
+    }
+  }
+  __syncthreads();
+  // this pass's place among the passes that do work
+  const uint32_t cmask = s_const;
+  const uint32_t all = (1u << io.passes) - 1u;
+  const int M = io.skip ? io.passes - __popc(cmask & all) : io.passes;
+  const int k = io.skip ? pass - __popc(cmask & ((1u << pass) - 1u)) : pass;
+  const bool mine_const = (cmask >> pass) & 1u;
+  const bool copy_all = io.skip && M == 0 && pass == io.passes - 1;
+  if (io.skip && mine_const && !copy_all) return;  // block-uniform
+  const int E = (io.passes - 1) & 1;
+  const int ob = io.skip ? (copy_all ? E : (E ^ ((M - 1 - k) & 1))) : (pass & 1);
+  const bool first = copy_all || k == 0;
+  const bool last = copy_all || k == M - 1;
+  const uint32_t *__restrict__ kin = first ? io.k0 : io.kbuf[ob ^ 1];
+  const uint32_t *__restrict__ vin = first ? io.v0 : io.vbuf[ob ^ 1];
+  uint32_t *__restrict__ kout = io.kbuf[ob];
+  uint32_t *__restrict__ vout = io.vbuf[ob];
+  const int sk = copy_all ? 0 : k;
+  uint64_t *__restrict__ st_cur = io.st[sk & 1];
+  uint64_t *__restrict__ st_next = io.st[(sk + 1) & 1];
+  const bool gen_idx = vin == nullptr;  // first pass over index values
+  const uint32_t *__restrict__ gsrc = last ? gsrc_in : nullptr;
+  uint32_t *__restrict__ gdst = last ? gdst_in : nullptr;
   // global exclusive digit offsets of this pass
   uint32_t g = 0, gx = 0;
   if (tid < 256) {
@@ -507,7 +569,7 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
     uint32_t off = 0;
     for (int k = 0; k < w; ++k) off += s_wtot[k];
     s_gex[tid] = off + gx - g;
-    if ((int64_t)g == n) s_trivial = 1;
+    if ((int64_t)g == n || copy_all) s_trivial = 1;
   }
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -525,7 +587,7 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
       for (int j = 0; j < kRows; ++j) {
         const int64_t i = c0 + (int64_t)j * kOsThreads + tid;
         if (i < n) {
-          const uint32_t v = kIdx ? (uint32_t)i : vin[i];
+          const uint32_t v = gen_idx ? (uint32_t)i : vin[i];
           kout[i] = kin[i];
           vout[i] = v;
           if (gdst) gather_put(gsrc, gtiles, gdst, gdst2, v, i);
@@ -544,7 +606,7 @@ radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vi
       const int64_t i = wb + (int64_t)j * 64 + lane;
       ok[j] = i < n;
       key[j] = ok[j] ? kin[i] : 0u;
-      val[j] = ok[j] ? (kIdx ? (uint32_t)i : vin[i]) : 0u;
+      val[j] = ok[j] ? (gen_idx ? (uint32_t)i : vin[i]) : 0u;
     }
 #pragma unroll
     for (int j = 0; j < kRows; ++j) {
@@ -807,27 +869,13 @@ size_t sort_tmp_bytes(int64_t n) {
   return kOsHead + (size_t)(2 * nch * 256) * sizeof(uint64_t);
 }
 
-template <int kRows>
-static void launch_pass(bool idx, unsigned grid, hipStream_t s, const uint32_t *kin,
-                        const uint32_t *vin, int64_t n, const uint64_t *n_dev, int p,
-                        uint32_t *words, uint64_t *st_cur, uint64_t *st_next, uint32_t *kout,
-                        uint32_t *vout, const uint32_t *gs, const uint32_t *gt, uint32_t *gd,
-                        uint32_t *gd2, uint32_t *err) {
-  if (idx)
-    hipLaunchKernelGGL((radix_onesweep<true, kRows>), dim3(grid), dim3(kOsThreads), 0, s, kin,
-                       vin, n, n_dev, p, words, st_cur, st_next, kout, vout, gs, gt, gd, gd2,
-                       err);
-  else
-    hipLaunchKernelGGL((radix_onesweep<false, kRows>), dim3(grid), dim3(kOsThreads), 0, s, kin,
-                       vin, n, n_dev, p, words, st_cur, st_next, kout, vout, gs, gt, gd, gd2,
-                       err);
-}
+
 
 int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint32_t *va,
                       uint32_t *kb, uint32_t *vb, int64_t n, int bits, void *tmp, hipStream_t s,
                       const uint64_t *n_dev, const uint32_t *gather_src, uint32_t *gather_dst,
                       uint32_t *err, uint32_t *zeroed_words, uint32_t *gather_dst2,
-                      const uint32_t *gather_tiles) {
+                      const uint32_t *gather_tiles, bool zero_free) {
   if (n <= 0) return 0;
   const int rows = sort_rows(n);
   const int chunk = kOsThreads * rows;
@@ -847,29 +895,29 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
   else
     hipLaunchKernelGGL(radix_hist_all<false>, dim3((unsigned)hb), dim3(kHistThreads), 0, s, k0,
                        n, n_dev, passes, chunk, words, st[0]);
-  const uint32_t *kin = k0, *vin = v0;
-  uint32_t *kout = ka, *vout = va;
-  int which = 0;
+  SortIO io;
+  io.k0 = k0;
+  io.v0 = v0;
+  io.kbuf[0] = ka;
+  io.vbuf[0] = va;
+  io.kbuf[1] = kb;
+  io.vbuf[1] = vb;
+  io.st[0] = st[0];
+  io.st[1] = st[1];
+  io.passes = passes;
+  // a constant-digit pass can be skipped only if the input stays intact
+  io.skip = (k0 != ka && k0 != kb && (v0 == nullptr || (v0 != va && v0 != vb))) ? 1 : 0;
+  io.zero_free = io.skip && zero_free ? 1 : 0;
+  const unsigned grid = (unsigned)std::min<int64_t>(nch, kOsMaxBlocks);
   for (int p = 0; p < passes; ++p) {
-    const bool lastp = p == passes - 1;
-    const uint32_t *gs = lastp ? gather_src : nullptr;
-    uint32_t *gd = lastp ? gather_dst : nullptr;
-    uint32_t *gd2 = lastp ? gather_dst2 : nullptr;
-    const uint32_t *gt = lastp ? gather_tiles : nullptr;
-    const unsigned grid = (unsigned)std::min<int64_t>(nch, kOsMaxBlocks);
     if (rows == kOsRowsSmall)
-      launch_pass<kOsRowsSmall>(vin == nullptr, grid, s, kin, vin, n, n_dev, p, words, st[p & 1],
-                                st[(p + 1) & 1], kout, vout, gs, gt, gd, gd2, err);
+      hipLaunchKernelGGL(radix_onesweep<kOsRowsSmall>, dim3(grid), dim3(kOsThreads), 0, s, io, n,
+                         n_dev, p, words, gather_src, gather_tiles, gather_dst, gather_dst2, err);
     else
-      launch_pass<kOsRowsBig>(vin == nullptr, grid, s, kin, vin, n, n_dev, p, words, st[p & 1],
-                              st[(p + 1) & 1], kout, vout, gs, gt, gd, gd2, err);
-    which = (kout == ka) ? 0 : 1;
-    kin = kout;
-    vin = vout;
-    kout = (which == 0) ? kb : ka;
-    vout = (which == 0) ? vb : va;
+      hipLaunchKernelGGL(radix_onesweep<kOsRowsBig>, dim3(grid), dim3(kOsThreads), 0, s, io, n,
+                         n_dev, p, words, gather_src, gather_tiles, gather_dst, gather_dst2, err);
   }
-  return which;
+  return (passes - 1) & 1;
 }
 
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
