@@ -23,6 +23,17 @@ def _cams_multi():
     return [sg.look_at_camera(e, width=96, height=80, fx=70.0) for e in eyes]
 
 
+def _plane_scene():
+    # every mean on the plane z = 0, seen along the z axis: all instances
+    # share one depth key, so every radix pass of the depth sort has a
+    # constant digit (the sort's copy-through path) and the blend order is
+    # the index order
+    sc = sg.scene_random(2000, seed=23, log_mu=-3.0)
+    sc["means"] = sc["means"].copy()
+    sc["means"][:, 2] = 0.0
+    return sc
+
+
 CASES = {
     # the 10k-Gaussian plain forward workload: 256x256, 16 full tiles per row
     "cube10k_256": lambda: (sg.scene_uniform_cube(), sg.camera_cube()),
@@ -44,6 +55,9 @@ CASES = {
     # a strip 258 tiles wide: the tile rectangles of splats past tile column
     # 255 do not fit the packed 8-bit form, so the duplicate reads theirs
     # unpacked (the per-instance fallback) beside packed ones
+    "plane2k_160x120": lambda: (_plane_scene(),
+                                sg.look_at_camera((0.0, 0.0, -3.0), width=160, height=120,
+                                                  fx=120.0)),
     "strip3k_4128x40": lambda: (sg.scene_random(3000, seed=31, log_mu=-3.0),
                                 sg.look_at_camera((0.0, 0.1, -3.5), width=4128, height=40,
                                                   fx=1500.0)),
