@@ -678,10 +678,26 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
     st->keys = w ? kb : ka;
     st->vals = w ? vb : va;
   }
+  // the pair count of this render, for the next render on this workspace:
+  // written to mapped pinned memory by the tile-order launch, read by the
+  // host once the event recorded after the forward has fired (no wait)
+  uint64_t *status_dst = nullptr;
+  if (!cap_mode && ctx->pair_cap <= 0) {
+    if (!ws->status_host) {
+      void *h = nullptr;
+      ST_HIP(hipHostMalloc(&h, 2 * sizeof(uint64_t), hipHostMallocMapped | hipHostMallocCoherent));
+      ws->status_host = static_cast<uint64_t *>(h);
+      void *d = nullptr;
+      ST_HIP(hipHostGetDevicePointer(&d, h, 0));
+      ws->status_dev = static_cast<uint64_t *>(d);
+    }
+    status_dst = ws->status_dev;
+  }
   {
     StageTimer t(ctx, HGS_STAGE_RANGES, st->stream);
     launch_ranges(st->keys, cap, st->ranges, st->stream, st->total);
-    launch_tile_order(st->ranges, (int)n_tiles, st->order, st->stream);
+    launch_tile_order(st->ranges, (int)n_tiles, st->order, st->stream, nullptr, nullptr,
+                      st->total, status_dst);
   }
 
   ro.T_final = st->T_final;
@@ -694,17 +710,8 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
     launch_raster_fwd(st->ranges, st->order, st->vals, st->rec, st->n_tiles, W, H,
                       st->tiles_x, st->tiles_per_view, st->opt, ro, st->bmask, st->stream);
   }
-  if (!cap_mode && ctx->pair_cap <= 0) {
-    // the pair count and overflow flag of this render, for the next render
-    // on this workspace (read without waiting)
-    if (!ws->status_host) {
-      void *h = nullptr;
-      ST_HIP(hipHostMalloc(&h, 2 * sizeof(uint64_t), hipHostMallocDefault));
-      ws->status_host = static_cast<uint64_t *>(h);
-    }
+  if (status_dst) {
     if (!ws->status_ev) ST_HIP(hipEventCreateWithFlags(&ws->status_ev, hipEventDisableTiming));
-    ST_HIP(hipMemcpyAsync(ws->status_host, st->total, sizeof(uint64_t), hipMemcpyDeviceToHost,
-                          st->stream));
     ST_HIP(hipEventRecord(ws->status_ev, st->stream));
     ws->status_pending = true;
   }

@@ -66,6 +66,7 @@ struct Workspace {
   int64_t pair_cap = 0;              // learned capacity (0: not yet known)
   int64_t shape_vn = -1, shape_tiles = -1;  // shape of the render that learned it
   uint64_t *status_host = nullptr;   // pinned: [0] D, [1] overflow of the last render
+  uint64_t *status_dev = nullptr;    // the same memory as the device addresses it
   hipEvent_t status_ev = nullptr;    // recorded after that copy
   bool status_pending = false;
 };

@@ -240,8 +240,11 @@ inline int64_t raster_mask_words(int64_t pairs, int64_t tiles) {
 // n_tiles_dev (may be NULL): the tile count on the device (at most
 // n_tiles_total).  n_split (may be NULL): receives how many tiles, at the
 // front of the order, the forward splits into half-quadrant waves.
+// total_out (may be NULL; mapped pinned host memory): receives *total, the
+// render's pair count, without a copy command of its own.
 void launch_tile_order(const uint2 *ranges, int n_tiles_total, uint32_t *order, hipStream_t s,
-                       const int *n_tiles_dev = nullptr, uint32_t *n_split = nullptr);
+                       const int *n_tiles_dev = nullptr, uint32_t *n_split = nullptr,
+                       const uint64_t *total = nullptr, uint64_t *total_out = nullptr);
 // order (may be NULL: tile index order): from launch_tile_order.
 void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
                        const Record *rec, int n_tiles_total, int W, int H, int tiles_x,

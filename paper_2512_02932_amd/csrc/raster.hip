@@ -874,7 +874,10 @@ __device__ __forceinline__ uint64_t bucket_peers(int b, bool valid) {
 constexpr int kOrderLds = 32768;  // tiles whose buckets are staged in LDS first
 __global__ void __launch_bounds__(kOrderWaves * kWave)
 tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, const int *__restrict__ n_dev,
-                  uint32_t *__restrict__ order, uint32_t *__restrict__ n_split) {
+                  uint32_t *__restrict__ order, uint32_t *__restrict__ n_split,
+                  const uint64_t *__restrict__ total, uint64_t *__restrict__ total_out) {
+  if (total_out && threadIdx.x == 0)
+    __hip_atomic_store(total_out, *total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   if (n_dev) n_tiles = min(n_tiles, max(*n_dev, 0));
   // per (bucket, wave) counts, then bases, at entry(bucket)
   __shared__ uint32_t s_cnt[kOrderBuckets * kOrderWaves];
@@ -962,10 +965,11 @@ unsigned quad_blocks_full(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 
 }  // namespace
 
 void launch_tile_order(const uint2 *ranges, int n_tiles_total, uint32_t *order,
-                       hipStream_t s, const int *n_tiles_dev, uint32_t *n_split) {
+                       hipStream_t s, const int *n_tiles_dev, uint32_t *n_split,
+                       const uint64_t *total, uint64_t *total_out) {
   if (n_tiles_total <= 0) return;
   hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderWaves * kWave), 0, s, ranges,
-                     n_tiles_total, n_tiles_dev, order, n_split);
+                     n_tiles_total, n_tiles_dev, order, n_split, total, total_out);
 }
 
 void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
