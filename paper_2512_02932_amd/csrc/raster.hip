@@ -3,15 +3,18 @@
 // Work unit: one wave64 per 8x8 quadrant of a 16x16 tile, one pixel per lane,
 // launched as its own workgroup so that waves never wait for each other; in
 // the forward, tiles with a long pair list get two waves per quadrant, each
-// on half of it (8x4 pixels).  The waves of a tile are given block ids that the dispatcher
+// on half of it (8x4 pixels, every pixel on two lanes that take alternate
+// records of the list).  The waves of a tile are given block ids that the dispatcher
 // sends to the same XCD, so the tile's pair list and records are fetched
 // into one L2.  A wave walks its tile's depth-sorted pair list in chunks of 64: each
 // lane loads one pair's 80-byte record (the next chunk is prefetched into
 // registers while the current one is composited), tests the record's pixel
 // rectangle against the quadrant, and the hits are compacted in list order
 // into the wave's LDS slots (ballot + mbcnt).  The serial loop then visits
-// only those records, broadcast from LDS; every lane evaluates the same
-// record at each step, so the 2D/3D branch is wave-uniform.  Skipping a
+// only those records, broadcast from LDS.  In a whole-quadrant wave every
+// lane evaluates the same record at each step, so the 2D/3D branch is
+// wave-uniform; in a half-quadrant wave each 32-lane half evaluates its own
+// record and the branch is per lane.  Skipping a
 // record whose rectangle misses the quadrant changes nothing: the rectangle
 // bounds the support where alpha~ >= alpha_min.
 //
@@ -108,10 +111,12 @@ struct Quad {
 };
 
 // Tiles whose pair list is at least this long are walked by two waves per
-// quadrant, each on 8 x 4 pixels (lanes 32-63 idle) and culling against its
-// own half: the densest tiles set the kernel's critical path, and a half
-// meets fewer splats than the whole quadrant.
-constexpr uint32_t kSplitLen = 768;
+// quadrant, each on 8 x 4 pixels and culling against its own half.  Each
+// pixel is held by two lanes (l and l + 32), which evaluate two consecutive
+// records at once: a step reads two records from LDS and composites both,
+// where a whole-quadrant wave reads one.  The long lists set the kernel's
+// length, and a half meets fewer splats than the whole quadrant.
+constexpr uint32_t kSplitLen = 512;
 
 // Quadrant `quad` of the view-local tile r (row-major over tiles_x columns);
 // with split, its half `half` (rows 4 half .. 4 half + 3).
@@ -127,11 +132,12 @@ __device__ __forceinline__ Quad make_quad(int tile, int v, int r, int quad, int 
   q.qx = tx * kTile + (quad & 1) * 8;
   q.qy = ty * kTile + (quad >> 1) * 8 + (split ? 4 * half : 0);
   const int lane = threadIdx.x;
+  // a half quadrant's 32 pixels are held twice: by lane l and lane l + 32
   q.px = q.qx + (lane & 7);
-  q.py = q.qy + (lane >> 3);
+  q.py = q.qy + ((lane >> 3) & (q.rows - 1));
   q.fx = (float)q.px + 0.5f;
   q.fy = (float)q.py + 0.5f;
-  q.inside = q.px < W && q.py < H && (lane >> 3) < q.rows;
+  q.inside = q.px < W && q.py < H;
   return q;
 }
 
@@ -281,6 +287,47 @@ __device__ __forceinline__ bool is3d_of(const float4 &r4) {
   return (__builtin_amdgcn_readfirstlane(__float_as_int(r4.w)) >> 31) == 0;
 }
 
+// Exponent e (alpha~ = alpha_eff 2^-e) and depth value d of a record at this
+// lane's pixel, in the operation order of eval_pair.
+__device__ __forceinline__ void fwd_exponent(bool two, const Quad &q, const float4 &r0,
+                                             const float4 &r1, const float4 &r2,
+                                             const float4 &r3, float &e, float &d) {
+#pragma clang fp contract(off)
+  const float xr = q.fx - r0.x, yr = q.fy - r0.y;
+  if (two) {
+    const float U = __builtin_fmaf(r1.x, xr, __builtin_fmaf(r1.y, yr, r1.z));
+    const float V = __builtin_fmaf(r1.w, xr, __builtin_fmaf(r2.x, yr, r2.y));
+    const float Wh = __builtin_fmaf(r2.z, xr, __builtin_fmaf(r2.w, yr, r3.x));
+    const float rw = __builtin_amdgcn_rcpf(Wh);
+    const float uu = U * rw, vv = V * rw;
+    e = __builtin_fmaf(uu, uu, vv * vv);
+    d = rw;
+  } else {
+    const float dx = xr - r1.x, dy = yr - r1.y;
+    const float t = __builtin_fmaf(r1.w, dy, r1.z * dx);
+    const float u3 = r2.x * dy;
+    e = __builtin_fmaf(dx, t, u3 * dy);
+    d = r2.y;
+  }
+}
+
+// One pair of the compositing chain at a pixel: its contribution a (0 unless
+// raw >= thr, clamped at alpha_max), the stop before a pair that would take
+// T below t_min, and the pair's weight a T (0 at the stop).  thr is the
+// activity threshold: alpha_min while the pixel composites, +inf once it has
+// stopped, so one compare serves both.  raw >= thr is false for NaN, so the
+// integer min of the bit patterns (the float min for numbers >= +0) only
+// sees numbers >= +0.
+__device__ __forceinline__ void fwd_step(float raw, int amax_bits, float tmin, float &T,
+                                         float &thr, float &wg) {
+  const float a = raw >= thr ? __int_as_float(min(__float_as_int(raw), amax_bits)) : 0.0f;
+  const float Tn = T * (1.0f - a);
+  const bool stop = Tn < tmin;
+  wg = stop ? 0.0f : a * T;
+  thr = stop ? __builtin_inff() : thr;
+  T = stop ? T : Tn;
+}
+
 // Composites one quadrant: the wave's 64 pixels over the tile's pair range.
 // kAcct: also count blended pairs by type for the work accounting (wcount).
 template <bool kAcct>
@@ -329,67 +376,100 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
     if (c + 2 * kWave + lane < n) nid = vals[rg.x + c + 2 * kWave + lane];
     const int k_end = __popcll(m);
     uint64_t used = 0;  // compacted slots blended at one or more lanes
-    for (int k0 = 0; k0 < k_end; k0 += 2) {
-      if (__ballot(thr < 1.0f) == 0ull) break;
+    if (q.rows == 8) {
+      for (int k0 = 0; k0 < k_end; k0 += 2) {
+        if (__ballot(thr < 1.0f) == 0ull) break;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int k = k0 + j;
-        if (k >= k_end) break;
-        const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
-                     r4 = srec[4][k];
-        // r3.x is used by the 2D branch only; naming it here keeps r3 one
-        // 16-byte LDS read instead of pieces with an address of their own
-        asm volatile("" ::"v"(r3.x));
-        // the type is the same at every lane (one record): a scalar branch,
-        // so a 3D pair does not pay for the 2D form's reciprocal
-        const bool two = !is3d_of(r4);
-        float e, d;
-        {
-#pragma clang fp contract(off)
-          const float xr = q.fx - r0.x, yr = q.fy - r0.y;
-          if (two) {
-            const float U = __builtin_fmaf(r1.x, xr, __builtin_fmaf(r1.y, yr, r1.z));
-            const float V = __builtin_fmaf(r1.w, xr, __builtin_fmaf(r2.x, yr, r2.y));
-            const float Wh = __builtin_fmaf(r2.z, xr, __builtin_fmaf(r2.w, yr, r3.x));
-            const float rw = __builtin_amdgcn_rcpf(Wh);
-            const float uu = U * rw, vv = V * rw;
-            e = __builtin_fmaf(uu, uu, vv * vv);
-            d = rw;
-          } else {
-            const float dx = xr - r1.x, dy = yr - r1.y;
-            const float t = __builtin_fmaf(r1.w, dy, r1.z * dx);
-            const float u3 = r2.x * dy;
-            e = __builtin_fmaf(dx, t, u3 * dy);
-            d = r2.y;
+        for (int j = 0; j < 2; ++j) {
+          const int k = k0 + j;
+          if (k >= k_end) break;
+          const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
+                       r4 = srec[4][k];
+          // r3.x is used by the 2D branch only; naming it here keeps r3 one
+          // 16-byte LDS read instead of pieces with an address of their own
+          asm volatile("" ::"v"(r3.x));
+          // the type is the same at every lane (one record): a scalar branch,
+          // so a 3D pair does not pay for the 2D form's reciprocal
+          const bool two = !is3d_of(r4);
+          float e, d;
+          fwd_exponent(two, q, r0, r1, r2, r3, e, d);
+          const float raw = fabsf(r4.w) * exp2_neg(e);
+          // active: raw >= thr (false for NaN).  An inactive pair has a = 0,
+          // so only an active pair can take T below t_min (the stop); the
+          // weight is 0 unless the pair is blended, and the accumulations run
+          // unconditionally (record values are finite, see preprocess).
+          const float thr0 = thr;
+          float wg;
+          fwd_step(raw, amax_bits, tmin, T, thr, wg);
+          cr = __builtin_fmaf(wg, r3.y, cr);
+          cg = __builtin_fmaf(wg, r3.z, cg);
+          cb = __builtin_fmaf(wg, r3.w, cb);
+          dep = __builtin_fmaf(wg, raw >= thr0 ? d : 0.0f, dep);  // 1/W is inf where W = 0
+          nx = __builtin_fmaf(wg, r4.x, nx);
+          ny = __builtin_fmaf(wg, r4.y, ny);
+          nz = __builtin_fmaf(wg, r4.z, nz);
+          const bool bl = wg > 0.0f;
+          used |= (__ballot(bl) != 0ull) ? (1ull << k) : 0ull;
+          cnt += bl ? 1u : 0u;
+          lastk = bl ? k : lastk;
+          if constexpr (kAcct) {
+            wc += bl ? (two ? (1u << 15) : 1u) : 0u;
+            wc |= thr0 < 1.0f && !(thr < 1.0f) ? (0x80000000u | (two ? 0x40000000u : 0u)) : 0u;
           }
         }
-        const float raw = fabsf(r4.w) * exp2_neg(e);
-        // active: raw >= thr (false for NaN).  An inactive pair has a = 0,
-        // so only an active pair can take T below t_min (the stop); the
-        // weight is 0 unless the pair is blended, and the accumulations run
-        // unconditionally (record values are finite, see preprocess).
-        // raw >= thr is false for NaN, so the min only sees numbers >= +0
-        const float a = raw >= thr ? __int_as_float(min(__float_as_int(raw), amax_bits)) : 0.0f;
-        const float Tn = T * (1.0f - a);
-        const bool stop = Tn < tmin;
-        const float wg = stop ? 0.0f : a * T;
+      }
+    } else {
+      // Half quadrant: lane l and lane l + 32 hold the same pixel.  Each step
+      // the lower half evaluates record k0 and the upper half record k0 + 1
+      // (the two exponents in parallel); both halves then run the same
+      // transmittance chain over the two records in list order, so T, the
+      // activity and stop decisions are those of the one-record walk, and
+      // each half accumulates its own record's weighted values.  The halves'
+      // sums are added at the end.
+      const int hi = lane >> 5;
+      for (int k0 = 0; k0 < k_end; k0 += 2) {
+        if (__ballot(thr < 1.0f) == 0ull) break;
+        const bool has = k0 + hi < k_end;
+        const int k = has ? k0 + hi : k0;
+        const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
+                     r4 = srec[4][k];
+        asm volatile("" ::"v"(r3.x));
+        // the halves' records may differ in type: a per-lane branch
+        const bool two = (__float_as_uint(r4.w) >> 31) != 0u;
+        float e, d;
+        fwd_exponent(two, q, r0, r1, r2, r3, e, d);
+        // a missing second record has raw 0, below any alpha_min
+        const float raw = has ? fabsf(r4.w) * exp2_neg(e) : 0.0f;
+        const auto rr = __builtin_amdgcn_permlane32_swap(__float_as_uint(raw),
+                                                         __float_as_uint(raw), false, false);
+        const float raw0 = __uint_as_float(rr[0]), raw1 = __uint_as_float(rr[1]);
+        const float thr0 = thr;
+        float wg0, wg1;
+        fwd_step(raw0, amax_bits, tmin, T, thr, wg0);
+        const float thr1 = thr;
+        fwd_step(raw1, amax_bits, tmin, T, thr, wg1);
+        const float wg = hi ? wg1 : wg0;
+        const bool on = raw >= (hi ? thr1 : thr0);
         cr = __builtin_fmaf(wg, r3.y, cr);
         cg = __builtin_fmaf(wg, r3.z, cg);
         cb = __builtin_fmaf(wg, r3.w, cb);
-        dep = __builtin_fmaf(wg, raw >= thr ? d : 0.0f, dep);  // 1/W is inf where W = 0
+        dep = __builtin_fmaf(wg, on ? d : 0.0f, dep);  // 1/W is inf where W = 0
         nx = __builtin_fmaf(wg, r4.x, nx);
         ny = __builtin_fmaf(wg, r4.y, ny);
         nz = __builtin_fmaf(wg, r4.z, nz);
-        const bool bl = wg > 0.0f;
-        used |= (__ballot(bl) != 0ull) ? (1ull << k) : 0ull;
-        cnt += bl ? 1u : 0u;
-        lastk = bl ? k : lastk;
+        const bool bl0 = wg0 > 0.0f, bl1 = wg1 > 0.0f;
+        used |= (__ballot(bl0) != 0ull) ? (1ull << k0) : 0ull;
+        used |= (__ballot(bl1) != 0ull) ? (2ull << k0) : 0ull;
+        cnt += (bl0 ? 1u : 0u) + (bl1 ? 1u : 0u);
+        lastk = bl1 ? k0 + 1 : bl0 ? k0 : lastk;
         if constexpr (kAcct) {
-          wc += bl ? (two ? (1u << 15) : 1u) : 0u;
-          wc |= stop ? (0x80000000u | (two ? 0x40000000u : 0u)) : 0u;
+          const uint64_t tb = __ballot(two);
+          const bool two0 = tb & 1ull, two1 = (tb >> 32) & 1ull;
+          wc += bl0 ? (two0 ? (1u << 15) : 1u) : 0u;
+          wc |= thr0 < 1.0f && !(thr1 < 1.0f) ? (0x80000000u | (two0 ? 0x40000000u : 0u)) : 0u;
+          wc += bl1 ? (two1 ? (1u << 15) : 1u) : 0u;
+          wc |= thr1 < 1.0f && !(thr < 1.0f) ? (0x80000000u | (two1 ? 0x40000000u : 0u)) : 0u;
         }
-        thr = stop ? __builtin_inff() : thr;
-        T = stop ? T : Tn;
       }
     }
     if (lastk >= 0) last = spos[lastk] + 1u;
@@ -398,6 +478,21 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
       const uint64_t pm = __ballot(hit && ((used >> lane_rank(m)) & 1ull));
       if (lane == 0) wm[c >> 6] = pm;
     }
+  }
+  if (q.rows != 8) {  // half quadrant: add the upper half's sums to the lower's
+    auto fold = [](float &x) {
+      const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x),
+                                                      false, false);
+      x = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    };
+    fold(cr);
+    fold(cg);
+    fold(cb);
+    fold(dep);
+    fold(nx);
+    fold(ny);
+    fold(nz);
+    if (lane >= 32) return;
   }
   if (!q.inside) return;
   const int64_t hw = (int64_t)H * W;
