@@ -371,10 +371,13 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
       srec[4][slot] = q4;
       spos[slot] = (uint32_t)(c + lane);
     }
+    const int k_end = __popcll(m);
+    // a half-quadrant wave takes records in pairs: an odd count gets a zero
+    // record (raw 0, never active) in the free slot after the last
+    if (q.rows != 8 && (k_end & 1) && lane < 5) srec[lane][k_end] = make_float4(0, 0, 0, 0);
     __syncthreads();
     if (c + kWave + lane < n) HGS_FETCH(rec, nid, q0, q1, q2, q3, q4);
     if (c + 2 * kWave + lane < n) nid = vals[rg.x + c + 2 * kWave + lane];
-    const int k_end = __popcll(m);
     uint64_t used = 0;  // compacted slots blended at one or more lanes
     if (q.rows == 8) {
       for (int k0 = 0; k0 < k_end; k0 += 2) {
@@ -426,11 +429,14 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
       // activity and stop decisions are those of the one-record walk, and
       // each half accumulates its own record's weighted values.  The halves'
       // sums are added at the end.
+      // Each half also keeps its own count of blended records and its own
+      // last blended slot; the two are combined at the chunk's end (last)
+      // and at the end (count).
       const int hi = lane >> 5;
+      const bool upper = lane >= 32;
       for (int k0 = 0; k0 < k_end; k0 += 2) {
         if (__ballot(thr < 1.0f) == 0ull) break;
-        const bool has = k0 + hi < k_end;
-        const int k = has ? k0 + hi : k0;
+        const int k = k0 + hi;
         const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
                      r4 = srec[4][k];
         asm volatile("" ::"v"(r3.x));
@@ -438,8 +444,7 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
         const bool two = (__float_as_uint(r4.w) >> 31) != 0u;
         float e, d;
         fwd_exponent(two, q, r0, r1, r2, r3, e, d);
-        // a missing second record has raw 0, below any alpha_min
-        const float raw = has ? fabsf(r4.w) * exp2_neg(e) : 0.0f;
+        const float raw = fabsf(r4.w) * exp2_neg(e);
         const auto rr = __builtin_amdgcn_permlane32_swap(__float_as_uint(raw),
                                                          __float_as_uint(raw), false, false);
         const float raw0 = __uint_as_float(rr[0]), raw1 = __uint_as_float(rr[1]);
@@ -448,21 +453,26 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
         fwd_step(raw0, amax_bits, tmin, T, thr, wg0);
         const float thr1 = thr;
         fwd_step(raw1, amax_bits, tmin, T, thr, wg1);
-        const float wg = hi ? wg1 : wg0;
-        const bool on = raw >= (hi ? thr1 : thr0);
+        // this half's record; a blended record (weight > 0) is active, so
+        // its d is finite (1/W is inf where W = 0), and a record that is not
+        // blended adds 0 whichever d it gets
+        const float wg = upper ? wg1 : wg0;
+        const bool bl = wg > 0.0f;
         cr = __builtin_fmaf(wg, r3.y, cr);
         cg = __builtin_fmaf(wg, r3.z, cg);
         cb = __builtin_fmaf(wg, r3.w, cb);
-        dep = __builtin_fmaf(wg, on ? d : 0.0f, dep);  // 1/W is inf where W = 0
+        dep = __builtin_fmaf(wg, bl ? d : 0.0f, dep);
         nx = __builtin_fmaf(wg, r4.x, nx);
         ny = __builtin_fmaf(wg, r4.y, ny);
         nz = __builtin_fmaf(wg, r4.z, nz);
-        const bool bl0 = wg0 > 0.0f, bl1 = wg1 > 0.0f;
-        used |= (__ballot(bl0) != 0ull) ? (1ull << k0) : 0ull;
-        used |= (__ballot(bl1) != 0ull) ? (2ull << k0) : 0ull;
-        cnt += (bl0 ? 1u : 0u) + (bl1 ? 1u : 0u);
-        lastk = bl1 ? k0 + 1 : bl0 ? k0 : lastk;
+        const uint64_t bm = __ballot(bl);  // bits 0-31: record k0, 32-63: k0 + 1
+        uint32_t bm_hi = (uint32_t)(bm >> 32);
+        asm("" : "+s"(bm_hi));  // a 32-bit scalar compare, not a 64-bit vector one
+        used |= ((uint32_t)bm != 0u ? (1ull << k0) : 0ull) | (bm_hi != 0u ? (2ull << k0) : 0ull);
+        cnt += bl ? 1u : 0u;
+        lastk = bl ? k : lastk;
         if constexpr (kAcct) {
+          const bool bl0 = wg0 > 0.0f, bl1 = wg1 > 0.0f;
           const uint64_t tb = __ballot(two);
           const bool two0 = tb & 1ull, two1 = (tb >> 32) & 1ull;
           wc += bl0 ? (two0 ? (1u << 15) : 1u) : 0u;
@@ -471,6 +481,8 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
           wc |= thr1 < 1.0f && !(thr < 1.0f) ? (0x80000000u | (two1 ? 0x40000000u : 0u)) : 0u;
         }
       }
+      // the later of the two halves' last blended slots
+      lastk = max(lastk, (int)__builtin_amdgcn_permlane32_swap(lastk, lastk, false, false)[upper ? 0 : 1]);
     }
     if (lastk >= 0) last = spos[lastk] + 1u;
     lastk = -1;
@@ -492,6 +504,7 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
     fold(nx);
     fold(ny);
     fold(nz);
+    cnt += __builtin_amdgcn_permlane32_swap(cnt, cnt, false, false)[1];
     if (lane >= 32) return;
   }
   if (!q.inside) return;
@@ -516,9 +529,11 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
   if (kAcct && out.wcount) out.wcount[o1] = wc;
 }
 
-// Views of one size: the block id picks the tile and quadrant (quad_of).
+// Views of one size: the block id picks the tile and quadrant (quad_of).  At
+// most 80 VGPRs: six waves per SIMD (the half-quadrant walk takes 88 when
+// left alone, which allows five).
 template <bool kAcct>
-__global__ void __launch_bounds__(kWave)
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6)))
 raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ order,
                   const uint32_t *__restrict__ vals, const Record *__restrict__ rec, int n_tiles,
                   int W, int H, int tiles_x, int tiles_per_view, DevOpts opt, RasterOut out,
