@@ -116,7 +116,7 @@ struct Quad {
 // records at once: a step reads two records from LDS and composites both,
 // where a whole-quadrant wave reads one.  The long lists set the kernel's
 // length, and a half meets fewer splats than the whole quadrant.
-constexpr uint32_t kSplitLen = 512;
+constexpr uint32_t kSplitLen = 0;
 
 // Quadrant `quad` of the view-local tile r (row-major over tiles_x columns);
 // with split, its half `half` (rows 4 half .. 4 half + 3).
@@ -659,6 +659,37 @@ __device__ __forceinline__ float wave_reduce_scatter16(const float (&g)[16], int
   return x;
 }
 
+// Sums each of the 16 per-lane values over the lanes of each 32-lane half of
+// the wave separately (the halves hold different pairs).  Lane l returns its
+// half's total of value 8 b4 + 4 b3 + 2 b2 + b1 (b_i = bit i of l); lanes l
+// and l ^ 1 hold the same total.  Pairings used: bit 4 (swap16), l ^ 15,
+// l ^ 7, l ^ 2, l ^ 1 -- together they span the 32 lanes of a half.
+__device__ __forceinline__ float half_reduce_scatter16(const float (&g)[16], int lane) {
+  float t[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) t[k] = swap16_sum(g[k], g[k + 8]);
+  const bool b3 = lane & 8;
+  float u[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float keep = b3 ? t[k + 4] : t[k];
+    const float send = b3 ? t[k] : t[k + 4];
+    u[k] = keep + dpp<kRowMirror>(send);
+  }
+  const bool b2 = lane & 4;
+  float w[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float keep = b2 ? u[k + 2] : u[k];
+    const float send = b2 ? u[k] : u[k + 2];
+    w[k] = keep + dpp<kRowHalfMirror>(send);
+  }
+  const bool b1 = lane & 2;
+  float x = (b1 ? w[1] : w[0]) + dpp<kQuadXor2>(b1 ? w[0] : w[1]);
+  x += dpp<kQuadXor1>(x);
+  return x;
+}
+
 // Record-geometry slots 0-8 of a pair from dL/de (ge) and, for a 2D pair,
 // the depth weight gdz = dL/d depth (3D: slot 5 is the depth slot, written
 // by the caller).  The slots are formed in scalars and stored once with
@@ -733,6 +764,184 @@ struct PackDst {
   int plane, slot;
 };
 
+// Backward of one half quadrant (8 x 4 pixels) for one cotangent set.  Lane
+// l and lane l + 32 hold the same pixel.  The wave walks the pairs its
+// forward wave blended (its blend mask) in reverse list order, two per
+// step: the upper half of the wave evaluates the later one (compacted slot
+// k), the lower half the earlier (slot k - 1).  One swap gives every lane
+// both pairs' alpha~ (0 where the pair is not active) and per-pair scalar
+// f; both halves then run the transmittance recovery and the suffix
+// recurrence over the two pairs in that order, so T, S and dL/dalpha~ at
+// each pixel are those of the one-pair walk bit for bit.  Each half forms
+// its own pair's 16 gradient terms, one 32-lane reduce-scatter sums both
+// pairs' terms, and one atomic instruction adds both totals.
+__device__ __forceinline__ void raster_bwd_half(const uint2 *ranges, const uint32_t *order,
+                                                const uint32_t *vals, const Record *rec,
+                                                int n_tiles, int W, int H, int tiles_x,
+                                                int tiles_per_view, const DevOpts &opt,
+                                                const float *T_final, const uint32_t *last_in,
+                                                const RasterGradIn &gin, float *accum,
+                                                const uint64_t *bmask) {
+  __shared__ float4 srec[5][kWave];
+  __shared__ uint32_t sid[kWave];
+  __shared__ uint32_t spos[kWave];
+  Quad q;
+  uint2 rg;
+  if (!quad_of(ranges, order, n_tiles, W, H, tiles_x, tiles_per_view, q, rg)) return;
+  const int lane = threadIdx.x;
+  const bool upper = lane >= 32;
+
+  float T = 1.0f;
+  uint32_t L = 0;
+  float Gr = 0, Gg = 0, Gb = 0, Ga = 0, Gd = 0, Gnx = 0, Gny = 0, Gnz = 0;
+  if (q.inside) {
+    const int64_t hw = (int64_t)H * W;
+    const int64_t pix = (int64_t)q.py * W + q.px;
+    const int64_t o1 = (int64_t)q.v * hw + pix;
+    const int64_t o3 = (int64_t)q.v * 3 * hw + pix;
+    T = T_final[o1];
+    L = last_in[o1];
+    if (gin.rgb) {
+      Gr = gin.rgb[o3];
+      Gg = gin.rgb[o3 + hw];
+      Gb = gin.rgb[o3 + 2 * hw];
+    }
+    if (gin.alpha) Ga = gin.alpha[o1];
+    if (gin.depth) Gd = gin.depth[o1];
+    if (gin.normal) {
+      Gnx = gin.normal[o3];
+      Gny = gin.normal[o3 + hw];
+      Gnz = gin.normal[o3 + 2 * hw];
+    }
+  }
+  // suffix value beyond the last blended pair: background and alpha terms
+  float S = Gr * opt.bg[0] + Gg * opt.bg[1] + Gb * opt.bg[2] - Ga;
+
+  const int amax_bits = __float_as_int(opt.alpha_max);
+  uint32_t wmax = L;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, d));
+  const int n = min((int)__builtin_amdgcn_readfirstlane(wmax), (int)(rg.y - rg.x));
+  if (n <= 0) return;
+  prio_for_list(n);
+  const int vidx = ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
+                   ((lane >> 1) & 1);
+  const uint64_t *wm = quad_mask_words(const_cast<uint64_t *>(bmask), rg, q.tile, q.sub);
+
+  // chunks of 64 list positions in reverse, the first the ragged one; only
+  // the positions this half's forward wave blended.  Pipeline: records of
+  // chunk c in q0..q4 (entry id), entries of chunk c - 64 in nid.
+  float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0, q4 = q0;
+  uint32_t id = 0, nid = 0;
+  int c = (n - 1) & ~(kWave - 1);
+  bool hit = (c + lane < n) && ((wm[c >> 6] >> lane) & 1ull);
+  if (hit) {
+    id = vals[rg.x + c + lane];
+    HGS_FETCH(rec, id, q0, q1, q2, q3, q4);
+  }
+  bool hit_n = c > 0 && ((wm[(c >> 6) - 1] >> lane) & 1ull);
+  if (hit_n) nid = vals[rg.x + c - kWave + lane];
+  for (; c >= 0; c -= kWave) {
+    const uint64_t m = __ballot(hit);
+    __syncthreads();  // the previous chunk's slots have been read
+    if (hit) {
+      const int slot = lane_rank(m);
+      srec[0][slot] = q0;
+      srec[1][slot] = q1;
+      srec[2][slot] = q2;
+      srec[3][slot] = q3;
+      srec[4][slot] = q4;
+      sid[slot] = id;
+      spos[slot] = (uint32_t)(c + lane);
+    }
+    // pairs are taken two at a time: an odd count gets a zero record
+    // (alpha~ 0, never active) in the free slot after the last
+    const int kk = __popcll(m);
+    if (kk & 1) {
+      if (lane < 5) srec[lane][kk] = make_float4(0, 0, 0, 0);
+      if (lane == 5) sid[kk] = 0u;
+      if (lane == 6) spos[kk] = 0u;
+    }
+    __syncthreads();
+    if (c > 0) {  // earlier chunks: every position is below n
+      hit = hit_n;
+      id = nid;
+      if (hit) HGS_FETCH(rec, id, q0, q1, q2, q3, q4);
+      hit_n = c > kWave && ((wm[(c >> 6) - 2] >> lane) & 1ull);
+      if (hit_n) nid = vals[rg.x + c - 2 * kWave + lane];
+    }
+    for (int k = kk + (kk & 1) - 1; k > 0; k -= 2) {
+      const int ks = upper ? k : k - 1;
+      const float4 r0 = srec[0][ks], r1 = srec[1][ks], r2 = srec[2][ks], r3 = srec[3][ks],
+                   r4 = srec[4][ks];
+      const uint32_t pos = spos[ks], sk = sid[ks];
+      asm volatile("" ::"v"(r2.z), "v"(r2.w), "v"(r3.x));
+      // the halves' pairs may differ in type: a per-lane branch
+      const bool is3d = (__float_as_uint(r4.w) >> 31) == 0u;
+      const PairEval p = eval_pair(is3d, q.fx, q.fy, r0, r1, r2, r3);
+      const float G = exp2_neg(p.e);
+      const float raw = fabsf(r4.w) * G;
+      const bool act = (pos < L) && (raw >= opt.alpha_min);
+      if (__ballot(act) == 0ull) continue;
+      // an inactive lane's weights are 0, and a 2D pair's intersection, which
+      // can be non-finite where the pair does not contribute, is replaced
+      // there by finite values, so its gradient terms are exact zeros
+      PairEval ps = p;
+      if (!is3d) {
+        ps.e = act ? p.e : 0.0f;
+        ps.rw = act ? p.rw : 0.0f;
+        ps.depth = act ? p.depth : 0.0f;
+      }
+      const float f = Gr * r3.y + Gg * r3.z + Gb * r3.w + Gd * ps.depth + Gnx * r4.x +
+                      Gny * r4.y + Gnz * r4.z;
+      // both pairs at every lane of the pixel: [0] the lower half's (slot
+      // k - 1), [1] the upper half's (slot k); alpha~ is 0 where the pair is
+      // not active (active implies alpha~ >= alpha_min > 0)
+      const float rawe = act ? raw : 0.0f;
+      const auto rs = __builtin_amdgcn_permlane32_swap(__float_as_uint(rawe),
+                                                       __float_as_uint(rawe), false, false);
+      const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(f), __float_as_uint(f),
+                                                       false, false);
+      // the later pair first (as the forward forms alpha~: the integer min of
+      // the bit patterns, the float min for numbers >= +0)
+      const float raw_h = __uint_as_float(rs[1]), raw_l = __uint_as_float(rs[0]);
+      const bool act_h = raw_h > 0.0f, act_l = raw_l > 0.0f;
+      const float a_h = __int_as_float(min(__float_as_int(raw_h), amax_bits));
+      const float Ti_h = T * __builtin_amdgcn_rcpf(1.0f - a_h);
+      const float dfa_h = __uint_as_float(fs[1]) - S;
+      const float ga_h = act_h ? Ti_h * dfa_h : 0.0f;
+      const float S1 = act_h ? __builtin_fmaf(a_h, dfa_h, S) : S;
+      const float T1 = act_h ? Ti_h : T;
+      const float a_l = __int_as_float(min(__float_as_int(raw_l), amax_bits));
+      const float Ti_l = T1 * __builtin_amdgcn_rcpf(1.0f - a_l);
+      const float dfa_l = __uint_as_float(fs[0]) - S1;
+      const float ga_l = act_l ? Ti_l * dfa_l : 0.0f;
+      S = act_l ? __builtin_fmaf(a_l, dfa_l, S1) : S1;
+      T = act_l ? Ti_l : T1;
+      // this half's pair
+      const float a = upper ? a_h : a_l;
+      const float Ti = upper ? Ti_h : Ti_l;
+      const float ga = upper ? ga_h : ga_l;
+      const bool live = act && !(raw > opt.alpha_max);  // not clamped: the exponent's path
+      const float wg = act ? a * Ti : 0.0f;
+      float g[16];
+      g[10] = wg * Gr;
+      g[11] = wg * Gg;
+      g[12] = wg * Gb;
+      g[13] = wg * Gnx;
+      g[14] = wg * Gny;
+      g[15] = wg * Gnz;
+      const float ge = live ? -ga * a * kLn2 : 0.0f;  // dL/de
+      g[9] = live ? ga * G : 0.0f;                    // dL/d alpha_eff
+      g[5] = wg * Gd;                                  // 3D: depth slot
+      pair_geometry_grads(g, ps, is3d, ge, wg * Gd, r1, r2);
+      const float tot = half_reduce_scatter16(g, lane);
+      if ((lane & 1) == 0 && tot != 0.0f)
+        unsafeAtomicAdd(accum + (size_t)sk * kGradSlots + vidx, tot);
+    }
+  }
+}
+
 // NS = 1: one cotangent set.  NS = 3: the main set plus two RGB-only sets
 // (rgb2[0], rgb2[1]) in the same reverse traversal -- one record fetch,
 // one geometry and transmittance recomputation per pair -- accumulated into
@@ -745,6 +954,10 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
                   int tiles_per_view, DevOpts opt, const float *__restrict__ T_final,
                   const uint32_t *__restrict__ last_in, RasterGradIn gin, RgbSets rgb2,
                   float *__restrict__ accum, int64_t plane, const uint64_t *__restrict__ bmask) {
+  if constexpr (NS == 1) {
+    raster_bwd_half(ranges, order, vals, rec, n_tiles, W, H, tiles_x, tiles_per_view, opt,
+                    T_final, last_in, gin, accum, bmask);
+  } else {
   __shared__ float4 srec[5][kWave];
   __shared__ uint32_t sid[kWave];
   __shared__ uint32_t spos[kWave];
@@ -944,6 +1157,7 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
       T = act ? Ti : T;
     }
   }
+  }
 }
 
 // Tile order of the raster launches: tiles by pair-list length, longest
@@ -1112,7 +1326,7 @@ void launch_raster_bwd(const uint2 *ranges, const uint32_t *order, const uint32_
                        const uint32_t *last, const uint64_t *bmask, RasterGradIn g,
                        float *accum, hipStream_t s) {
   if (n_tiles_total == 0) return;
-  hipLaunchKernelGGL(raster_bwd_kernel<1>, dim3(quad_blocks_full(n_tiles_total)), dim3(kWave), 0, s,
+  hipLaunchKernelGGL(raster_bwd_kernel<1>, dim3(quad_blocks(n_tiles_total)), dim3(kWave), 0, s,
                      ranges, order, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
                      T_final, last, g, RgbSets{}, accum, (int64_t)0, bmask);
 }
