@@ -52,6 +52,8 @@ struct hgs_state {
   uint32_t *vals = nullptr;  // instance id (view * N + splat) of each sorted pair
   uint2 *ranges = nullptr;
   uint32_t *order = nullptr;  // tiles by pair-list length, longest first
+  uint2 *vis = nullptr;       // per tile: the forward's largest blended count per wave
+  uint32_t *order_bwd = nullptr;  // tiles by that count, largest first (the backward's)
   float *T_final = nullptr;
   uint32_t *last = nullptr, *n_contrib = nullptr, *wcount = nullptr;
   int64_t D = -1;        // pairs in the sorted list, min(D_total, cap), once read back
@@ -574,6 +576,8 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ST_HIP(dalloc(st, &scan_tmp, scan_tmp_bytes(VN)));
   ST_HIP(dalloc_t(st, &st->ranges, (size_t)n_tiles));
   ST_HIP(dalloc_t(st, &st->order, (size_t)n_tiles));
+  ST_HIP(dalloc_t(st, &st->vis, (size_t)n_tiles));
+  ST_HIP(dalloc_t(st, &st->order_bwd, (size_t)n_tiles));
   ST_HIP(dalloc_t(st, &st->T_final, (size_t)P));
   ST_HIP(dalloc_t(st, &st->last, (size_t)P));
   ST_HIP(dalloc_t(st, &st->n_contrib, (size_t)P));
@@ -697,13 +701,14 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
     StageTimer t(ctx, HGS_STAGE_RANGES, st->stream);
     launch_ranges(st->keys, cap, st->ranges, st->stream, st->total);
     launch_tile_order(st->ranges, (int)n_tiles, st->order, st->stream, nullptr, nullptr,
-                      st->total, status_dst);
+                      st->total, status_dst, st->vis);
   }
 
   ro.T_final = st->T_final;
   ro.last = st->last;
   ro.n_contrib = st->n_contrib;
   ro.wcount = ctx->profile ? st->wcount : nullptr;  // work accounting while profiling
+  ro.vis = st->vis;
   st->has_wcount = ctx->profile;
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_FWD, st->stream);
@@ -771,7 +776,9 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_image
   }
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_BWD, s);
-    launch_raster_bwd(st->ranges, st->order, st->vals, st->rec, st->n_tiles, st->W, st->H,
+    // the backward's tiles by their forward waves' blended counts, largest first
+    launch_tile_order(st->vis, (int)st->n_tiles, st->order_bwd, s);
+    launch_raster_bwd(st->ranges, st->order_bwd, st->vals, st->rec, st->n_tiles, st->W, st->H,
                       st->tiles_x,
                       st->tiles_per_view, st->opt, st->T_final, st->last, st->bmask, gi, accum,
                       s);
@@ -859,7 +866,9 @@ hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *st, const hgs_grad_i
   x.rgb[1] = grad_high_rgb;
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_BWD, s);
-    launch_raster_bwd_sets(st->ranges, st->order, st->vals, st->rec, st->n_tiles, st->W, st->H,
+    launch_tile_order(st->vis, (int)st->n_tiles, st->order_bwd, s);
+    launch_raster_bwd_sets(st->ranges, st->order_bwd, st->vals, st->rec, st->n_tiles, st->W,
+                           st->H,
                            st->tiles_x,
                            st->tiles_per_view, st->opt, st->T_final, st->last, st->bmask, gi, x,
                            accum, plane, s);

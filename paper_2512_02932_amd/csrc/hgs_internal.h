@@ -229,6 +229,11 @@ struct RasterOut {
   // per pixel: bits 0-14 blended 3D pairs, 15-29 blended 2D pairs, bit 30 the
   // stopping pair was 2D, bit 31 the pixel stopped (work accounting)
   uint32_t *wcount;
+  // per tile (may be NULL; zero at launch): .y receives 8 times the largest
+  // number of list positions one of the tile's forward waves blended, the
+  // backward's work per wave, laid out as ranges so that launch_tile_order
+  // can order the backward's tiles by it
+  uint2 *vis;
 };
 // bmask (may be NULL): receives the blend masks the backward walks,
 // raster_mask_words(D capacity, tiles) 64-bit words.
@@ -241,10 +246,12 @@ inline int64_t raster_mask_words(int64_t pairs, int64_t tiles) {
 // n_tiles_total).  n_split (may be NULL): receives how many tiles, at the
 // front of the order, the forward splits into half-quadrant waves.
 // total_out (may be NULL; mapped pinned host memory): receives *total, the
-// render's pair count, without a copy command of its own.
+// render's pair count, without a copy command of its own.  clear (may be
+// NULL): n_tiles entries set to zero (a RasterOut::vis for the forward).
 void launch_tile_order(const uint2 *ranges, int n_tiles_total, uint32_t *order, hipStream_t s,
                        const int *n_tiles_dev = nullptr, uint32_t *n_split = nullptr,
-                       const uint64_t *total = nullptr, uint64_t *total_out = nullptr);
+                       const uint64_t *total = nullptr, uint64_t *total_out = nullptr,
+                       uint2 *clear = nullptr);
 // order (may be NULL: tile index order): from launch_tile_order.
 void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
                        const Record *rec, int n_tiles_total, int W, int H, int tiles_x,

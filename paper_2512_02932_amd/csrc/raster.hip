@@ -199,6 +199,7 @@ __device__ __forceinline__ uint64_t *quad_mask_words(uint64_t *bmask, uint2 rg, 
 struct ViewOut {
   float *rgb, *alpha, *depth, *normal, *T_final;
   uint32_t *last, *n_contrib, *wcount;
+  uint2 *vis;  // per tile, not per view (see RasterOut)
 };
 
 // 2D record: U, V, W (rows of the inverse map, affine in the local pixel
@@ -349,6 +350,7 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
   const int amax_bits = __float_as_int(opt.alpha_max);
   const float tmin = opt.t_min, inv_amin = opt.inv_amin;
   int lastk = -1;  // compacted slot of this lane's last blended pair in the chunk
+  uint32_t nvis = 0;  // positions blended at one or more of the wave's pixels
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, nx = 0.0f, ny = 0.0f, nz = 0.0f;
   uint32_t cnt = 0, last = 0, wc = 0;
 
@@ -486,11 +488,13 @@ __device__ __forceinline__ void raster_fwd_quad(const Quad &q, uint2 rg, const u
     }
     if (lastk >= 0) last = spos[lastk] + 1u;
     lastk = -1;
-    if (wm) {  // the chunk's positions blended in this quadrant
+    if (wm || out.vis) {  // the chunk's positions blended in this quadrant
       const uint64_t pm = __ballot(hit && ((used >> lane_rank(m)) & 1ull));
-      if (lane == 0) wm[c >> 6] = pm;
+      if (wm && lane == 0) wm[c >> 6] = pm;
+      nvis += (uint32_t)__popcll(pm);
     }
   }
+  if (out.vis && lane == 0) atomicMax(&out.vis[q.tile].y, 8u * nvis);
   if (q.rows != 8) {  // half quadrant: add the upper half's sums to the lower's
     auto fold = [](float &x) {
       const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x),
@@ -553,6 +557,7 @@ raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
   vo.last = out.last ? out.last + v * hw : nullptr;
   vo.n_contrib = out.n_contrib ? out.n_contrib + v * hw : nullptr;
   vo.wcount = out.wcount ? out.wcount + v * hw : nullptr;
+  vo.vis = out.vis;
   raster_fwd_quad<kAcct>(q, rg, vals, rec, W, H, opt, vo,
                          bmask ? quad_mask_words(bmask, rg, q.tile, q.sub) : nullptr, srec,
                          spos);
@@ -1199,7 +1204,8 @@ constexpr int kOrderLds = 32768;  // tiles whose buckets are staged in LDS first
 __global__ void __launch_bounds__(kOrderWaves * kWave)
 tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, const int *__restrict__ n_dev,
                   uint32_t *__restrict__ order, uint32_t *__restrict__ n_split,
-                  const uint64_t *__restrict__ total, uint64_t *__restrict__ total_out) {
+                  const uint64_t *__restrict__ total, uint64_t *__restrict__ total_out,
+                  uint2 *__restrict__ clear) {
   if (total_out && threadIdx.x == 0)
     __hip_atomic_store(total_out, *total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   if (n_dev) n_tiles = min(n_tiles, max(*n_dev, 0));
@@ -1209,6 +1215,8 @@ tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, const int *__re
   constexpr int kT = kOrderWaves * kWave;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   for (int e = threadIdx.x; e < kOrderBuckets * kOrderWaves; e += kT) s_cnt[e] = 0;
+  if (clear)
+    for (int t = threadIdx.x; t < n_tiles; t += kT) clear[t] = make_uint2(0u, 0u);
   // every tile's bucket into LDS, eight loads in flight per thread (the
   // sweeps below then wait on no memory)
   const bool staged = n_tiles <= kOrderLds;
@@ -1290,10 +1298,10 @@ unsigned quad_blocks_full(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 
 
 void launch_tile_order(const uint2 *ranges, int n_tiles_total, uint32_t *order,
                        hipStream_t s, const int *n_tiles_dev, uint32_t *n_split,
-                       const uint64_t *total, uint64_t *total_out) {
+                       const uint64_t *total, uint64_t *total_out, uint2 *clear) {
   if (n_tiles_total <= 0) return;
   hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderWaves * kWave), 0, s, ranges,
-                     n_tiles_total, n_tiles_dev, order, n_split, total, total_out);
+                     n_tiles_total, n_tiles_dev, order, n_split, total, total_out, clear);
 }
 
 void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
