@@ -1,22 +1,22 @@
 // Per-tile compositing (forward) and its reverse pass (backward), gfx950.
 //
-// Work unit: one wave64 per 8x8 quadrant of a 16x16 tile, one pixel per lane,
-// launched as its own workgroup so that waves never wait for each other; in
-// the forward, tiles with a long pair list get two waves per quadrant, each
-// on half of it (8x4 pixels, every pixel on two lanes that take alternate
-// records of the list).  The waves of a tile are given block ids that the dispatcher
-// sends to the same XCD, so the tile's pair list and records are fetched
-// into one L2.  A wave walks its tile's depth-sorted pair list in chunks of 64: each
-// lane loads one pair's 80-byte record (the next chunk is prefetched into
-// registers while the current one is composited), tests the record's pixel
-// rectangle against the quadrant, and the hits are compacted in list order
-// into the wave's LDS slots (ballot + mbcnt).  The serial loop then visits
-// only those records, broadcast from LDS.  In a whole-quadrant wave every
-// lane evaluates the same record at each step, so the 2D/3D branch is
-// wave-uniform; in a half-quadrant wave each 32-lane half evaluates its own
-// record and the branch is per lane.  Skipping a
-// record whose rectangle misses the quadrant changes nothing: the rectangle
-// bounds the support where alpha~ >= alpha_min.
+// Work unit: one wave64 per half quadrant (8x4 pixels) of a 16x16 tile,
+// launched as its own workgroup so that waves never wait for each other.
+// Every pixel is held by two lanes, l and l + 32, which take consecutive
+// records of the list: each step evaluates two records, one per 32-lane
+// half, and both halves run the pixel's compositing chain over the two in
+// list order.  (A whole-quadrant forward wave, one pixel per lane, remains
+// for tiles below the split threshold, which is zero.)  The eight waves of
+// a tile are given block ids that the dispatcher sends to the same XCD, so
+// the tile's pair list and records are fetched into one L2.  A wave walks
+// its tile's depth-sorted pair list in chunks of 64: each lane loads one
+// pair's 80-byte record (the next chunk is prefetched into registers while
+// the current one is composited), tests the record's pixel rectangle
+// against the wave's box, and the hits are compacted in list order into
+// the wave's LDS slots (ballot + mbcnt).  The serial loop then visits only
+// those records, read from LDS; the 2D/3D branch is per 32-lane half.
+// Skipping a record whose rectangle misses the box changes nothing: the
+// rectangle bounds the support where alpha~ >= alpha_min.
 //
 // Forward (Sec. 3.1, Eq. 1-2): d_i is the Mahalanobis distance under the
 // projected covariance (3D) or u^2 + v^2 at the ray-splat intersection (2D).
@@ -24,16 +24,16 @@
 // is skipped when alpha~ < alpha_min (false for NaN).  A pixel stops before
 // the pair that would take its transmittance below t_min (defaults 0.99,
 // 1/255 and 1e-4, the thresholds of the rasterizer the paper builds on).
-// A wave stops when its 64 pixels are done.
+// A wave stops when its pixels are done.
 //
 // Backward: each pixel walks its list in reverse from its last blended pair.
 // It recovers T_i = T_{i+1} / (1 - alpha~_i) and carries the suffix
 // S = alpha~ f + (1 - alpha~) S of the per-pair scalar
 // f = <G_rgb, c> + G_depth depth + <G_n, n>.  dL/dalpha~ = T_i (f - S).  The
-// 16 per-pair gradient terms are reduced over the wave in registers (a
-// transposed reduce-scatter on the cross-lane swap and DPP paths, no LDS) and
-// added with one 16-lane vector atomic per wave into the per-(view, splat)
-// accumulators.
+// 16 per-pair gradient terms are reduced over each 32-lane half in
+// registers (a transposed reduce-scatter on the cross-lane swap and DPP
+// paths, no LDS) and added with one atomic instruction per step (16 lanes
+// per half) into the per-(view, splat) accumulators.
 
 #include "hgs_internal.h"
 
@@ -159,22 +159,6 @@ __device__ __forceinline__ bool quad_of(const uint2 *ranges, const uint32_t *ord
   if (!split && (j & 1)) return false;
   const int v = tile / tiles_per_view;
   q = make_quad(tile, v, tile - v * tiles_per_view, j >> 1, W, H, tiles_x, split, j & 1);
-  return true;
-}
-
-// Backward: whole quadrants (the backward is bound by its total work, and a
-// half quadrant repeats a pair's per-pair cost for half the pixels).
-// Blocks 32g + 8q + x hold tile slot 8g + x, quadrant q.
-__device__ __forceinline__ bool quad_of_full(const uint2 *ranges, const uint32_t *order,
-                                             int n_tiles, int W, int H, int tiles_x,
-                                             int tiles_per_view, Quad &q, uint2 &rg) {
-  const int b = blockIdx.x;
-  const int slot = (b >> 5) * 8 + (b & 7);
-  if (slot >= n_tiles) return false;
-  const int tile = order ? (int)order[slot] : slot;
-  rg = ranges[tile];
-  const int v = tile / tiles_per_view;
-  q = make_quad(tile, v, tile - v * tiles_per_view, (b >> 3) & 3, W, H, tiles_x);
   return true;
 }
 
@@ -613,15 +597,10 @@ raster_fwd_queue_kernel(const uint2 *__restrict__ ranges, const uint32_t *__rest
   }
 }
 
-// Cross-lane helpers of the reduce-scatter.  swap32(a, b): lanes 0-31 get
-// (a, a of lane + 32), lanes 32-63 get (b of lane - 32, b); swap16 does the
-// same between the even and odd 16-lane rows.  The sum of the pair is then
-// the two-lane sum of a (lower half / even rows) or of b (upper / odd).
-__device__ __forceinline__ float swap32_sum(float a, float b) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
-                                                  false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
+// Cross-lane helper of the reduce-scatter: swap16(a, b) gives the lanes of
+// the even 16-lane rows (a, a of lane + 16) and those of the odd rows (b of
+// lane - 16, b); the sum of the pair is then the two-lane sum of a (even
+// rows) or of b (odd rows).
 __device__ __forceinline__ float swap16_sum(float a, float b) {
   const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
                                                   false);
@@ -636,33 +615,6 @@ __device__ __forceinline__ float dpp(float x) {
                                                                kCtrl, 0xf, 0xf, false));
 }
 constexpr int kRowMirror = 0x140, kRowHalfMirror = 0x141, kQuadXor1 = 0xB1, kQuadXor2 = 0x4E;
-
-// Sums each of the 16 per-lane values over the wave.  Lane l returns the
-// total of value 8 b5 + 4 b4 + 2 b3 + b2 (b_i = bit i of l); the four lanes
-// that differ only in bits 0-1 hold the same total.  Pairings used: bit 5
-// (swap32), bit 4 (swap16), l ^ 15, l ^ 7, l ^ 1, l ^ 2 -- together they span
-// all 64 lanes.
-__device__ __forceinline__ float wave_reduce_scatter16(const float (&g)[16], int lane) {
-  float s[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) s[k] = swap32_sum(g[k], g[k + 8]);
-  float t[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) t[k] = swap16_sum(s[k], s[k + 4]);
-  const bool b3 = lane & 8;
-  float u[2];
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const float keep = b3 ? t[k + 2] : t[k];
-    const float send = b3 ? t[k] : t[k + 2];
-    u[k] = keep + dpp<kRowMirror>(send);
-  }
-  const bool b2 = lane & 4;
-  float x = (b2 ? u[1] : u[0]) + dpp<kRowHalfMirror>(b2 ? u[0] : u[1]);
-  x += dpp<kQuadXor1>(x);
-  x += dpp<kQuadXor2>(x);
-  return x;
-}
 
 // Sums each of the 16 per-lane values over the lanes of each 32-lane half of
 // the wave separately (the halves hold different pairs).  Lane l returns its
@@ -741,51 +693,51 @@ __device__ __forceinline__ void pair_geometry_grads(float (&g)[16], const PairEv
   g[8] = x8;
 }
 
-// Gradients of one RGB-only cotangent set (FDO's low / high frequency
-// cotangents) for an active pair, into the 16 slots of the main set's layout:
-// the colour, alpha_eff and record-geometry slots; the depth and normal
-// slots are 0 (g[5] must be 0 on entry).  S is that set's suffix, advanced
-// where the pair is active; inactive lanes get zero gradients.
-__device__ __forceinline__ void rgb_set_grads(float (&g)[16], float cr, float cg, float cb,
-                                              float &S, const PairEval &p, bool is3d, bool act,
-                                              bool live, float a, float Ti, float wg, float G,
-                                              const float4 &r1, const float4 &r2,
-                                              const float4 &r3) {
-  const float f = cr * r3.y + cg * r3.z + cb * r3.w;
-  const float dfa = f - S;
-  const float ga = act ? Ti * dfa : 0.0f;
-  S = act ? __builtin_fmaf(a, dfa, S) : S;
-  g[10] = wg * cr;
-  g[11] = wg * cg;
-  g[12] = wg * cb;
-  g[13] = g[14] = g[15] = 0.0f;
-  const float ge = live ? -ga * a * kLn2 : 0.0f;
-  g[9] = live ? ga * G : 0.0f;
-  pair_geometry_grads(g, p, is3d, ge, 0.0f, r1, r2);
-}
-
 // Destination of a reduced gradient total: accumulator plane and slot.
 struct PackDst {
   int plane, slot;
 };
 
-// Backward of one half quadrant (8 x 4 pixels) for one cotangent set.  Lane
-// l and lane l + 32 hold the same pixel.  The wave walks the pairs its
-// forward wave blended (its blend mask) in reverse list order, two per
-// step: the upper half of the wave evaluates the later one (compacted slot
-// k), the lower half the earlier (slot k - 1).  One swap gives every lane
-// both pairs' alpha~ (0 where the pair is not active) and per-pair scalar
-// f; both halves then run the transmittance recovery and the suffix
-// recurrence over the two pairs in that order, so T, S and dL/dalpha~ at
-// each pixel are those of the one-pair walk bit for bit.  Each half forms
-// its own pair's 16 gradient terms, one 32-lane reduce-scatter sums both
-// pairs' terms, and one atomic instruction adds both totals.
+// Terms of one RGB-only cotangent set (cr, cg, cb) for a pair whose dL/dalpha~
+// in that set is ga, into the main set's 16-slot layout (depth and normal
+// slots 0).
+__device__ __forceinline__ void rgb_set_terms(float (&g)[16], float cr, float cg, float cb,
+                                              float ga, float wg, bool live, float a, float G,
+                                              const PairEval &p, bool is3d, const float4 &r1,
+                                              const float4 &r2) {
+  g[10] = wg * cr;
+  g[11] = wg * cg;
+  g[12] = wg * cb;
+  g[13] = g[14] = g[15] = 0.0f;
+  g[5] = 0.0f;
+  const float ge = live ? -ga * a * kLn2 : 0.0f;
+  g[9] = live ? ga * G : 0.0f;
+  pair_geometry_grads(g, p, is3d, ge, 0.0f, r1, r2);
+}
+
+// Backward of one half quadrant (8 x 4 pixels).  Lane l and lane l + 32 hold
+// the same pixel.  The wave walks the pairs its forward wave blended (its
+// blend mask) in reverse list order, two per step: the upper half of the
+// wave evaluates the later one (compacted slot k), the lower half the
+// earlier (slot k - 1).  One swap gives every lane both pairs' alpha~ (0
+// where the pair is not active) and one more each per-pair scalar f of a
+// cotangent set; both halves then run the transmittance recovery and the
+// suffix recurrences over the two pairs in that order, so T, S and
+// dL/dalpha~ at each pixel are those of the one-pair walk bit for bit.
+// Each half forms its own pair's 16 gradient terms per set, one 32-lane
+// reduce-scatter per 16 terms sums both pairs', and one atomic instruction
+// adds both totals.  NS = 1: one cotangent set (gin) into accum.  NS = 3:
+// also the RGB-only sets rgb2.rgb[0], rgb2.rgb[1] into accum + plane and
+// accum + 2 plane; where both pairs of a step are 3D, their 31 non-zero
+// terms travel in two reductions instead of three (layout at packA, packB).
+template <int NS>
 __device__ __forceinline__ void raster_bwd_half(const uint2 *ranges, const uint32_t *order,
                                                 const uint32_t *vals, const Record *rec,
                                                 int n_tiles, int W, int H, int tiles_x,
                                                 int tiles_per_view, const DevOpts &opt,
                                                 const float *T_final, const uint32_t *last_in,
-                                                const RasterGradIn &gin, float *accum,
+                                                const RasterGradIn &gin, const RgbSets &rgb2,
+                                                float *accum, int64_t plane,
                                                 const uint64_t *bmask) {
   __shared__ float4 srec[5][kWave];
   __shared__ uint32_t sid[kWave];
@@ -799,6 +751,7 @@ __device__ __forceinline__ void raster_bwd_half(const uint2 *ranges, const uint3
   float T = 1.0f;
   uint32_t L = 0;
   float Gr = 0, Gg = 0, Gb = 0, Ga = 0, Gd = 0, Gnx = 0, Gny = 0, Gnz = 0;
+  float Xr[2] = {0.0f, 0.0f}, Xg[2] = {0.0f, 0.0f}, Xb[2] = {0.0f, 0.0f};
   if (q.inside) {
     const int64_t hw = (int64_t)H * W;
     const int64_t pix = (int64_t)q.py * W + q.px;
@@ -818,9 +771,24 @@ __device__ __forceinline__ void raster_bwd_half(const uint2 *ranges, const uint3
       Gny = gin.normal[o3 + hw];
       Gnz = gin.normal[o3 + 2 * hw];
     }
+    if constexpr (NS == 3) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (rgb2.rgb[k]) {
+          Xr[k] = rgb2.rgb[k][o3];
+          Xg[k] = rgb2.rgb[k][o3 + hw];
+          Xb[k] = rgb2.rgb[k][o3 + 2 * hw];
+        }
+      }
+    }
   }
-  // suffix value beyond the last blended pair: background and alpha terms
+  // suffix values beyond the last blended pair: background and alpha terms
   float S = Gr * opt.bg[0] + Gg * opt.bg[1] + Gb * opt.bg[2] - Ga;
+  float XS[2] = {0.0f, 0.0f};
+  if constexpr (NS == 3) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) XS[k] = Xr[k] * opt.bg[0] + Xg[k] * opt.bg[1] + Xb[k] * opt.bg[2];
+  }
 
   const int amax_bits = __float_as_int(opt.alpha_max);
   uint32_t wmax = L;
@@ -831,6 +799,17 @@ __device__ __forceinline__ void raster_bwd_half(const uint2 *ranges, const uint3
   prio_for_list(n);
   const int vidx = ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
                    ((lane >> 1) & 1);
+  // NS = 3, both pairs 3D: destination (plane, slot) of this lane's total in
+  // the two packed reductions.  A: the main set, whose slots 6-8 (zero for a
+  // 3D pair) carry RGB set 1's colour slots 10-12.  B: set 1's slots 0-4 and
+  // 9, then set 2's slots 0-4, 9, 10-12; entry 15 is unused.
+  const PackDst packA = vidx >= 6 && vidx <= 8 ? PackDst{1, vidx + 4} : PackDst{0, vidx};
+  const PackDst packB = vidx <= 4    ? PackDst{1, vidx}
+                        : vidx == 5  ? PackDst{1, 9}
+                        : vidx <= 10 ? PackDst{2, vidx - 6}
+                        : vidx == 11 ? PackDst{2, 9}
+                        : vidx <= 14 ? PackDst{2, vidx - 2}
+                                     : PackDst{0, -1};
   const uint64_t *wm = quad_mask_words(const_cast<uint64_t *>(bmask), rg, q.tile, q.sub);
 
   // chunks of 64 list positions in reverse, the first the ragged one; only
@@ -929,6 +908,24 @@ __device__ __forceinline__ void raster_bwd_half(const uint2 *ranges, const uint3
       const float ga = upper ? ga_h : ga_l;
       const bool live = act && !(raw > opt.alpha_max);  // not clamped: the exponent's path
       const float wg = act ? a * Ti : 0.0f;
+      // the RGB-only sets' dL/dalpha~ of this half's pair, by the same
+      // recurrence on their own suffixes
+      float xga[2] = {0.0f, 0.0f};
+      if constexpr (NS == 3) {
+#pragma unroll
+        for (int set = 0; set < 2; ++set) {
+          const float fx = Xr[set] * r3.y + Xg[set] * r3.z + Xb[set] * r3.w;
+          const auto xs = __builtin_amdgcn_permlane32_swap(__float_as_uint(fx),
+                                                           __float_as_uint(fx), false, false);
+          const float xdfa_h = __uint_as_float(xs[1]) - XS[set];
+          const float xga_h = act_h ? Ti_h * xdfa_h : 0.0f;
+          const float XS1 = act_h ? __builtin_fmaf(a_h, xdfa_h, XS[set]) : XS[set];
+          const float xdfa_l = __uint_as_float(xs[0]) - XS1;
+          const float xga_l = act_l ? Ti_l * xdfa_l : 0.0f;
+          XS[set] = act_l ? __builtin_fmaf(a_l, xdfa_l, XS1) : XS1;
+          xga[set] = upper ? xga_h : xga_l;
+        }
+      }
       float g[16];
       g[10] = wg * Gr;
       g[11] = wg * Gg;
@@ -940,9 +937,37 @@ __device__ __forceinline__ void raster_bwd_half(const uint2 *ranges, const uint3
       g[9] = live ? ga * G : 0.0f;                    // dL/d alpha_eff
       g[5] = wg * Gd;                                  // 3D: depth slot
       pair_geometry_grads(g, ps, is3d, ge, wg * Gd, r1, r2);
-      const float tot = half_reduce_scatter16(g, lane);
-      if ((lane & 1) == 0 && tot != 0.0f)
-        unsafeAtomicAdd(accum + (size_t)sk * kGradSlots + vidx, tot);
+      const size_t rec_off = (size_t)sk * kGradSlots;
+      if constexpr (NS == 1) {
+        const float tot = half_reduce_scatter16(g, lane);
+        if ((lane & 1) == 0 && tot != 0.0f) unsafeAtomicAdd(accum + rec_off + vidx, tot);
+      } else {
+        float g1[16], g2[16];
+        rgb_set_terms(g1, Xr[0], Xg[0], Xb[0], xga[0], wg, live, a, G, ps, is3d, r1, r2);
+        rgb_set_terms(g2, Xr[1], Xg[1], Xb[1], xga[1], wg, live, a, G, ps, is3d, r1, r2);
+        if (__ballot(!is3d) == 0ull) {  // both pairs 3D: two packed reductions
+          g[6] = g1[10];
+          g[7] = g1[11];
+          g[8] = g1[12];
+          const float h[16] = {g1[0], g1[1], g1[2], g1[3],  g1[4],  g1[9],  g2[0],  g2[1],
+                               g2[2], g2[3], g2[4], g2[9], g2[10], g2[11], g2[12], 0.0f};
+          const float ta = half_reduce_scatter16(g, lane);
+          const float tb = half_reduce_scatter16(h, lane);
+          if ((lane & 1) == 0 && ta != 0.0f)
+            unsafeAtomicAdd(accum + packA.plane * plane + rec_off + packA.slot, ta);
+          if ((lane & 1) == 0 && tb != 0.0f && packB.slot >= 0)
+            unsafeAtomicAdd(accum + packB.plane * plane + rec_off + packB.slot, tb);
+        } else {
+          const float t0 = half_reduce_scatter16(g, lane);
+          const float t1 = half_reduce_scatter16(g1, lane);
+          const float t2 = half_reduce_scatter16(g2, lane);
+          if ((lane & 1) == 0) {
+            if (t0 != 0.0f) unsafeAtomicAdd(accum + rec_off + vidx, t0);
+            if (t1 != 0.0f) unsafeAtomicAdd(accum + plane + rec_off + vidx, t1);
+            if (t2 != 0.0f) unsafeAtomicAdd(accum + 2 * plane + rec_off + vidx, t2);
+          }
+        }
+      }
     }
   }
 }
@@ -950,7 +975,8 @@ __device__ __forceinline__ void raster_bwd_half(const uint2 *ranges, const uint3
 // NS = 1: one cotangent set.  NS = 3: the main set plus two RGB-only sets
 // (rgb2[0], rgb2[1]) in the same reverse traversal -- one record fetch,
 // one geometry and transmittance recomputation per pair -- accumulated into
-// planes accum, accum + plane, accum + 2 plane.
+// planes accum, accum + plane, accum + 2 plane.  Blocks as in the forward
+// (quad_of): one wave per half quadrant.
 template <int NS>
 __global__ void __launch_bounds__(kWave)
 raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ order,
@@ -959,210 +985,8 @@ raster_bwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
                   int tiles_per_view, DevOpts opt, const float *__restrict__ T_final,
                   const uint32_t *__restrict__ last_in, RasterGradIn gin, RgbSets rgb2,
                   float *__restrict__ accum, int64_t plane, const uint64_t *__restrict__ bmask) {
-  if constexpr (NS == 1) {
-    raster_bwd_half(ranges, order, vals, rec, n_tiles, W, H, tiles_x, tiles_per_view, opt,
-                    T_final, last_in, gin, accum, bmask);
-  } else {
-  __shared__ float4 srec[5][kWave];
-  __shared__ uint32_t sid[kWave];
-  __shared__ uint32_t spos[kWave];
-  Quad q;
-  uint2 rg;
-  if (!quad_of_full(ranges, order, n_tiles, W, H, tiles_x, tiles_per_view, q, rg)) return;
-  const int lane = threadIdx.x;
-
-  float T = 1.0f;
-  uint32_t L = 0;
-  float Gr = 0, Gg = 0, Gb = 0, Ga = 0, Gd = 0, Gnx = 0, Gny = 0, Gnz = 0;
-  float Xr[2] = {0.0f, 0.0f}, Xg[2] = {0.0f, 0.0f}, Xb[2] = {0.0f, 0.0f};
-  if (q.inside) {
-    const int64_t hw = (int64_t)H * W;
-    const int64_t pix = (int64_t)q.py * W + q.px;
-    const int64_t o1 = (int64_t)q.v * hw + pix;
-    const int64_t o3 = (int64_t)q.v * 3 * hw + pix;
-    T = T_final[o1];
-    L = last_in[o1];
-    if (gin.rgb) {
-      Gr = gin.rgb[o3];
-      Gg = gin.rgb[o3 + hw];
-      Gb = gin.rgb[o3 + 2 * hw];
-    }
-    if (gin.alpha) Ga = gin.alpha[o1];
-    if (gin.depth) Gd = gin.depth[o1];
-    if (gin.normal) {
-      Gnx = gin.normal[o3];
-      Gny = gin.normal[o3 + hw];
-      Gnz = gin.normal[o3 + 2 * hw];
-    }
-    if constexpr (NS == 3) {
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        if (rgb2.rgb[k]) {
-          Xr[k] = rgb2.rgb[k][o3];
-          Xg[k] = rgb2.rgb[k][o3 + hw];
-          Xb[k] = rgb2.rgb[k][o3 + 2 * hw];
-        }
-      }
-    }
-  }
-  // suffix value beyond the last blended pair: background and alpha terms
-  float S = Gr * opt.bg[0] + Gg * opt.bg[1] + Gb * opt.bg[2] - Ga;
-  float XS[2] = {0.0f, 0.0f};
-  if constexpr (NS == 3) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k) XS[k] = Xr[k] * opt.bg[0] + Xg[k] * opt.bg[1] + Xb[k] * opt.bg[2];
-  }
-
-  const int amax_bits = __float_as_int(opt.alpha_max);
-  uint32_t wmax = L;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, d));
-  const int n = min((int)__builtin_amdgcn_readfirstlane(wmax), (int)(rg.y - rg.x));
-  if (n <= 0) return;
-  prio_for_list(n);
-  const int vidx = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
-                   ((lane >> 2) & 1);
-  // Three-set kernel, 3D pair: destination (plane, slot) of this lane's
-  // total in the two packed reductions.  A: the main set, whose slots 6-8
-  // (zero for a 3D pair) carry RGB set 1's colour slots 10-12.  B: set 1's
-  // slots 0-4 and 9, then set 2's slots 0-4, 9, 10-12; entry 15 is unused.
-  const PackDst packA = vidx >= 6 && vidx <= 8 ? PackDst{1, vidx + 4} : PackDst{0, vidx};
-  const PackDst packB = vidx <= 4    ? PackDst{1, vidx}
-                        : vidx == 5  ? PackDst{1, 9}
-                        : vidx <= 10 ? PackDst{2, vidx - 6}
-                        : vidx == 11 ? PackDst{2, 9}
-                        : vidx <= 14 ? PackDst{2, vidx - 2}
-                                     : PackDst{0, -1};
-
-  // chunks of 64 list positions in reverse, the first the ragged one; only
-  // the positions the forward blended in this quadrant (its blend mask).
-  // Pipeline: records of chunk c in q0..q4 (entry id), entries of chunk
-  // c - 64 in nid.
-  // a split tile's quadrant: the union of its two halves' masks
-  const uint64_t *wm = quad_mask_words(const_cast<uint64_t *>(bmask), rg, q.tile, q.sub);
-  const uint64_t *wm2 = rg.y - rg.x >= kSplitLen
-                            ? quad_mask_words(const_cast<uint64_t *>(bmask), rg, q.tile, q.sub + 1)
-                            : wm;
-  auto mask_at = [&](int w) { return wm[w] | wm2[w]; };
-  float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0, q4 = q0;
-  uint32_t id = 0, nid = 0;
-  int c = (n - 1) & ~(kWave - 1);
-  bool hit = (c + lane < n) && ((mask_at(c >> 6) >> lane) & 1ull);
-  if (hit) {
-    id = vals[rg.x + c + lane];
-    HGS_FETCH(rec, id, q0, q1, q2, q3, q4);
-  }
-  bool hit_n = c > 0 && ((mask_at((c >> 6) - 1) >> lane) & 1ull);
-  if (hit_n) nid = vals[rg.x + c - kWave + lane];
-  for (; c >= 0; c -= kWave) {
-    const uint64_t m = __ballot(hit);
-    __syncthreads();  // the previous chunk's slots have been read
-    if (hit) {
-      const int slot = lane_rank(m);
-      srec[0][slot] = q0;
-      srec[1][slot] = q1;
-      srec[2][slot] = q2;
-      srec[3][slot] = q3;
-      srec[4][slot] = q4;
-      sid[slot] = id;
-      spos[slot] = (uint32_t)(c + lane);
-    }
-    __syncthreads();
-    if (c > 0) {  // earlier chunks: every position is below n
-      hit = hit_n;
-      id = nid;
-      if (hit) HGS_FETCH(rec, id, q0, q1, q2, q3, q4);
-      hit_n = c > kWave && ((mask_at((c >> 6) - 2) >> lane) & 1ull);
-      if (hit_n) nid = vals[rg.x + c - 2 * kWave + lane];
-    }
-    for (int k = __popcll(m) - 1; k >= 0; --k) {
-      const float4 r0 = srec[0][k], r1 = srec[1][k], r2 = srec[2][k], r3 = srec[3][k],
-                   r4 = srec[4][k];
-      const uint32_t pos = spos[k], sk = sid[k];
-      // fields only the 2D branch uses, named here so that each record row
-      // stays one 16-byte LDS read
-      asm volatile("" ::"v"(r2.z), "v"(r2.w), "v"(r3.x));
-      const bool is3d = is3d_of(r4);
-      const PairEval p = eval_pair(is3d, q.fx, q.fy, r0, r1, r2, r3);
-      const float G = exp2_neg(p.e);
-      const float raw = fabsf(r4.w) * G;
-      const bool act = (pos < L) && (raw >= opt.alpha_min);
-      if (__ballot(act) == 0ull) continue;
-      // Every lane runs the same instructions; an inactive lane's weights
-      // (wg, ga, ge) are 0, and a 2D pair's intersection, which can be
-      // non-finite where the pair does not contribute, is replaced there by
-      // finite values, so its gradient terms are exact zeros.
-      PairEval ps = p;
-      if (!is3d) {
-        ps.e = act ? p.e : 0.0f;
-        ps.rw = act ? p.rw : 0.0f;
-        ps.depth = act ? p.depth : 0.0f;
-      }
-      // as the forward forms it (the integer min of the bit patterns, equal to
-      // the float min for raw >= +0; a NaN raw, never active, gets alpha_max)
-      const float a = __int_as_float(min(__float_as_int(raw), amax_bits));
-      const bool live = act && !(raw > opt.alpha_max);  // not clamped: the exponent's path
-      const float Ti = T * __builtin_amdgcn_rcpf(1.0f - a);
-      const float wg = act ? a * Ti : 0.0f;
-      float g[16];
-      {
-        const float f = Gr * r3.y + Gg * r3.z + Gb * r3.w + Gd * ps.depth + Gnx * r4.x +
-                        Gny * r4.y + Gnz * r4.z;
-        const float dfa = f - S;
-        const float ga = act ? Ti * dfa : 0.0f;  // dL/d alpha~
-        S = act ? __builtin_fmaf(a, dfa, S) : S;
-        g[10] = wg * Gr;
-        g[11] = wg * Gg;
-        g[12] = wg * Gb;
-        g[13] = wg * Gnx;
-        g[14] = wg * Gny;
-        g[15] = wg * Gnz;
-        const float ge = live ? -ga * a * kLn2 : 0.0f;  // dL/de
-        g[9] = live ? ga * G : 0.0f;                    // dL/d alpha_eff
-        g[5] = wg * Gd;                                  // 3D: depth slot
-        pair_geometry_grads(g, ps, is3d, ge, wg * Gd, r1, r2);
-      }
-      const size_t rec_off = (size_t)sk * kGradSlots;
-      if (NS == 3 && is3d) {
-        // A 3D pair has 13 non-zero main slots and 9 per RGB set: two
-        // reductions carry all 31 (layout at packA / packB).
-        float g1[16], g2[16];
-        g1[5] = 0.0f;
-        g2[5] = 0.0f;
-        rgb_set_grads(g1, Xr[0], Xg[0], Xb[0], XS[0], ps, is3d, act, live, a, Ti, wg, G, r1, r2,
-                      r3);
-        rgb_set_grads(g2, Xr[1], Xg[1], Xb[1], XS[1], ps, is3d, act, live, a, Ti, wg, G, r1, r2,
-                      r3);
-        g[6] = g1[10];
-        g[7] = g1[11];
-        g[8] = g1[12];
-        const float h[16] = {g1[0], g1[1], g1[2], g1[3],  g1[4],  g1[9],  g2[0],  g2[1],
-                             g2[2], g2[3], g2[4], g2[9], g2[10], g2[11], g2[12], 0.0f};
-        const float ta = wave_reduce_scatter16(g, lane);
-        const float tb = wave_reduce_scatter16(h, lane);
-        if ((lane & 3) == 0 && ta != 0.0f)
-          unsafeAtomicAdd(accum + packA.plane * plane + rec_off + packA.slot, ta);
-        if ((lane & 3) == 0 && tb != 0.0f && packB.slot >= 0)
-          unsafeAtomicAdd(accum + packB.plane * plane + rec_off + packB.slot, tb);
-      } else {
-        const float tot = wave_reduce_scatter16(g, lane);
-        if ((lane & 3) == 0 && tot != 0.0f) unsafeAtomicAdd(accum + rec_off + vidx, tot);
-        if constexpr (NS == 3) {
-#pragma unroll
-          for (int set = 0; set < 2; ++set) {
-            g[5] = 0.0f;
-            rgb_set_grads(g, Xr[set], Xg[set], Xb[set], XS[set], ps, is3d, act, live, a, Ti, wg,
-                          G, r1, r2, r3);
-            const float t2 = wave_reduce_scatter16(g, lane);
-            if ((lane & 3) == 0 && t2 != 0.0f)
-              unsafeAtomicAdd(accum + (size_t)(set + 1) * plane + rec_off + vidx, t2);
-          }
-        }
-      }
-      T = act ? Ti : T;
-    }
-  }
-  }
+  raster_bwd_half<NS>(ranges, order, vals, rec, n_tiles, W, H, tiles_x, tiles_per_view, opt,
+                      T_final, last_in, gin, rgb2, accum, plane, bmask);
 }
 
 // Tile order of the raster launches: tiles by pair-list length, longest
@@ -1289,10 +1113,9 @@ tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, const int *__re
   }
 }
 
-// Blocks: 64 per group of 8 tiles (four quadrants of two halves each) for
-// the forward, see quad_of; 32 (four quadrants) for the backward.
+// Blocks: 64 per group of 8 tiles (four quadrants of two halves each), the
+// forward's and the backward's, see quad_of.
 unsigned quad_blocks(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 64u; }
-unsigned quad_blocks_full(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 32u; }
 
 }  // namespace
 
@@ -1345,7 +1168,9 @@ void launch_raster_bwd_sets(const uint2 *ranges, const uint32_t *order, const ui
                             const uint32_t *last, const uint64_t *bmask, RasterGradIn g,
                             RgbSets rgb2, float *accum, int64_t plane, hipStream_t s) {
   if (n_tiles_total <= 0) return;
-  hipLaunchKernelGGL(raster_bwd_kernel<3>, dim3(quad_blocks_full(n_tiles_total)), dim3(kWave), 0, s,
+  hipLaunchKernelGGL(raster_bwd_kernel<3>,
+                     dim3(quad_blocks(n_tiles_total)),
+                     dim3(kWave), 0, s,
                      ranges, order, vals, rec, n_tiles_total, W, H, tiles_x, tiles_per_view, opt,
                      T_final, last, g, rgb2, accum, plane, bmask);
 }
