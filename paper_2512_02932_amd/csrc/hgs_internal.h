@@ -258,11 +258,11 @@ void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_
                        int tiles_per_view, DevOpts opt, RasterOut out, uint64_t *bmask,
                        hipStream_t s);
 
-// Forward of a batch of slots on a persistent grid of n_blocks wave64s
-// that pull work units from *queue (zero at launch) over the device tile
-// count *n_tiles: with order and n_split (from launch_tile_order), the
-// per-view forward's waves in that order, else (tile, quadrant).  Writes
-// each slot's images.
+// Forward of a batch of slots on a persistent grid of n_blocks wave64s (a
+// multiple of 8) that pull work units from queue[0..7] (zero at launch; one
+// counter per XCD) over the device tile count *n_tiles: with order and
+// n_split (from launch_tile_order), the per-view forward's waves in that
+// order, else (tile, quadrant).  Writes each slot's images.
 void launch_raster_fwd_queue(const uint2 *ranges, const uint32_t *vals, const Record *rec,
                              const Slot *slots, const int *n_slots, const int *n_tiles,
                              int n_blocks, DevOpts opt, uint32_t *queue, hipStream_t s,

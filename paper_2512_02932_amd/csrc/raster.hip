@@ -550,9 +550,14 @@ raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
 // A batch of slots (requests of any size), persistent: each wave takes work
 // units from an atomic counter until they run out; every wave reaches that
 // exit.  With a tile order (order, n_split from tile_order_kernel), the
-// units are the waves of the per-view forward in that order: 8 per split
-// tile (quadrant x half) for the first *n_split tiles, then 4 per tile;
-// without one, u = 4 tile + quadrant.  `queue` must be zero at launch.
+// units are the waves of the per-view forward in that order: 8 per
+// non-empty tile (quadrant x half) for the first *n_split tiles, then 4
+// whole quadrants per (empty) tile; without one, 4 per tile.  The tiles are
+// dealt to the XCDs by slot mod 8, as the per-view forward's block mapping
+// does: the waves of block b (which the dispatcher sends to XCD b mod 8)
+// pop the units of the slots s = b (mod 8) from counter queue[b mod 8], so
+// a tile's waves share one L2 and each counter sees an eighth of the pops.
+// queue[0..7] must be zero at launch.
 __global__ void __launch_bounds__(kWave)
 raster_fwd_queue_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ order,
                         const uint32_t *__restrict__ n_split, const uint32_t *__restrict__ vals,
@@ -564,23 +569,30 @@ raster_fwd_queue_kernel(const uint2 *__restrict__ ranges, const uint32_t *__rest
   const int ns = *n_slots;
   const uint32_t nt = (uint32_t)max(*n_tiles, 0);
   const uint32_t nsp = order ? min(*n_split, nt) : 0u;
-  const uint32_t units = 8u * nsp + 4u * (nt - nsp);
+  const uint32_t x = blockIdx.x & 7u;
+  // this XCD's split slots x, x + 8, ... below nsp, then its other slots
+  // from the first s >= nsp with s = x (mod 8)
+  const uint32_t n_sp = nsp > x ? (nsp - x + 7u) >> 3 : 0u;
+  const uint32_t first = nsp + ((x - nsp) & 7u);
+  const uint32_t n_wq = first < nt ? (nt - first + 7u) >> 3 : 0u;
+  const uint32_t units = 8u * n_sp + 4u * n_wq;
   if (ns <= 0) return;
   for (;;) {
     uint32_t u = 0;
-    if (threadIdx.x == 0) u = atomicAdd(queue, 1u);
+    if (threadIdx.x == 0) u = atomicAdd(queue + x, 1u);
     u = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)u, 0));
     if (u >= units) break;
     uint32_t slot_i, quad, half = 0;
     bool split = false;
-    if (u < 8u * nsp) {
-      slot_i = u >> 3;
+    if (u < 8u * n_sp) {
+      slot_i = 8u * (u >> 3) + x;
       quad = (u >> 1) & 3u;
       half = u & 1u;
       split = true;
     } else {
-      slot_i = nsp + ((u - 8u * nsp) >> 2);
-      quad = (u - 8u * nsp) & 3u;
+      const uint32_t k = u - 8u * n_sp;
+      slot_i = first + 8u * (k >> 2);
+      quad = k & 3u;
     }
     const int tile = order ? (int)order[slot_i] : (int)slot_i;
     const Slot &sl = slots[slot_of_tile(slots, ns, tile)];

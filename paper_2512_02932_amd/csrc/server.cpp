@@ -59,7 +59,7 @@ struct Lane {
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
   uint2 *ranges = nullptr;
   uint32_t *order = nullptr;  // tiles by pair-list length, longest first
-  uint32_t *queue = nullptr;  // [0] the raster's unit counter, [1] split tiles
+  uint32_t *queue = nullptr;  // [0..7] the raster's unit counters (one per XCD), [8] split tiles
   void *scan_tmp = nullptr, *sort_tmp = nullptr;
   std::vector<void *> allocs;
   bool busy = false;
@@ -109,7 +109,7 @@ void enqueue_pass(const hgs_server *sv, Lane &L) {
   const uint64_t *n_inst = &hdr->n_inst;
   uint64_t *pairs = &L.status_dev->pairs;
   launch_fill_u32(reinterpret_cast<uint32_t *>(L.ranges), 0u, 2 * T, s);
-  launch_fill_u32(L.queue, 0u, 1, s);
+  launch_fill_u32(L.queue, 0u, 8, s);
   launch_fill_u32(&L.status_dev->overflow, 0u, 1, s);
   launch_preprocess_slots(slots, n_slots, n_inst, sv->opt, I, L.rec, L.tiles, L.zbits, L.rect,
                           L.flags, L.prect, s);
@@ -126,9 +126,9 @@ void enqueue_pass(const hgs_server *sv, Lane &L) {
   const uint32_t *keys = w2 ? L.kb : L.ka;
   const uint32_t *vals = w2 ? L.vb : L.va;
   launch_ranges(keys, P, L.ranges, s, pairs);
-  launch_tile_order(L.ranges, (int)T, L.order, s, n_tiles, L.queue + 1);
+  launch_tile_order(L.ranges, (int)T, L.order, s, n_tiles, L.queue + 8);
   launch_raster_fwd_queue(L.ranges, vals, L.rec, slots, n_slots, n_tiles, sv->raster_blocks,
-                          sv->opt, L.queue, s, L.order, L.queue + 1);
+                          sv->opt, L.queue, s, L.order, L.queue + 8);
   (void)hipMemcpyAsync(L.status_host, L.status_dev, sizeof(BatchStatus), hipMemcpyDeviceToHost,
                        s);
 }
@@ -164,7 +164,7 @@ hgs_status lane_init(hgs_server *sv, Lane &L) {
   HGS_HIP(lalloc(L, &L.vb, (size_t)P));
   HGS_HIP(lalloc(L, &L.ranges, (size_t)T));
   HGS_HIP(lalloc(L, &L.order, (size_t)T));
-  HGS_HIP(lalloc(L, &L.queue, 2));
+  HGS_HIP(lalloc(L, &L.queue, 9));
   HGS_HIP(lalloc(L, reinterpret_cast<char **>(&L.scan_tmp), scan_tmp_bytes(I)));
   HGS_HIP(lalloc(L, reinterpret_cast<char **>(&L.sort_tmp),
                  sort_tmp_bytes(std::max<int64_t>(I, P))));
