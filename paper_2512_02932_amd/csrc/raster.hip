@@ -557,8 +557,9 @@ raster_fwd_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__
 // does: the waves of block b (which the dispatcher sends to XCD b mod 8)
 // pop the units of the slots s = b (mod 8) from counter queue[b mod 8], so
 // a tile's waves share one L2 and each counter sees an eighth of the pops.
-// queue[0..7] must be zero at launch.
-__global__ void __launch_bounds__(kWave)
+// queue[0..7] must be zero at launch.  At most 80 VGPRs (six waves per
+// SIMD), as the per-view forward.
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6)))
 raster_fwd_queue_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ order,
                         const uint32_t *__restrict__ n_split, const uint32_t *__restrict__ vals,
                         const Record *__restrict__ rec, const Slot *__restrict__ slots,
