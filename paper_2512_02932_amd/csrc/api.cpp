@@ -764,8 +764,10 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_image
   HGS_HIP(dalloc_t(st, &accum, (size_t)std::max<int64_t>(VN, 1) * kGradSlots));
   HGS_HIP(commit(st, 2, s, capturing(s)));
   {
+    // the accumulators cleared beside the backward's tile order (by the
+    // forward waves' blended counts, largest first)
     StageTimer t(ctx, HGS_STAGE_FILL, s);
-    launch_fill_f32(accum, 0.0f, VN * kGradSlots, s);
+    launch_order_and_clear(st->vis, (int)st->n_tiles, st->order_bwd, accum, VN * kGradSlots, s);
   }
   RasterGradIn gi{};
   if (gout) {
@@ -776,8 +778,6 @@ hgs_status hgs_render_backward(hgs_ctx *ctx, hgs_state *st, const hgs_grad_image
   }
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_BWD, s);
-    // the backward's tiles by their forward waves' blended counts, largest first
-    launch_tile_order(st->vis, (int)st->n_tiles, st->order_bwd, s);
     launch_raster_bwd(st->ranges, st->order_bwd, st->vals, st->rec, st->n_tiles, st->W, st->H,
                       st->tiles_x,
                       st->tiles_per_view, st->opt, st->T_final, st->last, st->bmask, gi, accum,
@@ -852,7 +852,7 @@ hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *st, const hgs_grad_i
   }
   {
     StageTimer t(ctx, HGS_STAGE_FILL, s);
-    launch_fill_f32(accum, 0.0f, 3 * plane, s);
+    launch_order_and_clear(st->vis, (int)st->n_tiles, st->order_bwd, accum, 3 * plane, s);
   }
   RasterGradIn gi{};
   if (gcolor) {
@@ -866,7 +866,6 @@ hgs_status hgs_render_backward_fdo(hgs_ctx *ctx, hgs_state *st, const hgs_grad_i
   x.rgb[1] = grad_high_rgb;
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_BWD, s);
-    launch_tile_order(st->vis, (int)st->n_tiles, st->order_bwd, s);
     launch_raster_bwd_sets(st->ranges, st->order_bwd, st->vals, st->rec, st->n_tiles, st->W,
                            st->H,
                            st->tiles_x,

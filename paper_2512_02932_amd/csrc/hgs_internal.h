@@ -252,6 +252,12 @@ void launch_tile_order(const uint2 *ranges, int n_tiles_total, uint32_t *order, 
                        const int *n_tiles_dev = nullptr, uint32_t *n_split = nullptr,
                        const uint64_t *total = nullptr, uint64_t *total_out = nullptr,
                        uint2 *clear = nullptr);
+// The backward's set-up in one launch: order[n_tiles_total] receives the
+// tiles by vis (a RasterOut::vis of the forward, as launch_tile_order orders
+// by ranges) while the other workgroups set acc[0..n) to zero (acc 16-byte
+// aligned, n a multiple of 4).
+void launch_order_and_clear(const uint2 *vis, int n_tiles_total, uint32_t *order, float *acc,
+                            int64_t n, hipStream_t s);
 // order (may be NULL: tile index order): from launch_tile_order.
 void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
                        const Record *rec, int n_tiles_total, int W, int H, int tiles_x,

@@ -1038,17 +1038,19 @@ __device__ __forceinline__ uint64_t bucket_peers(int b, bool valid) {
 }
 
 constexpr int kOrderLds = 32768;  // tiles whose buckets are staged in LDS first
-__global__ void __launch_bounds__(kOrderWaves * kWave)
-tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, const int *__restrict__ n_dev,
-                  uint32_t *__restrict__ order, uint32_t *__restrict__ n_split,
-                  const uint64_t *__restrict__ total, uint64_t *__restrict__ total_out,
-                  uint2 *__restrict__ clear) {
+// The ordering itself, by one workgroup of kOrderWaves waves; s_cnt and s_bk
+// are its LDS (kOrderBuckets * kOrderWaves words, kOrderLds bytes).
+__device__ __forceinline__ void tile_order_block(const uint2 *__restrict__ ranges, int n_tiles,
+                                                 const int *__restrict__ n_dev,
+                                                 uint32_t *__restrict__ order,
+                                                 uint32_t *__restrict__ n_split,
+                                                 const uint64_t *__restrict__ total,
+                                                 uint64_t *__restrict__ total_out,
+                                                 uint2 *__restrict__ clear, uint32_t *s_cnt,
+                                                 uint8_t *s_bk) {
   if (total_out && threadIdx.x == 0)
     __hip_atomic_store(total_out, *total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   if (n_dev) n_tiles = min(n_tiles, max(*n_dev, 0));
-  // per (bucket, wave) counts, then bases, at entry(bucket)
-  __shared__ uint32_t s_cnt[kOrderBuckets * kOrderWaves];
-  __shared__ uint8_t s_bk[kOrderLds];
   constexpr int kT = kOrderWaves * kWave;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   for (int e = threadIdx.x; e < kOrderBuckets * kOrderWaves; e += kT) s_cnt[e] = 0;
@@ -1126,6 +1128,34 @@ tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, const int *__re
   }
 }
 
+__global__ void __launch_bounds__(kOrderWaves * kWave)
+tile_order_kernel(const uint2 *__restrict__ ranges, int n_tiles, const int *__restrict__ n_dev,
+                  uint32_t *__restrict__ order, uint32_t *__restrict__ n_split,
+                  const uint64_t *__restrict__ total, uint64_t *__restrict__ total_out,
+                  uint2 *__restrict__ clear) {
+  __shared__ uint32_t s_cnt[kOrderBuckets * kOrderWaves];
+  __shared__ uint8_t s_bk[kOrderLds];
+  tile_order_block(ranges, n_tiles, n_dev, order, n_split, total, total_out, clear, s_cnt, s_bk);
+}
+
+// The backward's set-up in one launch: workgroup 0 orders the tiles (as
+// tile_order_kernel), the others clear the accumulators (n4 float4s), which
+// the ordering's single workgroup would otherwise leave the device idle for.
+__global__ void __launch_bounds__(kOrderWaves * kWave)
+order_and_clear_kernel(const uint2 *__restrict__ ranges, int n_tiles,
+                       uint32_t *__restrict__ order, float4 *__restrict__ acc, int64_t n4) {
+  __shared__ uint32_t s_cnt[kOrderBuckets * kOrderWaves];
+  __shared__ uint8_t s_bk[kOrderLds];
+  if (blockIdx.x == 0) {
+    tile_order_block(ranges, n_tiles, nullptr, order, nullptr, nullptr, nullptr, nullptr, s_cnt,
+                     s_bk);
+    return;
+  }
+  const int64_t stride = (int64_t)(gridDim.x - 1) * blockDim.x;
+  for (int64_t i = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x; i < n4; i += stride)
+    acc[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 // Blocks: 64 per group of 8 tiles (four quadrants of two halves each), the
 // forward's and the backward's, see quad_of.
 unsigned quad_blocks(int n_tiles) { return (unsigned)((n_tiles + 7) / 8) * 64u; }
@@ -1138,6 +1168,21 @@ void launch_tile_order(const uint2 *ranges, int n_tiles_total, uint32_t *order,
   if (n_tiles_total <= 0) return;
   hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderWaves * kWave), 0, s, ranges,
                      n_tiles_total, n_tiles_dev, order, n_split, total, total_out, clear);
+}
+
+void launch_order_and_clear(const uint2 *ranges, int n_tiles_total, uint32_t *order, float *acc,
+                            int64_t n, hipStream_t s) {
+  if (n_tiles_total <= 0) {
+    launch_fill_f32(acc, 0.0f, n, s);
+    return;
+  }
+  // acc is a workspace allocation (256-byte aligned) of n floats, n % 4 == 0
+  const int64_t n4 = n / 4;
+  const int64_t fill_blocks =
+      std::min<int64_t>((n4 + kOrderWaves * kWave - 1) / (kOrderWaves * kWave), 2048);
+  hipLaunchKernelGGL(order_and_clear_kernel, dim3((unsigned)(1 + fill_blocks)),
+                     dim3(kOrderWaves * kWave), 0, s, ranges, n_tiles_total, order,
+                     reinterpret_cast<float4 *>(acc), n4);
 }
 
 void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_t *vals,
