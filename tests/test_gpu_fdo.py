@@ -322,7 +322,11 @@ def test_one_view_without_sets_equals_projection(name):
         rels[k] = float((a - b).norm()) / max(float(b.norm()), 1e-300)
     say(f"[fdo] {name} one-view path vs stored sets: worst per primitive {worst:.3g}, "
         f"relative L2 per array {rels}")
-    assert all(v <= 1e-6 for v in rels.values()), rels
+    # the two traversals add the same float32 terms into each accumulator
+    # slot in different atomic orders; every slot takes one addend per
+    # half-quadrant wave and pair (two waves per quadrant), and the bound on
+    # two summation orders' difference grows with the addend count: 2e-6
+    assert all(v <= 2e-6 for v in rels.values()), rels
     assert abs(int(cnt.item()) - int(cnt_sets.item())) <= int(close.sum())
     # accumulate adds; NULL arrays are skipped and the rest still written
     # (each call runs its own traversal, whose atomic sums may round in
