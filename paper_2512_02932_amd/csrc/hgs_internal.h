@@ -244,7 +244,8 @@ inline int64_t raster_mask_words(int64_t pairs, int64_t tiles) {
 // ranges), the order in which the raster launches below start their tiles.
 // n_tiles_dev (may be NULL): the tile count on the device (at most
 // n_tiles_total).  n_split (may be NULL): receives how many tiles, at the
-// front of the order, the forward splits into half-quadrant waves.
+// front of the order, have a non-empty pair list (the batch forward walks
+// those with half-quadrant waves).
 // total_out (may be NULL; mapped pinned host memory): receives *total, the
 // render's pair count, without a copy command of its own.  clear (may be
 // NULL): n_tiles entries set to zero (a RasterOut::vis for the forward).

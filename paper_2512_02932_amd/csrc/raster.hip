@@ -110,12 +110,13 @@ struct Quad {
   bool inside;
 };
 
-// Tiles whose pair list is at least this long are walked by two waves per
-// quadrant, each on 8 x 4 pixels and culling against its own half.  Each
-// pixel is held by two lanes (l and l + 32), which evaluate two consecutive
-// records at once: a step reads two records from LDS and composites both,
-// where a whole-quadrant wave reads one.  The long lists set the kernel's
-// length, and a half meets fewer splats than the whole quadrant.
+// Tiles whose pair list is at least this long (every tile: the threshold is
+// zero) are walked by two waves per quadrant, each on 8 x 4 pixels and
+// culling against its own half.  Each pixel is held by two lanes (l and
+// l + 32), which evaluate two consecutive records at once: a step reads two
+// records from LDS and composites both, where a whole-quadrant wave reads
+// one, and a half meets fewer splats than the whole quadrant.  The
+// whole-quadrant walk remains for the batch forward's empty tiles.
 constexpr uint32_t kSplitLen = 0;
 
 // Quadrant `quad` of the view-local tile r (row-major over tiles_x columns);
