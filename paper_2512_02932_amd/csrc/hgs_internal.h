@@ -216,6 +216,14 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
                       const uint32_t *gather_tiles = nullptr, bool zero_free = false);
 
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+// Up to kMax uint32 arrays set to zero in one launch (p[a] may be NULL when
+// n[a] is 0).
+struct FillList {
+  static constexpr int kMax = 6;
+  uint32_t *p[kMax] = {};
+  int64_t n[kMax] = {};
+};
+void launch_zero_list(const FillList &f, hipStream_t s);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 // ranges[t] = [first, last + 1) of tile t in the tile-sorted keys (ranges
 // must be zeroed first).

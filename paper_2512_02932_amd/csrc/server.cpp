@@ -60,6 +60,7 @@ struct Lane {
   uint2 *ranges = nullptr;
   uint32_t *order = nullptr;  // tiles by pair-list length, longest first
   uint32_t *queue = nullptr;  // [0..7] the raster's unit counters (one per XCD), [8] split tiles
+  uint32_t *dwords = nullptr, *twords = nullptr;  // digit tables of the two sorts
   void *scan_tmp = nullptr, *sort_tmp = nullptr;
   std::vector<void *> allocs;
   bool busy = false;
@@ -108,13 +109,24 @@ void enqueue_pass(const hgs_server *sv, Lane &L) {
   const int *n_tiles = &hdr->n_tiles;
   const uint64_t *n_inst = &hdr->n_inst;
   uint64_t *pairs = &L.status_dev->pairs;
-  launch_fill_u32(reinterpret_cast<uint32_t *>(L.ranges), 0u, 2 * T, s);
-  launch_fill_u32(L.queue, 0u, 8, s);
-  launch_fill_u32(&L.status_dev->overflow, 0u, 1, s);
+  // the pass's zero-initialised arrays in one launch: ranges, the raster's
+  // unit counters, the overflow flag, both sorts' digit tables
+  FillList zl;
+  zl.p[0] = reinterpret_cast<uint32_t *>(L.ranges);
+  zl.n[0] = 2 * T;
+  zl.p[1] = L.queue;
+  zl.n[1] = 8;
+  zl.p[2] = &L.status_dev->overflow;
+  zl.n[2] = 1;
+  zl.p[3] = L.dwords;
+  zl.n[3] = kSortWords;
+  zl.p[4] = L.twords;
+  zl.n[4] = kSortWords;
+  launch_zero_list(zl, s);
   launch_preprocess_slots(slots, n_slots, n_inst, sv->opt, I, L.rec, L.tiles, L.zbits, L.rect,
                           L.flags, L.prect, s);
   const int w = launch_radix_sort(L.zbits, nullptr, L.za, L.oa, L.zb, L.ob, I, 32, L.sort_tmp, s,
-                                  n_inst, L.prect, L.cnt, &L.status_dev->overflow, nullptr,
+                                  n_inst, L.prect, L.cnt, &L.status_dev->overflow, L.dwords,
                                   L.prect_s, L.tiles, /*zero_free=*/true);
   const uint32_t *order = w ? L.ob : L.oa;
   launch_scan(L.cnt, L.offsets, I, pairs, L.scan_tmp, s, n_inst);
@@ -122,7 +134,7 @@ void enqueue_pass(const hgs_server *sv, Lane &L) {
                          n_inst, (uint64_t)P, L.kb, L.vb, &L.status_dev->overflow, s);
   const int w2 = launch_radix_sort(L.kb, L.vb, L.ka, L.va, L.kb, L.vb, P, sv->tile_bits,
                                    L.sort_tmp, s, pairs, nullptr, nullptr,
-                                   &L.status_dev->overflow);
+                                   &L.status_dev->overflow, L.twords);
   const uint32_t *keys = w2 ? L.kb : L.ka;
   const uint32_t *vals = w2 ? L.vb : L.va;
   launch_ranges(keys, P, L.ranges, s, pairs);
@@ -165,6 +177,8 @@ hgs_status lane_init(hgs_server *sv, Lane &L) {
   HGS_HIP(lalloc(L, &L.ranges, (size_t)T));
   HGS_HIP(lalloc(L, &L.order, (size_t)T));
   HGS_HIP(lalloc(L, &L.queue, 9));
+  HGS_HIP(lalloc(L, &L.dwords, (size_t)kSortWords));
+  HGS_HIP(lalloc(L, &L.twords, (size_t)kSortWords));
   HGS_HIP(lalloc(L, reinterpret_cast<char **>(&L.scan_tmp), scan_tmp_bytes(I)));
   HGS_HIP(lalloc(L, reinterpret_cast<char **>(&L.sort_tmp),
                  sort_tmp_bytes(std::max<int64_t>(I, P))));

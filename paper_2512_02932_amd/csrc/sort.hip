@@ -22,7 +22,7 @@ namespace {
 
 constexpr int kScanItems = 16;                       // elements per thread
 constexpr int kScanChunk = kBlock * kScanItems;      // 4096 per block
-constexpr int64_t kFlatChunks = 2048;  // up to 8M elements: two launches per scan
+constexpr int64_t kFlatChunks = 4096;  // up to 16M elements: two launches per scan
 
 // Element count of a launch: the host capacity n, or min(n, *n_dev) when the
 // count lives on the device (graph-captured launches never read it back).
@@ -758,6 +758,19 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
+// Every region of f set to zero: a grid-stride loop over their concatenation.
+__global__ void zero_list_kernel(FillList f, int64_t total) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    int64_t k = i;
+#pragma unroll
+    for (int a = 0; a < FillList::kMax; ++a) {
+      if (k >= 0 && k < f.n[a]) f.p[a][k] = 0u;
+      k -= f.n[a];
+    }
+  }
+}
+
 __global__ void fill_f32_kernel(float *p, float v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -918,6 +931,17 @@ int launch_radix_sort(const uint32_t *k0, const uint32_t *v0, uint32_t *ka, uint
                          n_dev, p, words, gather_src, gather_tiles, gather_dst, gather_dst2, err);
   }
   return (passes - 1) & 1;
+}
+
+void launch_zero_list(const FillList &f, hipStream_t s) {
+  int64_t total = 0;
+  for (int a = 0; a < FillList::kMax; ++a) total += f.n[a] > 0 ? f.n[a] : 0;
+  if (total == 0) return;
+  FillList g = f;
+  for (int a = 0; a < FillList::kMax; ++a)
+    if (g.n[a] < 0) g.n[a] = 0;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1024);
+  hipLaunchKernelGGL(zero_list_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, total);
 }
 
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
