@@ -274,10 +274,13 @@ void launch_raster_fwd(const uint2 *ranges, const uint32_t *order, const uint32_
                        hipStream_t s);
 
 // Forward of a batch of slots on a persistent grid of n_blocks wave64s (a
-// multiple of 8) that pull work units from queue[0..7] (zero at launch; one
-// counter per XCD) over the device tile count *n_tiles: with order and
-// n_split (from launch_tile_order), the per-view forward's waves in that
-// order, else (tile, quadrant).  Writes each slot's images.
+// multiple of 8) that pull work units from the counters queue[kQueueStride x],
+// x = 0..7 (zero at launch; one per XCD, each on a 256-byte line of its
+// own) over the device tile count *n_tiles: with order and n_split (from
+// launch_tile_order), the per-view forward's waves in that order, else
+// (tile, quadrant).  Writes each slot's images.
+constexpr int kQueueStride = 64;
+constexpr int kQueueWords = 8 * kQueueStride;
 void launch_raster_fwd_queue(const uint2 *ranges, const uint32_t *vals, const Record *rec,
                              const Slot *slots, const int *n_slots, const int *n_tiles,
                              int n_blocks, DevOpts opt, uint32_t *queue, hipStream_t s,

@@ -59,7 +59,9 @@ struct Lane {
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
   uint2 *ranges = nullptr;
   uint32_t *order = nullptr;  // tiles by pair-list length, longest first
-  uint32_t *queue = nullptr;  // [0..7] the raster's unit counters (one per XCD), [8] split tiles
+  // the raster's unit counters, queue[kQueueStride x] for XCD x, then at
+  // queue[kQueueWords] the count of split tiles
+  uint32_t *queue = nullptr;
   uint32_t *dwords = nullptr, *twords = nullptr;  // digit tables of the two sorts
   void *scan_tmp = nullptr, *sort_tmp = nullptr;
   std::vector<void *> allocs;
@@ -115,7 +117,7 @@ void enqueue_pass(const hgs_server *sv, Lane &L) {
   zl.p[0] = reinterpret_cast<uint32_t *>(L.ranges);
   zl.n[0] = 2 * T;
   zl.p[1] = L.queue;
-  zl.n[1] = 8;
+  zl.n[1] = kQueueWords;
   zl.p[2] = &L.status_dev->overflow;
   zl.n[2] = 1;
   zl.p[3] = L.dwords;
@@ -138,9 +140,9 @@ void enqueue_pass(const hgs_server *sv, Lane &L) {
   const uint32_t *keys = w2 ? L.kb : L.ka;
   const uint32_t *vals = w2 ? L.vb : L.va;
   launch_ranges(keys, P, L.ranges, s, pairs);
-  launch_tile_order(L.ranges, (int)T, L.order, s, n_tiles, L.queue + 8);
+  launch_tile_order(L.ranges, (int)T, L.order, s, n_tiles, L.queue + kQueueWords);
   launch_raster_fwd_queue(L.ranges, vals, L.rec, slots, n_slots, n_tiles, sv->raster_blocks,
-                          sv->opt, L.queue, s, L.order, L.queue + 8);
+                          sv->opt, L.queue, s, L.order, L.queue + kQueueWords);
   (void)hipMemcpyAsync(L.status_host, L.status_dev, sizeof(BatchStatus), hipMemcpyDeviceToHost,
                        s);
 }
@@ -176,7 +178,7 @@ hgs_status lane_init(hgs_server *sv, Lane &L) {
   HGS_HIP(lalloc(L, &L.vb, (size_t)P));
   HGS_HIP(lalloc(L, &L.ranges, (size_t)T));
   HGS_HIP(lalloc(L, &L.order, (size_t)T));
-  HGS_HIP(lalloc(L, &L.queue, 9));
+  HGS_HIP(lalloc(L, &L.queue, kQueueWords + 1));
   HGS_HIP(lalloc(L, &L.dwords, (size_t)kSortWords));
   HGS_HIP(lalloc(L, &L.twords, (size_t)kSortWords));
   HGS_HIP(lalloc(L, reinterpret_cast<char **>(&L.scan_tmp), scan_tmp_bytes(I)));
