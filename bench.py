@@ -392,7 +392,8 @@ def render_leg(rast, name, steps, warmup):
     # work accounting of this workload (identical every step), and a check
     # that the pairs fit the render's capacity
     from paper_2512_02932_amd import _hgs
-    _hgs.hgs_profile_enable(rast.ctx, True)  # the forward records its pair counts
+    # the forward records its pair counts (work accounting)
+    _hgs.hgs_profile_enable(rast.ctx, _hgs.PROFILE_STAGES | _hgs.PROFILE_WORK)
     _, st = rast.render(sc, cams, images=images, want_state=True)
     _hgs.hgs_profile_enable(rast.ctx, False)
     _hgs.hgs_profile_read(rast.ctx, reset=True)

@@ -225,7 +225,7 @@ hgs_status hgs_state_sizes(hgs_ctx *ctx, hgs_state *state, int64_t *sizes5 /* [h
  *                               2D pairs, bit 30 the pair that stopped the
  *                               pixel was 2D, bit 31 the pixel stopped;
  *                               recorded only by a render made while
- *                               profiling is enabled, else EINVAL)
+ *                               HGS_PROFILE_WORK is enabled, else EINVAL)
  * `capacity` is the size of dst in bytes.  The call synchronises. */
 hgs_status hgs_state_debug(hgs_ctx *ctx, hgs_state *state, int32_t what, void *dst_host,
                            int64_t capacity);
@@ -235,11 +235,18 @@ hgs_status hgs_state_debug(hgs_ctx *ctx, hgs_state *state, int32_t what, void *d
  * render on this context is given room for them). */
 hgs_status hgs_state_check(hgs_ctx *ctx, hgs_state *state);
 
-/* Per-stage timing.  While enabled, every render/backward call records a
- * HIP event pair around each stage on the stream it enqueues on.
- * hgs_profile_read synchronises those events and returns the accumulated
+/* Per-stage timing and work accounting.  `on` is a set of flags (0 turns
+ * both off; other bits are EINVAL):
+ *   HGS_PROFILE_STAGES  every render/backward call records a HIP event pair
+ *                       around each stage on the stream it enqueues on;
+ *   HGS_PROFILE_WORK    the raster forward also records each pixel's pair
+ *                       counts (hgs_state_debug array 9).  This runs a
+ *                       slower variant of the forward, so stage times taken
+ *                       with it do not time the plain forward.
+ * hgs_profile_read synchronises the events and returns the accumulated
  * milliseconds per stage in ms[HGS_N_STAGES] and the number of launches in
  * calls[HGS_N_STAGES] (either may be NULL); reset != 0 clears the totals. */
+enum { HGS_PROFILE_STAGES = 1, HGS_PROFILE_WORK = 2 };
 enum {
   HGS_STAGE_PREPROCESS = 0,
   HGS_STAGE_SCAN = 1,

@@ -219,8 +219,12 @@ def hgs_set_pair_capacity(ctx, max_pairs: int):
     check(load().hgs_set_pair_capacity(ctx, int(max_pairs)))
 
 
-def hgs_profile_enable(ctx, on: bool):
-    check(load().hgs_profile_enable(ctx, 1 if on else 0))
+PROFILE_STAGES, PROFILE_WORK = 1, 2  # HGS_PROFILE_STAGES, HGS_PROFILE_WORK
+
+
+def hgs_profile_enable(ctx, on):
+    """on: False / 0 (off), True (stage events), or a set of PROFILE_* flags."""
+    check(load().hgs_profile_enable(ctx, int(on)))
 
 
 def hgs_profile_read(ctx, reset: bool = False):

@@ -707,9 +707,9 @@ hgs_status hgs_render(hgs_ctx *ctx, int32_t scene_id, const hgs_camera *cams, in
   ro.T_final = st->T_final;
   ro.last = st->last;
   ro.n_contrib = st->n_contrib;
-  ro.wcount = ctx->profile ? st->wcount : nullptr;  // work accounting while profiling
+  ro.wcount = ctx->work_acct ? st->wcount : nullptr;  // work accounting on request
   ro.vis = st->vis;
-  st->has_wcount = ctx->profile;
+  st->has_wcount = ctx->work_acct;
   {
     StageTimer t(ctx, HGS_STAGE_RASTER_FWD, st->stream);
     launch_raster_fwd(st->ranges, st->order, st->vals, st->rec, st->n_tiles, W, H,
@@ -1072,7 +1072,9 @@ hgs_status hgs_densify_stats(hgs_ctx *ctx, hgs_state *st, float *grad_norm, floa
 
 hgs_status hgs_profile_enable(hgs_ctx *ctx, int32_t on) {
   if (!ctx) return fail(HGS_EINVAL, "ctx is NULL");
-  ctx->profile = on != 0;
+  if (on & ~(HGS_PROFILE_STAGES | HGS_PROFILE_WORK)) return fail(HGS_EINVAL, "unknown profile flag");
+  ctx->profile = (on & HGS_PROFILE_STAGES) != 0;
+  ctx->work_acct = (on & HGS_PROFILE_WORK) != 0;
   return HGS_OK;
 }
 
@@ -1153,8 +1155,8 @@ hgs_status hgs_state_debug(hgs_ctx *ctx, hgs_state *st, int32_t what, void *dst,
     case 8: src = st->n_contrib; bytes = P * 4; break;
     case 9:
       if (!st->has_wcount)
-        return fail(HGS_EINVAL, "pair counts are recorded only by renders made while profiling "
-                                "is enabled (hgs_profile_enable)");
+        return fail(HGS_EINVAL, "pair counts are recorded only by renders made while "
+                                "HGS_PROFILE_WORK is enabled (hgs_profile_enable)");
       src = st->wcount;
       bytes = P * 4;
       break;

@@ -88,7 +88,8 @@ struct hgs_ctx {
   int device = 0;
   int n_cu = 1;  // compute units of `device`
   std::vector<hgs::Scene> scenes;
-  bool profile = false;
+  bool profile = false;     // stage events (HGS_PROFILE_STAGES)
+  bool work_acct = false;   // per-pixel pair counts (HGS_PROFILE_WORK)
   std::vector<hgs::StageEvent> pending;
   std::vector<hipEvent_t> event_pool;
   double stage_ms[HGS_N_STAGES] = {0};
