@@ -198,6 +198,38 @@ def test_all_culled_and_tiny_images():
         st.free()
 
 
+def test_profile_flags_select_stage_events_and_work_accounting():
+    """Stage events alone leave the plain forward in place (no pair counts);
+    HGS_PROFILE_WORK records them and renders the same images; an unknown
+    flag is EINVAL."""
+    from paper_2512_02932_amd import _hgs
+    from paper_2512_02932_amd.rasterizer import get_rasterizer, pair_counts
+    rast = get_rasterizer(0)
+    sc = sg.scene_random(300, seed=5)
+    cam = sg.look_at_camera((0.1, 0.0, -3.0), width=40, height=24, fx=40.0)
+    with pytest.raises(_hgs.HGSError):
+        _hgs.hgs_profile_enable(rast.ctx, 4)
+    try:
+        _hgs.hgs_profile_read(rast.ctx, reset=True)
+        _hgs.hgs_profile_enable(rast.ctx, _hgs.PROFILE_STAGES)
+        imgs, st, _ = gpu_render(sc, cam)
+        with pytest.raises(_hgs.HGSError):
+            st.debug("wcount")
+        st.free()
+        prof = _hgs.hgs_profile_read(rast.ctx, reset=True)
+        assert prof["raster_fwd"][1] == 1 and prof["raster_fwd"][0] > 0
+        _hgs.hgs_profile_enable(rast.ctx, _hgs.PROFILE_WORK)
+        imgs_w, st, _ = gpu_render(sc, cam)
+        counts = pair_counts(st)
+        assert counts["blend_3d"] + counts["blend_2d"] > 0
+        st.free()
+        assert _hgs.hgs_profile_read(rast.ctx, reset=True)["raster_fwd"][1] == 0
+        for k in imgs:  # the same per-pixel arithmetic, plus counting
+            np.testing.assert_allclose(imgs_w[k], imgs[k], rtol=0, atol=1e-6)
+    finally:
+        _hgs.hgs_profile_enable(rast.ctx, 0)
+
+
 def test_nan_and_inf_parameters_are_dropped():
     sc = sg.scene_random(500, seed=8)
     cam = sg.look_at_camera((0, 0, -3.5), width=64, height=48, fx=50.0)
